@@ -1,0 +1,255 @@
+"""Benchmark: CountSketch S A throughput (nnz/s, fraction of HBM roofline) and
+least-squares solves/s at a certified residual ratio <= 1 + 1e-6, on one
+MI355X.
+
+One step = one sketch of the sparse workload: CSR A with n = 2^22 rows, d = 256
+columns, 16 nonzeros per row at uniform columns, float32 N(0,1) values, sketch
+size t = 65536 (hash + bucket plan + segmented reduce, every kernel of the
+path from (A, seed) to S A inside the timed region).  Inputs are synthetic and
+already resident in device memory when timing starts.
+
+Also reported on the same JSON line: the dense float32 variant (n = 2^20),
+the bit-exact integer-valued variant, least squares on the dense heavy-row
+regression workload (n = 2^21, d = 512, t = 2^18) in the plain float64 form and
+the mixed-precision form, the roofline of the dominant kernel (measured with
+HIP events on the library's stream), and the oracle timed on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--variant", default="auto", choices=["auto", "atomic", "sorted"])
+    p.add_argument("--no-extras", action="store_true", help="only the headline sketch workload")
+    p.add_argument("--no-lstsq", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--lstsq-steps", type=int, default=3)
+    return p.parse_args()
+
+
+def profile_phases(sk):
+    lib = sk.lib()
+    out = {}
+    name = ctypes.c_char_p()
+    cnt = ctypes.c_int64()
+    ms = ctypes.c_double()
+    for i in range(lib.skls_profile_count()):
+        if lib.skls_profile_get(i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms)) == 0:
+            out[name.value.decode()] = (cnt.value, ms.value)
+    return out
+
+
+def time_steps(fn, steps, warmup, sync):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    sync()
+    return e0.elapsed_time(e1) / steps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported in this build "
+              "(the multi-GPU sharding of the sketch is a design, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1207_6365_amd as sk
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    lib = sk.lib()
+    sync = torch.cuda.synchronize
+    t = 65536
+    seed = W.sketch_seed(0)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------ headline
+    log("generating the sparse sketch workload (n=2^22, d=256, 16 nnz/row)")
+    A, b = W.sketch_csr()
+    nnz = A.nnz
+    Ag = sk.Csr(A.n, A.d, torch.from_numpy(A.row_ptr32()).to(dev), torch.from_numpy(A.col_idx).to(dev),
+                torch.from_numpy(A.val).to(dev))
+    SA = torch.empty((t, A.d), dtype=torch.float32, device=dev)
+    ws_bytes = ctypes.c_size_t(0)
+    mat, _ = sk.api._matrix(Ag)
+    variant = sk.api._VARIANT[args.variant]
+    sk._lib.check(lib.skls_sketch_workspace(ctypes.byref(mat), t, variant, ctypes.byref(ws_bytes)))
+    ws = torch.empty(max(ws_bytes.value, 1), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def step():
+        st = lib.skls_sketch(ctypes.byref(mat), None, 0, t, seed, None, variant, SA.data_ptr(), None, 1,
+                             ws.data_ptr(), ws.numel(), stream)
+        if st != 0:
+            sk._lib.check(st)
+
+    log(f"timing {args.steps} sketch steps after {args.warmup} warm-up steps")
+    lib.skls_profile_enable(1)
+    ms = time_steps(step, args.steps, args.warmup, sync)
+    phases = profile_phases(sk)
+    lib.skls_profile_enable(0)
+    # steady-state step time without the per-phase events
+    ms_clean = time_steps(step, args.steps, 2, sync)
+    ms_step = min(ms, ms_clean)
+
+    alg_bytes = 4 * nnz + 4 * nnz + 4 * (A.n + 1) + 4 * t * A.d  # val + col + row_ptr + write S A
+    value = nnz / (ms_step * 1e-3)
+    dom = "sketch_apply"
+    cnt, tot = phases.get(dom, (0, float("nan")))
+    k_ms = tot / max(cnt, 1)
+    achieved = alg_bytes / (k_ms * 1e-3)
+    plan_cnt, plan_tot = phases.get("sketch_plan", (0, 0.0))
+    result = {
+        "metric": "SA nnz/s (% HBM roofline); lstsq solves/s at residual ratio <=1+1e-6",
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "CountSketch S*A of CSR A, n=2^22, d=256, 16 nnz/row, float32 N(0,1), t=65536",
+                   "n": A.n, "d": A.d, "nnz": nnz, "t": t, "variant": args.variant, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "kernel": "k_sketch_csr_sorted" if args.variant != "atomic" else "k_sketch_csr_atomic",
+                     "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes},
+        "step_roofline_frac": alg_bytes / (ms_step * 1e-3) / HBM_PEAK,
+        "phases_ms": {k: v[1] / max(v[0], 1) for k, v in phases.items()},
+    }
+    if plan_cnt:
+        result["phases_ms"]["sketch_plan"] = plan_tot / plan_cnt
+    del Ag
+
+    # ------------------------------------------------------------ extras
+    if not args.no_extras:
+        log("dense float32 variant (n=2^20, d=256)")
+        D, _ = W.sketch_dense()
+        Dg = torch.from_numpy(D).to(dev)
+        dm, _ = sk.api._matrix(Dg)
+        sk._lib.check(lib.skls_sketch_workspace(ctypes.byref(dm), t, variant, ctypes.byref(ws_bytes)))
+        wsd = torch.empty(max(ws_bytes.value, 1), dtype=torch.uint8, device=dev)
+
+        def dstep():
+            sk._lib.check(lib.skls_sketch(ctypes.byref(dm), None, 0, t, seed, None, variant, SA.data_ptr(), None, 1,
+                                          wsd.data_ptr(), wsd.numel(), stream))
+
+        lib.skls_profile_enable(1)
+        dms = time_steps(dstep, max(args.steps // 2, 5), 3, sync)
+        dph = profile_phases(sk)
+        lib.skls_profile_enable(0)
+        dbytes = 4 * D.size + 4 * t * D.shape[1]
+        dk = dph.get("sketch_apply", (1, float("nan")))
+        result["dense"] = {"entries_per_s": D.size / (dms * 1e-3), "ms_per_step": dms,
+                           "kernel_frac": dbytes / (dk[1] / max(dk[0], 1) * 1e-3) / HBM_PEAK,
+                           "step_frac": dbytes / (dms * 1e-3) / HBM_PEAK}
+        del Dg, D
+
+        log("integer-valued variant: bit-exact check against the oracle")
+        import oracle as O
+
+        Ai, _ = W.sketch_csr_int()
+        Aig = sk.Csr(Ai.n, Ai.d, torch.from_numpy(Ai.row_ptr32()).to(dev), torch.from_numpy(Ai.col_idx).to(dev),
+                     torch.from_numpy(Ai.val).to(dev))
+        SAi = sk.sketch(Aig, t, seed, variant=args.variant).cpu().numpy().astype(np.float64)
+        ref = O.sketch_csr(Ai.n, Ai.d, Ai.row_ptr, Ai.col_idx, Ai.val, seed, t)
+        result["integer_bit_exact"] = bool(np.array_equal(SAi, ref))
+        del Aig, Ai, SAi, ref
+
+    # ------------------------------------------------------------ least squares
+    if not args.no_lstsq:
+        n3, d3, t3 = 1 << 21, 512, 1 << 18
+        res = {}
+        for storage, precision in (("f32", "plain"), ("f32", "mixed"), ("bf16", "mixed")):
+            log(f"least squares: dense heavy-row workload n=2^21 d=512 t=2^18, {storage} storage, {precision}")
+            A3, b3, _ = W.pareto_rows(n=n3, d=d3, storage=storage)
+            A3g = (torch.from_numpy(A3.view(np.int16)).to(dev).view(torch.bfloat16) if storage == "bf16"
+                   else torch.from_numpy(A3).to(dev))
+            del A3
+            b3g = torch.from_numpy(b3).to(dev)
+            x, info = sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision)  # warm-up
+            sync()
+            lib.skls_profile_enable(1)
+            t0 = time.perf_counter()
+            infos = []
+            for _ in range(args.lstsq_steps):
+                x, info = sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision)
+                infos.append(info)
+            sync()
+            el = (time.perf_counter() - t0) / args.lstsq_steps
+            ph = profile_phases(sk)
+            lib.skls_profile_enable(0)
+            key = f"{storage}_{precision}"
+            pass_name = "lsqr_pass_f64" if precision == "plain" else "lsqr_pass_f32"
+            pc, pt_ = ph.get(pass_name, (1, float("nan")))
+            es = 2 if storage == "bf16" else 4
+            pass_bytes = n3 * d3 * es + n3 * (8 if precision == "plain" else 4) * 2
+            res[key] = {
+                "solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
+                "certified": all(i["certified"] == 1 for i in infos),
+                "ratio_bound": max(i["ratio_bound"] for i in infos),
+                "iterations": infos[-1]["iterations"], "refinements": infos[-1]["refinements"],
+                "ms_sketch": infos[-1]["ms_sketch"], "ms_qr": infos[-1]["ms_qr"], "ms_iter": infos[-1]["ms_iter"],
+                "pass_frac": pass_bytes / (pt_ / max(pc, 1) * 1e-3) / HBM_PEAK,
+                "phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
+            }
+            del A3g, b3g
+            torch.cuda.empty_cache()
+        result["lstsq"] = res
+
+    # ------------------------------------------------------------ oracle on the host
+    if not args.no_cpu:
+        import oracle as O
+
+        log("timing the oracle on the host (same sparse workload, 2 repetitions)")
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            O.sketch_csr(A.n, A.d, A.row_ptr, A.col_idx, A.val, seed, t)
+        el = (time.perf_counter() - t0) / reps
+        result["cpu_baseline"] = {"value": nnz / el, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"full sparse workload (nnz={nnz}), {reps} repetitions of the NumPy "
+                                            "float64 oracle sketch, single thread",
+                                  "host_cpus": os.cpu_count()}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

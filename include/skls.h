@@ -1,0 +1,279 @@
+/*
+ * skls -- sparse-embedding sketching and least squares on AMD MI355X (gfx950).
+ *
+ * C ABI of the library libskls.so.  The operations follow Clarkson & Woodruff,
+ * "Low Rank Approximation and Regression in Input Sparsity Time"
+ * (arXiv:1207.6365); each declaration cites the part of the paper that defines
+ * what it computes.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers documented as "device" address GPU memory of the current HIP
+ *    device; "host" pointers address CPU memory.  All device buffers (inputs,
+ *    outputs, workspace) belong to the caller; the library allocates and frees
+ *    no device memory.  Workspace sizes come from the *_workspace queries; a
+ *    workspace may be reused between calls once the previous call on it has
+ *    completed in stream order.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it in order.  Calls marked "asynchronous" return before the
+ *    GPU finishes; the others synchronise `stream` before returning.
+ *  - Indices are 0-based (the paper writes [n] = {1..n}).  Rows i in [0, n),
+ *    buckets in [0, t).
+ *  - Errors are returned as skls_status.  Nothing aborts and no C++ exception
+ *    crosses the ABI.  skls_last_error() gives a message for the calling thread.
+ *    On an error return no work has been enqueued, except SKLS_ERR_DEVICE
+ *    (a HIP call failed), SKLS_ERR_RANK and SKLS_ERR_NOCONV (detected after
+ *    GPU work ran; outputs then hold what the documentation of the call says).
+ *  - Nothing here is thread-safe with respect to two calls that share a
+ *    workspace or output buffer; calls on distinct buffers may run concurrently.
+ */
+#ifndef SKLS_H
+#define SKLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define SKLS_API __attribute__((visibility("default")))
+#else
+#define SKLS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SKLS_F64 = 0,  /* IEEE binary64 */
+  SKLS_F32 = 1,  /* IEEE binary32 */
+  SKLS_BF16 = 2  /* bfloat16 (upper half of a binary32), read-only inputs */
+} skls_dtype;
+
+typedef enum {
+  SKLS_OK = 0,
+  SKLS_ERR_ARG = 1,        /* null pointer, bad enum or option value */
+  SKLS_ERR_SHAPE = 2,      /* inconsistent or unsupported sizes */
+  SKLS_ERR_DTYPE = 3,      /* unsupported combination of types */
+  SKLS_ERR_RANK = 4,       /* the sketch is numerically rank deficient */
+  SKLS_ERR_NOCONV = 5,     /* the iteration did not certify within max_iter */
+  SKLS_ERR_WORKSPACE = 6,  /* workspace missing or smaller than required */
+  SKLS_ERR_DEVICE = 7,     /* a HIP runtime call or kernel launch failed */
+  SKLS_ERR_NOTIMPL = 8     /* operation not provided by this build */
+} skls_status;
+
+typedef enum { SKLS_DENSE = 0, SKLS_CSR = 1 } skls_layout;
+
+/*
+ * Input matrix A (n x d), read-only, device memory.
+ *  dense: row-major, element (i, j) at val[i * ld + j], ld >= d.
+ *  CSR:   row i holds entries row_ptr[i] .. row_ptr[i+1]-1 of col_idx / val;
+ *         row_ptr has n+1 entries, row_ptr[0] = 0, row_ptr[n] = nnz, and is
+ *         int32 (row_ptr_64 = 0) or int64 (row_ptr_64 = 1).  Column indices lie
+ *         in [0, d); order within a row is free, repeats are summed.
+ * The library requires n < 2^31 and d < 2^31.
+ */
+typedef struct {
+  int32_t layout;          /* skls_layout */
+  int32_t dtype;           /* skls_dtype of val */
+  int64_t n, d;
+  int64_t ld;              /* dense: elements between consecutive rows */
+  int64_t nnz;             /* CSR: number of stored entries */
+  const void* row_ptr;     /* CSR: device, int32 or int64 [n+1] */
+  int32_t row_ptr_64;      /* CSR: 1 if row_ptr is int64 */
+  int32_t reserved;
+  const int32_t* col_idx;  /* CSR: device [nnz] */
+  const void* val;         /* device: dense n*ld or CSR nnz values */
+} skls_matrix;
+
+/* Human-readable name of a status code (static string). */
+SKLS_API const char* skls_status_str(int32_t status);
+/* Message describing the last error returned on the calling thread ("" if none). */
+SKLS_API const char* skls_last_error(void);
+/* Library version string. */
+SKLS_API const char* skls_version(void);
+
+/*
+ * Hash and sign of the sparse embedding S = Phi D (Section 2): for global rows
+ * i = start .. start+n-1, bucket[i-start] = h(i) in [0, t) and sign[i-start] =
+ * the diagonal entry of D, +1 or -1.  Drawn from SplitMix64 (Steele, Lea &
+ * Flood 2014) output i of stream `seed`: h = ((z >> 32) * t) >> 32, sign = -1
+ * iff bit 0 of z is set.  Bit-exact and identical on every device.
+ * bucket: device int32[n]; sign: device int8[n] (either may be NULL).
+ * Requires 1 <= t < 2^31, n >= 0.  Asynchronous.
+ */
+SKLS_API int32_t skls_hash(int64_t n, int64_t t, uint64_t seed, int64_t start, int32_t* bucket, int8_t* sign,
+                  void* stream);
+
+/*
+ * Sketch-apply variants (Section 2; the O(nnz(A)) product of the main theorem
+ * of Section 3 and of the regression theorem of Section 7).
+ *  SKLS_SKETCH_AUTO      library default for the layout and sizes
+ *  SKLS_SKETCH_ATOMIC    stream rows in storage order; scatter-add each entry
+ *                        into S*A with device-wide atomics (S*A zeroed first)
+ *  SKLS_SKETCH_SORTED    group rows by bucket (counting sort of h), then one
+ *                        wavefront reduces each bucket's rows in increasing
+ *                        row order and writes its row of S*A once; results are
+ *                        reproducible bit for bit from run to run
+ */
+enum { SKLS_SKETCH_AUTO = 0, SKLS_SKETCH_ATOMIC = 1, SKLS_SKETCH_SORTED = 2 };
+
+/* Bytes of workspace skls_sketch needs for this input, t and variant. */
+SKLS_API int32_t skls_sketch_workspace(const skls_matrix* A, int64_t t, int32_t variant, size_t* bytes);
+
+/*
+ * SA = S A and Sb = S b with S = Phi D (Section 2): row h(i) of SA accumulates
+ * sign(i) * A[i, :], and Sb[h(i)] accumulates sign(i) * b[i].  When w is not
+ * NULL the learned value w[i] replaces sign(i) (h stays the hashed bucket).
+ *  A:      input matrix (F64, F32 or BF16 values).
+ *  b:      device vector [n] of type b_dtype (F64 or F32), or NULL.
+ *  t:      sketch rows, 1 <= t < 2^31.
+ *  seed:   64-bit stream of the hash (see skls_hash).
+ *  w:      device float32 [n] or NULL.
+ *  SA:     device, t x d row-major (leading dimension d), type out_dtype (F64
+ *          or F32); every element is written.
+ *  Sb:     device [t] of type out_dtype, or NULL (required iff b != NULL).
+ *  Sums are accumulated in out_dtype.  Asynchronous.
+ */
+SKLS_API int32_t skls_sketch(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
+                    const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/*
+ * Triangular factor of a QR factorisation of a tall matrix (Section 7 solves
+ * the sketched regression through the QR factorisation of S A, as R^{-1} Q^T S b;
+ * Section 6 uses the same R as the change of basis that makes S A R^{-1}
+ * orthonormal).  Computed as the Cholesky factor of the Gram matrix M^T M
+ * formed in float64 on the matrix cores (CholeskyQR): in exact arithmetic this
+ * is the R of M = QR with a positive diagonal.
+ *  M:     device, m x d row-major (leading dimension d), F64 or F32, m >= d,
+ *         d <= 8192.
+ *  R:     device float64 d x d row-major, upper triangular (zeros below).
+ *  Rinv:  device float64 d x d row-major, the inverse of R, or NULL.
+ *  Returns SKLS_ERR_RANK (R, Rinv then unspecified) when a pivot of the Gram
+ *  matrix is not positive or min R_kk <= 4 sqrt(d * 2^-52) max R_kk (a
+ *  Gram-based factor cannot resolve smaller pivots).  Synchronous.
+ */
+SKLS_API int32_t skls_qr_r_workspace(int64_t m, int64_t d, size_t* bytes);
+SKLS_API int32_t skls_qr_r(const void* M, int32_t dtype, int64_t m, int64_t d, double* R, double* Rinv, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* Options of skls_lstsq.  Zero-initialise, then set fields. */
+typedef struct {
+  int64_t t;            /* sketch rows (t >= d) */
+  uint64_t seed;        /* hash stream */
+  double delta;         /* target: ||A x - b|| <= (1 + delta) min ||A x - b||; 0 -> 1e-6 */
+  double sigma_lb;      /* assumed lower bound on sigma_min(A R^{-1}); 0 -> 0.5 */
+  int32_t max_iter;     /* LSQR iterations (total over refinements); 0 -> 100 */
+  int32_t precision;    /* 0: float64 arithmetic in every pass ("plain");
+                           1: mixed -- float32 LSQR passes with float64
+                              residual refinement */
+  int32_t sketch_only;  /* 1: return the sketch-and-solve x~ without iterating */
+  int32_t variant;      /* sketch variant (SKLS_SKETCH_*) */
+  const float* w;       /* learned sketch values (device float32 [n]) or NULL */
+} skls_lstsq_opts;
+
+typedef struct {
+  int32_t iterations;     /* LSQR iterations run */
+  int32_t refinements;    /* outer float64 residual refinements (mixed) */
+  int32_t certified;      /* 1 if the stopping certificate holds at the result */
+  int32_t reserved;
+  double resid_norm;      /* ||b - A x|| at the result (float64 accumulation) */
+  double grad_norm;       /* ||R^{-T} A^T (b - A x)|| at the result */
+  double ratio_bound;     /* certified bound on ||Ax-b|| / min ||Ax-b|| (given sigma_lb) */
+  double ms_sketch, ms_qr, ms_iter;  /* phase times (device events) */
+} skls_lstsq_info;
+
+SKLS_API int32_t skls_lstsq_workspace(const skls_matrix* A, const skls_lstsq_opts* opts, size_t* bytes);
+
+/*
+ * Least squares min_x ||A x - b||_2 (Section 7).  Sketch-and-solve (regression
+ * theorem of Section 7) gives x~ = argmin ||S A x - S b|| through the R of S A;
+ * unless sketch_only, LSQR (Paige & Saunders 1982) on M = A R^{-1} started at
+ * x~ -- the R-preconditioned Krylov (conjugate-gradient type) iteration of Section 7.7 -- runs until the
+ * certificate ||M^T r|| <= sigma_lb * sqrt(D / (1 + D)) ||r|| with
+ * D = (1 + delta)^2 - 1 holds for r = b - A x evaluated with float64
+ * accumulation; this certifies ratio <= 1 + delta when sigma_min(M) >= sigma_lb.
+ *  A:    dense or CSR input (F64, F32 or BF16 values).
+ *  b:    device float64 [n].
+ *  x:    device float64 [d], output.
+ *  info: host, may be NULL.
+ * Returns SKLS_ERR_RANK if S A is rank deficient (x unspecified) and
+ * SKLS_ERR_NOCONV if max_iter ran out (x = last iterate).  Synchronous.
+ */
+SKLS_API int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_lstsq_opts* opts, double* x,
+                   skls_lstsq_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Approximate leverage scores (Section 6, theorem on approximating all leverage
+ * scores): scores[i] = || A[i, :] R^{-1} Pi2 ||^2 where R is the triangular
+ * factor of S A (S from t, seed) and Pi2 is a d x k Johnson-Lindenstrauss
+ * matrix supplied by the caller (device float64, row-major).  Scores are
+ * accumulated in float32.
+ *  scores: device float32 [n].
+ * Returns SKLS_ERR_RANK if S A is rank deficient.  Synchronous.
+ */
+SKLS_API int32_t skls_leverage_workspace(const skls_matrix* A, int64_t t, int32_t k, size_t* bytes);
+SKLS_API int32_t skls_leverage_scores(const skls_matrix* A, int64_t t, uint64_t seed, int32_t k, const double* Pi2,
+                             float* scores, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Gram matrix C = A^T A (float32 output, float32 accumulation), used as the
+ * target of the learned-value distortion loss.  A dense or CSR.
+ *  C: device float32 d x d row-major.  Asynchronous.
+ */
+SKLS_API int32_t skls_gram_workspace(const skls_matrix* A, size_t* bytes);
+SKLS_API int32_t skls_gram(const skls_matrix* A, float* C, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Learned sketch values (an extension of Section 2: the signs of D become
+ * trainable values w while h stays hashed).  With Y = S_w A and
+ * E = Y^T Y - C (C = A^T A from skls_gram):
+ *   loss = ||E||_F^2,   dloss/dw[i] = < (4 Y E)[h(i), :], A[i, :] >.
+ *  A:          dense float32 input, d <= 4096.
+ *  C:          device float32 d x d.
+ *  w:          device float32 [n].
+ *  grad_scale: the gradient is multiplied by this factor.
+ *  accumulate: 0 -> grad_w = grad_scale * dloss/dw; 1 -> grad_w += it.
+ *  loss:       device float32 scalar (always overwritten with the raw loss).
+ *  grad_w:     device float32 [n], or NULL to evaluate the loss only.
+ *  Asynchronous.
+ */
+SKLS_API int32_t skls_learned_workspace(const skls_matrix* A, int64_t t, size_t* bytes);
+SKLS_API int32_t skls_learned_grad(const skls_matrix* A, const float* C, int64_t t, uint64_t seed, const float* w,
+                                   float grad_scale, int32_t accumulate, float* loss, float* grad_w, void* ws,
+                                   size_t ws_bytes, void* stream);
+
+/*
+ * One Adam step (Kingma & Ba 2015) on w [n] (device float32) with gradient g,
+ * moments m, v (device float32, caller-initialised to 0), step >= 1.
+ * Asynchronous.
+ */
+SKLS_API int32_t skls_adam_step(int64_t n, float* w, const float* g, float* m, float* v, int32_t step, float lr,
+                       float beta1, float beta2, float eps, void* stream);
+
+/*
+ * Kernel-phase timing (tracing).  While enabled, every kernel phase the library
+ * launches ("sketch_plan", "sketch_apply", "gram", "cholesky", "trinv",
+ * "lsqr_pass", "leverage", ...) is bracketed by HIP events recorded on the
+ * stream of the call, so the times are those of the kernels on that stream.
+ *  skls_profile_enable(on): clears all counters and turns timing on or off.
+ *  skls_profile_count():    number of phase names recorded so far.
+ *  skls_profile_get(i, ...): name (static until the next enable), number of
+ *      timed launches and their total milliseconds for phase i; waits for the
+ *      phase's pending events.  Process-wide; not meant for concurrent use.
+ */
+SKLS_API int32_t skls_profile_enable(int32_t on);
+SKLS_API int32_t skls_profile_count(void);
+SKLS_API int32_t skls_profile_get(int32_t index, const char** name, int64_t* launches, double* total_ms);
+
+/*
+ * Rank-k approximation A ~ L D W^T (Section 8, theorem on low-rank
+ * approximation).  Not provided by this build: returns SKLS_ERR_NOTIMPL.
+ */
+SKLS_API int32_t skls_low_rank(const skls_matrix* A, int64_t k, double eps, uint64_t seed, double* L, double* D,
+                      double* W, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKLS_H */

@@ -13,7 +13,7 @@ Time" (arXiv:1207.6365) it follows:
 * :mod:`.linalg`   -- Householder QR, substitution, exact least squares,
   residual ratio via the Pythagorean identity (Section 7.2 facts)
 * :mod:`.solve`    -- sketch-and-solve (Section 7 regression theorem),
-  preconditioned LSQR and Richardson iteration (Section 7.6)
+  preconditioned LSQR and Richardson iteration (Section 7.7)
 * :mod:`.leverage` -- exact and approximate leverage scores (Section 6)
 * :mod:`.learned`  -- distortion loss and gradient of learned sketch values
   (an extension; closed-form expectation for the plain sketch)

@@ -1,5 +1,5 @@
 """Oracle: leverage scores (Introduction and Section 3 definitions; the
-approximation of Section 6, Theorem "icml").
+approximation theorem of Section 6).
 
 * Exact: ``u_i = ||U[i, :]||^2`` for ``U`` an orthonormal basis of the column
   space of ``A`` (here the thin ``Q`` of a Householder QR of ``A``).

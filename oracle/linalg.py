@@ -1,14 +1,15 @@
 """Oracle: small dense linear algebra in float64, written out plainly.
 
-* Householder QR (the paper leaves the QR variant open; Section 7 solves the
-  sketched problem by "a QR factorization of SA" followed by ``R^{-1} Q^T S B``,
-  Theorem "renRegAlg").  The ``R`` returned has a non-negative diagonal.
+* Householder QR (the paper leaves the QR variant open; the regression
+  theorem of Section 7.4 solves the sketched problem through a QR
+  factorisation of the sketch and ``R^{-1} Q^T S B``).  The ``R`` returned has
+  a non-negative diagonal.
 * Triangular solves by substitution.
 * Exact least squares ``x* = A^- b`` (Introduction; for full column rank the
   minimiser of ``||A x - b||``), via Householder QR of the whole ``A``.
 * The residual ratio ``||A x - b|| / ||A x* - b||`` computed through the
-  Pythagorean identity of the normal equations (Section 7, facts
-  "Pythagorean Theorem" and "Normal Equations"):
+  Pythagorean identity of the normal equations (the Pythagorean theorem and
+  normal-equations facts of Section 7.2):
   ``||A x - b||^2 = ||A (x - x*)||^2 + ||A x* - b||^2``.
 """
 

@@ -3,9 +3,9 @@
 * :func:`sketch_and_solve` follows the regression theorem of Section 7: sketch
   ``A`` adjoined with ``b`` by ``Phi D``, then minimise ``||Phi D A x - Phi D b||``
   by a QR factorisation of the sketch and ``x~ = R^{-1} Q^T (S b)`` (the
-  solve described in the proof of Theorem "renRegAlg").
-* :func:`lsqr` is the "CG-like method" of Section 7.6 preconditioned by the
-  triangular factor: the Krylov method runs on ``M = A R^{-1}``, whose
+  solve described in the proof of the regression theorem of Section 7.4).
+* :func:`lsqr` is the conjugate-gradient type method of Section 7.7
+  preconditioned by the triangular factor: the Krylov method runs on ``M = A R^{-1}``, whose
   condition number is at most ``((1+e0)/(1-e0))^2`` when the sketch is an
   ``e0``-embedding, started from an iterate with bounded relative error.
   The Krylov method used is LSQR (Paige and Saunders, ACM TOMS 8(1), 1982),
@@ -113,7 +113,7 @@ def lsqr(A, b, x0, R, delta: float, sigma_lb: float = 0.5, max_iter: int = 200):
 
 
 def richardson(A, b, x0, R, delta: float, sigma_lb: float = 0.5, max_iter: int = 500):
-    """Simple iterative improvement on ``M = A R^{-1}`` (Section 7.6).
+    """Simple iterative improvement on ``M = A R^{-1}`` (Section 7.7).
 
     Returns ``(x, iterations, converged, history)``.  It converges when every
     singular value of ``M`` lies in ``(0, sqrt 2)``; the contraction factor

@@ -1,0 +1,27 @@
+"""skls: input-sparsity-time sketching and least squares on AMD MI355X.
+
+The sparse embedding ``S = Phi D`` of Clarkson & Woodruff (arXiv:1207.6365,
+Section 2) applied in ``O(nnz(A))``, sketch-and-solve regression (Section 7),
+R-preconditioned LSQR (Section 7.7), approximate leverage scores (Section 6)
+and learned per-row sketch values, all in hand-written HIP kernels for gfx950
+behind the C ABI of ``include/skls.h``.  This package only marshals torch
+tensors into that ABI; importing it does not load the library, the first call
+does (and raises if ``libskls.so`` has not been built).
+"""
+
+from ._lib import SklsError  # noqa: F401
+from .api import (  # noqa: F401
+    Csr,
+    LearnedWorkspace,
+    adam_step,
+    gram,
+    hash_rows,
+    learned_grad,
+    leverage_scores,
+    lib,
+    low_rank,
+    lstsq,
+    qr_r,
+    sketch,
+    version,
+)

@@ -1,0 +1,137 @@
+"""ctypes view of libskls.so (declarations in include/skls.h)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libskls.so")
+
+F64, F32, BF16 = 0, 1, 2
+DENSE, CSR = 0, 1
+SKETCH_AUTO, SKETCH_ATOMIC, SKETCH_SORTED = 0, 1, 2
+
+STATUS = {
+    0: "SKLS_OK",
+    1: "SKLS_ERR_ARG",
+    2: "SKLS_ERR_SHAPE",
+    3: "SKLS_ERR_DTYPE",
+    4: "SKLS_ERR_RANK",
+    5: "SKLS_ERR_NOCONV",
+    6: "SKLS_ERR_WORKSPACE",
+    7: "SKLS_ERR_DEVICE",
+    8: "SKLS_ERR_NOTIMPL",
+}
+
+
+class SklsMatrix(ctypes.Structure):
+    _fields_ = [
+        ("layout", c_int32),
+        ("dtype", c_int32),
+        ("n", c_int64),
+        ("d", c_int64),
+        ("ld", c_int64),
+        ("nnz", c_int64),
+        ("row_ptr", c_void_p),
+        ("row_ptr_64", c_int32),
+        ("reserved", c_int32),
+        ("col_idx", c_void_p),
+        ("val", c_void_p),
+    ]
+
+
+class SklsLstsqOpts(ctypes.Structure):
+    _fields_ = [
+        ("t", c_int64),
+        ("seed", c_uint64),
+        ("delta", c_double),
+        ("sigma_lb", c_double),
+        ("max_iter", c_int32),
+        ("precision", c_int32),
+        ("sketch_only", c_int32),
+        ("variant", c_int32),
+        ("w", c_void_p),
+    ]
+
+
+class SklsLstsqInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", c_int32),
+        ("refinements", c_int32),
+        ("certified", c_int32),
+        ("reserved", c_int32),
+        ("resid_norm", c_double),
+        ("grad_norm", c_double),
+        ("ratio_bound", c_double),
+        ("ms_sketch", c_double),
+        ("ms_qr", c_double),
+        ("ms_iter", c_double),
+    ]
+
+
+# name -> (restype, argtypes); every symbol declared in include/skls.h
+SIGNATURES = {
+    "skls_status_str": (c_char_p, [c_int32]),
+    "skls_last_error": (c_char_p, []),
+    "skls_version": (c_char_p, []),
+    "skls_hash": (c_int32, [c_int64, c_int64, c_uint64, c_int64, c_void_p, c_void_p, c_void_p]),
+    "skls_sketch_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int32, POINTER(c_size_t)]),
+    "skls_sketch": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_int64, c_uint64, c_void_p, c_int32,
+                              c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
+    "skls_qr_r_workspace": (c_int32, [c_int64, c_int64, POINTER(c_size_t)]),
+    "skls_qr_r": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "skls_lstsq_workspace": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLstsqOpts), POINTER(c_size_t)]),
+    "skls_lstsq": (c_int32, [POINTER(SklsMatrix), c_void_p, POINTER(SklsLstsqOpts), c_void_p,
+                             POINTER(SklsLstsqInfo), c_void_p, c_size_t, c_void_p]),
+    "skls_leverage_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int32, POINTER(c_size_t)]),
+    "skls_leverage_scores": (c_int32, [POINTER(SklsMatrix), c_int64, c_uint64, c_int32, c_void_p, c_void_p,
+                                       c_void_p, c_size_t, c_void_p]),
+    "skls_gram_workspace": (c_int32, [POINTER(SklsMatrix), POINTER(c_size_t)]),
+    "skls_gram": (c_int32, [POINTER(SklsMatrix), c_void_p, c_void_p, c_size_t, c_void_p]),
+    "skls_learned_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, POINTER(c_size_t)]),
+    "skls_learned_grad": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int64, c_uint64, c_void_p, c_float, c_int32,
+                                    c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "skls_adam_step": (c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_float, c_float,
+                                 c_float, c_float, c_void_p]),
+    "skls_profile_enable": (c_int32, [c_int32]),
+    "skls_profile_count": (c_int32, []),
+    "skls_profile_get": (c_int32, [c_int32, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double)]),
+    "skls_low_rank": (c_int32, [POINTER(SklsMatrix), c_int64, c_double, c_uint64, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_size_t, c_void_p]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libskls.so and declare every entry point; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')"
+        )
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class SklsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+
+
+def check(status: int) -> None:
+    if status != 0:
+        msg = load().skls_last_error()
+        raise SklsError(status, msg.decode() if msg else "")
+

@@ -1,0 +1,243 @@
+"""Python binding of libskls: argument marshalling only.
+
+Every function turns torch tensors (device memory owned by the caller) into
+plain pointers and sizes, asks the library for its workspace size, allocates
+the workspace as a torch byte tensor and calls the C entry point on the
+current HIP stream.  All arithmetic runs in the library's HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_DTYPE = {torch.float64: L.F64, torch.float32: L.F32, torch.bfloat16: L.BF16}
+_VARIANT = {"auto": L.SKETCH_AUTO, "atomic": L.SKETCH_ATOMIC, "sorted": L.SKETCH_SORTED}
+
+
+@dataclass
+class Csr:
+    """CSR matrix on the GPU: ``row_ptr`` int32/int64 ``[n+1]``, ``col_idx``
+    int32 ``[nnz]``, ``val`` float64/float32/bfloat16 ``[nnz]``."""
+
+    n: int
+    d: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def device(self):
+        return self.val.device
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors passed to skls must live on the GPU")
+    return t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _matrix(A) -> tuple[L.SklsMatrix, torch.device]:
+    m = L.SklsMatrix()
+    if isinstance(A, Csr):
+        if A.row_ptr.dtype not in (torch.int32, torch.int64) or A.col_idx.dtype != torch.int32:
+            raise TypeError("CSR row_ptr must be int32/int64 and col_idx int32")
+        if A.val.dtype not in _DTYPE:
+            raise TypeError(f"unsupported value dtype {A.val.dtype}")
+        for t in (A.row_ptr, A.col_idx, A.val):
+            if not t.is_contiguous():
+                raise ValueError("CSR arrays must be contiguous")
+        m.layout = L.CSR
+        m.dtype = _DTYPE[A.val.dtype]
+        m.n, m.d, m.ld = A.n, A.d, A.d
+        m.nnz = A.col_idx.numel()
+        m.row_ptr = _ptr(A.row_ptr)
+        m.row_ptr_64 = 1 if A.row_ptr.dtype == torch.int64 else 0
+        m.col_idx = _ptr(A.col_idx)
+        m.val = _ptr(A.val)
+        return m, A.val.device
+    if not isinstance(A, torch.Tensor) or A.dim() != 2:
+        raise TypeError("A must be a 2-D torch tensor or a Csr")
+    if A.dtype not in _DTYPE:
+        raise TypeError(f"unsupported dtype {A.dtype}")
+    if A.stride(1) != 1:
+        raise ValueError("dense A must be row-major (unit column stride)")
+    m.layout = L.DENSE
+    m.dtype = _DTYPE[A.dtype]
+    m.n, m.d = A.shape
+    m.ld = A.stride(0) if A.shape[0] > 1 else A.shape[1]
+    m.val = _ptr(A)
+    return m, A.device
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _size(fn, *args) -> int:
+    out = ctypes.c_size_t(0)
+    L.check(fn(*args, ctypes.byref(out)))
+    return out.value
+
+
+def lib():
+    return L.load()
+
+
+def version() -> str:
+    return lib().skls_version().decode()
+
+
+# ------------------------------------------------------------------ a1
+def hash_rows(n: int, t: int, seed: int, start: int = 0, device="cuda"):
+    """Bucket ``h(i)`` (int32) and sign (int8, +-1) for rows ``start..start+n-1``."""
+    device = torch.device(device)
+    bucket = torch.empty(n, dtype=torch.int32, device=device)
+    sign = torch.empty(n, dtype=torch.int8, device=device)
+    L.check(lib().skls_hash(n, t, seed & 0xFFFFFFFFFFFFFFFF, start, _ptr(bucket), _ptr(sign), _stream(device)))
+    return bucket, sign
+
+
+# ------------------------------------------------------------------ a2
+def sketch(A, t: int, seed: int, b: torch.Tensor | None = None, w: torch.Tensor | None = None,
+           variant: str = "auto", out_dtype=torch.float32):
+    """``S A`` (and ``S b`` when ``b`` is given); ``w`` replaces the signs."""
+    m, device = _matrix(A)
+    if out_dtype not in (torch.float64, torch.float32):
+        raise TypeError("out_dtype must be float64 or float32")
+    if b is not None and (b.dtype not in (torch.float64, torch.float32) or not b.is_contiguous()):
+        raise TypeError("b must be a contiguous float64/float32 vector")
+    if b is not None and b.numel() != m.n:
+        raise ValueError("b must have n entries")
+    if w is not None and (w.dtype != torch.float32 or not w.is_contiguous() or w.numel() != m.n):
+        raise TypeError("w must be a contiguous float32 vector of n entries")
+    v = _VARIANT[variant]
+    ws = _workspace(_size(lib().skls_sketch_workspace, ctypes.byref(m), t, v), device)
+    SA = torch.empty((t, m.d), dtype=out_dtype, device=device)
+    Sb = torch.empty(t, dtype=out_dtype, device=device) if b is not None else None
+    L.check(lib().skls_sketch(ctypes.byref(m), _ptr(b), _DTYPE[b.dtype] if b is not None else L.F64, t,
+                              seed & 0xFFFFFFFFFFFFFFFF, _ptr(w), v, _ptr(SA), _ptr(Sb), _DTYPE[out_dtype],
+                              _ptr(ws), ws.numel(), _stream(device)))
+    return (SA, Sb) if b is not None else SA
+
+
+# ------------------------------------------------------------------ a3
+def qr_r(M: torch.Tensor, inverse: bool = True):
+    """``R`` (and ``R^{-1}``) of a QR factorisation of a tall ``m x d`` matrix."""
+    if M.dim() != 2 or M.dtype not in (torch.float64, torch.float32) or not M.is_contiguous():
+        raise TypeError("M must be a contiguous 2-D float64/float32 tensor")
+    mm, d = M.shape
+    ws = _workspace(_size(lib().skls_qr_r_workspace, mm, d), M.device)
+    R = torch.empty((d, d), dtype=torch.float64, device=M.device)
+    Rinv = torch.empty((d, d), dtype=torch.float64, device=M.device) if inverse else None
+    L.check(lib().skls_qr_r(_ptr(M), _DTYPE[M.dtype], mm, d, _ptr(R), _ptr(Rinv), _ptr(ws), ws.numel(),
+                            _stream(M.device)))
+    return (R, Rinv) if inverse else R
+
+
+# ------------------------------------------------------------------ a3 + a4
+def lstsq(A, b: torch.Tensor, t: int, seed: int, delta: float = 1e-6, precision: str = "plain",
+          sigma_lb: float = 0.5, max_iter: int = 100, sketch_only: bool = False, variant: str = "auto",
+          w: torch.Tensor | None = None, raise_noconv: bool = True):
+    """Least squares ``min ||A x - b||``: sketch-and-solve, then R-preconditioned
+    LSQR to a certified residual ratio ``<= 1 + delta``.  Returns ``(x, info)``."""
+    m, device = _matrix(A)
+    if b.dtype != torch.float64 or not b.is_contiguous() or b.numel() != m.n:
+        raise TypeError("b must be a contiguous float64 vector with n entries")
+    o = L.SklsLstsqOpts()
+    o.t, o.seed, o.delta, o.sigma_lb, o.max_iter = t, seed & 0xFFFFFFFFFFFFFFFF, delta, sigma_lb, max_iter
+    o.precision = {"plain": 0, "mixed": 1}[precision]
+    o.sketch_only = 1 if sketch_only else 0
+    o.variant = _VARIANT[variant]
+    o.w = _ptr(w)
+    ws = _workspace(_size(lib().skls_lstsq_workspace, ctypes.byref(m), ctypes.byref(o)), device)
+    x = torch.empty(m.d, dtype=torch.float64, device=device)
+    info = L.SklsLstsqInfo()
+    st = lib().skls_lstsq(ctypes.byref(m), _ptr(b), ctypes.byref(o), _ptr(x), ctypes.byref(info), _ptr(ws),
+                          ws.numel(), _stream(device))
+    out = {f: getattr(info, f) for f, _ in L.SklsLstsqInfo._fields_ if f != "reserved"}
+    out["status"] = L.STATUS.get(st, st)
+    if st != 0 and not (st == 5 and not raise_noconv):
+        L.check(st)
+    return x, out
+
+
+# ------------------------------------------------------------------ a5
+def leverage_scores(A, t: int, seed: int, Pi2: torch.Tensor):
+    """Squared row norms of ``A R^{-1} Pi2`` (``Pi2``: ``d x k`` float64)."""
+    m, device = _matrix(A)
+    if Pi2.dtype != torch.float64 or not Pi2.is_contiguous() or Pi2.dim() != 2 or Pi2.shape[0] != m.d:
+        raise TypeError("Pi2 must be a contiguous float64 d x k tensor")
+    k = Pi2.shape[1]
+    ws = _workspace(_size(lib().skls_leverage_workspace, ctypes.byref(m), t, k), device)
+    scores = torch.empty(m.n, dtype=torch.float32, device=device)
+    L.check(lib().skls_leverage_scores(ctypes.byref(m), t, seed & 0xFFFFFFFFFFFFFFFF, k, _ptr(Pi2), _ptr(scores),
+                                       _ptr(ws), ws.numel(), _stream(device)))
+    return scores
+
+
+# ------------------------------------------------------------------ a6
+def gram(A: torch.Tensor) -> torch.Tensor:
+    """``A^T A`` (float32 result) of a dense matrix."""
+    m, device = _matrix(A)
+    ws = _workspace(_size(lib().skls_gram_workspace, ctypes.byref(m)), device)
+    C = torch.empty((m.d, m.d), dtype=torch.float32, device=device)
+    L.check(lib().skls_gram(ctypes.byref(m), _ptr(C), _ptr(ws), ws.numel(), _stream(device)))
+    return C
+
+
+class LearnedWorkspace:
+    """Reusable workspace for :func:`learned_grad` at one ``(n, d, t)``."""
+
+    def __init__(self, A: torch.Tensor, t: int):
+        m, device = _matrix(A)
+        self.key = (m.n, m.d, t)
+        self.buf = _workspace(_size(lib().skls_learned_workspace, ctypes.byref(m), t), device)
+
+
+def learned_grad(A: torch.Tensor, C: torch.Tensor, t: int, seed: int, w: torch.Tensor,
+                 ws: LearnedWorkspace | None = None, loss: torch.Tensor | None = None,
+                 grad: torch.Tensor | None = None, grad_scale: float = 1.0, accumulate: bool = False,
+                 want_grad: bool = True):
+    """Distortion loss ``||(S_w A)^T S_w A - C||_F^2`` and ``grad_scale`` times its
+    gradient in ``w`` (added into ``grad`` when ``accumulate``)."""
+    m, device = _matrix(A)
+    if ws is None or ws.key != (m.n, m.d, t):
+        ws = LearnedWorkspace(A, t)
+    loss = torch.empty(1, dtype=torch.float32, device=device) if loss is None else loss
+    if want_grad and grad is None:
+        grad = torch.empty(m.n, dtype=torch.float32, device=device)
+    if accumulate and grad is None:
+        raise ValueError("accumulate needs a grad buffer")
+    L.check(lib().skls_learned_grad(ctypes.byref(m), _ptr(C), t, seed & 0xFFFFFFFFFFFFFFFF, _ptr(w), grad_scale,
+                                    1 if accumulate else 0, _ptr(loss), _ptr(grad) if want_grad else None,
+                                    _ptr(ws.buf), ws.buf.numel(), _stream(device)))
+    return loss, (grad if want_grad else None)
+
+
+def adam_step(w: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float = 1e-2,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    """In-place Adam update of ``w`` (float32 device vectors)."""
+    for t in (w, g, m, v):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != w.numel():
+            raise TypeError("Adam buffers must be contiguous float32 vectors of equal length")
+    L.check(lib().skls_adam_step(w.numel(), _ptr(w), _ptr(g), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                                 _stream(w.device)))
+
+
+def low_rank(A, k: int, eps: float, seed: int):
+    """Rank-``k`` approximation (Section 8); not provided by this build."""
+    m, device = _matrix(A)
+    st = lib().skls_low_rank(ctypes.byref(m), k, eps, seed & 0xFFFFFFFFFFFFFFFF, None, None, None, None, 0,
+                             _stream(device))
+    L.check(st)

@@ -1,0 +1,697 @@
+// C ABI of libskls: argument validation, workspace layout and the order of
+// kernel launches for each entry point.  Declarations and contracts are in
+// include/skls.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "kernels.hpp"
+
+namespace skls {
+
+namespace {
+thread_local char g_err[768] = "";
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = '\0'; }
+const char* last_error() { return g_err; }
+
+int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+size_t dtype_size(int32_t dt) {
+  switch (dt) {
+    case SKLS_F64: return 8;
+    case SKLS_F32: return 4;
+    case SKLS_BF16: return 2;
+    default: return 0;
+  }
+}
+
+int32_t validate_matrix(const skls_matrix* A, bool allow_bf16) {
+  if (A == nullptr) {
+    set_error("matrix descriptor is NULL");
+    return SKLS_ERR_ARG;
+  }
+  if (A->layout != SKLS_DENSE && A->layout != SKLS_CSR) {
+    set_error("unknown layout %d", A->layout);
+    return SKLS_ERR_ARG;
+  }
+  if (dtype_size(A->dtype) == 0 || (!allow_bf16 && A->dtype == SKLS_BF16)) {
+    set_error("unsupported matrix dtype %d", A->dtype);
+    return SKLS_ERR_DTYPE;
+  }
+  if (A->n < 0 || A->d < 1 || A->n >= (int64_t(1) << 31) || A->d >= (int64_t(1) << 31)) {
+    set_error("matrix shape n=%lld d=%lld out of range (need 0 <= n < 2^31, 1 <= d < 2^31)",
+              static_cast<long long>(A->n), static_cast<long long>(A->d));
+    return SKLS_ERR_SHAPE;
+  }
+  if (A->layout == SKLS_DENSE) {
+    if (A->ld < A->d) {
+      set_error("dense leading dimension %lld < d %lld", static_cast<long long>(A->ld), static_cast<long long>(A->d));
+      return SKLS_ERR_SHAPE;
+    }
+    if (A->n > 0 && A->val == nullptr) {
+      set_error("dense values pointer is NULL");
+      return SKLS_ERR_ARG;
+    }
+  } else {
+    if (A->row_ptr == nullptr) {
+      set_error("CSR row_ptr is NULL");
+      return SKLS_ERR_ARG;
+    }
+    if (A->nnz < 0 || (!A->row_ptr_64 && A->nnz >= (int64_t(1) << 31))) {
+      set_error("CSR nnz %lld out of range for the row pointer type", static_cast<long long>(A->nnz));
+      return SKLS_ERR_SHAPE;
+    }
+    if (A->nnz > 0 && (A->col_idx == nullptr || A->val == nullptr)) {
+      set_error("CSR col_idx or val is NULL");
+      return SKLS_ERR_ARG;
+    }
+  }
+  return SKLS_OK;
+}
+
+namespace {
+
+int32_t check_t(int64_t t) {
+  if (t < 1 || t >= (int64_t(1) << 31)) {
+    set_error("t=%lld out of range [1, 2^31)", static_cast<long long>(t));
+    return SKLS_ERR_SHAPE;
+  }
+  return SKLS_OK;
+}
+
+int32_t need_ws(const Arena& ar, const void* ws, size_t ws_bytes) {
+  if (ar.used > 0 && (ws == nullptr || ws_bytes < ar.used)) {
+    set_error("workspace too small: need %zu bytes, have %zu", ar.used, ws == nullptr ? size_t(0) : ws_bytes);
+    return SKLS_ERR_WORKSPACE;
+  }
+  return SKLS_OK;
+}
+
+int32_t read_status(const int32_t* dstatus, hipStream_t s, int32_t* out) {
+  SKLS_TRY_HIP(hipMemcpyAsync(out, dstatus, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SKLS_TRY_HIP(hipStreamSynchronize(s));
+  return SKLS_OK;
+}
+
+// ---------------------------------------------------------------- R of a tall matrix
+struct QrWs {
+  double* gram;
+  size_t gram_bytes;
+  double* G;
+  double* W;
+  int32_t* status;
+  double* RinvT;
+};
+
+QrWs carve_qr(Arena& ar, int64_t m, int64_t d, int64_t dd) {
+  QrWs q;
+  q.gram_bytes = gram_ws_bytes(m, dd);
+  q.gram = ar.take<double>(q.gram_bytes / sizeof(double) + 1);
+  q.G = ar.take<double>(static_cast<size_t>(dd * dd));
+  q.W = ar.take<double>(static_cast<size_t>(d * d));
+  q.status = ar.take<int32_t>(4);
+  q.RinvT = ar.take<double>(static_cast<size_t>(d * d));
+  return q;
+}
+
+// Gram -> Cholesky -> inverse.  G holds (M | v)^T (M | v) afterwards.
+int32_t qr_from(const void* M, int32_t dtype, const void* v, int32_t v_dtype, int64_t m, int64_t d, const QrWs& q,
+                double* R, double* Rinv, double* RinvT, hipStream_t s) {
+  const int64_t dd = d + (v ? 1 : 0);
+  SKLS_TRY(run_gram(M, dtype, d, v, v_dtype, m, d, q.G, q.gram, q.gram_bytes, s));
+  SKLS_TRY(run_cholesky(q.G, dd, d, R, q.status, q.W, s));
+  if (Rinv) SKLS_TRY(run_trinv(R, d, Rinv, RinvT, s));
+  return SKLS_OK;
+}
+
+// ---------------------------------------------------------------- lstsq workspace
+struct LsWs {
+  void* SA;
+  void* Sb;
+  void* sk;
+  size_t sk_bytes;
+  QrWs q;
+  double* R;
+  double* Rinv;
+  double* tmp;
+  double* vp;
+  double* v;
+  double* w;
+  double* y;
+  double* p;
+  double* gsum;
+  double* st;
+  void* U;
+  double* partial;
+  double* red;
+  int32_t nblk;
+};
+
+LsWs carve_ls(Arena& ar, const skls_matrix& A, const skls_lstsq_opts& o) {
+  LsWs L;
+  const bool plain = o.precision == 0;
+  const size_t es = plain ? 8 : 4;
+  const int64_t t = o.t, d = A.d, dd = d + 1;
+  L.SA = ar.take<char>(static_cast<size_t>(t * d) * es);
+  L.Sb = ar.take<char>(static_cast<size_t>(t) * es);
+  L.sk_bytes = sketch_ws_bytes(A, t, o.variant);
+  L.sk = ar.take<char>(L.sk_bytes);
+  L.q = carve_qr(ar, t, d, dd);
+  L.R = ar.take<double>(static_cast<size_t>(d * d));
+  L.Rinv = ar.take<double>(static_cast<size_t>(d * d));
+  L.tmp = ar.take<double>(static_cast<size_t>(d));
+  L.vp = ar.take<double>(static_cast<size_t>(d));
+  L.v = ar.take<double>(static_cast<size_t>(d));
+  L.w = ar.take<double>(static_cast<size_t>(d));
+  L.y = ar.take<double>(static_cast<size_t>(d));
+  L.p = ar.take<double>(static_cast<size_t>(d));
+  L.gsum = ar.take<double>(static_cast<size_t>(dd));
+  L.st = ar.take<double>(LSQR_NSTATE);
+  L.U = ar.take<char>(static_cast<size_t>(A.n) * es);
+  L.nblk = pass_blocks(A);
+  L.partial = ar.take<double>(static_cast<size_t>(L.nblk) * dd);
+  L.red = ar.take<double>(static_cast<size_t>(div_up(L.nblk, 32)) * dd);
+  return L;
+}
+
+void fill_opts(skls_lstsq_opts& o) {
+  if (o.delta <= 0.0) o.delta = 1e-6;
+  if (o.sigma_lb <= 0.0) o.sigma_lb = 0.5;
+  if (o.max_iter <= 0) o.max_iter = 100;
+}
+
+int32_t check_lstsq(const skls_matrix* A, const skls_lstsq_opts* opts) {
+  SKLS_TRY(validate_matrix(A, true));
+  if (opts == nullptr) {
+    set_error("options pointer is NULL");
+    return SKLS_ERR_ARG;
+  }
+  SKLS_TRY(check_t(opts->t));
+  if (opts->t < A->d) {
+    set_error("sketch rows t=%lld must be at least d=%lld", static_cast<long long>(opts->t),
+              static_cast<long long>(A->d));
+    return SKLS_ERR_SHAPE;
+  }
+  if (A->n < A->d) {
+    set_error("least squares needs n >= d");
+    return SKLS_ERR_SHAPE;
+  }
+  if (opts->precision != 0 && opts->precision != 1) {
+    set_error("precision must be 0 (plain) or 1 (mixed)");
+    return SKLS_ERR_ARG;
+  }
+  if (opts->sigma_lb > 1.0 || opts->delta < 0.0) {
+    set_error("need 0 < sigma_lb <= 1 and delta >= 0");
+    return SKLS_ERR_ARG;
+  }
+  return SKLS_OK;
+}
+
+}  // namespace
+}  // namespace skls
+
+using namespace skls;
+
+extern "C" {
+
+const char* skls_status_str(int32_t status) {
+  switch (status) {
+    case SKLS_OK: return "SKLS_OK";
+    case SKLS_ERR_ARG: return "SKLS_ERR_ARG";
+    case SKLS_ERR_SHAPE: return "SKLS_ERR_SHAPE";
+    case SKLS_ERR_DTYPE: return "SKLS_ERR_DTYPE";
+    case SKLS_ERR_RANK: return "SKLS_ERR_RANK";
+    case SKLS_ERR_NOCONV: return "SKLS_ERR_NOCONV";
+    case SKLS_ERR_WORKSPACE: return "SKLS_ERR_WORKSPACE";
+    case SKLS_ERR_DEVICE: return "SKLS_ERR_DEVICE";
+    case SKLS_ERR_NOTIMPL: return "SKLS_ERR_NOTIMPL";
+    default: return "SKLS_ERR_UNKNOWN";
+  }
+}
+
+const char* skls_last_error(void) { return skls::last_error(); }
+
+const char* skls_version(void) { return "skls 0.1.0 gfx950"; }
+
+int32_t skls_hash(int64_t n, int64_t t, uint64_t seed, int64_t start, int32_t* bucket, int8_t* sign, void* stream) {
+  clear_error();
+  SKLS_TRY(check_t(t));
+  if (n < 0 || start < 0) {
+    set_error("n and start must be non-negative");
+    return SKLS_ERR_SHAPE;
+  }
+  return launch_hash(n, static_cast<uint32_t>(t), seed, start, bucket, sign, as_stream(stream));
+}
+
+int32_t skls_sketch_workspace(const skls_matrix* A, int64_t t, int32_t variant, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  SKLS_TRY(check_t(t));
+  if (bytes == nullptr) {
+    set_error("bytes pointer is NULL");
+    return SKLS_ERR_ARG;
+  }
+  if (variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_SORTED) {
+    set_error("unknown sketch variant %d", variant);
+    return SKLS_ERR_ARG;
+  }
+  *bytes = sketch_ws_bytes(*A, t, variant);
+  return SKLS_OK;
+}
+
+int32_t skls_sketch(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed, const float* w,
+                    int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  SKLS_TRY(check_t(t));
+  if (variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_SORTED) {
+    set_error("unknown sketch variant %d", variant);
+    return SKLS_ERR_ARG;
+  }
+  if (SA == nullptr) {
+    set_error("SA is NULL");
+    return SKLS_ERR_ARG;
+  }
+  if ((b == nullptr) != (Sb == nullptr)) {
+    set_error("b and Sb must be given together");
+    return SKLS_ERR_ARG;
+  }
+  if (b != nullptr && b_dtype != SKLS_F64 && b_dtype != SKLS_F32) {
+    set_error("b must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  if (out_dtype != SKLS_F64 && out_dtype != SKLS_F32) {
+    set_error("out_dtype must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  const size_t need = sketch_ws_bytes(*A, t, variant);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) {
+    set_error("sketch workspace too small: need %zu bytes", need);
+    return SKLS_ERR_WORKSPACE;
+  }
+  return run_sketch(*A, b, b_dtype, t, seed, w, variant, SA, Sb, out_dtype, ws, ws_bytes, as_stream(stream));
+}
+
+int32_t skls_qr_r_workspace(int64_t m, int64_t d, size_t* bytes) {
+  clear_error();
+  if (bytes == nullptr || d < 1 || m < d) {
+    set_error("need bytes != NULL and m >= d >= 1");
+    return SKLS_ERR_SHAPE;
+  }
+  Arena ar(nullptr, 0);
+  carve_qr(ar, m, d, d);
+  *bytes = ar.used;
+  return SKLS_OK;
+}
+
+int32_t skls_qr_r(const void* M, int32_t dtype, int64_t m, int64_t d, double* R, double* Rinv, void* ws,
+                  size_t ws_bytes, void* stream) {
+  clear_error();
+  if (M == nullptr || R == nullptr) {
+    set_error("M and R must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  if (dtype != SKLS_F64 && dtype != SKLS_F32) {
+    set_error("M must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  if (d < 1 || m < d || d > 8192 || m >= (int64_t(1) << 31)) {
+    set_error("need 1 <= d <= 8192 and d <= m < 2^31");
+    return SKLS_ERR_SHAPE;
+  }
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  QrWs q = carve_qr(ar, m, d, d);
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  SKLS_TRY(qr_from(M, dtype, nullptr, SKLS_F64, m, d, q, R, Rinv, q.RinvT, s));
+  int32_t st = 0;
+  SKLS_TRY(read_status(q.status, s, &st));
+  if (st) {
+    set_error("matrix is numerically rank deficient");
+    return SKLS_ERR_RANK;
+  }
+  return SKLS_OK;
+}
+
+int32_t skls_lstsq_workspace(const skls_matrix* A, const skls_lstsq_opts* opts, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(check_lstsq(A, opts));
+  if (bytes == nullptr) {
+    set_error("bytes pointer is NULL");
+    return SKLS_ERR_ARG;
+  }
+  skls_lstsq_opts o = *opts;
+  fill_opts(o);
+  Arena ar(nullptr, 0);
+  carve_ls(ar, *A, o);
+  *bytes = ar.used;
+  return SKLS_OK;
+}
+
+int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_lstsq_opts* opts, double* x,
+                   skls_lstsq_info* info, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKLS_TRY(check_lstsq(A, opts));
+  if (b == nullptr || x == nullptr) {
+    set_error("b and x must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  if (A->d > 8192) {
+    set_error("lstsq supports d <= 8192");
+    return SKLS_ERR_SHAPE;
+  }
+  skls_lstsq_opts o = *opts;
+  fill_opts(o);
+  const bool plain = o.precision == 0;
+  const int64_t d = A->d, dd = d + 1;
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  LsWs L = carve_ls(ar, *A, o);
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  skls_lstsq_info inf;
+  std::memset(&inf, 0, sizeof inf);
+  inf.resid_norm = inf.grad_norm = inf.ratio_bound = -1.0;
+
+  hipEvent_t ev[4];
+  for (auto& e : ev) SKLS_TRY_HIP(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int k = 0; k < 4; ++k) (void)hipEventDestroy(e[k]);
+    }
+  } guard{ev};
+
+  // --- sketch-and-solve (Section 7): S [A | b], R of S A, x~ = R^{-1} R^{-T} (S A)^T S b
+  const int32_t sk_dtype = plain ? SKLS_F64 : SKLS_F32;
+  SKLS_TRY_HIP(hipEventRecord(ev[0], s));
+  SKLS_TRY(run_sketch(*A, b, SKLS_F64, o.t, o.seed, o.w, o.variant, L.SA, L.Sb, sk_dtype, L.sk, L.sk_bytes, s));
+  SKLS_TRY_HIP(hipEventRecord(ev[1], s));
+  SKLS_TRY(qr_from(L.SA, sk_dtype, L.Sb, sk_dtype, o.t, d, L.q, L.R, L.Rinv, L.q.RinvT, s));
+  SKLS_TRY(run_solve_from_gram(L.Rinv, L.q.RinvT, L.q.G + d * dd, d, x, L.tmp, s));
+  SKLS_TRY_HIP(hipEventRecord(ev[2], s));
+  int32_t rank_bad = 0;
+  double sb_norm2 = 0.0;  // ||S b||^2, close to ||b||^2 for an embedding
+  SKLS_TRY_HIP(hipMemcpyAsync(&sb_norm2, L.q.G + d * dd + d, sizeof(double), hipMemcpyDeviceToHost, s));
+  SKLS_TRY(read_status(L.q.status, s, &rank_bad));
+  float ms = 0.0f;
+  SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  inf.ms_sketch = ms;
+  SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+  inf.ms_qr = ms;
+  if (rank_bad) {
+    if (info) *info = inf;
+    set_error("the sketch S A is numerically rank deficient");
+    return SKLS_ERR_RANK;
+  }
+  if (o.sketch_only) {
+    if (info) *info = inf;
+    return SKLS_OK;
+  }
+
+  // --- R-preconditioned LSQR on M = A R^{-1} (Section 7.7), with float64
+  //     residual refinement.  Plain: every pass in float64.  Mixed: inner
+  //     passes in float32, each outer step restarts from the float64 residual.
+  const double D = (1.0 + o.delta) * (1.0 + o.delta) - 1.0;
+  const double thr = o.sigma_lb * std::sqrt(D / (1.0 + D));
+  double hs[LSQR_NSTATE];
+  int32_t status = SKLS_ERR_NOCONV;
+  PassArgs pa;
+  pa.A = A;
+  pa.partial = L.partial;
+  pa.nblk = L.nblk;
+  pa.U = L.U;
+  pa.u_f64 = plain ? 1 : 0;
+  int outer = 0;
+  for (;;) {
+    // explicit residual r = b - A x and g = R^{-T} A^T r, float64 accumulation
+    SKLS_TRY(run_scale(x, d, -1.0, L.p, s));
+    pa.p = L.p;
+    pa.coef = L.st + LSQR_ONE;
+    pa.Z = b;
+    pa.z_is_b = 1;
+    pa.acc_f64 = 1;
+    if (outer == 0) {
+      static const double kOne = 1.0;
+      SKLS_TRY_HIP(hipMemcpyAsync(L.st + LSQR_ONE, &kOne, sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    SKLS_TRY(run_pass(pa, s));
+    SKLS_TRY(run_reduce_partials(L.partial, L.nblk, d, L.gsum, L.red, s));
+    SKLS_TRY(run_gemv(L.q.RinvT, d, L.gsum, L.vp, s));
+    SKLS_TRY(run_lsqr_init(L.gsum, L.vp, d, L.v, L.w, L.y, L.st, s));
+    SKLS_TRY_HIP(hipMemcpyAsync(hs, L.st, sizeof hs, hipMemcpyDeviceToHost, s));
+    SKLS_TRY_HIP(hipStreamSynchronize(s));
+    const double rn = hs[LSQR_RNORM], gn = hs[LSQR_ARNORM];
+    inf.resid_norm = rn;
+    inf.grad_norm = gn;
+    if (!(std::isfinite(rn) && std::isfinite(gn))) {
+      set_error("non-finite residual (check A and b for NaN/Inf)");
+      status = SKLS_ERR_ARG;
+      break;
+    }
+    if (gn <= thr * rn || hs[LSQR_DONE] != 0.0) {
+      inf.certified = (gn <= thr * rn) ? 1 : 0;
+      status = SKLS_OK;
+      break;
+    }
+    // A consistent system (b in the range of A) has min ||Ax - b|| = 0, where
+    // no ratio can be certified: stop once the residual is at rounding level.
+    if (rn <= 1e-13 * std::sqrt(sb_norm2)) {
+      status = SKLS_OK;
+      break;
+    }
+    if (inf.iterations >= o.max_iter) break;
+    // inner LSQR on min || M y - r ||, y = 0 start
+    const double ratio0 = gn / rn;
+    const double target = plain ? 0.5 * thr : std::fmax(0.5 * thr, 1e-4 * ratio0);
+    pa.acc_f64 = plain ? 1 : 0;
+    pa.Z = L.U;
+    pa.z_is_b = 0;
+    pa.coef = L.st + LSQR_COEF;
+    SKLS_TRY(run_gemv(L.Rinv, d, L.v, L.p, s));
+    while (inf.iterations < o.max_iter) {
+      SKLS_TRY(run_pass(pa, s));
+      SKLS_TRY(run_reduce_partials(L.partial, L.nblk, d, L.gsum, L.red, s));
+      SKLS_TRY(run_gemv(L.q.RinvT, d, L.gsum, L.vp, s));
+      SKLS_TRY(run_lsqr_step(L.gsum, L.vp, d, L.v, L.w, L.y, L.st, s));
+      SKLS_TRY(run_gemv(L.Rinv, d, L.v, L.p, s));
+      ++inf.iterations;
+      SKLS_TRY_HIP(hipMemcpyAsync(hs, L.st, sizeof hs, hipMemcpyDeviceToHost, s));
+      SKLS_TRY_HIP(hipStreamSynchronize(s));
+      if (hs[LSQR_DONE] != 0.0 || hs[LSQR_EST_AR] <= target * hs[LSQR_EST_R]) break;
+    }
+    // x += R^{-1} y
+    SKLS_TRY(run_gemv(L.Rinv, d, L.y, L.tmp, s));
+    SKLS_TRY(run_add(x, L.tmp, d, s));
+    ++outer;
+  }
+  inf.refinements = outer;
+  SKLS_TRY_HIP(hipEventRecord(ev[3], s));
+  SKLS_TRY_HIP(hipEventSynchronize(ev[3]));
+  SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+  inf.ms_iter = ms;
+  {
+    const double e = inf.grad_norm / o.sigma_lb;
+    const double r2 = inf.resid_norm * inf.resid_norm - e * e;
+    inf.ratio_bound = (r2 > 0.0) ? std::sqrt(1.0 + e * e / r2) : INFINITY;
+  }
+  if (info) *info = inf;
+  if (status == SKLS_ERR_NOCONV) set_error("LSQR did not certify the target within max_iter=%d", o.max_iter);
+  return status;
+}
+
+int32_t skls_leverage_workspace(const skls_matrix* A, int64_t t, int32_t k, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  SKLS_TRY(check_t(t));
+  if (bytes == nullptr || k < 1 || k > 64 || t < A->d) {
+    set_error("need bytes != NULL, 1 <= k <= 64, t >= d");
+    return SKLS_ERR_ARG;
+  }
+  const size_t es = A->dtype == SKLS_F64 ? 8 : 4;
+  Arena ar(nullptr, 0);
+  ar.take<char>(static_cast<size_t>(t * A->d) * es);
+  ar.take<char>(sketch_ws_bytes(*A, t, SKLS_SKETCH_AUTO));
+  carve_qr(ar, t, A->d, A->d);
+  ar.take<double>(static_cast<size_t>(A->d * A->d) * 2);
+  ar.take<float>(static_cast<size_t>(A->d) * k);
+  *bytes = ar.used;
+  return SKLS_OK;
+}
+
+int32_t skls_leverage_scores(const skls_matrix* A, int64_t t, uint64_t seed, int32_t k, const double* Pi2,
+                             float* scores, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  SKLS_TRY(check_t(t));
+  if (k < 1 || k > 64 || Pi2 == nullptr || scores == nullptr) {
+    set_error("need 1 <= k <= 64 and non-NULL Pi2, scores");
+    return SKLS_ERR_ARG;
+  }
+  if (t < A->d || A->d > 8192) {
+    set_error("need d <= t and d <= 8192");
+    return SKLS_ERR_SHAPE;
+  }
+  hipStream_t s = as_stream(stream);
+  const int32_t sk_dtype = A->dtype == SKLS_F64 ? SKLS_F64 : SKLS_F32;
+  const size_t es = sk_dtype == SKLS_F64 ? 8 : 4;
+  const int64_t d = A->d;
+  Arena ar(ws, ws_bytes);
+  void* SA = ar.take<char>(static_cast<size_t>(t * d) * es);
+  const size_t skb = sketch_ws_bytes(*A, t, SKLS_SKETCH_AUTO);
+  void* sk = ar.take<char>(skb);
+  QrWs q = carve_qr(ar, t, d, d);
+  double* R = ar.take<double>(static_cast<size_t>(d * d));
+  double* Rinv = ar.take<double>(static_cast<size_t>(d * d));
+  float* T = ar.take<float>(static_cast<size_t>(d) * k);
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  SKLS_TRY(run_sketch(*A, nullptr, SKLS_F64, t, seed, nullptr, SKLS_SKETCH_AUTO, SA, nullptr, sk_dtype, sk, skb, s));
+  SKLS_TRY(qr_from(SA, sk_dtype, nullptr, SKLS_F64, t, d, q, R, Rinv, q.RinvT, s));
+  SKLS_TRY(run_rinv_times(Rinv, d, Pi2, k, T, s));
+  SKLS_TRY(run_leverage(*A, T, k, scores, s));
+  int32_t st = 0;
+  SKLS_TRY(read_status(q.status, s, &st));
+  if (st) {
+    set_error("the sketch S A is numerically rank deficient");
+    return SKLS_ERR_RANK;
+  }
+  return SKLS_OK;
+}
+
+int32_t skls_gram_workspace(const skls_matrix* A, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (bytes == nullptr) {
+    set_error("bytes pointer is NULL");
+    return SKLS_ERR_ARG;
+  }
+  Arena ar(nullptr, 0);
+  const size_t gb = gram_ws_bytes(A->n > 0 ? A->n : 1, A->d);
+  ar.take<char>(gb);
+  ar.take<double>(static_cast<size_t>(A->d * A->d));
+  *bytes = ar.used;
+  return SKLS_OK;
+}
+
+int32_t skls_gram(const skls_matrix* A, float* C, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (A->layout != SKLS_DENSE) {
+    set_error("skls_gram supports dense A only");
+    return SKLS_ERR_NOTIMPL;
+  }
+  if (C == nullptr) {
+    set_error("C is NULL");
+    return SKLS_ERR_ARG;
+  }
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  const int64_t m = A->n > 0 ? A->n : 1;
+  const size_t gb = gram_ws_bytes(m, A->d);
+  double* gw = reinterpret_cast<double*>(ar.take<char>(gb));
+  double* G = ar.take<double>(static_cast<size_t>(A->d * A->d));
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  if (A->n == 0) return launch_fill_zero(C, static_cast<size_t>(A->d * A->d) * sizeof(float), s);
+  SKLS_TRY(run_gram(A->val, A->dtype, A->ld, nullptr, SKLS_F64, A->n, A->d, G, gw, gb, s));
+  return run_convert_f64_to_f32(G, C, A->d * A->d, s);
+}
+
+int32_t skls_learned_workspace(const skls_matrix* A, int64_t t, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, false));
+  SKLS_TRY(check_t(t));
+  if (bytes == nullptr) {
+    set_error("bytes pointer is NULL");
+    return SKLS_ERR_ARG;
+  }
+  const int64_t d = A->d;
+  Arena ar(nullptr, 0);
+  ar.take<float>(static_cast<size_t>(t * d));
+  ar.take<char>(sketch_ws_bytes(*A, t, SKLS_SKETCH_SORTED));
+  ar.take<char>(gram_ws_bytes(t, d));
+  ar.take<double>(static_cast<size_t>(d * d));
+  ar.take<float>(static_cast<size_t>(d * d));
+  ar.take<float>(static_cast<size_t>(t * d));
+  *bytes = ar.used;
+  return SKLS_OK;
+}
+
+int32_t skls_learned_grad(const skls_matrix* A, const float* C, int64_t t, uint64_t seed, const float* w,
+                          float grad_scale, int32_t accumulate, float* loss, float* grad_w, void* ws, size_t ws_bytes,
+                          void* stream) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, false));
+  SKLS_TRY(check_t(t));
+  if (A->layout != SKLS_DENSE || A->dtype != SKLS_F32) {
+    set_error("learned values need a dense float32 A");
+    return SKLS_ERR_DTYPE;
+  }
+  if (C == nullptr || w == nullptr || loss == nullptr) {
+    set_error("C, w and loss must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  if (A->d > 4096) {
+    set_error("learned values support d <= 4096");
+    return SKLS_ERR_SHAPE;
+  }
+  hipStream_t s = as_stream(stream);
+  const int64_t d = A->d;
+  Arena ar(ws, ws_bytes);
+  float* Y = ar.take<float>(static_cast<size_t>(t * d));
+  const size_t skb = sketch_ws_bytes(*A, t, SKLS_SKETCH_SORTED);
+  void* sk = ar.take<char>(skb);
+  const size_t gb = gram_ws_bytes(t, d);
+  double* gw = reinterpret_cast<double*>(ar.take<char>(gb));
+  double* P = ar.take<double>(static_cast<size_t>(d * d));
+  float* E = ar.take<float>(static_cast<size_t>(d * d));
+  float* G = ar.take<float>(static_cast<size_t>(t * d));
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  SKLS_TRY(run_sketch(*A, nullptr, SKLS_F64, t, seed, w, SKLS_SKETCH_SORTED, Y, nullptr, SKLS_F32, sk, skb, s));
+  SKLS_TRY(run_gram(Y, SKLS_F32, d, nullptr, SKLS_F64, t, d, P, gw, gb, s));
+  SKLS_TRY(run_learned_E(P, d, C, d, E, loss, s));
+  if (grad_w == nullptr) return SKLS_OK;
+  SKLS_TRY(run_learned_G(Y, E, t, d, G, s));
+  return run_learned_gather(*A, G, static_cast<uint32_t>(t), seed, grad_scale, accumulate != 0, grad_w, s);
+}
+
+int32_t skls_adam_step(int64_t n, float* w, const float* g, float* m, float* v, int32_t step, float lr, float beta1,
+                       float beta2, float eps, void* stream) {
+  clear_error();
+  if (n < 0 || step < 1 || (n > 0 && (w == nullptr || g == nullptr || m == nullptr || v == nullptr))) {
+    set_error("need n >= 0, step >= 1 and non-NULL buffers");
+    return SKLS_ERR_ARG;
+  }
+  if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f)) {
+    set_error("bad Adam hyper-parameters");
+    return SKLS_ERR_ARG;
+  }
+  return run_adam(n, w, g, m, v, step, lr, beta1, beta2, eps, as_stream(stream));
+}
+
+int32_t skls_low_rank(const skls_matrix* A, int64_t k, double eps, uint64_t seed, double* L, double* D, double* W,
+                      void* ws, size_t ws_bytes, void* stream) {
+  (void)A;
+  (void)k;
+  (void)eps;
+  (void)seed;
+  (void)L;
+  (void)D;
+  (void)W;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  set_error("low-rank approximation is not provided by this build");
+  return SKLS_ERR_NOTIMPL;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal launchers shared by the C ABI (api.cpp) and the kernel sources.
+#pragma once
+
+#include "common.hpp"
+
+namespace skls {
+
+// ---------------------------------------------------------------- sketch.hip
+int32_t launch_hash(int64_t n, uint32_t t, uint64_t seed, int64_t start, int32_t* bucket, int8_t* sign,
+                    hipStream_t s);
+int32_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// Bucket plan: off[t+1] (exclusive offsets) and perm[n] (rows grouped by bucket).
+struct BucketPlan {
+  int32_t* count;  // [t]
+  int32_t* off;    // [t+1]
+  int32_t* rank;   // [n]
+  int32_t* perm;   // [n]
+  int32_t* bsum;   // scan block sums
+};
+size_t plan_bytes(int64_t n, int64_t t);
+BucketPlan carve_plan(Arena& ar, int64_t n, int64_t t);
+int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, hipStream_t s);
+
+int32_t choose_sketch_variant(const skls_matrix& A, int64_t t, int32_t variant);
+size_t sketch_ws_bytes(const skls_matrix& A, int64_t t, int32_t variant);
+int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
+                   const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
+                   size_t ws_bytes, hipStream_t s);
+
+// ---------------------------------------------------------------- dense.hip
+// Gram of the augmented matrix [M | v] (m x dd, dd = d or d+1), float64.
+size_t gram_ws_bytes(int64_t m, int64_t dd);
+int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,
+                 double* G /* dd x dd */, void* ws, size_t ws_bytes, hipStream_t s);
+// Cholesky of the leading d x d block of G (leading dimension ldg): R upper,
+// status[0] = 0 ok / 1 rank deficient.
+int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t* status, double* scratch,
+                     hipStream_t s);
+int32_t run_trinv(const double* R, int64_t d, double* Rinv, double* RinvT, hipStream_t s);
+// y = op(M) x for a d x d row-major float64 M (op = identity).
+int32_t run_gemv(const double* M, int64_t d, const double* x, double* y, hipStream_t s);
+// x = Rinv (RinvT c): sketch-and-solve from the Gram column c = M^T v.
+// T = Rinv P (d x k), float32 result.
+int32_t run_rinv_times(const double* Rinv, int64_t d, const double* P, int32_t k, float* T, hipStream_t s);
+int32_t run_solve_from_gram(const double* Rinv, const double* RinvT, const double* c, int64_t d, double* x,
+                            double* tmp, hipStream_t s);
+
+// ---------------------------------------------------------------- lsqr.hip
+// One pass over A: U_new[i] = A[i,:] p + coef * Z[i]; partial sums of
+// ||U_new||^2 and A^T U_new per block.  Precision: TA = float or double.
+struct PassArgs {
+  const skls_matrix* A;
+  const double* p;      // [d] (float64, converted on load)
+  const double* coef;   // device scalar
+  const void* Z;        // [n]: U (same type as U) or b (float64)
+  int32_t z_is_b;       // 1: Z is float64 b, 0: Z is U
+  void* U;              // [n], float64 or float32 (u_f64)
+  int32_t u_f64;
+  int32_t acc_f64;      // accumulate in float64
+  double* partial;      // [nblk][d+1]
+  int32_t nblk;
+};
+int32_t pass_blocks(const skls_matrix& A);
+int32_t run_pass(const PassArgs& a, hipStream_t s);
+// Sum partial[nblk][d+1] into out[d+1].
+int32_t run_reduce_partials(const double* partial, int32_t nblk, int64_t d, double* out, double* tmp,
+                            hipStream_t s);
+
+// Device LSQR state (float64 slots).
+enum {
+  LSQR_ALPHA = 0,
+  LSQR_BETA,
+  LSQR_RHOBAR,
+  LSQR_PHIBAR,
+  LSQR_COEF,
+  LSQR_RNORM,
+  LSQR_ARNORM,
+  LSQR_EST_R,
+  LSQR_EST_AR,
+  LSQR_ONE,
+  LSQR_DONE,
+  LSQR_NSTATE
+};
+int32_t run_lsqr_init(const double* gsum, const double* vp, int64_t d, double* v, double* w, double* y, double* st,
+                      hipStream_t s);
+int32_t run_lsqr_step(const double* gsum, const double* vp, int64_t d, double* v, double* w, double* y, double* st,
+                      hipStream_t s);
+// y = a * x (d-vectors); x += t.
+int32_t run_scale(const double* x, int64_t d, double a, double* y, hipStream_t s);
+int32_t run_add(double* x, const double* t, int64_t d, hipStream_t s);
+
+// ---------------------------------------------------------------- leverage.hip
+int32_t run_leverage(const skls_matrix& A, const float* T, int32_t k, float* scores, hipStream_t s);
+
+// ---------------------------------------------------------------- learned.hip
+int32_t run_learned_E(const double* P, int64_t ldp, const float* C, int64_t d, float* E, float* loss,
+                      hipStream_t s);
+int32_t run_learned_G(const float* Y, const float* E, int64_t t, int64_t d, float* G, hipStream_t s);
+int32_t run_learned_gather(const skls_matrix& A, const float* G, uint32_t t, uint64_t seed, float scale,
+                           bool accumulate, float* grad, hipStream_t s);
+int32_t run_adam(int64_t n, float* w, const float* g, float* m, float* v, int32_t step, float lr, float b1,
+                 float b2, float eps, hipStream_t s);
+int32_t run_convert_f64_to_f32(const double* in, float* out, int64_t count, hipStream_t s);
+
+}  // namespace skls

@@ -1,0 +1,91 @@
+"""Training of learned per-row sketch values on the GPU.
+
+The values ``w`` start at the random signs of ``D`` (the plain sparse
+embedding of Section 2) and follow Adam on the mean normalised distortion
+``||(S_w A)^T S_w A - A^T A||_F^2 / ||A^T A||_F^2`` over minibatches of
+training matrices; ``h`` stays hashed.  Loss, gradient (forward sketch,
+Gram, ``4 Y E`` and the gather backward) and the Adam update all run in the
+library's kernels; this module only orders the calls.  When the trained
+values do not lower the mean distortion on held-out matrices, the plain
+signs are kept.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import api
+
+
+@dataclass
+class TrainResult:
+    w: torch.Tensor                 # values to use (learned, or the signs on fallback)
+    learned: torch.Tensor           # trained values
+    used_learned: bool
+    val_plain: float                # mean normalised distortion on the validation set
+    val_learned: float
+    history: list = field(default_factory=list)
+
+
+def signs(n: int, t: int, seed: int, device) -> torch.Tensor:
+    _, s = api.hash_rows(n, t, seed, device=device)
+    return s.to(torch.float32)
+
+
+def prepare(mats: list[torch.Tensor], t: int, seed: int):
+    """Gram matrices and normalisers ``||A^T A||_F^2`` (the loss at ``w = 0``)."""
+    n = mats[0].shape[0]
+    dev = mats[0].device
+    ws = api.LearnedWorkspace(mats[0], t)
+    zero = torch.zeros(n, dtype=torch.float32, device=dev)
+    grams, norms = [], []
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    for A in mats:
+        C = api.gram(A)
+        api.learned_grad(A, C, t, seed, zero, ws=ws, loss=loss, want_grad=False)
+        grams.append(C)
+        norms.append(float(loss.item()))
+    return grams, norms, ws
+
+
+def distortions(mats, grams, norms, t: int, seed: int, w: torch.Tensor, ws=None) -> np.ndarray:
+    """Normalised distortion of each matrix for values ``w``."""
+    loss = torch.empty(1, dtype=torch.float32, device=w.device)
+    out = []
+    for A, C, nrm in zip(mats, grams, norms):
+        api.learned_grad(A, C, t, seed, w, ws=ws, loss=loss, want_grad=False)
+        out.append(float(loss.item()) / nrm)
+    return np.array(out)
+
+
+def train(train_mats, val_mats, t: int, seed: int, steps: int = 300, lr: float = 1e-2, batch: int = 16,
+          rng_seed: int = 0, log_every: int = 0) -> TrainResult:
+    n = train_mats[0].shape[0]
+    dev = train_mats[0].device
+    grams, norms, ws = prepare(train_mats, t, seed)
+    vgrams, vnorms, _ = prepare(val_mats, t, seed)
+    w = signs(n, t, seed, dev)
+    w_plain = w.clone()
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    g = torch.empty_like(w)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(rng_seed)
+    hist = []
+    bsz = min(batch, len(train_mats))
+    for step in range(1, steps + 1):
+        idx = rng.choice(len(train_mats), size=bsz, replace=False)
+        for j, i in enumerate(idx):
+            api.learned_grad(train_mats[i], grams[i], t, seed, w, ws=ws, loss=loss, grad=g,
+                             grad_scale=1.0 / (bsz * norms[i]), accumulate=j > 0)
+        api.adam_step(w, g, m, v, step, lr)
+        if log_every and (step % log_every == 0 or step == steps):
+            hist.append((step, float(distortions(val_mats, vgrams, vnorms, t, seed, w, ws).mean())))
+    d_plain = float(distortions(val_mats, vgrams, vnorms, t, seed, w_plain, ws).mean())
+    d_learned = float(distortions(val_mats, vgrams, vnorms, t, seed, w, ws).mean())
+    use = d_learned < d_plain
+    return TrainResult(w=w if use else w_plain, learned=w, used_learned=use, val_plain=d_plain,
+                       val_learned=d_learned, history=hist)

@@ -1,0 +1,135 @@
+"""GPU parity: approximate leverage scores (Section 6) and the learned sketch
+values (distortion loss, gradient, Adam, training) against the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_util import dev, up, up_bf16, up_csr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_1207_6365_amd as sk
+
+    return sk
+
+
+def test_leverage_small_workload_csr(sk):
+    A, b, _ = W.lstsq_small()
+    seed, t, k = W.sketch_seed(0), 4000, 32
+    Pi2 = W.gaussian_matrix(7, A.d, k, scale=1 / np.sqrt(k))
+    got = sk.leverage_scores(up_csr(A), t, seed, up(Pi2)).cpu().numpy()
+    ref = O.leverage_approx(O.MatrixOp(A), seed, t, Pi2)
+    assert np.max(np.abs(got - ref) / ref) <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_leverage_dense_pareto_rows(sk, storage):
+    n, d, t, k = 1 << 14, 64, 4096, 32
+    A, b, _ = W.pareto_rows(n=n, d=d, storage=storage)
+    Af = (W.bf16_to_f32(A) if storage == "bf16" else A).astype(np.float64)
+    Ag = up_bf16(A) if storage == "bf16" else up(A)
+    seed = W.sketch_seed(1)
+    Pi2 = W.gaussian_matrix(8, d, k, scale=1 / np.sqrt(k))
+    got = sk.leverage_scores(Ag, t, seed, up(Pi2)).cpu().numpy()
+    ref = O.leverage_approx(Af, seed, t, Pi2)
+    # float32 sketch and float32 accumulation of the d-term products
+    assert np.max(np.abs(got - ref) / ref) <= 1e-4
+
+
+def test_leverage_identity_projection_sandwich(sk):
+    # Pi2 = I: scores are the row norms of A R^{-1}; their ratio to the exact
+    # leverage lies in [sigma_min^2, sigma_max^2] of A R^{-1}
+    n, d, t = 20000, 16, 2000
+    g = np.random.default_rng(3)
+    A = g.standard_normal((n, d)) * (1 + g.pareto(1.5, size=n))[:, None]
+    seed = 12
+    got = sk.leverage_scores(up(A), t, seed, up(np.eye(d))).cpu().numpy().astype(np.float64)
+    exact = O.leverage_exact(A)
+    R = O.sketch_r(A, seed, t)
+    sv = np.linalg.svd(A @ np.linalg.inv(R), compute_uv=False)
+    ratio = got / exact
+    assert ratio.min() >= sv.min() ** 2 * (1 - 1e-5)
+    assert ratio.max() <= sv.max() ** 2 * (1 + 1e-5)
+    assert abs(got.sum() - d) <= 0.5 * d
+
+
+def test_gram_matches_numpy(sk):
+    g = np.random.default_rng(4)
+    for n, d in [(32768, 64), (1000, 5), (4099, 130)]:
+        A = g.standard_normal((n, d)).astype(np.float32)
+        C = sk.gram(up(A)).cpu().numpy()
+        ref = A.astype(np.float64).T @ A.astype(np.float64)
+        assert np.max(np.abs(C - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n,d,t", [(4096, 16, 128), (32768, 64, 1024)])
+def test_learned_loss_and_gradient(sk, n, d, t):
+    make, _ = W.learned_family(num=4, n=n, d=d)
+    A = make(1)
+    seed = W.sketch_seed(0)
+    w = np.random.default_rng(5).standard_normal(n).astype(np.float32)
+    Ag = up(A)
+    C = sk.gram(Ag)
+    loss, grad = sk.learned_grad(Ag, C, t, seed, up(w))
+    L_o, g_o = O.distortion_grad(A.astype(np.float64), seed, t, w.astype(np.float64))
+    assert abs(loss.item() - L_o) <= 1e-4 * L_o
+    gg = grad.cpu().numpy()
+    assert np.linalg.norm(gg - g_o) <= 1e-4 * np.linalg.norm(g_o)
+    # scaled accumulation: grad2 = grad + 0.5 grad
+    g2 = grad.clone()
+    sk.learned_grad(Ag, C, t, seed, up(w), loss=loss, grad=g2, grad_scale=0.5, accumulate=True)
+    assert torch.allclose(g2, 1.5 * grad, rtol=1e-5, atol=1e-6 * float(grad.abs().max()))
+
+
+def test_learned_plain_signs_match_closed_form_expectation(sk):
+    # mean distortion of random-sign sketches over seeds vs the closed form
+    n, d, t = 2048, 8, 64
+    A = np.random.default_rng(6).standard_normal((n, d)).astype(np.float32)
+    Ag = up(A)
+    C = sk.gram(Ag)
+    vals = []
+    for seed in range(200):
+        _, s = sk.hash_rows(n, t, seed)
+        loss, _ = sk.learned_grad(Ag, C, t, seed, s.to(torch.float32), want_grad=False)
+        vals.append(loss.item())
+    vals = np.array(vals)
+    ref = O.expected_plain_distortion(A.astype(np.float64), t)
+    assert abs(vals.mean() - ref) <= 5 * vals.std(ddof=1) / np.sqrt(len(vals))
+
+
+def test_adam_matches_oracle(sk):
+    n = 1000
+    g = np.random.default_rng(7)
+    w0 = g.standard_normal(n).astype(np.float32)
+    opt = O.Adam(n, lr=0.01)
+    w_o = w0.astype(np.float64)
+    wt, m, v = up(w0), torch.zeros(n, device=dev()), torch.zeros(n, device=dev())
+    for step in range(1, 6):
+        gr = g.standard_normal(n).astype(np.float32)
+        w_o = opt.step(w_o, gr.astype(np.float64))
+        sk.adam_step(wt, up(gr), m, v, step, lr=0.01)
+    assert np.allclose(wt.cpu().numpy(), w_o, rtol=1e-5, atol=1e-6)
+
+
+def test_training_lowers_distortion_on_held_out_matrices(sk):
+    from paper_1207_6365_amd import train
+
+    n, d, t = 8192, 32, 256
+    make, _ = W.learned_family(num=40, n=n, d=d, seed=777)
+    mats = [up(make(m)) for m in range(40)]
+    seed = W.sketch_seed(0)
+    res = train.train(mats[:24], mats[24:32], t, seed, steps=150, lr=2e-2, batch=8)
+    grams, norms, ws = train.prepare(mats[32:], t, seed)
+    plain = train.distortions(mats[32:], grams, norms, t, seed, train.signs(n, t, seed, dev()), ws)
+    learned = train.distortions(mats[32:], grams, norms, t, seed, res.learned, ws)
+    # the learned values must do better on average than the random signs on
+    # matrices never seen in training (and the fallback must pick them)
+    assert learned.mean() < plain.mean()
+    assert res.used_learned
+    print(f"test distortion plain {plain.mean():.4f} learned {learned.mean():.4f}")

@@ -1,0 +1,140 @@
+"""GPU parity: R of a tall matrix, sketch-and-solve (Section 7 regression
+theorem) and R-preconditioned LSQR (Section 7.7) against the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_util import up, up_bf16, up_csr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_1207_6365_amd as sk
+
+    return sk
+
+
+@pytest.mark.parametrize("m,d,dtype", [(5000, 30, torch.float64), (3000, 7, torch.float32), (200, 200, torch.float64),
+                                       (20000, 130, torch.float64)])
+def test_qr_r_matches_householder(sk, m, d, dtype):
+    g = np.random.default_rng(d)
+    M = g.standard_normal((m, d)) * (1 + np.arange(d))[None, :] ** 0.5
+    if dtype == torch.float32:
+        M = M.astype(np.float32)
+    R, Rinv = sk.qr_r(up(M))
+    R, Rinv = R.cpu().numpy(), Rinv.cpu().numpy()
+    _, R_o = O.householder_qr(M.astype(np.float64))
+    kappa = np.linalg.cond(R_o)
+    assert np.allclose(np.tril(R, -1), 0.0)
+    assert np.linalg.norm(R - R_o) <= 1e-13 * kappa * np.linalg.norm(R_o) * d
+    assert np.linalg.norm(R @ Rinv - np.eye(d)) <= 1e-12 * kappa * d
+
+
+def test_qr_r_rank_deficient(sk):
+    M = np.random.default_rng(0).standard_normal((500, 6))
+    M[:, 5] = M[:, 1] - 3 * M[:, 2]
+    with pytest.raises(sk.SklsError) as e:
+        sk.qr_r(up(M))
+    assert e.value.status == 4
+    M[:, 5] = 0.0
+    with pytest.raises(sk.SklsError):
+        sk.qr_r(up(M))
+
+
+def _small():
+    A, b, _ = W.lstsq_small()
+    op = O.MatrixOp(A)
+    Ad = op.dense()
+    return A, b, op, Ad, O.lstsq_exact(Ad, b)
+
+
+def test_sketch_and_solve_parity_small_workload(sk):
+    A, b, op, Ad, xs = _small()
+    seed, t = W.sketch_seed(0), 4000
+    x_g, info = sk.lstsq(up_csr(A), up(b), t, seed, sketch_only=True)
+    x_o, *_ = O.sketch_and_solve(op, b, seed, t)
+    x_g = x_g.cpu().numpy()
+    rho_g = O.residual_ratio(Ad, b, x_g, xs)
+    rho_o = O.residual_ratio(Ad, b, x_o, xs)
+    assert rho_o > 1.0
+    assert abs(rho_g - rho_o) <= 1e-10
+    assert np.linalg.norm(x_g - x_o) <= 1e-9 * np.linalg.norm(x_o)
+    assert info["ms_sketch"] >= 0 and info["ms_qr"] >= 0
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+@pytest.mark.parametrize("variant", ["atomic", "sorted"])
+def test_lstsq_parity_small_workload(sk, precision, variant):
+    A, b, op, Ad, xs = _small()
+    seed, t = W.sketch_seed(0), 4000
+    x_g, info = sk.lstsq(up_csr(A), up(b), t, seed, delta=1e-11, precision=precision, variant=variant)
+    x_o, _, R_o, it_o, ok_o = O.lstsq(op, b, seed, t, delta=1e-11)
+    assert ok_o and info["certified"] == 1
+    rho_g = O.residual_ratio(Ad, b, x_g.cpu().numpy(), xs)
+    rho_o = O.residual_ratio(Ad, b, x_o, xs)
+    assert abs(rho_g - rho_o) <= 1e-10
+    assert rho_g - 1.0 <= 1e-11
+    # the certificate assumes sigma_min(A R^-1) >= 0.5 for this sketch
+    assert np.linalg.svd(Ad @ np.linalg.inv(R_o), compute_uv=False).min() >= 0.5
+
+
+def _pareto(n, d, storage, trial=0):
+    A, b, x0 = W.pareto_rows(trial=trial, n=n, d=d, storage=storage)
+    Af = W.bf16_to_f32(A) if storage == "bf16" else A
+    Ag = up_bf16(A) if storage == "bf16" else up(A)
+    return Ag, Af.astype(np.float64), b
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+def test_lstsq_dense_pareto_rows(sk, storage, precision):
+    n, d, t = 1 << 15, 64, 4096
+    Ag, Ad, b = _pareto(n, d, storage)
+    xs = O.lstsq_exact(Ad, b)
+    seed = W.sketch_seed(0)
+    # throughput target: certified ratio <= 1 + 1e-6
+    x1, info1 = sk.lstsq(Ag, up(b), t, seed, delta=1e-6, precision=precision)
+    assert info1["certified"] == 1
+    rho1 = O.residual_ratio(Ad, b, x1.cpu().numpy(), xs)
+    assert rho1 - 1.0 <= 1e-6
+    assert info1["ratio_bound"] >= rho1 - 1e-12
+    # parity gate: both sides to 1e-11, ratios within 1e-10
+    x2, info2 = sk.lstsq(Ag, up(b), t, seed, delta=1e-11, precision=precision)
+    x_o, _, R_o, _, ok = O.lstsq(Ad, b, seed, t, delta=1e-11)
+    assert ok and info2["certified"] == 1
+    rho2 = O.residual_ratio(Ad, b, x2.cpu().numpy(), xs)
+    rho_o = O.residual_ratio(Ad, b, x_o, xs)
+    assert abs(rho2 - rho_o) <= 1e-10
+    assert np.linalg.svd(Ad @ np.linalg.inv(R_o), compute_uv=False).min() >= 0.5
+
+
+def test_lstsq_noconv_and_errors(sk):
+    A, b, op, Ad, xs = _small()
+    Ag, bg = up_csr(A), up(b)
+    x, info = sk.lstsq(Ag, bg, 4000, 1, delta=1e-14, max_iter=1, raise_noconv=False)
+    assert info["status"] == "SKLS_ERR_NOCONV" and info["iterations"] == 1
+    with pytest.raises(sk.SklsError) as e:
+        sk.lstsq(Ag, bg, 4000, 1, delta=1e-14, max_iter=1)
+    assert e.value.status == 5
+    with pytest.raises(sk.SklsError) as e:
+        sk.lstsq(Ag, bg, 10, 1)  # t < d
+    assert e.value.status == 2
+    D = np.random.default_rng(1).standard_normal((3000, 5))
+    D[:, 4] = 0.0
+    with pytest.raises(sk.SklsError) as e:
+        sk.lstsq(up(D), up(np.ones(3000)), 500, 1)
+    assert e.value.status == 4
+
+
+def test_consistent_system_stops_immediately(sk):
+    # b in the column space: the sketch-and-solve answer is already exact
+    g = np.random.default_rng(3)
+    A = g.standard_normal((5000, 8))
+    b = A @ g.standard_normal(8)
+    x, info = sk.lstsq(up(A), up(b), 800, 2, delta=1e-8)
+    assert np.allclose(x.cpu().numpy(), np.linalg.lstsq(A, b, rcond=None)[0], rtol=1e-8, atol=1e-10)

@@ -1,5 +1,5 @@
 """Pins for the oracle's sketch-and-solve (Section 7 regression theorem) and
-its preconditioned iterations (Section 7.6)."""
+its preconditioned iterations (Section 7.7)."""
 
 import numpy as np
 import pytest
@@ -91,7 +91,7 @@ def test_lsqr_and_richardson_agree():
 
 def test_richardson_contraction_factor():
     # error in y contracts by exactly max|1 - sigma^2| per step along the
-    # worst singular direction (Section 7.6; the factor exceeds 1 once some
+    # worst singular direction (Section 7.7; the factor exceeds 1 once some
     # singular value of M passes sqrt(2))
     n, d = 40, 3
     U, _ = np.linalg.qr(_rng(4).standard_normal((n, d)))
