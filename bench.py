@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--no-lstsq", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--lstsq-steps", type=int, default=3)
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="run a plain device copy of this many MiB first (scale for HBM byte counters)")
     return p.parse_args()
 
 
@@ -95,6 +97,17 @@ def main():
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+
+    if args.calib_copy_mib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+        # calibrate the byte counters taken on the sketch kernels
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        sync()
+        del src, dst
 
     # ------------------------------------------------------------ headline
     log("generating the sparse sketch workload (n=2^22, d=256, 16 nnz/row)")

@@ -119,7 +119,7 @@ QrWs carve_qr(Arena& ar, int64_t m, int64_t d, int64_t dd) {
   q.gram_bytes = gram_ws_bytes(m, dd);
   q.gram = ar.take<double>(q.gram_bytes / sizeof(double) + 1);
   q.G = ar.take<double>(static_cast<size_t>(dd * dd));
-  q.W = ar.take<double>(static_cast<size_t>(d * d));
+  q.W = ar.take<double>(cholesky_scratch_doubles(d));
   q.status = ar.take<int32_t>(4);
   q.RinvT = ar.take<double>(static_cast<size_t>(d * d));
   return q;
@@ -182,6 +182,33 @@ LsWs carve_ls(Arena& ar, const skls_matrix& A, const skls_lstsq_opts& o) {
   L.nblk = pass_blocks(A);
   L.partial = ar.take<double>(static_cast<size_t>(L.nblk) * dd);
   L.red = ar.take<double>(static_cast<size_t>(div_up(L.nblk, 32)) * dd);
+  return L;
+}
+
+// ---------------------------------------------------------------- leverage workspace
+struct LevWs {
+  int32_t sk_dtype;
+  void* SA;
+  void* sk;
+  size_t sk_bytes;
+  QrWs q;
+  double* R;
+  double* Rinv;
+  float* T;
+};
+
+LevWs carve_lev(Arena& ar, const skls_matrix& A, int64_t t, int32_t k) {
+  LevWs L;
+  const int64_t d = A.d;
+  L.sk_dtype = A.dtype == SKLS_F64 ? SKLS_F64 : SKLS_F32;
+  const size_t es = L.sk_dtype == SKLS_F64 ? 8 : 4;
+  L.SA = ar.take<char>(static_cast<size_t>(t * d) * es);
+  L.sk_bytes = sketch_ws_bytes(A, t, SKLS_SKETCH_AUTO);
+  L.sk = ar.take<char>(L.sk_bytes);
+  L.q = carve_qr(ar, t, d, d);
+  L.R = ar.take<double>(static_cast<size_t>(d * d));
+  L.Rinv = ar.take<double>(static_cast<size_t>(d * d));
+  L.T = ar.take<float>(static_cast<size_t>(d) * k);
   return L;
 }
 
@@ -518,13 +545,8 @@ int32_t skls_leverage_workspace(const skls_matrix* A, int64_t t, int32_t k, size
     set_error("need bytes != NULL, 1 <= k <= 64, t >= d");
     return SKLS_ERR_ARG;
   }
-  const size_t es = A->dtype == SKLS_F64 ? 8 : 4;
   Arena ar(nullptr, 0);
-  ar.take<char>(static_cast<size_t>(t * A->d) * es);
-  ar.take<char>(sketch_ws_bytes(*A, t, SKLS_SKETCH_AUTO));
-  carve_qr(ar, t, A->d, A->d);
-  ar.take<double>(static_cast<size_t>(A->d * A->d) * 2);
-  ar.take<float>(static_cast<size_t>(A->d) * k);
+  carve_lev(ar, *A, t, k);
   *bytes = ar.used;
   return SKLS_OK;
 }
@@ -543,24 +565,17 @@ int32_t skls_leverage_scores(const skls_matrix* A, int64_t t, uint64_t seed, int
     return SKLS_ERR_SHAPE;
   }
   hipStream_t s = as_stream(stream);
-  const int32_t sk_dtype = A->dtype == SKLS_F64 ? SKLS_F64 : SKLS_F32;
-  const size_t es = sk_dtype == SKLS_F64 ? 8 : 4;
   const int64_t d = A->d;
   Arena ar(ws, ws_bytes);
-  void* SA = ar.take<char>(static_cast<size_t>(t * d) * es);
-  const size_t skb = sketch_ws_bytes(*A, t, SKLS_SKETCH_AUTO);
-  void* sk = ar.take<char>(skb);
-  QrWs q = carve_qr(ar, t, d, d);
-  double* R = ar.take<double>(static_cast<size_t>(d * d));
-  double* Rinv = ar.take<double>(static_cast<size_t>(d * d));
-  float* T = ar.take<float>(static_cast<size_t>(d) * k);
+  LevWs L = carve_lev(ar, *A, t, k);
   SKLS_TRY(need_ws(ar, ws, ws_bytes));
-  SKLS_TRY(run_sketch(*A, nullptr, SKLS_F64, t, seed, nullptr, SKLS_SKETCH_AUTO, SA, nullptr, sk_dtype, sk, skb, s));
-  SKLS_TRY(qr_from(SA, sk_dtype, nullptr, SKLS_F64, t, d, q, R, Rinv, q.RinvT, s));
-  SKLS_TRY(run_rinv_times(Rinv, d, Pi2, k, T, s));
-  SKLS_TRY(run_leverage(*A, T, k, scores, s));
+  SKLS_TRY(run_sketch(*A, nullptr, SKLS_F64, t, seed, nullptr, SKLS_SKETCH_AUTO, L.SA, nullptr, L.sk_dtype, L.sk,
+                      L.sk_bytes, s));
+  SKLS_TRY(qr_from(L.SA, L.sk_dtype, nullptr, SKLS_F64, t, d, L.q, L.R, L.Rinv, L.q.RinvT, s));
+  SKLS_TRY(run_rinv_times(L.Rinv, d, Pi2, k, L.T, s));
+  SKLS_TRY(run_leverage(*A, L.T, k, scores, s));
   int32_t st = 0;
-  SKLS_TRY(read_status(q.status, s, &st));
+  SKLS_TRY(read_status(L.q.status, s, &st));
   if (st) {
     set_error("the sketch S A is numerically rank deficient");
     return SKLS_ERR_RANK;

@@ -115,55 +115,183 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   }
 }
 
-// Right-looking Cholesky of the leading d x d block of G in one work-group.
-__global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ G, int64_t ldg, int d,
-                                                   double* __restrict__ W, double* __restrict__ R,
-                                                   int32_t* __restrict__ status, double rtol) {
-  __shared__ double rkk;
-  __shared__ int bad;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid == 0) bad = 0;
-  for (int64_t idx = tid; idx < static_cast<int64_t>(d) * d; idx += nt) {
-    const int i = static_cast<int>(idx / d), j = static_cast<int>(idx % d);
-    W[idx] = j >= i ? G[static_cast<size_t>(i) * ldg + j] : 0.0;
+// ---------------------------------------------------------------- blocked Cholesky
+// Upper Cholesky G = R^T R in place on a d x d row-major copy W, by blocks of
+// kCB rows: factor the diagonal block in LDS (and invert it), solve for the
+// block row to its right, then update the trailing upper triangle.
+constexpr int kCB = 64;
+
+// W[K:K+kb, K:K+kb] -> R_KK (in place) and Kinv = R_KK^{-1} (kb x kb, ld kCB).
+// LDS holds R_KK in the upper triangle of `a`; the inverse is built column by
+// column (one thread per column) in the strict lower triangle, transposed,
+// with its diagonal in the spare column kCB.
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ W, int d, int K, double* __restrict__ Kinv,
+                                                   int32_t* __restrict__ bad) {
+  __shared__ double a[kCB][kCB + 1];
+  const int kb = (d - K) < kCB ? (d - K) : kCB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kCB * (kCB + 1); e += 256) {
+    const int i = e / (kCB + 1), j = e % (kCB + 1);
+    a[i][j] = (i < kb && j < kb && j >= i) ? W[static_cast<size_t>(K + i) * d + K + j] : 0.0;
   }
   __syncthreads();
-  for (int k = 0; k < d; ++k) {
+  for (int k = 0; k < kb; ++k) {
     if (tid == 0) {
-      double piv = W[static_cast<size_t>(k) * d + k];
+      double piv = a[k][k];
       if (!(piv > 0.0)) {
-        bad = 1;
+        bad[0] = 1;
         piv = 1.0;
       }
-      rkk = sqrt(piv);
-      W[static_cast<size_t>(k) * d + k] = rkk;
+      a[k][k] = sqrt(piv);
     }
     __syncthreads();
-    const double inv = 1.0 / rkk;
-    for (int j = k + 1 + tid; j < d; j += nt) W[static_cast<size_t>(k) * d + j] *= inv;
+    const double r = a[k][k];
+    for (int j = k + 1 + tid; j < kb; j += 256) a[k][j] /= r;
     __syncthreads();
-    const int nrem = d - k - 1;
-    const double* rowk = W + static_cast<size_t>(k) * d;
-    for (int64_t idx = tid; idx < static_cast<int64_t>(nrem) * nrem; idx += nt) {
-      const int i = k + 1 + static_cast<int>(idx / nrem);
-      const int j = k + 1 + static_cast<int>(idx % nrem);
-      if (j >= i) W[static_cast<size_t>(i) * d + j] -= rowk[i] * rowk[j];
+    const int nrem = kb - k - 1;
+    for (int e = tid; e < nrem * nrem; e += 256) {
+      const int i = k + 1 + e / nrem, j = k + 1 + e % nrem;
+      if (j >= i) a[i][j] -= a[k][i] * a[k][j];
     }
     __syncthreads();
   }
-  for (int64_t idx = tid; idx < static_cast<int64_t>(d) * d; idx += nt) {
+  if (tid < kb) {
+    const int j = tid;  // column j of the inverse: inv[i][j] kept at a[j][i] (i < j), inv[j][j] at a[j][kCB]
+    a[j][kCB] = 1.0 / a[j][j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = a[i][j] * a[j][kCB];
+      for (int l = i + 1; l < j; ++l) s += a[i][l] * a[j][l];
+      a[j][i] = -s / a[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kb * kb; e += 256) {
+    const int i = e / kb, j = e % kb;
+    if (j >= i) W[static_cast<size_t>(K + i) * d + K + j] = a[i][j];
+    Kinv[i * kCB + j] = (i == j) ? a[j][kCB] : (i < j ? a[j][i] : 0.0);
+  }
+}
+
+constexpr int kCL = 32;  // rows of the panels staged per step
+
+// Block row solve: W[K:K+kb, J0:J0+64] <- R_KK^{-T} W[K:K+kb, J0:J0+64].
+__global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ W, int d, int K,
+                                                   const double* __restrict__ Kinv) {
+  __shared__ double ki[kCL][kCB + 1];
+  __shared__ double p[kCL][kCB + 1];
+  const int kb = (d - K) < kCB ? (d - K) : kCB;
+  const int J0 = K + kb + blockIdx.x * kCB;
+  const int tid = threadIdx.x;
+  const int j = tid % kCB, i0 = tid / kCB;  // this thread: rows i0, i0+4, ..., column j
+  double acc[kCB / 4];
+#pragma unroll
+  for (int q = 0; q < kCB / 4; ++q) acc[q] = 0.0;
+  for (int l0 = 0; l0 < kb; l0 += kCL) {
+    __syncthreads();
+    for (int e = tid; e < kCL * kCB; e += 256) {
+      const int l = e / kCB, c = e % kCB;
+      ki[l][c] = (l0 + l < kb && c < kb) ? Kinv[(l0 + l) * kCB + c] : 0.0;
+      p[l][c] = (l0 + l < kb && J0 + c < d) ? W[static_cast<size_t>(K + l0 + l) * d + J0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kCB / 4; ++q) {
+      const int i = i0 + 4 * q;
+      double s = 0.0;
+      for (int l = 0; l < kCL; ++l) s += ki[l][i] * p[l][j];  // Kinv is upper: ki[l][i] = 0 for l > i
+      acc[q] += s;
+    }
+  }
+  __syncthreads();  // every panel row is read before any is overwritten
+  if (J0 + j < d) {
+#pragma unroll
+    for (int q = 0; q < kCB / 4; ++q) {
+      const int i = i0 + 4 * q;
+      if (i < kb) W[static_cast<size_t>(K + i) * d + J0 + j] = acc[q];
+    }
+  }
+}
+
+// Trailing update of the upper tile (I0, J0): W[I, J] -= R_KI^T R_KJ.
+__global__ __launch_bounds__(256) void k_chol_syrk(double* __restrict__ W, int d, int K) {
+  __shared__ double pi[kCL][kCB + 1];
+  __shared__ double pj[kCL][kCB + 1];
+  const int kb = (d - K) < kCB ? (d - K) : kCB;
+  const int T0 = K + kb;
+  const int nt = (d - T0 + kCB - 1) / kCB;
+  int p = blockIdx.x, ti = 0;
+  while (p >= nt - ti) {
+    p -= nt - ti;
+    ++ti;
+  }
+  const int I0 = T0 + ti * kCB, J0 = T0 + (ti + p) * kCB;
+  const int tid = threadIdx.x;
+  const int j = tid % kCB, i0 = tid / kCB;
+  double acc[kCB / 4];
+#pragma unroll
+  for (int q = 0; q < kCB / 4; ++q) acc[q] = 0.0;
+  for (int l0 = 0; l0 < kb; l0 += kCL) {
+    __syncthreads();
+    for (int e = tid; e < kCL * kCB; e += 256) {
+      const int l = e / kCB, c = e % kCB;
+      const bool in = l0 + l < kb;
+      pi[l][c] = (in && I0 + c < d) ? W[static_cast<size_t>(K + l0 + l) * d + I0 + c] : 0.0;
+      pj[l][c] = (in && J0 + c < d) ? W[static_cast<size_t>(K + l0 + l) * d + J0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kCB / 4; ++q) {
+      const int i = i0 + 4 * q;
+      double s = 0.0;
+      for (int l = 0; l < kCL; ++l) s += pi[l][i] * pj[l][j];
+      acc[q] += s;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kCB / 4; ++q) {
+    const int i = i0 + 4 * q;
+    if (I0 + i < d && J0 + j < d && J0 + j >= I0 + i) W[static_cast<size_t>(I0 + i) * d + J0 + j] -= acc[q];
+  }
+}
+
+// R = upper triangle of W; status = rank test on the diagonal.
+__global__ __launch_bounds__(256) void k_chol_finish(const double* __restrict__ W, int d, double* __restrict__ R,
+                                                     const int32_t* __restrict__ bad, int32_t* __restrict__ status,
+                                                     double rtol) {
+  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < static_cast<int64_t>(d) * d;
+       idx += static_cast<int64_t>(gridDim.x) * 256) {
     const int i = static_cast<int>(idx / d), j = static_cast<int>(idx % d);
     R[idx] = j >= i ? W[idx] : 0.0;
   }
-  if (tid == 0) {
+  if (blockIdx.x == 0) {
+    __shared__ double smx[256], smn[256];
     double mx = 0.0, mn = INFINITY;
-    for (int k = 0; k < d; ++k) {
+    for (int k = threadIdx.x; k < d; k += 256) {
       const double r = W[static_cast<size_t>(k) * d + k];
       mx = r > mx ? r : mx;
       mn = r < mn ? r : mn;
     }
-    status[0] = (bad || !(mn > rtol * mx)) ? 1 : 0;
+    smx[threadIdx.x] = mx;
+    smn[threadIdx.x] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int k = 1; k < 256; ++k) {
+        mx = smx[k] > mx ? smx[k] : mx;
+        mn = smn[k] < mn ? smn[k] : mn;
+      }
+      status[0] = (bad[0] || !(mn > rtol * mx)) ? 1 : 0;
+    }
   }
+}
+
+__global__ void k_copy_upper(const double* __restrict__ G, int64_t ldg, int d, double* __restrict__ W,
+                             int32_t* __restrict__ bad) {
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < static_cast<int64_t>(d) * d;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int i = static_cast<int>(idx / d), j = static_cast<int>(idx % d);
+    W[idx] = j >= i ? G[static_cast<size_t>(i) * ldg + j] : 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) bad[0] = 0;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -283,13 +411,35 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
   return SKLS_OK;
 }
 
+size_t cholesky_scratch_doubles(int64_t d) { return static_cast<size_t>(d * d) + kCB * kCB + 8; }
+
 int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t* status, double* scratch,
                      hipStream_t s) {
   // Threshold: a Gram-based factor cannot resolve |R_kk| below about
   // sqrt(d * eps) * max |R_jj|; treat that as numerical rank deficiency.
   const double rtol = 4.0 * std::sqrt(static_cast<double>(d) * 2.220446049250313e-16);
   PhaseTimer pt("cholesky", s);
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, G, ldg, static_cast<int>(d), scratch, R, status, rtol);
+  // scratch: W [d*d] | Kinv [kCB*kCB] | bad flag
+  double* W = scratch;
+  double* Kinv = scratch + d * d;
+  int32_t* bad = reinterpret_cast<int32_t*>(Kinv + kCB * kCB);
+  const int di = static_cast<int>(d);
+  const unsigned g = static_cast<unsigned>(div_up(d * d, 256) < 4096 ? div_up(d * d, 256) : 4096);
+  hipLaunchKernelGGL(k_copy_upper, dim3(g), dim3(256), 0, s, G, ldg, di, W, bad);
+  SKLS_CHECK_LAUNCH();
+  for (int K = 0; K < di; K += kCB) {
+    const int kb = (di - K) < kCB ? (di - K) : kCB;
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, W, di, K, Kinv, bad);
+    SKLS_CHECK_LAUNCH();
+    const int rest = di - K - kb;
+    if (rest <= 0) break;
+    const int nt = (rest + kCB - 1) / kCB;
+    hipLaunchKernelGGL(k_chol_trsm, dim3(nt), dim3(256), 0, s, W, di, K, Kinv);
+    SKLS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_chol_syrk, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, W, di, K);
+    SKLS_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_chol_finish, dim3(g), dim3(256), 0, s, W, di, R, bad, status, rtol);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }

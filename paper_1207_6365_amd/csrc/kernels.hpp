@@ -12,11 +12,14 @@ int32_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // Bucket plan: off[t+1] (exclusive offsets) and perm[n] (rows grouped by bucket).
 struct BucketPlan {
-  int32_t* count;  // [t]
   int32_t* off;    // [t+1]
-  int32_t* rank;   // [n]
   int32_t* perm;   // [n]
+  int32_t* rank;   // [n]: rows in coarse-bin order (two-level) or ranks (global counting)
+  int32_t* count;  // counts, scanned in place
   int32_t* bsum;   // scan block sums
+  int sh = 0;      // log2 of buckets per coarse bin
+  int C = 0;       // coarse bins; 0 selects counting with global atomics
+  int nblk = 1;    // row chunks of the coarse passes
 };
 size_t plan_bytes(int64_t n, int64_t t);
 BucketPlan carve_plan(Arena& ar, int64_t n, int64_t t);
@@ -37,6 +40,7 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
 // status[0] = 0 ok / 1 rank deficient.
 int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t* status, double* scratch,
                      hipStream_t s);
+size_t cholesky_scratch_doubles(int64_t d);
 int32_t run_trinv(const double* R, int64_t d, double* Rinv, double* RinvT, hipStream_t s);
 // y = op(M) x for a d x d row-major float64 M (op = identity).
 int32_t run_gemv(const double* M, int64_t d, const double* x, double* y, hipStream_t s);

@@ -22,8 +22,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kBucketWaves = kThreads / kWave;  // buckets per block in the sorted kernels
 constexpr int kSortCap = 256;                    // largest bucket sorted in LDS
-constexpr int kAccBudget = 4096;                 // bytes of LDS accumulators per wave (CSR)
-constexpr int kAccMax = 12288;                   // largest single accumulator row (CSR)
+constexpr int kAccMax = 12288;                   // largest accumulator row of S A in LDS (CSR)
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -130,8 +129,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(int32_t* __restrict__ bsu
   if (threadIdx.x == 0) *total_out = carry;
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_down(const int32_t* __restrict__ in, int64_t count,
-                                                        const int32_t* __restrict__ bsum, int32_t* __restrict__ out) {
+__global__ __launch_bounds__(kThreads) void k_scan_down(const int32_t* in, int64_t count,
+                                                        const int32_t* __restrict__ bsum, int32_t* out) {
   __shared__ int32_t wsum[kThreads / kWave];
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + static_cast<int64_t>(threadIdx.x) * kScanItems;
   int32_t v[kScanItems];
@@ -145,6 +144,93 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const int32_t* __restric
   for (int j = 0; j < kScanItems; ++j) {
     if (base + j < count) out[base + j] = run;
     run += v[j];
+  }
+}
+
+// ---------------------------------------------------------------- two-level plan
+// Counting sort of the rows by bucket without global atomics.  Buckets are
+// grouped into coarse bins of `fine` consecutive buckets (a power of two).
+//  1. coarse count: each block counts its chunk of rows per coarse bin in LDS
+//     and writes the counts bin-major, so an exclusive scan of the whole array
+//     gives every (bin, block) its output offset;
+//  2. coarse scatter: each block writes its row ids to those offsets (LDS
+//     atomics hand out the slots);
+//  3. fine pass: one block per coarse bin counts, scans and scatters the bin's
+//     rows by bucket with LDS counters, and writes the bucket offsets.
+constexpr int kPlanItems = 16;
+constexpr int kPlanChunk = kThreads * kPlanItems;  // rows per block in passes 1-2
+
+__global__ __launch_bounds__(kThreads) void k_plan_coarse_count(int64_t n, uint32_t t, uint64_t seed, int sh, int C,
+                                                                int nblk, int32_t* __restrict__ cnt) {
+  extern __shared__ int32_t hist[];  // [C]
+  for (int c = threadIdx.x; c < C; c += kThreads) hist[c] = 0;
+  __syncthreads();
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kPlanChunk;
+  for (int k = 0; k < kPlanItems; ++k) {
+    const int64_t i = r0 + static_cast<int64_t>(k) * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&hist[bucket_of(splitmix64(seed, static_cast<uint64_t>(i)), t) >> sh], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += kThreads) cnt[static_cast<size_t>(c) * nblk + blockIdx.x] = hist[c];
+}
+
+__global__ __launch_bounds__(kThreads) void k_plan_coarse_scatter(int64_t n, uint32_t t, uint64_t seed, int sh, int C,
+                                                                  int nblk, const int32_t* __restrict__ coff,
+                                                                  int32_t* __restrict__ coarse) {
+  extern __shared__ int32_t pos[];  // [C]
+  for (int c = threadIdx.x; c < C; c += kThreads) pos[c] = coff[static_cast<size_t>(c) * nblk + blockIdx.x];
+  __syncthreads();
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kPlanChunk;
+  for (int k = 0; k < kPlanItems; ++k) {
+    const int64_t i = r0 + static_cast<int64_t>(k) * kThreads + threadIdx.x;
+    if (i < n) {
+      const int c = static_cast<int>(bucket_of(splitmix64(seed, static_cast<uint64_t>(i)), t) >> sh);
+      coarse[atomicAdd(&pos[c], 1)] = static_cast<int32_t>(i);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, uint64_t seed, int sh, int C, int nblk,
+                                                        const int32_t* __restrict__ coff,
+                                                        const int32_t* __restrict__ coarse,
+                                                        int32_t* __restrict__ perm, int32_t* __restrict__ off) {
+  extern __shared__ int32_t fcnt[];  // [fine]
+  __shared__ int32_t wsum[kThreads / kWave];
+  const int fine = 1 << sh;
+  const int c = blockIdx.x;
+  const int64_t beg = coff[static_cast<size_t>(c) * nblk];
+  const int64_t end = (c + 1 < C) ? coff[static_cast<size_t>(c + 1) * nblk] : n;
+  for (int f = threadIdx.x; f < fine; f += kThreads) fcnt[f] = 0;
+  __syncthreads();
+  const uint32_t base_bucket = static_cast<uint32_t>(c) << sh;
+  for (int64_t p = beg + threadIdx.x; p < end; p += kThreads) {
+    const int32_t r = coarse[p];
+    atomicAdd(&fcnt[bucket_of(splitmix64(seed, static_cast<uint64_t>(r)), t) - base_bucket], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the fine counters: each thread owns a run of them
+  const int per = (fine + kThreads - 1) / kThreads;
+  const int f0 = threadIdx.x * per;
+  int32_t run = 0;
+  for (int q = 0; q < per; ++q)
+    if (f0 + q < fine) run += fcnt[f0 + q];
+  int32_t tot;
+  int32_t pre = block_exclusive_scan(run, wsum, &tot);
+  for (int q = 0; q < per; ++q) {
+    const int f = f0 + q;
+    if (f < fine) {
+      const int32_t v = fcnt[f];
+      fcnt[f] = pre;
+      if (base_bucket + static_cast<uint32_t>(f) < t) off[base_bucket + f] = static_cast<int32_t>(beg) + pre;
+      pre += v;
+    }
+  }
+  if (c == C - 1 && threadIdx.x == 0) off[t] = static_cast<int32_t>(n);
+  __syncthreads();
+  for (int64_t p = beg + threadIdx.x; p < end; p += kThreads) {
+    const int32_t r = coarse[p];
+    const uint32_t f = bucket_of(splitmix64(seed, static_cast<uint64_t>(r)), t) - base_bucket;
+    perm[beg + atomicAdd(&fcnt[f], 1)] = r;
   }
 }
 
@@ -188,53 +274,90 @@ constexpr size_t bucket_rows_bytes() {
 }
 
 // ---------------------------------------------------------------- a2: CSR, sorted
-template <typename TV, typename TR, typename TO, int L>
+// One wavefront per bucket.  Rows are taken 64 at a time: one lane per row
+// loads the row's extent, a wave-wide scan turns the lengths into offsets, and
+// the chunk's nonzeros are then walked as one flat list (a 6-step binary
+// search in LDS maps each position to its row), so the loads of col/val are
+// independent of each other and many are in flight.  Products accumulate into
+// a per-wave LDS row of S A, written once at the end.
+template <typename TR, typename TO>
+struct FlatLds {
+  TO scale[kSortCap];
+  int32_t src[kSortCap];
+  int32_t dst[kSortCap];
+  TR rstart[kWave];
+  int32_t pfx[kWave];
+  TO rscale[kWave];
+};
+
+constexpr int kFlatUnroll = 4;
+
+template <typename TV, typename TR, typename TO>
 __global__ __launch_bounds__(kThreads) void k_sketch_csr_sorted(
     int d, uint32_t t, uint64_t seed, const TR* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const TV* __restrict__ val, const void* __restrict__ b, int b_f64, const float* __restrict__ w,
     const int32_t* __restrict__ off, const int32_t* __restrict__ perm, TO* __restrict__ SA, TO* __restrict__ Sb,
-    int ncopy, int per_wave) {
+    int per_wave) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const uint32_t bkt = blockIdx.x * kBucketWaves + wid;
   if (bkt >= t) return;
   unsigned char* base = smem + static_cast<size_t>(wid) * per_wave;
-  TO* scale = reinterpret_cast<TO*>(base);
-  int32_t* src = reinterpret_cast<int32_t*>(base + kSortCap * sizeof(TO));
-  int32_t* dst = src + kSortCap;
-  TO* acc = reinterpret_cast<TO*>(base + bucket_rows_bytes<TO>());
-  for (int k = lane; k < ncopy * d; k += kWave) acc[k] = TO(0);
+  FlatLds<TR, TO>& L = *reinterpret_cast<FlatLds<TR, TO>*>(base);
+  TO* acc = reinterpret_cast<TO*>(base + sizeof(FlatLds<TR, TO>));
+  for (int k = lane; k < d; k += kWave) acc[k] = TO(0);
   const int beg = off[bkt], m = off[bkt + 1] - beg;
-  const bool sorted = load_bucket<TO>(perm, beg, m, seed, w, src, dst, scale, lane);
-  constexpr int G = kWave / L;
-  const int g = lane / L, sub = lane % L;
-  TO* myacc = acc + (g % ncopy) * d;
+  const bool sorted = load_bucket<TO>(perm, beg, m, seed, w, L.src, L.dst, L.scale, lane);
   TO sb = TO(0);
-  for (int j0 = 0; j0 < m; j0 += G) {
-    const int j = j0 + g;
+  for (int j0 = 0; j0 < m; j0 += kWave) {
+    const int j = j0 + lane;
+    TR rs = 0;
+    int32_t len = 0;
+    TO sc = TO(0);
     if (j < m) {
-      int32_t r;
-      TO s;
-      if (sorted) {
-        r = dst[j];
-        s = scale[j];
-      } else {
-        r = perm[beg + j];
-        s = row_scale<TO>(seed, r, w);
-      }
-      const TR a = row_ptr[r], e = row_ptr[r + 1];
-      for (TR k = a + sub; k < e; k += L) atomicAdd(&myacc[col[k]], s * load_as<TO>(val, static_cast<size_t>(k)));
-      if (b != nullptr && sub == 0) sb += s * load_b<TO>(b, b_f64, r);
+      const int32_t r = sorted ? L.dst[j] : perm[beg + j];
+      sc = sorted ? L.scale[j] : row_scale<TO>(seed, r, w);
+      rs = row_ptr[r];
+      len = static_cast<int32_t>(row_ptr[r + 1] - rs);
+      if (b != nullptr) sb += sc * load_b<TO>(b, b_f64, r);
     }
+    int32_t incl = len;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int32_t y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+    L.pfx[lane] = incl - len;
+    L.rstart[lane] = rs;
+    L.rscale[lane] = sc;
+    wave_sync();
+    for (int p0 = 0; p0 < total; p0 += kWave * kFlatUnroll) {
+      int32_t cidx[kFlatUnroll];
+      TO v[kFlatUnroll];
+#pragma unroll
+      for (int u = 0; u < kFlatUnroll; ++u) {
+        const int p = p0 + u * kWave + lane;
+        cidx[u] = -1;
+        if (p < total) {
+          int q = 0;  // largest q with pfx[q] <= p (empty rows share the next row's offset)
+#pragma unroll
+          for (int step = kWave / 2; step > 0; step >>= 1)
+            if (L.pfx[q + step] <= p) q += step;
+          const TR k = L.rstart[q] + static_cast<TR>(p - L.pfx[q]);
+          cidx[u] = col[k];
+          v[u] = L.rscale[q] * load_as<TO>(val, static_cast<size_t>(k));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kFlatUnroll; ++u)
+        if (cidx[u] >= 0) atomicAdd(&acc[cidx[u]], v[u]);
+    }
+    wave_sync();
   }
-  wave_sync();
   sb = wave_sum(sb);
   TO* out = SA + static_cast<size_t>(bkt) * d;
-  for (int c = lane; c < d; c += kWave) {
-    TO v = acc[c];
-    for (int q = 1; q < ncopy; ++q) v += acc[q * d + c];
-    out[c] = v;
-  }
+  for (int c = lane; c < d; c += kWave) out[c] = acc[c];
   if (Sb != nullptr && lane == 0) Sb[bkt] = sb;
 }
 
@@ -462,30 +585,60 @@ size_t plan_bytes(int64_t n, int64_t t) {
 
 BucketPlan carve_plan(Arena& ar, int64_t n, int64_t t) {
   BucketPlan P;
-  P.count = ar.take<int32_t>(static_cast<size_t>(t));
+  // coarse bins of 2^sh buckets holding about 4096 rows each on average
+  int sh = 0;
+  while (sh < 12 && (n << (sh + 1)) <= int64_t(4096) * t) ++sh;
+  const int64_t C = (t + (int64_t(1) << sh) - 1) >> sh;
+  P.sh = sh;
+  P.C = C <= 4096 ? static_cast<int>(C) : 0;  // 0: counting with global atomics
+  P.nblk = static_cast<int>(div_up(n > 0 ? n : 1, kPlanChunk));
+  const int64_t ncnt = P.C ? static_cast<int64_t>(P.C) * P.nblk : t;
   P.off = ar.take<int32_t>(static_cast<size_t>(t) + 1);
-  P.rank = ar.take<int32_t>(static_cast<size_t>(n));
   P.perm = ar.take<int32_t>(static_cast<size_t>(n));
-  P.bsum = ar.take<int32_t>(static_cast<size_t>(div_up(t, kScanTile)) + 1);
+  P.rank = ar.take<int32_t>(static_cast<size_t>(n));
+  P.count = ar.take<int32_t>(static_cast<size_t>(ncnt) + 1);
+  P.bsum = ar.take<int32_t>(static_cast<size_t>(div_up(ncnt, kScanTile)) + 1);
   return P;
 }
 
+// Exclusive scan of count[0..ncnt) into out[0..ncnt) with out[ncnt] = total.
+int32_t scan_counts(const int32_t* count, int64_t ncnt, int32_t* bsum, int32_t* out, hipStream_t s) {
+  const int64_t nb = div_up(ncnt, kScanTile);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, count, ncnt, bsum);
+  SKLS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, bsum, nb, out + ncnt);
+  SKLS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scan_down, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, count, ncnt, bsum, out);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
 int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, hipStream_t s) {
+  if (P.C > 0) {
+    const size_t lds = static_cast<size_t>(P.C) * sizeof(int32_t);
+    const int64_t ncnt = static_cast<int64_t>(P.C) * P.nblk;
+    hipLaunchKernelGGL(k_plan_coarse_count, dim3(P.nblk), dim3(kThreads), lds, s, n, t, seed, P.sh, P.C, P.nblk,
+                       P.count);
+    SKLS_CHECK_LAUNCH();
+    // the scanned (bin, block) offsets overwrite the counts in place (each
+    // scan block reads its tile before writing it)
+    SKLS_TRY(scan_counts(P.count, ncnt, P.bsum, P.count, s));
+    hipLaunchKernelGGL(k_plan_coarse_scatter, dim3(P.nblk), dim3(kThreads), lds, s, n, t, seed, P.sh, P.C, P.nblk,
+                       P.count, P.rank);
+    SKLS_CHECK_LAUNCH();
+    const size_t flds = (size_t(1) << P.sh) * sizeof(int32_t);
+    hipLaunchKernelGGL(k_plan_fine, dim3(P.C), dim3(kThreads), flds, s, n, t, seed, P.sh, P.C, P.nblk, P.count,
+                       P.rank, P.perm, P.off);
+    SKLS_CHECK_LAUNCH();
+    return SKLS_OK;
+  }
   SKLS_TRY(launch_fill_zero(P.count, static_cast<size_t>(t) * sizeof(int32_t), s));
   const unsigned g = grid_for(n, kThreads, 16384);
   if (n > 0) {
     hipLaunchKernelGGL(k_count, dim3(g), dim3(kThreads), 0, s, n, t, seed, P.count, P.rank);
     SKLS_CHECK_LAUNCH();
   }
-  const int64_t nb = div_up(t, kScanTile);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, P.count,
-                     static_cast<int64_t>(t), P.bsum);
-  SKLS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, P.bsum, nb, P.off + t);
-  SKLS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_scan_down, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, s, P.count,
-                     static_cast<int64_t>(t), P.bsum, P.off);
-  SKLS_CHECK_LAUNCH();
+  SKLS_TRY(scan_counts(P.count, static_cast<int64_t>(t), P.bsum, P.off, s));
   if (n > 0) {
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kThreads), 0, s, n, t, seed, P.off, P.rank, P.perm);
     SKLS_CHECK_LAUNCH();
@@ -592,20 +745,13 @@ int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t
       }
       return with_rowptr(A, [&](auto tr) -> int32_t {
         using TR = decltype(tr);
-        return with_lanes(lanes_per_row(A), [&](auto lc) -> int32_t {
-          constexpr int L = decltype(lc)::value;
-          constexpr int G = kWave / L;
-          int ncopy = row_bytes > 0 ? static_cast<int>(kAccBudget / row_bytes) : G;
-          if (ncopy < 1) ncopy = 1;
-          if (ncopy > G) ncopy = G;
-          const int per_wave = static_cast<int>((bucket_rows_bytes<TO>() + ncopy * row_bytes + 15) / 16 * 16);
-          hipLaunchKernelGGL((k_sketch_csr_sorted<TV, TR, TO, L>), dim3(grid), dim3(kThreads),
-                             static_cast<size_t>(per_wave) * kBucketWaves, s, d, tt, seed,
-                             static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), b, b_f64,
-                             w, P.off, P.perm, static_cast<TO*>(SA), static_cast<TO*>(Sb), ncopy, per_wave);
-          SKLS_CHECK_LAUNCH();
-          return SKLS_OK;
-        });
+        const int per_wave = static_cast<int>((sizeof(FlatLds<TR, TO>) + row_bytes + 15) / 16 * 16);
+        hipLaunchKernelGGL((k_sketch_csr_sorted<TV, TR, TO>), dim3(grid), dim3(kThreads),
+                           static_cast<size_t>(per_wave) * kBucketWaves, s, d, tt, seed,
+                           static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), b, b_f64, w,
+                           P.off, P.perm, static_cast<TO*>(SA), static_cast<TO*>(Sb), per_wave);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
       });
     });
   });
