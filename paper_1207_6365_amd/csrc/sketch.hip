@@ -11,6 +11,9 @@
 //    accumulator for CSR rows) and writes its row of SA exactly once.  No
 //    zero-fill of SA, no global atomics on SA, bit-reproducible results.
 #include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -21,7 +24,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kBucketWaves = kThreads / kWave;  // buckets per block in the sorted kernels
-constexpr int kSortCap = 256;                    // largest bucket sorted in LDS
 constexpr int kAccMax = 12288;                   // largest accumulator row of S A in LDS (CSR)
 
 __device__ __forceinline__ void wave_sync() {
@@ -70,12 +72,20 @@ __global__ void k_count(int64_t n, uint32_t t, uint64_t seed, int32_t* __restric
   }
 }
 
+template <typename TR, bool EXT>
 __global__ void k_scatter(int64_t n, uint32_t t, uint64_t seed, const int32_t* __restrict__ off,
-                          const int32_t* __restrict__ rank, int32_t* __restrict__ perm) {
+                          const int32_t* __restrict__ rank, int32_t* __restrict__ perm, const TR* __restrict__ row_ptr,
+                          TR* __restrict__ pstart, int32_t* __restrict__ plen) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const uint32_t h = bucket_of(splitmix64(seed, static_cast<uint64_t>(i)), t);
-    perm[off[h] + rank[i]] = static_cast<int32_t>(i);
+    const int64_t p = off[h] + rank[i];
+    perm[p] = static_cast<int32_t>(i);
+    if (EXT) {
+      const TR s0 = row_ptr[i];
+      pstart[p] = s0;
+      plen[p] = static_cast<int32_t>(row_ptr[i + 1] - s0);
+    }
   }
 }
 
@@ -174,9 +184,14 @@ __global__ __launch_bounds__(kThreads) void k_plan_coarse_count(int64_t n, uint3
   for (int c = threadIdx.x; c < C; c += kThreads) cnt[static_cast<size_t>(c) * nblk + blockIdx.x] = hist[c];
 }
 
+// With EXT, each row also carries its CSR extent (start, length), read here
+// in storage order, so the reduce kernels never gather row pointers.
+template <typename TR, bool EXT>
 __global__ __launch_bounds__(kThreads) void k_plan_coarse_scatter(int64_t n, uint32_t t, uint64_t seed, int sh, int C,
                                                                   int nblk, const int32_t* __restrict__ coff,
-                                                                  int32_t* __restrict__ coarse) {
+                                                                  int32_t* __restrict__ coarse,
+                                                                  const TR* __restrict__ row_ptr,
+                                                                  TR* __restrict__ cstart, int32_t* __restrict__ clen) {
   extern __shared__ int32_t pos[];  // [C]
   for (int c = threadIdx.x; c < C; c += kThreads) pos[c] = coff[static_cast<size_t>(c) * nblk + blockIdx.x];
   __syncthreads();
@@ -185,15 +200,25 @@ __global__ __launch_bounds__(kThreads) void k_plan_coarse_scatter(int64_t n, uin
     const int64_t i = r0 + static_cast<int64_t>(k) * kThreads + threadIdx.x;
     if (i < n) {
       const int c = static_cast<int>(bucket_of(splitmix64(seed, static_cast<uint64_t>(i)), t) >> sh);
-      coarse[atomicAdd(&pos[c], 1)] = static_cast<int32_t>(i);
+      const int32_t slot = atomicAdd(&pos[c], 1);
+      coarse[slot] = static_cast<int32_t>(i);
+      if (EXT) {
+        const TR s0 = row_ptr[i];
+        cstart[slot] = s0;
+        clen[slot] = static_cast<int32_t>(row_ptr[i + 1] - s0);
+      }
     }
   }
 }
 
+template <typename TR, bool EXT>
 __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, uint64_t seed, int sh, int C, int nblk,
                                                         const int32_t* __restrict__ coff,
                                                         const int32_t* __restrict__ coarse,
-                                                        int32_t* __restrict__ perm, int32_t* __restrict__ off) {
+                                                        int32_t* __restrict__ perm, int32_t* __restrict__ off,
+                                                        const TR* __restrict__ cstart,
+                                                        const int32_t* __restrict__ clen, TR* __restrict__ pstart,
+                                                        int32_t* __restrict__ plen) {
   extern __shared__ int32_t fcnt[];  // [fine]
   __shared__ int32_t wsum[kThreads / kWave];
   const int fine = 1 << sh;
@@ -230,135 +255,301 @@ __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, u
   for (int64_t p = beg + threadIdx.x; p < end; p += kThreads) {
     const int32_t r = coarse[p];
     const uint32_t f = bucket_of(splitmix64(seed, static_cast<uint64_t>(r)), t) - base_bucket;
-    perm[beg + atomicAdd(&fcnt[f], 1)] = r;
-  }
-}
-
-// ---------------------------------------------------------------- bucket rows
-// Loads the row ids of one bucket, sorted ascending, with their scales, into
-// per-wave LDS.  Buckets larger than kSortCap are left unsorted (false).
-template <typename TS>
-__device__ __forceinline__ bool load_bucket(const int32_t* __restrict__ perm, int beg, int m, uint64_t seed,
-                                            const float* __restrict__ w, int32_t* src, int32_t* dst, TS* scale,
-                                            int lane) {
-  if (m <= kWave) {
-    const int32_t r = lane < m ? perm[beg + lane] : INT_MAX;
-    int rank = 0;
-    for (int k = 0; k < m; ++k) rank += (__builtin_amdgcn_readlane(r, k) < r) ? 1 : 0;
-    if (lane < m) {
-      dst[rank] = r;
-      scale[rank] = row_scale<TS>(seed, r, w);
+    const int64_t dstp = beg + atomicAdd(&fcnt[f], 1);
+    perm[dstp] = r;
+    if (EXT) {
+      pstart[dstp] = cstart[p];
+      plen[dstp] = clen[p];
     }
-    wave_sync();
-    return true;
   }
-  if (m <= kSortCap) {
-    for (int j = lane; j < m; j += kWave) src[j] = perm[beg + j];
-    wave_sync();
-    for (int j = lane; j < m; j += kWave) {
-      const int32_t r = src[j];
-      int rank = 0;
-      for (int k = 0; k < m; ++k) rank += (src[k] < r) ? 1 : 0;
-      dst[rank] = r;
-      scale[rank] = row_scale<TS>(seed, r, w);
-    }
-    wave_sync();
-    return true;
-  }
-  return false;
-}
-
-template <typename TO>
-constexpr size_t bucket_rows_bytes() {
-  return kSortCap * (sizeof(TO) + 2 * sizeof(int32_t));
 }
 
 // ---------------------------------------------------------------- a2: CSR, sorted
-// One wavefront per bucket.  Rows are taken 64 at a time: one lane per row
-// loads the row's extent, a wave-wide scan turns the lengths into offsets, and
-// the chunk's nonzeros are then walked as one flat list (a 6-step binary
-// search in LDS maps each position to its row), so the loads of col/val are
-// independent of each other and many are in flight.  Products accumulate into
-// a per-wave LDS row of S A, written once at the end.
+// A wavefront reduces one bucket at a time.  The plan already carries each row's extent
+// (start, length), so the bucket's rows are loaded with coalesced reads and
+// sorted by row id (up to kCsrSortCap rows, two per lane).  Rows are then
+// taken 64 at a time: a wave-wide scan of the lengths gives each row its
+// offset in the chunk's flat list of nonzeros, a byte table in LDS maps every
+// position of that list to its row, and the column/value loads of up to
+// 64 * kBurst positions are issued back to back before their products are
+// added into the per-wave LDS row of S A (written once at the end).
+constexpr int kCsrSortCap = 2 * kWave;
+constexpr int kPosCap = 2048;
+constexpr int kBurst = 16;
+
 template <typename TR, typename TO>
-struct FlatLds {
-  TO scale[kSortCap];
-  int32_t src[kSortCap];
-  int32_t dst[kSortCap];
-  TR rstart[kWave];
-  int32_t pfx[kWave];
+struct CsrLds {
+  TO dscale[kCsrSortCap];
+  TR dstart[kCsrSortCap];
+  int32_t dlen[kCsrSortCap];
+  int32_t drow[kCsrSortCap];
+  TR base[kWave];      // row start minus its offset in the flat list
   TO rscale[kWave];
+  int32_t pfx[kWave];  // offsets (binary search when the table does not fit)
+  uint8_t pos2row[kPosCap];
 };
 
-constexpr int kFlatUnroll = 4;
+template <typename TV, typename TR, typename TO, bool TABLE>
+__device__ __forceinline__ void csr_burst(const CsrLds<TR, TO>& L, const int32_t* __restrict__ col,
+                                          const TV* __restrict__ val, TO* acc, int p0, int total, int lane) {
+  int32_t c[kBurst];
+  TO v[kBurst];
+  bool ok[kBurst];
+#pragma unroll
+  for (int u = 0; u < kBurst; ++u) {
+    const int p = p0 + u * kWave + lane;
+    ok[u] = p < total;
+    const int pp = ok[u] ? p : 0;
+    int q;
+    if (TABLE) {
+      q = L.pos2row[pp];
+    } else {
+      q = 0;  // largest q with pfx[q] <= pp (empty rows share the next offset)
+#pragma unroll
+      for (int step = kWave / 2; step > 0; step >>= 1)
+        if (L.pfx[q + step] <= pp) q += step;
+    }
+    const TR k = L.base[q] + static_cast<TR>(pp);
+    c[u] = col[k];
+    v[u] = L.rscale[q] * load_as<TO>(val, static_cast<size_t>(k));
+  }
+#pragma unroll
+  for (int u = 0; u < kBurst; ++u)
+    if (ok[u]) atomicAdd(&acc[c[u]], v[u]);
+}
 
+// Four consecutive values of a row (16-byte aligned group of nonzeros).
+template <typename TV, typename TO>
+struct Quad {
+  __device__ __forceinline__ static void load(const TV* __restrict__ p, TO (&o)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = load_as<TO>(p, k);
+  }
+};
+template <typename TO>
+struct Quad<float, TO> {
+  __device__ __forceinline__ static void load(const float* __restrict__ p, TO (&o)[4]) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    o[0] = x.x;
+    o[1] = x.y;
+    o[2] = x.z;
+    o[3] = x.w;
+  }
+};
+template <typename TO>
+struct Quad<double, TO> {
+  __device__ __forceinline__ static void load(const double* __restrict__ p, TO (&o)[4]) {
+    const double2 x = *reinterpret_cast<const double2*>(p);
+    const double2 y = *reinterpret_cast<const double2*>(p + 2);
+    o[0] = static_cast<TO>(x.x);
+    o[1] = static_cast<TO>(x.y);
+    o[2] = static_cast<TO>(y.x);
+    o[3] = static_cast<TO>(y.y);
+  }
+};
+template <typename TO>
+struct Quad<bf16_t, TO> {
+  __device__ __forceinline__ static void load(const bf16_t* __restrict__ p, TO (&o)[4]) {
+    const uint2 x = *reinterpret_cast<const uint2*>(p);
+    o[0] = bf16_lo(x.x);
+    o[1] = bf16_hi(x.x);
+    o[2] = bf16_lo(x.y);
+    o[3] = bf16_hi(x.y);
+  }
+};
+
+// Burst over groups of four nonzeros (rows whose start and length are
+// multiples of four): one 16-byte load of columns and one of values per
+// lane, so a load instruction covers sixteen rows of sixteen nonzeros.
+constexpr int kBurstQ = 4;
+
+template <typename TV, typename TR, typename TO, bool TABLE>
+__device__ __forceinline__ void csr_burst_quad(const CsrLds<TR, TO>& L, const int32_t* __restrict__ col,
+                                               const TV* __restrict__ val, TO* acc, int p0, int total, int lane) {
+  int4 c[kBurstQ];
+  TO v[kBurstQ][4];
+  TO sc[kBurstQ];
+  bool ok[kBurstQ];
+#pragma unroll
+  for (int u = 0; u < kBurstQ; ++u) {
+    const int p = p0 + u * kWave + lane;
+    ok[u] = p < total;
+    const int pp = ok[u] ? p : 0;
+    int q;
+    if (TABLE) {
+      q = L.pos2row[pp];
+    } else {
+      q = 0;
+#pragma unroll
+      for (int step = kWave / 2; step > 0; step >>= 1)
+        if (L.pfx[q + step] <= pp) q += step;
+    }
+    const TR k = L.base[q] + static_cast<TR>(4 * pp);
+    c[u] = *reinterpret_cast<const int4*>(col + k);
+    Quad<TV, TO>::load(val + k, v[u]);
+    sc[u] = L.rscale[q];
+  }
+#pragma unroll
+  for (int u = 0; u < kBurstQ; ++u)
+    if (ok[u]) {
+      atomicAdd(&acc[c[u].x], sc[u] * v[u][0]);
+      atomicAdd(&acc[c[u].y], sc[u] * v[u][1]);
+      atomicAdd(&acc[c[u].z], sc[u] * v[u][2]);
+      atomicAdd(&acc[c[u].w], sc[u] * v[u][3]);
+    }
+}
+
+// Prefetched description of one bucket: its range in the plan and, for up
+// to two rows per lane, the row id, extent and length.
+template <typename TR>
+struct CsrMeta {
+  int beg, m;
+  int32_t r0, r1, l0, l1;
+  TR s0, s1;
+};
+
+template <typename TR>
+__device__ __forceinline__ CsrMeta<TR> csr_meta(const int32_t* __restrict__ perm, const TR* __restrict__ pstart,
+                                                const int32_t* __restrict__ plen, int beg, int m, int lane) {
+  CsrMeta<TR> q;
+  q.beg = beg;
+  q.m = m;
+  const bool h0 = lane < m && m <= kCsrSortCap, h1 = lane + kWave < m && m <= kCsrSortCap;
+  q.r0 = h0 ? perm[beg + lane] : INT_MAX;
+  q.r1 = h1 ? perm[beg + kWave + lane] : INT_MAX;
+  q.s0 = h0 ? pstart[beg + lane] : TR(0);
+  q.s1 = h1 ? pstart[beg + kWave + lane] : TR(0);
+  q.l0 = h0 ? plen[beg + lane] : 0;
+  q.l1 = h1 ? plen[beg + kWave + lane] : 0;
+  return q;
+}
+
+// Each wavefront owns `bpw` consecutive buckets and walks them in order,
+// loading the next bucket's rows while it reduces the current one.
 template <typename TV, typename TR, typename TO>
 __global__ __launch_bounds__(kThreads) void k_sketch_csr_sorted(
-    int d, uint32_t t, uint64_t seed, const TR* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const TV* __restrict__ val, const void* __restrict__ b, int b_f64, const float* __restrict__ w,
-    const int32_t* __restrict__ off, const int32_t* __restrict__ perm, TO* __restrict__ SA, TO* __restrict__ Sb,
-    int per_wave) {
+    int d, uint32_t t, int bpw, uint64_t seed, const int32_t* __restrict__ col, const TV* __restrict__ val,
+    const void* __restrict__ b, int b_f64, const float* __restrict__ w, const int32_t* __restrict__ off,
+    const int32_t* __restrict__ perm, const TR* __restrict__ pstart, const int32_t* __restrict__ plen,
+    TO* __restrict__ SA, TO* __restrict__ Sb, int per_wave, int quad_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const uint32_t bkt = blockIdx.x * kBucketWaves + wid;
-  if (bkt >= t) return;
+  const int64_t b0 = (static_cast<int64_t>(blockIdx.x) * kBucketWaves + wid) * bpw;
+  if (b0 >= t) return;
+  const int nb = static_cast<int>((t - b0) < bpw ? (t - b0) : bpw);
   unsigned char* base = smem + static_cast<size_t>(wid) * per_wave;
-  FlatLds<TR, TO>& L = *reinterpret_cast<FlatLds<TR, TO>*>(base);
-  TO* acc = reinterpret_cast<TO*>(base + sizeof(FlatLds<TR, TO>));
-  for (int k = lane; k < d; k += kWave) acc[k] = TO(0);
-  const int beg = off[bkt], m = off[bkt + 1] - beg;
-  const bool sorted = load_bucket<TO>(perm, beg, m, seed, w, L.src, L.dst, L.scale, lane);
-  TO sb = TO(0);
-  for (int j0 = 0; j0 < m; j0 += kWave) {
-    const int j = j0 + lane;
-    TR rs = 0;
-    int32_t len = 0;
-    TO sc = TO(0);
-    if (j < m) {
-      const int32_t r = sorted ? L.dst[j] : perm[beg + j];
-      sc = sorted ? L.scale[j] : row_scale<TO>(seed, r, w);
-      rs = row_ptr[r];
-      len = static_cast<int32_t>(row_ptr[r + 1] - rs);
-      if (b != nullptr) sb += sc * load_b<TO>(b, b_f64, r);
+  CsrLds<TR, TO>& L = *reinterpret_cast<CsrLds<TR, TO>*>(base);
+  TO* acc = reinterpret_cast<TO*>(base + sizeof(CsrLds<TR, TO>));
+  // bucket offsets of this wave's range (bpw < 64): lane k holds off[b0 + k]
+  const int32_t myoff = lane <= nb ? off[b0 + lane] : 0;
+  auto off_at = [&](int k) -> int32_t { return __builtin_amdgcn_readlane(myoff, k); };
+  CsrMeta<TR> cur = csr_meta<TR>(perm, pstart, plen, off_at(0), off_at(1) - off_at(0), lane);
+  for (int kb = 0; kb < nb; ++kb) {
+    const uint32_t bkt = static_cast<uint32_t>(b0 + kb);
+    CsrMeta<TR> nxt = cur;
+    if (kb + 1 < nb) {
+      const int nbeg = off_at(kb + 1);
+      nxt = csr_meta<TR>(perm, pstart, plen, nbeg, off_at(kb + 2) - nbeg, lane);
     }
-    int32_t incl = len;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int32_t y = __shfl_up(incl, o, kWave);
-      if (lane >= o) incl += y;
-    }
-    const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
-    L.pfx[lane] = incl - len;
-    L.rstart[lane] = rs;
-    L.rscale[lane] = sc;
-    wave_sync();
-    for (int p0 = 0; p0 < total; p0 += kWave * kFlatUnroll) {
-      int32_t cidx[kFlatUnroll];
-      TO v[kFlatUnroll];
-#pragma unroll
-      for (int u = 0; u < kFlatUnroll; ++u) {
-        const int p = p0 + u * kWave + lane;
-        cidx[u] = -1;
-        if (p < total) {
-          int q = 0;  // largest q with pfx[q] <= p (empty rows share the next row's offset)
-#pragma unroll
-          for (int step = kWave / 2; step > 0; step >>= 1)
-            if (L.pfx[q + step] <= p) q += step;
-          const TR k = L.rstart[q] + static_cast<TR>(p - L.pfx[q]);
-          cidx[u] = col[k];
-          v[u] = L.rscale[q] * load_as<TO>(val, static_cast<size_t>(k));
-        }
+    for (int k = lane; k < d; k += kWave) acc[k] = TO(0);
+    const int beg = cur.beg, m = cur.m;
+    const bool sorted = m <= kCsrSortCap;
+    if (sorted) {
+      int rk0 = 0, rk1 = 0;
+      const int m0 = m < kWave ? m : kWave;
+      for (int k = 0; k < m0; ++k) {
+        const int32_t x = __builtin_amdgcn_readlane(cur.r0, k);
+        rk0 += x < cur.r0 ? 1 : 0;
+        rk1 += x < cur.r1 ? 1 : 0;
       }
-#pragma unroll
-      for (int u = 0; u < kFlatUnroll; ++u)
-        if (cidx[u] >= 0) atomicAdd(&acc[cidx[u]], v[u]);
+      for (int k = kWave; k < m; ++k) {
+        const int32_t x = __builtin_amdgcn_readlane(cur.r1, k - kWave);
+        rk0 += x < cur.r0 ? 1 : 0;
+        rk1 += x < cur.r1 ? 1 : 0;
+      }
+      if (lane < m) {
+        L.drow[rk0] = cur.r0;
+        L.dstart[rk0] = cur.s0;
+        L.dlen[rk0] = cur.l0;
+        L.dscale[rk0] = row_scale<TO>(seed, cur.r0, w);
+      }
+      if (lane + kWave < m) {
+        L.drow[rk1] = cur.r1;
+        L.dstart[rk1] = cur.s1;
+        L.dlen[rk1] = cur.l1;
+        L.dscale[rk1] = row_scale<TO>(seed, cur.r1, w);
+      }
     }
     wave_sync();
+    TO sb = TO(0);
+    for (int j0 = 0; j0 < m; j0 += kWave) {
+      const int j = j0 + lane;
+      int32_t len = 0;
+      TR st = 0;
+      TO sc = TO(0);
+      if (j < m) {
+        int32_t r;
+        if (sorted) {
+          r = L.drow[j];
+          st = L.dstart[j];
+          len = L.dlen[j];
+          sc = L.dscale[j];
+        } else {
+          r = perm[beg + j];
+          st = pstart[beg + j];
+          len = plen[beg + j];
+          sc = row_scale<TO>(seed, r, w);
+        }
+        if (b != nullptr) sb += sc * load_b<TO>(b, b_f64, r);
+      }
+      // groups of four nonzeros when every row of the chunk allows it
+      const bool quad = quad_ok && __all(((static_cast<int64_t>(st) | len) & 3) == 0);
+      const int32_t units = quad ? (len >> 2) : len;
+      int32_t incl = units, mx = units;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+        const int32_t z = __shfl_xor(mx, o, kWave);
+        mx = z > mx ? z : mx;
+      }
+      const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+      const int32_t pf = incl - units;
+      L.base[lane] = st - static_cast<TR>(quad ? 4 * pf : pf);
+      L.rscale[lane] = sc;
+      L.pfx[lane] = pf;
+      const bool table = total <= kPosCap && mx <= kWave;
+      if (table)
+        for (int e = 0; e < mx; ++e)
+          if (e < units) L.pos2row[pf + e] = static_cast<uint8_t>(lane);
+      wave_sync();
+      // Branch-free bursts: positions past the end read position 0 (always
+      // valid when total > 0) and are masked afterwards, so every load of
+      // the burst is issued before the first wait.
+      if (quad) {
+        if (table) {
+          for (int p0 = 0; p0 < total; p0 += kWave * kBurstQ)
+            csr_burst_quad<TV, TR, TO, true>(L, col, val, acc, p0, total, lane);
+        } else {
+          for (int p0 = 0; p0 < total; p0 += kWave * kBurstQ)
+            csr_burst_quad<TV, TR, TO, false>(L, col, val, acc, p0, total, lane);
+        }
+      } else if (table) {
+        for (int p0 = 0; p0 < total; p0 += kWave * kBurst)
+          csr_burst<TV, TR, TO, true>(L, col, val, acc, p0, total, lane);
+      } else {
+        for (int p0 = 0; p0 < total; p0 += kWave * kBurst)
+          csr_burst<TV, TR, TO, false>(L, col, val, acc, p0, total, lane);
+      }
+      wave_sync();
+    }
+    sb = wave_sum(sb);
+    TO* out = SA + static_cast<size_t>(bkt) * d;
+    for (int c = lane; c < d; c += kWave) out[c] = acc[c];
+    if (Sb != nullptr && lane == 0) Sb[bkt] = sb;
+    wave_sync();
+    cur = nxt;
   }
-  sb = wave_sum(sb);
-  TO* out = SA + static_cast<size_t>(bkt) * d;
-  for (int c = lane; c < d; c += kWave) out[c] = acc[c];
-  if (Sb != nullptr && lane == 0) Sb[bkt] = sb;
 }
 
 // ---------------------------------------------------------------- a2: dense, sorted
@@ -402,63 +593,123 @@ struct RowLoad<bf16_t, TO, 8> {
   }
 };
 
-template <typename TV, typename TO, int V>
-__global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted(
-    int d, int64_t ld, uint32_t t, uint64_t seed, const TV* __restrict__ A, const void* __restrict__ b, int b_f64,
-    const float* __restrict__ w, const int32_t* __restrict__ off, const int32_t* __restrict__ perm,
-    TO* __restrict__ SA, TO* __restrict__ Sb) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const uint32_t bkt = blockIdx.x * kBucketWaves + wid;
-  if (bkt >= t) return;
-  unsigned char* base = smem + static_cast<size_t>(wid) * bucket_rows_bytes<TO>();
-  TO* scale = reinterpret_cast<TO*>(base);
-  int32_t* src = reinterpret_cast<int32_t*>(base + kSortCap * sizeof(TO));
-  int32_t* dst = src + kSortCap;
-  const int beg = off[bkt], m = off[bkt + 1] - beg;
-  const bool sorted = load_bucket<TO>(perm, beg, m, seed, w, src, dst, scale, lane);
-  auto row_at = [&](int j) -> int32_t { return sorted ? dst[j] : perm[beg + j]; };
-  auto scale_at = [&](int j, int32_t r) -> TO { return sorted ? scale[j] : row_scale<TO>(seed, r, w); };
-  if (Sb != nullptr) {
-    TO sb = TO(0);
-    for (int j = lane; j < m; j += kWave) {
-      const int32_t r = row_at(j);
-      sb += scale_at(j, r) * load_b<TO>(b, b_f64, r);
-    }
-    sb = wave_sum(sb);
-    if (lane == 0) Sb[bkt] = sb;
-  }
-  TO* out = SA + static_cast<size_t>(bkt) * d;
+// Each wavefront owns `bpw` consecutive buckets; the next bucket's row ids are
+// loaded while the current bucket's rows are summed in registers (lanes own
+// column slices, 8 rows in flight).
+template <typename TO>
+struct DenseLds {
+  TO dscale[kCsrSortCap];
+  int32_t drow[kCsrSortCap];
+};
+
+// Sum of the bucket's rows for this lane's column slices.  Batches of RB rows
+// are loaded unconditionally (rows past the end repeat row 0 and are skipped
+// when summing), so all loads of a batch are in flight together; rows are
+// added in bucket order.
+template <typename TV, typename TO, int V, bool SORTED>
+__device__ __forceinline__ void dense_rows(const DenseLds<TO>& L, const int32_t* __restrict__ perm, int beg, int m,
+                                           uint64_t seed, const float* __restrict__ w, const TV* __restrict__ A,
+                                           int64_t ld, int d, TO* __restrict__ out, int lane) {
+  constexpr int RB = 8;
   for (int c0 = lane * V; c0 < d; c0 += kWave * V) {
     TO acc[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) acc[k] = TO(0);
-    int j = 0;
-    for (; j + 4 <= m; j += 4) {
-      int32_t r[4];
-      TO s[4], x[4][V];
+    for (int j = 0; j < m; j += RB) {
+      TO sc[RB], x[RB][V];
+      bool ok[RB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        r[q] = row_at(j + q);
-        s[q] = scale_at(j + q, r[q]);
+      for (int q = 0; q < RB; ++q) {
+        ok[q] = j + q < m;
+        const int jc = ok[q] ? j + q : 0;
+        const int32_t r = SORTED ? L.drow[jc] : perm[beg + jc];
+        sc[q] = SORTED ? L.dscale[jc] : row_scale<TO>(seed, r, w);
+        RowLoad<TV, TO, V>::load(A + static_cast<size_t>(r) * ld + c0, x[q]);
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) RowLoad<TV, TO, V>::load(A + static_cast<size_t>(r[q]) * ld + c0, x[q]);
+      for (int q = 0; q < RB; ++q)
+        if (ok[q])
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int k = 0; k < V; ++k) acc[k] += s[q] * x[q][k];
-    }
-    for (; j < m; ++j) {
-      const int32_t r = row_at(j);
-      const TO s = scale_at(j, r);
-      TO x[V];
-      RowLoad<TV, TO, V>::load(A + static_cast<size_t>(r) * ld + c0, x);
-#pragma unroll
-      for (int k = 0; k < V; ++k) acc[k] += s * x[k];
+          for (int k = 0; k < V; ++k) acc[k] += sc[q] * x[q][k];
     }
 #pragma unroll
     for (int k = 0; k < V; ++k) out[c0 + k] = acc[k];
+  }
+}
+
+template <typename TV, typename TO, int V>
+__global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted(
+    int d, int64_t ld, uint32_t t, int bpw, uint64_t seed, const TV* __restrict__ A, const void* __restrict__ b,
+    int b_f64, const float* __restrict__ w, const int32_t* __restrict__ off, const int32_t* __restrict__ perm,
+    TO* __restrict__ SA, TO* __restrict__ Sb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t b0 = (static_cast<int64_t>(blockIdx.x) * kBucketWaves + wid) * bpw;
+  if (b0 >= t) return;
+  const int nb = static_cast<int>((t - b0) < bpw ? (t - b0) : bpw);
+  DenseLds<TO>& L = *reinterpret_cast<DenseLds<TO>*>(smem + static_cast<size_t>(wid) * sizeof(DenseLds<TO>));
+  const int32_t myoff = lane <= nb ? off[b0 + lane] : 0;
+  auto off_at = [&](int k) -> int32_t { return __builtin_amdgcn_readlane(myoff, k); };
+  auto fetch = [&](int beg, int m, int32_t& r0, int32_t& r1) {
+    const bool ok = m <= kCsrSortCap;
+    r0 = (ok && lane < m) ? perm[beg + lane] : INT_MAX;
+    r1 = (ok && lane + kWave < m) ? perm[beg + kWave + lane] : INT_MAX;
+  };
+  int beg = off_at(0), m = off_at(1) - beg;
+  int32_t r0, r1;
+  fetch(beg, m, r0, r1);
+  for (int kb = 0; kb < nb; ++kb) {
+    const uint32_t bkt = static_cast<uint32_t>(b0 + kb);
+    int nbeg = beg, nm = m;
+    int32_t n0 = r0, n1 = r1;
+    if (kb + 1 < nb) {
+      nbeg = off_at(kb + 1);
+      nm = off_at(kb + 2) - nbeg;
+      fetch(nbeg, nm, n0, n1);
+    }
+    const bool sorted = m <= kCsrSortCap;
+    if (sorted) {
+      int rk0 = 0, rk1 = 0;
+      const int m0 = m < kWave ? m : kWave;
+      for (int k = 0; k < m0; ++k) {
+        const int32_t x = __builtin_amdgcn_readlane(r0, k);
+        rk0 += x < r0 ? 1 : 0;
+        rk1 += x < r1 ? 1 : 0;
+      }
+      for (int k = kWave; k < m; ++k) {
+        const int32_t x = __builtin_amdgcn_readlane(r1, k - kWave);
+        rk0 += x < r0 ? 1 : 0;
+        rk1 += x < r1 ? 1 : 0;
+      }
+      if (lane < m) {
+        L.drow[rk0] = r0;
+        L.dscale[rk0] = row_scale<TO>(seed, r0, w);
+      }
+      if (lane + kWave < m) {
+        L.drow[rk1] = r1;
+        L.dscale[rk1] = row_scale<TO>(seed, r1, w);
+      }
+    }
+    wave_sync();
+    if (Sb != nullptr) {
+      TO sb = TO(0);
+      for (int j = lane; j < m; j += kWave) {
+        const int32_t r = sorted ? L.drow[j] : perm[beg + j];
+        sb += (sorted ? L.dscale[j] : row_scale<TO>(seed, r, w)) * load_b<TO>(b, b_f64, r);
+      }
+      sb = wave_sum(sb);
+      if (lane == 0) Sb[bkt] = sb;
+    }
+    TO* out = SA + static_cast<size_t>(bkt) * d;
+    if (sorted)
+      dense_rows<TV, TO, V, true>(L, perm, beg, m, seed, w, A, ld, d, out, lane);
+    else
+      dense_rows<TV, TO, V, false>(L, perm, beg, m, seed, w, A, ld, d, out, lane);
+    wave_sync();
+    beg = nbeg;
+    m = nm;
+    r0 = n0;
+    r1 = n1;
   }
 }
 
@@ -577,13 +828,13 @@ int32_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   return SKLS_OK;
 }
 
-size_t plan_bytes(int64_t n, int64_t t) {
+size_t plan_bytes(int64_t n, int64_t t, int ext) {
   Arena ar(nullptr, 0);
-  carve_plan(ar, n, t);
+  carve_plan(ar, n, t, ext);
   return ar.used;
 }
 
-BucketPlan carve_plan(Arena& ar, int64_t n, int64_t t) {
+BucketPlan carve_plan(Arena& ar, int64_t n, int64_t t, int ext) {
   BucketPlan P;
   // coarse bins of 2^sh buckets holding about 4096 rows each on average
   int sh = 0;
@@ -592,12 +843,19 @@ BucketPlan carve_plan(Arena& ar, int64_t n, int64_t t) {
   P.sh = sh;
   P.C = C <= 4096 ? static_cast<int>(C) : 0;  // 0: counting with global atomics
   P.nblk = static_cast<int>(div_up(n > 0 ? n : 1, kPlanChunk));
+  P.ext = ext;
   const int64_t ncnt = P.C ? static_cast<int64_t>(P.C) * P.nblk : t;
   P.off = ar.take<int32_t>(static_cast<size_t>(t) + 1);
   P.perm = ar.take<int32_t>(static_cast<size_t>(n));
   P.rank = ar.take<int32_t>(static_cast<size_t>(n));
   P.count = ar.take<int32_t>(static_cast<size_t>(ncnt) + 1);
   P.bsum = ar.take<int32_t>(static_cast<size_t>(div_up(ncnt, kScanTile)) + 1);
+  if (ext) {
+    P.pstart = ar.take<char>(static_cast<size_t>(n) * ext);
+    P.plen = ar.take<int32_t>(static_cast<size_t>(n));
+    P.cstart = ar.take<char>(static_cast<size_t>(n) * ext);
+    P.clen = ar.take<int32_t>(static_cast<size_t>(n));
+  }
   return P;
 }
 
@@ -613,7 +871,10 @@ int32_t scan_counts(const int32_t* count, int64_t ncnt, int32_t* bsum, int32_t* 
   return SKLS_OK;
 }
 
-int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, hipStream_t s) {
+template <typename TR, bool EXT>
+int32_t build_plan_t(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, const TR* row_ptr, hipStream_t s) {
+  TR* cstart = static_cast<TR*>(P.cstart);
+  TR* pstart = static_cast<TR*>(P.pstart);
   if (P.C > 0) {
     const size_t lds = static_cast<size_t>(P.C) * sizeof(int32_t);
     const int64_t ncnt = static_cast<int64_t>(P.C) * P.nblk;
@@ -623,12 +884,12 @@ int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, hi
     // the scanned (bin, block) offsets overwrite the counts in place (each
     // scan block reads its tile before writing it)
     SKLS_TRY(scan_counts(P.count, ncnt, P.bsum, P.count, s));
-    hipLaunchKernelGGL(k_plan_coarse_scatter, dim3(P.nblk), dim3(kThreads), lds, s, n, t, seed, P.sh, P.C, P.nblk,
-                       P.count, P.rank);
+    hipLaunchKernelGGL((k_plan_coarse_scatter<TR, EXT>), dim3(P.nblk), dim3(kThreads), lds, s, n, t, seed, P.sh, P.C,
+                       P.nblk, P.count, P.rank, row_ptr, cstart, P.clen);
     SKLS_CHECK_LAUNCH();
     const size_t flds = (size_t(1) << P.sh) * sizeof(int32_t);
-    hipLaunchKernelGGL(k_plan_fine, dim3(P.C), dim3(kThreads), flds, s, n, t, seed, P.sh, P.C, P.nblk, P.count,
-                       P.rank, P.perm, P.off);
+    hipLaunchKernelGGL((k_plan_fine<TR, EXT>), dim3(P.C), dim3(kThreads), flds, s, n, t, seed, P.sh, P.C, P.nblk,
+                       P.count, P.rank, P.perm, P.off, cstart, P.clen, pstart, P.plen);
     SKLS_CHECK_LAUNCH();
     return SKLS_OK;
   }
@@ -640,10 +901,23 @@ int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, hi
   }
   SKLS_TRY(scan_counts(P.count, static_cast<int64_t>(t), P.bsum, P.off, s));
   if (n > 0) {
-    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kThreads), 0, s, n, t, seed, P.off, P.rank, P.perm);
+    hipLaunchKernelGGL((k_scatter<TR, EXT>), dim3(g), dim3(kThreads), 0, s, n, t, seed, P.off, P.rank, P.perm,
+                       row_ptr, pstart, P.plen);
     SKLS_CHECK_LAUNCH();
   }
   return SKLS_OK;
+}
+
+int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, const void* row_ptr, hipStream_t s) {
+  if (P.ext == 8) return build_plan_t<int64_t, true>(n, t, seed, P, static_cast<const int64_t*>(row_ptr), s);
+  if (P.ext == 4) return build_plan_t<int32_t, true>(n, t, seed, P, static_cast<const int32_t*>(row_ptr), s);
+  return build_plan_t<int32_t, false>(n, t, seed, P, nullptr, s);
+}
+
+// Bytes per carried row start in the plan (0 for dense inputs).
+int plan_ext(const skls_matrix& A) {
+  if (A.layout != SKLS_CSR) return 0;
+  return A.row_ptr_64 ? 8 : 4;
 }
 
 int32_t choose_sketch_variant(const skls_matrix& A, int64_t t, int32_t variant) {
@@ -656,8 +930,29 @@ int32_t choose_sketch_variant(const skls_matrix& A, int64_t t, int32_t variant) 
 
 size_t sketch_ws_bytes(const skls_matrix& A, int64_t t, int32_t variant) {
   const int32_t v = choose_sketch_variant(A, t, variant);
-  if (v == SKLS_SKETCH_SORTED) return plan_bytes(A.n, t);
+  if (v == SKLS_SKETCH_SORTED) return plan_bytes(A.n, t, plan_ext(A));
   return 0;
+}
+
+// Wavefronts of a kBucketWaves-wave block kernel that the device holds at
+// once (occupancy from registers and LDS), cached per kernel, LDS size and
+// device.
+static int64_t resident_waves(const void* kernel, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, size_t, int>, int64_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const auto key = std::make_tuple(kernel, lds, dev);
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  const int64_t r = static_cast<int64_t>(per_cu) * cus * kBucketWaves;
+  cache.emplace(key, r);
+  return r;
 }
 
 int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
@@ -708,32 +1003,37 @@ int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t
   }
   // SORTED
   Arena ar(ws, ws_bytes);
-  BucketPlan P = carve_plan(ar, n, t);
+  BucketPlan P = carve_plan(ar, n, t, plan_ext(A));
   if (!ws || !ar.fits()) {
     set_error("sketch workspace too small: need %zu bytes, have %zu", ar.used, ws_bytes);
     return SKLS_ERR_WORKSPACE;
   }
   {
     PhaseTimer pt("sketch_plan", s);
-    SKLS_TRY(build_plan(n, tt, seed, P, s));
+    SKLS_TRY(build_plan(n, tt, seed, P, A.layout == SKLS_CSR ? A.row_ptr : nullptr, s));
   }
-  const unsigned grid = static_cast<unsigned>(div_up(t, kBucketWaves));
   PhaseTimer pt("sketch_apply", s);
   return with_out(out_dtype, [&](auto to) -> int32_t {
     using TO = decltype(to);
     return with_value(A.dtype, [&](auto tv) -> int32_t {
       using TV = decltype(tv);
       if (A.layout == SKLS_DENSE) {
-        const size_t lds = kBucketWaves * bucket_rows_bytes<TO>();
+        const size_t lds = kBucketWaves * sizeof(DenseLds<TO>);
         constexpr int VV = sizeof(TV) == 8 ? 2 : (sizeof(TV) == 4 ? 4 : 8);
-        if (vec_ok<TV>(A.val, A.ld, A.d, VV)) {
-          hipLaunchKernelGGL((k_sketch_dense_sorted<TV, TO, VV>), dim3(grid), dim3(kThreads), lds, s, d, A.ld, tt,
-                             seed, static_cast<const TV*>(A.val), b, b_f64, w, P.off, P.perm, static_cast<TO*>(SA),
-                             static_cast<TO*>(Sb));
+        const bool vec = vec_ok<TV>(A.val, A.ld, A.d, VV);
+        const void* kern = vec ? reinterpret_cast<const void*>(&k_sketch_dense_sorted<TV, TO, VV>)
+                               : reinterpret_cast<const void*>(&k_sketch_dense_sorted<TV, TO, 1>);
+        int bpw = static_cast<int>(div_up(t, resident_waves(kern, lds)));
+        bpw = bpw < 1 ? 1 : (bpw > 63 ? 63 : bpw);
+        const unsigned dgrid = static_cast<unsigned>(div_up(div_up(t, bpw), kBucketWaves));
+        if (vec) {
+          hipLaunchKernelGGL((k_sketch_dense_sorted<TV, TO, VV>), dim3(dgrid), dim3(kThreads), lds, s, d, A.ld, tt,
+                             bpw, seed, static_cast<const TV*>(A.val), b, b_f64, w, P.off, P.perm,
+                             static_cast<TO*>(SA), static_cast<TO*>(Sb));
         } else {
-          hipLaunchKernelGGL((k_sketch_dense_sorted<TV, TO, 1>), dim3(grid), dim3(kThreads), lds, s, d, A.ld, tt,
-                             seed, static_cast<const TV*>(A.val), b, b_f64, w, P.off, P.perm, static_cast<TO*>(SA),
-                             static_cast<TO*>(Sb));
+          hipLaunchKernelGGL((k_sketch_dense_sorted<TV, TO, 1>), dim3(dgrid), dim3(kThreads), lds, s, d, A.ld, tt,
+                             bpw, seed, static_cast<const TV*>(A.val), b, b_f64, w, P.off, P.perm,
+                             static_cast<TO*>(SA), static_cast<TO*>(Sb));
         }
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
@@ -745,11 +1045,20 @@ int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t
       }
       return with_rowptr(A, [&](auto tr) -> int32_t {
         using TR = decltype(tr);
-        const int per_wave = static_cast<int>((sizeof(FlatLds<TR, TO>) + row_bytes + 15) / 16 * 16);
-        hipLaunchKernelGGL((k_sketch_csr_sorted<TV, TR, TO>), dim3(grid), dim3(kThreads),
-                           static_cast<size_t>(per_wave) * kBucketWaves, s, d, tt, seed,
-                           static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), b, b_f64, w,
-                           P.off, P.perm, static_cast<TO*>(SA), static_cast<TO*>(Sb), per_wave);
+        const int per_wave = static_cast<int>((sizeof(CsrLds<TR, TO>) + row_bytes + 15) / 16 * 16);
+        // one round of resident wavefronts, each walking consecutive buckets
+        const size_t lds = static_cast<size_t>(per_wave) * kBucketWaves;
+        int cbpw = static_cast<int>(div_up(t, resident_waves(
+                                                  reinterpret_cast<const void*>(&k_sketch_csr_sorted<TV, TR, TO>), lds)));
+        cbpw = cbpw < 1 ? 1 : (cbpw > 63 ? 63 : cbpw);
+        const unsigned cgrid = static_cast<unsigned>(div_up(div_up(t, cbpw), kBucketWaves));
+        const int quad_ok = (reinterpret_cast<uintptr_t>(A.col_idx) % 16 == 0) &&
+                            (reinterpret_cast<uintptr_t>(A.val) % (4 * sizeof(TV)) == 0);
+        hipLaunchKernelGGL((k_sketch_csr_sorted<TV, TR, TO>), dim3(cgrid), dim3(kThreads), lds, s, d, tt, cbpw,
+                           seed, A.col_idx,
+                           static_cast<const TV*>(A.val), b, b_f64, w, P.off, P.perm,
+                           static_cast<const TR*>(P.pstart), P.plen, static_cast<TO*>(SA), static_cast<TO*>(Sb),
+                           per_wave, quad_ok);
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
       });
