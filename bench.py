@@ -36,7 +36,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--variant", default="auto", choices=["auto", "atomic", "sorted"])
+    p.add_argument("--variant", default="auto", choices=["auto", "atomic", "sorted", "binned"])
     p.add_argument("--no-extras", action="store_true", help="only the headline sketch workload")
     p.add_argument("--no-lstsq", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
@@ -105,7 +105,7 @@ def main():
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 2.0, out=dst)  # an elementwise kernel: reads nb bytes, writes nb bytes
         sync()
         del src, dst
 
@@ -162,7 +162,8 @@ def main():
                    "n": A.n, "d": A.d, "nnz": nnz, "t": t, "variant": args.variant, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": None,
-                     "kernel": "k_sketch_csr_sorted" if args.variant != "atomic" else "k_sketch_csr_atomic",
+                     "kernel": {"atomic": "k_sketch_csr_atomic", "sorted": "k_sketch_csr_sorted"}.get(
+                         args.variant, "k_sketch_csr_binned"),
                      "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes},
         "step_roofline_frac": alg_bytes / (ms_step * 1e-3) / HBM_PEAK,
         "phases_ms": {k: v[1] / max(v[0], 1) for k, v in phases.items()},

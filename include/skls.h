@@ -112,9 +112,20 @@ SKLS_API int32_t skls_hash(int64_t n, int64_t t, uint64_t seed, int64_t start, i
  *  SKLS_SKETCH_SORTED    group rows by bucket (counting sort of h), then one
  *                        wavefront reduces each bucket's rows in increasing
  *                        row order and writes its row of S*A once; results are
- *                        reproducible bit for bit from run to run
+ *                        reproducible bit for bit from run to run when no
+ *                        bucket holds more than 128 rows.  CSR inputs need
+ *                        d * sizeof(out) <= 12288 bytes.
+ *  SKLS_SKETCH_BINNED    group rows into bins of consecutive buckets; one
+ *                        block keeps a bin's rows of S*A in LDS, adds the
+ *                        bin's rows into them with LDS atomics and writes
+ *                        them once (float results depend on the order of the
+ *                        additions).  Needs d * sizeof(out) <= 32768 bytes.
+ * AUTO picks BINNED for CSR inputs and SORTED for dense inputs with at most
+ * 256 rows per bucket on average (BINNED above that), and ATOMIC where the
+ * chosen one does not apply.  An explicitly requested variant that does not
+ * support the shape fails with SKLS_ERR_SHAPE.
  */
-enum { SKLS_SKETCH_AUTO = 0, SKLS_SKETCH_ATOMIC = 1, SKLS_SKETCH_SORTED = 2 };
+enum { SKLS_SKETCH_AUTO = 0, SKLS_SKETCH_ATOMIC = 1, SKLS_SKETCH_SORTED = 2, SKLS_SKETCH_BINNED = 3 };
 
 /* Bytes of workspace skls_sketch needs for this input, t and variant. */
 SKLS_API int32_t skls_sketch_workspace(const skls_matrix* A, int64_t t, int32_t variant, size_t* bytes);

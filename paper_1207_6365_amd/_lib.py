@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libskls.so")
 
 F64, F32, BF16 = 0, 1, 2
 DENSE, CSR = 0, 1
-SKETCH_AUTO, SKETCH_ATOMIC, SKETCH_SORTED = 0, 1, 2
+SKETCH_AUTO, SKETCH_ATOMIC, SKETCH_SORTED, SKETCH_BINNED = 0, 1, 2, 3
 
 STATUS = {
     0: "SKLS_OK",

@@ -16,7 +16,8 @@ import torch
 from . import _lib as L
 
 _DTYPE = {torch.float64: L.F64, torch.float32: L.F32, torch.bfloat16: L.BF16}
-_VARIANT = {"auto": L.SKETCH_AUTO, "atomic": L.SKETCH_ATOMIC, "sorted": L.SKETCH_SORTED}
+_VARIANT = {"auto": L.SKETCH_AUTO, "atomic": L.SKETCH_ATOMIC, "sorted": L.SKETCH_SORTED,
+            "binned": L.SKETCH_BINNED}
 
 
 @dataclass

@@ -289,7 +289,7 @@ int32_t skls_sketch_workspace(const skls_matrix* A, int64_t t, int32_t variant, 
     set_error("bytes pointer is NULL");
     return SKLS_ERR_ARG;
   }
-  if (variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_SORTED) {
+  if (variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_BINNED) {
     set_error("unknown sketch variant %d", variant);
     return SKLS_ERR_ARG;
   }
@@ -302,7 +302,7 @@ int32_t skls_sketch(const skls_matrix* A, const void* b, int32_t b_dtype, int64_
   clear_error();
   SKLS_TRY(validate_matrix(A, true));
   SKLS_TRY(check_t(t));
-  if (variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_SORTED) {
+  if (variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_BINNED) {
     set_error("unknown sketch variant %d", variant);
     return SKLS_ERR_ARG;
   }

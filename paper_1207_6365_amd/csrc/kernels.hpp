@@ -10,29 +10,8 @@ int32_t launch_hash(int64_t n, uint32_t t, uint64_t seed, int64_t start, int32_t
                     hipStream_t s);
 int32_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
-// Bucket plan: off[t+1] (exclusive offsets) and perm[n] (rows grouped by bucket).
-struct BucketPlan {
-  int32_t* off;    // [t+1]
-  int32_t* perm;   // [n]
-  int32_t* rank;   // [n]: rows in coarse-bin order (two-level) or ranks (global counting)
-  int32_t* count;  // counts, scanned in place
-  int32_t* bsum;   // scan block sums
-  int sh = 0;      // log2 of buckets per coarse bin
-  int C = 0;       // coarse bins; 0 selects counting with global atomics
-  int nblk = 1;    // row chunks of the coarse passes
-  int ext = 0;     // bytes per carried CSR row start (0: no extents)
-  void* pstart = nullptr;   // [n] row starts in bucket order (int32/int64)
-  int32_t* plen = nullptr;  // [n] row lengths in bucket order
-  void* cstart = nullptr;   // [n] the same in coarse-bin order
-  int32_t* clen = nullptr;
-};
-int plan_ext(const skls_matrix& A);
-size_t plan_bytes(int64_t n, int64_t t, int ext);
-BucketPlan carve_plan(Arena& ar, int64_t n, int64_t t, int ext);
-// row_ptr (int32 or int64 per P.ext) is read only when P.ext != 0.
-int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, const void* row_ptr, hipStream_t s);
-
-int32_t choose_sketch_variant(const skls_matrix& A, int64_t t, int32_t variant);
+// Sketch variant the library runs for this input (SKLS_SKETCH_AUTO resolved).
+int32_t choose_sketch_variant(const skls_matrix& A, int64_t t, int32_t variant, int32_t out_dtype);
 size_t sketch_ws_bytes(const skls_matrix& A, int64_t t, int32_t variant);
 int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
                    const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,

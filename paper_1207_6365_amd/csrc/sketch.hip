@@ -2,14 +2,16 @@
 // Woodruff; the O(nnz(A)) product behind the main theorem of Section 3 and the
 // regression theorem of Section 7).
 //
-// Two schedules of the same sum SA[h(i), :] += sign(i) * A[i, :]:
+// Three schedules of the same sum SA[h(i), :] += sign(i) * A[i, :]:
 //  * ATOMIC: rows are streamed in storage order (fully coalesced reads of A)
 //    and every entry is added into SA with a device-wide float atomic.
-//  * SORTED: a counting sort groups the rows by bucket (count -> scan ->
-//    scatter); then one wavefront owns one bucket, sorts its row ids, reduces
-//    its rows in increasing row order (registers for dense rows, a per-wave LDS
-//    accumulator for CSR rows) and writes its row of SA exactly once.  No
-//    zero-fill of SA, no global atomics on SA, bit-reproducible results.
+//  * BINNED: a counting sort groups the rows into coarse bins of consecutive
+//    buckets; one block holds a bin's rows of SA in LDS, streams the bin's
+//    rows and adds them with LDS atomics, then writes its rows of SA once.
+//  * SORTED: a second counting pass orders each bin by bucket; one wavefront
+//    owns one bucket, sorts its row ids, reduces its rows in increasing row
+//    order (registers for dense rows, a per-wave LDS accumulator for CSR rows)
+//    and writes its row of SA exactly once: bit-reproducible results.
 #include <climits>
 #include <map>
 #include <mutex>
@@ -63,7 +65,61 @@ __global__ void k_fill_zero(uint32_t* __restrict__ p, size_t words) {
   for (size_t k = vec * 4 + i; k < words; k += stride) p[k] = 0;
 }
 
+// ---------------------------------------------------------------- plan entries
+// What the bucket plan carries per row.  Dense inputs: the row index.  CSR
+// inputs: a record with the row's extent, its index and its share of S b, so
+// the reduce kernels read row pointers and b only in storage order (here,
+// while the plan is built) and never gather them.
+template <typename TR, typename TO>
+struct alignas(sizeof(TR) + sizeof(TO) == 8 ? 16 : 8) CsrRec {
+  TR start;     // first nonzero of the row
+  int32_t len;  // nonzeros in the row
+  int32_t row;  // row index
+  TO sbv;       // scale(row) * b[row], 0 without b
+};
+static_assert(sizeof(CsrRec<int32_t, float>) == 16, "record layout");
+static_assert(sizeof(CsrRec<int64_t, float>) == 24, "record layout");
+static_assert(sizeof(CsrRec<int32_t, double>) == 24, "record layout");
+static_assert(sizeof(CsrRec<int64_t, double>) == 24, "record layout");
+
+// Inputs the plan reads in storage order.
+struct RowSrc {
+  const void* row_ptr;  // CSR only
+  const void* b;
+  int b_f64;
+  const float* w;
+};
+
+template <typename R>
+struct Entry;
+template <>
+struct Entry<int32_t> {
+  __device__ __forceinline__ static int32_t make(const RowSrc&, int64_t i, uint64_t) {
+    return static_cast<int32_t>(i);
+  }
+  __device__ __forceinline__ static int32_t row(const int32_t& e) { return e; }
+};
+template <typename TR, typename TO>
+struct Entry<CsrRec<TR, TO>> {
+  __device__ __forceinline__ static CsrRec<TR, TO> make(const RowSrc& src, int64_t i, uint64_t z) {
+    const TR* rp = static_cast<const TR*>(src.row_ptr);
+    CsrRec<TR, TO> e;
+    e.start = rp[i];
+    e.len = static_cast<int32_t>(rp[i + 1] - e.start);
+    e.row = static_cast<int32_t>(i);
+    e.sbv = TO(0);
+    if (src.b != nullptr) {
+      const TO sc = src.w ? static_cast<TO>(src.w[i]) : (negative_of(z) ? TO(-1) : TO(1));
+      e.sbv = sc * load_b<TO>(src.b, src.b_f64, i);
+    }
+    return e;
+  }
+  __device__ __forceinline__ static int32_t row(const CsrRec<TR, TO>& e) { return e.row; }
+};
+
 // ---------------------------------------------------------------- counting sort
+// One-level counting sort with global atomics, for plans with too many coarse
+// bins for the LDS counters of the two-level plan.
 __global__ void k_count(int64_t n, uint32_t t, uint64_t seed, int32_t* __restrict__ count, int32_t* __restrict__ rank) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -72,20 +128,13 @@ __global__ void k_count(int64_t n, uint32_t t, uint64_t seed, int32_t* __restric
   }
 }
 
-template <typename TR, bool EXT>
+template <typename R>
 __global__ void k_scatter(int64_t n, uint32_t t, uint64_t seed, const int32_t* __restrict__ off,
-                          const int32_t* __restrict__ rank, int32_t* __restrict__ perm, const TR* __restrict__ row_ptr,
-                          TR* __restrict__ pstart, int32_t* __restrict__ plen) {
+                          const int32_t* __restrict__ rank, RowSrc src, R* __restrict__ out) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const uint32_t h = bucket_of(splitmix64(seed, static_cast<uint64_t>(i)), t);
-    const int64_t p = off[h] + rank[i];
-    perm[p] = static_cast<int32_t>(i);
-    if (EXT) {
-      const TR s0 = row_ptr[i];
-      pstart[p] = s0;
-      plen[p] = static_cast<int32_t>(row_ptr[i + 1] - s0);
-    }
+    const uint64_t z = splitmix64(seed, static_cast<uint64_t>(i));
+    out[off[bucket_of(z, t)] + rank[i]] = Entry<R>::make(src, i, z);
   }
 }
 
@@ -159,66 +208,61 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const int32_t* in, int64
 
 // ---------------------------------------------------------------- two-level plan
 // Counting sort of the rows by bucket without global atomics.  Buckets are
-// grouped into coarse bins of `fine` consecutive buckets (a power of two).
+// grouped into coarse bins of 2^sh consecutive buckets.
 //  1. coarse count: each block counts its chunk of rows per coarse bin in LDS
 //     and writes the counts bin-major, so an exclusive scan of the whole array
 //     gives every (bin, block) its output offset;
-//  2. coarse scatter: each block writes its row ids to those offsets (LDS
-//     atomics hand out the slots);
-//  3. fine pass: one block per coarse bin counts, scans and scatters the bin's
-//     rows by bucket with LDS counters, and writes the bucket offsets.
+//  2. coarse scatter: each block writes its rows' plan entries to those
+//     offsets (LDS atomics hand out the slots);
+//  3. fine pass (bucket order only): one block per coarse bin counts, scans
+//     and scatters the bin's entries by bucket and writes the bucket offsets.
+// Large row chunks per block keep each (block, bin) run of entries long, so
+// the scattered writes of pass 2 stay close to whole cache lines.
+constexpr int kPlanThreads = 1024;
 constexpr int kPlanItems = 16;
-constexpr int kPlanChunk = kThreads * kPlanItems;  // rows per block in passes 1-2
+constexpr int kPlanChunk = kPlanThreads * kPlanItems;  // rows per block in passes 1-2
+constexpr int kMaxBins = 8192;                         // LDS counters of passes 1-2
 
-__global__ __launch_bounds__(kThreads) void k_plan_coarse_count(int64_t n, uint32_t t, uint64_t seed, int sh, int C,
-                                                                int nblk, int32_t* __restrict__ cnt) {
+__global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_count(int64_t n, uint32_t t, uint64_t seed, int sh,
+                                                                    int C, int nblk, int32_t* __restrict__ cnt) {
   extern __shared__ int32_t hist[];  // [C]
-  for (int c = threadIdx.x; c < C; c += kThreads) hist[c] = 0;
+  for (int c = threadIdx.x; c < C; c += kPlanThreads) hist[c] = 0;
   __syncthreads();
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kPlanChunk;
+#pragma unroll 4
   for (int k = 0; k < kPlanItems; ++k) {
-    const int64_t i = r0 + static_cast<int64_t>(k) * kThreads + threadIdx.x;
+    const int64_t i = r0 + static_cast<int64_t>(k) * kPlanThreads + threadIdx.x;
     if (i < n) atomicAdd(&hist[bucket_of(splitmix64(seed, static_cast<uint64_t>(i)), t) >> sh], 1);
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < C; c += kThreads) cnt[static_cast<size_t>(c) * nblk + blockIdx.x] = hist[c];
+  for (int c = threadIdx.x; c < C; c += kPlanThreads) cnt[static_cast<size_t>(c) * nblk + blockIdx.x] = hist[c];
 }
 
-// With EXT, each row also carries its CSR extent (start, length), read here
-// in storage order, so the reduce kernels never gather row pointers.
-template <typename TR, bool EXT>
-__global__ __launch_bounds__(kThreads) void k_plan_coarse_scatter(int64_t n, uint32_t t, uint64_t seed, int sh, int C,
-                                                                  int nblk, const int32_t* __restrict__ coff,
-                                                                  int32_t* __restrict__ coarse,
-                                                                  const TR* __restrict__ row_ptr,
-                                                                  TR* __restrict__ cstart, int32_t* __restrict__ clen) {
+template <typename R>
+__global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_scatter(int64_t n, uint32_t t, uint64_t seed, int sh,
+                                                                      int C, int nblk,
+                                                                      const int32_t* __restrict__ coff, RowSrc src,
+                                                                      R* __restrict__ coarse) {
   extern __shared__ int32_t pos[];  // [C]
-  for (int c = threadIdx.x; c < C; c += kThreads) pos[c] = coff[static_cast<size_t>(c) * nblk + blockIdx.x];
+  for (int c = threadIdx.x; c < C; c += kPlanThreads) pos[c] = coff[static_cast<size_t>(c) * nblk + blockIdx.x];
   __syncthreads();
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kPlanChunk;
+#pragma unroll 4
   for (int k = 0; k < kPlanItems; ++k) {
-    const int64_t i = r0 + static_cast<int64_t>(k) * kThreads + threadIdx.x;
+    const int64_t i = r0 + static_cast<int64_t>(k) * kPlanThreads + threadIdx.x;
     if (i < n) {
-      const int c = static_cast<int>(bucket_of(splitmix64(seed, static_cast<uint64_t>(i)), t) >> sh);
-      const int32_t slot = atomicAdd(&pos[c], 1);
-      coarse[slot] = static_cast<int32_t>(i);
-      if (EXT) {
-        const TR s0 = row_ptr[i];
-        cstart[slot] = s0;
-        clen[slot] = static_cast<int32_t>(row_ptr[i + 1] - s0);
-      }
+      const uint64_t z = splitmix64(seed, static_cast<uint64_t>(i));
+      const R e = Entry<R>::make(src, i, z);
+      const int32_t slot = atomicAdd(&pos[bucket_of(z, t) >> sh], 1);
+      coarse[slot] = e;
     }
   }
 }
 
-template <typename TR, bool EXT>
+template <typename R>
 __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, uint64_t seed, int sh, int C, int nblk,
-                                                        const int32_t* __restrict__ coff,
-                                                        const int32_t* __restrict__ coarse,
-                                                        int32_t* __restrict__ perm, int32_t* __restrict__ off,
-                                                        const TR* __restrict__ cstart,
-                                                        const int32_t* __restrict__ clen, TR* __restrict__ pstart,
-                                                        int32_t* __restrict__ plen) {
+                                                        const int32_t* __restrict__ coff, const R* __restrict__ coarse,
+                                                        R* __restrict__ fine_out, int32_t* __restrict__ off) {
   extern __shared__ int32_t fcnt[];  // [fine]
   __shared__ int32_t wsum[kThreads / kWave];
   const int fine = 1 << sh;
@@ -229,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, u
   __syncthreads();
   const uint32_t base_bucket = static_cast<uint32_t>(c) << sh;
   for (int64_t p = beg + threadIdx.x; p < end; p += kThreads) {
-    const int32_t r = coarse[p];
+    const int32_t r = Entry<R>::row(coarse[p]);
     atomicAdd(&fcnt[bucket_of(splitmix64(seed, static_cast<uint64_t>(r)), t) - base_bucket], 1);
   }
   __syncthreads();
@@ -253,184 +297,406 @@ __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, u
   if (c == C - 1 && threadIdx.x == 0) off[t] = static_cast<int32_t>(n);
   __syncthreads();
   for (int64_t p = beg + threadIdx.x; p < end; p += kThreads) {
-    const int32_t r = coarse[p];
-    const uint32_t f = bucket_of(splitmix64(seed, static_cast<uint64_t>(r)), t) - base_bucket;
-    const int64_t dstp = beg + atomicAdd(&fcnt[f], 1);
-    perm[dstp] = r;
-    if (EXT) {
-      pstart[dstp] = cstart[p];
-      plen[dstp] = clen[p];
+    const R e = coarse[p];
+    const uint32_t f = bucket_of(splitmix64(seed, static_cast<uint64_t>(Entry<R>::row(e))), t) - base_bucket;
+    fine_out[beg + atomicAdd(&fcnt[f], 1)] = e;
+  }
+}
+
+// ---------------------------------------------------------------- CSR row gather
+// A wavefront reduces up to 128 CSR rows at a time (two per lane: rows lane
+// and lane + 64 of the chunk) into an LDS accumulator.  Wave-wide scans of
+// the row lengths give each row its offset in the chunk's flat list of
+// nonzeros; a byte table in LDS maps every position of that list to its row
+// (a binary search over the offsets when the table does not fit), and the
+// column/value loads of 64 * K positions are issued back to back before their
+// products are added into the accumulator.  When every row of the chunk
+// starts and ends on a multiple of four nonzeros (and the arrays are 16-byte
+// aligned), positions are groups of four: one 16-byte load of column indices
+// and one of values per lane.
+constexpr int kChunkRows = 2 * kWave;
+constexpr int kPosCap = 2048;
+constexpr int kBurst = 16;
+constexpr int kBurstQ = 8;
+
+template <typename TR, typename TO>
+struct alignas(16) RowRef {
+  TR base;      // row start minus its offset in the flat list
+  int32_t off;  // row of the accumulator (element offset)
+  TO scale;     // sign or learned value of the row
+};
+
+template <typename TR, typename TO>
+struct GatherLds {
+  RowRef<TR, TO> ref[kChunkRows];
+  int32_t pfx[kChunkRows];
+  uint8_t pos2row[kPosCap];
+};
+
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS round trips).
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+  return x;
+}
+
+// Floating-point adds into LDS as compare-and-swap loops.  gfx950 executes
+// ds_add_f32 / ds_add_f64 at a small fraction of the rate of its integer LDS
+// atomics (about 190 cycles per wave64 instruction per compute unit against
+// 7 for ds_add_u32, measured), while ds_cmpst runs at integer speed; a lane
+// whose swap lost to another lane or wave retries with the value it saw.
+template <typename T>
+struct FBits;
+template <>
+struct FBits<float> {
+  using U = uint32_t;
+  __device__ __forceinline__ static U to(float x) { return __float_as_uint(x); }
+  __device__ __forceinline__ static float from(U u) { return __uint_as_float(u); }
+};
+template <>
+struct FBits<double> {
+  using U = unsigned long long;
+  __device__ __forceinline__ static U to(double x) { return static_cast<U>(__double_as_longlong(x)); }
+  __device__ __forceinline__ static double from(U u) { return __longlong_as_double(static_cast<long long>(u)); }
+};
+
+// acc[a[k]] += v[k] for the k < N whose bit is set in `mask` (elements of
+// one lane may alias: their swaps are ordered and a stale one retries).
+template <typename TO, int N>
+__device__ __forceinline__ void lds_add(TO* acc, const int32_t (&a)[N], const TO (&v)[N],
+                                        uint32_t mask = 0xffffffffu) {
+  static_assert(N <= 32, "pending mask is 32 bits");
+  using B = FBits<TO>;
+  using U = typename B::U;
+  U* q = reinterpret_cast<U*>(acc);
+  U old[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) old[k] = q[a[k]];
+  uint32_t pend = mask & (N == 32 ? 0xffffffffu : ((1u << N) - 1u));
+  while (pend != 0) {
+    U got[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      got[k] = ((pend >> k) & 1u) ? atomicCAS(q + a[k], old[k], B::to(B::from(old[k]) + v[k])) : old[k];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      if (got[k] == old[k]) pend &= ~(1u << k);
+      old[k] = got[k];
     }
+  }
+}
+
+template <typename TO>
+__device__ __forceinline__ void lds_add1(TO* acc, int32_t a, TO v) {
+  const int32_t aa[1] = {a};
+  const TO vv[1] = {v};
+  lds_add<TO, 1>(acc, aa, vv);
+}
+
+// Column indices and values of E consecutive nonzeros.
+template <typename TV, typename TO, int E>
+struct Group {
+  __device__ __forceinline__ static void load(const int32_t* __restrict__ c, const TV* __restrict__ v,
+                                              int32_t (&ci)[E], TO (&vo)[E]) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      ci[e] = c[e];
+      vo[e] = load_as<TO>(v, e);
+    }
+  }
+};
+template <typename TV, typename TO>
+struct Group<TV, TO, 4> {
+  __device__ __forceinline__ static void load(const int32_t* __restrict__ c, const TV* __restrict__ v,
+                                              int32_t (&ci)[4], TO (&vo)[4]) {
+    const int4 x = *reinterpret_cast<const int4*>(c);
+    ci[0] = x.x;
+    ci[1] = x.y;
+    ci[2] = x.z;
+    ci[3] = x.w;
+    if constexpr (std::is_same<TV, float>::value) {
+      const float4 y = *reinterpret_cast<const float4*>(v);
+      vo[0] = y.x;
+      vo[1] = y.y;
+      vo[2] = y.z;
+      vo[3] = y.w;
+    } else if constexpr (std::is_same<TV, double>::value) {
+      const double2 y0 = *reinterpret_cast<const double2*>(v);
+      const double2 y1 = *reinterpret_cast<const double2*>(v + 2);
+      vo[0] = static_cast<TO>(y0.x);
+      vo[1] = static_cast<TO>(y0.y);
+      vo[2] = static_cast<TO>(y1.x);
+      vo[3] = static_cast<TO>(y1.y);
+    } else {
+      const uint2 y = *reinterpret_cast<const uint2*>(v);
+      vo[0] = bf16_lo(y.x);
+      vo[1] = bf16_hi(y.x);
+      vo[2] = bf16_lo(y.y);
+      vo[3] = bf16_hi(y.y);
+    }
+  }
+};
+
+template <bool TABLE, typename TR, typename TO>
+__device__ __forceinline__ int row_at(const GatherLds<TR, TO>& G, int pp) {
+  if (TABLE) return G.pos2row[pp];
+  int q = 0;  // largest q with pfx[q] <= pp (empty rows share the next offset)
+#pragma unroll
+  for (int step = kChunkRows / 2; step > 0; step >>= 1)
+    if (G.pfx[q + step] <= pp) q += step;
+  return q;
+}
+
+// One burst: positions p0 + u * 64 + lane.  Positions past the end repeat
+// position 0 (valid whenever total > 0) so that every load of the burst is
+// unconditional and in flight together, and add nothing.
+template <typename TV, typename TR, typename TO, bool TABLE, int E>
+__device__ __forceinline__ void gather_burst(const GatherLds<TR, TO>& G, const int32_t* __restrict__ col,
+                                             const TV* __restrict__ val, TO* acc, int trash, int p0, int total,
+                                             int lane) {
+  constexpr int K = E == 4 ? kBurstQ : kBurst;
+  int pp[K], q[K];
+  bool ok[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int p = p0 + u * kWave + lane;
+    ok[u] = p < total;
+    pp[u] = ok[u] ? p : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u) q[u] = row_at<TABLE>(G, pp[u]);
+  RowRef<TR, TO> ref[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) ref[u] = G.ref[q[u]];
+  int32_t c[K][E];
+  TO v[K][E];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const TR k = ref[u].base + static_cast<TR>(E * pp[u]);
+    Group<TV, TO, E>::load(col + k, val + k, c[u], v[u]);
+  }
+  // adds in groups of eight elements
+  constexpr int NG = E * K >= 8 ? 8 : E * K;
+  static_assert((E * K) % NG == 0, "group size");
+#pragma unroll
+  for (int g0 = 0; g0 < E * K; g0 += NG) {
+    int32_t a[NG];
+    TO x[NG];
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const int u = (g0 + k) / E, e = (g0 + k) % E;
+      a[k] = ref[u].off + c[u][e];
+      x[k] = ref[u].scale * v[u][e];
+      m |= ok[u] ? (1u << k) : 0u;
+    }
+    lds_add<TO, NG>(acc, a, x, m);
+  }
+}
+
+// This lane's two rows of the chunk: start, length (0: no row), scale and
+// accumulator row.
+template <typename TR, typename TO>
+struct RowPair {
+  TR st[2];
+  int32_t len[2];
+  TO sc[2];
+  int32_t off[2];
+};
+
+// Reduce the chunk's rows into acc; `trash` is the offset of a spare row of acc.
+template <typename TV, typename TR, typename TO>
+__device__ __forceinline__ void gather_chunk(GatherLds<TR, TO>& G, const RowPair<TR, TO>& R, int quad_ok,
+                                             const int32_t* __restrict__ col, const TV* __restrict__ val, TO* acc,
+                                             int trash, int lane) {
+  const bool quad = quad_ok && __all((((static_cast<int64_t>(R.st[0]) | R.len[0]) & 3) == 0) &&
+                                     (((static_cast<int64_t>(R.st[1]) | R.len[1]) & 3) == 0));
+  const int32_t u0 = quad ? (R.len[0] >> 2) : R.len[0];
+  const int32_t u1 = quad ? (R.len[1] >> 2) : R.len[1];
+  const int32_t i0 = wave_incl_scan(u0), i1 = wave_incl_scan(u1);
+  const int32_t t0 = __builtin_amdgcn_readlane(i0, kWave - 1);
+  const int32_t total = t0 + __builtin_amdgcn_readlane(i1, kWave - 1);
+  if (total == 0) return;
+  const int32_t pf0 = i0 - u0, pf1 = t0 + i1 - u1;
+  const int E = quad ? 4 : 1;
+  RowRef<TR, TO> r0, r1;
+  r0.base = R.st[0] - static_cast<TR>(E * pf0);
+  r0.off = R.off[0];
+  r0.scale = R.sc[0];
+  r1.base = R.st[1] - static_cast<TR>(E * pf1);
+  r1.off = R.off[1];
+  r1.scale = R.sc[1];
+  G.ref[lane] = r0;
+  G.ref[lane + kWave] = r1;
+  G.pfx[lane] = pf0;
+  G.pfx[lane + kWave] = pf1;
+  const bool table = total <= kPosCap && !__any(u0 > kWave || u1 > kWave);
+  if (table)
+    for (int e = 0; __any(e < u0 || e < u1); ++e) {
+      if (e < u0) G.pos2row[pf0 + e] = static_cast<uint8_t>(lane);
+      if (e < u1) G.pos2row[pf1 + e] = static_cast<uint8_t>(lane + kWave);
+    }
+  wave_sync();
+  if (quad) {
+    if (table) {
+      for (int p0 = 0; p0 < total; p0 += kWave * kBurstQ)
+        gather_burst<TV, TR, TO, true, 4>(G, col, val, acc, trash, p0, total, lane);
+    } else {
+      for (int p0 = 0; p0 < total; p0 += kWave * kBurstQ)
+        gather_burst<TV, TR, TO, false, 4>(G, col, val, acc, trash, p0, total, lane);
+    }
+  } else if (table) {
+    for (int p0 = 0; p0 < total; p0 += kWave * kBurst)
+      gather_burst<TV, TR, TO, true, 1>(G, col, val, acc, trash, p0, total, lane);
+  } else {
+    for (int p0 = 0; p0 < total; p0 += kWave * kBurst)
+      gather_burst<TV, TR, TO, false, 1>(G, col, val, acc, trash, p0, total, lane);
+  }
+  wave_sync();
+}
+
+// ---------------------------------------------------------------- a2: CSR, binned
+// LDS-privatised scatter-add.  One block per (coarse bin, split) holds the
+// bin's 2^sh rows of S A in LDS, its waves stream the bin's plan records in
+// coarse order (128 rows per wave step) and add every product into the LDS
+// copy with LDS atomics; the block then writes the rows once (one split) or
+// adds them into S A with global atomics (several splits of a crowded bin,
+// S A zeroed first).  The order of the additions is not fixed, so float
+// results are not bit-reproducible (integer-valued inputs are exact).
+constexpr int kBinThreads = 512;
+constexpr int kBinWaves = kBinThreads / kWave;
+
+template <typename TR, typename TO>
+__device__ __forceinline__ CsrRec<TR, TO> load_rec(const CsrRec<TR, TO>* __restrict__ recs, int64_t j, bool has) {
+  CsrRec<TR, TO> e;
+  if (has) {
+    e = recs[j];
+  } else {
+    e.start = TR(0);
+    e.len = 0;
+    e.row = 0;
+    e.sbv = TO(0);
+  }
+  return e;
+}
+
+template <typename TV, typename TR, typename TO>
+__global__ __launch_bounds__(kBinThreads) void k_sketch_csr_binned(
+    int d, uint32_t t, int sh, int C, int nblk, int splits, int64_t n, uint64_t seed,
+    const int32_t* __restrict__ col, const TV* __restrict__ val, const float* __restrict__ w,
+    const int32_t* __restrict__ coff, const CsrRec<TR, TO>* __restrict__ recs, TO* __restrict__ SA,
+    TO* __restrict__ Sb, int acc_bytes, int sb_bytes, int quad_ok) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int c = blockIdx.x / splits, sp = blockIdx.x % splits;
+  const uint32_t bk0 = static_cast<uint32_t>(c) << sh;
+  const int fine = 1 << sh;
+  const int nbk = (t - bk0) < static_cast<uint32_t>(fine) ? static_cast<int>(t - bk0) : fine;
+  TO* acc = reinterpret_cast<TO*>(smem);
+  TO* sbacc = reinterpret_cast<TO*>(smem + acc_bytes);
+  GatherLds<TR, TO>& G =
+      *reinterpret_cast<GatherLds<TR, TO>*>(smem + acc_bytes + sb_bytes + wid * sizeof(GatherLds<TR, TO>));
+  const int64_t b0 = coff[static_cast<size_t>(c) * nblk];
+  const int64_t b1 = (c + 1 < C) ? coff[static_cast<size_t>(c + 1) * nblk] : n;
+  const int64_t beg = b0 + (b1 - b0) * sp / splits, end = b0 + (b1 - b0) * (sp + 1) / splits;
+  const int nacc = nbk * d;
+  for (int e = threadIdx.x; e < nacc; e += kBinThreads) acc[e] = TO(0);
+  for (int e = threadIdx.x; e < nbk; e += kBinThreads) sbacc[e] = TO(0);
+  __syncthreads();
+  constexpr int64_t kStep = static_cast<int64_t>(kBinWaves) * kChunkRows;
+  int64_t j0 = beg + static_cast<int64_t>(wid) * kChunkRows;
+  // Record loads are unconditional: indexes past the end read the bin's last
+  // record (its row counts as empty), so no load sits behind a branch whose
+  // join makes the compiler wait for it.
+  auto rec_at = [&](int64_t j) -> CsrRec<TR, TO> { return recs[j < end ? j : end - 1]; };
+  CsrRec<TR, TO> cur[2];
+  if (j0 < end) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) cur[h] = rec_at(j0 + h * kWave + lane);
+  }
+  for (; j0 < end; j0 += kStep) {
+    RowPair<TR, TO> R;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bool has = j0 + h * kWave + lane < end;
+      const uint64_t z = splitmix64(seed, static_cast<uint64_t>(cur[h].row));
+      const int lb = static_cast<int>(bucket_of(z, t) - bk0);
+      R.st[h] = cur[h].start;
+      R.len[h] = has ? cur[h].len : 0;
+      R.sc[h] = w ? static_cast<TO>(w[cur[h].row]) : (negative_of(z) ? TO(-1) : TO(1));
+      R.off[h] = lb * d;
+      if (Sb != nullptr && has) lds_add1(sbacc, lb, cur[h].sbv);
+    }
+    // next step's records are requested after this step's rows are set up
+    // (so no wait there covers them) and before this step's gathers
+    CsrRec<TR, TO> nxt[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) nxt[h] = rec_at(j0 + kStep + h * kWave + lane);
+    gather_chunk<TV, TR, TO>(G, R, quad_ok, col, val, acc, fine * d, lane);
+    cur[0] = nxt[0];
+    cur[1] = nxt[1];
+  }
+  __syncthreads();
+  TO* out = SA + static_cast<size_t>(bk0) * d;
+  if (splits == 1) {
+    for (int e = threadIdx.x; e < nacc; e += kBinThreads) out[e] = acc[e];
+    if (Sb != nullptr)
+      for (int e = threadIdx.x; e < nbk; e += kBinThreads) Sb[bk0 + e] = sbacc[e];
+  } else {
+    for (int e = threadIdx.x; e < nacc; e += kBinThreads) unsafeAtomicAdd(out + e, acc[e]);
+    if (Sb != nullptr)
+      for (int e = threadIdx.x; e < nbk; e += kBinThreads) unsafeAtomicAdd(Sb + bk0 + e, sbacc[e]);
   }
 }
 
 // ---------------------------------------------------------------- a2: CSR, sorted
-// A wavefront reduces one bucket at a time.  The plan already carries each row's extent
-// (start, length), so the bucket's rows are loaded with coalesced reads and
-// sorted by row id (up to kCsrSortCap rows, two per lane).  Rows are then
-// taken 64 at a time: a wave-wide scan of the lengths gives each row its
-// offset in the chunk's flat list of nonzeros, a byte table in LDS maps every
-// position of that list to its row, and the column/value loads of up to
-// 64 * kBurst positions are issued back to back before their products are
-// added into the per-wave LDS row of S A (written once at the end).
+// One wavefront reduces one bucket at a time from the plan's records in
+// bucket order: it sorts the bucket's rows by row id (up to kCsrSortCap rows,
+// two per lane), gathers them 128 at a time into its LDS row of S A and writes
+// that row once.  Row order is fixed, so results are bit-reproducible for
+// buckets of up to kCsrSortCap rows.
 constexpr int kCsrSortCap = 2 * kWave;
-constexpr int kPosCap = 2048;
-constexpr int kBurst = 16;
 
 template <typename TR, typename TO>
 struct CsrLds {
   TO dscale[kCsrSortCap];
+  TO dsbv[kCsrSortCap];
   TR dstart[kCsrSortCap];
   int32_t dlen[kCsrSortCap];
-  int32_t drow[kCsrSortCap];
-  TR base[kWave];      // row start minus its offset in the flat list
-  TO rscale[kWave];
-  int32_t pfx[kWave];  // offsets (binary search when the table does not fit)
-  uint8_t pos2row[kPosCap];
+  GatherLds<TR, TO> g;
 };
 
-template <typename TV, typename TR, typename TO, bool TABLE>
-__device__ __forceinline__ void csr_burst(const CsrLds<TR, TO>& L, const int32_t* __restrict__ col,
-                                          const TV* __restrict__ val, TO* acc, int p0, int total, int lane) {
-  int32_t c[kBurst];
-  TO v[kBurst];
-  bool ok[kBurst];
-#pragma unroll
-  for (int u = 0; u < kBurst; ++u) {
-    const int p = p0 + u * kWave + lane;
-    ok[u] = p < total;
-    const int pp = ok[u] ? p : 0;
-    int q;
-    if (TABLE) {
-      q = L.pos2row[pp];
-    } else {
-      q = 0;  // largest q with pfx[q] <= pp (empty rows share the next offset)
-#pragma unroll
-      for (int step = kWave / 2; step > 0; step >>= 1)
-        if (L.pfx[q + step] <= pp) q += step;
-    }
-    const TR k = L.base[q] + static_cast<TR>(pp);
-    c[u] = col[k];
-    v[u] = L.rscale[q] * load_as<TO>(val, static_cast<size_t>(k));
-  }
-#pragma unroll
-  for (int u = 0; u < kBurst; ++u)
-    if (ok[u]) atomicAdd(&acc[c[u]], v[u]);
-}
-
-// Four consecutive values of a row (16-byte aligned group of nonzeros).
-template <typename TV, typename TO>
-struct Quad {
-  __device__ __forceinline__ static void load(const TV* __restrict__ p, TO (&o)[4]) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = load_as<TO>(p, k);
-  }
-};
-template <typename TO>
-struct Quad<float, TO> {
-  __device__ __forceinline__ static void load(const float* __restrict__ p, TO (&o)[4]) {
-    const float4 x = *reinterpret_cast<const float4*>(p);
-    o[0] = x.x;
-    o[1] = x.y;
-    o[2] = x.z;
-    o[3] = x.w;
-  }
-};
-template <typename TO>
-struct Quad<double, TO> {
-  __device__ __forceinline__ static void load(const double* __restrict__ p, TO (&o)[4]) {
-    const double2 x = *reinterpret_cast<const double2*>(p);
-    const double2 y = *reinterpret_cast<const double2*>(p + 2);
-    o[0] = static_cast<TO>(x.x);
-    o[1] = static_cast<TO>(x.y);
-    o[2] = static_cast<TO>(y.x);
-    o[3] = static_cast<TO>(y.y);
-  }
-};
-template <typename TO>
-struct Quad<bf16_t, TO> {
-  __device__ __forceinline__ static void load(const bf16_t* __restrict__ p, TO (&o)[4]) {
-    const uint2 x = *reinterpret_cast<const uint2*>(p);
-    o[0] = bf16_lo(x.x);
-    o[1] = bf16_hi(x.x);
-    o[2] = bf16_lo(x.y);
-    o[3] = bf16_hi(x.y);
-  }
-};
-
-// Burst over groups of four nonzeros (rows whose start and length are
-// multiples of four): one 16-byte load of columns and one of values per
-// lane, so a load instruction covers sixteen rows of sixteen nonzeros.
-constexpr int kBurstQ = 4;
-
-template <typename TV, typename TR, typename TO, bool TABLE>
-__device__ __forceinline__ void csr_burst_quad(const CsrLds<TR, TO>& L, const int32_t* __restrict__ col,
-                                               const TV* __restrict__ val, TO* acc, int p0, int total, int lane) {
-  int4 c[kBurstQ];
-  TO v[kBurstQ][4];
-  TO sc[kBurstQ];
-  bool ok[kBurstQ];
-#pragma unroll
-  for (int u = 0; u < kBurstQ; ++u) {
-    const int p = p0 + u * kWave + lane;
-    ok[u] = p < total;
-    const int pp = ok[u] ? p : 0;
-    int q;
-    if (TABLE) {
-      q = L.pos2row[pp];
-    } else {
-      q = 0;
-#pragma unroll
-      for (int step = kWave / 2; step > 0; step >>= 1)
-        if (L.pfx[q + step] <= pp) q += step;
-    }
-    const TR k = L.base[q] + static_cast<TR>(4 * pp);
-    c[u] = *reinterpret_cast<const int4*>(col + k);
-    Quad<TV, TO>::load(val + k, v[u]);
-    sc[u] = L.rscale[q];
-  }
-#pragma unroll
-  for (int u = 0; u < kBurstQ; ++u)
-    if (ok[u]) {
-      atomicAdd(&acc[c[u].x], sc[u] * v[u][0]);
-      atomicAdd(&acc[c[u].y], sc[u] * v[u][1]);
-      atomicAdd(&acc[c[u].z], sc[u] * v[u][2]);
-      atomicAdd(&acc[c[u].w], sc[u] * v[u][3]);
-    }
-}
-
-// Prefetched description of one bucket: its range in the plan and, for up
-// to two rows per lane, the row id, extent and length.
-template <typename TR>
+template <typename TR, typename TO>
 struct CsrMeta {
   int beg, m;
-  int32_t r0, r1, l0, l1;
-  TR s0, s1;
+  CsrRec<TR, TO> a, b;  // rows lane and lane + 64 of the bucket (row INT_MAX: none)
 };
 
-template <typename TR>
-__device__ __forceinline__ CsrMeta<TR> csr_meta(const int32_t* __restrict__ perm, const TR* __restrict__ pstart,
-                                                const int32_t* __restrict__ plen, int beg, int m, int lane) {
-  CsrMeta<TR> q;
+template <typename TR, typename TO>
+__device__ __forceinline__ CsrMeta<TR, TO> csr_meta(const CsrRec<TR, TO>* __restrict__ recs, int beg, int m,
+                                                    int lane) {
+  CsrMeta<TR, TO> q;
   q.beg = beg;
   q.m = m;
   const bool h0 = lane < m && m <= kCsrSortCap, h1 = lane + kWave < m && m <= kCsrSortCap;
-  q.r0 = h0 ? perm[beg + lane] : INT_MAX;
-  q.r1 = h1 ? perm[beg + kWave + lane] : INT_MAX;
-  q.s0 = h0 ? pstart[beg + lane] : TR(0);
-  q.s1 = h1 ? pstart[beg + kWave + lane] : TR(0);
-  q.l0 = h0 ? plen[beg + lane] : 0;
-  q.l1 = h1 ? plen[beg + kWave + lane] : 0;
+  q.a = load_rec(recs, beg + lane, h0);
+  q.b = load_rec(recs, beg + kWave + lane, h1);
+  if (!h0) q.a.row = INT_MAX;
+  if (!h1) q.b.row = INT_MAX;
   return q;
 }
 
 // Each wavefront owns `bpw` consecutive buckets and walks them in order,
-// loading the next bucket's rows while it reduces the current one.
+// loading the next bucket's records while it reduces the current one.
 template <typename TV, typename TR, typename TO>
 __global__ __launch_bounds__(kThreads) void k_sketch_csr_sorted(
     int d, uint32_t t, int bpw, uint64_t seed, const int32_t* __restrict__ col, const TV* __restrict__ val,
-    const void* __restrict__ b, int b_f64, const float* __restrict__ w, const int32_t* __restrict__ off,
-    const int32_t* __restrict__ perm, const TR* __restrict__ pstart, const int32_t* __restrict__ plen,
+    const float* __restrict__ w, const int32_t* __restrict__ off, const CsrRec<TR, TO>* __restrict__ recs,
     TO* __restrict__ SA, TO* __restrict__ Sb, int per_wave, int quad_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -443,105 +709,71 @@ __global__ __launch_bounds__(kThreads) void k_sketch_csr_sorted(
   // bucket offsets of this wave's range (bpw < 64): lane k holds off[b0 + k]
   const int32_t myoff = lane <= nb ? off[b0 + lane] : 0;
   auto off_at = [&](int k) -> int32_t { return __builtin_amdgcn_readlane(myoff, k); };
-  CsrMeta<TR> cur = csr_meta<TR>(perm, pstart, plen, off_at(0), off_at(1) - off_at(0), lane);
+  CsrMeta<TR, TO> cur = csr_meta<TR, TO>(recs, off_at(0), off_at(1) - off_at(0), lane);
   for (int kb = 0; kb < nb; ++kb) {
     const uint32_t bkt = static_cast<uint32_t>(b0 + kb);
-    CsrMeta<TR> nxt = cur;
+    CsrMeta<TR, TO> nxt = cur;
     if (kb + 1 < nb) {
       const int nbeg = off_at(kb + 1);
-      nxt = csr_meta<TR>(perm, pstart, plen, nbeg, off_at(kb + 2) - nbeg, lane);
+      nxt = csr_meta<TR, TO>(recs, nbeg, off_at(kb + 2) - nbeg, lane);
     }
     for (int k = lane; k < d; k += kWave) acc[k] = TO(0);
     const int beg = cur.beg, m = cur.m;
     const bool sorted = m <= kCsrSortCap;
     if (sorted) {
+      const int32_t r0 = cur.a.row, r1 = cur.b.row;
       int rk0 = 0, rk1 = 0;
       const int m0 = m < kWave ? m : kWave;
       for (int k = 0; k < m0; ++k) {
-        const int32_t x = __builtin_amdgcn_readlane(cur.r0, k);
-        rk0 += x < cur.r0 ? 1 : 0;
-        rk1 += x < cur.r1 ? 1 : 0;
+        const int32_t x = __builtin_amdgcn_readlane(r0, k);
+        rk0 += x < r0 ? 1 : 0;
+        rk1 += x < r1 ? 1 : 0;
       }
       for (int k = kWave; k < m; ++k) {
-        const int32_t x = __builtin_amdgcn_readlane(cur.r1, k - kWave);
-        rk0 += x < cur.r0 ? 1 : 0;
-        rk1 += x < cur.r1 ? 1 : 0;
+        const int32_t x = __builtin_amdgcn_readlane(r1, k - kWave);
+        rk0 += x < r0 ? 1 : 0;
+        rk1 += x < r1 ? 1 : 0;
       }
       if (lane < m) {
-        L.drow[rk0] = cur.r0;
-        L.dstart[rk0] = cur.s0;
-        L.dlen[rk0] = cur.l0;
-        L.dscale[rk0] = row_scale<TO>(seed, cur.r0, w);
+        L.dstart[rk0] = cur.a.start;
+        L.dlen[rk0] = cur.a.len;
+        L.dscale[rk0] = row_scale<TO>(seed, r0, w);
+        L.dsbv[rk0] = cur.a.sbv;
       }
       if (lane + kWave < m) {
-        L.drow[rk1] = cur.r1;
-        L.dstart[rk1] = cur.s1;
-        L.dlen[rk1] = cur.l1;
-        L.dscale[rk1] = row_scale<TO>(seed, cur.r1, w);
+        L.dstart[rk1] = cur.b.start;
+        L.dlen[rk1] = cur.b.len;
+        L.dscale[rk1] = row_scale<TO>(seed, r1, w);
+        L.dsbv[rk1] = cur.b.sbv;
       }
     }
     wave_sync();
     TO sb = TO(0);
-    for (int j0 = 0; j0 < m; j0 += kWave) {
-      const int j = j0 + lane;
-      int32_t len = 0;
-      TR st = 0;
-      TO sc = TO(0);
-      if (j < m) {
-        int32_t r;
-        if (sorted) {
-          r = L.drow[j];
-          st = L.dstart[j];
-          len = L.dlen[j];
-          sc = L.dscale[j];
-        } else {
-          r = perm[beg + j];
-          st = pstart[beg + j];
-          len = plen[beg + j];
-          sc = row_scale<TO>(seed, r, w);
-        }
-        if (b != nullptr) sb += sc * load_b<TO>(b, b_f64, r);
-      }
-      // groups of four nonzeros when every row of the chunk allows it
-      const bool quad = quad_ok && __all(((static_cast<int64_t>(st) | len) & 3) == 0);
-      const int32_t units = quad ? (len >> 2) : len;
-      int32_t incl = units, mx = units;
+    for (int j0 = 0; j0 < m; j0 += kChunkRows) {
+      RowPair<TR, TO> R;
 #pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int32_t y = __shfl_up(incl, o, kWave);
-        if (lane >= o) incl += y;
-        const int32_t z = __shfl_xor(mx, o, kWave);
-        mx = z > mx ? z : mx;
-      }
-      const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
-      const int32_t pf = incl - units;
-      L.base[lane] = st - static_cast<TR>(quad ? 4 * pf : pf);
-      L.rscale[lane] = sc;
-      L.pfx[lane] = pf;
-      const bool table = total <= kPosCap && mx <= kWave;
-      if (table)
-        for (int e = 0; e < mx; ++e)
-          if (e < units) L.pos2row[pf + e] = static_cast<uint8_t>(lane);
-      wave_sync();
-      // Branch-free bursts: positions past the end read position 0 (always
-      // valid when total > 0) and are masked afterwards, so every load of
-      // the burst is issued before the first wait.
-      if (quad) {
-        if (table) {
-          for (int p0 = 0; p0 < total; p0 += kWave * kBurstQ)
-            csr_burst_quad<TV, TR, TO, true>(L, col, val, acc, p0, total, lane);
-        } else {
-          for (int p0 = 0; p0 < total; p0 += kWave * kBurstQ)
-            csr_burst_quad<TV, TR, TO, false>(L, col, val, acc, p0, total, lane);
+      for (int h = 0; h < 2; ++h) {
+        const int j = j0 + h * kWave + lane;
+        R.st[h] = TR(0);
+        R.len[h] = 0;
+        R.sc[h] = TO(0);
+        R.off[h] = 0;
+        if (j < m) {
+          if (sorted) {
+            R.st[h] = L.dstart[j];
+            R.len[h] = L.dlen[j];
+            R.sc[h] = L.dscale[j];
+            sb += L.dsbv[j];
+          } else {
+            const CsrRec<TR, TO> e = recs[beg + j];
+            R.st[h] = e.start;
+            R.len[h] = e.len;
+            R.sc[h] = row_scale<TO>(seed, e.row, w);
+            sb += e.sbv;
+          }
         }
-      } else if (table) {
-        for (int p0 = 0; p0 < total; p0 += kWave * kBurst)
-          csr_burst<TV, TR, TO, true>(L, col, val, acc, p0, total, lane);
-      } else {
-        for (int p0 = 0; p0 < total; p0 += kWave * kBurst)
-          csr_burst<TV, TR, TO, false>(L, col, val, acc, p0, total, lane);
       }
-      wave_sync();
+      gather_chunk<TV, TR, TO>(L.g, R, quad_ok, col, val, acc, d, lane);
     }
     sb = wave_sum(sb);
     TO* out = SA + static_cast<size_t>(bkt) * d;
@@ -713,6 +945,75 @@ __global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted(
   }
 }
 
+// ---------------------------------------------------------------- a2: dense, binned
+// The same LDS-privatised schedule for dense rows: each wave takes rows of
+// the bin (RB at a time, all loads in flight together) and adds them, column
+// slices per lane, into the bin's LDS rows of S A.
+template <typename TV, typename TO, int V>
+__global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
+    int d, int64_t ld, uint32_t t, int sh, int C, int nblk, int splits, int64_t n, uint64_t seed,
+    const TV* __restrict__ A, const void* __restrict__ b, int b_f64, const float* __restrict__ w,
+    const int32_t* __restrict__ coff, const int32_t* __restrict__ rows, TO* __restrict__ SA, TO* __restrict__ Sb,
+    int acc_bytes) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int RB = 4;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int c = blockIdx.x / splits, sp = blockIdx.x % splits;
+  const uint32_t bk0 = static_cast<uint32_t>(c) << sh;
+  const int fine = 1 << sh;
+  const int nbk = (t - bk0) < static_cast<uint32_t>(fine) ? static_cast<int>(t - bk0) : fine;
+  TO* acc = reinterpret_cast<TO*>(smem);
+  TO* sbacc = reinterpret_cast<TO*>(smem + acc_bytes);
+  const int64_t b0 = coff[static_cast<size_t>(c) * nblk];
+  const int64_t b1 = (c + 1 < C) ? coff[static_cast<size_t>(c + 1) * nblk] : n;
+  const int64_t beg = b0 + (b1 - b0) * sp / splits, end = b0 + (b1 - b0) * (sp + 1) / splits;
+  const int nacc = nbk * d;
+  for (int e = threadIdx.x; e < nacc; e += kBinThreads) acc[e] = TO(0);
+  for (int e = threadIdx.x; e < nbk; e += kBinThreads) sbacc[e] = TO(0);
+  __syncthreads();
+  for (int64_t j0 = beg + static_cast<int64_t>(wid) * RB; j0 < end; j0 += static_cast<int64_t>(kBinWaves) * RB) {
+    int32_t r[RB], o[RB];
+    TO sc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const bool ok = j0 + q < end;
+      r[q] = rows[ok ? j0 + q : j0];
+      const uint64_t z = splitmix64(seed, static_cast<uint64_t>(r[q]));
+      const int lb = static_cast<int>(bucket_of(z, t) - bk0);
+      o[q] = ok ? lb * d : fine * d;  // rows past the end go to the spare row
+      sc[q] = w ? static_cast<TO>(w[r[q]]) : (negative_of(z) ? TO(-1) : TO(1));
+      if (Sb != nullptr && ok && lane == 0) lds_add1(sbacc, lb, sc[q] * load_b<TO>(b, b_f64, r[q]));
+    }
+    for (int c0 = lane * V; c0 < d; c0 += kWave * V) {
+      TO x[RB][V];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) RowLoad<TV, TO, V>::load(A + static_cast<size_t>(r[q]) * ld + c0, x[q]);
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        int32_t a[V];
+        TO y[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          a[k] = o[q] + c0 + k;
+          y[k] = sc[q] * x[q][k];
+        }
+        lds_add<TO, V>(acc, a, y);
+      }
+    }
+  }
+  __syncthreads();
+  TO* out = SA + static_cast<size_t>(bk0) * d;
+  if (splits == 1) {
+    for (int e = threadIdx.x; e < nacc; e += kBinThreads) out[e] = acc[e];
+    if (Sb != nullptr)
+      for (int e = threadIdx.x; e < nbk; e += kBinThreads) Sb[bk0 + e] = sbacc[e];
+  } else {
+    for (int e = threadIdx.x; e < nacc; e += kBinThreads) unsafeAtomicAdd(out + e, acc[e]);
+    if (Sb != nullptr)
+      for (int e = threadIdx.x; e < nbk; e += kBinThreads) unsafeAtomicAdd(Sb + bk0 + e, sbacc[e]);
+  }
+}
+
 // ---------------------------------------------------------------- a2: atomic
 template <typename TV, typename TR, typename TO, int L>
 __global__ __launch_bounds__(kThreads) void k_sketch_csr_atomic(
@@ -828,35 +1129,120 @@ int32_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   return SKLS_OK;
 }
 
-size_t plan_bytes(int64_t n, int64_t t, int ext) {
-  Arena ar(nullptr, 0);
-  carve_plan(ar, n, t, ext);
-  return ar.used;
+namespace {
+
+constexpr size_t kBinAcc = 32768;  // LDS bytes of S A rows held by one binned block
+
+size_t round16(size_t x) { return (x + 15) / 16 * 16; }
+
+// Shape of the bucket plan for one input, variant and output precision.
+struct PlanShape {
+  int32_t variant = SKLS_SKETCH_SORTED;
+  int sh = 0;         // log2 of buckets per coarse bin
+  int C = 0;          // coarse bins; 0 selects one global counting pass (sorted only)
+  int nblk = 1;       // row chunks of the coarse passes
+  size_t entry = 4;   // bytes per plan entry (row index or CSR record)
+  int splits = 1;     // binned: blocks sharing one bin
+};
+
+size_t entry_bytes(const skls_matrix& A, int out_bytes) {
+  if (A.layout != SKLS_CSR) return sizeof(int32_t);
+  return (!A.row_ptr_64 && out_bytes == 4) ? 16 : 24;
 }
 
-BucketPlan carve_plan(Arena& ar, int64_t n, int64_t t, int ext) {
-  BucketPlan P;
-  // coarse bins of 2^sh buckets holding about 4096 rows each on average
+// Buckets per binned block: the largest power of two whose rows of S A fit
+// kBinAcc bytes (at most 4096, and no more than t needs); 0 if one row does
+// not fit.
+int64_t binned_fine(const skls_matrix& A, int64_t t, int out_bytes) {
+  const int64_t row = A.d * out_bytes;
+  if (row > static_cast<int64_t>(kBinAcc)) return 0;
+  int64_t fine = 1;
+  while (fine < 4096 && fine < t && 2 * fine * row <= static_cast<int64_t>(kBinAcc)) fine *= 2;
+  return fine;
+}
+
+bool binned_ok(const skls_matrix& A, int64_t t, int out_bytes) {
+  const int64_t fine = binned_fine(A, t, out_bytes);
+  return fine > 0 && div_up(t, fine) <= kMaxBins;
+}
+
+bool sorted_ok(const skls_matrix& A, int out_bytes) {
+  return A.layout != SKLS_CSR || A.d * out_bytes <= kAccMax;
+}
+
+int32_t pick_variant(const skls_matrix& A, int64_t t, int32_t variant, int out_bytes) {
+  if (variant != SKLS_SKETCH_AUTO) return variant;
+  if (A.layout == SKLS_CSR) {
+    // LDS-privatised accumulation when the bin rows fit in LDS
+    if (binned_ok(A, t, out_bytes)) return SKLS_SKETCH_BINNED;
+    if (A.n <= 256 * t && sorted_ok(A, out_bytes)) return SKLS_SKETCH_SORTED;
+    return SKLS_SKETCH_ATOMIC;
+  }
+  // dense rows: one wavefront per bucket sums whole rows in registers
+  if (A.n > 256 * t) return binned_ok(A, t, out_bytes) ? SKLS_SKETCH_BINNED : SKLS_SKETCH_ATOMIC;
+  return SKLS_SKETCH_SORTED;
+}
+
+PlanShape plan_shape(const skls_matrix& A, int64_t t, int32_t v, int out_bytes) {
+  PlanShape S;
+  const int64_t n = A.n;
+  S.variant = v;
+  S.entry = entry_bytes(A, out_bytes);
+  S.nblk = static_cast<int>(div_up(n > 0 ? n : 1, kPlanChunk));
+  if (v == SKLS_SKETCH_BINNED) {
+    const int64_t fine = binned_fine(A, t, out_bytes);
+    while ((int64_t(1) << S.sh) < fine) ++S.sh;
+    S.C = static_cast<int>(div_up(t, fine));
+    // spread crowded bins over several blocks: about 1024 blocks in all,
+    // each with at least 2048 rows
+    const int64_t want = div_up(1024, S.C), rows = n / (static_cast<int64_t>(S.C) * 2048);
+    int64_t sp = want < rows ? want : rows;
+    S.splits = static_cast<int>(sp < 1 ? 1 : (sp > 64 ? 64 : sp));
+    return S;
+  }
+  // bucket order: coarse bins of about 4096 rows for the fine pass
   int sh = 0;
   while (sh < 12 && (n << (sh + 1)) <= int64_t(4096) * t) ++sh;
   const int64_t C = (t + (int64_t(1) << sh) - 1) >> sh;
-  P.sh = sh;
-  P.C = C <= 4096 ? static_cast<int>(C) : 0;  // 0: counting with global atomics
-  P.nblk = static_cast<int>(div_up(n > 0 ? n : 1, kPlanChunk));
-  P.ext = ext;
-  const int64_t ncnt = P.C ? static_cast<int64_t>(P.C) * P.nblk : t;
-  P.off = ar.take<int32_t>(static_cast<size_t>(t) + 1);
-  P.perm = ar.take<int32_t>(static_cast<size_t>(n));
-  P.rank = ar.take<int32_t>(static_cast<size_t>(n));
+  S.sh = sh;
+  S.C = C <= kMaxBins ? static_cast<int>(C) : 0;
+  return S;
+}
+
+// Workspace of the plan: bin or bucket counts, scan partials, entries in
+// coarse-bin order, and (bucket order) entries by bucket and bucket offsets.
+struct BucketPlan {
+  PlanShape S;
+  int32_t* count = nullptr;  // [C * nblk + 1] (two-level) or [t + 1] (global)
+  int32_t* bsum = nullptr;
+  int32_t* rank = nullptr;   // [n] global counting only
+  void* coarse = nullptr;    // [n] entries in coarse-bin order (two-level)
+  void* fine = nullptr;      // [n] entries in bucket order (sorted)
+  int32_t* off = nullptr;    // [t + 1] bucket offsets (sorted)
+};
+
+BucketPlan carve_plan(Arena& ar, const PlanShape& S, int64_t n, int64_t t) {
+  BucketPlan P;
+  P.S = S;
+  const int64_t ncnt = S.C ? static_cast<int64_t>(S.C) * S.nblk : t;
   P.count = ar.take<int32_t>(static_cast<size_t>(ncnt) + 1);
   P.bsum = ar.take<int32_t>(static_cast<size_t>(div_up(ncnt, kScanTile)) + 1);
-  if (ext) {
-    P.pstart = ar.take<char>(static_cast<size_t>(n) * ext);
-    P.plen = ar.take<int32_t>(static_cast<size_t>(n));
-    P.cstart = ar.take<char>(static_cast<size_t>(n) * ext);
-    P.clen = ar.take<int32_t>(static_cast<size_t>(n));
+  if (S.C) {
+    P.coarse = ar.take<char>(static_cast<size_t>(n) * S.entry);
+  } else {
+    P.rank = ar.take<int32_t>(static_cast<size_t>(n));
+  }
+  if (S.variant == SKLS_SKETCH_SORTED) {
+    P.fine = ar.take<char>(static_cast<size_t>(n) * S.entry);
+    P.off = ar.take<int32_t>(static_cast<size_t>(t) + 1);
   }
   return P;
+}
+
+size_t plan_bytes(const PlanShape& S, int64_t n, int64_t t) {
+  Arena ar(nullptr, 0);
+  carve_plan(ar, S, n, t);
+  return ar.used;
 }
 
 // Exclusive scan of count[0..ncnt) into out[0..ncnt) with out[ncnt] = total.
@@ -871,26 +1257,27 @@ int32_t scan_counts(const int32_t* count, int64_t ncnt, int32_t* bsum, int32_t* 
   return SKLS_OK;
 }
 
-template <typename TR, bool EXT>
-int32_t build_plan_t(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, const TR* row_ptr, hipStream_t s) {
-  TR* cstart = static_cast<TR*>(P.cstart);
-  TR* pstart = static_cast<TR*>(P.pstart);
-  if (P.C > 0) {
-    const size_t lds = static_cast<size_t>(P.C) * sizeof(int32_t);
-    const int64_t ncnt = static_cast<int64_t>(P.C) * P.nblk;
-    hipLaunchKernelGGL(k_plan_coarse_count, dim3(P.nblk), dim3(kThreads), lds, s, n, t, seed, P.sh, P.C, P.nblk,
+template <typename R>
+int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, const RowSrc& src, hipStream_t s) {
+  const PlanShape& S = P.S;
+  if (S.C > 0) {
+    const size_t lds = static_cast<size_t>(S.C) * sizeof(int32_t);
+    const int64_t ncnt = static_cast<int64_t>(S.C) * S.nblk;
+    hipLaunchKernelGGL(k_plan_coarse_count, dim3(S.nblk), dim3(kPlanThreads), lds, s, n, t, seed, S.sh, S.C, S.nblk,
                        P.count);
     SKLS_CHECK_LAUNCH();
     // the scanned (bin, block) offsets overwrite the counts in place (each
     // scan block reads its tile before writing it)
     SKLS_TRY(scan_counts(P.count, ncnt, P.bsum, P.count, s));
-    hipLaunchKernelGGL((k_plan_coarse_scatter<TR, EXT>), dim3(P.nblk), dim3(kThreads), lds, s, n, t, seed, P.sh, P.C,
-                       P.nblk, P.count, P.rank, row_ptr, cstart, P.clen);
+    hipLaunchKernelGGL((k_plan_coarse_scatter<R>), dim3(S.nblk), dim3(kPlanThreads), lds, s, n, t, seed, S.sh, S.C,
+                       S.nblk, P.count, src, static_cast<R*>(P.coarse));
     SKLS_CHECK_LAUNCH();
-    const size_t flds = (size_t(1) << P.sh) * sizeof(int32_t);
-    hipLaunchKernelGGL((k_plan_fine<TR, EXT>), dim3(P.C), dim3(kThreads), flds, s, n, t, seed, P.sh, P.C, P.nblk,
-                       P.count, P.rank, P.perm, P.off, cstart, P.clen, pstart, P.plen);
-    SKLS_CHECK_LAUNCH();
+    if (S.variant == SKLS_SKETCH_SORTED) {
+      const size_t flds = (size_t(1) << S.sh) * sizeof(int32_t);
+      hipLaunchKernelGGL((k_plan_fine<R>), dim3(S.C), dim3(kThreads), flds, s, n, t, seed, S.sh, S.C, S.nblk, P.count,
+                         static_cast<const R*>(P.coarse), static_cast<R*>(P.fine), P.off);
+      SKLS_CHECK_LAUNCH();
+    }
     return SKLS_OK;
   }
   SKLS_TRY(launch_fill_zero(P.count, static_cast<size_t>(t) * sizeof(int32_t), s));
@@ -901,43 +1288,17 @@ int32_t build_plan_t(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, 
   }
   SKLS_TRY(scan_counts(P.count, static_cast<int64_t>(t), P.bsum, P.off, s));
   if (n > 0) {
-    hipLaunchKernelGGL((k_scatter<TR, EXT>), dim3(g), dim3(kThreads), 0, s, n, t, seed, P.off, P.rank, P.perm,
-                       row_ptr, pstart, P.plen);
+    hipLaunchKernelGGL((k_scatter<R>), dim3(g), dim3(kThreads), 0, s, n, t, seed, P.off, P.rank, src,
+                       static_cast<R*>(P.fine));
     SKLS_CHECK_LAUNCH();
   }
   return SKLS_OK;
 }
 
-int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, const void* row_ptr, hipStream_t s) {
-  if (P.ext == 8) return build_plan_t<int64_t, true>(n, t, seed, P, static_cast<const int64_t*>(row_ptr), s);
-  if (P.ext == 4) return build_plan_t<int32_t, true>(n, t, seed, P, static_cast<const int32_t*>(row_ptr), s);
-  return build_plan_t<int32_t, false>(n, t, seed, P, nullptr, s);
-}
-
-// Bytes per carried row start in the plan (0 for dense inputs).
-int plan_ext(const skls_matrix& A) {
-  if (A.layout != SKLS_CSR) return 0;
-  return A.row_ptr_64 ? 8 : 4;
-}
-
-int32_t choose_sketch_variant(const skls_matrix& A, int64_t t, int32_t variant) {
-  if (variant != SKLS_SKETCH_AUTO) return variant;
-  // One wavefront per bucket needs many buckets with modest loads.
-  if (A.n > 256 * t) return SKLS_SKETCH_ATOMIC;
-  if (A.layout == SKLS_CSR && A.d * 8 > kAccMax) return SKLS_SKETCH_ATOMIC;
-  return SKLS_SKETCH_SORTED;
-}
-
-size_t sketch_ws_bytes(const skls_matrix& A, int64_t t, int32_t variant) {
-  const int32_t v = choose_sketch_variant(A, t, variant);
-  if (v == SKLS_SKETCH_SORTED) return plan_bytes(A.n, t, plan_ext(A));
-  return 0;
-}
-
 // Wavefronts of a kBucketWaves-wave block kernel that the device holds at
 // once (occupancy from registers and LDS), cached per kernel, LDS size and
 // device.
-static int64_t resident_waves(const void* kernel, size_t lds) {
+int64_t resident_waves(const void* kernel, size_t lds) {
   static std::mutex mu;
   static std::map<std::tuple<const void*, size_t, int>, int64_t> cache;
   int dev = 0;
@@ -955,13 +1316,138 @@ static int64_t resident_waves(const void* kernel, size_t lds) {
   return r;
 }
 
+int buckets_per_wave(int64_t t, int64_t resident) {
+  int64_t b = div_up(t, resident > 0 ? resident : 1);
+  return static_cast<int>(b < 1 ? 1 : (b > 63 ? 63 : b));
+}
+
+int32_t allow_lds(const void* kernel, size_t lds) {
+  if (lds > 65536) SKLS_TRY_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    static_cast<int>(lds)));
+  return SKLS_OK;
+}
+
+// Apply of the SORTED and BINNED variants once the plan is built.
+template <typename TO>
+int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, int b_f64, uint32_t t, uint64_t seed,
+                      const float* w, TO* SA, TO* Sb, hipStream_t s) {
+  const PlanShape& S = P.S;
+  const int d = static_cast<int>(A.d);
+  const int64_t n = A.n;
+  return with_value(A.dtype, [&](auto tv) -> int32_t {
+    using TV = decltype(tv);
+    if (A.layout == SKLS_DENSE) {
+      constexpr int VV = sizeof(TV) == 8 ? 2 : (sizeof(TV) == 4 ? 4 : 8);
+      const bool vec = vec_ok<TV>(A.val, A.ld, A.d, VV);
+      if (S.variant == SKLS_SKETCH_BINNED) {
+        // the bin's rows of S A plus one spare row
+        const int acc_bytes = static_cast<int>(round16(((size_t(1) << S.sh) + 1) * d * sizeof(TO)));
+        const size_t lds = acc_bytes + round16((size_t(1) << S.sh) * sizeof(TO));
+        const unsigned grid = static_cast<unsigned>(S.C) * S.splits;
+        const int32_t* rows = static_cast<const int32_t*>(P.coarse);
+        if (vec) {
+          SKLS_TRY(allow_lds(reinterpret_cast<const void*>(&k_sketch_dense_binned<TV, TO, VV>), lds));
+          hipLaunchKernelGGL((k_sketch_dense_binned<TV, TO, VV>), dim3(grid), dim3(kBinThreads), lds, s, d, A.ld, t,
+                             S.sh, S.C, S.nblk, S.splits, n, seed, static_cast<const TV*>(A.val), b, b_f64, w,
+                             P.count, rows, SA, Sb, acc_bytes);
+        } else {
+          SKLS_TRY(allow_lds(reinterpret_cast<const void*>(&k_sketch_dense_binned<TV, TO, 1>), lds));
+          hipLaunchKernelGGL((k_sketch_dense_binned<TV, TO, 1>), dim3(grid), dim3(kBinThreads), lds, s, d, A.ld, t,
+                             S.sh, S.C, S.nblk, S.splits, n, seed, static_cast<const TV*>(A.val), b, b_f64, w,
+                             P.count, rows, SA, Sb, acc_bytes);
+        }
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      }
+      const size_t lds = kBucketWaves * sizeof(DenseLds<TO>);
+      const void* kern = vec ? reinterpret_cast<const void*>(&k_sketch_dense_sorted<TV, TO, VV>)
+                             : reinterpret_cast<const void*>(&k_sketch_dense_sorted<TV, TO, 1>);
+      const int bpw = buckets_per_wave(t, resident_waves(kern, lds));
+      const unsigned grid = static_cast<unsigned>(div_up(div_up(t, bpw), kBucketWaves));
+      const int32_t* perm = static_cast<const int32_t*>(P.fine);
+      if (vec) {
+        hipLaunchKernelGGL((k_sketch_dense_sorted<TV, TO, VV>), dim3(grid), dim3(kThreads), lds, s, d, A.ld, t, bpw,
+                           seed, static_cast<const TV*>(A.val), b, b_f64, w, P.off, perm, SA, Sb);
+      } else {
+        hipLaunchKernelGGL((k_sketch_dense_sorted<TV, TO, 1>), dim3(grid), dim3(kThreads), lds, s, d, A.ld, t, bpw,
+                           seed, static_cast<const TV*>(A.val), b, b_f64, w, P.off, perm, SA, Sb);
+      }
+      SKLS_CHECK_LAUNCH();
+      return SKLS_OK;
+    }
+    return with_rowptr(A, [&](auto tr) -> int32_t {
+      using TR = decltype(tr);
+      using Rec = CsrRec<TR, TO>;
+      const int quad_ok = (reinterpret_cast<uintptr_t>(A.col_idx) % 16 == 0) &&
+                          (reinterpret_cast<uintptr_t>(A.val) % (4 * sizeof(TV)) == 0);
+      if (S.variant == SKLS_SKETCH_BINNED) {
+        // the bin's rows of S A plus one spare row (see gather_burst)
+        const int acc_bytes = static_cast<int>(round16(((size_t(1) << S.sh) + 1) * d * sizeof(TO)));
+        const int sb_bytes = static_cast<int>(round16((size_t(1) << S.sh) * sizeof(TO)));
+        const size_t lds = acc_bytes + sb_bytes + kBinWaves * sizeof(GatherLds<TR, TO>);
+        const void* kern = reinterpret_cast<const void*>(&k_sketch_csr_binned<TV, TR, TO>);
+        SKLS_TRY(allow_lds(kern, lds));
+        hipLaunchKernelGGL((k_sketch_csr_binned<TV, TR, TO>), dim3(static_cast<unsigned>(S.C) * S.splits),
+                           dim3(kBinThreads), lds, s, d, t, S.sh, S.C, S.nblk, S.splits, n, seed, A.col_idx,
+                           static_cast<const TV*>(A.val), w, P.count, static_cast<const Rec*>(P.coarse), SA, Sb,
+                           acc_bytes, sb_bytes, quad_ok);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      }
+      // per wave: sort and gather tables, the bucket's row of S A and a spare row
+      const size_t row_bytes = static_cast<size_t>(d) * sizeof(TO);
+      const int per_wave = static_cast<int>(round16(sizeof(CsrLds<TR, TO>) + 2 * row_bytes));
+      const size_t lds = static_cast<size_t>(per_wave) * kBucketWaves;
+      const void* kern = reinterpret_cast<const void*>(&k_sketch_csr_sorted<TV, TR, TO>);
+      SKLS_TRY(allow_lds(kern, lds));
+      // one round of resident wavefronts, each walking consecutive buckets
+      const int bpw = buckets_per_wave(t, resident_waves(kern, lds));
+      const unsigned grid = static_cast<unsigned>(div_up(div_up(t, bpw), kBucketWaves));
+      hipLaunchKernelGGL((k_sketch_csr_sorted<TV, TR, TO>), dim3(grid), dim3(kThreads), lds, s, d, t, bpw, seed,
+                         A.col_idx, static_cast<const TV*>(A.val), w, P.off, static_cast<const Rec*>(P.fine), SA,
+                         Sb, per_wave, quad_ok);
+      SKLS_CHECK_LAUNCH();
+      return SKLS_OK;
+    });
+  });
+}
+
+int out_bytes_of(int32_t out_dtype) { return out_dtype == SKLS_F64 ? 8 : 4; }
+
+}  // namespace
+
+int32_t choose_sketch_variant(const skls_matrix& A, int64_t t, int32_t variant, int32_t out_dtype) {
+  return pick_variant(A, t, variant, out_bytes_of(out_dtype));
+}
+
+// Workspace for either output precision (the query does not name one).
+size_t sketch_ws_bytes(const skls_matrix& A, int64_t t, int32_t variant) {
+  size_t need = 0;
+  for (int ob : {4, 8}) {
+    const int32_t v = pick_variant(A, t, variant, ob);
+    if (v != SKLS_SKETCH_SORTED && v != SKLS_SKETCH_BINNED) continue;
+    const size_t b = plan_bytes(plan_shape(A, t, v, ob), A.n, t);
+    need = b > need ? b : need;
+  }
+  return need;
+}
+
 int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
                    const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
                    size_t ws_bytes, hipStream_t s) {
-  const int32_t v = choose_sketch_variant(A, t, variant);
-  if (v != SKLS_SKETCH_ATOMIC && v != SKLS_SKETCH_SORTED) {
+  const int ob = out_bytes_of(out_dtype);
+  const int32_t v = pick_variant(A, t, variant, ob);
+  if (v != SKLS_SKETCH_ATOMIC && v != SKLS_SKETCH_SORTED && v != SKLS_SKETCH_BINNED) {
     set_error("unknown sketch variant %d", variant);
     return SKLS_ERR_ARG;
+  }
+  if (v == SKLS_SKETCH_BINNED && !binned_ok(A, t, ob)) {
+    set_error("binned sketch needs d * sizeof(out) <= %zu bytes and t / buckets-per-bin <= %d", kBinAcc, kMaxBins);
+    return SKLS_ERR_SHAPE;
+  }
+  if (v == SKLS_SKETCH_SORTED && !sorted_ok(A, ob)) {
+    set_error("sorted CSR sketch supports d * sizeof(out) <= %d bytes; use the binned or atomic variant", kAccMax);
+    return SKLS_ERR_SHAPE;
   }
   const int b_f64 = (b_dtype == SKLS_F64) ? 1 : 0;
   const uint32_t tt = static_cast<uint32_t>(t);
@@ -1001,68 +1487,32 @@ int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t
       });
     });
   }
-  // SORTED
+  const PlanShape S = plan_shape(A, t, v, ob);
   Arena ar(ws, ws_bytes);
-  BucketPlan P = carve_plan(ar, n, t, plan_ext(A));
+  const BucketPlan P = carve_plan(ar, S, n, t);
   if (!ws || !ar.fits()) {
     set_error("sketch workspace too small: need %zu bytes, have %zu", ar.used, ws_bytes);
     return SKLS_ERR_WORKSPACE;
   }
-  {
-    PhaseTimer pt("sketch_plan", s);
-    SKLS_TRY(build_plan(n, tt, seed, P, A.layout == SKLS_CSR ? A.row_ptr : nullptr, s));
-  }
-  PhaseTimer pt("sketch_apply", s);
+  const RowSrc src{A.layout == SKLS_CSR ? A.row_ptr : nullptr, b, b_f64, w};
   return with_out(out_dtype, [&](auto to) -> int32_t {
     using TO = decltype(to);
-    return with_value(A.dtype, [&](auto tv) -> int32_t {
-      using TV = decltype(tv);
-      if (A.layout == SKLS_DENSE) {
-        const size_t lds = kBucketWaves * sizeof(DenseLds<TO>);
-        constexpr int VV = sizeof(TV) == 8 ? 2 : (sizeof(TV) == 4 ? 4 : 8);
-        const bool vec = vec_ok<TV>(A.val, A.ld, A.d, VV);
-        const void* kern = vec ? reinterpret_cast<const void*>(&k_sketch_dense_sorted<TV, TO, VV>)
-                               : reinterpret_cast<const void*>(&k_sketch_dense_sorted<TV, TO, 1>);
-        int bpw = static_cast<int>(div_up(t, resident_waves(kern, lds)));
-        bpw = bpw < 1 ? 1 : (bpw > 63 ? 63 : bpw);
-        const unsigned dgrid = static_cast<unsigned>(div_up(div_up(t, bpw), kBucketWaves));
-        if (vec) {
-          hipLaunchKernelGGL((k_sketch_dense_sorted<TV, TO, VV>), dim3(dgrid), dim3(kThreads), lds, s, d, A.ld, tt,
-                             bpw, seed, static_cast<const TV*>(A.val), b, b_f64, w, P.off, P.perm,
-                             static_cast<TO*>(SA), static_cast<TO*>(Sb));
-        } else {
-          hipLaunchKernelGGL((k_sketch_dense_sorted<TV, TO, 1>), dim3(dgrid), dim3(kThreads), lds, s, d, A.ld, tt,
-                             bpw, seed, static_cast<const TV*>(A.val), b, b_f64, w, P.off, P.perm,
-                             static_cast<TO*>(SA), static_cast<TO*>(Sb));
-        }
-        SKLS_CHECK_LAUNCH();
-        return SKLS_OK;
+    {
+      PhaseTimer pt("sketch_plan", s);
+      if (A.layout == SKLS_CSR) {
+        const int32_t st = A.row_ptr_64 ? build_plan<CsrRec<int64_t, TO>>(n, tt, seed, P, src, s)
+                                        : build_plan<CsrRec<int32_t, TO>>(n, tt, seed, P, src, s);
+        SKLS_TRY(st);
+      } else {
+        SKLS_TRY(build_plan<int32_t>(n, tt, seed, P, src, s));
       }
-      const size_t row_bytes = static_cast<size_t>(d) * sizeof(TO);
-      if (row_bytes > static_cast<size_t>(kAccMax)) {
-        set_error("sorted CSR sketch supports d * sizeof(out) <= %d bytes; use the atomic variant", kAccMax);
-        return SKLS_ERR_SHAPE;
+      if (S.splits > 1) {
+        SKLS_TRY(launch_fill_zero(SA, static_cast<size_t>(t) * A.d * sizeof(TO), s));
+        if (Sb) SKLS_TRY(launch_fill_zero(Sb, static_cast<size_t>(t) * sizeof(TO), s));
       }
-      return with_rowptr(A, [&](auto tr) -> int32_t {
-        using TR = decltype(tr);
-        const int per_wave = static_cast<int>((sizeof(CsrLds<TR, TO>) + row_bytes + 15) / 16 * 16);
-        // one round of resident wavefronts, each walking consecutive buckets
-        const size_t lds = static_cast<size_t>(per_wave) * kBucketWaves;
-        int cbpw = static_cast<int>(div_up(t, resident_waves(
-                                                  reinterpret_cast<const void*>(&k_sketch_csr_sorted<TV, TR, TO>), lds)));
-        cbpw = cbpw < 1 ? 1 : (cbpw > 63 ? 63 : cbpw);
-        const unsigned cgrid = static_cast<unsigned>(div_up(div_up(t, cbpw), kBucketWaves));
-        const int quad_ok = (reinterpret_cast<uintptr_t>(A.col_idx) % 16 == 0) &&
-                            (reinterpret_cast<uintptr_t>(A.val) % (4 * sizeof(TV)) == 0);
-        hipLaunchKernelGGL((k_sketch_csr_sorted<TV, TR, TO>), dim3(cgrid), dim3(kThreads), lds, s, d, tt, cbpw,
-                           seed, A.col_idx,
-                           static_cast<const TV*>(A.val), b, b_f64, w, P.off, P.perm,
-                           static_cast<const TR*>(P.pstart), P.plen, static_cast<TO*>(SA), static_cast<TO*>(Sb),
-                           per_wave, quad_ok);
-        SKLS_CHECK_LAUNCH();
-        return SKLS_OK;
-      });
-    });
+    }
+    PhaseTimer pt("sketch_apply", s);
+    return apply_planned<TO>(A, P, b, b_f64, tt, seed, w, static_cast<TO*>(SA), static_cast<TO*>(Sb), s);
   });
 }
 

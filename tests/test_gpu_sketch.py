@@ -38,7 +38,7 @@ def test_hash_bit_exact(sk, n, t, seed, start):
     assert np.array_equal(s.cpu().numpy(), s_o)
 
 
-VARIANTS = ["atomic", "sorted"]
+VARIANTS = ["atomic", "sorted", "binned"]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -144,6 +144,62 @@ def test_edge_cases(sk, variant):
     assert np.array_equal(SA.cpu().numpy().astype(np.float64), O.sketch_dense(A, 11, 7))
 
 
+def _int_csr(g, n, d, lens):
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    cols = np.concatenate([np.sort(g.choice(d, size=k, replace=False)) for k in lens]).astype(np.int32)
+    val = g.integers(-8, 9, size=row_ptr[-1]).astype(np.float32)
+    val[val == 0] = 1
+    return W.CSR(n=n, d=d, row_ptr=row_ptr, col_idx=cols, val=val)
+
+
+def _shifted_csr(A: W.CSR, row64: bool):
+    """The same matrix with column and value arrays starting 4 bytes into
+    their allocations (no 16-byte groups of nonzeros)."""
+    import paper_1207_6365_amd as sk
+
+    rp = A.row_ptr if row64 else A.row_ptr32()
+    col = torch.zeros(A.col_idx.size + 1, dtype=torch.int32, device=dev())
+    val = torch.zeros(A.val.size + 1, dtype=torch.float32, device=dev())
+    col[1:] = up(A.col_idx.astype(np.int32))
+    val[1:] = up(A.val)
+    return sk.Csr(A.n, A.d, up(rp), col[1:], val[1:])
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("shift", [False, True])
+def test_csr_gather_paths_bit_exact(sk, variant, shift):
+    """Integer-valued CSR through every gather path: rows whose lengths are
+    multiples of four (grouped loads when aligned), long rows that overflow
+    the position table (binary search), crowded buckets (binned: several
+    blocks per bin; sorted: buckets past the in-LDS sort) and an empty
+    input."""
+    g = np.random.default_rng(11)
+    n, d = 6000, 512
+    lens = 4 * g.integers(0, 101, size=n)  # 0..400 nonzeros, multiples of 4
+    lens[::13] = 0
+    A = _int_csr(g, n, d, lens)
+    for row64 in (False, True):
+        Ag = _shifted_csr(A, row64) if shift else up_csr(A, row64=row64)
+        for t, seed in ((501, 3), (3, 8)):
+            SA = sk.sketch(Ag, t, seed, variant=variant)
+            ref = O.sketch_csr(A.n, A.d, A.row_ptr, A.col_idx, A.val, seed, t)
+            assert np.array_equal(SA.cpu().numpy().astype(np.float64), ref), (row64, t)
+    # ragged lengths, many rows per bucket, b folded into the plan
+    lens = g.integers(0, 23, size=200000)
+    B = _int_csr(g, 200000, 40, lens)
+    b = g.integers(-5, 6, size=200000).astype(np.float64)
+    Bg = _shifted_csr(B, False) if shift else up_csr(B)
+    SA, Sb = sk.sketch(Bg, 5, 21, b=up(b), variant=variant)
+    assert np.array_equal(SA.cpu().numpy().astype(np.float64),
+                          O.sketch_csr(B.n, B.d, B.row_ptr, B.col_idx, B.val, 21, 5))
+    assert np.array_equal(Sb.cpu().numpy().astype(np.float64), O.sketch_dense(b, 21, 5))
+    # empty CSR: S A is all zeros
+    E = W.CSR(n=0, d=16, row_ptr=np.zeros(1, np.int64), col_idx=np.zeros(0, np.int32),
+              val=np.zeros(0, np.float32))
+    SA = sk.sketch(up_csr(E), 40, 1, variant=variant)
+    assert SA.shape == (40, 16) and torch.count_nonzero(SA).item() == 0
+
+
 def test_sorted_variant_is_deterministic(sk):
     A, b = W.sketch_csr(n=200000, d=64, k=8)
     Ag = up_csr(A)
@@ -173,10 +229,11 @@ def test_full_size_integer_csr_bit_exact(sk, variant):
     assert np.array_equal(Sb.cpu().numpy().astype(np.float64), O.sketch_dense(b.astype(np.float64), seed, t))
 
 
-def test_full_size_f32_csr(sk):
+@pytest.mark.parametrize("variant", ["binned", "sorted"])
+def test_full_size_f32_csr(sk, variant):
     A, b = W.sketch_csr()
     seed, t = W.sketch_seed(0), 65536
-    SA = sk.sketch(up_csr(A), t, seed).cpu().numpy()
+    SA = sk.sketch(up_csr(A), t, seed, variant=variant).cpu().numpy()
     op = O.MatrixOp(A)
     ref = O.sketch_matrix(op, seed, t)
     assert np.linalg.norm(SA - ref) <= 1e-5 * np.linalg.norm(ref)
