@@ -94,26 +94,38 @@ template <typename R>
 struct Entry;
 template <>
 struct Entry<int32_t> {
+  static constexpr bool kSb = false;
+  using TO = float;
   __device__ __forceinline__ static int32_t make(const RowSrc&, int64_t i, uint64_t) {
     return static_cast<int32_t>(i);
   }
+  __device__ __forceinline__ static int32_t extent(const RowSrc&, int64_t i) { return static_cast<int32_t>(i); }
+  __device__ __forceinline__ static void set_sb(int32_t&, float) {}
   __device__ __forceinline__ static int32_t row(const int32_t& e) { return e; }
 };
-template <typename TR, typename TO>
-struct Entry<CsrRec<TR, TO>> {
-  __device__ __forceinline__ static CsrRec<TR, TO> make(const RowSrc& src, int64_t i, uint64_t z) {
+template <typename TR, typename TO_>
+struct Entry<CsrRec<TR, TO_>> {
+  static constexpr bool kSb = true;
+  using TO = TO_;
+  // the record without its share of S b
+  __device__ __forceinline__ static CsrRec<TR, TO> extent(const RowSrc& src, int64_t i) {
     const TR* rp = static_cast<const TR*>(src.row_ptr);
     CsrRec<TR, TO> e;
     e.start = rp[i];
     e.len = static_cast<int32_t>(rp[i + 1] - e.start);
     e.row = static_cast<int32_t>(i);
     e.sbv = TO(0);
+    return e;
+  }
+  __device__ __forceinline__ static CsrRec<TR, TO> make(const RowSrc& src, int64_t i, uint64_t z) {
+    CsrRec<TR, TO> e = extent(src, i);
     if (src.b != nullptr) {
       const TO sc = src.w ? static_cast<TO>(src.w[i]) : (negative_of(z) ? TO(-1) : TO(1));
       e.sbv = sc * load_b<TO>(src.b, src.b_f64, i);
     }
     return e;
   }
+  __device__ __forceinline__ static void set_sb(CsrRec<TR, TO>& e, TO v) { e.sbv = v; }
   __device__ __forceinline__ static int32_t row(const CsrRec<TR, TO>& e) { return e.row; }
 };
 
@@ -247,15 +259,51 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_scatter(int64_t n,
   for (int c = threadIdx.x; c < C; c += kPlanThreads) pos[c] = coff[static_cast<size_t>(c) * nblk + blockIdx.x];
   __syncthreads();
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kPlanChunk;
-#pragma unroll 4
-  for (int k = 0; k < kPlanItems; ++k) {
-    const int64_t i = r0 + static_cast<int64_t>(k) * kPlanThreads + threadIdx.x;
-    if (i < n) {
-      const uint64_t z = splitmix64(seed, static_cast<uint64_t>(i));
-      const R e = Entry<R>::make(src, i, z);
-      const int32_t slot = atomicAdd(&pos[bucket_of(z, t) >> sh], 1);
-      coarse[slot] = e;
+  if (r0 >= n) return;
+  // eight rows per thread at a time: their loads (clamped to the last row so
+  // none sits behind a branch) are in flight together, then the slots, then
+  // the stores
+  // (the optional inputs b and w are read in batches of their own under
+  // uniform branches)
+  constexpr int kU = 8;
+  using TO = typename Entry<R>::TO;
+  for (int k0 = 0; k0 < kPlanItems; k0 += kU) {
+    R e[kU];
+    int32_t bin[kU];
+    bool ok[kU];
+    int64_t ii[kU];
+    uint64_t z[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = r0 + static_cast<int64_t>(k0 + u) * kPlanThreads + threadIdx.x;
+      ok[u] = i < n;
+      ii[u] = ok[u] ? i : n - 1;
+      z[u] = splitmix64(seed, static_cast<uint64_t>(ii[u]));
+      e[u] = Entry<R>::extent(src, ii[u]);
+      bin[u] = static_cast<int32_t>(bucket_of(z[u], t) >> sh);
     }
+    if (Entry<R>::kSb && src.b != nullptr) {
+      TO bv[kU], sc[kU];
+      if (src.b_f64) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) bv[u] = static_cast<TO>(static_cast<const double*>(src.b)[ii[u]]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) bv[u] = static_cast<TO>(static_cast<const float*>(src.b)[ii[u]]);
+      }
+      if (src.w != nullptr) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) sc[u] = static_cast<TO>(src.w[ii[u]]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) sc[u] = negative_of(z[u]) ? TO(-1) : TO(1);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) Entry<R>::set_sb(e[u], sc[u] * bv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (ok[u]) coarse[atomicAdd(&pos[bin[u]], 1)] = e[u];
   }
 }
 
@@ -457,7 +505,7 @@ __device__ __forceinline__ int row_at(const GatherLds<TR, TO>& G, int pp) {
 // unconditional and in flight together, and add nothing.
 template <typename TV, typename TR, typename TO, bool TABLE, int E>
 __device__ __forceinline__ void gather_burst(const GatherLds<TR, TO>& G, const int32_t* __restrict__ col,
-                                             const TV* __restrict__ val, TO* acc, int trash, int p0, int total,
+                                             const TV* __restrict__ val, TO* acc, int p0, int total,
                                              int lane) {
   constexpr int K = E == 4 ? kBurstQ : kBurst;
   int pp[K], q[K];
@@ -509,11 +557,11 @@ struct RowPair {
   int32_t off[2];
 };
 
-// Reduce the chunk's rows into acc; `trash` is the offset of a spare row of acc.
+// Reduce the chunk's rows into acc.
 template <typename TV, typename TR, typename TO>
 __device__ __forceinline__ void gather_chunk(GatherLds<TR, TO>& G, const RowPair<TR, TO>& R, int quad_ok,
                                              const int32_t* __restrict__ col, const TV* __restrict__ val, TO* acc,
-                                             int trash, int lane) {
+                                             int lane) {
   const bool quad = quad_ok && __all((((static_cast<int64_t>(R.st[0]) | R.len[0]) & 3) == 0) &&
                                      (((static_cast<int64_t>(R.st[1]) | R.len[1]) & 3) == 0));
   const int32_t u0 = quad ? (R.len[0] >> 2) : R.len[0];
@@ -545,17 +593,17 @@ __device__ __forceinline__ void gather_chunk(GatherLds<TR, TO>& G, const RowPair
   if (quad) {
     if (table) {
       for (int p0 = 0; p0 < total; p0 += kWave * kBurstQ)
-        gather_burst<TV, TR, TO, true, 4>(G, col, val, acc, trash, p0, total, lane);
+        gather_burst<TV, TR, TO, true, 4>(G, col, val, acc, p0, total, lane);
     } else {
       for (int p0 = 0; p0 < total; p0 += kWave * kBurstQ)
-        gather_burst<TV, TR, TO, false, 4>(G, col, val, acc, trash, p0, total, lane);
+        gather_burst<TV, TR, TO, false, 4>(G, col, val, acc, p0, total, lane);
     }
   } else if (table) {
     for (int p0 = 0; p0 < total; p0 += kWave * kBurst)
-      gather_burst<TV, TR, TO, true, 1>(G, col, val, acc, trash, p0, total, lane);
+      gather_burst<TV, TR, TO, true, 1>(G, col, val, acc, p0, total, lane);
   } else {
     for (int p0 = 0; p0 < total; p0 += kWave * kBurst)
-      gather_burst<TV, TR, TO, false, 1>(G, col, val, acc, trash, p0, total, lane);
+      gather_burst<TV, TR, TO, false, 1>(G, col, val, acc, p0, total, lane);
   }
   wave_sync();
 }
@@ -637,7 +685,7 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_csr_binned(
     CsrRec<TR, TO> nxt[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) nxt[h] = rec_at(j0 + kStep + h * kWave + lane);
-    gather_chunk<TV, TR, TO>(G, R, quad_ok, col, val, acc, fine * d, lane);
+    gather_chunk<TV, TR, TO>(G, R, quad_ok, col, val, acc, lane);
     cur[0] = nxt[0];
     cur[1] = nxt[1];
   }
@@ -773,7 +821,7 @@ __global__ __launch_bounds__(kThreads) void k_sketch_csr_sorted(
           }
         }
       }
-      gather_chunk<TV, TR, TO>(L.g, R, quad_ok, col, val, acc, d, lane);
+      gather_chunk<TV, TR, TO>(L.g, R, quad_ok, col, val, acc, lane);
     }
     sb = wave_sum(sb);
     TO* out = SA + static_cast<size_t>(bkt) * d;
@@ -973,6 +1021,7 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
   __syncthreads();
   for (int64_t j0 = beg + static_cast<int64_t>(wid) * RB; j0 < end; j0 += static_cast<int64_t>(kBinWaves) * RB) {
     int32_t r[RB], o[RB];
+    bool okq[RB];
     TO sc[RB];
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
@@ -980,7 +1029,8 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
       r[q] = rows[ok ? j0 + q : j0];
       const uint64_t z = splitmix64(seed, static_cast<uint64_t>(r[q]));
       const int lb = static_cast<int>(bucket_of(z, t) - bk0);
-      o[q] = ok ? lb * d : fine * d;  // rows past the end go to the spare row
+      o[q] = lb * d;
+      okq[q] = ok;
       sc[q] = w ? static_cast<TO>(w[r[q]]) : (negative_of(z) ? TO(-1) : TO(1));
       if (Sb != nullptr && ok && lane == 0) lds_add1(sbacc, lb, sc[q] * load_b<TO>(b, b_f64, r[q]));
     }
@@ -997,7 +1047,7 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
           a[k] = o[q] + c0 + k;
           y[k] = sc[q] * x[q][k];
         }
-        lds_add<TO, V>(acc, a, y);
+        lds_add<TO, V>(acc, a, y, okq[q] ? 0xffffffffu : 0u);
       }
     }
   }
@@ -1155,9 +1205,18 @@ size_t entry_bytes(const skls_matrix& A, int out_bytes) {
 // not fit.
 int64_t binned_fine(const skls_matrix& A, int64_t t, int out_bytes) {
   const int64_t row = A.d * out_bytes;
-  if (row > static_cast<int64_t>(kBinAcc)) return 0;
+  // LDS left for the rows of S A next to the per-wave gather tables (CSR)
+  // and the bin's share of S b, within the 160 KiB of a compute unit
+  int64_t budget = static_cast<int64_t>(kBinAcc);
+  if (A.layout == SKLS_CSR) {
+    const int64_t ref = (A.row_ptr_64 && out_bytes == 8) ? 32 : 16;
+    const int64_t tables = kBinWaves * (kChunkRows * (ref + 4) + kPosCap);
+    const int64_t left = 160 * 1024 - tables - 4096 * out_bytes;
+    budget = left < budget ? left : budget;
+  }
+  if (row > budget) return 0;
   int64_t fine = 1;
-  while (fine < 4096 && fine < t && 2 * fine * row <= static_cast<int64_t>(kBinAcc)) fine *= 2;
+  while (fine < 4096 && fine < t && 2 * fine * row <= budget) fine *= 2;
   return fine;
 }
 
@@ -1340,8 +1399,7 @@ int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, 
       constexpr int VV = sizeof(TV) == 8 ? 2 : (sizeof(TV) == 4 ? 4 : 8);
       const bool vec = vec_ok<TV>(A.val, A.ld, A.d, VV);
       if (S.variant == SKLS_SKETCH_BINNED) {
-        // the bin's rows of S A plus one spare row
-        const int acc_bytes = static_cast<int>(round16(((size_t(1) << S.sh) + 1) * d * sizeof(TO)));
+        const int acc_bytes = static_cast<int>(round16((size_t(1) << S.sh) * d * sizeof(TO)));
         const size_t lds = acc_bytes + round16((size_t(1) << S.sh) * sizeof(TO));
         const unsigned grid = static_cast<unsigned>(S.C) * S.splits;
         const int32_t* rows = static_cast<const int32_t*>(P.coarse);
@@ -1381,8 +1439,7 @@ int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, 
       const int quad_ok = (reinterpret_cast<uintptr_t>(A.col_idx) % 16 == 0) &&
                           (reinterpret_cast<uintptr_t>(A.val) % (4 * sizeof(TV)) == 0);
       if (S.variant == SKLS_SKETCH_BINNED) {
-        // the bin's rows of S A plus one spare row (see gather_burst)
-        const int acc_bytes = static_cast<int>(round16(((size_t(1) << S.sh) + 1) * d * sizeof(TO)));
+        const int acc_bytes = static_cast<int>(round16((size_t(1) << S.sh) * d * sizeof(TO)));
         const int sb_bytes = static_cast<int>(round16((size_t(1) << S.sh) * sizeof(TO)));
         const size_t lds = acc_bytes + sb_bytes + kBinWaves * sizeof(GatherLds<TR, TO>);
         const void* kern = reinterpret_cast<const void*>(&k_sketch_csr_binned<TV, TR, TO>);
@@ -1394,9 +1451,9 @@ int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, 
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
       }
-      // per wave: sort and gather tables, the bucket's row of S A and a spare row
+      // per wave: sort and gather tables and the bucket's row of S A
       const size_t row_bytes = static_cast<size_t>(d) * sizeof(TO);
-      const int per_wave = static_cast<int>(round16(sizeof(CsrLds<TR, TO>) + 2 * row_bytes));
+      const int per_wave = static_cast<int>(round16(sizeof(CsrLds<TR, TO>) + row_bytes));
       const size_t lds = static_cast<size_t>(per_wave) * kBucketWaves;
       const void* kern = reinterpret_cast<const void*>(&k_sketch_csr_sorted<TV, TR, TO>);
       SKLS_TRY(allow_lds(kern, lds));
