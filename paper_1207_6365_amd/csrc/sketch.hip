@@ -351,6 +351,172 @@ __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, u
   }
 }
 
+// ---------------------------------------------------------------- one-pass local plan
+// Rows grouped by coarse bin within fixed chunks of kPlanChunk rows, in one
+// kernel: each block counts its chunk's rows per bin in LDS, scans the counts,
+// ranks every row within its bin (LDS atomics) and writes the chunk's plan
+// entries in bin order to the chunk's own slice of the output, so all global
+// writes are coalesced.  The per-chunk bin offsets go to offT[(C + 1) x nseg]
+// (row c holds bin c's offset in every chunk; row C holds the chunk sizes):
+// bin c of chunk q is out[q * kPlanChunk + offT[c][q] .. + offT[c + 1][q]).
+template <typename R>
+__global__ __launch_bounds__(kPlanThreads) void k_plan_local(int64_t n, uint32_t t, uint64_t seed, int sh, int C,
+                                                             RowSrc src, R* __restrict__ out,
+                                                             int32_t* __restrict__ offT, int nseg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint16_t* bin = reinterpret_cast<uint16_t*>(smem);                   // [kPlanChunk]
+  uint16_t* perm = bin + kPlanChunk;                                   // [kPlanChunk]
+  int32_t* cnt = reinterpret_cast<int32_t*>(perm + kPlanChunk);        // [C + 1]
+  __shared__ int32_t wsum[kPlanThreads / kWave];
+  const int q = blockIdx.x;
+  const int64_t r0 = static_cast<int64_t>(q) * kPlanChunk;
+  const int m = static_cast<int>(n - r0 < kPlanChunk ? (n - r0 > 0 ? n - r0 : 0) : kPlanChunk);
+  for (int c = threadIdx.x; c <= C; c += kPlanThreads) cnt[c] = 0;
+  __syncthreads();
+  for (int p = threadIdx.x; p < m; p += kPlanThreads) {
+    const int b = static_cast<int>(bucket_of(splitmix64(seed, static_cast<uint64_t>(r0 + p)), t) >> sh);
+    bin[p] = static_cast<uint16_t>(b);
+    atomicAdd(&cnt[b], 1);
+  }
+  __syncthreads();
+  // exclusive scan of cnt[0..C): each thread owns a run of counters
+  const int per = (C + kPlanThreads - 1) / kPlanThreads;
+  const int c0 = threadIdx.x * per;
+  int32_t run = 0;
+  for (int k = 0; k < per; ++k)
+    if (c0 + k < C) run += cnt[c0 + k];
+  int32_t tot;
+  int32_t pre = block_exclusive_scan(run, wsum, &tot);
+  for (int k = 0; k < per; ++k)
+    if (c0 + k < C) {
+      const int32_t v = cnt[c0 + k];
+      cnt[c0 + k] = pre;
+      pre += v;
+    }
+  if (threadIdx.x == 0) cnt[C] = m;
+  __syncthreads();
+  for (int c = threadIdx.x; c <= C; c += kPlanThreads) offT[static_cast<size_t>(c) * nseg + q] = cnt[c];
+  __syncthreads();
+  for (int p = threadIdx.x; p < m; p += kPlanThreads) perm[atomicAdd(&cnt[bin[p]], 1)] = static_cast<uint16_t>(p);
+  __syncthreads();
+  // entries in bin order: eight per thread at a time, loads clamped to the
+  // chunk's last row so that all of them are in flight together
+  using TO = typename Entry<R>::TO;
+  constexpr int kU = 8;
+  for (int s0 = 0; s0 < m; s0 += kU * kPlanThreads) {
+    R e[kU];
+    int64_t ii[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int sidx = s0 + u * kPlanThreads + threadIdx.x;
+      ii[u] = r0 + perm[sidx < m ? sidx : m - 1];
+      e[u] = Entry<R>::extent(src, ii[u]);
+    }
+    if (Entry<R>::kSb && src.b != nullptr) {
+      TO bv[kU], sc[kU];
+      if (src.b_f64) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) bv[u] = static_cast<TO>(static_cast<const double*>(src.b)[ii[u]]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) bv[u] = static_cast<TO>(static_cast<const float*>(src.b)[ii[u]]);
+      }
+      if (src.w != nullptr) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) sc[u] = static_cast<TO>(src.w[ii[u]]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          sc[u] = negative_of(splitmix64(seed, static_cast<uint64_t>(ii[u]))) ? TO(-1) : TO(1);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) Entry<R>::set_sb(e[u], sc[u] * bv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int sidx = s0 + u * kPlanThreads + threadIdx.x;
+      if (sidx < m) out[r0 + sidx] = e[u];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- bin segments
+// Where a coarse bin's plan entries are: one contiguous range (two-level
+// plan) or one range per chunk (one-pass local plan).
+struct BinSegs {
+  const int32_t* off;  // coarse offsets [C * nblk + 1] or local offsets [(C + 1) x nseg]
+  int nseg;            // chunks (local) or row chunks of the coarse passes
+  int local;
+  int C;
+  int64_t n;
+};
+
+constexpr int kMaxSeg = 1024;  // chunks a local plan may have (LDS table of the reduce)
+constexpr int kMapCap = 2048;  // entries of a bin mapped at once
+
+// LDS of a binned block besides the rows of S A: the bin's segment starts and
+// prefix lengths, and the map from the bin's row index to its plan entry.
+struct SegLds {
+  int32_t start[kMaxSeg];
+  int32_t pfx[kMaxSeg + 1];
+  int32_t map[kMapCap];
+};
+
+// Fill L.start / L.pfx for bin c and return the bin's row count.
+__device__ __forceinline__ int32_t load_segments(const BinSegs& S, int c, SegLds& L, int32_t* wsum) {
+  const int ns = S.local ? S.nseg : 1;
+  const int per = (ns + static_cast<int>(blockDim.x) - 1) / static_cast<int>(blockDim.x);
+  const int q0 = threadIdx.x * per;
+  int32_t len[4];  // ns <= kMaxSeg and blockDim.x >= 256: at most 4 per thread
+  int32_t run = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int q = q0 + k;
+    len[k] = 0;
+    if (k < per && q < ns) {
+      int64_t st, en;
+      if (S.local) {
+        st = static_cast<int64_t>(q) * kPlanChunk + S.off[static_cast<size_t>(c) * ns + q];
+        en = static_cast<int64_t>(q) * kPlanChunk + S.off[static_cast<size_t>(c + 1) * ns + q];
+      } else {
+        st = S.off[static_cast<size_t>(c) * S.nseg];
+        en = (c + 1 < S.C) ? S.off[static_cast<size_t>(c + 1) * S.nseg] : S.n;
+      }
+      L.start[q] = static_cast<int32_t>(st);
+      len[k] = static_cast<int32_t>(en - st);
+      run += len[k];
+    }
+  }
+  int32_t tot;
+  int32_t pre = block_exclusive_scan(run, wsum, &tot);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int q = q0 + k;
+    if (k < per && q < ns) {
+      L.pfx[q] = pre;
+      pre += len[k];
+    }
+  }
+  if (threadIdx.x == 0) L.pfx[ns] = tot;
+  __syncthreads();
+  return tot;
+}
+
+// L.map[k] = plan entry of the bin's row p0 + k, for p0 + k < pe: one
+// thread per segment writes the segment's part of [p0, pe), or, for a single
+// segment, one thread per row.
+__device__ __forceinline__ void map_rows(const BinSegs& S, SegLds& L, int32_t p0, int32_t pe) {
+  if (!S.local) {
+    for (int32_t k = threadIdx.x; k < pe - p0; k += blockDim.x) L.map[k] = L.start[0] + p0 + k;
+    return;
+  }
+  for (int q = threadIdx.x; q < S.nseg; q += blockDim.x) {
+    const int32_t lo = L.pfx[q] > p0 ? L.pfx[q] : p0;
+    const int32_t hi = L.pfx[q + 1] < pe ? L.pfx[q + 1] : pe;
+    for (int32_t j = lo; j < hi; ++j) L.map[j - p0] = L.start[q] + (j - L.pfx[q]);
+  }
+}
+
 // ---------------------------------------------------------------- CSR row gather
 // A wavefront reduces up to 128 CSR rows at a time (two per lane: rows lane
 // and lane + 64 of the chunk) into an LDS accumulator.  Wave-wide scans of
@@ -363,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, u
 // aligned), positions are groups of four: one 16-byte load of column indices
 // and one of values per lane.
 constexpr int kChunkRows = 2 * kWave;
-constexpr int kPosCap = 2048;
+constexpr int kPosCap = 1024;
 constexpr int kBurst = 16;
 constexpr int kBurstQ = 8;
 
@@ -635,11 +801,11 @@ __device__ __forceinline__ CsrRec<TR, TO> load_rec(const CsrRec<TR, TO>* __restr
 
 template <typename TV, typename TR, typename TO>
 __global__ __launch_bounds__(kBinThreads) void k_sketch_csr_binned(
-    int d, uint32_t t, int sh, int C, int nblk, int splits, int64_t n, uint64_t seed,
-    const int32_t* __restrict__ col, const TV* __restrict__ val, const float* __restrict__ w,
-    const int32_t* __restrict__ coff, const CsrRec<TR, TO>* __restrict__ recs, TO* __restrict__ SA,
-    TO* __restrict__ Sb, int acc_bytes, int sb_bytes, int quad_ok) {
+    int d, uint32_t t, int sh, int splits, uint64_t seed, const int32_t* __restrict__ col,
+    const TV* __restrict__ val, const float* __restrict__ w, BinSegs S, const CsrRec<TR, TO>* __restrict__ recs,
+    TO* __restrict__ SA, TO* __restrict__ Sb, int acc_bytes, int sb_bytes, int quad_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t wsum[kBinWaves];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int c = blockIdx.x / splits, sp = blockIdx.x % splits;
   const uint32_t bk0 = static_cast<uint32_t>(c) << sh;
@@ -647,49 +813,54 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_csr_binned(
   const int nbk = (t - bk0) < static_cast<uint32_t>(fine) ? static_cast<int>(t - bk0) : fine;
   TO* acc = reinterpret_cast<TO*>(smem);
   TO* sbacc = reinterpret_cast<TO*>(smem + acc_bytes);
-  GatherLds<TR, TO>& G =
-      *reinterpret_cast<GatherLds<TR, TO>*>(smem + acc_bytes + sb_bytes + wid * sizeof(GatherLds<TR, TO>));
-  const int64_t b0 = coff[static_cast<size_t>(c) * nblk];
-  const int64_t b1 = (c + 1 < C) ? coff[static_cast<size_t>(c + 1) * nblk] : n;
-  const int64_t beg = b0 + (b1 - b0) * sp / splits, end = b0 + (b1 - b0) * (sp + 1) / splits;
+  SegLds& L = *reinterpret_cast<SegLds*>(smem + acc_bytes + sb_bytes);
+  GatherLds<TR, TO>& G = *reinterpret_cast<GatherLds<TR, TO>*>(smem + acc_bytes + sb_bytes + sizeof(SegLds) +
+                                                              wid * sizeof(GatherLds<TR, TO>));
   const int nacc = nbk * d;
   for (int e = threadIdx.x; e < nacc; e += kBinThreads) acc[e] = TO(0);
   for (int e = threadIdx.x; e < nbk; e += kBinThreads) sbacc[e] = TO(0);
-  __syncthreads();
-  constexpr int64_t kStep = static_cast<int64_t>(kBinWaves) * kChunkRows;
-  int64_t j0 = beg + static_cast<int64_t>(wid) * kChunkRows;
-  // Record loads are unconditional: indexes past the end read the bin's last
-  // record (its row counts as empty), so no load sits behind a branch whose
-  // join makes the compiler wait for it.
-  auto rec_at = [&](int64_t j) -> CsrRec<TR, TO> { return recs[j < end ? j : end - 1]; };
-  CsrRec<TR, TO> cur[2];
-  if (j0 < end) {
+  const int32_t total = load_segments(S, c, L, wsum);
+  const int32_t beg = static_cast<int32_t>(static_cast<int64_t>(total) * sp / splits);
+  const int32_t end = static_cast<int32_t>(static_cast<int64_t>(total) * (sp + 1) / splits);
+  constexpr int32_t kStep = kBinWaves * kChunkRows;
+  for (int32_t p0 = beg; p0 < end; p0 += kMapCap) {
+    const int32_t pe = end - p0 < kMapCap ? end : p0 + kMapCap;
+    map_rows(S, L, p0, pe);
+    __syncthreads();
+    // Record loads are unconditional: rows past the end read the piece's last
+    // record (and count as empty), so no load sits behind a branch whose join
+    // makes the compiler wait for it.
+    auto rec_at = [&](int32_t j) -> CsrRec<TR, TO> { return recs[L.map[(j < pe ? j : pe - 1) - p0]]; };
+    int32_t j0 = p0 + wid * kChunkRows;
+    CsrRec<TR, TO> cur[2];
+    if (j0 < pe) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) cur[h] = rec_at(j0 + h * kWave + lane);
-  }
-  for (; j0 < end; j0 += kStep) {
-    RowPair<TR, TO> R;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const bool has = j0 + h * kWave + lane < end;
-      const uint64_t z = splitmix64(seed, static_cast<uint64_t>(cur[h].row));
-      const int lb = static_cast<int>(bucket_of(z, t) - bk0);
-      R.st[h] = cur[h].start;
-      R.len[h] = has ? cur[h].len : 0;
-      R.sc[h] = w ? static_cast<TO>(w[cur[h].row]) : (negative_of(z) ? TO(-1) : TO(1));
-      R.off[h] = lb * d;
-      if (Sb != nullptr && has) lds_add1(sbacc, lb, cur[h].sbv);
+      for (int h = 0; h < 2; ++h) cur[h] = rec_at(j0 + h * kWave + lane);
     }
-    // next step's records are requested after this step's rows are set up
-    // (so no wait there covers them) and before this step's gathers
-    CsrRec<TR, TO> nxt[2];
+    for (; j0 < pe; j0 += kStep) {
+      RowPair<TR, TO> R;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) nxt[h] = rec_at(j0 + kStep + h * kWave + lane);
-    gather_chunk<TV, TR, TO>(G, R, quad_ok, col, val, acc, lane);
-    cur[0] = nxt[0];
-    cur[1] = nxt[1];
+      for (int h = 0; h < 2; ++h) {
+        const bool has = j0 + h * kWave + lane < pe;
+        const uint64_t z = splitmix64(seed, static_cast<uint64_t>(cur[h].row));
+        const int lb = static_cast<int>(bucket_of(z, t) - bk0);
+        R.st[h] = cur[h].start;
+        R.len[h] = has ? cur[h].len : 0;
+        R.sc[h] = w ? static_cast<TO>(w[cur[h].row]) : (negative_of(z) ? TO(-1) : TO(1));
+        R.off[h] = lb * d;
+        if (Sb != nullptr && has) lds_add1(sbacc, lb, cur[h].sbv);
+      }
+      // next step's records are requested after this step's rows are set up
+      // (so no wait there covers them) and before this step's gathers
+      CsrRec<TR, TO> nxt[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) nxt[h] = rec_at(j0 + kStep + h * kWave + lane);
+      gather_chunk<TV, TR, TO>(G, R, quad_ok, col, val, acc, lane);
+      cur[0] = nxt[0];
+      cur[1] = nxt[1];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   TO* out = SA + static_cast<size_t>(bk0) * d;
   if (splits == 1) {
     for (int e = threadIdx.x; e < nacc; e += kBinThreads) out[e] = acc[e];
@@ -999,11 +1170,11 @@ __global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted(
 // slices per lane, into the bin's LDS rows of S A.
 template <typename TV, typename TO, int V>
 __global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
-    int d, int64_t ld, uint32_t t, int sh, int C, int nblk, int splits, int64_t n, uint64_t seed,
-    const TV* __restrict__ A, const void* __restrict__ b, int b_f64, const float* __restrict__ w,
-    const int32_t* __restrict__ coff, const int32_t* __restrict__ rows, TO* __restrict__ SA, TO* __restrict__ Sb,
-    int acc_bytes) {
+    int d, int64_t ld, uint32_t t, int sh, int splits, uint64_t seed, const TV* __restrict__ A,
+    const void* __restrict__ b, int b_f64, const float* __restrict__ w, BinSegs S,
+    const int32_t* __restrict__ rows, TO* __restrict__ SA, TO* __restrict__ Sb, int acc_bytes, int sb_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t wsum[kBinWaves];
   constexpr int RB = 4;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int c = blockIdx.x / splits, sp = blockIdx.x % splits;
@@ -1012,46 +1183,51 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
   const int nbk = (t - bk0) < static_cast<uint32_t>(fine) ? static_cast<int>(t - bk0) : fine;
   TO* acc = reinterpret_cast<TO*>(smem);
   TO* sbacc = reinterpret_cast<TO*>(smem + acc_bytes);
-  const int64_t b0 = coff[static_cast<size_t>(c) * nblk];
-  const int64_t b1 = (c + 1 < C) ? coff[static_cast<size_t>(c + 1) * nblk] : n;
-  const int64_t beg = b0 + (b1 - b0) * sp / splits, end = b0 + (b1 - b0) * (sp + 1) / splits;
+  SegLds& L = *reinterpret_cast<SegLds*>(smem + acc_bytes + sb_bytes);
   const int nacc = nbk * d;
   for (int e = threadIdx.x; e < nacc; e += kBinThreads) acc[e] = TO(0);
   for (int e = threadIdx.x; e < nbk; e += kBinThreads) sbacc[e] = TO(0);
-  __syncthreads();
-  for (int64_t j0 = beg + static_cast<int64_t>(wid) * RB; j0 < end; j0 += static_cast<int64_t>(kBinWaves) * RB) {
-    int32_t r[RB], o[RB];
-    bool okq[RB];
-    TO sc[RB];
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const bool ok = j0 + q < end;
-      r[q] = rows[ok ? j0 + q : j0];
-      const uint64_t z = splitmix64(seed, static_cast<uint64_t>(r[q]));
-      const int lb = static_cast<int>(bucket_of(z, t) - bk0);
-      o[q] = lb * d;
-      okq[q] = ok;
-      sc[q] = w ? static_cast<TO>(w[r[q]]) : (negative_of(z) ? TO(-1) : TO(1));
-      if (Sb != nullptr && ok && lane == 0) lds_add1(sbacc, lb, sc[q] * load_b<TO>(b, b_f64, r[q]));
-    }
-    for (int c0 = lane * V; c0 < d; c0 += kWave * V) {
-      TO x[RB][V];
-#pragma unroll
-      for (int q = 0; q < RB; ++q) RowLoad<TV, TO, V>::load(A + static_cast<size_t>(r[q]) * ld + c0, x[q]);
+  const int32_t total = load_segments(S, c, L, wsum);
+  const int32_t beg = static_cast<int32_t>(static_cast<int64_t>(total) * sp / splits);
+  const int32_t end = static_cast<int32_t>(static_cast<int64_t>(total) * (sp + 1) / splits);
+  for (int32_t p0 = beg; p0 < end; p0 += kMapCap) {
+    const int32_t pe = end - p0 < kMapCap ? end : p0 + kMapCap;
+    map_rows(S, L, p0, pe);
+    __syncthreads();
+    for (int32_t j0 = p0 + wid * RB; j0 < pe; j0 += kBinWaves * RB) {
+      int32_t r[RB], o[RB];
+      bool okq[RB];
+      TO sc[RB];
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
-        int32_t a[V];
-        TO y[V];
+        const bool ok = j0 + q < pe;
+        r[q] = rows[L.map[(ok ? j0 + q : j0) - p0]];
+        const uint64_t z = splitmix64(seed, static_cast<uint64_t>(r[q]));
+        const int lb = static_cast<int>(bucket_of(z, t) - bk0);
+        o[q] = lb * d;
+        okq[q] = ok;
+        sc[q] = w ? static_cast<TO>(w[r[q]]) : (negative_of(z) ? TO(-1) : TO(1));
+        if (Sb != nullptr && ok && lane == 0) lds_add1(sbacc, lb, sc[q] * load_b<TO>(b, b_f64, r[q]));
+      }
+      for (int c0 = lane * V; c0 < d; c0 += kWave * V) {
+        TO x[RB][V];
 #pragma unroll
-        for (int k = 0; k < V; ++k) {
-          a[k] = o[q] + c0 + k;
-          y[k] = sc[q] * x[q][k];
+        for (int q = 0; q < RB; ++q) RowLoad<TV, TO, V>::load(A + static_cast<size_t>(r[q]) * ld + c0, x[q]);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          int32_t a[V];
+          TO y[V];
+#pragma unroll
+          for (int k = 0; k < V; ++k) {
+            a[k] = o[q] + c0 + k;
+            y[k] = sc[q] * x[q][k];
+          }
+          lds_add<TO, V>(acc, a, y, okq[q] ? 0xffffffffu : 0u);
         }
-        lds_add<TO, V>(acc, a, y, okq[q] ? 0xffffffffu : 0u);
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
   TO* out = SA + static_cast<size_t>(bk0) * d;
   if (splits == 1) {
     for (int e = threadIdx.x; e < nacc; e += kBinThreads) out[e] = acc[e];
@@ -1193,6 +1369,8 @@ struct PlanShape {
   int nblk = 1;       // row chunks of the coarse passes
   size_t entry = 4;   // bytes per plan entry (row index or CSR record)
   int splits = 1;     // binned: blocks sharing one bin
+  int local = 0;      // binned: one-pass plan by chunks of kPlanChunk rows
+  int nseg = 0;       // chunks of the one-pass plan
 };
 
 size_t entry_bytes(const skls_matrix& A, int out_bytes) {
@@ -1208,12 +1386,13 @@ int64_t binned_fine(const skls_matrix& A, int64_t t, int out_bytes) {
   // LDS left for the rows of S A next to the per-wave gather tables (CSR)
   // and the bin's share of S b, within the 160 KiB of a compute unit
   int64_t budget = static_cast<int64_t>(kBinAcc);
+  int64_t tables = static_cast<int64_t>(sizeof(SegLds));
   if (A.layout == SKLS_CSR) {
     const int64_t ref = (A.row_ptr_64 && out_bytes == 8) ? 32 : 16;
-    const int64_t tables = kBinWaves * (kChunkRows * (ref + 4) + kPosCap);
-    const int64_t left = 160 * 1024 - tables - 4096 * out_bytes;
-    budget = left < budget ? left : budget;
+    tables += kBinWaves * (kChunkRows * (ref + 4) + kPosCap);
   }
+  const int64_t left = 160 * 1024 - tables - 4096 * out_bytes;
+  budget = left < budget ? left : budget;
   if (row > budget) return 0;
   int64_t fine = 1;
   while (fine < 4096 && fine < t && 2 * fine * row <= budget) fine *= 2;
@@ -1257,6 +1436,9 @@ PlanShape plan_shape(const skls_matrix& A, int64_t t, int32_t v, int out_bytes) 
     const int64_t want = div_up(1024, S.C), rows = n / (static_cast<int64_t>(S.C) * 2048);
     int64_t sp = want < rows ? want : rows;
     S.splits = static_cast<int>(sp < 1 ? 1 : (sp > 64 ? 64 : sp));
+    // one-pass plan while the per-bin segment table fits the reduce's LDS
+    S.nseg = S.nblk;
+    S.local = S.nseg <= kMaxSeg ? 1 : 0;
     return S;
   }
   // bucket order: coarse bins of about 4096 rows for the fine pass
@@ -1278,11 +1460,17 @@ struct BucketPlan {
   void* coarse = nullptr;    // [n] entries in coarse-bin order (two-level)
   void* fine = nullptr;      // [n] entries in bucket order (sorted)
   int32_t* off = nullptr;    // [t + 1] bucket offsets (sorted)
+  int32_t* offT = nullptr;   // [(C + 1) x nseg] per-chunk bin offsets (one-pass plan)
 };
 
 BucketPlan carve_plan(Arena& ar, const PlanShape& S, int64_t n, int64_t t) {
   BucketPlan P;
   P.S = S;
+  if (S.local) {
+    P.offT = ar.take<int32_t>(static_cast<size_t>(S.C + 1) * S.nseg);
+    P.coarse = ar.take<char>(static_cast<size_t>(n) * S.entry);
+    return P;
+  }
   const int64_t ncnt = S.C ? static_cast<int64_t>(S.C) * S.nblk : t;
   P.count = ar.take<int32_t>(static_cast<size_t>(ncnt) + 1);
   P.bsum = ar.take<int32_t>(static_cast<size_t>(div_up(ncnt, kScanTile)) + 1);
@@ -1316,9 +1504,19 @@ int32_t scan_counts(const int32_t* count, int64_t ncnt, int32_t* bsum, int32_t* 
   return SKLS_OK;
 }
 
+int32_t allow_lds(const void* kernel, size_t lds);
+
 template <typename R>
 int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, const RowSrc& src, hipStream_t s) {
   const PlanShape& S = P.S;
+  if (S.local) {
+    const size_t lds = 2 * sizeof(uint16_t) * kPlanChunk + static_cast<size_t>(S.C + 1) * sizeof(int32_t);
+    SKLS_TRY(allow_lds(reinterpret_cast<const void*>(&k_plan_local<R>), lds));
+    hipLaunchKernelGGL((k_plan_local<R>), dim3(S.nseg), dim3(kPlanThreads), lds, s, n, t, seed, S.sh, S.C, src,
+                       static_cast<R*>(P.coarse), P.offT, S.nseg);
+    SKLS_CHECK_LAUNCH();
+    return SKLS_OK;
+  }
   if (S.C > 0) {
     const size_t lds = static_cast<size_t>(S.C) * sizeof(int32_t);
     const int64_t ncnt = static_cast<int64_t>(S.C) * S.nblk;
@@ -1386,6 +1584,16 @@ int32_t allow_lds(const void* kernel, size_t lds) {
   return SKLS_OK;
 }
 
+BinSegs bin_segs(const BucketPlan& P, int64_t n) {
+  BinSegs g;
+  g.off = P.S.local ? P.offT : P.count;
+  g.nseg = P.S.local ? P.S.nseg : P.S.nblk;
+  g.local = P.S.local;
+  g.C = P.S.C;
+  g.n = n;
+  return g;
+}
+
 // Apply of the SORTED and BINNED variants once the plan is built.
 template <typename TO>
 int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, int b_f64, uint32_t t, uint64_t seed,
@@ -1400,19 +1608,21 @@ int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, 
       const bool vec = vec_ok<TV>(A.val, A.ld, A.d, VV);
       if (S.variant == SKLS_SKETCH_BINNED) {
         const int acc_bytes = static_cast<int>(round16((size_t(1) << S.sh) * d * sizeof(TO)));
-        const size_t lds = acc_bytes + round16((size_t(1) << S.sh) * sizeof(TO));
+        const int sb_bytes = static_cast<int>(round16((size_t(1) << S.sh) * sizeof(TO)));
+        const size_t lds = acc_bytes + sb_bytes + sizeof(SegLds);
         const unsigned grid = static_cast<unsigned>(S.C) * S.splits;
         const int32_t* rows = static_cast<const int32_t*>(P.coarse);
+        const BinSegs segs = bin_segs(P, n);
         if (vec) {
           SKLS_TRY(allow_lds(reinterpret_cast<const void*>(&k_sketch_dense_binned<TV, TO, VV>), lds));
           hipLaunchKernelGGL((k_sketch_dense_binned<TV, TO, VV>), dim3(grid), dim3(kBinThreads), lds, s, d, A.ld, t,
-                             S.sh, S.C, S.nblk, S.splits, n, seed, static_cast<const TV*>(A.val), b, b_f64, w,
-                             P.count, rows, SA, Sb, acc_bytes);
+                             S.sh, S.splits, seed, static_cast<const TV*>(A.val), b, b_f64, w, segs, rows, SA, Sb,
+                             acc_bytes, sb_bytes);
         } else {
           SKLS_TRY(allow_lds(reinterpret_cast<const void*>(&k_sketch_dense_binned<TV, TO, 1>), lds));
           hipLaunchKernelGGL((k_sketch_dense_binned<TV, TO, 1>), dim3(grid), dim3(kBinThreads), lds, s, d, A.ld, t,
-                             S.sh, S.C, S.nblk, S.splits, n, seed, static_cast<const TV*>(A.val), b, b_f64, w,
-                             P.count, rows, SA, Sb, acc_bytes);
+                             S.sh, S.splits, seed, static_cast<const TV*>(A.val), b, b_f64, w, segs, rows, SA, Sb,
+                             acc_bytes, sb_bytes);
         }
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
@@ -1441,13 +1651,13 @@ int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, 
       if (S.variant == SKLS_SKETCH_BINNED) {
         const int acc_bytes = static_cast<int>(round16((size_t(1) << S.sh) * d * sizeof(TO)));
         const int sb_bytes = static_cast<int>(round16((size_t(1) << S.sh) * sizeof(TO)));
-        const size_t lds = acc_bytes + sb_bytes + kBinWaves * sizeof(GatherLds<TR, TO>);
+        const size_t lds = acc_bytes + sb_bytes + sizeof(SegLds) + kBinWaves * sizeof(GatherLds<TR, TO>);
         const void* kern = reinterpret_cast<const void*>(&k_sketch_csr_binned<TV, TR, TO>);
         SKLS_TRY(allow_lds(kern, lds));
         hipLaunchKernelGGL((k_sketch_csr_binned<TV, TR, TO>), dim3(static_cast<unsigned>(S.C) * S.splits),
-                           dim3(kBinThreads), lds, s, d, t, S.sh, S.C, S.nblk, S.splits, n, seed, A.col_idx,
-                           static_cast<const TV*>(A.val), w, P.count, static_cast<const Rec*>(P.coarse), SA, Sb,
-                           acc_bytes, sb_bytes, quad_ok);
+                           dim3(kBinThreads), lds, s, d, t, S.sh, S.splits, seed, A.col_idx,
+                           static_cast<const TV*>(A.val), w, bin_segs(P, n), static_cast<const Rec*>(P.coarse), SA,
+                           Sb, acc_bytes, sb_bytes, quad_ok);
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
       }
