@@ -352,31 +352,35 @@ __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, u
 }
 
 // ---------------------------------------------------------------- one-pass local plan
-// Rows grouped by coarse bin within fixed chunks of kPlanChunk rows, in one
-// kernel: each block counts its chunk's rows per bin in LDS, scans the counts,
-// ranks every row within its bin (LDS atomics) and writes the chunk's plan
-// entries in bin order to the chunk's own slice of the output, so all global
-// writes are coalesced.  The per-chunk bin offsets go to offT[(C + 1) x nseg]
-// (row c holds bin c's offset in every chunk; row C holds the chunk sizes):
-// bin c of chunk q is out[q * kPlanChunk + offT[c][q] .. + offT[c + 1][q]).
-template <typename R>
+// Rows grouped by coarse bin within fixed chunks of PER * kPlanThreads rows,
+// in one kernel: each block counts its chunk's rows per bin in LDS, scans the
+// counts, builds every row's plan entry from row pointers read in storage
+// order, places it at its slot in an LDS copy of the chunk (LDS atomics hand
+// out the slots) and writes the chunk out in bin order, so every global read
+// and write is coalesced.  The per-chunk bin offsets go to
+// offT[nseg x (C + 1)] (row q holds chunk q's exclusive offsets, then its
+// size): bin c of chunk q is out[q * chunk + offT[q][c] ..
+// q * chunk + offT[q][c + 1]).
+template <typename R, int PER>
 __global__ __launch_bounds__(kPlanThreads) void k_plan_local(int64_t n, uint32_t t, uint64_t seed, int sh, int C,
                                                              RowSrc src, R* __restrict__ out,
                                                              int32_t* __restrict__ offT, int nseg) {
+  constexpr int CH = PER * kPlanThreads;
   extern __shared__ __align__(16) unsigned char smem[];
-  uint16_t* bin = reinterpret_cast<uint16_t*>(smem);                   // [kPlanChunk]
-  uint16_t* perm = bin + kPlanChunk;                                   // [kPlanChunk]
-  int32_t* cnt = reinterpret_cast<int32_t*>(perm + kPlanChunk);        // [C + 1]
+  R* stage = reinterpret_cast<R*>(smem);                       // [CH]
+  int32_t* cnt = reinterpret_cast<int32_t*>(smem + sizeof(R) * CH);  // [C + 1]
   __shared__ int32_t wsum[kPlanThreads / kWave];
   const int q = blockIdx.x;
-  const int64_t r0 = static_cast<int64_t>(q) * kPlanChunk;
-  const int m = static_cast<int>(n - r0 < kPlanChunk ? (n - r0 > 0 ? n - r0 : 0) : kPlanChunk);
+  const int64_t r0 = static_cast<int64_t>(q) * CH;
+  const int m = static_cast<int>(n - r0 < CH ? (n - r0 > 0 ? n - r0 : 0) : CH);
   for (int c = threadIdx.x; c <= C; c += kPlanThreads) cnt[c] = 0;
   __syncthreads();
-  for (int p = threadIdx.x; p < m; p += kPlanThreads) {
-    const int b = static_cast<int>(bucket_of(splitmix64(seed, static_cast<uint64_t>(r0 + p)), t) >> sh);
-    bin[p] = static_cast<uint16_t>(b);
-    atomicAdd(&cnt[b], 1);
+  int32_t bin[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int p = u * kPlanThreads + threadIdx.x;
+    bin[u] = static_cast<int32_t>(bucket_of(splitmix64(seed, static_cast<uint64_t>(r0 + p)), t) >> sh);
+    if (p < m) atomicAdd(&cnt[bin[u]], 1);
   }
   __syncthreads();
   // exclusive scan of cnt[0..C): each thread owns a run of counters
@@ -395,58 +399,67 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_local(int64_t n, uint32_t
     }
   if (threadIdx.x == 0) cnt[C] = m;
   __syncthreads();
-  for (int c = threadIdx.x; c <= C; c += kPlanThreads) offT[static_cast<size_t>(c) * nseg + q] = cnt[c];
+  for (int c = threadIdx.x; c <= C; c += kPlanThreads) offT[static_cast<size_t>(q) * (C + 1) + c] = cnt[c];
   __syncthreads();
-  for (int p = threadIdx.x; p < m; p += kPlanThreads) perm[atomicAdd(&cnt[bin[p]], 1)] = static_cast<uint16_t>(p);
-  __syncthreads();
-  // entries in bin order: eight per thread at a time, loads clamped to the
-  // chunk's last row so that all of them are in flight together
-  using TO = typename Entry<R>::TO;
-  constexpr int kU = 8;
-  for (int s0 = 0; s0 < m; s0 += kU * kPlanThreads) {
-    R e[kU];
-    int64_t ii[kU];
+  if (m > 0) {
+    // entries of this thread's rows, read in storage order with loads clamped
+    // to the chunk's last row so that all of them are in flight together
+    // (the optional b and w under uniform branches of their own)
+    using TO = typename Entry<R>::TO;
+    R e[PER];
+    int64_t ii[PER];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int sidx = s0 + u * kPlanThreads + threadIdx.x;
-      ii[u] = r0 + perm[sidx < m ? sidx : m - 1];
+    for (int u = 0; u < PER; ++u) {
+      const int p = u * kPlanThreads + threadIdx.x;
+      ii[u] = r0 + (p < m ? p : m - 1);
       e[u] = Entry<R>::extent(src, ii[u]);
     }
     if (Entry<R>::kSb && src.b != nullptr) {
-      TO bv[kU], sc[kU];
+      TO bv[PER], sc[PER];
       if (src.b_f64) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) bv[u] = static_cast<TO>(static_cast<const double*>(src.b)[ii[u]]);
+        for (int u = 0; u < PER; ++u) bv[u] = static_cast<TO>(static_cast<const double*>(src.b)[ii[u]]);
       } else {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) bv[u] = static_cast<TO>(static_cast<const float*>(src.b)[ii[u]]);
+        for (int u = 0; u < PER; ++u) bv[u] = static_cast<TO>(static_cast<const float*>(src.b)[ii[u]]);
       }
       if (src.w != nullptr) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) sc[u] = static_cast<TO>(src.w[ii[u]]);
+        for (int u = 0; u < PER; ++u) sc[u] = static_cast<TO>(src.w[ii[u]]);
       } else {
 #pragma unroll
-        for (int u = 0; u < kU; ++u)
+        for (int u = 0; u < PER; ++u)
           sc[u] = negative_of(splitmix64(seed, static_cast<uint64_t>(ii[u]))) ? TO(-1) : TO(1);
       }
 #pragma unroll
-      for (int u = 0; u < kU; ++u) Entry<R>::set_sb(e[u], sc[u] * bv[u]);
+      for (int u = 0; u < PER; ++u) Entry<R>::set_sb(e[u], sc[u] * bv[u]);
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int sidx = s0 + u * kPlanThreads + threadIdx.x;
-      if (sidx < m) out[r0 + sidx] = e[u];
-    }
+    for (int u = 0; u < PER; ++u)
+      if (u * kPlanThreads + static_cast<int>(threadIdx.x) < m) stage[atomicAdd(&cnt[bin[u]], 1)] = e[u];
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < m; k += kPlanThreads) out[r0 + k] = stage[k];
+}
+
+// Blocks are dispatched to the eight XCDs of the chip in turn; this maps the
+// dispatch index to a work index so that each XCD takes one contiguous range
+// of the work (neighbouring bins then share their L2 lines: segment tables,
+// rows of S A).
+__device__ __forceinline__ int xcd_major(int g, int G) {
+  constexpr int kXcd = 8;
+  if (G % kXcd != 0) return g;
+  return (g % kXcd) * (G / kXcd) + g / kXcd;
 }
 
 // ---------------------------------------------------------------- bin segments
 // Where a coarse bin's plan entries are: one contiguous range (two-level
 // plan) or one range per chunk (one-pass local plan).
 struct BinSegs {
-  const int32_t* off;  // coarse offsets [C * nblk + 1] or local offsets [(C + 1) x nseg]
+  const int32_t* off;  // coarse offsets [C * nblk + 1] or local offsets [nseg x (C + 1)]
   int nseg;            // chunks (local) or row chunks of the coarse passes
   int local;
+  int chunk;           // rows per chunk of the local plan
   int C;
   int64_t n;
 };
@@ -476,8 +489,9 @@ __device__ __forceinline__ int32_t load_segments(const BinSegs& S, int c, SegLds
     if (k < per && q < ns) {
       int64_t st, en;
       if (S.local) {
-        st = static_cast<int64_t>(q) * kPlanChunk + S.off[static_cast<size_t>(c) * ns + q];
-        en = static_cast<int64_t>(q) * kPlanChunk + S.off[static_cast<size_t>(c + 1) * ns + q];
+        const int32_t* o = S.off + static_cast<size_t>(q) * (S.C + 1) + c;
+        st = static_cast<int64_t>(q) * S.chunk + o[0];
+        en = static_cast<int64_t>(q) * S.chunk + o[1];
       } else {
         st = S.off[static_cast<size_t>(c) * S.nseg];
         en = (c + 1 < S.C) ? S.off[static_cast<size_t>(c + 1) * S.nseg] : S.n;
@@ -807,7 +821,8 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_csr_binned(
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t wsum[kBinWaves];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int c = blockIdx.x / splits, sp = blockIdx.x % splits;
+  const int gb = xcd_major(blockIdx.x, gridDim.x);
+  const int c = gb / splits, sp = gb % splits;
   const uint32_t bk0 = static_cast<uint32_t>(c) << sh;
   const int fine = 1 << sh;
   const int nbk = (t - bk0) < static_cast<uint32_t>(fine) ? static_cast<int>(t - bk0) : fine;
@@ -1177,7 +1192,8 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
   __shared__ int32_t wsum[kBinWaves];
   constexpr int RB = 4;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int c = blockIdx.x / splits, sp = blockIdx.x % splits;
+  const int gb = xcd_major(blockIdx.x, gridDim.x);
+  const int c = gb / splits, sp = gb % splits;
   const uint32_t bk0 = static_cast<uint32_t>(c) << sh;
   const int fine = 1 << sh;
   const int nbk = (t - bk0) < static_cast<uint32_t>(fine) ? static_cast<int>(t - bk0) : fine;
@@ -1369,7 +1385,8 @@ struct PlanShape {
   int nblk = 1;       // row chunks of the coarse passes
   size_t entry = 4;   // bytes per plan entry (row index or CSR record)
   int splits = 1;     // binned: blocks sharing one bin
-  int local = 0;      // binned: one-pass plan by chunks of kPlanChunk rows
+  int local = 0;      // binned: one-pass plan by chunks of `per` * kPlanThreads rows
+  int per = 0;        // rows per thread of the one-pass plan (4, 8 or 16)
   int nseg = 0;       // chunks of the one-pass plan
 };
 
@@ -1421,6 +1438,11 @@ int32_t pick_variant(const skls_matrix& A, int64_t t, int32_t variant, int out_b
   return SKLS_SKETCH_SORTED;
 }
 
+// LDS of the one-pass plan kernel: the chunk's entries and the bin counters.
+size_t local_lds(int per, size_t entry, int C) {
+  return entry * static_cast<size_t>(per) * kPlanThreads + static_cast<size_t>(C + 1) * sizeof(int32_t) + 256;
+}
+
 PlanShape plan_shape(const skls_matrix& A, int64_t t, int32_t v, int out_bytes) {
   PlanShape S;
   const int64_t n = A.n;
@@ -1436,9 +1458,12 @@ PlanShape plan_shape(const skls_matrix& A, int64_t t, int32_t v, int out_bytes) 
     const int64_t want = div_up(1024, S.C), rows = n / (static_cast<int64_t>(S.C) * 2048);
     int64_t sp = want < rows ? want : rows;
     S.splits = static_cast<int>(sp < 1 ? 1 : (sp > 64 ? 64 : sp));
-    // one-pass plan while the per-bin segment table fits the reduce's LDS
-    S.nseg = S.nblk;
-    S.local = S.nseg <= kMaxSeg ? 1 : 0;
+    // one-pass plan: the largest chunk whose LDS copy and counters fit, used
+    // while the per-bin segment table fits the reduce's LDS
+    S.per = 16;
+    while (S.per > 4 && local_lds(S.per, S.entry, S.C) > 160 * 1024) S.per >>= 1;
+    S.nseg = static_cast<int>(div_up(n > 0 ? n : 1, static_cast<int64_t>(S.per) * kPlanThreads));
+    S.local = (S.nseg <= kMaxSeg && local_lds(S.per, S.entry, S.C) <= 160 * 1024) ? 1 : 0;
     return S;
   }
   // bucket order: coarse bins of about 4096 rows for the fine pass
@@ -1460,7 +1485,7 @@ struct BucketPlan {
   void* coarse = nullptr;    // [n] entries in coarse-bin order (two-level)
   void* fine = nullptr;      // [n] entries in bucket order (sorted)
   int32_t* off = nullptr;    // [t + 1] bucket offsets (sorted)
-  int32_t* offT = nullptr;   // [(C + 1) x nseg] per-chunk bin offsets (one-pass plan)
+  int32_t* offT = nullptr;   // [nseg x (C + 1)] per-chunk bin offsets (one-pass plan)
 };
 
 BucketPlan carve_plan(Arena& ar, const PlanShape& S, int64_t n, int64_t t) {
@@ -1510,12 +1535,17 @@ template <typename R>
 int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, const RowSrc& src, hipStream_t s) {
   const PlanShape& S = P.S;
   if (S.local) {
-    const size_t lds = 2 * sizeof(uint16_t) * kPlanChunk + static_cast<size_t>(S.C + 1) * sizeof(int32_t);
-    SKLS_TRY(allow_lds(reinterpret_cast<const void*>(&k_plan_local<R>), lds));
-    hipLaunchKernelGGL((k_plan_local<R>), dim3(S.nseg), dim3(kPlanThreads), lds, s, n, t, seed, S.sh, S.C, src,
-                       static_cast<R*>(P.coarse), P.offT, S.nseg);
-    SKLS_CHECK_LAUNCH();
-    return SKLS_OK;
+    const size_t lds = sizeof(R) * static_cast<size_t>(S.per) * kPlanThreads + static_cast<size_t>(S.C + 1) * 4;
+    auto launch = [&](auto kern) -> int32_t {
+      SKLS_TRY(allow_lds(reinterpret_cast<const void*>(kern), lds));
+      hipLaunchKernelGGL(kern, dim3(S.nseg), dim3(kPlanThreads), lds, s, n, t, seed, S.sh, S.C, src,
+                         static_cast<R*>(P.coarse), P.offT, S.nseg);
+      SKLS_CHECK_LAUNCH();
+      return SKLS_OK;
+    };
+    if (S.per == 16) return launch(&k_plan_local<R, 16>);
+    if (S.per == 8) return launch(&k_plan_local<R, 8>);
+    return launch(&k_plan_local<R, 4>);
   }
   if (S.C > 0) {
     const size_t lds = static_cast<size_t>(S.C) * sizeof(int32_t);
@@ -1589,6 +1619,7 @@ BinSegs bin_segs(const BucketPlan& P, int64_t n) {
   g.off = P.S.local ? P.offT : P.count;
   g.nseg = P.S.local ? P.S.nseg : P.S.nblk;
   g.local = P.S.local;
+  g.chunk = P.S.per * kPlanThreads;
   g.C = P.S.C;
   g.n = n;
   return g;
