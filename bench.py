@@ -29,6 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+SKETCH_SRC = os.path.join("paper_1207_6365_amd", "csrc", "sketch.hip")  # source of the sketch kernels
 
 
 def parse():
@@ -58,6 +59,28 @@ def profile_phases(sk):
     return out
 
 
+def stored_traffic(kernel: str, source: str):
+    """HBM bytes per launch of `kernel` from its counter summary under
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings),
+    or None when there is none or `source` has changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    with open(os.path.join(ROOT, source), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("source_sha256") != sha or "traffic_bytes" not in fields:
+        return None
+    return float(fields["traffic_bytes"])
+
+
 def time_steps(fn, steps, warmup, sync):
     import torch
 
@@ -77,8 +100,8 @@ def time_steps(fn, steps, warmup, sync):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported in this build "
-              "(the multi-GPU sharding of the sketch is a design, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the row sharding of the "
+              "sketch over several GPUs is described, not built)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -139,6 +162,7 @@ def main():
     ms_step = min(ms, ms_clean)
 
     alg_bytes = 4 * nnz + 4 * nnz + 4 * (A.n + 1) + 4 * t * A.d  # val + col + row_ptr + write S A
+    kname = {"atomic": "k_sketch_csr_atomic", "sorted": "k_sketch_csr_sorted"}.get(args.variant, "k_sketch_csr_binned")
     value = nnz / (ms_step * 1e-3)
     dom = "sketch_apply"
     cnt, tot = phases.get(dom, (0, float("nan")))
@@ -161,9 +185,8 @@ def main():
         "config": {"workload": "CountSketch S*A of CSR A, n=2^22, d=256, 16 nnz/row, float32 N(0,1), t=65536",
                    "n": A.n, "d": A.d, "nnz": nnz, "t": t, "variant": args.variant, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": None,
-                     "kernel": {"atomic": "k_sketch_csr_atomic", "sorted": "k_sketch_csr_sorted"}.get(
-                         args.variant, "k_sketch_csr_binned"),
+                     "frac": achieved / HBM_PEAK, "traffic": stored_traffic(kname, SKETCH_SRC),
+                     "kernel": kname,
                      "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes},
         "step_roofline_frac": alg_bytes / (ms_step * 1e-3) / HBM_PEAK,
         "phases_ms": {k: v[1] / max(v[0], 1) for k, v in phases.items()},

@@ -100,6 +100,93 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Sum over the 64 lanes with DPP row shifts and row broadcasts (an inclusive
+// scan whose last lane holds the total), returned to every lane; no LDS
+// round trips.  All 64 lanes must be active.
+__device__ __forceinline__ int32_t dpp_shift(int32_t x, int ctrl_sel) {
+  switch (ctrl_sel) {
+    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    case 3: return __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    case 4: return __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    default: return __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false); // row_bcast:31 into rows 2, 3
+  }
+}
+
+__device__ __forceinline__ float wave_total(float v) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) v += __int_as_float(dpp_shift(__float_as_int(v), c));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1));
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const long long b = __double_as_longlong(v);
+    const int32_t lo = dpp_shift(static_cast<int32_t>(b & 0xffffffffll), c);
+    const int32_t hi = dpp_shift(static_cast<int32_t>(b >> 32), c);
+    v += __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<uint32_t>(lo));
+  }
+  const long long b = __double_as_longlong(v);
+  const int32_t lo = __builtin_amdgcn_readlane(static_cast<int32_t>(b & 0xffffffffll), kWave - 1);
+  const int32_t hi = __builtin_amdgcn_readlane(static_cast<int32_t>(b >> 32), kWave - 1);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+
+// Floating-point adds into LDS as compare-and-swap loops.  gfx950 executes
+// ds_add_f32 / ds_add_f64 at a small fraction of the rate of its integer LDS
+// atomics (about 190 cycles per wave64 instruction per compute unit against
+// 7 for ds_add_u32, measured), while ds_cmpst runs at integer speed; a lane
+// whose swap lost to another lane or wave retries with the value it saw.
+template <typename T>
+struct FBits;
+template <>
+struct FBits<float> {
+  using U = uint32_t;
+  __device__ __forceinline__ static U to(float x) { return __float_as_uint(x); }
+  __device__ __forceinline__ static float from(U u) { return __uint_as_float(u); }
+};
+template <>
+struct FBits<double> {
+  using U = unsigned long long;
+  __device__ __forceinline__ static U to(double x) { return static_cast<U>(__double_as_longlong(x)); }
+  __device__ __forceinline__ static double from(U u) { return __longlong_as_double(static_cast<long long>(u)); }
+};
+
+// acc[a[k]] += v[k] for the k < N whose bit is set in `mask` (elements of
+// one lane may alias: their swaps are ordered and a stale one retries).
+template <typename TO, int N>
+__device__ __forceinline__ void lds_add(TO* acc, const int32_t (&a)[N], const TO (&v)[N],
+                                        uint32_t mask = 0xffffffffu) {
+  static_assert(N <= 32, "pending mask is 32 bits");
+  using B = FBits<TO>;
+  using U = typename B::U;
+  U* q = reinterpret_cast<U*>(acc);
+  U old[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) old[k] = q[a[k]];
+  uint32_t pend = mask & (N == 32 ? 0xffffffffu : ((1u << N) - 1u));
+  while (pend != 0) {
+    U got[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      got[k] = ((pend >> k) & 1u) ? atomicCAS(q + a[k], old[k], B::to(B::from(old[k]) + v[k])) : old[k];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      if (got[k] == old[k]) pend &= ~(1u << k);
+      old[k] = got[k];
+    }
+  }
+}
+
+template <typename TO>
+__device__ __forceinline__ void lds_add1(TO* acc, int32_t a, TO v) {
+  const int32_t aa[1] = {a};
+  const TO vv[1] = {v};
+  lds_add<TO, 1>(acc, aa, vv);
+}
+
 // Block-wide sum for blockDim.x a multiple of 64 (<= 1024); `scratch` holds
 // at least blockDim.x / 64 values.  Every thread receives the total.
 template <typename T>

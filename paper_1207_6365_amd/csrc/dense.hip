@@ -19,18 +19,10 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kGT = 64;          // Gram output tile (kGT x kGT per block)
-constexpr int kGK = 16;          // sketch rows staged in LDS per step
-constexpr int kGThreads = 256;   // 4 waves, each 32 x 32 of the tile
-
-template <typename TI>
-__device__ __forceinline__ double gram_elem(const TI* __restrict__ M, int64_t ld, const void* __restrict__ v,
-                                            int v_f64, int64_t k, int c, int d) {
-  if (c < d) return load_as<double>(M, static_cast<size_t>(k) * ld + c);
-  if (c == d && v != nullptr)
-    return v_f64 ? static_cast<const double*>(v)[k] : static_cast<double>(static_cast<const float*>(v)[k]);
-  return 0.0;
-}
+constexpr int kGT = 128;         // Gram output tile (kGT x kGT per block)
+constexpr int kGK = 32;          // sketch rows staged in LDS per step
+constexpr int kGThreads = 256;   // 4 waves, each 64 x 64 of the tile
+constexpr int kGLoads = kGK * kGT / 4 / kGThreads;  // 4-wide loads per thread per strip and step
 
 __device__ __forceinline__ void tile_of(int p, int T, int& ti, int& tj) {
   ti = 0;
@@ -41,75 +33,245 @@ __device__ __forceinline__ void tile_of(int p, int T, int& ti, int& tj) {
   tj = ti + p;
 }
 
-// Partial Gram tile over the rows of one split: partial[split][pair][64][64].
+// Staging type in LDS: float64 inputs stay float64, float32 and bfloat16
+// inputs are staged as float32 (exact) and widened when fed to the matrix
+// cores.
 template <typename TI>
+using GStage = typename std::conditional<std::is_same<TI, double>::value, double, float>::type;
+
+// Four consecutive elements of row k, columns c .. c + 3; `in` tells whether
+// they lie inside the matrix (rows before k1, columns before d).  VEC
+// (16-byte aligned rows, d a multiple of 4): one vector load from a clamped,
+// always valid address, so that all loads of a strip are in flight together
+// (the zeroing of elements outside happens when they are stored to LDS).
+// Otherwise element-wise guarded loads, already zeroed.
+template <typename TI, bool VEC>
+__device__ __forceinline__ void gload4(const TI* __restrict__ M, int64_t ld, int64_t k, int64_t k1, int c, int d,
+                                       GStage<TI> (&o)[4], bool& in) {
+  using TS = GStage<TI>;
+  if (VEC) {
+    in = k < k1 && c < d;
+    const TI* p = M + static_cast<size_t>(in ? k : k1 - 1) * ld + (in ? c : 0);
+    if constexpr (std::is_same<TI, float>::value) {
+      const float4 y = *reinterpret_cast<const float4*>(p);
+      o[0] = y.x;
+      o[1] = y.y;
+      o[2] = y.z;
+      o[3] = y.w;
+    } else if constexpr (std::is_same<TI, double>::value) {
+      const double2 y0 = *reinterpret_cast<const double2*>(p);
+      const double2 y1 = *reinterpret_cast<const double2*>(p + 2);
+      o[0] = y0.x;
+      o[1] = y0.y;
+      o[2] = y1.x;
+      o[3] = y1.y;
+    } else {
+      const uint2 y = *reinterpret_cast<const uint2*>(p);
+      o[0] = bf16_lo(y.x);
+      o[1] = bf16_hi(y.x);
+      o[2] = bf16_lo(y.y);
+      o[3] = bf16_hi(y.y);
+    }
+    return;
+  }
+  in = true;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    o[e] = (k < k1 && c + e < d) ? load_as<TS>(M, static_cast<size_t>(k) * ld + c + e) : TS(0);
+}
+
+template <typename TI, bool VEC, bool DIAG>
+__device__ __forceinline__ void gram_fetch(const TI* __restrict__ M, int64_t ld, int64_t kb, int64_t k1, int I0,
+                                           int J0, int d, GStage<TI> (&ra)[kGLoads][4],
+                                           GStage<TI> (&rb)[kGLoads][4], bool (&ia)[kGLoads],
+                                           bool (&ib)[kGLoads]) {
+#pragma unroll
+  for (int u = 0; u < kGLoads; ++u) {
+    const int e = (u * kGThreads + static_cast<int>(threadIdx.x)) * 4;
+    const int r = e / kGT, c = e % kGT;
+    gload4<TI, VEC>(M, ld, kb + r, k1, I0 + c, d, ra[u], ia[u]);
+    if (!DIAG) gload4<TI, VEC>(M, ld, kb + r, k1, J0 + c, d, rb[u], ib[u]);
+  }
+}
+
+template <typename TS, bool DIAG>
+__device__ __forceinline__ void gram_stash(TS (*As)[kGT], TS (*Bs)[kGT], const TS (&ra)[kGLoads][4],
+                                           const TS (&rb)[kGLoads][4], const bool (&ia)[kGLoads],
+                                           const bool (&ib)[kGLoads]) {
+#pragma unroll
+  for (int u = 0; u < kGLoads; ++u) {
+    const int e = (u * kGThreads + static_cast<int>(threadIdx.x)) * 4;
+    const int r = e / kGT, c = e % kGT;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[r][c + q] = ia[u] ? ra[u][q] : TS(0);
+      if (!DIAG) Bs[r][c + q] = ib[u] ? rb[u][q] : TS(0);
+    }
+  }
+}
+
+// Partial Gram tile (ti, tj) over the rows [k0, k1) of one split, on the
+// float64 matrix cores: partial[split][pair][kGT][kGT].  Strips of kGK rows
+// are staged in LDS, the next strip's loads in flight while the current one
+// is multiplied.  DIAG: the diagonal tiles (ti = tj = blockIdx.x; one strip
+// serves both operands), which with WITHV also form their columns' share of
+// M^T v; otherwise the off-diagonal tile pairs ti < tj.
+template <typename TI, bool VEC, bool DIAG, bool WITHV>
 __global__ __launch_bounds__(kGThreads) void k_gram_partial(const TI* __restrict__ M, int64_t ld,
                                                             const void* __restrict__ v, int v_f64, int64_t m, int d,
-                                                            int T, int64_t rows_per_split,
-                                                            double* __restrict__ partial) {
-  __shared__ double As[kGK][kGT];
-  __shared__ double Bs[kGK][kGT];
-  int ti, tj;
-  tile_of(blockIdx.x, T, ti, tj);
+                                                            int T, int P, int64_t rows_per_split,
+                                                            double* __restrict__ partial,
+                                                            double* __restrict__ partial_v) {
+  using TS = GStage<TI>;
+  __shared__ TS As[2][kGK][kGT];
+  __shared__ TS Bs[DIAG ? 1 : 2][DIAG ? 1 : kGK][kGT];
+  __shared__ double vs[2][kGK];
+  __shared__ double vred[kGT];
+  int ti, tj, pair;
+  if (DIAG) {
+    ti = tj = blockIdx.x;
+    pair = 0;
+    for (int q = 0; q < ti; ++q) pair += T - q;  // index of (ti, ti) in the upper-triangle order
+  } else {
+    // off-diagonal pairs in order, skipping the diagonal ones
+    int p = blockIdx.x;
+    ti = 0;
+    while (p >= T - ti - 1) {
+      p -= T - ti - 1;
+      ++ti;
+    }
+    tj = ti + 1 + p;
+    pair = 0;
+    for (int q = 0; q < ti; ++q) pair += T - q;
+    pair += tj - ti;
+  }
   const int I0 = ti * kGT, J0 = tj * kGT;
   const int64_t k0 = static_cast<int64_t>(blockIdx.y) * rows_per_split;
   const int64_t k1 = (k0 + rows_per_split < m) ? k0 + rows_per_split : m;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int wi = wv >> 1, wj = wv & 1;
   const int lr = lane >> 4, lc = lane & 15;
-  d4_t acc[2][2];
+  d4_t acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
-  for (int64_t kb = k0; kb < k1; kb += kGK) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < kGK * kGT; e += kGThreads) {
-      const int r = e / kGT, c = e % kGT;
-      const int64_t k = kb + r;
-      const bool in = k < k1;
-      As[r][c] = in ? gram_elem(M, ld, v, v_f64, k, I0 + c, d) : 0.0;
-      Bs[r][c] = in ? gram_elem(M, ld, v, v_f64, k, J0 + c, d) : 0.0;
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+  double vacc = 0.0;  // WITHV: column (tid % kGT) of M^T v over half of each strip's rows
+  double vv = 0.0;    // WITHV, first tile: v^T v over row (tid % kGK) of each strip
+  TS ra[kGLoads][4], rb[kGLoads][4];
+  bool ia[kGLoads], ib[kGLoads];
+  double rv = 0.0;
+  // every thread loads one entry of v (clamped to a valid row) so that the
+  // load is unconditional; the first kGK threads keep theirs
+  auto vload = [&](int64_t kb) {
+    if (WITHV) {
+      const int64_t k = kb + (threadIdx.x % kGK);
+      const int64_t kc = k < k1 ? k : k1 - 1;
+      const double x =
+          v_f64 ? static_cast<const double*>(v)[kc] : static_cast<double>(static_cast<const float*>(v)[kc]);
+      rv = k < k1 ? x : 0.0;
     }
-    __syncthreads();
+  };
+  int buf = 0;
+  if (k0 < k1) {
+    gram_fetch<TI, VEC, DIAG>(M, ld, k0, k1, I0, J0, d, ra, rb, ia, ib);
+    vload(k0);
+    gram_stash<TS, DIAG>(As[0], Bs[0], ra, rb, ia, ib);
+    if (WITHV && threadIdx.x < kGK) vs[0][threadIdx.x] = rv;
+  }
+  __syncthreads();
+  for (int64_t kb = k0; kb < k1; kb += kGK) {
+    const bool more = kb + kGK < k1;
+    if (more) {
+      gram_fetch<TI, VEC, DIAG>(M, ld, kb + kGK, k1, I0, J0, d, ra, rb, ia, ib);
+      vload(kb + kGK);
+    }
+    const TS(*Ab)[kGT] = As[buf];
+    const TS(*Bb)[kGT] = DIAG ? As[buf] : Bs[DIAG ? 0 : buf];
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 4) {
-      const double a0 = As[kk + lr][wi * 32 + lc];
-      const double a1 = As[kk + lr][wi * 32 + 16 + lc];
-      const double b0 = Bs[kk + lr][wj * 32 + lc];
-      const double b1 = Bs[kk + lr][wj * 32 + 16 + lc];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = static_cast<double>(Ab[kk + lr][wi * 64 + q * 16 + lc]);
+        b[q] = static_cast<double>(Bb[kk + lr][wj * 64 + q * 16 + lc]);
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
     }
+    if (WITHV) {
+      const int c = threadIdx.x % kGT, h = threadIdx.x / kGT;
+#pragma unroll 4
+      for (int r = h; r < kGK; r += kGThreads / kGT) vacc += static_cast<double>(Ab[r][c]) * vs[buf][r];
+      if (threadIdx.x < kGK) vv += vs[buf][threadIdx.x] * vs[buf][threadIdx.x];
+    }
+    if (more) {
+      gram_stash<TS, DIAG>(As[buf ^ 1], Bs[DIAG ? 0 : (buf ^ 1)], ra, rb, ia, ib);
+      if (WITHV && threadIdx.x < kGK) vs[buf ^ 1][threadIdx.x] = rv;
+    }
+    __syncthreads();
+    buf ^= 1;
   }
   // Output layout of v_mfma_f64_16x16x4f64: element e of lane l holds row
   // (l / 16) + 4 e, column l % 16 of the 16 x 16 block (checked on gfx950).
-  double* out = partial + (static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x) * (kGT * kGT);
+  double* out = partial + (static_cast<size_t>(blockIdx.y) * P + pair) * (kGT * kGT);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = wi * 32 + a * 16 + lr + 4 * e;
-        const int colx = wj * 32 + b * 16 + lc;
-        out[row * kGT + colx] = acc[a][b][e];
+        const int row = wi * 64 + x * 16 + lr + 4 * e;
+        const int colx = wj * 64 + y * 16 + lc;
+        out[row * kGT + colx] = acc[x][y][e];
       }
+  if (WITHV) {
+    const int c = threadIdx.x % kGT, h = threadIdx.x / kGT;
+    if (h == 1) vred[c] = vacc;
+    __syncthreads();
+    if (h == 0) partial_v[(static_cast<size_t>(blockIdx.y) * T + ti) * kGT + c] = vacc + vred[c];
+    if (ti == 0 && threadIdx.x < kWave) {  // the first wave holds the kGK row sums of v^T v
+      vv = wave_sum(vv);
+      if (threadIdx.x == 0) partial_v[static_cast<size_t>(gridDim.y) * T * kGT + blockIdx.y] = vv;
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ partial, int P, int S, int T, int dd,
-                                                     double* __restrict__ G) {
+// G[i][j] (both triangles) from the partial tiles (diagonal tiles summed over
+// Sd splits, the others over So); column d from the partial M^T v when v was
+// given.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ partial,
+                                                     const double* __restrict__ partial_v, int P, int Sd, int So,
+                                                     int T, int d, int with_v, double* __restrict__ G) {
+  const int dd = d + with_v;
   const int p = blockIdx.x;
+  if (p == P) {  // the M^T v column and v^T v
+    if (!with_v) return;
+    for (int i = blockIdx.y * 256 + threadIdx.x; i < T * kGT; i += gridDim.y * 256) {
+      if (i >= d) continue;
+      double s = 0.0;
+      for (int sp = 0; sp < Sd; ++sp) s += partial_v[static_cast<size_t>(sp) * T * kGT + i];
+      G[static_cast<size_t>(i) * dd + d] = s;
+      G[static_cast<size_t>(d) * dd + i] = s;
+    }
+    if (blockIdx.y == 0 && threadIdx.x == 0) {
+      double s = 0.0;
+      for (int sp = 0; sp < Sd; ++sp) s += partial_v[static_cast<size_t>(Sd) * T * kGT + sp];
+      G[static_cast<size_t>(d) * dd + d] = s;
+    }
+    return;
+  }
+  int ti, tj;
+  tile_of(p, T, ti, tj);
+  const int S = ti == tj ? Sd : So;
   const int idx = blockIdx.y * 256 + threadIdx.x;
   double s = 0.0;
   for (int sp = 0; sp < S; ++sp) s += partial[(static_cast<size_t>(sp) * P + p) * (kGT * kGT) + idx];
-  int ti, tj;
-  tile_of(p, T, ti, tj);
   const int i = ti * kGT + idx / kGT, j = tj * kGT + idx % kGT;
   // diagonal tiles hold both (i, j) and (j, i): write each pair once
-  if (i < dd && j < dd && (ti != tj || i <= j)) {
+  if (i < d && j < d && (ti != tj || i <= j)) {
     G[static_cast<size_t>(i) * dd + j] = s;
     G[static_cast<size_t>(j) * dd + i] = s;
   }
@@ -354,59 +516,99 @@ __global__ void k_f64_to_f32(const double* __restrict__ in, float* __restrict__ 
 }
 
 struct GramShape {
-  int T, P, S;
-  int64_t rps;
+  int T, P;
+  int Sd, So;            // row splits of the diagonal / off-diagonal tiles
+  int64_t rpd, rpo;      // rows per split
 };
 
-GramShape gram_shape(int64_t m, int64_t dd) {
+// Tiles of the d x d Gram (upper triangle of tile pairs) and row splits: each
+// of the two launches (diagonal tiles, off-diagonal pairs) has about one block
+// per compute unit, each taking a run of whole kGK-row strips.
+GramShape gram_shape(int64_t m, int64_t d) {
   GramShape g;
-  g.T = static_cast<int>(div_up(dd, kGT));
+  g.T = static_cast<int>(div_up(d > 0 ? d : 1, kGT));
   g.P = g.T * (g.T + 1) / 2;
-  int64_t S = div_up(2048, g.P);
-  const int64_t max_split = div_up(m, 256);
-  if (S > max_split) S = max_split;
-  if (S < 1) S = 1;
-  g.rps = div_up(div_up(m, S), kGK) * kGK;
-  g.S = static_cast<int>(div_up(m, g.rps));
-  if (g.S < 1) g.S = 1;
+  const int64_t max_split = div_up(m > 0 ? m : 1, 4 * kGK);
+  auto split = [&](int tiles, int& S, int64_t& rps) {
+    int64_t x = tiles > 0 ? 256 / tiles : 1;
+    if (x > max_split) x = max_split;
+    if (x < 1) x = 1;
+    rps = div_up(div_up(m > 0 ? m : 1, x), kGK) * kGK;
+    S = static_cast<int>(div_up(m > 0 ? m : 1, rps));
+  };
+  split(g.T, g.Sd, g.rpd);
+  split(g.P - g.T, g.So, g.rpo);
+  if (g.P == g.T) g.So = 0;
   return g;
+}
+
+size_t gram_bytes(const GramShape& g) {
+  const int S = g.Sd > g.So ? g.Sd : g.So;
+  return (static_cast<size_t>(S) * g.P * kGT * kGT + static_cast<size_t>(g.Sd) * (g.T * kGT + 1)) * sizeof(double) +
+         512;
 }
 
 }  // namespace
 
 size_t gram_ws_bytes(int64_t m, int64_t dd) {
-  const GramShape g = gram_shape(m, dd);
-  return static_cast<size_t>(g.S) * g.P * kGT * kGT * sizeof(double) + 256;
+  // dd = d (no v) or d + 1 (with v): size for either reading of dd
+  size_t need = 0;
+  for (int64_t d : {dd, dd - 1}) {
+    if (d < 1) continue;
+    const size_t b = gram_bytes(gram_shape(m, d));
+    need = b > need ? b : need;
+  }
+  return need;
 }
 
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,
                  double* G, void* ws, size_t ws_bytes, hipStream_t s) {
-  const int64_t dd = d + (v ? 1 : 0);
-  const GramShape g = gram_shape(m, dd);
-  if (ws_bytes < gram_ws_bytes(m, dd) || ws == nullptr) {
+  const GramShape g = gram_shape(m, d);
+  if (ws_bytes < gram_bytes(g) || ws == nullptr) {
     set_error("gram workspace too small");
     return SKLS_ERR_WORKSPACE;
   }
-  double* partial = static_cast<double*>(ws);
+  Arena ar(ws, ws_bytes);
+  const int S = g.Sd > g.So ? g.Sd : g.So;
+  double* partial = ar.take<double>(static_cast<size_t>(S) * g.P * kGT * kGT);
+  double* partial_v = ar.take<double>(static_cast<size_t>(g.Sd) * (g.T * kGT + 1));  // M^T v parts, then v^T v parts
   const int v_f64 = v_dtype == SKLS_F64 ? 1 : 0;
+  const int di = static_cast<int>(d);
   PhaseTimer pt("gram", s);
-  auto launch = [&](auto tag) -> int32_t {
+  auto launch = [&](auto tag, auto vec) -> int32_t {
     using TI = decltype(tag);
-    hipLaunchKernelGGL((k_gram_partial<TI>), dim3(g.P, g.S), dim3(kGThreads), 0, s, static_cast<const TI*>(M), ld,
-                       v, v_f64, m, static_cast<int>(d), g.T, g.rps, partial);
+    constexpr bool VEC = decltype(vec)::value;
+    const TI* Mt = static_cast<const TI*>(M);
+    if (v != nullptr) {
+      hipLaunchKernelGGL((k_gram_partial<TI, VEC, true, true>), dim3(g.T, g.Sd), dim3(kGThreads), 0, s, Mt, ld, v,
+                         v_f64, m, di, g.T, g.P, g.rpd, partial, partial_v);
+    } else {
+      hipLaunchKernelGGL((k_gram_partial<TI, VEC, true, false>), dim3(g.T, g.Sd), dim3(kGThreads), 0, s, Mt, ld, v,
+                         v_f64, m, di, g.T, g.P, g.rpd, partial, partial_v);
+    }
     SKLS_CHECK_LAUNCH();
+    if (g.So > 0) {
+      hipLaunchKernelGGL((k_gram_partial<TI, VEC, false, false>), dim3(g.P - g.T, g.So), dim3(kGThreads), 0, s, Mt,
+                         ld, v, v_f64, m, di, g.T, g.P, g.rpo, partial, partial_v);
+      SKLS_CHECK_LAUNCH();
+    }
     return SKLS_OK;
+  };
+  auto with_vec = [&](auto tag) -> int32_t {
+    using TI = decltype(tag);
+    const bool vec = (reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * sizeof(TI)) % 16 == 0) && (d % 4 == 0);
+    return vec ? launch(tag, std::true_type{}) : launch(tag, std::false_type{});
   };
   int32_t st;
   switch (dtype) {
-    case SKLS_F64: st = launch(double{}); break;
-    case SKLS_F32: st = launch(float{}); break;
-    case SKLS_BF16: st = launch(bf16_t{}); break;
+    case SKLS_F64: st = with_vec(double{}); break;
+    case SKLS_F32: st = with_vec(float{}); break;
+    case SKLS_BF16: st = with_vec(bf16_t{}); break;
     default: set_error("gram: bad dtype"); return SKLS_ERR_DTYPE;
   }
   if (st != SKLS_OK) return st;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(g.P, kGT * kGT / 256), dim3(256), 0, s, partial, g.P, g.S, g.T,
-                     static_cast<int>(dd), G);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(g.P + 1, kGT * kGT / 256), dim3(256), 0, s, partial, partial_v, g.P, g.Sd,
+                     g.So, g.T, di, v ? 1 : 0, G);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }

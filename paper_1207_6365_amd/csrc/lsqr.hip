@@ -61,18 +61,22 @@ struct Ld<bf16_t, TA, 8> {
   }
 };
 
-template <typename TA, typename TU>
-__device__ __forceinline__ TA load_z(const void* Z, int z_is_b, int64_t r) {
-  return z_is_b ? static_cast<TA>(static_cast<const double*>(Z)[r]) : static_cast<TA>(static_cast<const TU*>(Z)[r]);
+template <typename TA, typename TU, bool ZB>
+__device__ __forceinline__ TA load_z(const void* Z, int64_t r) {
+  if (ZB) return static_cast<TA>(static_cast<const double*>(Z)[r]);
+  return static_cast<TA>(static_cast<const TU*>(Z)[r]);
 }
 
 // Dense row-major A.  Lane `lane` owns columns q*64*V + lane*V + [0, V) for
 // q < NC; each wavefront streams a contiguous range of rows, kRows at a time.
-template <typename TV, typename TA, typename TU, int V, int NC>
+// Lanes past column d load column 0 instead (their p is 0 and their A^T U is
+// never stored), so every load of a step is unconditional and in flight
+// together.  ZB: Z is the float64 b (else U).
+template <typename TV, typename TA, typename TU, int V, int NC, bool ZB>
 __global__ __launch_bounds__(kPassThreads) void k_pass_dense(int64_t n, int d, int64_t ld, const TV* __restrict__ A,
                                                              const double* __restrict__ p,
                                                              const double* __restrict__ coefp, const void* Z,
-                                                             int z_is_b, TU* U, double* __restrict__ partial) {
+                                                             TU* U, double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
   TA* red = reinterpret_cast<TA*>(smem);  // [kPassWaves][d]
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -94,19 +98,18 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_dense(int64_t n, int d, i
   const int64_t nw = static_cast<int64_t>(gridDim.x) * kPassWaves;
   const int64_t r0 = gw * n / nw, r1 = (gw + 1) * n / nw;
   int64_t r = r0;
+  int cl[NC];  // this lane's first column of each slice (0 past d)
+#pragma unroll
+  for (int q = 0; q < NC; ++q) cl[q] = live[q] ? q * kWave * V + lane * V : 0;
   for (; r + kRows <= r1; r += kRows) {
     TA x[kRows][NC][V];
+    TA z[kRows];
 #pragma unroll
-    for (int j = 0; j < kRows; ++j)
+    for (int j = 0; j < kRows; ++j) {
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        if (live[q]) {
-          Ld<TV, TA, V>::get(A + static_cast<size_t>(r + j) * ld + q * kWave * V + lane * V, x[j][q]);
-        } else {
-#pragma unroll
-          for (int k = 0; k < V; ++k) x[j][q][k] = TA(0);
-        }
-      }
+      for (int q = 0; q < NC; ++q) Ld<TV, TA, V>::get(A + static_cast<size_t>(r + j) * ld + cl[q], x[j][q]);
+      z[j] = load_z<TA, TU, ZB>(Z, r + j);
+    }
     TA dot[kRows];
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
@@ -118,10 +121,10 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_dense(int64_t n, int d, i
       dot[j] = s;
     }
 #pragma unroll
-    for (int j = 0; j < kRows; ++j) dot[j] = wave_sum(dot[j]);
+    for (int j = 0; j < kRows; ++j) dot[j] = wave_total(dot[j]);
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
-      const TA u = dot[j] + coef * load_z<TA, TU>(Z, z_is_b, r + j);
+      const TA u = dot[j] + coef * z[j];
       if (lane == 0) U[r + j] = static_cast<TU>(u);
       un += u * u;
 #pragma unroll
@@ -135,17 +138,12 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_dense(int64_t n, int d, i
     TA s = TA(0);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      if (live[q]) {
-        Ld<TV, TA, V>::get(A + static_cast<size_t>(r) * ld + q * kWave * V + lane * V, x[q]);
-      } else {
-#pragma unroll
-        for (int k = 0; k < V; ++k) x[q][k] = TA(0);
-      }
+      Ld<TV, TA, V>::get(A + static_cast<size_t>(r) * ld + cl[q], x[q]);
 #pragma unroll
       for (int k = 0; k < V; ++k) s += pv[q][k] * x[q][k];
     }
-    s = wave_sum(s);
-    const TA u = s + coef * load_z<TA, TU>(Z, z_is_b, r);
+    s = wave_total(s);
+    const TA u = s + coef * load_z<TA, TU, ZB>(Z, r);
     if (lane == 0) U[r] = static_cast<TU>(u);
     un += u * u;
 #pragma unroll
@@ -175,13 +173,14 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_dense(int64_t n, int d, i
   }
 }
 
-// CSR A: a group of L lanes per row; A^T U_new accumulated with LDS atomics.
-template <typename TV, typename TR, typename TA, typename TU, int L>
+// CSR A: a group of L lanes per row; A^T U_new accumulated in LDS with
+// compare-and-swap adds.  ZB: Z is the float64 b (else U).
+template <typename TV, typename TR, typename TA, typename TU, int L, bool ZB>
 __global__ __launch_bounds__(kPassThreads) void k_pass_csr(int64_t n, int d, const TR* __restrict__ row_ptr,
                                                            const int32_t* __restrict__ col, const TV* __restrict__ val,
                                                            const double* __restrict__ p,
-                                                           const double* __restrict__ coefp, const void* Z,
-                                                           int z_is_b, TU* U, double* __restrict__ partial) {
+                                                           const double* __restrict__ coefp, const void* Z, TU* U,
+                                                           double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
   TA* sp = reinterpret_cast<TA*>(smem);
   TA* gacc = sp + d;
@@ -202,12 +201,12 @@ __global__ __launch_bounds__(kPassThreads) void k_pass_csr(int64_t n, int d, con
     for (TR k = a + sub; k < e; k += L) s += load_as<TA>(val, static_cast<size_t>(k)) * sp[col[k]];
 #pragma unroll
     for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-    const TA u = s + coef * load_z<TA, TU>(Z, z_is_b, r);
+    const TA u = s + coef * load_z<TA, TU, ZB>(Z, r);
     if (sub == 0) {
       U[r] = static_cast<TU>(u);
       un += u * u;
     }
-    for (TR k = a + sub; k < e; k += L) atomicAdd(&gacc[col[k]], u * load_as<TA>(val, static_cast<size_t>(k)));
+    for (TR k = a + sub; k < e; k += L) lds_add1(gacc, col[k], u * load_as<TA>(val, static_cast<size_t>(k)));
   }
   const TA tot = block_sum(un, scratch);
   __syncthreads();
@@ -275,9 +274,14 @@ int32_t launch_pass_dense(const PassArgs& a, hipStream_t s) {
     }
     return with_nc(nc, [&](auto ncc) -> int32_t {
       constexpr int NC = decltype(ncc)::value;
-      hipLaunchKernelGGL((k_pass_dense<TV, TA, TU, V, NC>), dim3(a.nblk), dim3(kPassThreads), lds, s, A.n, d, A.ld,
-                         static_cast<const TV*>(A.val), a.p, a.coef, a.Z, a.z_is_b, static_cast<TU*>(a.U),
-                         a.partial);
+      if (a.z_is_b) {
+        hipLaunchKernelGGL((k_pass_dense<TV, TA, TU, V, NC, true>), dim3(a.nblk), dim3(kPassThreads), lds, s, A.n, d,
+                           A.ld, static_cast<const TV*>(A.val), a.p, a.coef, a.Z, static_cast<TU*>(a.U), a.partial);
+      } else {
+        hipLaunchKernelGGL((k_pass_dense<TV, TA, TU, V, NC, false>), dim3(a.nblk), dim3(kPassThreads), lds, s, A.n,
+                           d, A.ld, static_cast<const TV*>(A.val), a.p, a.coef, a.Z, static_cast<TU*>(a.U),
+                           a.partial);
+      }
       SKLS_CHECK_LAUNCH();
       return SKLS_OK;
     });
@@ -299,9 +303,15 @@ int32_t launch_pass_csr(const PassArgs& a, hipStream_t s) {
   auto go = [&](auto tr, auto lc) -> int32_t {
     using TR = decltype(tr);
     constexpr int L = decltype(lc)::value;
-    hipLaunchKernelGGL((k_pass_csr<TV, TR, TA, TU, L>), dim3(a.nblk), dim3(kPassThreads), lds, s, A.n, d,
-                       static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), a.p, a.coef, a.Z,
-                       a.z_is_b, static_cast<TU*>(a.U), a.partial);
+    if (a.z_is_b) {
+      hipLaunchKernelGGL((k_pass_csr<TV, TR, TA, TU, L, true>), dim3(a.nblk), dim3(kPassThreads), lds, s, A.n, d,
+                         static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), a.p, a.coef,
+                         a.Z, static_cast<TU*>(a.U), a.partial);
+    } else {
+      hipLaunchKernelGGL((k_pass_csr<TV, TR, TA, TU, L, false>), dim3(a.nblk), dim3(kPassThreads), lds, s, A.n, d,
+                         static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), a.p, a.coef,
+                         a.Z, static_cast<TU*>(a.U), a.partial);
+    }
     SKLS_CHECK_LAUNCH();
     return SKLS_OK;
   };

@@ -573,59 +573,6 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
   return x;
 }
 
-// Floating-point adds into LDS as compare-and-swap loops.  gfx950 executes
-// ds_add_f32 / ds_add_f64 at a small fraction of the rate of its integer LDS
-// atomics (about 190 cycles per wave64 instruction per compute unit against
-// 7 for ds_add_u32, measured), while ds_cmpst runs at integer speed; a lane
-// whose swap lost to another lane or wave retries with the value it saw.
-template <typename T>
-struct FBits;
-template <>
-struct FBits<float> {
-  using U = uint32_t;
-  __device__ __forceinline__ static U to(float x) { return __float_as_uint(x); }
-  __device__ __forceinline__ static float from(U u) { return __uint_as_float(u); }
-};
-template <>
-struct FBits<double> {
-  using U = unsigned long long;
-  __device__ __forceinline__ static U to(double x) { return static_cast<U>(__double_as_longlong(x)); }
-  __device__ __forceinline__ static double from(U u) { return __longlong_as_double(static_cast<long long>(u)); }
-};
-
-// acc[a[k]] += v[k] for the k < N whose bit is set in `mask` (elements of
-// one lane may alias: their swaps are ordered and a stale one retries).
-template <typename TO, int N>
-__device__ __forceinline__ void lds_add(TO* acc, const int32_t (&a)[N], const TO (&v)[N],
-                                        uint32_t mask = 0xffffffffu) {
-  static_assert(N <= 32, "pending mask is 32 bits");
-  using B = FBits<TO>;
-  using U = typename B::U;
-  U* q = reinterpret_cast<U*>(acc);
-  U old[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) old[k] = q[a[k]];
-  uint32_t pend = mask & (N == 32 ? 0xffffffffu : ((1u << N) - 1u));
-  while (pend != 0) {
-    U got[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-      got[k] = ((pend >> k) & 1u) ? atomicCAS(q + a[k], old[k], B::to(B::from(old[k]) + v[k])) : old[k];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      if (got[k] == old[k]) pend &= ~(1u << k);
-      old[k] = got[k];
-    }
-  }
-}
-
-template <typename TO>
-__device__ __forceinline__ void lds_add1(TO* acc, int32_t a, TO v) {
-  const int32_t aa[1] = {a};
-  const TO vv[1] = {v};
-  lds_add<TO, 1>(acc, aa, vv);
-}
-
 // Column indices and values of E consecutive nonzeros.
 template <typename TV, typename TO, int E>
 struct Group {
