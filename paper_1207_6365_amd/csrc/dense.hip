@@ -283,55 +283,94 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 // block row to its right, then update the trailing upper triangle.
 constexpr int kCB = 64;
 
+// x = r^{-1} for the kb x kb upper triangle r (kb <= kCB), in LDS, by
+// doubling: with the inverses of two neighbouring diagonal blocks known, the
+// block above the diagonal between them is -X11 (R12 X22).  `t` holds the
+// products R12 X22 of one level (at most kCB * kCB / 4 values).  The whole
+// block of threads takes part; x is zero below the diagonal.
+__device__ void tri_inv_lds(const double (*r)[kCB + 1], double (*x)[kCB + 1], double* t, int kb) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < kCB * kCB; e += nt) {
+    const int i = e / kCB, j = e % kCB;
+    x[i][j] = (i == j && i < kb) ? 1.0 / r[i][i] : 0.0;
+  }
+  __syncthreads();
+  for (int sb = 0; (1 << sb) < kb; ++sb) {
+    const int b = 1 << sb, mb = b - 1;
+    const int nm = (kb + 2 * b - 1) >> (sb + 1);  // merges (the last may lack a right block)
+    // t_m[i][j] = sum_l r[o1 + i][o2 + l] x[o2 + l][o2 + j], l <= j
+    for (int e = tid; e < (nm << (2 * sb)); e += nt) {
+      const int m = e >> (2 * sb), i = (e >> sb) & mb, j = e & mb;
+      const int o1 = (2 * m) << sb, o2 = o1 + b;
+      if (o2 + j >= kb) continue;
+      double s0 = 0.0, s1 = 0.0;
+      int l = 0;
+      for (; l + 1 <= j; l += 2) {
+        s0 += r[o1 + i][o2 + l] * x[o2 + l][o2 + j];
+        s1 += r[o1 + i][o2 + l + 1] * x[o2 + l + 1][o2 + j];
+      }
+      if (l <= j) s0 += r[o1 + i][o2 + l] * x[o2 + l][o2 + j];
+      t[e] = s0 + s1;
+    }
+    __syncthreads();
+    // x[o1 + i][o2 + j] = -sum_l x[o1 + i][o1 + l] t_m[l][j], l >= i
+    for (int e = tid; e < (nm << (2 * sb)); e += nt) {
+      const int m = e >> (2 * sb), i = (e >> sb) & mb, j = e & mb;
+      const int o1 = (2 * m) << sb, o2 = o1 + b;
+      if (o2 + j >= kb) continue;
+      const double* tm = t + (m << (2 * sb));
+      double s0 = 0.0, s1 = 0.0;
+      int l = i;
+      for (; l + 1 < b; l += 2) {
+        s0 += x[o1 + i][o1 + l] * tm[(l << sb) + j];
+        s1 += x[o1 + i][o1 + l + 1] * tm[((l + 1) << sb) + j];
+      }
+      if (l < b) s0 += x[o1 + i][o1 + l] * tm[(l << sb) + j];
+      x[o1 + i][o2 + j] = -(s0 + s1);
+    }
+    __syncthreads();
+  }
+}
+
 // W[K:K+kb, K:K+kb] -> R_KK (in place) and Kinv = R_KK^{-1} (kb x kb, ld kCB).
-// LDS holds R_KK in the upper triangle of `a`; the inverse is built column by
-// column (one thread per column) in the strict lower triangle, transposed,
-// with its diagonal in the spare column kCB.
+// Right-looking factorisation in LDS with one barrier per column: every
+// thread reads the pivot, the row of R is written to its own array while
+// the trailing triangle is updated from the unscaled row.
 __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ W, int d, int K, double* __restrict__ Kinv,
                                                    int32_t* __restrict__ bad) {
-  __shared__ double a[kCB][kCB + 1];
+  __shared__ double a[kCB][kCB + 1];   // working copy, then the inverse
+  __shared__ double rr[kCB][kCB + 1];  // R_KK
+  __shared__ double t[kCB * kCB / 4];
   const int kb = (d - K) < kCB ? (d - K) : kCB;
   const int tid = threadIdx.x;
   for (int e = tid; e < kCB * (kCB + 1); e += 256) {
     const int i = e / (kCB + 1), j = e % (kCB + 1);
     a[i][j] = (i < kb && j < kb && j >= i) ? W[static_cast<size_t>(K + i) * d + K + j] : 0.0;
+    rr[i][j] = 0.0;
   }
   __syncthreads();
+  // thread (g, j): column j of the block, rows g, g + 4, ... of each update
+  const int j = tid & (kCB - 1), g = tid >> 6;
   for (int k = 0; k < kb; ++k) {
-    if (tid == 0) {
-      double piv = a[k][k];
-      if (!(piv > 0.0)) {
-        bad[0] = 1;
-        piv = 1.0;
-      }
-      a[k][k] = sqrt(piv);
+    double piv = a[k][k];
+    if (!(piv > 0.0)) {
+      if (tid == 0) bad[0] = 1;
+      piv = 1.0;
     }
-    __syncthreads();
-    const double r = a[k][k];
-    for (int j = k + 1 + tid; j < kb; j += 256) a[k][j] /= r;
-    __syncthreads();
-    const int nrem = kb - k - 1;
-    for (int e = tid; e < nrem * nrem; e += 256) {
-      const int i = k + 1 + e / nrem, j = k + 1 + e % nrem;
-      if (j >= i) a[i][j] -= a[k][i] * a[k][j];
+    const double rk = sqrt(piv);
+    if (j >= k && j < kb) {
+      const double akj = a[k][j];
+      if (g == 0) rr[k][j] = j == k ? rk : akj / rk;
+      const double f = akj / piv;
+      for (int i = k + 1 + g; i <= j; i += 4) a[i][j] -= a[k][i] * f;
     }
     __syncthreads();
   }
-  if (tid < kb) {
-    const int j = tid;  // column j of the inverse: inv[i][j] kept at a[j][i] (i < j), inv[j][j] at a[j][kCB]
-    a[j][kCB] = 1.0 / a[j][j];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = a[i][j] * a[j][kCB];
-      for (int l = i + 1; l < j; ++l) s += a[i][l] * a[j][l];
-      a[j][i] = -s / a[i][i];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < kb * kb; e += 256) {
-    const int i = e / kb, j = e % kb;
-    if (j >= i) W[static_cast<size_t>(K + i) * d + K + j] = a[i][j];
-    Kinv[i * kCB + j] = (i == j) ? a[j][kCB] : (i < j ? a[j][i] : 0.0);
-  }
+  for (int i = g; i < kb; i += 4)
+    if (j >= i && j < kb) W[static_cast<size_t>(K + i) * d + K + j] = rr[i][j];
+  tri_inv_lds(rr, a, t, kb);
+  for (int i = g; i < kb; i += 4)
+    if (j < kb) Kinv[i * kCB + j] = a[i][j];
 }
 
 constexpr int kCL = 32;  // rows of the panels staged per step
@@ -462,26 +501,108 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Column j of R^{-1} by back substitution, one wavefront per column.
-__global__ __launch_bounds__(kWave) void k_trinv(const double* __restrict__ R, int d, double* __restrict__ Rinv,
-                                                 double* __restrict__ RinvT) {
-  extern __shared__ double x[];
-  const int lane = threadIdx.x;
-  const int j = blockIdx.x;
-  if (lane == 0) x[j] = 1.0 / R[static_cast<size_t>(j) * d + j];
-  wave_sync();
-  for (int i = j - 1; i >= 0; --i) {
-    double s = 0.0;
-    const double* row = R + static_cast<size_t>(i) * d;
-    for (int k = i + 1 + lane; k <= j; k += kWave) s += row[k] * x[k];
-    s = wave_sum(s);
-    if (lane == 0) x[i] = -s / row[i];
-    wave_sync();
+// Inverses of the diagonal kCB x kCB blocks of R, one block of threads per
+// diagonal block, written into Rinv; the rest of Rinv is zeroed here.
+__global__ __launch_bounds__(256) void k_trinv_diag(const double* __restrict__ R, int d, double* __restrict__ Rinv) {
+  __shared__ double rr[kCB][kCB + 1];
+  __shared__ double x[kCB][kCB + 1];
+  __shared__ double t[kCB * kCB / 4];
+  const int K = blockIdx.x * kCB;
+  const int kb = (d - K) < kCB ? (d - K) : kCB;
+  for (int e = threadIdx.x; e < kCB * (kCB + 1); e += 256) {
+    const int i = e / (kCB + 1), j = e % (kCB + 1);
+    rr[i][j] = (i < kb && j < kb && j >= i) ? R[static_cast<size_t>(K + i) * d + K + j] : 0.0;
   }
-  for (int i = lane; i < d; i += kWave) {
-    const double v = i <= j ? x[i] : 0.0;
-    Rinv[static_cast<size_t>(i) * d + j] = v;
-    RinvT[static_cast<size_t>(j) * d + i] = v;
+  __syncthreads();
+  tri_inv_lds(rr, x, t, kb);
+  // this block writes rows K .. K + kb of Rinv: x on the diagonal block, zero elsewhere
+  for (int64_t e = threadIdx.x; e < static_cast<int64_t>(kb) * d; e += 256) {
+    const int i = static_cast<int>(e / d), j = static_cast<int>(e % d);
+    Rinv[static_cast<size_t>(K + i) * d + j] = (j >= K && j < K + kb) ? x[i][j - K] : 0.0;
+  }
+}
+
+// One 64 x 64 tile of C = alpha A B (row-major, M x N, inner dimension K) on
+// the float64 matrix cores; A, B, C point at the sub-blocks.
+__device__ void gemm_tile64(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+                            double* __restrict__ C, int ldc, int M, int N, int K, int i0, int j0, double alpha,
+                            double (*As)[64], double (*Bs)[64]) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int wi = wv >> 1, wj = wv & 1;
+  const int lr = lane >> 4, lc = lane & 15;
+  d4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int kk = e / 64, c = e % 64;
+      As[kk][c] = (i0 + c < M && k0 + kk < K) ? A[static_cast<size_t>(i0 + c) * lda + k0 + kk] : 0.0;
+      Bs[kk][c] = (k0 + kk < K && j0 + c < N) ? B[static_cast<size_t>(k0 + kk) * ldb + j0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const double a0 = As[kk + lr][wi * 32 + lc], a1 = As[kk + lr][wi * 32 + 16 + lc];
+      const double b0 = Bs[kk + lr][wj * 32 + lc], b1 = Bs[kk + lr][wj * 32 + 16 + lc];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+  // element e of lane l: row (l / 16) + 4 e, column l % 16 of each 16 x 16 block
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = i0 + wi * 32 + a * 16 + lr + 4 * e, col = j0 + wj * 32 + b * 16 + lc;
+        if (row < M && col < N) C[static_cast<size_t>(row) * ldc + col] = alpha * acc[a][b][e];
+      }
+}
+
+// One level of the doubling for R^{-1}: for merge z of blocks of size b,
+// o1 = 2 z b, o2 = o1 + b, o3 = min(o2 + b, d):
+//   STEP 0: T[o1:o2, o2:o3] = R[o1:o2, o2:o3] Rinv[o2:o3, o2:o3]
+//   STEP 1: Rinv[o1:o2, o2:o3] = -Rinv[o1:o2, o1:o2] T[o1:o2, o2:o3]
+// (T is a d x d scratch used at the same positions).  Tiles of 64 x 64 over
+// blockIdx.x, merges over blockIdx.y.
+template <int STEP>
+__global__ __launch_bounds__(256) void k_trinv_merge(const double* __restrict__ R, double* __restrict__ Rinv,
+                                                     double* __restrict__ T, int d, int b) {
+  __shared__ double As[16][64], Bs[16][64];
+  const int o1 = 2 * blockIdx.y * b, o2 = o1 + b;
+  if (o2 >= d) return;
+  const int o3 = (o2 + b) < d ? o2 + b : d;
+  const int b2 = o3 - o2;
+  const int tn = (b2 + 63) / 64;
+  const int i0 = (blockIdx.x / tn) * 64, j0 = (blockIdx.x % tn) * 64;
+  if (i0 >= b) return;
+  const size_t off12 = static_cast<size_t>(o1) * d + o2;
+  if (STEP == 0) {
+    gemm_tile64(R + off12, d, Rinv + static_cast<size_t>(o2) * d + o2, d, T + off12, d, b, b2, b2, i0, j0, 1.0, As,
+                Bs);
+  } else {
+    gemm_tile64(Rinv + static_cast<size_t>(o1) * d + o1, d, T + off12, d, Rinv + off12, d, b, b2, b, i0, j0, -1.0,
+                As, Bs);
+  }
+}
+
+__global__ void k_transpose(const double* __restrict__ X, int d, double* __restrict__ Y) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int i = by + k, j = bx + threadIdx.x;
+    tile[k][threadIdx.x] = (i < d && j < d) ? X[static_cast<size_t>(i) * d + j] : 0.0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int i = bx + k, j = by + threadIdx.x;
+    if (i < d && j < d) Y[static_cast<size_t>(i) * d + j] = tile[threadIdx.x][k];
   }
 }
 
@@ -646,10 +767,26 @@ int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t
   return SKLS_OK;
 }
 
+// R^{-1} by doubling over diagonal blocks: inverses of the kCB-blocks, then
+// levels b = kCB, 2 kCB, ... each merging neighbouring blocks with two
+// products on the matrix cores.  RinvT (d x d) serves as the product scratch
+// before it receives the transpose.
 int32_t run_trinv(const double* R, int64_t d, double* Rinv, double* RinvT, hipStream_t s) {
   PhaseTimer pt("trinv", s);
-  hipLaunchKernelGGL(k_trinv, dim3(static_cast<unsigned>(d)), dim3(kWave), static_cast<size_t>(d) * sizeof(double), s,
-                     R, static_cast<int>(d), Rinv, RinvT);
+  const int di = static_cast<int>(d);
+  const int nb = static_cast<int>(div_up(d, kCB));
+  hipLaunchKernelGGL(k_trinv_diag, dim3(nb), dim3(256), 0, s, R, di, Rinv);
+  SKLS_CHECK_LAUNCH();
+  for (int b = kCB; b < di; b *= 2) {
+    const unsigned merges = static_cast<unsigned>(div_up(d, 2 * static_cast<int64_t>(b)));
+    const unsigned tiles = static_cast<unsigned>(div_up(b, 64) * div_up(b, 64));
+    hipLaunchKernelGGL(k_trinv_merge<0>, dim3(tiles, merges), dim3(256), 0, s, R, Rinv, RinvT, di, b);
+    SKLS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_trinv_merge<1>, dim3(tiles, merges), dim3(256), 0, s, R, Rinv, RinvT, di, b);
+    SKLS_CHECK_LAUNCH();
+  }
+  const unsigned g = static_cast<unsigned>(div_up(d, 32));
+  hipLaunchKernelGGL(k_transpose, dim3(g, g), dim3(32, 8), 0, s, Rinv, di, RinvT);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }
