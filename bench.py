@@ -9,10 +9,12 @@ path from (A, seed) to S A inside the timed region).  Inputs are synthetic and
 already resident in device memory when timing starts.
 
 Also reported on the same JSON line: the dense float32 variant (n = 2^20),
-the bit-exact integer-valued variant, least squares on the dense heavy-row
-regression workload (n = 2^21, d = 512, t = 2^18) in the plain float64 form and
-the mixed-precision form, the roofline of the dominant kernel (measured with
-HIP events on the library's stream), and the oracle timed on the host.
+sketch-and-solve on the small sparse regression (n = 20000, d = 20), least
+squares on the dense heavy-row regression workload (n = 2^21, d = 512,
+t = 2^18) in the plain float64 form and the mixed-precision forms, leverage
+scores on the same workload, a short training run of learned sketch values,
+the roofline of the dominant kernel (measured with HIP events on the
+library's stream), and the oracle timed on the host.
 """
 
 from __future__ import annotations
@@ -219,16 +221,24 @@ def main():
                            "step_frac": dbytes / (dms * 1e-3) / HBM_PEAK}
         del Dg, D
 
-        log("integer-valued variant: bit-exact check against the oracle")
-        import oracle as O
-
-        Ai, _ = W.sketch_csr_int()
-        Aig = sk.Csr(Ai.n, Ai.d, torch.from_numpy(Ai.row_ptr32()).to(dev), torch.from_numpy(Ai.col_idx).to(dev),
-                     torch.from_numpy(Ai.val).to(dev))
-        SAi = sk.sketch(Aig, t, seed, variant=args.variant).cpu().numpy().astype(np.float64)
-        ref = O.sketch_csr(Ai.n, Ai.d, Ai.row_ptr, Ai.col_idx, Ai.val, seed, t)
-        result["integer_bit_exact"] = bool(np.array_equal(SAi, ref))
-        del Aig, Ai, SAi, ref
+        log("small sparse regression: sketch-and-solve, n=20000 d=20 4 nnz/row float64, t=4000")
+        A1, b1, _ = W.lstsq_small()
+        A1g = sk.Csr(A1.n, A1.d, torch.from_numpy(A1.row_ptr32()).to(dev), torch.from_numpy(A1.col_idx).to(dev),
+                     torch.from_numpy(A1.val).to(dev))
+        b1g = torch.from_numpy(b1).to(dev)
+        for _ in range(3):
+            x1, info1 = sk.lstsq(A1g, b1g, 4000, seed, sketch_only=True)
+        sync()
+        reps = 50
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x1, info1 = sk.lstsq(A1g, b1g, 4000, seed, sketch_only=True)
+        sync()
+        el = (time.perf_counter() - t0) / reps
+        result["lstsq_small"] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
+                                 "note": "sketch-and-solve only (no LSQR), launch-bound; parity with the oracle is "
+                                         "in the tests"}
+        del A1g, b1g
 
     # ------------------------------------------------------------ least squares
     if not args.no_lstsq:
@@ -270,6 +280,49 @@ def main():
             del A3g, b3g
             torch.cuda.empty_cache()
         result["lstsq"] = res
+
+        # leverage scores on the same heavy-row workload (float32 storage), k = 32
+        log("leverage scores: n=2^21 d=512 float32, t=2^18, k=32")
+        A3, b3, _ = W.pareto_rows(n=n3, d=d3, storage="f32")
+        A3g = torch.from_numpy(A3).to(dev)
+        del A3, b3
+        Pi2 = torch.from_numpy(np.random.default_rng(7).standard_normal((d3, 32)) / np.sqrt(32.0)).to(dev)
+        sk.leverage_scores(A3g, t3, seed, Pi2)
+        sync()
+        lib.skls_profile_enable(1)
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            sk.leverage_scores(A3g, t3, seed, Pi2)
+        sync()
+        el = (time.perf_counter() - t0) / reps
+        ph = profile_phases(sk)
+        lib.skls_profile_enable(0)
+        lc, lt = ph.get("leverage", (1, float("nan")))
+        result["leverage"] = {"ms_per_call": el * 1e3, "phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
+                              "pass_frac": (n3 * d3 * 4 + n3 * 4) / (lt / max(lc, 1) * 1e-3) / HBM_PEAK}
+        del A3g
+        torch.cuda.empty_cache()
+
+        # learned per-row values: a short training run on the GPU
+        log("learned values: n=32768 d=64 t=1024, 32 training / 8 validation / 16 test matrices")
+        from paper_1207_6365_amd import train as TR
+
+        make, _ = W.learned_family()
+        mats = [torch.from_numpy(make(m)).to(dev) for m in range(56)]
+        tr_m, va_m, te_m = mats[:32], mats[32:40], mats[40:]
+        t0 = time.perf_counter()
+        out = TR.train(tr_m, va_m, 1024, seed, steps=100, lr=1e-2, batch=8)
+        sync()
+        train_s = time.perf_counter() - t0
+        grams, norms, ws5 = TR.prepare(te_m, 1024, seed)
+        plain = TR.distortions(te_m, grams, norms, 1024, seed, TR.signs(32768, 1024, seed, dev), ws=ws5)
+        learned = TR.distortions(te_m, grams, norms, 1024, seed, out.learned, ws=ws5)
+        result["learned"] = {"train_s": train_s, "steps": 100, "batch": 8, "used_learned": bool(out.used_learned),
+                             "test_distortion_plain": float(plain.mean()),
+                             "test_distortion_learned": float(learned.mean())}
+        del mats, tr_m, va_m, te_m
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ oracle on the host
     if not args.no_cpu:

@@ -62,6 +62,82 @@ __global__ __launch_bounds__(kLevThreads) void k_leverage_dense(int64_t n, int d
   }
 }
 
+// Dense A on the float32 matrix cores (v_mfma_f32_16x16x4f32).  Each
+// wavefront takes 16 rows at a time and walks the columns 4 at a time: lane l
+// loads A[row0 + l % 16][c + l / 16] straight into the A operand (the 16 rows
+// of a 64-column chunk are 4 KiB that stay in the L1 while the chunk is
+// consumed), and the next chunk's loads are issued before the current one is
+// multiplied.  T (zero-padded to d64 x 16 NB, float32) is in LDS and feeds the
+// B operands.  Output element e of lane l is row 4 (l / 16) + e, column
+// l % 16 of the 16 x 16 block; the squares of a row's NB blocks are summed
+// over the 16 lanes of a DPP row.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+constexpr int kLevChunk = 64;  // columns per chunk
+
+template <typename TV, int NB>
+__global__ __launch_bounds__(512) void k_leverage_mfma(int64_t n, int d, int64_t ld, const TV* __restrict__ A,
+                                                       const float* __restrict__ T, int k, int d64,
+                                                       float* __restrict__ scores) {
+  extern __shared__ __align__(16) float sT[];  // [d64][16 NB]
+  constexpr int KW = 16 * NB;
+  for (int e = threadIdx.x; e < d64 * KW; e += blockDim.x) {
+    const int r = e / KW, q = e % KW;
+    sT[e] = (r < d && q < k) ? T[static_cast<size_t>(r) * k + q] : 0.0f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwave = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  const int nchunk = d64 / kLevChunk;
+  for (int64_t r0 = wave * 16; r0 < n; r0 += nwave * 16) {
+    const int64_t row = r0 + li < n ? r0 + li : n - 1;  // clamped: rows past n are computed, not stored
+    const TV* arow = A + static_cast<size_t>(row) * ld;
+    f4_t acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = f4_t{0.f, 0.f, 0.f, 0.f};
+    // a[s] = A[row][c0 + 4 s + lk]: columns past d read column 0 (T is zero there)
+    float cur[kLevChunk / 4], nxt[kLevChunk / 4];
+#pragma unroll
+    for (int q = 0; q < kLevChunk / 4; ++q) {
+      const int c = 4 * q + lk;
+      cur[q] = load_as<float>(arow, static_cast<size_t>(c < d ? c : 0));
+    }
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int c0 = ch * kLevChunk;
+      if (ch + 1 < nchunk) {
+#pragma unroll
+        for (int q = 0; q < kLevChunk / 4; ++q) {
+          const int c = c0 + kLevChunk + 4 * q + lk;
+          nxt[q] = load_as<float>(arow, static_cast<size_t>(c < d ? c : 0));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kLevChunk / 4; ++q) {
+        const float* trow = sT + static_cast<size_t>(c0 + 4 * q + lk) * KW + li;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[q], trow[16 * b], acc[b], 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < kLevChunk / 4; ++q) cur[q] = nxt[q];
+    }
+    // row 4 lk + e: sum of squares over the NB blocks and the 16 lanes of the DPP row
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float v = 0.0f;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) v += acc[b][e] * acc[b][e];
+      v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));  // row_shr:1
+      v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, false));  // row_shr:2
+      v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, false));  // row_shr:4
+      v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, false));  // row_shr:8
+      const int64_t r = r0 + 4 * lk + e;
+      if (li == 15 && r < n) scores[r] = v;
+    }
+  }
+}
+
 template <typename TV, typename TR, int K>
 __global__ __launch_bounds__(kLevThreads) void k_leverage_csr(int64_t n, int d, const TR* __restrict__ row_ptr,
                                                               const int32_t* __restrict__ col,
@@ -126,6 +202,19 @@ int32_t run_leverage(const skls_matrix& A, const float* T, int32_t k, float* sco
       int64_t blocks = div_up(A.n, kLevThreads);
       if (blocks > 4096) blocks = 4096;
       if (A.layout == SKLS_DENSE) {
+        // matrix-core kernel while T fits LDS (d64 x 16 NB floats, two blocks per compute unit)
+        constexpr int NB = K <= 16 ? 1 : (K <= 32 ? 2 : 4);
+        const int d64 = static_cast<int>(div_up(d, kLevChunk) * kLevChunk);
+        const size_t tl = static_cast<size_t>(d64) * 16 * NB * sizeof(float);
+        if (tl <= 72 * 1024) {
+          SKLS_TRY(allow_lds(k_leverage_mfma<TV, NB>, tl));
+          int64_t g = div_up(A.n, 16 * 8);
+          if (g > 512) g = 512;
+          hipLaunchKernelGGL((k_leverage_mfma<TV, NB>), dim3(static_cast<unsigned>(g)), dim3(512), tl, s, A.n, d, A.ld,
+                             static_cast<const TV*>(A.val), T, k, d64, scores);
+          SKLS_CHECK_LAUNCH();
+          return SKLS_OK;
+        }
         const size_t lds = (static_cast<size_t>(d) * K + kLevThreads * kTilePitch) * sizeof(float);
         if (lds > 160 * 1024) {
           set_error("leverage: d * k too large for LDS");
