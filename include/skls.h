@@ -57,7 +57,7 @@ typedef enum {
   SKLS_ERR_NOCONV = 5,     /* the iteration did not certify within max_iter */
   SKLS_ERR_WORKSPACE = 6,  /* workspace missing or smaller than required */
   SKLS_ERR_DEVICE = 7,     /* a HIP runtime call or kernel launch failed */
-  SKLS_ERR_NOTIMPL = 8     /* operation not provided by this build */
+  SKLS_ERR_NOTIMPL = 8     /* operation not provided by the library */
 } skls_status;
 
 typedef enum { SKLS_DENSE = 0, SKLS_CSR = 1 } skls_layout;
@@ -278,7 +278,7 @@ SKLS_API int32_t skls_profile_get(int32_t index, const char** name, int64_t* lau
 
 /*
  * Rank-k approximation A ~ L D W^T (Section 8, theorem on low-rank
- * approximation).  Not provided by this build: returns SKLS_ERR_NOTIMPL.
+ * approximation).  Not provided by the library yet: returns SKLS_ERR_NOTIMPL.
  */
 SKLS_API int32_t skls_low_rank(const skls_matrix* A, int64_t k, double eps, uint64_t seed, double* L, double* D,
                       double* W, void* ws, size_t ws_bytes, void* stream);

@@ -113,7 +113,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build the HIP library first "
-            "(python -c 'import __graft_entry__ as g; g.build()')"
+            "(python paper_1207_6365_amd/build.py)"
         )
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():

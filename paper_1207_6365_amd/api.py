@@ -237,7 +237,7 @@ def adam_step(w: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor
 
 
 def low_rank(A, k: int, eps: float, seed: int):
-    """Rank-``k`` approximation (Section 8); not provided by this build."""
+    """Rank-``k`` approximation (Section 8); not provided by the library yet."""
     m, device = _matrix(A)
     st = lib().skls_low_rank(ctypes.byref(m), k, eps, seed & 0xFFFFFFFFFFFFFFFF, None, None, None, None, 0,
                              _stream(device))

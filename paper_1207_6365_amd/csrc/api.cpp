@@ -705,7 +705,7 @@ int32_t skls_low_rank(const skls_matrix* A, int64_t k, double eps, uint64_t seed
   (void)ws;
   (void)ws_bytes;
   (void)stream;
-  set_error("low-rank approximation is not provided by this build");
+  set_error("low-rank approximation is not provided by the library yet");
   return SKLS_ERR_NOTIMPL;
 }
 
