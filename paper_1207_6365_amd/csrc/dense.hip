@@ -333,39 +333,66 @@ __device__ void tri_inv_lds(const double (*r)[kCB + 1], double (*x)[kCB + 1], do
 }
 
 // W[K:K+kb, K:K+kb] -> R_KK (in place) and Kinv = R_KK^{-1} (kb x kb, ld kCB).
-// Right-looking factorisation in LDS with one barrier per column: every
-// thread reads the pivot, the row of R is written to its own array while
-// the trailing triangle is updated from the unscaled row.
+// Right-looking factorisation with the trailing triangle in registers: wave
+// g, lane j holds rows g, g + 4, ..., g + 60 of column j.  Step k publishes
+// row k (double-buffered in LDS, stored by residue class of the row index so
+// that each wave reads its 16 values as 8 contiguous pairs), then every
+// thread updates its column: one barrier per column, no LDS round trip in
+// the update.
 __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ W, int d, int K, double* __restrict__ Kinv,
                                                    int32_t* __restrict__ bad) {
-  __shared__ double a[kCB][kCB + 1];   // working copy, then the inverse
+  __shared__ double a[kCB][kCB + 1];   // the inverse
   __shared__ double rr[kCB][kCB + 1];  // R_KK
   __shared__ double t[kCB * kCB / 4];
+  __shared__ __align__(16) double prow[2][4][kCB / 4 + 2];  // row k of the trailing block, [i % 4][i / 4]
   const int kb = (d - K) < kCB ? (d - K) : kCB;
   const int tid = threadIdx.x;
-  for (int e = tid; e < kCB * (kCB + 1); e += 256) {
-    const int i = e / (kCB + 1), j = e % (kCB + 1);
-    a[i][j] = (i < kb && j < kb && j >= i) ? W[static_cast<size_t>(K + i) * d + K + j] : 0.0;
-    rr[i][j] = 0.0;
-  }
-  __syncthreads();
-  // thread (g, j): column j of the block, rows g, g + 4, ... of each update
   const int j = tid & (kCB - 1), g = tid >> 6;
-  for (int k = 0; k < kb; ++k) {
-    double piv = a[k][k];
-    if (!(piv > 0.0)) {
-      if (tid == 0) bad[0] = 1;
-      piv = 1.0;
-    }
-    const double rk = sqrt(piv);
-    if (j >= k && j < kb) {
-      const double akj = a[k][j];
-      if (g == 0) rr[k][j] = j == k ? rk : akj / rk;
-      const double f = akj / piv;
-      for (int i = k + 1 + g; i <= j; i += 4) a[i][j] -= a[k][i] * f;
-    }
-    __syncthreads();
+  double c[kCB / 4];
+#pragma unroll
+  for (int q = 0; q < kCB / 4; ++q) {
+    const int i = 4 * q + g;
+    c[q] = (j < kb && i <= j) ? W[static_cast<size_t>(K + i) * d + K + j] : 0.0;
   }
+  for (int e = tid; e < kCB * (kCB + 1); e += 256) (&rr[0][0])[e] = 0.0;
+  int badk = 0;
+#pragma unroll
+  for (int qk = 0; qk < kCB / 4; ++qk) {
+#pragma unroll
+    for (int gk = 0; gk < 4; ++gk) {
+      const int k = 4 * qk + gk;
+      if (k < kb) {
+        double (*pr)[kCB / 4 + 2] = prow[k & 1];
+        if (g == gk && j >= k) pr[j & 3][j >> 2] = c[qk];
+        __syncthreads();
+        double piv = pr[gk][qk];
+        if (!(piv > 0.0)) {
+          badk = 1;
+          piv = 1.0;
+        }
+        const double rk = sqrt(piv);
+        const double ri = 1.0 / rk;
+        const double akj = j >= k ? pr[j & 3][j >> 2] : 0.0;
+        const double rkj = akj * ri;
+        if (g == 0 && j >= k && j < kb) rr[k][j] = j == k ? rk : rkj;
+        const double f = rkj * ri;
+        double rowk[kCB / 4];
+#pragma unroll
+        for (int q = 0; q < kCB / 4; q += 2) {
+          const double2 v = *reinterpret_cast<const double2*>(&pr[g][q]);
+          rowk[q] = v.x;
+          rowk[q + 1] = v.y;
+        }
+#pragma unroll
+        for (int q = 0; q < kCB / 4; ++q) {
+          const int i = 4 * q + g;
+          if (q >= qk) c[q] = (i > k && i <= j) ? c[q] - rowk[q] * f : c[q];
+        }
+      }
+    }
+  }
+  if (badk && tid == 0) bad[0] = 1;
+  __syncthreads();
   for (int i = g; i < kb; i += 4)
     if (j >= i && j < kb) W[static_cast<size_t>(K + i) * d + K + j] = rr[i][j];
   tri_inv_lds(rr, a, t, kb);
