@@ -12,8 +12,9 @@ Also reported on the same JSON line: the dense float32 variant (n = 2^20),
 sketch-and-solve on the small sparse regression (n = 20000, d = 20), least
 squares on the dense heavy-row regression workload (n = 2^21, d = 512,
 t = 2^18) in the plain float64 form and the mixed-precision forms, leverage
-scores on the same workload, a short training run of learned sketch values,
-the roofline of the dominant kernel (measured with HIP events on the
+scores on the same workload, learned sketch values trained on a family of 256
+related matrices and compared with the random signs on held-out ones, the
+roofline of the dominant kernel (measured with HIP events on the
 library's stream), and the oracle timed on the host.
 """
 
@@ -304,24 +305,70 @@ def main():
         del A3g
         torch.cuda.empty_cache()
 
-        # learned per-row values: a short training run on the GPU
-        log("learned values: n=32768 d=64 t=1024, 32 training / 8 validation / 16 test matrices")
+        # learned per-row values: the full family of 256 matrices, trained on
+        # the GPU, then compared with the random signs on held-out matrices by
+        # distortion, by the sketch-and-solve residual ratio, and by solves to
+        # a certified ratio of 1 + 1e-6 with the values as the sketch.
+        nl, tl, steps_l, batch_l = 32768, 1024, 500, 16
+        log("learned values: 256 matrices n=32768 d=64 t=1024 (160 train / 32 validation / 64 test), "
+            f"{steps_l} Adam steps, batch {batch_l}")
         from paper_1207_6365_amd import train as TR
 
         make, _ = W.learned_family()
-        mats = [torch.from_numpy(make(m)).to(dev) for m in range(56)]
-        tr_m, va_m, te_m = mats[:32], mats[32:40], mats[40:]
+        host = [make(m) for m in range(256)]
+        mats = [torch.from_numpy(a).to(dev) for a in host]
+        rhs = [torch.from_numpy(W.learned_rhs(host[m], m)).to(dev) for m in range(192, 256)]
+        del host
+        tr_m, va_m, te_m = mats[:160], mats[160:192], mats[192:]
+        sync()
         t0 = time.perf_counter()
-        out = TR.train(tr_m, va_m, 1024, seed, steps=100, lr=1e-2, batch=8)
+        out = TR.train(tr_m, va_m, tl, seed, steps=steps_l, lr=1e-2, batch=batch_l)
         sync()
         train_s = time.perf_counter() - t0
-        grams, norms, ws5 = TR.prepare(te_m, 1024, seed)
-        plain = TR.distortions(te_m, grams, norms, 1024, seed, TR.signs(32768, 1024, seed, dev), ws=ws5)
-        learned = TR.distortions(te_m, grams, norms, 1024, seed, out.learned, ws=ws5)
-        result["learned"] = {"train_s": train_s, "steps": 100, "batch": 8, "used_learned": bool(out.used_learned),
-                             "test_distortion_plain": float(plain.mean()),
-                             "test_distortion_learned": float(learned.mean())}
-        del mats, tr_m, va_m, te_m
+        grams, norms, ws5 = TR.prepare(te_m, tl, seed)
+        sgn = TR.signs(nl, tl, seed, dev)
+        plain = TR.distortions(te_m, grams, norms, tl, seed, sgn, ws=ws5)
+        learned = TR.distortions(te_m, grams, norms, tl, seed, out.learned, ws=ws5)
+        norms_a = np.array(norms)
+
+        def ratios(w):
+            # residual of the sketch-and-solve x~ (no iteration) over the optimum,
+            # the latter from a solve certified to 1 + 1e-11
+            r = []
+            for A, b in zip(te_m, rhs):
+                _, i0 = sk.lstsq(A, b, tl, seed, max_iter=0, w=w, raise_noconv=False)
+                _, i1 = sk.lstsq(A, b, tl, seed, delta=1e-11, w=w)
+                r.append(i0["resid_norm"] / i1["resid_norm"])
+            return np.array(r)
+
+        def solves(w):
+            for A, b in zip(te_m[:4], rhs[:4]):
+                sk.lstsq(A, b, tl, seed, delta=1e-6, w=w)
+            sync()
+            its, cert = [], True
+            t0 = time.perf_counter()
+            for A, b in zip(te_m, rhs):
+                _, i = sk.lstsq(A, b, tl, seed, delta=1e-6, w=w)
+                its.append(i["iterations"])
+                cert = cert and i["certified"] == 1
+            sync()
+            el = (time.perf_counter() - t0) / len(te_m)
+            return {"solves_per_s": 1.0 / el, "mean_iterations": float(np.mean(its)), "certified": cert}
+
+        rho_p, rho_l = ratios(None), ratios(out.learned)
+        result["learned"] = {
+            "matrices": {"train": 160, "validation": 32, "test": 64}, "n": nl, "d": 64, "t": tl,
+            "train_s": train_s, "steps": steps_l, "batch": batch_l, "used_learned": bool(out.used_learned),
+            "validation_distortion": {"plain": out.val_plain, "learned": out.val_learned},
+            "test_distortion": {"plain": float(plain.mean()), "learned": float(learned.mean())},
+            "test_distortion_raw": {"plain": float((plain * norms_a).mean()),
+                                    "learned": float((learned * norms_a).mean())},
+            "sketch_solve_ratio_minus_1": {"plain": float((rho_p - 1).mean()), "learned": float((rho_l - 1).mean()),
+                                           "plain_max": float((rho_p - 1).max()),
+                                           "learned_max": float((rho_l - 1).max())},
+            "lstsq_1e-6": {"plain": solves(None), "learned": solves(out.learned)},
+        }
+        del mats, tr_m, va_m, te_m, rhs
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ oracle on the host

@@ -19,6 +19,7 @@ from .gen import (  # noqa: F401
     sketch_dense,
     pareto_rows,
     learned_family,
+    learned_rhs,
     planted_lowrank_sparse,
     SKETCH_SEED_BASE,
     data_seed,

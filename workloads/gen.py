@@ -243,5 +243,14 @@ def learned_family(num: int = 256, n: int = 32768, d: int = 64, rank: int = 16,
     return make, s
 
 
+def learned_rhs(A: np.ndarray, m: int, noise: float = 0.01, seed: int | None = None) -> np.ndarray:
+    """Right-hand side ``b = A x0 + noise N(0,1)`` (float64, from the stored
+    ``A``) for matrix ``m`` of the learned-values family, ``x0 ~ N(0,1)``."""
+    base = data_seed(5, 0) if seed is None else seed
+    g = _rng(base + 100000 + m)
+    x0 = g.standard_normal(A.shape[1])
+    return A.astype(np.float64) @ x0 + noise * g.standard_normal(A.shape[0])
+
+
 def planted_lowrank_sparse(*args, **kwargs):  # pragma: no cover - later workload
     raise NotImplementedError("planted low-rank sparse workload is not generated yet")
