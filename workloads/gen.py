@@ -252,5 +252,29 @@ def learned_rhs(A: np.ndarray, m: int, noise: float = 0.01, seed: int | None = N
     return A.astype(np.float64) @ x0 + noise * g.standard_normal(A.shape[0])
 
 
-def planted_lowrank_sparse(*args, **kwargs):  # pragma: no cover - later workload
-    raise NotImplementedError("planted low-rank sparse workload is not generated yet")
+def planted_lowrank_sparse(trial: int = 0, n: int = 65536, rank: int = 32, density: float = 0.0085,
+                           noise: float = 0.01, dtype=np.float32) -> CSR:
+    """Sparse ``n x n`` matrix ``P Q^T + E``: ``P`` and ``Q`` are ``n x rank``
+    with each entry nonzero with probability ``density`` (values N(0,1)), and
+    ``E`` carries N(0, noise^2) values on the nonzero pattern of ``P Q^T``.
+
+    The default density 0.0085 gives about 10 million nonzeros at
+    ``n = 65536`` (the pattern of ``P Q^T`` is nonzero with probability
+    ``1 - (1 - density^2)^rank``).  Columns are sorted within each row.
+    """
+    import scipy.sparse as sp
+
+    g = _rng(data_seed(4, trial))
+
+    def factor():
+        mask = g.random((n, rank)) < density
+        r, c = np.nonzero(mask)
+        return sp.csr_matrix((g.standard_normal(r.size), (r, c)), shape=(n, rank))
+
+    P = factor()
+    Q = factor()
+    M = (P @ Q.T).tocsr()
+    M.sum_duplicates()
+    M.sort_indices()
+    val = M.data + noise * g.standard_normal(M.data.size)
+    return CSR(n, n, M.indptr.astype(np.int64), M.indices.astype(np.int32), val.astype(dtype))
