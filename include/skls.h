@@ -277,11 +277,69 @@ SKLS_API int32_t skls_profile_count(void);
 SKLS_API int32_t skls_profile_get(int32_t index, const char** name, int64_t* launches, double* total_ms);
 
 /*
- * Rank-k approximation A ~ L D W^T (Section 8, theorem on low-rank
- * approximation).  Not provided by the library yet: returns SKLS_ERR_NOTIMPL.
+ * Rank-k approximation A ~ L diag(D) W^T (Section 8, theorem on low-rank
+ * approximation), in the simplified form of the Section 10 experiments:
+ *  1. Y = A R^T for R^ a t_r x m sparse embedding of the columns of A (h and
+ *     the signs from the SplitMix64 stream `seed`, as for the rows in
+ *     skls_sketch); U = an orthonormal basis of the column space of Y;
+ *  2. S: t_s rows of the n drawn independently with replacement with
+ *     probabilities proportional to the leverage scores of Y (Section 6: the
+ *     squared row norms of Y R_Y^{-1} Pi2, R_Y the triangular factor of Y and
+ *     Pi2 a t_r x k_g matrix of signs / sqrt(k_g), bit 0 of outputs
+ *     r * k_g + c of the stream seed ^ 0x6C65766572616765), each drawn row
+ *     scaled by 1 / sqrt(t_s p); draw j takes u_j = (z_j >> 11) * 2^-53 from
+ *     output j of the stream seed ^ 0x73616D706C696E67 and picks the first
+ *     row whose running score sum exceeds u_j times the total;
+ *  3. S U = U~ S~ V~^T;  4. the best rank-k approximation [U~^T S A]_k and
+ *     the SVD U^ D W^T of V~ S~^{-1} [U~^T S A]_k;  5. L = U U^.
+ * The library evaluates these through equivalent QR-based factorisations and
+ * finds [U~^T S A]_k by block subspace iteration with k + oversample columns,
+ * stopped when the top-k Ritz values change by at most tol relative.
+ * Synchronous (returns after the stream has finished the call).
  */
-SKLS_API int32_t skls_low_rank(const skls_matrix* A, int64_t k, double eps, uint64_t seed, double* L, double* D,
-                      double* W, void* ws, size_t ws_bytes, void* stream);
+typedef struct {
+  int64_t k;           /* target rank, 1 <= k <= 48 and k <= min(n, m) */
+  int64_t t_r;         /* columns of R^; 0: ceil(k / eps), then at least k + oversample, at most min(m, 2048) */
+  int64_t t_s;         /* draws of the sampling; 0: 64 * t_r */
+  uint64_t seed;
+  double eps;          /* accuracy parameter that sets the default t_r (0 < eps <= 1) */
+  int32_t k_g;         /* columns of Pi2 (0: 32; at most 64) */
+  int32_t oversample;  /* extra columns of the subspace iteration (0: 16); k + oversample <= 64 */
+  int32_t max_iter;    /* subspace iterations (0: 60) */
+  double tol;          /* relative change of the top-k Ritz values that ends the iteration (0: 1e-13) */
+  int32_t reserved[4];
+} skls_low_rank_opts;
+
+typedef struct {
+  int64_t t_r, t_s;       /* sizes used */
+  int64_t rows_sampled;   /* distinct rows of A drawn by S */
+  int64_t nnz_sampled;    /* their nonzeros (CSR) */
+  int32_t iterations;     /* subspace iterations run */
+  int32_t converged;      /* 1 when the Ritz values settled within max_iter */
+  double resid_fro;       /* ||A - L diag(D) W^T||_F (float64 accumulation) */
+  double fro_norm;        /* ||A||_F */
+  float ms_sketch, ms_sample, ms_topk, ms_factors;
+  int32_t reserved[4];
+} skls_low_rank_info;
+
+/*
+ * Workspace of skls_low_rank for this matrix and these options (bytes).
+ * Returns SKLS_ERR_ARG / SKLS_ERR_SHAPE for options the call would reject.
+ */
+SKLS_API int32_t skls_low_rank_workspace(const skls_matrix* A, const skls_low_rank_opts* opts, size_t* bytes);
+
+/*
+ *  A:      dense (F64, F32 or BF16) or CSR, n x m, n >= 1, m >= 1.
+ *  L:      device float64 n x k row-major, orthonormal columns.
+ *  D:      device float64 [k], decreasing, >= 0.
+ *  W:      device float64 m x k row-major, orthonormal columns.
+ *  info:   host, or NULL.
+ * Errors: SKLS_ERR_RANK when Y or S U is numerically rank deficient (lower
+ * t_r or raise t_s); SKLS_ERR_WORKSPACE when ws_bytes is below the query.
+ * Columns of L and W that belong to zero values of D are zero.
+ */
+SKLS_API int32_t skls_low_rank(const skls_matrix* A, const skls_low_rank_opts* opts, double* L, double* D, double* W,
+                               skls_low_rank_info* info, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -71,6 +71,39 @@ class SklsLstsqInfo(ctypes.Structure):
     ]
 
 
+class SklsLowRankOpts(ctypes.Structure):
+    _fields_ = [
+        ("k", c_int64),
+        ("t_r", c_int64),
+        ("t_s", c_int64),
+        ("seed", c_uint64),
+        ("eps", c_double),
+        ("k_g", c_int32),
+        ("oversample", c_int32),
+        ("max_iter", c_int32),
+        ("tol", c_double),
+        ("reserved", c_int32 * 4),
+    ]
+
+
+class SklsLowRankInfo(ctypes.Structure):
+    _fields_ = [
+        ("t_r", c_int64),
+        ("t_s", c_int64),
+        ("rows_sampled", c_int64),
+        ("nnz_sampled", c_int64),
+        ("iterations", c_int32),
+        ("converged", c_int32),
+        ("resid_fro", c_double),
+        ("fro_norm", c_double),
+        ("ms_sketch", ctypes.c_float),
+        ("ms_sample", ctypes.c_float),
+        ("ms_topk", ctypes.c_float),
+        ("ms_factors", ctypes.c_float),
+        ("reserved", c_int32 * 4),
+    ]
+
+
 # name -> (restype, argtypes); every symbol declared in include/skls.h
 SIGNATURES = {
     "skls_status_str": (c_char_p, [c_int32]),
@@ -98,8 +131,9 @@ SIGNATURES = {
     "skls_profile_enable": (c_int32, [c_int32]),
     "skls_profile_count": (c_int32, []),
     "skls_profile_get": (c_int32, [c_int32, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double)]),
-    "skls_low_rank": (c_int32, [POINTER(SklsMatrix), c_int64, c_double, c_uint64, c_void_p, c_void_p, c_void_p,
-                                c_void_p, c_size_t, c_void_p]),
+    "skls_low_rank_workspace": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLowRankOpts), POINTER(c_size_t)]),
+    "skls_low_rank": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLowRankOpts), c_void_p, c_void_p, c_void_p,
+                                POINTER(SklsLowRankInfo), c_void_p, c_size_t, c_void_p]),
 }
 
 _lib = None

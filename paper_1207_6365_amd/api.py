@@ -236,9 +236,27 @@ def adam_step(w: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor
                                  _stream(w.device)))
 
 
-def low_rank(A, k: int, eps: float, seed: int):
-    """Rank-``k`` approximation (Section 8); not provided by the library yet."""
+def low_rank_opts(k: int, seed: int, eps: float = 0.0, t_r: int = 0, t_s: int = 0, k_g: int = 0,
+                  oversample: int = 0, max_iter: int = 0, tol: float = 0.0) -> L.SklsLowRankOpts:
+    o = L.SklsLowRankOpts()
+    o.k, o.t_r, o.t_s, o.seed, o.eps = k, t_r, t_s, seed & 0xFFFFFFFFFFFFFFFF, eps
+    o.k_g, o.oversample, o.max_iter, o.tol = k_g, oversample, max_iter, tol
+    return o
+
+
+def low_rank(A, k: int, seed: int, eps: float = 0.0, t_r: int = 0, t_s: int = 0, k_g: int = 0,
+             oversample: int = 0, max_iter: int = 0, tol: float = 0.0):
+    """Rank-``k`` approximation ``A ~ L diag(D) W^T`` (Section 8 theorem,
+    simplified as in the Section 10 experiments).  Returns ``(L, D, W, info)``
+    with float64 device tensors ``L`` (n x k), ``D`` (k), ``W`` (m x k)."""
     m, device = _matrix(A)
-    st = lib().skls_low_rank(ctypes.byref(m), k, eps, seed & 0xFFFFFFFFFFFFFFFF, None, None, None, None, 0,
-                             _stream(device))
-    L.check(st)
+    o = low_rank_opts(k, seed, eps, t_r, t_s, k_g, oversample, max_iter, tol)
+    ws = _workspace(_size(lib().skls_low_rank_workspace, ctypes.byref(m), ctypes.byref(o)), device)
+    Lm = torch.empty((m.n, k), dtype=torch.float64, device=device)
+    D = torch.empty(k, dtype=torch.float64, device=device)
+    Wm = torch.empty((m.d, k), dtype=torch.float64, device=device)
+    info = L.SklsLowRankInfo()
+    L.check(lib().skls_low_rank(ctypes.byref(m), ctypes.byref(o), _ptr(Lm), _ptr(D), _ptr(Wm), ctypes.byref(info),
+                                _ptr(ws), ws.numel(), _stream(device)))
+    out = {f: getattr(info, f) for f, _ in L.SklsLowRankInfo._fields_ if f != "reserved"}
+    return Lm, D, Wm, out

@@ -693,20 +693,30 @@ int32_t skls_adam_step(int64_t n, float* w, const float* g, float* m, float* v, 
   return run_adam(n, w, g, m, v, step, lr, beta1, beta2, eps, as_stream(stream));
 }
 
-int32_t skls_low_rank(const skls_matrix* A, int64_t k, double eps, uint64_t seed, double* L, double* D, double* W,
-                      void* ws, size_t ws_bytes, void* stream) {
-  (void)A;
-  (void)k;
-  (void)eps;
-  (void)seed;
-  (void)L;
-  (void)D;
-  (void)W;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  set_error("low-rank approximation is not provided by the library yet");
-  return SKLS_ERR_NOTIMPL;
+int32_t skls_low_rank_workspace(const skls_matrix* A, const skls_low_rank_opts* opts, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (opts == nullptr || bytes == nullptr) {
+    set_error("opts and bytes must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  LowRankPlan P;
+  SKLS_TRY(low_rank_plan(*A, *opts, P));
+  *bytes = low_rank_ws_bytes(P);
+  return SKLS_OK;
+}
+
+int32_t skls_low_rank(const skls_matrix* A, const skls_low_rank_opts* opts, double* L, double* D, double* W,
+                      skls_low_rank_info* info, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (opts == nullptr || L == nullptr || D == nullptr || W == nullptr) {
+    set_error("opts, L, D and W must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  LowRankPlan P;
+  SKLS_TRY(low_rank_plan(*A, *opts, P));
+  return run_low_rank(*A, P, opts->seed, L, D, W, info, ws, ws_bytes, as_stream(stream));
 }
 
 }  // extern "C"

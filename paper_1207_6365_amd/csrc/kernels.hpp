@@ -93,4 +93,17 @@ int32_t run_adam(int64_t n, float* w, const float* g, float* m, float* v, int32_
                  float b2, float eps, hipStream_t s);
 int32_t run_convert_f64_to_f32(const double* in, float* out, int64_t count, hipStream_t s);
 
+// ---------------------------------------------------------------- lowrank.hip
+// Resolved sizes of a rank-k approximation (options checked and defaulted).
+struct LowRankPlan {
+  int64_t n, m, k, tr, ts, nsmax, nnzmax;
+  int p, kg, max_iter;
+  double tol;
+  bool csr;
+};
+int32_t low_rank_plan(const skls_matrix& A, const skls_low_rank_opts& o, LowRankPlan& P);
+size_t low_rank_ws_bytes(const LowRankPlan& P);
+int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, double* L, double* D, double* W,
+                     skls_low_rank_info* info, void* ws, size_t ws_bytes, hipStream_t s);
+
 }  // namespace skls

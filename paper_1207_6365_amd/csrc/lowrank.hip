@@ -1,0 +1,1162 @@
+// Rank-k approximation A ~ L D W^T (Section 8, theorem on low-rank
+// approximation) in the simplified form of the Section 10 experiments: a
+// sparse embedding R^ of the columns, leverage-score sampling for S, and no
+// randomized Hadamard transform.
+//
+// The steps of the theorem are evaluated through equivalent factorisations
+// that keep every large product tall and thin:
+//   1. Y = A R^T (n x t_R) by hashing columns; R_Y, the triangular factor of Y
+//      (Gram on the float64 matrix cores, Cholesky).  U = Y R_Y^{-1} is the
+//      orthonormal basis of the theorem and is never formed.
+//   2. Scores of Section 6 for Y (squared row norms of Y R_Y^{-1} Pi2, Pi2 a
+//      t_R x k_G sign matrix / sqrt(k_G)); t_S draws with replacement.  A row
+//      drawn c times enters once with weight sqrt(c / (t_S p)), which leaves
+//      S^T S, and so every quantity below, unchanged.
+//   3. The QR factor R' of the weighted sampled rows of Y gives S U = Q' (R'
+//      R_Y^{-1}) with Q' = (S Y) R'^{-1}; for an SVD S U = U~ S~ V~^T,
+//      V~ S~^{-1} [U~^T S A]_k = R_Y R'^{-1} [Q'^T S A]_k.
+//   4. [Q'^T S A]_k = P_k C_k by block subspace iteration on M = Q'^T S A
+//      (t_R x m) with p = k + oversample columns, each side orthonormalised
+//      through the eigendecomposition of its p x p Gram (one-sided Jacobi),
+//      stopped when the top-k Ritz values settle; then the Rayleigh-Ritz
+//      rotation.
+//   5. U X~ = (Y R'^{-1} P_k) C_k = B C_k; with B = Q_B G_B and C_k^T = Q_C G_C
+//      (orthonormal Q), the SVD U^ D V^^T of G_B G_C^T gives L = Q_B U^,
+//      W = Q_C V^.
+// Randomness: R^ from the SplitMix64 stream `seed`, the signs of Pi2 from
+// the stream seed ^ "leverage", the sampling uniforms u_j = (z_j >> 11) 2^-53
+// from the stream seed ^ "sampling" (a draw takes the first row whose running
+// score exceeds u_j times the total).
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "kernels.hpp"
+#include "profile.hpp"
+
+namespace skls {
+namespace {
+
+constexpr uint64_t kPi2Salt = 0x6C65766572616765ull;     // "leverage"
+constexpr uint64_t kSampleSalt = 0x73616D706C696E67ull;  // "sampling"
+constexpr uint64_t kStartSalt = 0x7374617274626C6Bull;   // "startblk": subspace start
+constexpr int kMaxTr = 2048;  // columns of Y a wave can hold in LDS
+constexpr int kMaxP = 64;     // columns of the subspace iteration (Jacobi size)
+constexpr int kT = 256;
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+unsigned grid_for(int64_t work, int per_block, int64_t cap) {
+  int64_t g = div_up(work > 0 ? work : 1, per_block);
+  if (g > cap) g = cap;
+  return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------- step 1: Y = A R^T
+// One wavefront per row; the row of Y is summed in LDS (compare-and-swap
+// float64 adds) and written once.  Column j goes to bucket h(j) with sign
+// sigma(j), read from the hashed column tables.
+template <typename TV, typename TR>
+__global__ __launch_bounds__(kT) void k_colsketch_csr(int64_t n, int tr, const TR* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ col, const TV* __restrict__ val,
+                                                      const int32_t* __restrict__ hb, const int8_t* __restrict__ hs,
+                                                      double* __restrict__ Y) {
+  extern __shared__ double ylds[];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  double* acc = ylds + static_cast<size_t>(wid) * tr;
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kT / kWave) + wid; i < n; i += nw) {
+    for (int c = lane; c < tr; c += kWave) acc[c] = 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t b = static_cast<int64_t>(row_ptr[i]), e = static_cast<int64_t>(row_ptr[i + 1]);
+    for (int64_t k = b + lane; k < e; k += kWave) {
+      const int32_t j = col[k];
+      const double x = load_as<double>(val, static_cast<size_t>(k));
+      lds_add1<double>(acc, hb[j], hs[j] < 0 ? -x : x);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double* yr = Y + static_cast<size_t>(i) * tr;
+    for (int c = lane; c < tr; c += kWave) yr[c] = acc[c];
+  }
+}
+
+template <typename TV>
+__global__ __launch_bounds__(kT) void k_colsketch_dense(int64_t n, int64_t m, int64_t ld, int tr,
+                                                        const TV* __restrict__ A, const int32_t* __restrict__ hb,
+                                                        const int8_t* __restrict__ hs, double* __restrict__ Y) {
+  extern __shared__ double ylds[];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  double* acc = ylds + static_cast<size_t>(wid) * tr;
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kT / kWave) + wid; i < n; i += nw) {
+    for (int c = lane; c < tr; c += kWave) acc[c] = 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const size_t base = static_cast<size_t>(i) * ld;
+    for (int64_t j = lane; j < m; j += kWave) {
+      const double x = load_as<double>(A, base + j);
+      if (x != 0.0) lds_add1<double>(acc, hb[j], hs[j] < 0 ? -x : x);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double* yr = Y + static_cast<size_t>(i) * tr;
+    for (int c = lane; c < tr; c += kWave) yr[c] = acc[c];
+  }
+}
+
+// ---------------------------------------------------------------- float64 GEMM
+// C (M x N) = alpha op(A) B on the float64 matrix cores, one 64 x 64 tile per
+// block of four wavefronts (32 x 32 each), the inner dimension staged through
+// LDS 16 at a time.  op(A) = A (M x K, row-major, lda) or, with TA, A^T for A
+// stored K x M.  B is K x N (ldb).  With several splits of the inner
+// dimension (blockIdx.z), split z writes its partial product to
+// C + z * split_stride.
+template <bool TA>
+__global__ __launch_bounds__(kT) void k_gemm(int64_t M, int64_t N, int64_t K, int64_t kc, double alpha,
+                                             const double* __restrict__ A, int64_t lda,
+                                             const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
+                                             int64_t ldc, int64_t split_stride) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  const int wi = wv >> 1, wj = wv & 1;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 64, j0 = static_cast<int64_t>(blockIdx.y) * 64;
+  const int64_t kb = static_cast<int64_t>(blockIdx.z) * kc;
+  const int64_t ke = (kb + kc) < K ? kb + kc : K;
+  C += static_cast<int64_t>(blockIdx.z) * split_stride;
+  d4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * kT;
+      if (TA) {
+        const int c = e & 63, kk = e >> 6;
+        const int64_t gi = i0 + c, gk = k0 + kk;
+        As[kk][c] = (gi < M && gk < ke) ? A[gk * lda + gi] : 0.0;
+      } else {
+        const int kk = e & 15, c = e >> 4;
+        const int64_t gi = i0 + c, gk = k0 + kk;
+        As[kk][c] = (gi < M && gk < ke) ? A[gi * lda + gk] : 0.0;
+      }
+      const int c = e & 63, kk = e >> 6;
+      const int64_t gj = j0 + c, gk = k0 + kk;
+      Bs[kk][c] = (gj < N && gk < ke) ? B[gk * ldb + gj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const double a0 = As[kk + lr][wi * 32 + lc], a1 = As[kk + lr][wi * 32 + 16 + lc];
+      const double b0 = Bs[kk + lr][wj * 32 + lc], b1 = Bs[kk + lr][wj * 32 + 16 + lc];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+  // element e of lane l: row l / 16 + 4 e, column l % 16 of each 16 x 16 block
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = i0 + wi * 32 + a * 16 + lr + 4 * e, col = j0 + wj * 32 + b * 16 + lc;
+        if (row < M && col < N) C[row * ldc + col] = alpha * acc[a][b][e];
+      }
+}
+
+// C[i, j] = sum over splits of P[z][i, j] (M x N, leading dimension N).
+__global__ void k_sum_splits(const double* __restrict__ P, int splits, int64_t MN, double* __restrict__ C) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < MN;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < splits; ++z) s += P[static_cast<int64_t>(z) * MN + e];
+    C[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------- step 2: scores, sampling
+// Pi2 [r][c] = +-1 / sqrt(k_G), sign from bit 0 of output r * k_G + c.
+__global__ void k_sign_projection(int rows, int kg, uint64_t seed, double* __restrict__ Pi2) {
+  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (e >= static_cast<int64_t>(rows) * kg) return;
+  const uint64_t z = splitmix64(seed ^ kPi2Salt, static_cast<uint64_t>(e));
+  const double v = 1.0 / sqrt(static_cast<double>(kg));
+  Pi2[e] = negative_of(z) ? -v : v;
+}
+
+// Omega [j][c] = +-1 (start of the subspace iteration).
+__global__ void k_sign_block(int64_t rows, int cols, uint64_t seed, double* __restrict__ X) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < rows * cols;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t z = splitmix64(seed ^ kStartSalt, static_cast<uint64_t>(e));
+    X[e] = negative_of(z) ? -1.0 : 1.0;
+  }
+}
+
+// out[i] = sum_c Z[i][c]^2 (one wavefront per row); last[0] = largest i with out[i] > 0.
+__global__ __launch_bounds__(kT) void k_row_sqnorm(int64_t n, int cols, const double* __restrict__ Z,
+                                                   double* __restrict__ out, int32_t* __restrict__ last) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; i < n; i += nw) {
+    double s = 0.0;
+    for (int c = lane; c < cols; c += kWave) {
+      const double z = Z[static_cast<size_t>(i) * cols + c];
+      s += z * z;
+    }
+    s = wave_total(s);
+    if (lane == 0) {
+      out[i] = s;
+      if (s > 0.0) atomicMax(last, static_cast<int32_t>(i));
+    }
+  }
+}
+
+// Inclusive prefix sums in three passes: per-block sums of kScanTile
+// elements, a single-block scan of those sums, then the block scans with
+// their offsets.  The order of additions is fixed (deterministic).
+constexpr int kScanTile = 2048;  // 256 threads x 8
+
+template <typename T>
+__device__ T block_incl_scan(T v, T* sh) {
+  // inclusive scan of one value per thread over the block (256 threads)
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kT; off <<= 1) {
+    const T add = tid >= off ? sh[tid - off] : T(0);
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  const T r = sh[tid];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_scan_tiles(const T* __restrict__ in, int64_t n, T* __restrict__ tile_sum) {
+  __shared__ T sh[kT];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * 8;
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s += (base + q < n) ? in[base + q] : T(0);
+  const T tot = block_incl_scan(s, sh);
+  if (threadIdx.x == kT - 1) tile_sum[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_scan_top(T* __restrict__ tile_sum, int64_t ntiles) {
+  // exclusive scan of the tile sums in place, one block, 256 at a time
+  __shared__ T sh[kT];
+  __shared__ T tot;
+  T carry = 0;
+  for (int64_t c0 = 0; c0 < ntiles; c0 += kT) {
+    const int64_t i = c0 + threadIdx.x;
+    const T v = i < ntiles ? tile_sum[i] : T(0);
+    const T inc = block_incl_scan(v, sh);
+    if (i < ntiles) tile_sum[i] = carry + inc - v;
+    if (threadIdx.x == kT - 1) tot = inc;
+    __syncthreads();
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_scan_apply(const T* __restrict__ in, int64_t n,
+                                                   const T* __restrict__ tile_off, T* __restrict__ out,
+                                                   int exclusive) {
+  __shared__ T sh[kT];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * 8;
+  T v[8];
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    v[q] = (base + q < n) ? in[base + q] : T(0);
+    s += v[q];
+  }
+  const T inc = block_incl_scan(s, sh);
+  T run = tile_off[blockIdx.x] + inc - s;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const T before = run;
+    run += v[q];
+    if (base + q < n) out[base + q] = exclusive ? before : run;
+  }
+}
+
+// Draw j: u = (z >> 11) 2^-53 from the sampling stream, x = u * total; the row
+// is the first i with cum[i] > x, at most `last` (the last positive score).
+__global__ void k_sample(int64_t ts, int64_t n, uint64_t seed, const double* __restrict__ cum,
+                         const double* __restrict__ score, const int32_t* __restrict__ last,
+                         int32_t* __restrict__ counts) {
+  const double total = cum[n - 1];
+  const int64_t hi_row = static_cast<int64_t>(last[0]);
+  for (int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; j < ts;
+       j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t z = splitmix64(seed ^ kSampleSalt, static_cast<uint64_t>(j));
+    const double x = static_cast<double>(z >> 11) * 0x1.0p-53 * total;
+    int64_t lo = 0, hi = n;  // first index with cum > x lies in [lo, hi]
+    while (lo < hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (cum[mid] > x)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    int64_t r = lo < hi_row ? lo : hi_row;
+    // the running sums are rounded per tile; never land on a row without score
+    while (r < hi_row && !(score[r] > 0.0)) ++r;
+    atomicAdd(&counts[r], 1);
+  }
+}
+
+__global__ void k_flags(int64_t n, const int32_t* __restrict__ counts, int32_t* __restrict__ flag) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    flag[i] = counts[i] > 0 ? 1 : 0;
+}
+
+// Sampled rows in increasing order: list[pos[i]] = i with weight
+// sqrt(count_i total / (t_S score_i)); len[pos[i]] = nonzeros of row i (CSR).
+template <typename TR>
+__global__ void k_compact(int64_t n, int64_t ts, const int32_t* __restrict__ counts, const int32_t* __restrict__ pos,
+                          const double* __restrict__ score, const double* __restrict__ cum,
+                          const TR* __restrict__ row_ptr, int32_t* __restrict__ list, double* __restrict__ wts,
+                          int64_t* __restrict__ len) {
+  const double total = cum[n - 1];
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int32_t c = counts[i];
+    if (c == 0) continue;
+    const int32_t p = pos[i];
+    list[p] = static_cast<int32_t>(i);
+    wts[p] = sqrt(static_cast<double>(c) * total / (static_cast<double>(ts) * score[i]));
+    if (len) len[p] = static_cast<int64_t>(row_ptr[i + 1]) - static_cast<int64_t>(row_ptr[i]);
+  }
+}
+
+// out[r][:] = w[r] * X[list[r]][:] (rows of width `cols`, float64 out)
+template <typename TV>
+__global__ __launch_bounds__(kT) void k_gather_rows(int64_t ns, int64_t cols, int64_t ldx, const TV* __restrict__ X,
+                                                    const int32_t* __restrict__ list,
+                                                    const double* __restrict__ w, double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < ns; r += nw) {
+    const size_t src = static_cast<size_t>(list[r]) * ldx;
+    const double s = w[r];
+    for (int64_t c = lane; c < cols; c += kWave)
+      out[static_cast<size_t>(r) * cols + c] = s * load_as<double>(X, src + c);
+  }
+}
+
+// Sampled CSR rows: columns copied, values scaled by the row weight (float64).
+template <typename TV, typename TR>
+__global__ __launch_bounds__(kT) void k_gather_csr(int64_t ns, const TR* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col, const TV* __restrict__ val,
+                                                   const int32_t* __restrict__ list, const double* __restrict__ w,
+                                                   const int64_t* __restrict__ rp, int32_t* __restrict__ col_out,
+                                                   double* __restrict__ val_out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < ns; r += nw) {
+    const int32_t i = list[r];
+    const int64_t b = static_cast<int64_t>(row_ptr[i]), e = static_cast<int64_t>(row_ptr[i + 1]);
+    const int64_t o = rp[r];
+    const double s = w[r];
+    for (int64_t k = lane; k < e - b; k += kWave) {
+      col_out[o + k] = col[b + k];
+      val_out[o + k] = s * load_as<double>(val, static_cast<size_t>(b + k));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- sparse products
+// out (rows x p) = S X for S in CSR (any value and row-pointer type) and X
+// (cols x p, float64); one wavefront per row, lane = column of X (p <= 64).
+// The row's entries are loaded 64 at a time and broadcast lane by lane.
+template <typename TV, typename TR>
+__global__ __launch_bounds__(kT) void k_spmm(int64_t rows, int p, const TR* __restrict__ rp,
+                                             const int32_t* __restrict__ col, const TV* __restrict__ val,
+                                             const double* __restrict__ X, double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  const int lc = lane < p ? lane : 0;
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
+    const int64_t b = static_cast<int64_t>(rp[r]), e = static_cast<int64_t>(rp[r + 1]);
+    double acc = 0.0;
+    for (int64_t k0 = b; k0 < e; k0 += kWave) {
+      const int64_t k = k0 + lane;
+      const int32_t cj = k < e ? col[k] : 0;
+      const double vj = k < e ? load_as<double>(val, static_cast<size_t>(k)) : 0.0;
+      const int cnt = (e - k0) < kWave ? static_cast<int>(e - k0) : kWave;
+      for (int q = 0; q < cnt; ++q) {
+        const int32_t j = __shfl(cj, q);
+        const double v = __shfl(vj, q);
+        acc += v * X[static_cast<size_t>(j) * p + lc];
+      }
+    }
+    if (lane < p) out[static_cast<size_t>(r) * p + lane] = acc;
+  }
+}
+
+// out (rows x p) = A X for dense A (rows x cols, leading dimension ld, any
+// value type) and X (cols x p); one wavefront per row as in k_spmm.
+template <typename TV>
+__global__ __launch_bounds__(kT) void k_dense_times(int64_t rows, int64_t cols, int64_t ld, int p,
+                                                    const TV* __restrict__ A, const double* __restrict__ X,
+                                                    double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  const int lc = lane < p ? lane : 0;
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
+    double acc = 0.0;
+    for (int64_t j0 = 0; j0 < cols; j0 += kWave) {
+      const int64_t j = j0 + lane;
+      const double aj = j < cols ? load_as<double>(A, static_cast<size_t>(r) * ld + j) : 0.0;
+      const int cnt = (cols - j0) < kWave ? static_cast<int>(cols - j0) : kWave;
+      for (int q = 0; q < cnt; ++q) {
+        const double v = __shfl(aj, q);
+        acc += v * X[static_cast<size_t>(j0 + q) * p + lc];
+      }
+    }
+    if (lane < p) out[static_cast<size_t>(r) * p + lane] = acc;
+  }
+}
+
+// C = A B^T for k x k row-major A, B (k <= 64).
+__global__ void k_small_abt(int k, const double* __restrict__ A, const double* __restrict__ B,
+                            double* __restrict__ C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int i = e / k, j = e % k;
+  double s = 0.0;
+  for (int l = 0; l < k; ++l) s += A[i * k + l] * B[j * k + l];
+  C[e] = s;
+}
+
+// out (cols x p) += S^T X for S (CSR, rows x cols) and X (rows x p): row r
+// adds val * X[r, :] into out[col, :] with float64 atomics (out zeroed first).
+__global__ __launch_bounds__(kT) void k_spmm_t(int64_t rows, int p, const int64_t* __restrict__ rp,
+                                               const int32_t* __restrict__ col, const double* __restrict__ val,
+                                               const double* __restrict__ X, double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
+    const int64_t b = rp[r], e = rp[r + 1];
+    const double x = lane < p ? X[static_cast<size_t>(r) * p + lane] : 0.0;
+    for (int64_t k0 = b; k0 < e; k0 += kWave) {
+      const int64_t k = k0 + lane;
+      const int32_t cj = k < e ? col[k] : 0;
+      const double vj = k < e ? val[k] : 0.0;
+      const int cnt = (e - k0) < kWave ? static_cast<int>(e - k0) : kWave;
+      for (int q = 0; q < cnt; ++q) {
+        const int32_t j = __shfl(cj, q);
+        const double v = __shfl(vj, q);
+        if (lane < p) unsafeAtomicAdd(out + static_cast<size_t>(j) * p + lane, v * x);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- one-sided Jacobi
+// SVD of a small r x c matrix G (r, c <= 64, row-major, leading dimension c)
+// by one-sided Jacobi rotations of its columns (Hestenes): G V = W with
+// orthogonal columns; sig[j] = ||W_j|| sorted in decreasing order, V (c x c)
+// and W (r x c, columns divided by sig where it is positive) permuted alike.
+// For a symmetric positive semidefinite G, sig are its eigenvalues and V its
+// eigenvectors.  Sweeps of a round-robin ordering (c - 1 rounds of disjoint
+// pairs, one wavefront per pair, lane = row) until every pair is orthogonal
+// to 1e-15 relative, at most 60 sweeps.
+__global__ __launch_bounds__(1024) void k_jacobi(int r, int c, const double* __restrict__ G, double* __restrict__ sig,
+                                                 double* __restrict__ V, double* __restrict__ Wout) {
+  __shared__ double a[kMaxP][kMaxP + 1];  // a[column][row]
+  __shared__ double v[kMaxP][kMaxP + 1];  // v[column][row]
+  __shared__ double nrm[kMaxP];
+  __shared__ int perm[kMaxP];
+  __shared__ int pos[kMaxP];
+  __shared__ int rotated;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int nwaves = blockDim.x / kWave;
+  const int cc = c + (c & 1);  // even count (a zero column pads odd c)
+  for (int e = tid; e < kMaxP * kMaxP; e += blockDim.x) {
+    const int j = e / kMaxP, i = e % kMaxP;
+    a[j][i] = (j < c && i < r) ? G[i * c + j] : 0.0;
+    v[j][i] = (i == j) ? 1.0 : 0.0;
+  }
+  for (int e = tid; e < cc; e += blockDim.x) pos[e] = e;
+  for (int e = tid; e < kMaxP; e += blockDim.x) perm[e] = e < c ? e : 0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < cc - 1; ++round) {
+      for (int pr = wid; pr < cc / 2; pr += nwaves) {
+        // round-robin pairing: position 0 fixed, the others rotate
+        const int x0 = pr == 0 ? 0 : 1 + (pr - 1 + round) % (cc - 1);
+        const int x1 = 1 + (cc - 2 - pr + round) % (cc - 1);
+        const int p = pos[x0], q = pos[x1];
+        const double ap = a[p][lane], aq = a[q][lane];
+        const double al = wave_total(ap * ap), be = wave_total(aq * aq), ga = wave_total(ap * aq);
+        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          a[p][lane] = cs * ap - sn * aq;
+          a[q][lane] = sn * ap + cs * aq;
+          const double vp = v[p][lane], vq = v[q][lane];
+          v[p][lane] = cs * vp - sn * vq;
+          v[q][lane] = sn * vp + cs * vq;
+          if (lane == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int j = wid; j < c; j += nwaves) {
+    const double x = a[j][lane];
+    const double s = wave_total(x * x);
+    if (lane == 0) nrm[j] = sqrt(s);
+  }
+  __syncthreads();
+  if (tid < c) {
+    int rank = 0;
+    for (int i = 0; i < c; ++i) rank += (nrm[i] > nrm[tid] || (nrm[i] == nrm[tid] && i < tid)) ? 1 : 0;
+    perm[rank] = tid;
+  }
+  __syncthreads();
+  for (int e = tid; e < c * c; e += blockDim.x) {
+    const int i = e / c, k = e % c;
+    V[e] = v[perm[k]][i];
+  }
+  for (int e = tid; e < r * c; e += blockDim.x) {
+    const int i = e / c, k = e % c;
+    const double s = nrm[perm[k]];
+    Wout[e] = s > 0.0 ? a[perm[k]][i] / s : 0.0;
+  }
+  if (tid < c) sig[tid] = nrm[perm[tid]];
+}
+
+// Orthonormalising map from the eigendecomposition G = V diag(lam) V^T of a
+// p x p Gram: Mx = V diag(lam^{-1/2}) (zero for lam <= floor * lam_max) and
+// the factor F = diag(lam^{1/2}) V^T, so that X = (X Mx) F on the span kept.
+__global__ void k_svqb_maps(int p, const double* __restrict__ lam, const double* __restrict__ V, double floor_rel,
+                            double* __restrict__ Mx, double* __restrict__ F) {
+  const int e = threadIdx.x + blockIdx.x * blockDim.x;
+  if (e >= p * p) return;
+  const int i = e / p, j = e % p;
+  const double lmax = lam[0];
+  const double lj = lam[j];
+  const bool keep = lj > floor_rel * lmax && lj > 0.0;
+  Mx[e] = keep ? V[e] / sqrt(lj) : 0.0;               // Mx[i][j] = V[i][j] lam_j^{-1/2}
+  const double li = lam[i];
+  const bool keepi = li > floor_rel * lmax && li > 0.0;
+  F[e] = keepi ? sqrt(li) * V[j * p + i] : 0.0;       // F[i][j] = lam_i^{1/2} V[j][i]
+}
+
+// ---------------------------------------------------------------- residual
+// partial[b][c] = sum over the block's rows of L[i, c] * AW[i, c]; slot k
+// (c = k) of the block holds its share of sum A_ij^2 (CSR values or dense rows).
+__global__ __launch_bounds__(kT) void k_col_dots(int64_t n, int k, const double* __restrict__ L,
+                                                 const double* __restrict__ AW, double* __restrict__ partial) {
+  __shared__ double sh[kT / kWave];
+  for (int c = 0; c < k; ++c) {
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kT)
+      s += L[static_cast<size_t>(i) * k + c] * AW[static_cast<size_t>(i) * k + c];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[static_cast<size_t>(blockIdx.x) * (k + 1) + c] = s;
+  }
+}
+
+template <typename TV>
+__global__ __launch_bounds__(kT) void k_sumsq(int64_t count, const TV* __restrict__ x, int64_t rows, int64_t cols,
+                                              int64_t ld, int k, double* __restrict__ partial) {
+  __shared__ double sh[kT / kWave];
+  double s = 0.0;
+  if (rows < 0) {
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x; e < count;
+         e += static_cast<int64_t>(gridDim.x) * kT) {
+      const double v = load_as<double>(x, static_cast<size_t>(e));
+      s += v * v;
+    }
+  } else {
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x; e < rows * cols;
+         e += static_cast<int64_t>(gridDim.x) * kT) {
+      const double v = load_as<double>(x, static_cast<size_t>((e / cols) * ld + e % cols));
+      s += v * v;
+    }
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[static_cast<size_t>(blockIdx.x) * (k + 1) + k] = s;
+}
+
+__global__ void k_sum_cols(const double* __restrict__ partial, int nblk, int w, double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= w) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[static_cast<size_t>(b) * w + c];
+  out[c] = s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+namespace {
+
+template <typename F>
+int32_t with_value(int32_t dt, F&& f) {
+  switch (dt) {
+    case SKLS_F64: return f(double{});
+    case SKLS_F32: return f(float{});
+    case SKLS_BF16: return f(bf16_t{});
+    default: set_error("unsupported value dtype %d", dt); return SKLS_ERR_DTYPE;
+  }
+}
+template <typename F>
+int32_t with_rowptr(const skls_matrix& A, F&& f) {
+  if (A.row_ptr_64) return f(int64_t{});
+  return f(int32_t{});
+}
+
+struct GemmScratch {
+  double* part;
+  size_t doubles;
+};
+
+// C = alpha op(A) B with the inner dimension split when the output has few
+// tiles and the inner dimension is long.
+int32_t gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+             int64_t ldb, double* C, int64_t ldc, const GemmScratch& sc, hipStream_t s) {
+  if (M == 0 || N == 0) return SKLS_OK;
+  const int64_t tiles = div_up(M, 64) * div_up(N, 64);
+  int64_t splits = 1;
+  if (tiles < 256 && K > 2048) {
+    splits = div_up(512, tiles);
+    const int64_t by_k = div_up(K, 1024);
+    if (splits > by_k) splits = by_k;
+    if (splits > 256) splits = 256;
+    while (splits > 1 && static_cast<size_t>(splits) * M * N > sc.doubles) --splits;
+  }
+  const int64_t kc = div_up(div_up(K > 0 ? K : 1, splits), 16) * 16;
+  splits = div_up(K > 0 ? K : 1, kc);
+  const dim3 grid(static_cast<unsigned>(div_up(M, 64)), static_cast<unsigned>(div_up(N, 64)),
+                  static_cast<unsigned>(splits));
+  double* out = splits > 1 ? sc.part : C;
+  const int64_t ldo = splits > 1 ? N : ldc;
+  if (splits > 1 && ldc != N) {
+    set_error("internal: split GEMM needs a packed output");
+    return SKLS_ERR_ARG;
+  }
+  if (ta)
+    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(kT), 0, s, M, N, K, kc, alpha, A, lda, B, ldb, out, ldo, M * N);
+  else
+    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(kT), 0, s, M, N, K, kc, alpha, A, lda, B, ldb, out, ldo, M * N);
+  SKLS_CHECK_LAUNCH();
+  if (splits > 1) {
+    hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(M * N, kT, 4096)), dim3(kT), 0, s, sc.part,
+                       static_cast<int>(splits), M * N, C);
+    SKLS_CHECK_LAUNCH();
+  }
+  return SKLS_OK;
+}
+
+template <typename T>
+int32_t scan(const T* in, int64_t n, T* tiles, T* out, bool exclusive, hipStream_t s) {
+  if (n == 0) return SKLS_OK;
+  const int64_t nt = div_up(n, kScanTile);
+  hipLaunchKernelGGL(k_scan_tiles<T>, dim3(static_cast<unsigned>(nt)), dim3(kT), 0, s, in, n, tiles);
+  SKLS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(kT), 0, s, tiles, nt);
+  SKLS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3(static_cast<unsigned>(nt)), dim3(kT), 0, s, in, n, tiles, out,
+                     exclusive ? 1 : 0);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
+
+constexpr double kDropRel = 1e-24;  // Gram eigenvalues below this (relative) count as zero
+
+struct LrWs {
+  int32_t* hb;
+  int8_t* hs;
+  double* Y;
+  void* gram;
+  size_t gram_bytes;
+  double *G, *cholw, *R, *Rinv, *RinvT;
+  int32_t* status;
+  double *Pi2, *T, *Z, *score, *cum, *dtiles;
+  int32_t *counts, *flag, *pos, *itiles, *last;
+  int32_t* list;
+  double* wts;
+  int64_t *len, *rp, *ltiles;
+  int32_t* colc;
+  double* valc;
+  double *SY, *Q, *F, *Ft, *G1, *X1, *P, *Pt;
+  GemmScratch part;
+  double *Gp, *V, *Wj, *lam, *Mx, *F1, *F2, *Fac;
+  double *Pk, *T2, *Bq, *Bt, *Cq, *Ct, *FacB, *FacC, *K, *Uh, *Vh, *AW, *dots, *dsum;
+  int nblk;
+};
+
+int64_t lr_tiles(int64_t n) { return div_up(n > 0 ? n : 1, kScanTile) + 1; }
+
+LrWs carve_lr(Arena& ar, const LowRankPlan& P) {
+  LrWs w;
+  const int64_t n = P.n, m = P.m, tr = P.tr, ns = P.nsmax, p = P.p, k = P.k;
+  w.hb = ar.take<int32_t>(m);
+  w.hs = ar.take<int8_t>(m);
+  w.Y = ar.take<double>(static_cast<size_t>(n) * tr);
+  size_t gb = 0;
+  const int64_t rows_d[][2] = {{n, tr}, {ns, tr}, {tr, p}, {m, p}, {n, k}, {m, k}};
+  for (const auto& rd : rows_d) {
+    const size_t b = gram_ws_bytes(rd[0], rd[1]);
+    gb = b > gb ? b : gb;
+  }
+  w.gram_bytes = gb;
+  w.gram = ar.take<double>(gb / sizeof(double) + 1);
+  w.G = ar.take<double>(static_cast<size_t>(tr) * tr);
+  w.cholw = ar.take<double>(cholesky_scratch_doubles(tr));
+  w.R = ar.take<double>(static_cast<size_t>(tr) * tr);
+  w.Rinv = ar.take<double>(static_cast<size_t>(tr) * tr);
+  w.RinvT = ar.take<double>(static_cast<size_t>(tr) * tr);
+  w.status = ar.take<int32_t>(4);
+  w.Pi2 = ar.take<double>(static_cast<size_t>(tr) * P.kg);
+  w.T = ar.take<double>(static_cast<size_t>(tr) * P.kg);
+  w.Z = ar.take<double>(static_cast<size_t>(n) * P.kg);
+  w.score = ar.take<double>(n);
+  w.cum = ar.take<double>(n);
+  w.dtiles = ar.take<double>(lr_tiles(n));
+  w.counts = ar.take<int32_t>(n);
+  w.flag = ar.take<int32_t>(n);
+  w.pos = ar.take<int32_t>(n);
+  w.itiles = ar.take<int32_t>(lr_tiles(n));
+  w.last = ar.take<int32_t>(4);
+  w.list = ar.take<int32_t>(ns);
+  w.wts = ar.take<double>(ns);
+  w.len = ar.take<int64_t>(ns);
+  w.rp = ar.take<int64_t>(ns + 1);
+  w.ltiles = ar.take<int64_t>(lr_tiles(ns));
+  w.colc = P.csr ? ar.take<int32_t>(P.nnzmax) : nullptr;
+  w.valc = ar.take<double>(P.nnzmax);
+  w.SY = ar.take<double>(static_cast<size_t>(ns) * tr);
+  w.Q = ar.take<double>(static_cast<size_t>(ns) * tr);
+  w.F = ar.take<double>(static_cast<size_t>(m) * p);
+  w.Ft = ar.take<double>(static_cast<size_t>(m) * p);
+  w.G1 = ar.take<double>(static_cast<size_t>(ns) * p);
+  w.X1 = ar.take<double>(static_cast<size_t>(ns) * p);
+  w.P = ar.take<double>(static_cast<size_t>(tr) * p);
+  w.Pt = ar.take<double>(static_cast<size_t>(tr) * p);
+  w.part.doubles = size_t(1) << 23;  // split-K partial products (64 MiB)
+  w.part.part = ar.take<double>(w.part.doubles);
+  const size_t pp = static_cast<size_t>(kMaxP) * kMaxP;
+  w.Gp = ar.take<double>(pp);
+  w.V = ar.take<double>(pp);
+  w.Wj = ar.take<double>(pp);
+  w.lam = ar.take<double>(kMaxP);
+  w.Mx = ar.take<double>(pp);
+  w.F1 = ar.take<double>(pp);
+  w.F2 = ar.take<double>(pp);
+  w.Fac = ar.take<double>(pp);
+  w.Pk = ar.take<double>(static_cast<size_t>(tr) * k);
+  w.T2 = ar.take<double>(static_cast<size_t>(tr) * k);
+  w.Bq = ar.take<double>(static_cast<size_t>(n) * k);
+  w.Bt = ar.take<double>(static_cast<size_t>(n) * k);
+  w.Cq = ar.take<double>(static_cast<size_t>(m) * k);
+  w.Ct = ar.take<double>(static_cast<size_t>(m) * k);
+  w.FacB = ar.take<double>(pp);
+  w.FacC = ar.take<double>(pp);
+  w.K = ar.take<double>(pp);
+  w.Uh = ar.take<double>(pp);
+  w.Vh = ar.take<double>(pp);
+  w.AW = ar.take<double>(static_cast<size_t>(n) * k);
+  w.nblk = 256;
+  w.dots = ar.take<double>(static_cast<size_t>(w.nblk) * (k + 1));
+  w.dsum = ar.take<double>(k + 1);
+  return w;
+}
+
+int32_t to_host(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  SKLS_TRY_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+  SKLS_TRY_HIP(hipStreamSynchronize(s));
+  return SKLS_OK;
+}
+
+// X (rows x c, packed) -> X with orthonormal columns (two passes of
+// eigendecomposition-based orthonormalisation); fac (c x c) with
+// X_in = X_out fac; lam gets the eigenvalues of the first pass's Gram.
+int32_t svqb2(double* X, double* tmp, int64_t rows, int c, double* fac, LrWs& w, hipStream_t s) {
+  double* cur = X;
+  double* nxt = tmp;
+  for (int pass = 0; pass < 2; ++pass) {
+    SKLS_TRY(run_gram(cur, SKLS_F64, c, nullptr, SKLS_F64, rows, c, w.Gp, w.gram, w.gram_bytes, s));
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, c, c, w.Gp, w.lam, w.V, w.Wj);
+    SKLS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_svqb_maps, dim3(grid_for(c * c, kT, 64)), dim3(kT), 0, s, c, w.lam, w.V, kDropRel, w.Mx,
+                       pass == 0 ? w.F1 : w.F2);
+    SKLS_CHECK_LAUNCH();
+    SKLS_TRY(gemm(false, rows, c, c, 1.0, cur, c, w.Mx, c, nxt, c, w.part, s));
+    std::swap(cur, nxt);
+  }
+  // after two passes the result is back in X
+  if (fac) SKLS_TRY(gemm(false, c, c, c, 1.0, w.F2, c, w.F1, c, fac, c, w.part, s));
+  return SKLS_OK;
+}
+
+}  // namespace
+
+int32_t low_rank_plan(const skls_matrix& A, const skls_low_rank_opts& o, LowRankPlan& P) {
+  P.n = A.n;
+  P.m = A.d;
+  P.csr = A.layout == SKLS_CSR;
+  P.k = o.k;
+  if (P.n >= (int64_t(1) << 31) || P.m >= (int64_t(1) << 31)) {
+    set_error("low_rank: n and m must be below 2^31");
+    return SKLS_ERR_SHAPE;
+  }
+  if (o.k < 1 || o.k > 48 || o.k > P.n || o.k > P.m) {
+    set_error("low_rank: need 1 <= k <= 48 and k <= min(n, m)");
+    return SKLS_ERR_ARG;
+  }
+  const int over = o.oversample > 0 ? o.oversample : 16;
+  P.kg = o.k_g > 0 ? o.k_g : 32;
+  if (P.kg > 64 || o.k_g < 0 || o.oversample < 0) {
+    set_error("low_rank: need 0 <= k_g <= 64 and oversample >= 0");
+    return SKLS_ERR_ARG;
+  }
+  const int64_t cap = std::min<int64_t>(std::min<int64_t>(P.m, P.n), kMaxTr);
+  int64_t tr = o.t_r;
+  if (tr == 0) {
+    if (!(o.eps > 0.0 && o.eps <= 1.0)) {
+      set_error("low_rank: give t_r or 0 < eps <= 1");
+      return SKLS_ERR_ARG;
+    }
+    tr = static_cast<int64_t>(std::ceil(static_cast<double>(o.k) / o.eps));
+    tr = std::max<int64_t>(tr, std::min<int64_t>(o.k + over, kMaxP));
+    tr = std::min(tr, cap);
+  }
+  if (tr < o.k || tr > cap) {
+    set_error("low_rank: need k <= t_r <= min(n, m, 2048)");
+    return SKLS_ERR_ARG;
+  }
+  P.tr = tr;
+  P.p = static_cast<int>(std::min<int64_t>(std::min<int64_t>(o.k + over, kMaxP), tr));
+  P.ts = o.t_s > 0 ? o.t_s : 64 * tr;
+  if (P.ts < tr || P.ts >= (int64_t(1) << 31) || o.t_s < 0) {
+    set_error("low_rank: need t_r <= t_s < 2^31");
+    return SKLS_ERR_ARG;
+  }
+  P.nsmax = std::min(P.n, P.ts);
+  P.nnzmax = P.csr ? std::max<int64_t>(A.nnz, 1) : P.nsmax * P.m;
+  P.max_iter = o.max_iter > 0 ? o.max_iter : 60;
+  P.tol = o.tol > 0.0 ? o.tol : 1e-13;
+  return SKLS_OK;
+}
+
+size_t low_rank_ws_bytes(const LowRankPlan& P) {
+  Arena ar(nullptr, 0);
+  carve_lr(ar, P);
+  return ar.used;
+}
+
+int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, double* Lout, double* Dout,
+                     double* Wout, skls_low_rank_info* info, void* ws, size_t ws_bytes, hipStream_t s) {
+  Arena ar(ws, ws_bytes);
+  LrWs w = carve_lr(ar, P);
+  if (!ar.fits() || ws == nullptr) {
+    set_error("low_rank: workspace too small (%zu bytes needed)", ar.used);
+    return SKLS_ERR_WORKSPACE;
+  }
+  const int64_t n = P.n, m = P.m, tr = P.tr, k = P.k;
+  const int p = P.p, kg = P.kg, tri = static_cast<int>(tr);
+  skls_low_rank_info inf{};
+  inf.t_r = tr;
+  inf.t_s = P.ts;
+  hipEvent_t ev[5];
+  for (auto& e : ev) SKLS_TRY_HIP(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  SKLS_TRY_HIP(hipEventRecord(ev[0], s));
+
+  // ---- step 1: Y = A R^T, and R_Y
+  {
+    PhaseTimer pt("lowrank_sketch", s);
+    SKLS_TRY(launch_hash(m, static_cast<uint32_t>(tr), seed, 0, w.hb, w.hs, s));
+    const size_t lds = static_cast<size_t>(kT / kWave) * tr * sizeof(double);
+    const unsigned g = grid_for(n, kT / kWave, 8192);
+    int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
+      using TV = decltype(tv);
+      if (!P.csr) {
+        if (lds > 65536)
+          SKLS_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colsketch_dense<TV>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        hipLaunchKernelGGL(k_colsketch_dense<TV>, dim3(g), dim3(kT), lds, s, n, m, A.ld, tri,
+                           static_cast<const TV*>(A.val), w.hb, w.hs, w.Y);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      }
+      return with_rowptr(A, [&](auto trt) -> int32_t {
+        using TR = decltype(trt);
+        if (lds > 65536)
+          SKLS_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_colsketch_csr<TV, TR>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        hipLaunchKernelGGL((k_colsketch_csr<TV, TR>), dim3(g), dim3(kT), lds, s, n, tri,
+                           static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), w.hb, w.hs,
+                           w.Y);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      });
+    });
+    SKLS_TRY(st);
+  }
+  SKLS_TRY(run_gram(w.Y, SKLS_F64, tr, nullptr, SKLS_F64, n, tr, w.G, w.gram, w.gram_bytes, s));
+  SKLS_TRY(run_cholesky(w.G, tr, tr, w.R, w.status, w.cholw, s));
+  int32_t st_h = 0;
+  SKLS_TRY(to_host(&st_h, w.status, sizeof st_h, s));
+  if (st_h) {
+    set_error("low_rank: A R^T is numerically rank deficient (lower t_r)");
+    return SKLS_ERR_RANK;
+  }
+  SKLS_TRY(run_trinv(w.R, tr, w.Rinv, w.RinvT, s));
+  SKLS_TRY_HIP(hipEventRecord(ev[1], s));
+
+  // ---- step 2: scores of Y, sampling, sampled rows
+  int64_t ns = 0, nnz_s = 0;
+  {
+    PhaseTimer pt("lowrank_sample", s);
+    hipLaunchKernelGGL(k_sign_projection, dim3(grid_for(tr * kg, kT, 1 << 20)), dim3(kT), 0, s, tri, kg, seed,
+                       w.Pi2);
+    SKLS_CHECK_LAUNCH();
+    SKLS_TRY(gemm(false, tr, kg, tr, 1.0, w.Rinv, tr, w.Pi2, kg, w.T, kg, w.part, s));
+    SKLS_TRY(gemm(false, n, kg, tr, 1.0, w.Y, tr, w.T, kg, w.Z, kg, w.part, s));
+    SKLS_TRY(launch_fill_zero(w.last, 16, s));
+    hipLaunchKernelGGL(k_row_sqnorm, dim3(grid_for(n, kT / kWave, 8192)), dim3(kT), 0, s, n, kg, w.Z, w.score,
+                       w.last);
+    SKLS_CHECK_LAUNCH();
+    SKLS_TRY(scan<double>(w.score, n, w.dtiles, w.cum, false, s));
+    SKLS_TRY(launch_fill_zero(w.counts, static_cast<size_t>((n + 3) / 4) * 16, s));
+    hipLaunchKernelGGL(k_sample, dim3(grid_for(P.ts, kT, 4096)), dim3(kT), 0, s, P.ts, n, seed, w.cum, w.score,
+                       w.last, w.counts);
+    SKLS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_flags, dim3(grid_for(n, kT, 4096)), dim3(kT), 0, s, n, w.counts, w.flag);
+    SKLS_CHECK_LAUNCH();
+    SKLS_TRY(scan<int32_t>(w.flag, n, w.itiles, w.pos, true, s));
+    int32_t hv[2];
+    double total = 0.0;
+    SKLS_TRY_HIP(hipMemcpyAsync(&hv[0], w.pos + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SKLS_TRY_HIP(hipMemcpyAsync(&hv[1], w.flag + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SKLS_TRY(to_host(&total, w.cum + (n - 1), sizeof total, s));
+    if (!(total > 0.0) || !std::isfinite(total)) {
+      set_error("low_rank: the leverage scores of A R^T are not positive and finite");
+      return SKLS_ERR_RANK;
+    }
+    ns = static_cast<int64_t>(hv[0]) + hv[1];
+    if (ns < tr) {
+      set_error("low_rank: %lld distinct rows drawn, fewer than t_r = %lld (raise t_s)", static_cast<long long>(ns),
+                static_cast<long long>(tr));
+      return SKLS_ERR_RANK;
+    }
+    int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
+      using TV = decltype(tv);
+      if (!P.csr) {
+        hipLaunchKernelGGL(k_compact<int32_t>, dim3(grid_for(n, kT, 4096)), dim3(kT), 0, s, n, P.ts, w.counts,
+                           w.pos, w.score, w.cum, nullptr, w.list, w.wts, nullptr);
+        SKLS_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_gather_rows<TV>, dim3(grid_for(ns, kT / kWave, 8192)), dim3(kT), 0, s, ns, m, A.ld,
+                           static_cast<const TV*>(A.val), w.list, w.wts, w.valc);
+        SKLS_CHECK_LAUNCH();
+        nnz_s = ns * m;
+        return SKLS_OK;
+      }
+      return with_rowptr(A, [&](auto trt) -> int32_t {
+        using TR = decltype(trt);
+        const TR* rpA = static_cast<const TR*>(A.row_ptr);
+        hipLaunchKernelGGL(k_compact<TR>, dim3(grid_for(n, kT, 4096)), dim3(kT), 0, s, n, P.ts, w.counts, w.pos,
+                           w.score, w.cum, rpA, w.list, w.wts, w.len);
+        SKLS_CHECK_LAUNCH();
+        SKLS_TRY(scan<int64_t>(w.len, ns, w.ltiles, w.rp, true, s));
+        int64_t hl[2];
+        SKLS_TRY_HIP(hipMemcpyAsync(&hl[0], w.rp + (ns - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SKLS_TRY(to_host(&hl[1], w.len + (ns - 1), sizeof(int64_t), s));
+        nnz_s = hl[0] + hl[1];
+        SKLS_TRY_HIP(hipMemcpyAsync(w.rp + ns, &nnz_s, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        SKLS_TRY_HIP(hipStreamSynchronize(s));
+        hipLaunchKernelGGL((k_gather_csr<TV, TR>), dim3(grid_for(ns, kT / kWave, 8192)), dim3(kT), 0, s, ns, rpA,
+                           A.col_idx, static_cast<const TV*>(A.val), w.list, w.wts, w.rp, w.colc, w.valc);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      });
+    });
+    SKLS_TRY(st);
+    hipLaunchKernelGGL(k_gather_rows<double>, dim3(grid_for(ns, kT / kWave, 8192)), dim3(kT), 0, s, ns, tr, tr,
+                       w.Y, w.list, w.wts, w.SY);
+    SKLS_CHECK_LAUNCH();
+  }
+  inf.rows_sampled = ns;
+  inf.nnz_sampled = P.csr ? nnz_s : 0;
+  SKLS_TRY_HIP(hipEventRecord(ev[2], s));
+
+  // ---- steps 3 and 4: R' of S Y, Q' = S Y R'^{-1}, top-k of M = Q'^T S A
+  {
+    PhaseTimer pt("lowrank_topk", s);
+    SKLS_TRY(run_gram(w.SY, SKLS_F64, tr, nullptr, SKLS_F64, ns, tr, w.G, w.gram, w.gram_bytes, s));
+    SKLS_TRY(run_cholesky(w.G, tr, tr, w.R, w.status, w.cholw, s));
+    SKLS_TRY(to_host(&st_h, w.status, sizeof st_h, s));
+    if (st_h) {
+      set_error("low_rank: S U is numerically rank deficient (raise t_s)");
+      return SKLS_ERR_RANK;
+    }
+    SKLS_TRY(run_trinv(w.R, tr, w.Rinv, w.RinvT, s));
+    SKLS_TRY(gemm(false, ns, tr, tr, 1.0, w.SY, tr, w.Rinv, tr, w.Q, tr, w.part, s));
+    hipLaunchKernelGGL(k_sign_block, dim3(grid_for(m * p, kT, 8192)), dim3(kT), 0, s, m, p, seed, w.F);
+    SKLS_CHECK_LAUNCH();
+    const unsigned gr = grid_for(ns, kT / kWave, 8192);
+    auto times_SA = [&](const double* X, double* out) -> int32_t {  // out (ns x p) = S A X
+      if (P.csr) {
+        hipLaunchKernelGGL((k_spmm<double, int64_t>), dim3(gr), dim3(kT), 0, s, ns, p, w.rp, w.colc, w.valc, X,
+                           out);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      }
+      return gemm(false, ns, p, m, 1.0, w.valc, m, X, p, out, p, w.part, s);
+    };
+    auto times_SAt = [&](const double* X, double* out) -> int32_t {  // out (m x p) = (S A)^T X
+      if (P.csr) {
+        SKLS_TRY(launch_fill_zero(out, static_cast<size_t>(m) * p * sizeof(double), s));
+        hipLaunchKernelGGL(k_spmm_t, dim3(gr), dim3(kT), 0, s, ns, p, w.rp, w.colc, w.valc, X, out);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      }
+      return gemm(true, m, p, ns, 1.0, w.valc, m, X, p, out, p, w.part, s);
+    };
+    std::vector<double> prev(p, 0.0), cur(p, 0.0);
+    int it = 0;
+    bool conv = false;
+    for (;;) {
+      SKLS_TRY(times_SA(w.F, w.G1));
+      SKLS_TRY(gemm(true, tr, p, ns, 1.0, w.Q, tr, w.G1, p, w.P, p, w.part, s));  // P = Q'^T (S A F)
+      SKLS_TRY(svqb2(w.P, w.Pt, tr, p, nullptr, w, s));
+      SKLS_TRY(gemm(false, ns, p, tr, 1.0, w.Q, tr, w.P, p, w.X1, p, w.part, s));
+      SKLS_TRY(times_SAt(w.X1, w.F));  // F = M^T P
+      SKLS_TRY(run_gram(w.F, SKLS_F64, p, nullptr, SKLS_F64, m, p, w.Gp, w.gram, w.gram_bytes, s));
+      hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, p, p, w.Gp, w.lam, w.V, w.Wj);
+      SKLS_CHECK_LAUNCH();
+      SKLS_TRY(to_host(cur.data(), w.lam, sizeof(double) * p, s));
+      ++it;
+      if (it > 1) {
+        double worst = 0.0;
+        for (int64_t i = 0; i < k; ++i) {
+          const double d = std::fabs(cur[i] - prev[i]) / (cur[0] > 0.0 ? cur[0] : 1.0);
+          worst = d > worst ? d : worst;
+        }
+        if (worst <= P.tol) conv = true;
+      }
+      if (conv || it >= P.max_iter) break;
+      prev = cur;
+      // keep F well conditioned for the next product: F <- F V lam^{-1/2}
+      hipLaunchKernelGGL(k_svqb_maps, dim3(grid_for(p * p, kT, 64)), dim3(kT), 0, s, p, w.lam, w.V, kDropRel,
+                         w.Mx, w.F1);
+      SKLS_CHECK_LAUNCH();
+      SKLS_TRY(gemm(false, m, p, p, 1.0, w.F, p, w.Mx, p, w.Ft, p, w.part, s));
+      std::swap(w.F, w.Ft);
+    }
+    inf.iterations = it;
+    inf.converged = conv ? 1 : 0;
+    // Rayleigh-Ritz: P_k = P V[:, :k], C_k^T = M^T P_k = F V[:, :k]
+    SKLS_TRY(gemm(false, tr, k, p, 1.0, w.P, p, w.V, p, w.Pk, k, w.part, s));
+    SKLS_TRY(gemm(false, m, k, p, 1.0, w.F, p, w.V, p, w.Cq, k, w.part, s));
+  }
+  SKLS_TRY_HIP(hipEventRecord(ev[3], s));
+
+  // ---- step 5: B = Y R'^{-1} P_k, orthonormal factors, k x k SVD
+  {
+    PhaseTimer pt("lowrank_factors", s);
+    SKLS_TRY(gemm(false, tr, k, tr, 1.0, w.Rinv, tr, w.Pk, k, w.T2, k, w.part, s));
+    SKLS_TRY(gemm(false, n, k, tr, 1.0, w.Y, tr, w.T2, k, w.Bq, k, w.part, s));
+    const int ki = static_cast<int>(k);
+    SKLS_TRY(svqb2(w.Bq, w.Bt, n, ki, w.FacB, w, s));
+    SKLS_TRY(svqb2(w.Cq, w.Ct, m, ki, w.FacC, w, s));
+    hipLaunchKernelGGL(k_small_abt, dim3(grid_for(k * k, kT, 64)), dim3(kT), 0, s, ki, w.FacB, w.FacC, w.K);
+    SKLS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, ki, ki, w.K, Dout, w.Vh, w.Uh);
+    SKLS_CHECK_LAUNCH();
+    SKLS_TRY(gemm(false, n, k, k, 1.0, w.Bq, k, w.Uh, k, Lout, k, w.part, s));
+    SKLS_TRY(gemm(false, m, k, k, 1.0, w.Cq, k, w.Vh, k, Wout, k, w.part, s));
+    // ||A - L D W^T||_F^2 = ||A||_F^2 - 2 sum_c D_c <L_c, (A W)_c> + sum_c D_c^2
+    int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
+      using TV = decltype(tv);
+      const unsigned g = grid_for(n, kT / kWave, 8192);
+      if (!P.csr) {
+        hipLaunchKernelGGL(k_dense_times<TV>, dim3(g), dim3(kT), 0, s, n, m, A.ld, ki,
+                           static_cast<const TV*>(A.val), Wout, w.AW);
+        SKLS_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_sumsq<TV>, dim3(w.nblk), dim3(kT), 0, s, int64_t(0), static_cast<const TV*>(A.val), n,
+                           m, A.ld, ki, w.dots);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      }
+      return with_rowptr(A, [&](auto trt) -> int32_t {
+        using TR = decltype(trt);
+        hipLaunchKernelGGL((k_spmm<TV, TR>), dim3(g), dim3(kT), 0, s, n, ki, static_cast<const TR*>(A.row_ptr),
+                           A.col_idx, static_cast<const TV*>(A.val), Wout, w.AW);
+        SKLS_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_sumsq<TV>, dim3(w.nblk), dim3(kT), 0, s, A.nnz, static_cast<const TV*>(A.val),
+                           int64_t(-1), int64_t(0), int64_t(0), ki, w.dots);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      });
+    });
+    SKLS_TRY(st);
+    hipLaunchKernelGGL(k_col_dots, dim3(w.nblk), dim3(kT), 0, s, n, ki, Lout, w.AW, w.dots);
+    SKLS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(kT), 0, s, w.dots, w.nblk, ki + 1, w.dsum);
+    SKLS_CHECK_LAUNCH();
+  }
+  SKLS_TRY_HIP(hipEventRecord(ev[4], s));
+  std::vector<double> hs(k + 1), hd(k);
+  SKLS_TRY_HIP(hipMemcpyAsync(hd.data(), Dout, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  SKLS_TRY(to_host(hs.data(), w.dsum, sizeof(double) * (k + 1), s));
+  double r2 = hs[k];
+  for (int64_t c = 0; c < k; ++c) r2 += hd[c] * hd[c] - 2.0 * hd[c] * hs[c];
+  inf.fro_norm = std::sqrt(hs[k]);
+  inf.resid_fro = std::sqrt(r2 > 0.0 ? r2 : 0.0);
+  float ms = 0.0f;
+  SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  inf.ms_sketch = ms;
+  SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+  inf.ms_sample = ms;
+  SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+  inf.ms_topk = ms;
+  SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[3], ev[4]));
+  inf.ms_factors = ms;
+  if (info) *info = inf;
+  return SKLS_OK;
+}
+
+}  // namespace skls

@@ -87,8 +87,25 @@ def test_workspace_sizes(lib):
     assert lib.skls_qr_r_workspace(10, 20, ctypes.byref(sz)) == 2
 
 
-def test_low_rank_reports_not_implemented(lib):
-    assert lib.skls_low_rank(ctypes.byref(_mat()), 2, 0.1, 0, None, None, None, None, 0, None) == 8
+def test_low_rank_workspace_checks_options(lib):
+    from paper_1207_6365_amd import _lib as L
+
+    sz = ctypes.c_size_t(0)
+    A = _mat(n=5000, d=300, ld=300)
+    o = L.SklsLowRankOpts()
+    o.k, o.t_r, o.seed = 4, 32, 1
+    assert lib.skls_low_rank_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 0
+    assert sz.value > 5000 * 32 * 8
+    o.k = 0
+    assert lib.skls_low_rank_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 1
+    o.k, o.t_r, o.eps = 4, 0, 0.0  # neither t_r nor eps
+    assert lib.skls_low_rank_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 1
+    o.eps = 0.25  # t_r = max(ceil(k / eps), k + 16), capped by min(n, m)
+    assert lib.skls_low_rank_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 0
+    o.t_r, o.t_s = 32, 16  # fewer draws than t_r
+    assert lib.skls_low_rank_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 1
+    o.t_s, o.k = 0, 60
+    assert lib.skls_low_rank_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 1
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
