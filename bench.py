@@ -12,7 +12,9 @@ Also reported on the same JSON line: the dense float32 variant (n = 2^20),
 sketch-and-solve on the small sparse regression (n = 20000, d = 20), least
 squares on the dense heavy-row regression workload (n = 2^21, d = 512,
 t = 2^18) in the plain float64 form and the mixed-precision forms, leverage
-scores on the same workload, learned sketch values trained on a family of 256
+scores on the same workload, a rank-k approximation of a planted low-rank
+sparse matrix (n = 65536, about 10M nonzeros, k = 32), learned sketch values
+trained on a family of 256
 related matrices and compared with the random signs on held-out ones, the
 roofline of the dominant kernel (measured with HIP events on the
 library's stream), and the oracle timed on the host.
@@ -303,6 +305,42 @@ def main():
         result["leverage"] = {"ms_per_call": el * 1e3, "phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
                               "pass_frac": (n3 * d3 * 4 + n3 * 4) / (lt / max(lc, 1) * 1e-3) / HBM_PEAK}
         del A3g
+        torch.cuda.empty_cache()
+
+        # rank-k approximation of the planted low-rank sparse matrix (65536 x
+        # 65536, about 10M nonzeros, k = 32, t_R = 512); error against the
+        # stored best rank-k error of the same seeded matrix
+        log("low rank: planted sparse n=65536 ~10M nnz, k=32, t_R=512")
+        A4 = W.planted_lowrank_sparse()
+        A4g = sk.Csr(A4.n, A4.d, torch.from_numpy(A4.row_ptr32()).to(dev), torch.from_numpy(A4.col_idx).to(dev),
+                     torch.from_numpy(A4.val).to(dev))
+        gold = {}
+        with open(os.path.join(ROOT, "tests", "golden", "lowrank_planted_n65536_r32.txt")) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    key, v = line.split(":", 1)
+                    gold[key.strip()] = float(v)
+        lr_seed = W.sketch_seed(0)
+        sk.low_rank(A4g, 32, lr_seed, t_r=512)  # warm-up
+        sync()
+        lib.skls_profile_enable(1)
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, _, _, linfo = sk.low_rank(A4g, 32, lr_seed, t_r=512)
+        sync()
+        el = (time.perf_counter() - t0) / reps
+        ph = profile_phases(sk)
+        lib.skls_profile_enable(0)
+        result["low_rank"] = {
+            "ms_per_call": el * 1e3, "nnz": A4.nnz, "k": 32, "t_r": linfo["t_r"], "t_s": linfo["t_s"],
+            "error_ratio": linfo["resid_fro"] / gold["delta_k"], "iterations": linfo["iterations"],
+            "rows_sampled": linfo["rows_sampled"],
+            "ms_phases": {"sketch_and_basis": linfo["ms_sketch"], "scores_and_sampling": linfo["ms_sample"],
+                          "top_k": linfo["ms_topk"], "factors_and_error": linfo["ms_factors"]},
+            "kernel_phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
+        }
+        del A4, A4g
         torch.cuda.empty_cache()
 
         # learned per-row values: the full family of 256 matrices, trained on

@@ -17,7 +17,7 @@
 //      V~ S~^{-1} [U~^T S A]_k = R_Y R'^{-1} [Q'^T S A]_k.
 //   4. [Q'^T S A]_k = P_k C_k by block subspace iteration on M = Q'^T S A
 //      (t_R x m) with p = k + oversample columns, each side orthonormalised
-//      through the eigendecomposition of its p x p Gram (one-sided Jacobi),
+//      through the eigendecomposition of its p x p Gram (Jacobi rotations),
 //      stopped when the top-k Ritz values settle; then the Rayleigh-Ritz
 //      rotation.
 //   5. U X~ = (Y R'^{-1} P_k) C_k = B C_k; with B = Q_B G_B and C_k^T = Q_C G_C
@@ -327,6 +327,31 @@ __global__ void k_sample(int64_t ts, int64_t n, uint64_t seed, const double* __r
   }
 }
 
+// Column counts of a CSR matrix (one atomic per entry).
+__global__ void k_col_count(int64_t nnz, const int32_t* __restrict__ col, int32_t* __restrict__ cnt) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < nnz;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    atomicAdd(cnt + col[e], 1);
+}
+
+// Transpose (CSR -> CSC): entry (r, j, v) goes to slot cp[j] + (running count
+// of column j); rows within a column come in no fixed order.
+__global__ __launch_bounds__(kT) void k_csr_to_csc(int64_t rows, const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                   const int32_t* __restrict__ cp, int32_t* __restrict__ cursor,
+                                                   int32_t* __restrict__ row_out, double* __restrict__ val_out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
+    for (int64_t k = rp[r] + lane; k < rp[r + 1]; k += kWave) {
+      const int32_t j = col[k];
+      const int32_t slot = cp[j] + atomicAdd(cursor + j, 1);
+      row_out[slot] = static_cast<int32_t>(r);
+      val_out[slot] = val[k];
+    }
+  }
+}
+
 __global__ void k_flags(int64_t n, const int32_t* __restrict__ counts, int32_t* __restrict__ flag) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -389,31 +414,65 @@ __global__ __launch_bounds__(kT) void k_gather_csr(int64_t ns, const TR* __restr
 }
 
 // ---------------------------------------------------------------- sparse products
+__device__ __forceinline__ int32_t lane_i(int32_t v, int q) { return __builtin_amdgcn_readlane(v, q); }
+__device__ __forceinline__ double lane_d(double v, int q) {
+  const long long b = __double_as_longlong(v);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(b & 0xffffffffll), q));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(b >> 32), q));
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
 // out (rows x p) = S X for S in CSR (any value and row-pointer type) and X
-// (cols x p, float64); one wavefront per row, lane = column of X (p <= 64).
-// The row's entries are loaded 64 at a time and broadcast lane by lane.
-template <typename TV, typename TR>
+// (cols x p, float64); one wavefront per row.  The row's entries are loaded
+// 64 at a time and read back lane by lane as scalars (uniform index), four
+// independent loads of X in flight.  HALF: p <= 32, the two half-waves take
+// alternate entries and are summed at the end.
+template <typename TV, typename TR, bool HALF>
 __global__ __launch_bounds__(kT) void k_spmm(int64_t rows, int p, const TR* __restrict__ rp,
                                              const int32_t* __restrict__ col, const TV* __restrict__ val,
                                              const double* __restrict__ X, double* __restrict__ out) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
-  const int lc = lane < p ? lane : 0;
+  const int c = HALF ? (lane & 31) : lane;
+  const int h = HALF ? (lane >> 5) : 0;
+  const bool live = c < p;
+  const int lc = live ? c : 0;
+  constexpr int STEP = HALF ? 2 : 1;
   for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
     const int64_t b = static_cast<int64_t>(rp[r]), e = static_cast<int64_t>(rp[r + 1]);
-    double acc = 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
     for (int64_t k0 = b; k0 < e; k0 += kWave) {
       const int64_t k = k0 + lane;
       const int32_t cj = k < e ? col[k] : 0;
-      const double vj = k < e ? load_as<double>(val, static_cast<size_t>(k)) : 0.0;
+      const double vj = k < e ? load_as<double>(val, static_cast<size_t>(k)) : 0.0;  // 0 beyond the row
       const int cnt = (e - k0) < kWave ? static_cast<int>(e - k0) : kWave;
-      for (int q = 0; q < cnt; ++q) {
-        const int32_t j = __shfl(cj, q);
-        const double v = __shfl(vj, q);
-        acc += v * X[static_cast<size_t>(j) * p + lc];
+      const int cnt_up = (cnt + 4 * STEP - 1) / (4 * STEP) * (4 * STEP);  // zero values pad the tail
+      for (int q = 0; q < cnt_up; q += 4 * STEP) {
+        int32_t j[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int qa = q + u * STEP;
+          if (HALF) {
+            const int32_t ja = lane_i(cj, qa), jb = lane_i(cj, qa + 1);
+            const double va = lane_d(vj, qa), vb = lane_d(vj, qa + 1);
+            j[u] = h ? jb : ja;
+            v[u] = h ? vb : va;
+          } else {
+            j[u] = lane_i(cj, qa);
+            v[u] = lane_d(vj, qa);
+          }
+        }
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = X[static_cast<size_t>(j[u]) * p + lc];
+        acc0 += v[0] * x[0] + v[2] * x[2];
+        acc1 += v[1] * x[1] + v[3] * x[3];
       }
     }
-    if (lane < p) out[static_cast<size_t>(r) * p + lane] = acc;
+    double acc = acc0 + acc1;
+    if (HALF) acc += __shfl_xor(acc, 32);
+    if (live && h == 0) out[static_cast<size_t>(r) * p + c] = acc;
   }
 }
 
@@ -432,10 +491,7 @@ __global__ __launch_bounds__(kT) void k_dense_times(int64_t rows, int64_t cols, 
       const int64_t j = j0 + lane;
       const double aj = j < cols ? load_as<double>(A, static_cast<size_t>(r) * ld + j) : 0.0;
       const int cnt = (cols - j0) < kWave ? static_cast<int>(cols - j0) : kWave;
-      for (int q = 0; q < cnt; ++q) {
-        const double v = __shfl(aj, q);
-        acc += v * X[static_cast<size_t>(j0 + q) * p + lc];
-      }
+      for (int q = 0; q < cnt; ++q) acc += lane_d(aj, q) * X[static_cast<size_t>(j0 + q) * p + lc];
     }
     if (lane < p) out[static_cast<size_t>(r) * p + lane] = acc;
   }
@@ -450,30 +506,6 @@ __global__ void k_small_abt(int k, const double* __restrict__ A, const double* _
   double s = 0.0;
   for (int l = 0; l < k; ++l) s += A[i * k + l] * B[j * k + l];
   C[e] = s;
-}
-
-// out (cols x p) += S^T X for S (CSR, rows x cols) and X (rows x p): row r
-// adds val * X[r, :] into out[col, :] with float64 atomics (out zeroed first).
-__global__ __launch_bounds__(kT) void k_spmm_t(int64_t rows, int p, const int64_t* __restrict__ rp,
-                                               const int32_t* __restrict__ col, const double* __restrict__ val,
-                                               const double* __restrict__ X, double* __restrict__ out) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
-  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
-    const int64_t b = rp[r], e = rp[r + 1];
-    const double x = lane < p ? X[static_cast<size_t>(r) * p + lane] : 0.0;
-    for (int64_t k0 = b; k0 < e; k0 += kWave) {
-      const int64_t k = k0 + lane;
-      const int32_t cj = k < e ? col[k] : 0;
-      const double vj = k < e ? val[k] : 0.0;
-      const int cnt = (e - k0) < kWave ? static_cast<int>(e - k0) : kWave;
-      for (int q = 0; q < cnt; ++q) {
-        const int32_t j = __shfl(cj, q);
-        const double v = __shfl(vj, q);
-        if (lane < p) unsafeAtomicAdd(out + static_cast<size_t>(j) * p + lane, v * x);
-      }
-    }
-  }
 }
 
 // ---------------------------------------------------------------- one-sided Jacobi
@@ -496,6 +528,9 @@ __global__ __launch_bounds__(1024) void k_jacobi(int r, int c, const double* __r
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int nwaves = blockDim.x / kWave;
   const int cc = c + (c & 1);  // even count (a zero column pads odd c)
+  // pairs count as orthogonal once |<a_p, a_q>| is within twice the rounding
+  // error of an r-term dot product
+  const double tol = 2.0 * (r > 1 ? r : 1) * 0x1.0p-52;
   for (int e = tid; e < kMaxP * kMaxP; e += blockDim.x) {
     const int j = e / kMaxP, i = e % kMaxP;
     a[j][i] = (j < c && i < r) ? G[i * c + j] : 0.0;
@@ -504,6 +539,11 @@ __global__ __launch_bounds__(1024) void k_jacobi(int r, int c, const double* __r
   for (int e = tid; e < cc; e += blockDim.x) pos[e] = e;
   for (int e = tid; e < kMaxP; e += blockDim.x) perm[e] = e < c ? e : 0;
   __syncthreads();
+  // rounding leaves |<a_p, a_q>| of order r u ||G||_F^2 at best
+  double fro2 = 0.0;
+  for (int j = 0; j < c; ++j)
+    for (int i = 0; i < r; ++i) fro2 += a[j][i] * a[j][i];
+  const double floor_abs = tol * fro2;
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -515,7 +555,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(int r, int c, const double* __r
         const int p = pos[x0], q = pos[x1];
         const double ap = a[p][lane], aq = a[q][lane];
         const double al = wave_total(ap * ap), be = wave_total(aq * aq), ga = wave_total(ap * aq);
-        if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+        if (fabs(ga) > floor_abs && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
@@ -557,21 +597,181 @@ __global__ __launch_bounds__(1024) void k_jacobi(int r, int c, const double* __r
   if (tid < c) sig[tid] = nrm[perm[tid]];
 }
 
-// Orthonormalising map from the eigendecomposition G = V diag(lam) V^T of a
-// p x p Gram: Mx = V diag(lam^{-1/2}) (zero for lam <= floor * lam_max) and
-// the factor F = diag(lam^{1/2}) V^T, so that X = (X Mx) F on the span kept.
+// Eigendecomposition of a symmetric c x c matrix (c <= 64) held in LDS, by
+// the cyclic two-sided Jacobi method with a round-robin ordering.  Each
+// round rotates the c/2 disjoint pairs of its schedule: one thread per pair
+// computes the rotation from the current matrix, then each thread applies
+// G <- J^T G J to one 2 x 2 block (row pair x column pair) and V <- V J to
+// rows of one column pair.  Sweeps end when no pair has |g_pq| above twice
+// the rounding level of a c-term sum, relative to sqrt(|g_pp g_qq|) and to
+// max |g_ii| (below the latter rounding alone can keep it), at most 60.
+// All 1024 threads of the block call it; g and v are c padded to even cc.
+struct JacLds {
+  double g[kMaxP][kMaxP + 1];
+  double v[kMaxP][kMaxP + 1];
+  uint8_t tp[kMaxP][kMaxP / 2], tq[kMaxP][kMaxP / 2];  // schedule: round x pair
+  double rc[kMaxP / 2], rs[kMaxP / 2];
+  int rotated;
+};
+
+__device__ void jacobi_sym_lds(int c, JacLds& L) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int cc = c + (c & 1);
+  const int np = cc / 2;
+  const double tol = 2.0 * (c > 1 ? c : 1) * 0x1.0p-52;
+  for (int e = tid; e < (cc - 1) * np; e += nt) {
+    const int round = e / np, pr = e % np;
+    L.tp[round][pr] = static_cast<uint8_t>(pr == 0 ? 0 : 1 + (pr - 1 + round) % (cc - 1));
+    L.tq[round][pr] = static_cast<uint8_t>(1 + (cc - 2 - pr + round) % (cc - 1));
+  }
+  double dmax = 0.0;
+  for (int i = 0; i < c; ++i) dmax = fmax(dmax, fabs(L.g[i][i]));
+  const double floor_abs = tol * dmax;
+  __syncthreads();
+  // block (a, b) of this thread for the G update; (row, pair) items for V
+  const int ba = tid / np, bb = tid % np;
+  const bool gblk = tid < np * np;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) L.rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < cc - 1; ++round) {
+      if (tid < np) {
+        const int p = L.tp[round][tid], q = L.tq[round][tid];
+        const double al = L.g[p][p], be = L.g[q][q], ga = L.g[p][q];
+        double cs = 1.0, sn = 0.0;
+        if (fabs(ga) > floor_abs && fabs(ga) > tol * sqrt(fabs(al * be))) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          cs = rsqrt(1.0 + t * t);
+          sn = cs * t;
+          L.rotated = 1;
+        }
+        L.rc[tid] = cs;
+        L.rs[tid] = sn;
+      }
+      __syncthreads();
+      if (gblk) {
+        const int pa = L.tp[round][ba], qa = L.tq[round][ba], pb = L.tp[round][bb], qb = L.tq[round][bb];
+        const double ca = L.rc[ba], sa = L.rs[ba], cb = L.rc[bb], sb = L.rs[bb];
+        // columns: (x_pb, x_qb) -> (cb x_pb - sb x_qb, sb x_pb + cb x_qb)
+        const double g00 = L.g[pa][pb], g01 = L.g[pa][qb], g10 = L.g[qa][pb], g11 = L.g[qa][qb];
+        const double h00 = cb * g00 - sb * g01, h01 = sb * g00 + cb * g01;
+        const double h10 = cb * g10 - sb * g11, h11 = sb * g10 + cb * g11;
+        // rows: (y_pa, y_qa) -> (ca y_pa - sa y_qa, sa y_pa + ca y_qa)
+        L.g[pa][pb] = ca * h00 - sa * h10;
+        L.g[qa][pb] = sa * h00 + ca * h10;
+        L.g[pa][qb] = ca * h01 - sa * h11;
+        L.g[qa][qb] = sa * h01 + ca * h11;
+      }
+      for (int e = tid; e < cc * 32; e += nt) {
+        const int i = e >> 5, pr = e & 31;
+        if (pr < np) {
+          const int p = L.tp[round][pr], q = L.tq[round][pr];
+          const double cs = L.rc[pr], sn = L.rs[pr];
+          const double vp = L.v[i][p], vq = L.v[i][q];
+          L.v[i][p] = cs * vp - sn * vq;
+          L.v[i][q] = sn * vp + cs * vq;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = L.rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+}
+
+__device__ void jacobi_load(int c, const double* __restrict__ G, JacLds& L) {
+  for (int e = threadIdx.x; e < kMaxP * kMaxP; e += blockDim.x) {
+    const int i = e / kMaxP, j = e % kMaxP;
+    L.g[i][j] = (i < c && j < c) ? G[i * c + j] : 0.0;
+    L.v[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+}
+
+// Rank of diagonal entry tid among the first c (decreasing, ties by index).
+__device__ int diag_rank(int c, const JacLds& L, int tid) {
+  int rank = 0;
+  const double d = L.g[tid][tid];
+  for (int i = 0; i < c; ++i) rank += (L.g[i][i] > d || (L.g[i][i] == d && i < tid)) ? 1 : 0;
+  return rank;
+}
+
+// G = V diag(lam) V^T for a symmetric c x c G; lam decreasing, V's columns
+// permuted alike.
+__global__ __launch_bounds__(1024) void k_jacobi_sym(int c, const double* __restrict__ G, double* __restrict__ lam,
+                                                     double* __restrict__ V) {
+  __shared__ JacLds L;
+  __shared__ int perm[kMaxP];
+  jacobi_load(c, G, L);
+  jacobi_sym_lds(c, L);
+  if (threadIdx.x < c) perm[diag_rank(c, L, threadIdx.x)] = threadIdx.x;
+  __syncthreads();
+  for (int e = threadIdx.x; e < c * c; e += blockDim.x) V[e] = L.v[e / c][perm[e % c]];
+  if (threadIdx.x < c) lam[threadIdx.x] = L.g[perm[threadIdx.x]][perm[threadIdx.x]];
+}
+
+// Orthonormalising maps from the c x c Gram G = X^T X: Mx with X Mx having
+// orthonormal columns and F with X = (X Mx) F on the span kept.  Near the
+// identity (||G - I||_inf <= 1e-5) by the series G^{-1/2} = I - E/2 + 3E^2/8
+// and G^{1/2} = I + E/2 - E^2/8 (E = G - I; the rest is O(||E||^3));
+// otherwise from the eigendecomposition G = V diag(lam) V^T:
+// Mx = V diag(lam^{-1/2}), F = diag(lam^{1/2}) V^T, with directions of
+// eigenvalue <= floor_rel * lam_max dropped (zero columns).
+__global__ __launch_bounds__(1024) void k_orth_maps(int c, const double* __restrict__ G, double floor_rel,
+                                                    double* __restrict__ Mx, double* __restrict__ F) {
+  __shared__ JacLds L;
+  __shared__ double rowsum[kMaxP];
+  __shared__ double lam[kMaxP];
+  const int tid = threadIdx.x;
+  jacobi_load(c, G, L);
+  if (tid < c) {
+    double sacc = 0.0;
+    for (int j = 0; j < c; ++j) sacc += fabs(L.g[tid][j] - (tid == j ? 1.0 : 0.0));
+    rowsum[tid] = sacc;
+  }
+  __syncthreads();
+  double enorm = 0.0;
+  for (int i = 0; i < c; ++i) enorm = fmax(enorm, rowsum[i]);
+  if (enorm <= 1e-5) {
+    for (int e = tid; e < c * c; e += blockDim.x) {
+      const int i = e / c, j = e % c;
+      double e2 = 0.0;
+      for (int l = 0; l < c; ++l)
+        e2 += (L.g[i][l] - (i == l ? 1.0 : 0.0)) * (L.g[l][j] - (l == j ? 1.0 : 0.0));
+      const double eij = L.g[i][j] - (i == j ? 1.0 : 0.0);
+      const double id = i == j ? 1.0 : 0.0;
+      Mx[e] = id - 0.5 * eij + 0.375 * e2;
+      F[e] = id + 0.5 * eij - 0.125 * e2;
+    }
+    return;
+  }
+  jacobi_sym_lds(c, L);
+  if (tid < c) lam[tid] = L.g[tid][tid];
+  __syncthreads();
+  double lmax = 0.0;
+  for (int i = 0; i < c; ++i) lmax = fmax(lmax, lam[i]);
+  for (int e = tid; e < c * c; e += blockDim.x) {
+    const int i = e / c, j = e % c;
+    const double lj = lam[j], li = lam[i];
+    const bool keepj = lj > floor_rel * lmax && lj > 0.0;
+    const bool keepi = li > floor_rel * lmax && li > 0.0;
+    Mx[e] = keepj ? L.v[i][j] / sqrt(lj) : 0.0;          // V[i][j] lam_j^{-1/2}
+    F[e] = keepi ? sqrt(li) * L.v[j][i] : 0.0;           // lam_i^{1/2} V[j][i]
+  }
+}
+
+// F' = F V lam^{-1/2} map (columns of eigenvalue <= floor_rel * lam_max
+// dropped) from an eigendecomposition already at hand.
 __global__ void k_svqb_maps(int p, const double* __restrict__ lam, const double* __restrict__ V, double floor_rel,
-                            double* __restrict__ Mx, double* __restrict__ F) {
+                            double* __restrict__ Mx) {
   const int e = threadIdx.x + blockIdx.x * blockDim.x;
   if (e >= p * p) return;
-  const int i = e / p, j = e % p;
-  const double lmax = lam[0];
+  const int j = e % p;
   const double lj = lam[j];
-  const bool keep = lj > floor_rel * lmax && lj > 0.0;
-  Mx[e] = keep ? V[e] / sqrt(lj) : 0.0;               // Mx[i][j] = V[i][j] lam_j^{-1/2}
-  const double li = lam[i];
-  const bool keepi = li > floor_rel * lmax && li > 0.0;
-  F[e] = keepi ? sqrt(li) * V[j * p + i] : 0.0;       // F[i][j] = lam_i^{1/2} V[j][i]
+  const bool keep = lj > floor_rel * lam[0] && lj > 0.0;
+  Mx[e] = keep ? V[e] / sqrt(lj) : 0.0;
 }
 
 // ---------------------------------------------------------------- residual
@@ -652,9 +852,9 @@ int32_t gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const doubl
   if (M == 0 || N == 0) return SKLS_OK;
   const int64_t tiles = div_up(M, 64) * div_up(N, 64);
   int64_t splits = 1;
-  if (tiles < 256 && K > 2048) {
+  if (tiles < 256 && K > 1024) {
     splits = div_up(512, tiles);
-    const int64_t by_k = div_up(K, 1024);
+    const int64_t by_k = div_up(K, 256);
     if (splits > by_k) splits = by_k;
     if (splits > 256) splits = 256;
     while (splits > 1 && static_cast<size_t>(splits) * M * N > sc.doubles) --splits;
@@ -714,6 +914,9 @@ struct LrWs {
   int64_t *len, *rp, *ltiles;
   int32_t* colc;
   double* valc;
+  int32_t* rowT;
+  double* valT;
+  int32_t *cp, *ccnt, *ctiles;
   double *SY, *Q, *F, *Ft, *G1, *X1, *P, *Pt;
   GemmScratch part;
   double *Gp, *V, *Wj, *lam, *Mx, *F1, *F2, *Fac;
@@ -761,6 +964,11 @@ LrWs carve_lr(Arena& ar, const LowRankPlan& P) {
   w.ltiles = ar.take<int64_t>(lr_tiles(ns));
   w.colc = P.csr ? ar.take<int32_t>(P.nnzmax) : nullptr;
   w.valc = ar.take<double>(P.nnzmax);
+  w.rowT = P.csr ? ar.take<int32_t>(P.nnzmax) : nullptr;
+  w.valT = P.csr ? ar.take<double>(P.nnzmax) : nullptr;
+  w.cp = P.csr ? ar.take<int32_t>(m + 1) : nullptr;
+  w.ccnt = P.csr ? ar.take<int32_t>(m + 1) : nullptr;
+  w.ctiles = P.csr ? ar.take<int32_t>(lr_tiles(m + 1)) : nullptr;
   w.SY = ar.take<double>(static_cast<size_t>(ns) * tr);
   w.Q = ar.take<double>(static_cast<size_t>(ns) * tr);
   w.F = ar.take<double>(static_cast<size_t>(m) * p);
@@ -805,17 +1013,13 @@ int32_t to_host(void* dst, const void* src, size_t bytes, hipStream_t s) {
 }
 
 // X (rows x c, packed) -> X with orthonormal columns (two passes of
-// eigendecomposition-based orthonormalisation); fac (c x c) with
-// X_in = X_out fac; lam gets the eigenvalues of the first pass's Gram.
+// Gram-based orthonormalisation); fac (c x c) with X_in = X_out fac.
 int32_t svqb2(double* X, double* tmp, int64_t rows, int c, double* fac, LrWs& w, hipStream_t s) {
   double* cur = X;
   double* nxt = tmp;
   for (int pass = 0; pass < 2; ++pass) {
     SKLS_TRY(run_gram(cur, SKLS_F64, c, nullptr, SKLS_F64, rows, c, w.Gp, w.gram, w.gram_bytes, s));
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, c, c, w.Gp, w.lam, w.V, w.Wj);
-    SKLS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_svqb_maps, dim3(grid_for(c * c, kT, 64)), dim3(kT), 0, s, c, w.lam, w.V, kDropRel, w.Mx,
-                       pass == 0 ? w.F1 : w.F2);
+    hipLaunchKernelGGL(k_orth_maps, dim3(1), dim3(1024), 0, s, c, w.Gp, kDropRel, w.Mx, pass == 0 ? w.F1 : w.F2);
     SKLS_CHECK_LAUNCH();
     SKLS_TRY(gemm(false, rows, c, c, 1.0, cur, c, w.Mx, c, nxt, c, w.part, s));
     std::swap(cur, nxt);
@@ -1010,6 +1214,20 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
         hipLaunchKernelGGL((k_gather_csr<TV, TR>), dim3(grid_for(ns, kT / kWave, 8192)), dim3(kT), 0, s, ns, rpA,
                            A.col_idx, static_cast<const TV*>(A.val), w.list, w.wts, w.rp, w.colc, w.valc);
         SKLS_CHECK_LAUNCH();
+        // the transpose of the sampled rows, for the products with (S A)^T
+        if (nnz_s >= (int64_t(1) << 31)) {
+          set_error("low_rank: the sampled rows hold 2^31 or more nonzeros");
+          return SKLS_ERR_SHAPE;
+        }
+        const size_t cbytes = static_cast<size_t>((m + 1 + 3) / 4) * 16;
+        SKLS_TRY(launch_fill_zero(w.ccnt, cbytes, s));
+        hipLaunchKernelGGL(k_col_count, dim3(grid_for(nnz_s, kT, 8192)), dim3(kT), 0, s, nnz_s, w.colc, w.ccnt);
+        SKLS_CHECK_LAUNCH();
+        SKLS_TRY(scan<int32_t>(w.ccnt, m + 1, w.ctiles, w.cp, true, s));  // cp[m] = nnz_s
+        SKLS_TRY(launch_fill_zero(w.ccnt, cbytes, s));
+        hipLaunchKernelGGL(k_csr_to_csc, dim3(grid_for(ns, kT / kWave, 8192)), dim3(kT), 0, s, ns, w.rp, w.colc,
+                           w.valc, w.cp, w.ccnt, w.rowT, w.valT);
+        SKLS_CHECK_LAUNCH();
         return SKLS_OK;
       });
     });
@@ -1039,8 +1257,12 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
     const unsigned gr = grid_for(ns, kT / kWave, 8192);
     auto times_SA = [&](const double* X, double* out) -> int32_t {  // out (ns x p) = S A X
       if (P.csr) {
-        hipLaunchKernelGGL((k_spmm<double, int64_t>), dim3(gr), dim3(kT), 0, s, ns, p, w.rp, w.colc, w.valc, X,
-                           out);
+        if (p <= 32)
+          hipLaunchKernelGGL((k_spmm<double, int64_t, true>), dim3(gr), dim3(kT), 0, s, ns, p, w.rp, w.colc, w.valc,
+                             X, out);
+        else
+          hipLaunchKernelGGL((k_spmm<double, int64_t, false>), dim3(gr), dim3(kT), 0, s, ns, p, w.rp, w.colc, w.valc,
+                             X, out);
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
       }
@@ -1048,8 +1270,13 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
     };
     auto times_SAt = [&](const double* X, double* out) -> int32_t {  // out (m x p) = (S A)^T X
       if (P.csr) {
-        SKLS_TRY(launch_fill_zero(out, static_cast<size_t>(m) * p * sizeof(double), s));
-        hipLaunchKernelGGL(k_spmm_t, dim3(gr), dim3(kT), 0, s, ns, p, w.rp, w.colc, w.valc, X, out);
+        const unsigned gm = grid_for(m, kT / kWave, 8192);
+        if (p <= 32)
+          hipLaunchKernelGGL((k_spmm<double, int32_t, true>), dim3(gm), dim3(kT), 0, s, m, p, w.cp, w.rowT, w.valT,
+                             X, out);
+        else
+          hipLaunchKernelGGL((k_spmm<double, int32_t, false>), dim3(gm), dim3(kT), 0, s, m, p, w.cp, w.rowT, w.valT,
+                             X, out);
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
       }
@@ -1065,7 +1292,7 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
       SKLS_TRY(gemm(false, ns, p, tr, 1.0, w.Q, tr, w.P, p, w.X1, p, w.part, s));
       SKLS_TRY(times_SAt(w.X1, w.F));  // F = M^T P
       SKLS_TRY(run_gram(w.F, SKLS_F64, p, nullptr, SKLS_F64, m, p, w.Gp, w.gram, w.gram_bytes, s));
-      hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, p, p, w.Gp, w.lam, w.V, w.Wj);
+      hipLaunchKernelGGL(k_jacobi_sym, dim3(1), dim3(1024), 0, s, p, w.Gp, w.lam, w.V);
       SKLS_CHECK_LAUNCH();
       SKLS_TRY(to_host(cur.data(), w.lam, sizeof(double) * p, s));
       ++it;
@@ -1081,7 +1308,7 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
       prev = cur;
       // keep F well conditioned for the next product: F <- F V lam^{-1/2}
       hipLaunchKernelGGL(k_svqb_maps, dim3(grid_for(p * p, kT, 64)), dim3(kT), 0, s, p, w.lam, w.V, kDropRel,
-                         w.Mx, w.F1);
+                         w.Mx);
       SKLS_CHECK_LAUNCH();
       SKLS_TRY(gemm(false, m, p, p, 1.0, w.F, p, w.Mx, p, w.Ft, p, w.part, s));
       std::swap(w.F, w.Ft);
@@ -1123,8 +1350,12 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
       }
       return with_rowptr(A, [&](auto trt) -> int32_t {
         using TR = decltype(trt);
-        hipLaunchKernelGGL((k_spmm<TV, TR>), dim3(g), dim3(kT), 0, s, n, ki, static_cast<const TR*>(A.row_ptr),
-                           A.col_idx, static_cast<const TV*>(A.val), Wout, w.AW);
+        if (ki <= 32)
+          hipLaunchKernelGGL((k_spmm<TV, TR, true>), dim3(g), dim3(kT), 0, s, n, ki,
+                             static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), Wout, w.AW);
+        else
+          hipLaunchKernelGGL((k_spmm<TV, TR, false>), dim3(g), dim3(kT), 0, s, n, ki,
+                             static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), Wout, w.AW);
         SKLS_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_sumsq<TV>, dim3(w.nblk), dim3(kT), 0, s, A.nnz, static_cast<const TV*>(A.val),
                            int64_t(-1), int64_t(0), int64_t(0), ki, w.dots);
