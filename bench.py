@@ -47,6 +47,9 @@ def parse():
     p.add_argument("--no-lstsq", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--lstsq-steps", type=int, default=3)
+    p.add_argument("--only", default=None,
+                   choices=["dense", "small", "lstsq", "leverage", "low_rank", "learned"],
+                   help="run only this extra workload after the headline")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run a plain device copy of this many MiB first (scale for HBM byte counters)")
     return p.parse_args()
@@ -126,6 +129,9 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    def want(name):
+        return args.only is None or args.only == name
+
     if args.calib_copy_mib > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
         # calibrate the byte counters taken on the sketch kernels
@@ -202,212 +208,218 @@ def main():
 
     # ------------------------------------------------------------ extras
     if not args.no_extras:
-        log("dense float32 variant (n=2^20, d=256)")
-        D, _ = W.sketch_dense()
-        Dg = torch.from_numpy(D).to(dev)
-        dm, _ = sk.api._matrix(Dg)
-        sk._lib.check(lib.skls_sketch_workspace(ctypes.byref(dm), t, variant, ctypes.byref(ws_bytes)))
-        wsd = torch.empty(max(ws_bytes.value, 1), dtype=torch.uint8, device=dev)
+        if want("dense"):
+            log("dense float32 variant (n=2^20, d=256)")
+            D, _ = W.sketch_dense()
+            Dg = torch.from_numpy(D).to(dev)
+            dm, _ = sk.api._matrix(Dg)
+            sk._lib.check(lib.skls_sketch_workspace(ctypes.byref(dm), t, variant, ctypes.byref(ws_bytes)))
+            wsd = torch.empty(max(ws_bytes.value, 1), dtype=torch.uint8, device=dev)
 
-        def dstep():
-            sk._lib.check(lib.skls_sketch(ctypes.byref(dm), None, 0, t, seed, None, variant, SA.data_ptr(), None, 1,
-                                          wsd.data_ptr(), wsd.numel(), stream))
+            def dstep():
+                sk._lib.check(lib.skls_sketch(ctypes.byref(dm), None, 0, t, seed, None, variant, SA.data_ptr(), None, 1,
+                                              wsd.data_ptr(), wsd.numel(), stream))
 
-        lib.skls_profile_enable(1)
-        dms = time_steps(dstep, max(args.steps // 2, 5), 3, sync)
-        dph = profile_phases(sk)
-        lib.skls_profile_enable(0)
-        dbytes = 4 * D.size + 4 * t * D.shape[1]
-        dk = dph.get("sketch_apply", (1, float("nan")))
-        result["dense"] = {"entries_per_s": D.size / (dms * 1e-3), "ms_per_step": dms,
-                           "kernel_frac": dbytes / (dk[1] / max(dk[0], 1) * 1e-3) / HBM_PEAK,
-                           "step_frac": dbytes / (dms * 1e-3) / HBM_PEAK}
-        del Dg, D
+            lib.skls_profile_enable(1)
+            dms = time_steps(dstep, max(args.steps // 2, 5), 3, sync)
+            dph = profile_phases(sk)
+            lib.skls_profile_enable(0)
+            dbytes = 4 * D.size + 4 * t * D.shape[1]
+            dk = dph.get("sketch_apply", (1, float("nan")))
+            result["dense"] = {"entries_per_s": D.size / (dms * 1e-3), "ms_per_step": dms,
+                               "kernel_frac": dbytes / (dk[1] / max(dk[0], 1) * 1e-3) / HBM_PEAK,
+                               "step_frac": dbytes / (dms * 1e-3) / HBM_PEAK}
+            del Dg, D
 
-        log("small sparse regression: sketch-and-solve, n=20000 d=20 4 nnz/row float64, t=4000")
-        A1, b1, _ = W.lstsq_small()
-        A1g = sk.Csr(A1.n, A1.d, torch.from_numpy(A1.row_ptr32()).to(dev), torch.from_numpy(A1.col_idx).to(dev),
-                     torch.from_numpy(A1.val).to(dev))
-        b1g = torch.from_numpy(b1).to(dev)
-        for _ in range(3):
-            x1, info1 = sk.lstsq(A1g, b1g, 4000, seed, sketch_only=True)
-        sync()
-        reps = 50
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            x1, info1 = sk.lstsq(A1g, b1g, 4000, seed, sketch_only=True)
-        sync()
-        el = (time.perf_counter() - t0) / reps
-        result["lstsq_small"] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
-                                 "note": "sketch-and-solve only (no LSQR), launch-bound; parity with the oracle is "
-                                         "in the tests"}
-        del A1g, b1g
+        if want("small"):
+            log("small sparse regression: sketch-and-solve, n=20000 d=20 4 nnz/row float64, t=4000")
+            A1, b1, _ = W.lstsq_small()
+            A1g = sk.Csr(A1.n, A1.d, torch.from_numpy(A1.row_ptr32()).to(dev), torch.from_numpy(A1.col_idx).to(dev),
+                         torch.from_numpy(A1.val).to(dev))
+            b1g = torch.from_numpy(b1).to(dev)
+            for _ in range(3):
+                x1, info1 = sk.lstsq(A1g, b1g, 4000, seed, sketch_only=True)
+            sync()
+            reps = 50
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                x1, info1 = sk.lstsq(A1g, b1g, 4000, seed, sketch_only=True)
+            sync()
+            el = (time.perf_counter() - t0) / reps
+            result["lstsq_small"] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
+                                     "note": "sketch-and-solve only (no LSQR), launch-bound; parity with the oracle is "
+                                             "in the tests"}
+            del A1g, b1g
 
     # ------------------------------------------------------------ least squares
     if not args.no_lstsq:
         n3, d3, t3 = 1 << 21, 512, 1 << 18
-        res = {}
-        for storage, precision in (("f32", "plain"), ("f32", "mixed"), ("bf16", "mixed")):
-            log(f"least squares: dense heavy-row workload n=2^21 d=512 t=2^18, {storage} storage, {precision}")
-            A3, b3, _ = W.pareto_rows(n=n3, d=d3, storage=storage)
-            A3g = (torch.from_numpy(A3.view(np.int16)).to(dev).view(torch.bfloat16) if storage == "bf16"
-                   else torch.from_numpy(A3).to(dev))
-            del A3
-            b3g = torch.from_numpy(b3).to(dev)
-            x, info = sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision)  # warm-up
+        if want("lstsq"):
+            res = {}
+            for storage, precision in (("f32", "plain"), ("f32", "mixed"), ("bf16", "mixed")):
+                log(f"least squares: dense heavy-row workload n=2^21 d=512 t=2^18, {storage} storage, {precision}")
+                A3, b3, _ = W.pareto_rows(n=n3, d=d3, storage=storage)
+                A3g = (torch.from_numpy(A3.view(np.int16)).to(dev).view(torch.bfloat16) if storage == "bf16"
+                       else torch.from_numpy(A3).to(dev))
+                del A3
+                b3g = torch.from_numpy(b3).to(dev)
+                x, info = sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision)  # warm-up
+                sync()
+                lib.skls_profile_enable(1)
+                t0 = time.perf_counter()
+                infos = []
+                for _ in range(args.lstsq_steps):
+                    x, info = sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision)
+                    infos.append(info)
+                sync()
+                el = (time.perf_counter() - t0) / args.lstsq_steps
+                ph = profile_phases(sk)
+                lib.skls_profile_enable(0)
+                key = f"{storage}_{precision}"
+                pass_name = "lsqr_pass_f64" if precision == "plain" else "lsqr_pass_f32"
+                pc, pt_ = ph.get(pass_name, (1, float("nan")))
+                es = 2 if storage == "bf16" else 4
+                pass_bytes = n3 * d3 * es + n3 * (8 if precision == "plain" else 4) * 2
+                res[key] = {
+                    "solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
+                    "certified": all(i["certified"] == 1 for i in infos),
+                    "ratio_bound": max(i["ratio_bound"] for i in infos),
+                    "iterations": infos[-1]["iterations"], "refinements": infos[-1]["refinements"],
+                    "ms_sketch": infos[-1]["ms_sketch"], "ms_qr": infos[-1]["ms_qr"], "ms_iter": infos[-1]["ms_iter"],
+                    "pass_frac": pass_bytes / (pt_ / max(pc, 1) * 1e-3) / HBM_PEAK,
+                    "phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
+                }
+                del A3g, b3g
+                torch.cuda.empty_cache()
+            result["lstsq"] = res
+
+        if want("leverage"):
+            # leverage scores on the same heavy-row workload (float32 storage), k = 32
+            log("leverage scores: n=2^21 d=512 float32, t=2^18, k=32")
+            A3, b3, _ = W.pareto_rows(n=n3, d=d3, storage="f32")
+            A3g = torch.from_numpy(A3).to(dev)
+            del A3, b3
+            Pi2 = torch.from_numpy(np.random.default_rng(7).standard_normal((d3, 32)) / np.sqrt(32.0)).to(dev)
+            sk.leverage_scores(A3g, t3, seed, Pi2)
             sync()
             lib.skls_profile_enable(1)
             t0 = time.perf_counter()
-            infos = []
-            for _ in range(args.lstsq_steps):
-                x, info = sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision)
-                infos.append(info)
+            reps = 3
+            for _ in range(reps):
+                sk.leverage_scores(A3g, t3, seed, Pi2)
             sync()
-            el = (time.perf_counter() - t0) / args.lstsq_steps
+            el = (time.perf_counter() - t0) / reps
             ph = profile_phases(sk)
             lib.skls_profile_enable(0)
-            key = f"{storage}_{precision}"
-            pass_name = "lsqr_pass_f64" if precision == "plain" else "lsqr_pass_f32"
-            pc, pt_ = ph.get(pass_name, (1, float("nan")))
-            es = 2 if storage == "bf16" else 4
-            pass_bytes = n3 * d3 * es + n3 * (8 if precision == "plain" else 4) * 2
-            res[key] = {
-                "solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
-                "certified": all(i["certified"] == 1 for i in infos),
-                "ratio_bound": max(i["ratio_bound"] for i in infos),
-                "iterations": infos[-1]["iterations"], "refinements": infos[-1]["refinements"],
-                "ms_sketch": infos[-1]["ms_sketch"], "ms_qr": infos[-1]["ms_qr"], "ms_iter": infos[-1]["ms_iter"],
-                "pass_frac": pass_bytes / (pt_ / max(pc, 1) * 1e-3) / HBM_PEAK,
-                "phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
-            }
-            del A3g, b3g
+            lc, lt = ph.get("leverage", (1, float("nan")))
+            result["leverage"] = {"ms_per_call": el * 1e3, "phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
+                                  "pass_frac": (n3 * d3 * 4 + n3 * 4) / (lt / max(lc, 1) * 1e-3) / HBM_PEAK}
+            del A3g
             torch.cuda.empty_cache()
-        result["lstsq"] = res
 
-        # leverage scores on the same heavy-row workload (float32 storage), k = 32
-        log("leverage scores: n=2^21 d=512 float32, t=2^18, k=32")
-        A3, b3, _ = W.pareto_rows(n=n3, d=d3, storage="f32")
-        A3g = torch.from_numpy(A3).to(dev)
-        del A3, b3
-        Pi2 = torch.from_numpy(np.random.default_rng(7).standard_normal((d3, 32)) / np.sqrt(32.0)).to(dev)
-        sk.leverage_scores(A3g, t3, seed, Pi2)
-        sync()
-        lib.skls_profile_enable(1)
-        t0 = time.perf_counter()
-        reps = 3
-        for _ in range(reps):
-            sk.leverage_scores(A3g, t3, seed, Pi2)
-        sync()
-        el = (time.perf_counter() - t0) / reps
-        ph = profile_phases(sk)
-        lib.skls_profile_enable(0)
-        lc, lt = ph.get("leverage", (1, float("nan")))
-        result["leverage"] = {"ms_per_call": el * 1e3, "phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
-                              "pass_frac": (n3 * d3 * 4 + n3 * 4) / (lt / max(lc, 1) * 1e-3) / HBM_PEAK}
-        del A3g
-        torch.cuda.empty_cache()
-
-        # rank-k approximation of the planted low-rank sparse matrix (65536 x
-        # 65536, about 10M nonzeros, k = 32, t_R = 512); error against the
-        # stored best rank-k error of the same seeded matrix
-        log("low rank: planted sparse n=65536 ~10M nnz, k=32, t_R=512")
-        A4 = W.planted_lowrank_sparse()
-        A4g = sk.Csr(A4.n, A4.d, torch.from_numpy(A4.row_ptr32()).to(dev), torch.from_numpy(A4.col_idx).to(dev),
-                     torch.from_numpy(A4.val).to(dev))
-        gold = {}
-        with open(os.path.join(ROOT, "tests", "golden", "lowrank_planted_n65536_r32.txt")) as f:
-            for line in f:
-                if ":" in line and not line.startswith("#"):
-                    key, v = line.split(":", 1)
-                    gold[key.strip()] = float(v)
-        lr_seed = W.sketch_seed(0)
-        sk.low_rank(A4g, 32, lr_seed, t_r=512)  # warm-up
-        sync()
-        lib.skls_profile_enable(1)
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            _, _, _, linfo = sk.low_rank(A4g, 32, lr_seed, t_r=512)
-        sync()
-        el = (time.perf_counter() - t0) / reps
-        ph = profile_phases(sk)
-        lib.skls_profile_enable(0)
-        result["low_rank"] = {
-            "ms_per_call": el * 1e3, "nnz": A4.nnz, "k": 32, "t_r": linfo["t_r"], "t_s": linfo["t_s"],
-            "error_ratio": linfo["resid_fro"] / gold["delta_k"], "iterations": linfo["iterations"],
-            "rows_sampled": linfo["rows_sampled"],
-            "ms_phases": {"sketch_and_basis": linfo["ms_sketch"], "scores_and_sampling": linfo["ms_sample"],
-                          "top_k": linfo["ms_topk"], "factors_and_error": linfo["ms_factors"]},
-            "kernel_phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
-        }
-        del A4, A4g
-        torch.cuda.empty_cache()
-
-        # learned per-row values: the full family of 256 matrices, trained on
-        # the GPU, then compared with the random signs on held-out matrices by
-        # distortion, by the sketch-and-solve residual ratio, and by solves to
-        # a certified ratio of 1 + 1e-6 with the values as the sketch.
-        nl, tl, steps_l, batch_l = 32768, 1024, 500, 16
-        log("learned values: 256 matrices n=32768 d=64 t=1024 (160 train / 32 validation / 64 test), "
-            f"{steps_l} Adam steps, batch {batch_l}")
-        from paper_1207_6365_amd import train as TR
-
-        make, _ = W.learned_family()
-        host = [make(m) for m in range(256)]
-        mats = [torch.from_numpy(a).to(dev) for a in host]
-        rhs = [torch.from_numpy(W.learned_rhs(host[m], m)).to(dev) for m in range(192, 256)]
-        del host
-        tr_m, va_m, te_m = mats[:160], mats[160:192], mats[192:]
-        sync()
-        t0 = time.perf_counter()
-        out = TR.train(tr_m, va_m, tl, seed, steps=steps_l, lr=1e-2, batch=batch_l)
-        sync()
-        train_s = time.perf_counter() - t0
-        grams, norms, ws5 = TR.prepare(te_m, tl, seed)
-        sgn = TR.signs(nl, tl, seed, dev)
-        plain = TR.distortions(te_m, grams, norms, tl, seed, sgn, ws=ws5)
-        learned = TR.distortions(te_m, grams, norms, tl, seed, out.learned, ws=ws5)
-        norms_a = np.array(norms)
-
-        def ratios(w):
-            # residual of the sketch-and-solve x~ (no iteration) over the optimum,
-            # the latter from a solve certified to 1 + 1e-11
-            r = []
-            for A, b in zip(te_m, rhs):
-                _, i0 = sk.lstsq(A, b, tl, seed, max_iter=0, w=w, raise_noconv=False)
-                _, i1 = sk.lstsq(A, b, tl, seed, delta=1e-11, w=w)
-                r.append(i0["resid_norm"] / i1["resid_norm"])
-            return np.array(r)
-
-        def solves(w):
-            for A, b in zip(te_m[:4], rhs[:4]):
-                sk.lstsq(A, b, tl, seed, delta=1e-6, w=w)
+        if want("low_rank"):
+            # rank-k approximation of the planted low-rank sparse matrix (65536 x
+            # 65536, about 10M nonzeros, k = 32, t_R = 512); error against the
+            # stored best rank-k error of the same seeded matrix
+            log("low rank: planted sparse n=65536 ~10M nnz, k=32, t_R=512")
+            A4 = W.planted_lowrank_sparse()
+            A4g = sk.Csr(A4.n, A4.d, torch.from_numpy(A4.row_ptr32()).to(dev), torch.from_numpy(A4.col_idx).to(dev),
+                         torch.from_numpy(A4.val).to(dev))
+            gold = {}
+            with open(os.path.join(ROOT, "tests", "golden", "lowrank_planted_n65536_r32.txt")) as f:
+                for line in f:
+                    if ":" in line and not line.startswith("#"):
+                        key, v = line.split(":", 1)
+                        gold[key.strip()] = float(v)
+            lr_seed = W.sketch_seed(0)
+            sk.low_rank(A4g, 32, lr_seed, t_r=512)  # warm-up
             sync()
-            its, cert = [], True
+            lib.skls_profile_enable(1)
+            reps = 3
             t0 = time.perf_counter()
-            for A, b in zip(te_m, rhs):
-                _, i = sk.lstsq(A, b, tl, seed, delta=1e-6, w=w)
-                its.append(i["iterations"])
-                cert = cert and i["certified"] == 1
+            for _ in range(reps):
+                _, _, _, linfo = sk.low_rank(A4g, 32, lr_seed, t_r=512)
             sync()
-            el = (time.perf_counter() - t0) / len(te_m)
-            return {"solves_per_s": 1.0 / el, "mean_iterations": float(np.mean(its)), "certified": cert}
+            el = (time.perf_counter() - t0) / reps
+            ph = profile_phases(sk)
+            lib.skls_profile_enable(0)
+            result["low_rank"] = {
+                "ms_per_call": el * 1e3, "nnz": A4.nnz, "k": 32, "t_r": linfo["t_r"], "t_s": linfo["t_s"],
+                "error_ratio": linfo["resid_fro"] / gold["delta_k"], "iterations": linfo["iterations"],
+                "rows_sampled": linfo["rows_sampled"],
+                "ms_phases": {"sketch_and_basis": linfo["ms_sketch"], "scores_and_sampling": linfo["ms_sample"],
+                              "top_k": linfo["ms_topk"], "factors_and_error": linfo["ms_factors"]},
+                "kernel_phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
+            }
+            del A4, A4g
+            torch.cuda.empty_cache()
 
-        rho_p, rho_l = ratios(None), ratios(out.learned)
-        result["learned"] = {
-            "matrices": {"train": 160, "validation": 32, "test": 64}, "n": nl, "d": 64, "t": tl,
-            "train_s": train_s, "steps": steps_l, "batch": batch_l, "used_learned": bool(out.used_learned),
-            "validation_distortion": {"plain": out.val_plain, "learned": out.val_learned},
-            "test_distortion": {"plain": float(plain.mean()), "learned": float(learned.mean())},
-            "test_distortion_raw": {"plain": float((plain * norms_a).mean()),
-                                    "learned": float((learned * norms_a).mean())},
-            "sketch_solve_ratio_minus_1": {"plain": float((rho_p - 1).mean()), "learned": float((rho_l - 1).mean()),
-                                           "plain_max": float((rho_p - 1).max()),
-                                           "learned_max": float((rho_l - 1).max())},
-            "lstsq_1e-6": {"plain": solves(None), "learned": solves(out.learned)},
-        }
-        del mats, tr_m, va_m, te_m, rhs
-        torch.cuda.empty_cache()
+        if want("learned"):
+            # learned per-row values: the full family of 256 matrices, trained on
+            # the GPU, then compared with the random signs on held-out matrices by
+            # distortion, by the sketch-and-solve residual ratio, and by solves to
+            # a certified ratio of 1 + 1e-6 with the values as the sketch.
+            nl, tl, steps_l, batch_l = 32768, 1024, 500, 16
+            log("learned values: 256 matrices n=32768 d=64 t=1024 (160 train / 32 validation / 64 test), "
+                f"{steps_l} Adam steps, batch {batch_l}")
+            from paper_1207_6365_amd import train as TR
+
+            make, _ = W.learned_family()
+            host = [make(m) for m in range(256)]
+            mats = [torch.from_numpy(a).to(dev) for a in host]
+            rhs = [torch.from_numpy(W.learned_rhs(host[m], m)).to(dev) for m in range(192, 256)]
+            del host
+            tr_m, va_m, te_m = mats[:160], mats[160:192], mats[192:]
+            sync()
+            t0 = time.perf_counter()
+            out = TR.train(tr_m, va_m, tl, seed, steps=steps_l, lr=1e-2, batch=batch_l)
+            sync()
+            train_s = time.perf_counter() - t0
+            grams, norms, ws5 = TR.prepare(te_m, tl, seed)
+            sgn = TR.signs(nl, tl, seed, dev)
+            plain = TR.distortions(te_m, grams, norms, tl, seed, sgn, ws=ws5)
+            learned = TR.distortions(te_m, grams, norms, tl, seed, out.learned, ws=ws5)
+            norms_a = np.array(norms)
+
+            def ratios(w):
+                # residual of the sketch-and-solve x~ (no iteration) over the optimum,
+                # the latter from a solve certified to 1 + 1e-11
+                r = []
+                for A, b in zip(te_m, rhs):
+                    _, i0 = sk.lstsq(A, b, tl, seed, max_iter=0, w=w, raise_noconv=False)
+                    _, i1 = sk.lstsq(A, b, tl, seed, delta=1e-11, w=w)
+                    r.append(i0["resid_norm"] / i1["resid_norm"])
+                return np.array(r)
+
+            def solves(w):
+                for A, b in zip(te_m[:4], rhs[:4]):
+                    sk.lstsq(A, b, tl, seed, delta=1e-6, w=w)
+                sync()
+                its, cert = [], True
+                t0 = time.perf_counter()
+                for A, b in zip(te_m, rhs):
+                    _, i = sk.lstsq(A, b, tl, seed, delta=1e-6, w=w)
+                    its.append(i["iterations"])
+                    cert = cert and i["certified"] == 1
+                sync()
+                el = (time.perf_counter() - t0) / len(te_m)
+                return {"solves_per_s": 1.0 / el, "mean_iterations": float(np.mean(its)), "certified": cert}
+
+            rho_p, rho_l = ratios(None), ratios(out.learned)
+            result["learned"] = {
+                "matrices": {"train": 160, "validation": 32, "test": 64}, "n": nl, "d": 64, "t": tl,
+                "train_s": train_s, "steps": steps_l, "batch": batch_l, "used_learned": bool(out.used_learned),
+                "validation_distortion": {"plain": out.val_plain, "learned": out.val_learned},
+                "test_distortion": {"plain": float(plain.mean()), "learned": float(learned.mean())},
+                "test_distortion_raw": {"plain": float((plain * norms_a).mean()),
+                                        "learned": float((learned * norms_a).mean())},
+                "sketch_solve_ratio_minus_1": {"plain": float((rho_p - 1).mean()), "learned": float((rho_l - 1).mean()),
+                                               "plain_max": float((rho_p - 1).max()),
+                                               "learned_max": float((rho_l - 1).max())},
+                "lstsq_1e-6": {"plain": solves(None), "learned": solves(out.learned)},
+            }
+            del mats, tr_m, va_m, te_m, rhs
+            torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ oracle on the host
     if not args.no_cpu:
