@@ -9,7 +9,8 @@ Clarkson & Woodruff, "Low Rank Approximation and Regression in Input Sparsity
 Time" (arXiv:1207.6365) it follows:
 
 * :mod:`.hashing`  -- ``h`` and ``D`` of the sparse embedding (Section 2)
-* :mod:`.sketch`   -- ``S A = Phi D A`` (Section 2; Section 3 main theorem)
+* :mod:`.sketch`   -- ``S A = Phi D A`` (Section 2; Section 3 main theorem) and
+  the generalized sparse embedding (Section 5)
 * :mod:`.linalg`   -- Householder QR, substitution, exact least squares,
   residual ratio via the Pythagorean identity (Section 7.2 facts)
 * :mod:`.solve`    -- sketch-and-solve (Section 7 regression theorem),
@@ -41,7 +42,15 @@ from .linalg import (  # noqa: F401
     thin_q,
 )
 from .operator import MatrixOp  # noqa: F401
-from .sketch import explicit_S, sketch_bucket_rows, sketch_csr, sketch_dense  # noqa: F401
+from .sketch import (  # noqa: F401
+    copy_seed,
+    explicit_S,
+    generalized_S,
+    sketch_bucket_rows,
+    sketch_csr,
+    sketch_dense,
+    sketch_generalized,
+)
 from .solve import (  # noqa: F401
     certificate_threshold,
     lsqr,
