@@ -149,6 +149,30 @@ SKLS_API int32_t skls_sketch(const skls_matrix* A, const void* b, int32_t b_dtyp
                     size_t ws_bytes, void* stream);
 
 /*
+ * Generalized sparse embedding (Section 5, the construction): a hash h sends
+ * each row i to one of q groups; group g applies its own matrix B^(g), the
+ * stack of `a` independent sparse embeddings sqrt(1/a) Phi_j D_j onto v
+ * rows each.  S = blockdiag(B^(1), ..., B^(q)) P has t = a q v rows and
+ * exactly `a` nonzeros +-1/sqrt(a) per column.
+ * Randomness: h(i) = bucket of output i of the stream `seed` reduced to
+ * [0, q) (as in skls_hash); copy j (0-based) hashes row i to
+ * h_j(i) in [0, v) with sign from output i of the stream
+ * seed + (j + 1) * 0xD1B54A32D192ED03 (mod 2^64).
+ * Row order of SA: copy-major, row j q v + h(i) v + h_j(i) (a permutation of
+ * the block-diagonal order; norms and the R of a QR of S A do not change).
+ *  q, v:   groups and rows per copy, q v < 2^31; a: copies, 1 <= a <= 256.
+ *  SA:     device, (a q v) x d row-major, type out_dtype; Sb: (a q v) or NULL.
+ *  variant, ws: as for skls_sketch with t = q v (one copy at a time).
+ * Each copy is one pass over A, so the cost is a times that of skls_sketch.
+ * Asynchronous.
+ */
+SKLS_API int32_t skls_sketch_general_workspace(const skls_matrix* A, int64_t q, int64_t v, int32_t variant,
+                                               size_t* bytes);
+SKLS_API int32_t skls_sketch_general(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t q, int64_t v,
+                                     int32_t a, uint64_t seed, int32_t variant, void* SA, void* Sb,
+                                     int32_t out_dtype, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Triangular factor of a QR factorisation of a tall matrix (Section 7 solves
  * the sketched regression through the QR factorisation of S A, as R^{-1} Q^T S b;
  * Section 6 uses the same R as the change of basis that makes S A R^{-1}

@@ -23,5 +23,6 @@ from .api import (  # noqa: F401
     lstsq,
     qr_r,
     sketch,
+    sketch_general,
     version,
 )

@@ -113,6 +113,9 @@ SIGNATURES = {
     "skls_sketch_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int32, POINTER(c_size_t)]),
     "skls_sketch": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_int64, c_uint64, c_void_p, c_int32,
                               c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
+    "skls_sketch_general_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int64, c_int32, POINTER(c_size_t)]),
+    "skls_sketch_general": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_int64, c_int64, c_int32, c_uint64,
+                                      c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "skls_qr_r_workspace": (c_int32, [c_int64, c_int64, POINTER(c_size_t)]),
     "skls_qr_r": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "skls_lstsq_workspace": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLstsqOpts), POINTER(c_size_t)]),

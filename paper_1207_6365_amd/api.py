@@ -132,6 +132,27 @@ def sketch(A, t: int, seed: int, b: torch.Tensor | None = None, w: torch.Tensor 
     return (SA, Sb) if b is not None else SA
 
 
+def sketch_general(A, q: int, v: int, a: int, seed: int, b: torch.Tensor | None = None, variant: str = "auto",
+                   out_dtype=torch.float32):
+    """Generalized sparse embedding (Section 5): ``S A`` with ``a q v`` rows,
+    copy-major (row ``j q v + h(i) v + h_j(i)``), and ``S b`` when ``b`` is given."""
+    m, device = _matrix(A)
+    if out_dtype not in (torch.float64, torch.float32):
+        raise TypeError("out_dtype must be float64 or float32")
+    if b is not None and (b.dtype not in (torch.float64, torch.float32) or not b.is_contiguous()
+                          or b.numel() != m.n):
+        raise TypeError("b must be a contiguous float64/float32 vector of n entries")
+    vv = _VARIANT[variant]
+    ws = _workspace(_size(lib().skls_sketch_general_workspace, ctypes.byref(m), q, v, vv), device)
+    t = a * q * v
+    SA = torch.empty((t, m.d), dtype=out_dtype, device=device)
+    Sb = torch.empty(t, dtype=out_dtype, device=device) if b is not None else None
+    L.check(lib().skls_sketch_general(ctypes.byref(m), _ptr(b), _DTYPE[b.dtype] if b is not None else L.F64, q, v, a,
+                                      seed & 0xFFFFFFFFFFFFFFFF, vv, _ptr(SA), _ptr(Sb), _DTYPE[out_dtype],
+                                      _ptr(ws), ws.numel(), _stream(device)))
+    return (SA, Sb) if b is not None else SA
+
+
 # ------------------------------------------------------------------ a3
 def qr_r(M: torch.Tensor, inverse: bool = True):
     """``R`` (and ``R^{-1}``) of a QR factorisation of a tall ``m x d`` matrix."""

@@ -330,6 +330,64 @@ int32_t skls_sketch(const skls_matrix* A, const void* b, int32_t b_dtype, int64_
   return run_sketch(*A, b, b_dtype, t, seed, w, variant, SA, Sb, out_dtype, ws, ws_bytes, as_stream(stream));
 }
 
+int32_t skls_sketch_general_workspace(const skls_matrix* A, int64_t q, int64_t v, int32_t variant, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (bytes == nullptr || q < 1 || v < 1 || q * v >= (int64_t(1) << 31)) {
+    set_error("need bytes != NULL, q >= 1, v >= 1 and q v < 2^31");
+    return SKLS_ERR_ARG;
+  }
+  if (variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_BINNED) {
+    set_error("unknown sketch variant %d", variant);
+    return SKLS_ERR_ARG;
+  }
+  *bytes = sketch_ws_bytes(*A, q * v, variant);
+  return SKLS_OK;
+}
+
+int32_t skls_sketch_general(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t q, int64_t v, int32_t a,
+                            uint64_t seed, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
+                            size_t ws_bytes, void* stream) {
+  clear_error();
+  size_t need = 0;
+  SKLS_TRY(skls_sketch_general_workspace(A, q, v, variant, &need));
+  if (a < 1 || a > 256 || SA == nullptr || (b == nullptr) != (Sb == nullptr)) {
+    set_error("need 1 <= a <= 256, SA != NULL, and b and Sb given together");
+    return SKLS_ERR_ARG;
+  }
+  if (b != nullptr && b_dtype != SKLS_F64 && b_dtype != SKLS_F32) {
+    set_error("b must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  if (out_dtype != SKLS_F64 && out_dtype != SKLS_F32) {
+    set_error("out_dtype must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) {
+    set_error("sketch workspace too small: need %zu bytes", need);
+    return SKLS_ERR_WORKSPACE;
+  }
+  hipStream_t s = as_stream(stream);
+  const int64_t tc = q * v;
+  const size_t ob = out_dtype == SKLS_F64 ? 8 : 4;
+  for (int32_t j = 0; j < a; ++j) {
+    HashKey key;
+    key.seed = seed + static_cast<uint64_t>(j + 1) * 0xD1B54A32D192ED03ull;
+    key.outer = seed;
+    key.q = static_cast<uint32_t>(q);
+    key.v = static_cast<uint32_t>(v);
+    char* sa = static_cast<char*>(SA) + static_cast<size_t>(j) * tc * A->d * ob;
+    char* sb = Sb ? static_cast<char*>(Sb) + static_cast<size_t>(j) * tc * ob : nullptr;
+    SKLS_TRY(run_sketch_key(*A, b, b_dtype, tc, key, nullptr, variant, sa, sb, out_dtype, ws, ws_bytes, s));
+  }
+  if (a > 1) {
+    const double sc = 1.0 / std::sqrt(static_cast<double>(a));
+    SKLS_TRY(launch_scale(SA, static_cast<size_t>(a) * tc * A->d, out_dtype, sc, s));
+    if (Sb) SKLS_TRY(launch_scale(Sb, static_cast<size_t>(a) * tc, out_dtype, sc, s));
+  }
+  return SKLS_OK;
+}
+
 int32_t skls_qr_r_workspace(int64_t m, int64_t d, size_t* bytes) {
   clear_error();
   if (bytes == nullptr || d < 1 || m < d) {

@@ -68,6 +68,26 @@ __device__ __forceinline__ uint32_t bucket_of(uint64_t z, uint32_t t) {
 }
 __device__ __forceinline__ bool negative_of(uint64_t z) { return (z & 1ull) != 0; }
 
+// Which hash a sketch uses.  Plain sparse embedding (Section 2; v = 0): z =
+// output r of the stream `seed`, bucket h(r) = bucket_of(z, t), sign from z.
+// Generalized sparse embedding (Section 5), one of its stacked copies:
+// bucket = h(r) v + h_j(r) with the outer h(r) = bucket_of(output r of the
+// stream `outer`, q) shared by all copies and h_j(r) = bucket_of(z, v), z =
+// output r of the copy's stream `seed` (which also gives the sign); t = q v.
+struct HashKey {
+  uint64_t seed;
+  uint64_t outer;
+  uint32_t q, v;
+};
+inline HashKey plain_key(uint64_t s) { return HashKey{s, 0, 0, 0}; }
+__device__ __forceinline__ uint64_t hk_z(const HashKey& k, uint64_t r) { return splitmix64(k.seed, r); }
+__device__ __forceinline__ uint32_t hk_bucket(const HashKey& k, uint64_t z, uint64_t r, uint32_t t) {
+  return k.v == 0 ? bucket_of(z, t) : bucket_of(splitmix64(k.outer, r), k.q) * k.v + bucket_of(z, k.v);
+}
+__device__ __forceinline__ uint32_t hk_bucket_r(const HashKey& k, uint64_t r, uint32_t t) {
+  return hk_bucket(k, hk_z(k, r), r, t);
+}
+
 // ------------------------------------------------------------------ values
 // bfloat16 storage: the upper 16 bits of a binary32.
 struct bf16_t {

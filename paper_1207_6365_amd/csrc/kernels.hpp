@@ -9,6 +9,8 @@ namespace skls {
 int32_t launch_hash(int64_t n, uint32_t t, uint64_t seed, int64_t start, int32_t* bucket, int8_t* sign,
                     hipStream_t s);
 int32_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// p[i] *= alpha for count elements of type dtype (F64 or F32).
+int32_t launch_scale(void* p, size_t count, int32_t dtype, double alpha, hipStream_t s);
 
 // Sketch variant the library runs for this input (SKLS_SKETCH_AUTO resolved).
 int32_t choose_sketch_variant(const skls_matrix& A, int64_t t, int32_t variant, int32_t out_dtype);
@@ -16,6 +18,13 @@ size_t sketch_ws_bytes(const skls_matrix& A, int64_t t, int32_t variant);
 int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
                    const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
                    size_t ws_bytes, hipStream_t s);
+// The same with the hash given by a key (plain or one copy of a generalized
+// sparse embedding).
+int32_t run_sketch_key(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, HashKey key,
+                       const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
+                       size_t ws_bytes, hipStream_t s);
+int32_t launch_hash_key(int64_t n, uint32_t t, HashKey key, int64_t start, int32_t* bucket, int8_t* sign,
+                        hipStream_t s);
 
 // ---------------------------------------------------------------- dense.hip
 // Gram of the augmented matrix [M | v] (m x dd, dd = d or d+1), float64.

@@ -35,9 +35,9 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 template <typename TS>
-__device__ __forceinline__ TS row_scale(uint64_t seed, int64_t r, const float* __restrict__ w) {
+__device__ __forceinline__ TS row_scale(HashKey seed, int64_t r, const float* __restrict__ w) {
   if (w) return static_cast<TS>(w[r]);
-  return negative_of(splitmix64(seed, static_cast<uint64_t>(r))) ? TS(-1) : TS(1);
+  return negative_of(hk_z(seed, static_cast<uint64_t>(r))) ? TS(-1) : TS(1);
 }
 
 template <typename TS>
@@ -46,14 +46,21 @@ __device__ __forceinline__ TS load_b(const void* __restrict__ b, int b_f64, int6
 }
 
 // ---------------------------------------------------------------- a1: hash
-__global__ void k_hash(int64_t n, uint32_t t, uint64_t seed, int64_t start, int32_t* __restrict__ bucket,
+__global__ void k_hash(int64_t n, uint32_t t, HashKey seed, int64_t start, int32_t* __restrict__ bucket,
                        int8_t* __restrict__ sign) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t z = splitmix64(seed, static_cast<uint64_t>(start + i));
-    if (bucket) bucket[i] = static_cast<int32_t>(bucket_of(z, t));
+    const uint64_t z = hk_z(seed, static_cast<uint64_t>(start + i));
+    if (bucket) bucket[i] = static_cast<int32_t>(hk_bucket(seed, z, static_cast<uint64_t>(start + i), t));
     if (sign) sign[i] = negative_of(z) ? int8_t(-1) : int8_t(1);
   }
+}
+
+template <typename T>
+__global__ void k_scale(T* __restrict__ p, size_t count, T alpha) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < count;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] *= alpha;
 }
 
 __global__ void k_fill_zero(uint32_t* __restrict__ p, size_t words) {
@@ -132,21 +139,21 @@ struct Entry<CsrRec<TR, TO_>> {
 // ---------------------------------------------------------------- counting sort
 // One-level counting sort with global atomics, for plans with too many coarse
 // bins for the LDS counters of the two-level plan.
-__global__ void k_count(int64_t n, uint32_t t, uint64_t seed, int32_t* __restrict__ count, int32_t* __restrict__ rank) {
+__global__ void k_count(int64_t n, uint32_t t, HashKey seed, int32_t* __restrict__ count, int32_t* __restrict__ rank) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const uint32_t h = bucket_of(splitmix64(seed, static_cast<uint64_t>(i)), t);
+    const uint32_t h = hk_bucket_r(seed, static_cast<uint64_t>(i), t);
     rank[i] = atomicAdd(&count[h], 1);
   }
 }
 
 template <typename R>
-__global__ void k_scatter(int64_t n, uint32_t t, uint64_t seed, const int32_t* __restrict__ off,
+__global__ void k_scatter(int64_t n, uint32_t t, HashKey seed, const int32_t* __restrict__ off,
                           const int32_t* __restrict__ rank, RowSrc src, R* __restrict__ out) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t z = splitmix64(seed, static_cast<uint64_t>(i));
-    out[off[bucket_of(z, t)] + rank[i]] = Entry<R>::make(src, i, z);
+    const uint64_t z = hk_z(seed, static_cast<uint64_t>(i));
+    out[off[hk_bucket(seed, z, static_cast<uint64_t>(i), t)] + rank[i]] = Entry<R>::make(src, i, z);
   }
 }
 
@@ -235,7 +242,7 @@ constexpr int kPlanItems = 16;
 constexpr int kPlanChunk = kPlanThreads * kPlanItems;  // rows per block in passes 1-2
 constexpr int kMaxBins = 8192;                         // LDS counters of passes 1-2
 
-__global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_count(int64_t n, uint32_t t, uint64_t seed, int sh,
+__global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_count(int64_t n, uint32_t t, HashKey seed, int sh,
                                                                     int C, int nblk, int32_t* __restrict__ cnt) {
   extern __shared__ int32_t hist[];  // [C]
   for (int c = threadIdx.x; c < C; c += kPlanThreads) hist[c] = 0;
@@ -244,14 +251,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_count(int64_t n, u
 #pragma unroll 4
   for (int k = 0; k < kPlanItems; ++k) {
     const int64_t i = r0 + static_cast<int64_t>(k) * kPlanThreads + threadIdx.x;
-    if (i < n) atomicAdd(&hist[bucket_of(splitmix64(seed, static_cast<uint64_t>(i)), t) >> sh], 1);
+    if (i < n) atomicAdd(&hist[hk_bucket_r(seed, static_cast<uint64_t>(i), t) >> sh], 1);
   }
   __syncthreads();
   for (int c = threadIdx.x; c < C; c += kPlanThreads) cnt[static_cast<size_t>(c) * nblk + blockIdx.x] = hist[c];
 }
 
 template <typename R>
-__global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_scatter(int64_t n, uint32_t t, uint64_t seed, int sh,
+__global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_scatter(int64_t n, uint32_t t, HashKey seed, int sh,
                                                                       int C, int nblk,
                                                                       const int32_t* __restrict__ coff, RowSrc src,
                                                                       R* __restrict__ coarse) {
@@ -278,9 +285,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_scatter(int64_t n,
       const int64_t i = r0 + static_cast<int64_t>(k0 + u) * kPlanThreads + threadIdx.x;
       ok[u] = i < n;
       ii[u] = ok[u] ? i : n - 1;
-      z[u] = splitmix64(seed, static_cast<uint64_t>(ii[u]));
+      z[u] = hk_z(seed, static_cast<uint64_t>(ii[u]));
       e[u] = Entry<R>::extent(src, ii[u]);
-      bin[u] = static_cast<int32_t>(bucket_of(z[u], t) >> sh);
+      bin[u] = static_cast<int32_t>(hk_bucket(seed, z[u], static_cast<uint64_t>(ii[u]), t) >> sh);
     }
     if (Entry<R>::kSb && src.b != nullptr) {
       TO bv[kU], sc[kU];
@@ -308,7 +315,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_coarse_scatter(int64_t n,
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, uint64_t seed, int sh, int C, int nblk,
+__global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, HashKey seed, int sh, int C, int nblk,
                                                         const int32_t* __restrict__ coff, const R* __restrict__ coarse,
                                                         R* __restrict__ fine_out, int32_t* __restrict__ off) {
   extern __shared__ int32_t fcnt[];  // [fine]
@@ -322,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, u
   const uint32_t base_bucket = static_cast<uint32_t>(c) << sh;
   for (int64_t p = beg + threadIdx.x; p < end; p += kThreads) {
     const int32_t r = Entry<R>::row(coarse[p]);
-    atomicAdd(&fcnt[bucket_of(splitmix64(seed, static_cast<uint64_t>(r)), t) - base_bucket], 1);
+    atomicAdd(&fcnt[hk_bucket_r(seed, static_cast<uint64_t>(r), t) - base_bucket], 1);
   }
   __syncthreads();
   // exclusive scan of the fine counters: each thread owns a run of them
@@ -346,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, u
   __syncthreads();
   for (int64_t p = beg + threadIdx.x; p < end; p += kThreads) {
     const R e = coarse[p];
-    const uint32_t f = bucket_of(splitmix64(seed, static_cast<uint64_t>(Entry<R>::row(e))), t) - base_bucket;
+    const uint32_t f = hk_bucket_r(seed, static_cast<uint64_t>(Entry<R>::row(e)), t) - base_bucket;
     fine_out[beg + atomicAdd(&fcnt[f], 1)] = e;
   }
 }
@@ -362,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void k_plan_fine(int64_t n, uint32_t t, u
 // size): bin c of chunk q is out[q * chunk + offT[q][c] ..
 // q * chunk + offT[q][c + 1]).
 template <typename R, int PER>
-__global__ __launch_bounds__(kPlanThreads) void k_plan_local(int64_t n, uint32_t t, uint64_t seed, int sh, int C,
+__global__ __launch_bounds__(kPlanThreads) void k_plan_local(int64_t n, uint32_t t, HashKey seed, int sh, int C,
                                                              RowSrc src, R* __restrict__ out,
                                                              int32_t* __restrict__ offT, int nseg) {
   constexpr int CH = PER * kPlanThreads;
@@ -379,7 +386,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_local(int64_t n, uint32_t
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int p = u * kPlanThreads + threadIdx.x;
-    bin[u] = static_cast<int32_t>(bucket_of(splitmix64(seed, static_cast<uint64_t>(r0 + p)), t) >> sh);
+    bin[u] = static_cast<int32_t>(hk_bucket_r(seed, static_cast<uint64_t>(r0 + p), t) >> sh);
     if (p < m) atomicAdd(&cnt[bin[u]], 1);
   }
   __syncthreads();
@@ -429,7 +436,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_local(int64_t n, uint32_t
       } else {
 #pragma unroll
         for (int u = 0; u < PER; ++u)
-          sc[u] = negative_of(splitmix64(seed, static_cast<uint64_t>(ii[u]))) ? TO(-1) : TO(1);
+          sc[u] = negative_of(hk_z(seed, static_cast<uint64_t>(ii[u]))) ? TO(-1) : TO(1);
       }
 #pragma unroll
       for (int u = 0; u < PER; ++u) Entry<R>::set_sb(e[u], sc[u] * bv[u]);
@@ -762,7 +769,7 @@ __device__ __forceinline__ CsrRec<TR, TO> load_rec(const CsrRec<TR, TO>* __restr
 
 template <typename TV, typename TR, typename TO>
 __global__ __launch_bounds__(kBinThreads) void k_sketch_csr_binned(
-    int d, uint32_t t, int sh, int splits, uint64_t seed, const int32_t* __restrict__ col,
+    int d, uint32_t t, int sh, int splits, HashKey seed, const int32_t* __restrict__ col,
     const TV* __restrict__ val, const float* __restrict__ w, BinSegs S, const CsrRec<TR, TO>* __restrict__ recs,
     TO* __restrict__ SA, TO* __restrict__ Sb, int acc_bytes, int sb_bytes, int quad_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -804,8 +811,8 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_csr_binned(
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const bool has = j0 + h * kWave + lane < pe;
-        const uint64_t z = splitmix64(seed, static_cast<uint64_t>(cur[h].row));
-        const int lb = static_cast<int>(bucket_of(z, t) - bk0);
+        const uint64_t z = hk_z(seed, static_cast<uint64_t>(cur[h].row));
+        const int lb = static_cast<int>(hk_bucket(seed, z, static_cast<uint64_t>(cur[h].row), t) - bk0);
         R.st[h] = cur[h].start;
         R.len[h] = has ? cur[h].len : 0;
         R.sc[h] = w ? static_cast<TO>(w[cur[h].row]) : (negative_of(z) ? TO(-1) : TO(1));
@@ -876,7 +883,7 @@ __device__ __forceinline__ CsrMeta<TR, TO> csr_meta(const CsrRec<TR, TO>* __rest
 // loading the next bucket's records while it reduces the current one.
 template <typename TV, typename TR, typename TO>
 __global__ __launch_bounds__(kThreads) void k_sketch_csr_sorted(
-    int d, uint32_t t, int bpw, uint64_t seed, const int32_t* __restrict__ col, const TV* __restrict__ val,
+    int d, uint32_t t, int bpw, HashKey seed, const int32_t* __restrict__ col, const TV* __restrict__ val,
     const float* __restrict__ w, const int32_t* __restrict__ off, const CsrRec<TR, TO>* __restrict__ recs,
     TO* __restrict__ SA, TO* __restrict__ Sb, int per_wave, int quad_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1021,7 +1028,7 @@ struct DenseLds {
 // added in bucket order.
 template <typename TV, typename TO, int V, bool SORTED>
 __device__ __forceinline__ void dense_rows(const DenseLds<TO>& L, const int32_t* __restrict__ perm, int beg, int m,
-                                           uint64_t seed, const float* __restrict__ w, const TV* __restrict__ A,
+                                           HashKey seed, const float* __restrict__ w, const TV* __restrict__ A,
                                            int64_t ld, int d, TO* __restrict__ out, int lane) {
   constexpr int RB = 8;
   for (int c0 = lane * V; c0 < d; c0 += kWave * V) {
@@ -1052,7 +1059,7 @@ __device__ __forceinline__ void dense_rows(const DenseLds<TO>& L, const int32_t*
 
 template <typename TV, typename TO, int V>
 __global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted(
-    int d, int64_t ld, uint32_t t, int bpw, uint64_t seed, const TV* __restrict__ A, const void* __restrict__ b,
+    int d, int64_t ld, uint32_t t, int bpw, HashKey seed, const TV* __restrict__ A, const void* __restrict__ b,
     int b_f64, const float* __restrict__ w, const int32_t* __restrict__ off, const int32_t* __restrict__ perm,
     TO* __restrict__ SA, TO* __restrict__ Sb) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1132,7 +1139,7 @@ __global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted(
 // slices per lane, into the bin's LDS rows of S A.
 template <typename TV, typename TO, int V>
 __global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
-    int d, int64_t ld, uint32_t t, int sh, int splits, uint64_t seed, const TV* __restrict__ A,
+    int d, int64_t ld, uint32_t t, int sh, int splits, HashKey seed, const TV* __restrict__ A,
     const void* __restrict__ b, int b_f64, const float* __restrict__ w, BinSegs S,
     const int32_t* __restrict__ rows, TO* __restrict__ SA, TO* __restrict__ Sb, int acc_bytes, int sb_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1165,8 +1172,8 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
       for (int q = 0; q < RB; ++q) {
         const bool ok = j0 + q < pe;
         r[q] = rows[L.map[(ok ? j0 + q : j0) - p0]];
-        const uint64_t z = splitmix64(seed, static_cast<uint64_t>(r[q]));
-        const int lb = static_cast<int>(bucket_of(z, t) - bk0);
+        const uint64_t z = hk_z(seed, static_cast<uint64_t>(r[q]));
+        const int lb = static_cast<int>(hk_bucket(seed, z, static_cast<uint64_t>(r[q]), t) - bk0);
         o[q] = lb * d;
         okq[q] = ok;
         sc[q] = w ? static_cast<TO>(w[r[q]]) : (negative_of(z) ? TO(-1) : TO(1));
@@ -1206,15 +1213,15 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_dense_binned(
 // ---------------------------------------------------------------- a2: atomic
 template <typename TV, typename TR, typename TO, int L>
 __global__ __launch_bounds__(kThreads) void k_sketch_csr_atomic(
-    int64_t n, int d, uint32_t t, uint64_t seed, const TR* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    int64_t n, int d, uint32_t t, HashKey seed, const TR* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const TV* __restrict__ val, const void* __restrict__ b, int b_f64, const float* __restrict__ w,
     TO* __restrict__ SA, TO* __restrict__ Sb) {
   const int64_t gid = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / L;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x / L;
   const int sub = threadIdx.x % L;
   for (int64_t r = gid; r < n; r += stride) {
-    const uint64_t z = splitmix64(seed, static_cast<uint64_t>(r));
-    const uint32_t h = bucket_of(z, t);
+    const uint64_t z = hk_z(seed, static_cast<uint64_t>(r));
+    const uint32_t h = hk_bucket(seed, z, static_cast<uint64_t>(r), t);
     const TO s = w ? static_cast<TO>(w[r]) : (negative_of(z) ? TO(-1) : TO(1));
     TO* dstrow = SA + static_cast<size_t>(h) * d;
     const TR e = row_ptr[r + 1];
@@ -1226,14 +1233,14 @@ __global__ __launch_bounds__(kThreads) void k_sketch_csr_atomic(
 
 template <typename TV, typename TO>
 __global__ __launch_bounds__(kThreads) void k_sketch_dense_atomic(
-    int64_t n, int d, int64_t ld, uint32_t t, uint64_t seed, const TV* __restrict__ A, const void* __restrict__ b,
+    int64_t n, int d, int64_t ld, uint32_t t, HashKey seed, const TV* __restrict__ A, const void* __restrict__ b,
     int b_f64, const float* __restrict__ w, TO* __restrict__ SA, TO* __restrict__ Sb) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
   for (int64_t r = wave; r < n; r += nwaves) {
-    const uint64_t z = splitmix64(seed, static_cast<uint64_t>(r));
-    const uint32_t h = bucket_of(z, t);
+    const uint64_t z = hk_z(seed, static_cast<uint64_t>(r));
+    const uint32_t h = hk_bucket(seed, z, static_cast<uint64_t>(r), t);
     const TO s = w ? static_cast<TO>(w[r]) : (negative_of(z) ? TO(-1) : TO(1));
     TO* dstrow = SA + static_cast<size_t>(h) * d;
     const TV* row = A + static_cast<size_t>(r) * ld;
@@ -1296,11 +1303,28 @@ bool vec_ok(const void* p, int64_t ld, int64_t d, int V) {
 }  // namespace
 
 // ================================================================ host
-int32_t launch_hash(int64_t n, uint32_t t, uint64_t seed, int64_t start, int32_t* bucket, int8_t* sign,
-                    hipStream_t s) {
+int32_t launch_hash_key(int64_t n, uint32_t t, HashKey seed, int64_t start, int32_t* bucket, int8_t* sign,
+                        hipStream_t s) {
   if (n == 0) return SKLS_OK;
   hipLaunchKernelGGL(k_hash, dim3(grid_for(n, kThreads, 16384)), dim3(kThreads), 0, s, n, t, seed, start, bucket,
                      sign);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
+int32_t launch_hash(int64_t n, uint32_t t, uint64_t seed, int64_t start, int32_t* bucket, int8_t* sign,
+                    hipStream_t s) {
+  return launch_hash_key(n, t, plain_key(seed), start, bucket, sign, s);
+}
+
+int32_t launch_scale(void* p, size_t count, int32_t dtype, double alpha, hipStream_t s) {
+  if (count == 0) return SKLS_OK;
+  const unsigned g = grid_for(static_cast<int64_t>(count), kThreads, 8192);
+  if (dtype == SKLS_F64)
+    hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kThreads), 0, s, static_cast<double*>(p), count, alpha);
+  else
+    hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(kThreads), 0, s, static_cast<float*>(p), count,
+                       static_cast<float>(alpha));
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }
@@ -1479,7 +1503,7 @@ int32_t scan_counts(const int32_t* count, int64_t ncnt, int32_t* bsum, int32_t* 
 int32_t allow_lds(const void* kernel, size_t lds);
 
 template <typename R>
-int32_t build_plan(int64_t n, uint32_t t, uint64_t seed, const BucketPlan& P, const RowSrc& src, hipStream_t s) {
+int32_t build_plan(int64_t n, uint32_t t, HashKey seed, const BucketPlan& P, const RowSrc& src, hipStream_t s) {
   const PlanShape& S = P.S;
   if (S.local) {
     const size_t lds = sizeof(R) * static_cast<size_t>(S.per) * kPlanThreads + static_cast<size_t>(S.C + 1) * 4;
@@ -1574,7 +1598,7 @@ BinSegs bin_segs(const BucketPlan& P, int64_t n) {
 
 // Apply of the SORTED and BINNED variants once the plan is built.
 template <typename TO>
-int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, int b_f64, uint32_t t, uint64_t seed,
+int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, int b_f64, uint32_t t, HashKey seed,
                       const float* w, TO* SA, TO* Sb, hipStream_t s) {
   const PlanShape& S = P.S;
   const int d = static_cast<int>(A.d);
@@ -1677,9 +1701,9 @@ size_t sketch_ws_bytes(const skls_matrix& A, int64_t t, int32_t variant) {
   return need;
 }
 
-int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
-                   const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
-                   size_t ws_bytes, hipStream_t s) {
+int32_t run_sketch_key(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, HashKey seed,
+                       const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
+                       size_t ws_bytes, hipStream_t s) {
   const int ob = out_bytes_of(out_dtype);
   const int32_t v = pick_variant(A, t, variant, ob);
   if (v != SKLS_SKETCH_ATOMIC && v != SKLS_SKETCH_SORTED && v != SKLS_SKETCH_BINNED) {
@@ -1759,6 +1783,12 @@ int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t
     PhaseTimer pt("sketch_apply", s);
     return apply_planned<TO>(A, P, b, b_f64, tt, seed, w, static_cast<TO*>(SA), static_cast<TO*>(Sb), s);
   });
+}
+
+int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
+                   const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
+                   size_t ws_bytes, hipStream_t s) {
+  return run_sketch_key(A, b, b_dtype, t, plain_key(seed), w, variant, SA, Sb, out_dtype, ws, ws_bytes, s);
 }
 
 }  // namespace skls
