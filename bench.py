@@ -8,7 +8,8 @@ size t = 65536 (hash + bucket plan + segmented reduce, every kernel of the
 path from (A, seed) to S A inside the timed region).  Inputs are synthetic and
 already resident in device memory when timing starts.
 
-Also reported on the same JSON line: the dense float32 variant (n = 2^20),
+Also reported on the same JSON line: the generalized sparse embedding of the
+same input (4 copies), the dense float32 variant (n = 2^20),
 sketch-and-solve on the small sparse regression (n = 20000, d = 20), least
 squares on the dense heavy-row regression workload (n = 2^21, d = 512,
 t = 2^18) in the plain float64 form and the mixed-precision forms, leverage
@@ -48,7 +49,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--lstsq-steps", type=int, default=3)
     p.add_argument("--only", default=None,
-                   choices=["dense", "small", "lstsq", "leverage", "low_rank", "learned"],
+                   choices=["general", "dense", "small", "lstsq", "leverage", "low_rank", "learned"],
                    help="run only this extra workload after the headline")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run a plain device copy of this many MiB first (scale for HBM byte counters)")
@@ -204,6 +205,26 @@ def main():
     }
     if plan_cnt:
         result["phases_ms"]["sketch_plan"] = plan_tot / plan_cnt
+
+    if not args.no_extras and want("general"):
+        # generalized sparse embedding (Section 5) of the same input: q groups,
+        # a copies of v rows each, a q v = t rows in all
+        q_g, v_g, a_g = 1024, 16, 4
+        log(f"generalized sparse embedding: same CSR input, q={q_g} v={v_g} a={a_g} (t={q_g * v_g * a_g})")
+        gws = ctypes.c_size_t(0)
+        sk._lib.check(lib.skls_sketch_general_workspace(ctypes.byref(mat), q_g, v_g, variant, ctypes.byref(gws)))
+        wsg = torch.empty(max(gws.value, 1), dtype=torch.uint8, device=dev)
+
+        def gstep():
+            st = lib.skls_sketch_general(ctypes.byref(mat), None, 0, q_g, v_g, a_g, seed, variant, SA.data_ptr(),
+                                         None, 1, wsg.data_ptr(), wsg.numel(), stream)
+            if st != 0:
+                sk._lib.check(st)
+
+        gms = time_steps(gstep, max(args.steps // 2, 5), 3, sync)
+        result["general"] = {"q": q_g, "v": v_g, "a": a_g, "t": q_g * v_g * a_g, "ms_per_call": gms,
+                             "nnz_per_s": nnz / (gms * 1e-3), "ms_per_copy": gms / a_g}
+        del wsg
     del Ag
 
     # ------------------------------------------------------------ extras
