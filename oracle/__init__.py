@@ -16,6 +16,8 @@ Time" (arXiv:1207.6365) it follows:
 * :mod:`.solve`    -- sketch-and-solve (Section 7 regression theorem),
   preconditioned LSQR and Richardson iteration (Section 7.7)
 * :mod:`.leverage` -- exact and approximate leverage scores (Section 6)
+* :mod:`.multiresponse` -- multiple-response regression by leverage-score
+  sampling (Section 7, generalized-regression algorithm)
 * :mod:`.lowrank`  -- rank-k approximation ``L D W^T`` (Section 8 theorem in
   the simplified form of the Section 10 experiments)
 * :mod:`.learned`  -- distortion loss and gradient of learned sketch values
@@ -30,6 +32,7 @@ from .hashing import bucket_and_sign, splitmix64  # noqa: F401
 from .learned import Adam, distortion_grad, distortion_loss, expected_plain_distortion  # noqa: F401
 from .leverage import leverage_approx, leverage_exact, sketch_r  # noqa: F401
 from .lowrank import best_rank_k_error, frobenius_error, low_rank  # noqa: F401
+from .multiresponse import multi_response_lstsq, residual_fro  # noqa: F401
 from .linalg import (  # noqa: F401
     RankDeficient,
     apply_qt,

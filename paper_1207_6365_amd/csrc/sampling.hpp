@@ -1,0 +1,468 @@
+// Kernels and host helpers shared by the paths that sample rows by leverage
+// scores (the rank-k approximation, Section 8 theorem in the Section 10 form,
+// and multiple-response regression, Section 7 generalized regression):
+// float64 GEMM on the matrix cores, fixed-order prefix sums, draws by binary
+// search, compaction and gathers of the drawn rows, and sparse-times-dense
+// products.  Everything sits in an unnamed namespace: each source file that
+// includes this gets its own copy.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace skls {
+namespace {
+
+constexpr uint64_t kPi2Salt = 0x6C65766572616765ull;     // "leverage"
+constexpr uint64_t kSampleSalt = 0x73616D706C696E67ull;  // "sampling"
+constexpr int kT = 256;
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+unsigned grid_for(int64_t work, int per_block, int64_t cap) {
+  int64_t g = div_up(work > 0 ? work : 1, per_block);
+  if (g > cap) g = cap;
+  return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------- float64 GEMM
+// C (M x N) = alpha op(A) B on the float64 matrix cores, one 64 x 64 tile per
+// block of four wavefronts (32 x 32 each), the inner dimension staged through
+// LDS 16 at a time.  op(A) = A (M x K, row-major, lda) or, with TA, A^T for A
+// stored K x M.  B is K x N (ldb).  With several splits of the inner
+// dimension (blockIdx.z), split z writes its partial product to
+// C + z * split_stride.
+template <bool TA>
+__global__ __launch_bounds__(kT) void k_gemm(int64_t M, int64_t N, int64_t K, int64_t kc, double alpha,
+                                             const double* __restrict__ A, int64_t lda,
+                                             const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
+                                             int64_t ldc, int64_t split_stride) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  const int wi = wv >> 1, wj = wv & 1;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 64, j0 = static_cast<int64_t>(blockIdx.y) * 64;
+  const int64_t kb = static_cast<int64_t>(blockIdx.z) * kc;
+  const int64_t ke = (kb + kc) < K ? kb + kc : K;
+  C += static_cast<int64_t>(blockIdx.z) * split_stride;
+  d4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * kT;
+      if (TA) {
+        const int c = e & 63, kk = e >> 6;
+        const int64_t gi = i0 + c, gk = k0 + kk;
+        As[kk][c] = (gi < M && gk < ke) ? A[gk * lda + gi] : 0.0;
+      } else {
+        const int kk = e & 15, c = e >> 4;
+        const int64_t gi = i0 + c, gk = k0 + kk;
+        As[kk][c] = (gi < M && gk < ke) ? A[gi * lda + gk] : 0.0;
+      }
+      const int c = e & 63, kk = e >> 6;
+      const int64_t gj = j0 + c, gk = k0 + kk;
+      Bs[kk][c] = (gj < N && gk < ke) ? B[gk * ldb + gj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const double a0 = As[kk + lr][wi * 32 + lc], a1 = As[kk + lr][wi * 32 + 16 + lc];
+      const double b0 = Bs[kk + lr][wj * 32 + lc], b1 = Bs[kk + lr][wj * 32 + 16 + lc];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+  // element e of lane l: row l / 16 + 4 e, column l % 16 of each 16 x 16 block
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = i0 + wi * 32 + a * 16 + lr + 4 * e, col = j0 + wj * 32 + b * 16 + lc;
+        if (row < M && col < N) C[row * ldc + col] = alpha * acc[a][b][e];
+      }
+}
+
+// C[i, j] = sum over splits of P[z][i, j] (M x N, leading dimension N).
+__global__ void k_sum_splits(const double* __restrict__ P, int splits, int64_t MN, double* __restrict__ C) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < MN;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < splits; ++z) s += P[static_cast<int64_t>(z) * MN + e];
+    C[e] = s;
+  }
+}
+
+// Pi2 [r][c] = +-1 / sqrt(k_G), sign from bit 0 of output r * k_G + c.
+__global__ void k_sign_projection(int rows, int kg, uint64_t seed, double* __restrict__ Pi2) {
+  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (e >= static_cast<int64_t>(rows) * kg) return;
+  const uint64_t z = splitmix64(seed ^ kPi2Salt, static_cast<uint64_t>(e));
+  const double v = 1.0 / sqrt(static_cast<double>(kg));
+  Pi2[e] = negative_of(z) ? -v : v;
+}
+
+// out[i] = sum_c Z[i][c]^2 (one wavefront per row); last[0] = largest i with out[i] > 0.
+__global__ __launch_bounds__(kT) void k_row_sqnorm(int64_t n, int cols, const double* __restrict__ Z,
+                                                   double* __restrict__ out, int32_t* __restrict__ last) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; i < n; i += nw) {
+    double s = 0.0;
+    for (int c = lane; c < cols; c += kWave) {
+      const double z = Z[static_cast<size_t>(i) * cols + c];
+      s += z * z;
+    }
+    s = wave_total(s);
+    if (lane == 0) {
+      out[i] = s;
+      if (s > 0.0) atomicMax(last, static_cast<int32_t>(i));
+    }
+  }
+}
+
+// Inclusive prefix sums in three passes: per-block sums of kScanTile
+// elements, a single-block scan of those sums, then the block scans with
+// their offsets.  The order of additions is fixed (deterministic).
+constexpr int kScanTile = 2048;  // 256 threads x 8
+
+template <typename T>
+__device__ T block_incl_scan(T v, T* sh) {
+  // inclusive scan of one value per thread over the block (256 threads)
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kT; off <<= 1) {
+    const T add = tid >= off ? sh[tid - off] : T(0);
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  const T r = sh[tid];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_scan_tiles(const T* __restrict__ in, int64_t n, T* __restrict__ tile_sum) {
+  __shared__ T sh[kT];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * 8;
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s += (base + q < n) ? in[base + q] : T(0);
+  const T tot = block_incl_scan(s, sh);
+  if (threadIdx.x == kT - 1) tile_sum[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_scan_top(T* __restrict__ tile_sum, int64_t ntiles) {
+  // exclusive scan of the tile sums in place, one block, 256 at a time
+  __shared__ T sh[kT];
+  __shared__ T tot;
+  T carry = 0;
+  for (int64_t c0 = 0; c0 < ntiles; c0 += kT) {
+    const int64_t i = c0 + threadIdx.x;
+    const T v = i < ntiles ? tile_sum[i] : T(0);
+    const T inc = block_incl_scan(v, sh);
+    if (i < ntiles) tile_sum[i] = carry + inc - v;
+    if (threadIdx.x == kT - 1) tot = inc;
+    __syncthreads();
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_scan_apply(const T* __restrict__ in, int64_t n,
+                                                   const T* __restrict__ tile_off, T* __restrict__ out,
+                                                   int exclusive) {
+  __shared__ T sh[kT];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * 8;
+  T v[8];
+  T s = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    v[q] = (base + q < n) ? in[base + q] : T(0);
+    s += v[q];
+  }
+  const T inc = block_incl_scan(s, sh);
+  T run = tile_off[blockIdx.x] + inc - s;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const T before = run;
+    run += v[q];
+    if (base + q < n) out[base + q] = exclusive ? before : run;
+  }
+}
+
+// Draw j: u = (z >> 11) 2^-53 from the sampling stream, x = u * total; the row
+// is the first i with cum[i] > x, at most `last` (the last positive score).
+__global__ void k_sample(int64_t ts, int64_t n, uint64_t seed, const double* __restrict__ cum,
+                         const double* __restrict__ score, const int32_t* __restrict__ last,
+                         int32_t* __restrict__ counts) {
+  const double total = cum[n - 1];
+  const int64_t hi_row = static_cast<int64_t>(last[0]);
+  for (int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; j < ts;
+       j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t z = splitmix64(seed ^ kSampleSalt, static_cast<uint64_t>(j));
+    const double x = static_cast<double>(z >> 11) * 0x1.0p-53 * total;
+    int64_t lo = 0, hi = n;  // first index with cum > x lies in [lo, hi]
+    while (lo < hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (cum[mid] > x)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    int64_t r = lo < hi_row ? lo : hi_row;
+    // the running sums are rounded per tile; never land on a row without score
+    while (r < hi_row && !(score[r] > 0.0)) ++r;
+    atomicAdd(&counts[r], 1);
+  }
+}
+
+__global__ void k_flags(int64_t n, const int32_t* __restrict__ counts, int32_t* __restrict__ flag) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    flag[i] = counts[i] > 0 ? 1 : 0;
+}
+
+// Sampled rows in increasing order: list[pos[i]] = i with weight
+// sqrt(count_i total / (t_S score_i)); len[pos[i]] = nonzeros of row i (CSR).
+template <typename TR>
+__global__ void k_compact(int64_t n, int64_t ts, const int32_t* __restrict__ counts, const int32_t* __restrict__ pos,
+                          const double* __restrict__ score, const double* __restrict__ cum,
+                          const TR* __restrict__ row_ptr, int32_t* __restrict__ list, double* __restrict__ wts,
+                          int64_t* __restrict__ len) {
+  const double total = cum[n - 1];
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int32_t c = counts[i];
+    if (c == 0) continue;
+    const int32_t p = pos[i];
+    list[p] = static_cast<int32_t>(i);
+    wts[p] = sqrt(static_cast<double>(c) * total / (static_cast<double>(ts) * score[i]));
+    if (len) len[p] = static_cast<int64_t>(row_ptr[i + 1]) - static_cast<int64_t>(row_ptr[i]);
+  }
+}
+
+// out[r][:] = w[r] * X[list[r]][:] (rows of width `cols`, float64 out)
+template <typename TV>
+__global__ __launch_bounds__(kT) void k_gather_rows(int64_t ns, int64_t cols, int64_t ldx, const TV* __restrict__ X,
+                                                    const int32_t* __restrict__ list,
+                                                    const double* __restrict__ w, double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < ns; r += nw) {
+    const size_t src = static_cast<size_t>(list[r]) * ldx;
+    const double s = w[r];
+    for (int64_t c = lane; c < cols; c += kWave)
+      out[static_cast<size_t>(r) * cols + c] = s * load_as<double>(X, src + c);
+  }
+}
+
+// Sampled CSR rows: columns copied, values scaled by the row weight (float64).
+template <typename TV, typename TR>
+__global__ __launch_bounds__(kT) void k_gather_csr(int64_t ns, const TR* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col, const TV* __restrict__ val,
+                                                   const int32_t* __restrict__ list, const double* __restrict__ w,
+                                                   const int64_t* __restrict__ rp, int32_t* __restrict__ col_out,
+                                                   double* __restrict__ val_out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < ns; r += nw) {
+    const int32_t i = list[r];
+    const int64_t b = static_cast<int64_t>(row_ptr[i]), e = static_cast<int64_t>(row_ptr[i + 1]);
+    const int64_t o = rp[r];
+    const double s = w[r];
+    for (int64_t k = lane; k < e - b; k += kWave) {
+      col_out[o + k] = col[b + k];
+      val_out[o + k] = s * load_as<double>(val, static_cast<size_t>(b + k));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- sparse products
+__device__ __forceinline__ int32_t lane_i(int32_t v, int q) { return __builtin_amdgcn_readlane(v, q); }
+__device__ __forceinline__ double lane_d(double v, int q) {
+  const long long b = __double_as_longlong(v);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(b & 0xffffffffll), q));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int32_t>(b >> 32), q));
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+// out (rows x p) = S X for S in CSR (any value and row-pointer type) and X
+// (cols x p, float64); one wavefront per row.  The row's entries are loaded
+// 64 at a time and read back lane by lane as scalars (uniform index), four
+// independent loads of X in flight.  HALF: p <= 32, the two half-waves take
+// alternate entries and are summed at the end.
+template <typename TV, typename TR, bool HALF>
+__global__ __launch_bounds__(kT) void k_spmm(int64_t rows, int p, const TR* __restrict__ rp,
+                                             const int32_t* __restrict__ col, const TV* __restrict__ val,
+                                             const double* __restrict__ X, double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  const int c = HALF ? (lane & 31) : lane;
+  const int h = HALF ? (lane >> 5) : 0;
+  const bool live = c < p;
+  const int lc = live ? c : 0;
+  constexpr int STEP = HALF ? 2 : 1;
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
+    const int64_t b = static_cast<int64_t>(rp[r]), e = static_cast<int64_t>(rp[r + 1]);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int64_t k0 = b; k0 < e; k0 += kWave) {
+      const int64_t k = k0 + lane;
+      const int32_t cj = k < e ? col[k] : 0;
+      const double vj = k < e ? load_as<double>(val, static_cast<size_t>(k)) : 0.0;  // 0 beyond the row
+      const int cnt = (e - k0) < kWave ? static_cast<int>(e - k0) : kWave;
+      const int cnt_up = (cnt + 4 * STEP - 1) / (4 * STEP) * (4 * STEP);  // zero values pad the tail
+      for (int q = 0; q < cnt_up; q += 4 * STEP) {
+        int32_t j[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int qa = q + u * STEP;
+          if (HALF) {
+            const int32_t ja = lane_i(cj, qa), jb = lane_i(cj, qa + 1);
+            const double va = lane_d(vj, qa), vb = lane_d(vj, qa + 1);
+            j[u] = h ? jb : ja;
+            v[u] = h ? vb : va;
+          } else {
+            j[u] = lane_i(cj, qa);
+            v[u] = lane_d(vj, qa);
+          }
+        }
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = X[static_cast<size_t>(j[u]) * p + lc];
+        acc0 += v[0] * x[0] + v[2] * x[2];
+        acc1 += v[1] * x[1] + v[3] * x[3];
+      }
+    }
+    double acc = acc0 + acc1;
+    if (HALF) acc += __shfl_xor(acc, 32);
+    if (live && h == 0) out[static_cast<size_t>(r) * p + c] = acc;
+  }
+}
+
+// out (rows x p) = A X for dense A (rows x cols, leading dimension ld, any
+// value type) and X (cols x p); one wavefront per row as in k_spmm.
+template <typename TV>
+__global__ __launch_bounds__(kT) void k_dense_times(int64_t rows, int64_t cols, int64_t ld, int p,
+                                                    const TV* __restrict__ A, const double* __restrict__ X,
+                                                    double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  const int lc = lane < p ? lane : 0;
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
+    double acc = 0.0;
+    for (int64_t j0 = 0; j0 < cols; j0 += kWave) {
+      const int64_t j = j0 + lane;
+      const double aj = j < cols ? load_as<double>(A, static_cast<size_t>(r) * ld + j) : 0.0;
+      const int cnt = (cols - j0) < kWave ? static_cast<int>(cols - j0) : kWave;
+      for (int q = 0; q < cnt; ++q) acc += lane_d(aj, q) * X[static_cast<size_t>(j0 + q) * p + lc];
+    }
+    if (lane < p) out[static_cast<size_t>(r) * p + lane] = acc;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+namespace {
+
+template <typename F>
+int32_t with_value(int32_t dt, F&& f) {
+  switch (dt) {
+    case SKLS_F64: return f(double{});
+    case SKLS_F32: return f(float{});
+    case SKLS_BF16: return f(bf16_t{});
+    default: set_error("unsupported value dtype %d", dt); return SKLS_ERR_DTYPE;
+  }
+}
+template <typename F>
+int32_t with_rowptr(const skls_matrix& A, F&& f) {
+  if (A.row_ptr_64) return f(int64_t{});
+  return f(int32_t{});
+}
+
+struct GemmScratch {
+  double* part;
+  size_t doubles;
+};
+
+// C = alpha op(A) B with the inner dimension split when the output has few
+// tiles and the inner dimension is long.
+int32_t gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+             int64_t ldb, double* C, int64_t ldc, const GemmScratch& sc, hipStream_t s) {
+  if (M == 0 || N == 0) return SKLS_OK;
+  const int64_t tiles = div_up(M, 64) * div_up(N, 64);
+  int64_t splits = 1;
+  if (tiles < 256 && K > 1024) {
+    splits = div_up(512, tiles);
+    const int64_t by_k = div_up(K, 256);
+    if (splits > by_k) splits = by_k;
+    if (splits > 256) splits = 256;
+    while (splits > 1 && static_cast<size_t>(splits) * M * N > sc.doubles) --splits;
+  }
+  const int64_t kc = div_up(div_up(K > 0 ? K : 1, splits), 16) * 16;
+  splits = div_up(K > 0 ? K : 1, kc);
+  const dim3 grid(static_cast<unsigned>(div_up(M, 64)), static_cast<unsigned>(div_up(N, 64)),
+                  static_cast<unsigned>(splits));
+  double* out = splits > 1 ? sc.part : C;
+  const int64_t ldo = splits > 1 ? N : ldc;
+  if (splits > 1 && ldc != N) {
+    set_error("internal: split GEMM needs a packed output");
+    return SKLS_ERR_ARG;
+  }
+  if (ta)
+    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(kT), 0, s, M, N, K, kc, alpha, A, lda, B, ldb, out, ldo, M * N);
+  else
+    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(kT), 0, s, M, N, K, kc, alpha, A, lda, B, ldb, out, ldo, M * N);
+  SKLS_CHECK_LAUNCH();
+  if (splits > 1) {
+    hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(M * N, kT, 4096)), dim3(kT), 0, s, sc.part,
+                       static_cast<int>(splits), M * N, C);
+    SKLS_CHECK_LAUNCH();
+  }
+  return SKLS_OK;
+}
+
+template <typename T>
+int32_t scan(const T* in, int64_t n, T* tiles, T* out, bool exclusive, hipStream_t s) {
+  if (n == 0) return SKLS_OK;
+  const int64_t nt = div_up(n, kScanTile);
+  hipLaunchKernelGGL(k_scan_tiles<T>, dim3(static_cast<unsigned>(nt)), dim3(kT), 0, s, in, n, tiles);
+  SKLS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(kT), 0, s, tiles, nt);
+  SKLS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3(static_cast<unsigned>(nt)), dim3(kT), 0, s, in, n, tiles, out,
+                     exclusive ? 1 : 0);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
+
+int64_t tiles_for(int64_t n) { return div_up(n > 0 ? n : 1, kScanTile) + 1; }
+
+int32_t to_host(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  SKLS_TRY_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+  SKLS_TRY_HIP(hipStreamSynchronize(s));
+  return SKLS_OK;
+}
+
+}  // namespace
+}  // namespace skls
