@@ -301,6 +301,52 @@ SKLS_API int32_t skls_profile_count(void);
 SKLS_API int32_t skls_profile_get(int32_t index, const char** name, int64_t* launches, double* total_ms);
 
 /*
+ * Multiple-response regression min_Y ||A Y - B||_F by leverage-score sampling
+ * (Section 7, theorem on the generalized-regression algorithm):
+ *  1. leverage scores of A to constant relative error (Section 6 theorem):
+ *     R1 from the float64 Gram of S1 A for the sparse embedding S1 with t rows
+ *     (stream `seed`, as skls_sketch), scores = squared row norms of
+ *     A R1^{-1} Pi2 with Pi2 the d x k_g sign matrix / sqrt(k_g) of
+ *     skls_low_rank (stream seed ^ 0x6C65766572616765), float64 throughout;
+ *  2. t_s draws with replacement with probabilities proportional to the
+ *     scores (uniforms and the rule of skls_low_rank, stream
+ *     seed ^ 0x73616D706C696E67); a row drawn c times enters once with weight
+ *     sqrt(c / (t_s p)) -- the coreset;
+ *  3. Y = R^{-1} Q^T (S B) for S A = Q R.
+ * Synchronous.
+ */
+typedef struct {
+  int64_t t;          /* rows of S1 (d <= t < 2^31) */
+  int64_t t_s;        /* draws of the sampling (d <= t_s < 2^31) */
+  uint64_t seed;
+  int32_t k_g;        /* columns of Pi2 (0: 32; at most 64) */
+  int32_t reserved[5];
+} skls_multi_opts;
+
+typedef struct {
+  int64_t rows_sampled;  /* distinct rows in the coreset */
+  double resid_fro;      /* ||A Y - B||_F (float64 accumulation) */
+  double b_fro;          /* ||B||_F */
+  float ms_scores, ms_solve;
+  int32_t reserved[4];
+} skls_multi_info;
+
+SKLS_API int32_t skls_multi_lstsq_workspace(const skls_matrix* A, int64_t dp, const skls_multi_opts* opts,
+                                            size_t* bytes);
+/*
+ *  A:       dense (F64, F32, BF16) or CSR, n x d, d <= 8192.
+ *  B:       device float64 n x dp row-major, 1 <= dp <= 64.
+ *  Y:       device float64 d x dp row-major.
+ *  rows:    device int32 [min(n, t_s)] or NULL: the coreset's rows in
+ *           increasing order (the first info->rows_sampled entries).
+ *  weights: device float64 [min(n, t_s)] or NULL: their weights.
+ * Errors: SKLS_ERR_RANK when S1 A or S A is numerically rank deficient.
+ */
+SKLS_API int32_t skls_multi_lstsq(const skls_matrix* A, const double* B, int64_t dp, const skls_multi_opts* opts,
+                                  double* Y, int32_t* rows, double* weights, skls_multi_info* info, void* ws,
+                                  size_t ws_bytes, void* stream);
+
+/*
  * Rank-k approximation A ~ L diag(D) W^T (Section 8, theorem on low-rank
  * approximation), in the simplified form of the Section 10 experiments:
  *  1. Y = A R^T for R^ a t_r x m sparse embedding of the columns of A (h and

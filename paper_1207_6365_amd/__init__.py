@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     lib,
     low_rank,
     lstsq,
+    multi_lstsq,
     qr_r,
     sketch,
     sketch_general,

@@ -104,6 +104,27 @@ class SklsLowRankInfo(ctypes.Structure):
     ]
 
 
+class SklsMultiOpts(ctypes.Structure):
+    _fields_ = [
+        ("t", c_int64),
+        ("t_s", c_int64),
+        ("seed", c_uint64),
+        ("k_g", c_int32),
+        ("reserved", c_int32 * 5),
+    ]
+
+
+class SklsMultiInfo(ctypes.Structure):
+    _fields_ = [
+        ("rows_sampled", c_int64),
+        ("resid_fro", c_double),
+        ("b_fro", c_double),
+        ("ms_scores", ctypes.c_float),
+        ("ms_solve", ctypes.c_float),
+        ("reserved", c_int32 * 4),
+    ]
+
+
 # name -> (restype, argtypes); every symbol declared in include/skls.h
 SIGNATURES = {
     "skls_status_str": (c_char_p, [c_int32]),
@@ -134,6 +155,9 @@ SIGNATURES = {
     "skls_profile_enable": (c_int32, [c_int32]),
     "skls_profile_count": (c_int32, []),
     "skls_profile_get": (c_int32, [c_int32, POINTER(c_char_p), POINTER(c_int64), POINTER(c_double)]),
+    "skls_multi_lstsq_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, POINTER(SklsMultiOpts), POINTER(c_size_t)]),
+    "skls_multi_lstsq": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int64, POINTER(SklsMultiOpts), c_void_p, c_void_p,
+                                   c_void_p, POINTER(SklsMultiInfo), c_void_p, c_size_t, c_void_p]),
     "skls_low_rank_workspace": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLowRankOpts), POINTER(c_size_t)]),
     "skls_low_rank": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLowRankOpts), c_void_p, c_void_p, c_void_p,
                                 POINTER(SklsLowRankInfo), c_void_p, c_size_t, c_void_p]),

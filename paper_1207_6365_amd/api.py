@@ -194,6 +194,31 @@ def lstsq(A, b: torch.Tensor, t: int, seed: int, delta: float = 1e-6, precision:
     return x, out
 
 
+def multi_lstsq(A, B: torch.Tensor, t: int, t_s: int, seed: int, k_g: int = 0, coreset: bool = False):
+    """Multiple-response regression ``min_Y ||A Y - B||_F`` by leverage-score
+    sampling (Section 7, generalized-regression algorithm).  Returns ``(Y,
+    info)``, plus the coreset ``(rows, weights)`` when ``coreset``."""
+    m, device = _matrix(A)
+    if B.dtype != torch.float64 or not B.is_contiguous() or B.dim() != 2 or B.shape[0] != m.n:
+        raise TypeError("B must be a contiguous float64 n x d' tensor")
+    dp = B.shape[1]
+    o = L.SklsMultiOpts()
+    o.t, o.t_s, o.seed, o.k_g = t, t_s, seed & 0xFFFFFFFFFFFFFFFF, k_g
+    ws = _workspace(_size(lib().skls_multi_lstsq_workspace, ctypes.byref(m), dp, ctypes.byref(o)), device)
+    Y = torch.empty((m.d, dp), dtype=torch.float64, device=device)
+    cap = min(m.n, t_s)
+    rows = torch.empty(cap, dtype=torch.int32, device=device) if coreset else None
+    wts = torch.empty(cap, dtype=torch.float64, device=device) if coreset else None
+    info = L.SklsMultiInfo()
+    L.check(lib().skls_multi_lstsq(ctypes.byref(m), _ptr(B), dp, ctypes.byref(o), _ptr(Y), _ptr(rows), _ptr(wts),
+                                   ctypes.byref(info), _ptr(ws), ws.numel(), _stream(device)))
+    out = {f: getattr(info, f) for f, _ in L.SklsMultiInfo._fields_ if f != "reserved"}
+    if coreset:
+        k = out["rows_sampled"]
+        return Y, out, (rows[:k], wts[:k])
+    return Y, out
+
+
 # ------------------------------------------------------------------ a5
 def leverage_scores(A, t: int, seed: int, Pi2: torch.Tensor):
     """Squared row norms of ``A R^{-1} Pi2`` (``Pi2``: ``d x k`` float64)."""

@@ -751,6 +751,33 @@ int32_t skls_adam_step(int64_t n, float* w, const float* g, float* m, float* v, 
   return run_adam(n, w, g, m, v, step, lr, beta1, beta2, eps, as_stream(stream));
 }
 
+int32_t skls_multi_lstsq_workspace(const skls_matrix* A, int64_t dp, const skls_multi_opts* opts, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (opts == nullptr || bytes == nullptr) {
+    set_error("opts and bytes must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  MultiPlan P;
+  SKLS_TRY(multi_plan(*A, dp, *opts, P));
+  *bytes = multi_ws_bytes(P);
+  return SKLS_OK;
+}
+
+int32_t skls_multi_lstsq(const skls_matrix* A, const double* B, int64_t dp, const skls_multi_opts* opts, double* Y,
+                         int32_t* rows, double* weights, skls_multi_info* info, void* ws, size_t ws_bytes,
+                         void* stream) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (opts == nullptr || B == nullptr || Y == nullptr) {
+    set_error("opts, B and Y must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  MultiPlan P;
+  SKLS_TRY(multi_plan(*A, dp, *opts, P));
+  return run_multi_lstsq(*A, B, P, opts->seed, Y, rows, weights, info, ws, ws_bytes, as_stream(stream));
+}
+
 int32_t skls_low_rank_workspace(const skls_matrix* A, const skls_low_rank_opts* opts, size_t* bytes) {
   clear_error();
   SKLS_TRY(validate_matrix(A, true));

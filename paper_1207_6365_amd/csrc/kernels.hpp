@@ -115,4 +115,16 @@ size_t low_rank_ws_bytes(const LowRankPlan& P);
 int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, double* L, double* D, double* W,
                      skls_low_rank_info* info, void* ws, size_t ws_bytes, hipStream_t s);
 
+// ---------------------------------------------------------------- regress.hip
+struct MultiPlan {
+  int64_t n, d, dp, t, ts, nsmax;
+  int kg;
+  size_t sk_bytes;
+};
+int32_t multi_plan(const skls_matrix& A, int64_t dp, const skls_multi_opts& o, MultiPlan& P);
+size_t multi_ws_bytes(const MultiPlan& P);
+int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& P, uint64_t seed, double* Y,
+                        int32_t* rows_out, double* weights_out, skls_multi_info* info, void* ws, size_t ws_bytes,
+                        hipStream_t s);
+
 }  // namespace skls

@@ -26,7 +26,7 @@ def lib():
 def test_header_declares_the_entry_points():
     names = _declared()
     for must in ("skls_hash", "skls_sketch", "skls_lstsq", "skls_leverage_scores", "skls_low_rank",
-                 "skls_learned_grad", "skls_qr_r"):
+                 "skls_learned_grad", "skls_qr_r", "skls_sketch_general", "skls_multi_lstsq"):
         assert must in names
 
 
