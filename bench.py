@@ -12,7 +12,8 @@ Also reported on the same JSON line: the generalized sparse embedding of the
 same input (4 copies), the dense float32 variant (n = 2^20),
 sketch-and-solve on the small sparse regression (n = 20000, d = 20), least
 squares on the dense heavy-row regression workload (n = 2^21, d = 512,
-t = 2^18) in the plain float64 form and the mixed-precision forms, leverage
+t = 2^18) in the plain float64 form and the mixed-precision forms,
+multiple-response regression by leverage-score sampling on it, leverage
 scores on the same workload, a rank-k approximation of a planted low-rank
 sparse matrix (n = 65536, about 10M nonzeros, k = 32), learned sketch values
 trained on a family of 256
@@ -49,7 +50,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--lstsq-steps", type=int, default=3)
     p.add_argument("--only", default=None,
-                   choices=["general", "dense", "small", "lstsq", "leverage", "low_rank", "learned"],
+                   choices=["general", "dense", "small", "lstsq", "multi", "leverage", "low_rank", "learned"],
                    help="run only this extra workload after the headline")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run a plain device copy of this many MiB first (scale for HBM byte counters)")
@@ -313,6 +314,41 @@ def main():
                 del A3g, b3g
                 torch.cuda.empty_cache()
             result["lstsq"] = res
+
+        if want("multi"):
+            # multiple-response regression by leverage-score sampling on the
+            # heavy-row workload with d' = 16 responses; the optimum per
+            # response from solves certified to 1 + 1e-11
+            dp, t_s = 16, 16384
+            log(f"multiple-response regression: n=2^21 d=512 float32, d'={dp}, t=2^18, t_s={t_s}")
+            A3, _, _ = W.pareto_rows(n=n3, d=d3, storage="f32")
+            g5 = np.random.default_rng(W.data_seed(3, 7))
+            Y0 = g5.standard_normal((d3, dp))
+            B3 = np.empty((n3, dp))
+            for r0 in range(0, n3, 1 << 18):
+                B3[r0:r0 + (1 << 18)] = A3[r0:r0 + (1 << 18)].astype(np.float64) @ Y0
+            B3 += 1e-3 * g5.standard_normal((n3, dp))
+            A3g = torch.from_numpy(A3).to(dev)
+            B3g = torch.from_numpy(B3).to(dev)
+            del A3, B3
+            sk.multi_lstsq(A3g, B3g, t3, t_s, seed)  # warm-up
+            sync()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                Ym, minfo = sk.multi_lstsq(A3g, B3g, t3, t_s, seed)
+            sync()
+            el = (time.perf_counter() - t0) / reps
+            opt2 = 0.0
+            for c in range(dp):
+                _, ci = sk.lstsq(A3g, B3g[:, c].contiguous(), t3, seed, delta=1e-11)
+                opt2 += ci["resid_norm"] ** 2
+            result["multi_response"] = {
+                "ms_per_call": el * 1e3, "d_rhs": dp, "t": t3, "t_s": t_s, "rows_sampled": minfo["rows_sampled"],
+                "residual_ratio": minfo["resid_fro"] / np.sqrt(opt2), "ms_scores": minfo["ms_scores"],
+                "ms_solve": minfo["ms_solve"]}
+            del A3g, B3g
+            torch.cuda.empty_cache()
 
         if want("leverage"):
             # leverage scores on the same heavy-row workload (float32 storage), k = 32

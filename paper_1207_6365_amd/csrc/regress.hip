@@ -195,10 +195,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
     int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
       using TV = decltype(tv);
       if (A.layout != SKLS_CSR) {
-        hipLaunchKernelGGL(k_dense_times<TV>, dim3(g), dim3(kT), 0, s, n, d, A.ld, kg, static_cast<const TV*>(A.val),
-                           w.T, w.Z);
-        SKLS_CHECK_LAUNCH();
-        return SKLS_OK;
+        return gemm<TV>(false, n, kg, d, 1.0, static_cast<const TV*>(A.val), A.ld, w.T, kg, w.Z, kg, w.gs, s);
       }
       return with_rowptr(A, [&](auto trt) -> int32_t {
         using TR = decltype(trt);
@@ -293,10 +290,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
     st = with_value(A.dtype, [&](auto tv) -> int32_t {
       using TV = decltype(tv);
       if (A.layout != SKLS_CSR) {
-        hipLaunchKernelGGL(k_dense_times<TV>, dim3(g), dim3(kT), 0, s, n, d, A.ld, dpi, static_cast<const TV*>(A.val),
-                           Y, w.AY);
-        SKLS_CHECK_LAUNCH();
-        return SKLS_OK;
+        return gemm<TV>(false, n, dp, d, 1.0, static_cast<const TV*>(A.val), A.ld, Y, dp, w.AY, dp, w.gs, s);
       }
       return with_rowptr(A, [&](auto trt) -> int32_t {
         using TR = decltype(trt);

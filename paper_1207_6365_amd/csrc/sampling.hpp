@@ -29,24 +29,28 @@ unsigned grid_for(int64_t work, int per_block, int64_t cap) {
 }
 
 // ---------------------------------------------------------------- float64 GEMM
-// C (M x N) = alpha op(A) B on the float64 matrix cores, one 64 x 64 tile per
-// block of four wavefronts (32 x 32 each), the inner dimension staged through
+// C (M x N) = alpha op(A) B on the float64 matrix cores, one tile per block
+// of four wavefronts (32 x 32 outputs each; 64 x 64 tiles, or 128 x 32 for
+// outputs at most 32 wide), the inner dimension staged through
 // LDS 16 at a time.  op(A) = A (M x K, row-major, lda) or, with TA, A^T for A
-// stored K x M.  B is K x N (ldb).  With several splits of the inner
+// stored K x M; A may hold float64, float32 or bfloat16 values (widened on
+// load).  B is K x N (ldb).  With several splits of the inner
 // dimension (blockIdx.z), split z writes its partial product to
 // C + z * split_stride.
-template <bool TA>
+template <bool TA, typename TAV, int WI>
 __global__ __launch_bounds__(kT) void k_gemm(int64_t M, int64_t N, int64_t K, int64_t kc, double alpha,
-                                             const double* __restrict__ A, int64_t lda,
+                                             const TAV* __restrict__ A, int64_t lda,
                                              const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
                                              int64_t ldc, int64_t split_stride) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  constexpr int WJ = 4 / WI;           // wavefronts: WI x WJ, 32 x 32 outputs each
+  constexpr int TM = 32 * WI, TN = 32 * WJ;
+  __shared__ double As[16][TM + 1];
+  __shared__ double Bs[16][TN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wv = tid / kWave;
-  const int wi = wv >> 1, wj = wv & 1;
+  const int wi = wv / WJ, wj = wv % WJ;
   const int lr = lane >> 4, lc = lane & 15;
-  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * 64, j0 = static_cast<int64_t>(blockIdx.y) * 64;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * TM, j0 = static_cast<int64_t>(blockIdx.y) * TN;
   const int64_t kb = static_cast<int64_t>(blockIdx.z) * kc;
   const int64_t ke = (kb + kc) < K ? kb + kc : K;
   C += static_cast<int64_t>(blockIdx.z) * split_stride;
@@ -58,18 +62,22 @@ __global__ __launch_bounds__(kT) void k_gemm(int64_t M, int64_t N, int64_t K, in
   for (int64_t k0 = kb; k0 < ke; k0 += 16) {
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 16 * TM / kT; ++r) {
       const int e = tid + r * kT;
       if (TA) {
-        const int c = e & 63, kk = e >> 6;
+        const int c = e % TM, kk = e / TM;
         const int64_t gi = i0 + c, gk = k0 + kk;
-        As[kk][c] = (gi < M && gk < ke) ? A[gk * lda + gi] : 0.0;
+        As[kk][c] = (gi < M && gk < ke) ? load_as<double>(A, static_cast<size_t>(gk * lda + gi)) : 0.0;
       } else {
         const int kk = e & 15, c = e >> 4;
         const int64_t gi = i0 + c, gk = k0 + kk;
-        As[kk][c] = (gi < M && gk < ke) ? A[gi * lda + gk] : 0.0;
+        As[kk][c] = (gi < M && gk < ke) ? load_as<double>(A, static_cast<size_t>(gi * lda + gk)) : 0.0;
       }
-      const int c = e & 63, kk = e >> 6;
+    }
+#pragma unroll
+    for (int r = 0; r < 16 * TN / kT; ++r) {
+      const int e = tid + r * kT;
+      const int c = e % TN, kk = e / TN;
       const int64_t gj = j0 + c, gk = k0 + kk;
       Bs[kk][c] = (gj < N && gk < ke) ? B[gk * ldb + gj] : 0.0;
     }
@@ -118,8 +126,10 @@ __global__ void k_sign_projection(int rows, int kg, uint64_t seed, double* __res
 // out[i] = sum_c Z[i][c]^2 (one wavefront per row); last[0] = largest i with out[i] > 0.
 __global__ __launch_bounds__(kT) void k_row_sqnorm(int64_t n, int cols, const double* __restrict__ Z,
                                                    double* __restrict__ out, int32_t* __restrict__ last) {
+  __shared__ int32_t wlast[kT / kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  int32_t mine = -1;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; i < n; i += nw) {
     double s = 0.0;
     for (int c = lane; c < cols; c += kWave) {
@@ -127,10 +137,15 @@ __global__ __launch_bounds__(kT) void k_row_sqnorm(int64_t n, int cols, const do
       s += z * z;
     }
     s = wave_total(s);
-    if (lane == 0) {
-      out[i] = s;
-      if (s > 0.0) atomicMax(last, static_cast<int32_t>(i));
-    }
+    if (lane == 0) out[i] = s;
+    if (s > 0.0) mine = static_cast<int32_t>(i);  // rows only grow along the loop
+  }
+  if (lane == 0) wlast[threadIdx.x / kWave] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t m = -1;
+    for (int k = 0; k < kT / kWave; ++k) m = wlast[k] > m ? wlast[k] : m;
+    if (m >= 0) atomicMax(last, m);
   }
 }
 
@@ -406,10 +421,13 @@ struct GemmScratch {
 
 // C = alpha op(A) B with the inner dimension split when the output has few
 // tiles and the inner dimension is long.
-int32_t gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+template <typename TAV = double>
+int32_t gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const TAV* A, int64_t lda, const double* B,
              int64_t ldb, double* C, int64_t ldc, const GemmScratch& sc, hipStream_t s) {
   if (M == 0 || N == 0) return SKLS_OK;
-  const int64_t tiles = div_up(M, 64) * div_up(N, 64);
+  const bool narrow = N <= 32;
+  const int64_t TM = narrow ? 128 : 64, TN = narrow ? 32 : 64;
+  const int64_t tiles = div_up(M, TM) * div_up(N, TN);
   int64_t splits = 1;
   if (tiles < 256 && K > 1024) {
     splits = div_up(512, tiles);
@@ -420,7 +438,7 @@ int32_t gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const doubl
   }
   const int64_t kc = div_up(div_up(K > 0 ? K : 1, splits), 16) * 16;
   splits = div_up(K > 0 ? K : 1, kc);
-  const dim3 grid(static_cast<unsigned>(div_up(M, 64)), static_cast<unsigned>(div_up(N, 64)),
+  const dim3 grid(static_cast<unsigned>(div_up(M, TM)), static_cast<unsigned>(div_up(N, TN)),
                   static_cast<unsigned>(splits));
   double* out = splits > 1 ? sc.part : C;
   const int64_t ldo = splits > 1 ? N : ldc;
@@ -428,10 +446,13 @@ int32_t gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const doubl
     set_error("internal: split GEMM needs a packed output");
     return SKLS_ERR_ARG;
   }
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(kT), 0, s, M, N, K, kc, alpha, A, lda, B, ldb, out, ldo, M * N);
+  };
   if (ta)
-    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(kT), 0, s, M, N, K, kc, alpha, A, lda, B, ldb, out, ldo, M * N);
+    narrow ? launch(k_gemm<true, TAV, 4>) : launch(k_gemm<true, TAV, 2>);
   else
-    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(kT), 0, s, M, N, K, kc, alpha, A, lda, B, ldb, out, ldo, M * N);
+    narrow ? launch(k_gemm<false, TAV, 4>) : launch(k_gemm<false, TAV, 2>);
   SKLS_CHECK_LAUNCH();
   if (splits > 1) {
     hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(M * N, kT, 4096)), dim3(kT), 0, s, sc.part,
