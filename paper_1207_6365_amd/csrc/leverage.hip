@@ -74,6 +74,108 @@ __global__ __launch_bounds__(kLevThreads) void k_leverage_dense(int64_t n, int d
 typedef float f4_t __attribute__((ext_vector_type(4)));
 constexpr int kLevChunk = 64;  // columns per chunk
 
+// Wide-load form for rows whose length is a multiple of 4 and 16-byte aligned:
+// each wavefront stages its 16 rows x 32 columns through a private LDS tile
+// filled by 16-byte loads (8 lanes cover 128 contiguous bytes of a row), and
+// reads the A operand back as 16-byte rows.  The contraction index is taken
+// in a permuted order -- step (m, e) pairs lane (row, kk)'s element
+// A[row][c0 + 16 m + 4 kk + e] with B row c0 + 16 m + 4 kk + e -- so that
+// each lane's operands are one contiguous float4.  The next chunk is loaded
+// before the current one is multiplied.  One block of 16 wavefronts per
+// compute unit shares T.
+constexpr int kWideCols = 32;
+constexpr int kWidePitch = kWideCols + 4;  // floats; rows stay 16-byte aligned
+
+template <typename TV>
+__device__ __forceinline__ f4_t load4f(const TV* p) {
+  if constexpr (std::is_same<TV, float>::value) {
+    return *reinterpret_cast<const f4_t*>(p);
+  } else if constexpr (std::is_same<TV, double>::value) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    return f4_t{static_cast<float>(a.x), static_cast<float>(a.y), static_cast<float>(b.x), static_cast<float>(b.y)};
+  } else {
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    return f4_t{bf16_lo(u.x), bf16_hi(u.x), bf16_lo(u.y), bf16_hi(u.y)};
+  }
+}
+
+template <typename TV, int NB>
+__global__ __launch_bounds__(1024) void k_leverage_wide(int64_t n, int d, int64_t ld, const TV* __restrict__ A,
+                                                        const float* __restrict__ T, int k, int dpad,
+                                                        float* __restrict__ scores) {
+  extern __shared__ __align__(16) float smem[];
+  constexpr int KW = 16 * NB;
+  float* sT = smem;                                    // [dpad][KW]
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  float* tile = smem + static_cast<size_t>(dpad) * KW + static_cast<size_t>(wid) * 16 * kWidePitch;
+  for (int e = threadIdx.x; e < dpad * KW; e += blockDim.x) {
+    const int r = e / KW, q = e % KW;
+    sT[e] = (r < d && q < k) ? T[static_cast<size_t>(r) * k + q] : 0.0f;
+  }
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  // loads: lane -> row (lane >> 3) + 8 it, columns 4 (lane & 7) .. + 3
+  const int lrow = lane >> 3, lcol = 4 * (lane & 7);
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwave = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  const int nchunk = dpad / kWideCols;
+  for (int64_t r0 = wave * 16; r0 < n; r0 += nwave * 16) {
+    const TV* rowp[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int64_t r = r0 + lrow + 8 * it;
+      rowp[it] = A + static_cast<size_t>(r < n ? r : n - 1) * ld;  // rows past n: computed, not stored
+    }
+    f4_t nxt[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) nxt[it] = lcol < d ? load4f<TV>(rowp[it] + lcol) : f4_t{0.f, 0.f, 0.f, 0.f};
+    f4_t acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int c0 = ch * kWideCols;
+#pragma unroll
+      for (int it = 0; it < 2; ++it)
+        *reinterpret_cast<f4_t*>(tile + (lrow + 8 * it) * kWidePitch + lcol) = nxt[it];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (ch + 1 < nchunk) {
+        const int c = c0 + kWideCols + lcol;
+#pragma unroll
+        for (int it = 0; it < 2; ++it) nxt[it] = c < d ? load4f<TV>(rowp[it] + c) : f4_t{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int m = 0; m < kWideCols / 16; ++m) {
+        const f4_t a = *reinterpret_cast<const f4_t*>(tile + li * kWidePitch + 16 * m + 4 * lk);
+        const float* tb = sT + static_cast<size_t>(c0 + 16 * m + 4 * lk) * KW + li;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], tb[e * KW + 16 * b], acc[b], 0, 0, 0);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // row 4 lk + e: sum of squares over the NB blocks and the 16 lanes of the DPP row
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float v = 0.0f;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) v += acc[b][e] * acc[b][e];
+      v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));  // row_shr:1
+      v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, false));  // row_shr:2
+      v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, false));  // row_shr:4
+      v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, false));  // row_shr:8
+      const int64_t r = r0 + 4 * lk + e;
+      if (li == 15 && r < n) scores[r] = v;
+    }
+  }
+}
+
 template <typename TV, int NB>
 __global__ __launch_bounds__(512) void k_leverage_mfma(int64_t n, int d, int64_t ld, const TV* __restrict__ A,
                                                        const float* __restrict__ T, int k, int d64,
@@ -206,6 +308,24 @@ int32_t run_leverage(const skls_matrix& A, const float* T, int32_t k, float* sco
         constexpr int NB = K <= 16 ? 1 : (K <= 32 ? 2 : 4);
         const int d64 = static_cast<int>(div_up(d, kLevChunk) * kLevChunk);
         const size_t tl = static_cast<size_t>(d64) * 16 * NB * sizeof(float);
+        constexpr int VB = sizeof(TV) == 2 ? 8 : 16;  // bytes of a 4-element load
+        const bool wide = d % 4 == 0 && (A.ld * static_cast<int64_t>(sizeof(TV))) % VB == 0 &&
+                          reinterpret_cast<uintptr_t>(A.val) % VB == 0;
+        const int dpad = static_cast<int>(div_up(d, kWideCols) * kWideCols);
+        const size_t wl = (static_cast<size_t>(dpad) * 16 * NB + 16 * kWidePitch * 16) * sizeof(float);
+        if (wide && wl <= 150 * 1024) {
+          SKLS_TRY(allow_lds(k_leverage_wide<TV, NB>, wl));
+          int cus = 256;
+          int dev = 0;
+          if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+          int64_t g = div_up(A.n, 16 * 16);
+          if (g > cus) g = cus;
+          hipLaunchKernelGGL((k_leverage_wide<TV, NB>), dim3(static_cast<unsigned>(g)), dim3(1024), wl, s, A.n, d,
+                             A.ld, static_cast<const TV*>(A.val), T, k, dpad, scores);
+          SKLS_CHECK_LAUNCH();
+          return SKLS_OK;
+        }
         if (tl <= 72 * 1024) {
           SKLS_TRY(allow_lds(k_leverage_mfma<TV, NB>, tl));
           int64_t g = div_up(A.n, 16 * 8);
