@@ -107,40 +107,6 @@ def time_steps(fn, steps, warmup, sync):
     return e0.elapsed_time(e1) / steps
 
 
-def gather_ceiling(dev, sync):
-    """Useful read bandwidth of a gather-and-sum of random 64- and 128-byte rows
-    on this GPU (torch's embedding_bag over a 512 MiB table, bags of 256 rows):
-    the rate a CSR sketch can reach when every row it reads is one random
-    64-byte piece of the column array and one of the value array."""
-    import torch
-    import torch.nn.functional as F
-
-    out = {}
-    g = torch.Generator(device=dev)
-    g.manual_seed(0)
-    for row_bytes in (64, 128):
-        cols = row_bytes // 4
-        nrows = (1 << 29) // row_bytes
-        X = torch.ones(nrows, cols, device=dev)
-        idx = torch.randint(0, nrows, (nrows // 2,), device=dev, generator=g)
-        offs = torch.arange(0, idx.numel(), 256, device=dev)
-        for _ in range(2):
-            F.embedding_bag(idx, X, offs, mode="sum")
-        sync()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            F.embedding_bag(idx, X, offs, mode="sum")
-        e1.record()
-        sync()
-        ms = e0.elapsed_time(e1) / 5
-        out[f"rows_{row_bytes}B_GBps"] = idx.numel() * row_bytes / (ms * 1e-3) / 1e9
-        del X, idx, offs
-    torch.cuda.empty_cache()
-    return out
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -240,10 +206,6 @@ def main():
     }
     if plan_cnt:
         result["phases_ms"]["sketch_plan"] = plan_tot / plan_cnt
-
-    if not args.no_extras and args.only is None:
-        log("gather ceiling: random 64 B and 128 B rows, torch embedding_bag")
-        result["gather_ceiling"] = gather_ceiling(dev, sync)
 
     if not args.no_extras and want("general"):
         # generalized sparse embedding (Section 5) of the same input: q groups,
