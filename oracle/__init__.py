@@ -20,6 +20,8 @@ Time" (arXiv:1207.6365) it follows:
   sampling (Section 7, generalized-regression algorithm)
 * :mod:`.lowrank`  -- rank-k approximation ``L D W^T`` (Section 8 theorem in
   the simplified form of the Section 10 experiments)
+* :mod:`.lp`       -- l_p regression: block-diagonal generalized embedding,
+  conditioning, two-stage row sampling, exact weighted l_p fits (Section 9)
 * :mod:`.learned`  -- distortion loss and gradient of learned sketch values
   (an extension; closed-form expectation for the plain sketch)
 
@@ -32,6 +34,7 @@ from .hashing import bucket_and_sign, splitmix64  # noqa: F401
 from .learned import Adam, distortion_grad, distortion_loss, expected_plain_distortion  # noqa: F401
 from .leverage import leverage_approx, leverage_exact, sketch_r  # noqa: F401
 from .lowrank import best_rank_k_error, frobenius_error, low_rank  # noqa: F401
+from .lp import block_embedding, lp_exact, lp_objective, lp_regression  # noqa: F401
 from .multiresponse import multi_response_lstsq, residual_fro  # noqa: F401
 from .linalg import (  # noqa: F401
     RankDeficient,

@@ -1,0 +1,166 @@
+"""Pins of the l_p regression oracle (Section 9) against facts that do not
+depend on it: the written-out block-diagonal embedding, expectations of the
+embedding and of the sampling, brute force over the vertices of the l_1
+problem, least squares for p = 2, first-order optimality, the subspace
+embedding property, and the (1 + eps) guarantee on small problems."""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle.lp as LP
+import workloads as W
+from oracle.lowrank import SAMPLE_SALT
+from oracle.sketch import generalized_S
+
+
+def _small_csr(n=300, d=6, k=3, seed=4):
+    return W.csr_uniform_rows(seed, n, d, k, dtype=np.float64)
+
+
+def test_block_embedding_matches_written_out_F():
+    # F = blockdiag(S, ..., S) with the same S on every block; a short last
+    # block takes the first columns of S
+    A = _small_csr(n=250)
+    Ad = A.to_dense().astype(np.float64)
+    seed, q, v, a, w = 0xABC, 3, 4, 2, 100
+    S = generalized_S(seed, w, q, v, a)  # t x w
+    t = a * q * v
+    F = np.zeros((3 * t, 250))
+    F[:t, :100] = S
+    F[t:2 * t, 100:200] = S
+    F[2 * t:, 200:] = S[:, :50]
+    assert np.allclose(LP.block_embedding(A, seed, q, v, a, w), F @ Ad, rtol=1e-13, atol=1e-13)
+    # one block (w = 0 or w >= n) is the generalized embedding itself
+    S1 = generalized_S(seed, 250, q, v, a)
+    assert np.allclose(LP.block_embedding(Ad, seed, q, v, a, 0), S1 @ Ad, rtol=1e-13, atol=1e-13)
+    assert np.allclose(LP.block_embedding(Ad, seed, q, v, a, 400), S1 @ Ad, rtol=1e-13, atol=1e-13)
+
+
+def test_block_embedding_preserves_norms_in_expectation():
+    # E ||F A x||^2 = ||A x||^2 over the hash seed (every block of F is an
+    # embedding with E S^T S = I)
+    g = np.random.default_rng(1)
+    A = g.standard_normal((120, 4))
+    x = g.standard_normal(4)
+    ref = np.sum((A @ x) ** 2)
+    vals = [np.sum((LP.block_embedding(A, s, 4, 2, 1, 50) @ x) ** 2) for s in range(3000)]
+    se = np.std(vals) / np.sqrt(len(vals))
+    assert abs(np.mean(vals) - ref) < 4 * se
+
+
+def test_uniform_streams_are_uniform_and_distinct():
+    from scipy.stats import kstest
+
+    u = LP.stream_uniforms(7, SAMPLE_SALT, 20000)
+    u2 = LP.stream_uniforms(7, LP.STAGE2_SALT, 20000)
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert kstest(u, "uniform").pvalue > 1e-3 and kstest(u2, "uniform").pvalue > 1e-3
+    assert abs(np.corrcoef(u, u2)[0, 1]) < 0.05
+
+
+@pytest.mark.parametrize("p", [1.0, 1.5, 3.0])
+def test_sampling_is_unbiased_for_the_lp_norm(p):
+    # sum over kept rows of w_i^p |y_i|^p has expectation ||y||_p^p, and the
+    # expected number of kept rows is sum(prob)
+    g = np.random.default_rng(2)
+    y = g.standard_normal(400) * np.exp(g.standard_normal(400))
+    prob = np.minimum(1.0, 60 * np.abs(y) / np.sum(np.abs(y)))
+    ref = np.sum(np.abs(y) ** p)
+    est, cnt = [], []
+    for s in range(3000):
+        rows, wts = LP.bernoulli_sample(prob, p, LP.stream_uniforms(s, SAMPLE_SALT, y.size))
+        est.append(np.sum(wts ** p * np.abs(y[rows]) ** p))
+        cnt.append(rows.size)
+    assert abs(np.mean(est) - ref) < 4 * np.std(est) / np.sqrt(len(est))
+    assert abs(np.mean(cnt) - prob.sum()) < 4 * np.std(cnt) / np.sqrt(len(cnt)) + 1e-9
+    # rows with probability one are always kept, with weight one
+    sure = np.nonzero(prob == 1.0)[0]
+    rows, wts = LP.bernoulli_sample(prob, p, LP.stream_uniforms(0, SAMPLE_SALT, y.size))
+    assert np.all(np.isin(sure, rows)) and np.all(wts[np.isin(rows, sure)] == 1.0)
+
+
+def test_l1_solver_matches_vertex_brute_force():
+    # an l_1 fit has an optimal vertex: d residuals are zero, so the optimum
+    # is the best of the solutions of all nonsingular d x d row subsystems
+    g = np.random.default_rng(3)
+    for _ in range(5):
+        M = g.standard_normal((9, 2))
+        y = g.standard_normal(9) + 3 * (g.random(9) < 0.2)
+        best = np.inf
+        for idx in itertools.combinations(range(9), 2):
+            sub = M[list(idx)]
+            if abs(np.linalg.det(sub)) < 1e-12:
+                continue
+            best = min(best, np.sum(np.abs(M @ np.linalg.solve(sub, y[list(idx)]) - y)))
+        x = LP.solve_weighted(M, y, np.ones(9), 1.0)
+        assert LP.lp_objective(M, y, x, 1.0) == pytest.approx(best, rel=1e-9)
+
+
+def test_l2_solver_is_weighted_least_squares():
+    g = np.random.default_rng(4)
+    M, y, w = g.standard_normal((50, 5)), g.standard_normal(50), g.random(50) + 0.5
+    x = LP.solve_weighted(M, y, w, 2.0)
+    ref = np.linalg.lstsq(M * w[:, None], y * w, rcond=None)[0]
+    assert np.allclose(x, ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [1.25, 1.5, 3.0, 4.0])
+def test_general_p_solver_is_stationary_and_minimal(p):
+    g = np.random.default_rng(5)
+    M, y = g.standard_normal((200, 6)), g.standard_normal(200) + g.laplace(size=200)
+    w = np.exp(0.3 * g.standard_normal(200))
+    x = LP.solve_weighted(M, y, w, p)
+    r = w * (M @ x - y)
+    grad = (M * w[:, None]).T @ (np.sign(r) * np.abs(r) ** (p - 1))
+    scale = np.abs(M * w[:, None]).T @ np.abs(r) ** (p - 1)
+    assert np.max(np.abs(grad) / scale) < 1e-8
+    f = np.sum(np.abs(r) ** p)
+    for _ in range(20):
+        xp = x + 1e-3 * g.standard_normal(6)
+        assert np.sum(np.abs(w * (M @ xp - y)) ** p) >= f * (1 - 1e-13)
+
+
+def test_conditioned_basis_is_an_l2_embedding():
+    # U = R^{-1} from a subspace embedding F A makes A U nearly orthonormal
+    # (Section 5 theorem); a transposed R or a wrong block hash breaks this
+    A, _, _ = W.lp_dense(n=3000, d=8)
+    for w in (0, 1000):
+        R = LP.condition(A, 11, 64, 8, 2, w)
+        sv = np.linalg.svd(A @ np.linalg.inv(R), compute_uv=False)
+        assert 0.6 < sv.min() <= sv.max() < 1.4
+
+
+@pytest.mark.parametrize("p", [1.0, 1.5, 2.0, 3.0])
+def test_keeping_every_row_gives_the_exact_fit(p):
+    A, b, _ = W.lp_dense(n=600, d=5)
+    out = LP.lp_regression(A, b, p, 3, 16, 4, 1, s1=1e30, s2=1e30)
+    assert out["rows1"].size == 600 and out["rows2"].size == 600
+    assert np.all(out["w2"] == 1.0)
+    fx = LP.lp_objective(A, b, out["x"], p)
+    fe = LP.lp_objective(A, b, LP.lp_exact(A, b, p), p)
+    assert fx == pytest.approx(fe, rel=1e-9)
+    if p == 2.0:
+        assert np.allclose(out["x"], np.linalg.lstsq(A, b, rcond=None)[0], rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [1.0, 1.5, 3.0])
+def test_sampled_fit_is_within_one_plus_eps(p):
+    A, b, _ = W.lp_dense(n=20000, d=8)
+    out = LP.lp_regression(A, b, p, 0x5EED, 64, 8, 1, s1=800, s2=800)
+    assert 8 <= out["rows2"].size < 2000
+    ratio = LP.lp_objective(A, b, out["x"], p) / LP.lp_objective(A, b, LP.lp_exact(A, b, p), p)
+    assert 1 - 1e-12 <= ratio < 1.1 ** p
+    # the stage-2 probabilities dominate the stage-1 share of every row
+    share = out["pi"] / 800
+    assert np.all(out["q"] >= np.minimum(1.0, 800 * share) * (1 - 1e-12))
+
+
+def test_rank_deficient_input_is_rejected():
+    A, b, _ = W.lp_dense(n=500, d=4)
+    A[:, 2] = 0.0
+    with pytest.raises(ValueError):
+        LP.lp_regression(A, b, 1.0, 1, 16, 4, 1, s1=100, s2=100)
+    with pytest.raises(ValueError):
+        LP.lp_regression(A, b, 0.5, 1, 16, 4, 1, s1=100, s2=100)

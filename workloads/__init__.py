@@ -21,6 +21,8 @@ from .gen import (  # noqa: F401
     learned_family,
     learned_rhs,
     planted_lowrank_sparse,
+    lp_sparse,
+    lp_dense,
     SKETCH_SEED_BASE,
     data_seed,
     sketch_seed,

@@ -278,3 +278,33 @@ def planted_lowrank_sparse(trial: int = 0, n: int = 65536, rank: int = 32, densi
     M.sort_indices()
     val = M.data + noise * g.standard_normal(M.data.size)
     return CSR(n, n, M.indptr.astype(np.int64), M.indices.astype(np.int32), val.astype(dtype))
+
+
+def lp_sparse(trial: int = 0, n: int = 2**22, d: int = 256, k: int = 16, scale: float = 0.1,
+              outliers: float = 0.01):
+    """l_p regression workload: the CSR matrix of :func:`sketch_csr`'s shape
+    (``k`` float32 N(0,1) nonzeros per row at distinct uniform columns),
+    ``x0 ~ N(0, I)`` and ``b = A x0 + e`` in float64 with Laplace(``scale``)
+    noise plus, on a fraction ``outliers`` of the rows, a gross error of
+    100 ``scale`` times a standard Cauchy draw.  Returns ``(A, b, x0)``."""
+    seed = data_seed(6, trial)
+    A = csr_uniform_rows(seed, n, d, k, dtype=np.float32)
+    g = _rng(seed + 500)
+    x0 = g.standard_normal(d)
+    e = g.laplace(scale=scale, size=n)
+    bad = g.random(n) < outliers
+    e[bad] += 100.0 * scale * g.standard_cauchy(int(bad.sum()))
+    return A, A.matvec64(x0) + e, x0
+
+
+def lp_dense(trial: int = 0, n: int = 4096, d: int = 16, scale: float = 0.1, outliers: float = 0.01):
+    """Small dense l_p regression: float64 rows ``s_i g_i`` with ``g_i ~ N(0, I)``
+    and ``s_i = exp(N(0, 1))`` (uneven row norms), ``b`` as in
+    :func:`lp_sparse`.  Returns ``(A, b, x0)``."""
+    g = _rng(data_seed(6, trial) + 300)
+    A = g.standard_normal((n, d)) * np.exp(g.standard_normal((n, 1)))
+    x0 = g.standard_normal(d)
+    e = g.laplace(scale=scale, size=n)
+    bad = g.random(n) < outliers
+    e[bad] += 100.0 * scale * g.standard_cauchy(int(bad.sum()))
+    return A, A @ x0 + e, x0
