@@ -347,6 +347,87 @@ SKLS_API int32_t skls_multi_lstsq(const skls_matrix* A, const double* B, int64_t
                                   size_t ws_bytes, void* stream);
 
 /*
+ * l_p regression min_x ||A x - b||_p for 1 <= p < inf (Section 9: the
+ * conditioning step on generalized sparse embeddings, then two-stage row
+ * sampling as in the l_p coreset algorithm of Dasgupta, Drineas, Harb, Kumar
+ * and Mahoney that the section builds on):
+ *  1. F A for F block-diagonal: the rows of A in blocks of w, every block
+ *     embedded by the same generalized sparse embedding of skls_sketch_general
+ *     (q groups of v buckets, a copies, stream `seed`; rows hashed by their
+ *     index inside the block; t = a q v rows per block), float64;
+ *  2. R from the float64 Gram of F A (Cholesky); A R^{-1} is the conditioned
+ *     basis (the l_2 basis: the section leaves the general-p construction to
+ *     its reference, and an l_2 basis is well conditioned for every p up to
+ *     factors polynomial in the dimensions, which only the sample sizes feel);
+ *  3. lam_i = (squared row norm of A R^{-1} Pi2)^{p/2}, Pi2 the d x k_g sign
+ *     matrix / sqrt(k_g) of skls_low_rank (stream seed ^ 0x6C65766572616765):
+ *     the l_p row norms of the basis estimated through l_2 norms;
+ *  4. stage 1: row i kept iff u_i < pi_i = min(1, s1 lam_i / sum(lam)), u_i =
+ *     (z_i >> 11) 2^-53 for output i of the stream seed ^ 0x73616D706C696E67,
+ *     with weight pi_i^{-1/p}; x_c = the weighted l_p fit of the kept rows;
+ *  5. stage 2: rho = A x_c - b; row i kept iff u'_i < min(1, s2 max(lam_i /
+ *     sum(lam), |rho_i|^p / sum |rho|^p)) (u' from the stream
+ *     seed ^ 0x726573616D706C65; the residual share is left out when rho = 0),
+ *     with weight q_i^{-1/p}; x = the weighted l_p fit of those rows.
+ * The weighted fits (min sum_i w_i^p |A_i x - b_i|^p over the kept rows) run
+ * on the float64 coreset: p = 2 through the normal equations, p = 1 by a
+ * primal-dual interior-point method on the dual linear program (stops when
+ * the duality gap is at most tol * max(1, objective)), other p by iteratively
+ * reweighted least squares (Newton steps 1/(p-1) long with halving for p > 2;
+ * a floor on |r| that shrinks 4x per step to 1e-9 of the mean for p < 2; stops
+ * at the floor once the objective changes by at most tol relative).
+ * Synchronous.
+ */
+typedef struct {
+  double p;           /* 1 <= p < inf */
+  int64_t q, v;       /* embedding groups and buckets per group (0: v = 8, q = max(16, ceil(2 d^2 / v))) */
+  int32_t a;          /* copies of the embedding (0: 1; at most 256) */
+  int32_t k_g;        /* columns of Pi2 (0: 32; at most 64) */
+  int64_t w;          /* rows per block of F (0 or >= n: one block) */
+  double s1, s2;      /* expected sample sizes of the two stages (0: 32 d each) */
+  uint64_t seed;
+  int32_t max_iter;   /* iterations of each weighted fit (0: 100) */
+  int32_t reserved0;
+  double tol;         /* stopping tolerance of the weighted fits (0: 1e-12) */
+  int64_t reserved[4];
+} skls_lp_opts;
+
+typedef struct {
+  int64_t rows_stage1, rows_stage2;  /* rows kept by the two draws */
+  int32_t iters_stage1, iters_stage2;  /* weighted solves of each fit */
+  int32_t converged;     /* 1 if both fits met their stopping rule */
+  int32_t reserved0;
+  double obj_stage1;     /* ||A x_c - b||_p^p (float64 accumulation) */
+  double obj;            /* ||A x - b||_p^p */
+  double coreset_obj;    /* stage-2 weighted objective at x */
+  float ms_condition, ms_stage1, ms_stage2;
+  int32_t reserved1;
+  int64_t reserved[4];
+} skls_lp_info;
+
+SKLS_API int32_t skls_lp_regression_workspace(const skls_matrix* A, const skls_lp_opts* opts, size_t* bytes);
+/*
+ *  A:      dense (F64, F32, BF16) or CSR, n x d, d <= n < 2^31, d <= 4096
+ *          (the residual passes further limit dense d to 512, or to 1024 /
+ *          2048 / 4096 for F64 / F32 / BF16 rows whose length and start are
+ *          multiples of 16 bytes).
+ *  b:      device float64 [n].
+ *  x:      device float64 [d], the result.
+ *  x_c:    device float64 [d] or NULL: the stage-1 solution.
+ *  rows1, w1, rows2, w2: device int32 / float64 arrays of at least n entries,
+ *          or NULL: the kept rows of each stage in increasing order and their
+ *          weights (the first info->rows_stage1 / rows_stage2 entries).
+ * Errors: SKLS_ERR_ARG for p outside [1, inf); SKLS_ERR_RANK when F A is
+ * numerically rank deficient or a stage keeps fewer than d rows or a rank
+ * deficient set; SKLS_ERR_SHAPE when a stage keeps more rows than its
+ * capacity (s + 8 sqrt(s) + 64, with s = s1 and 2 s2; not reached in
+ * practice).
+ */
+SKLS_API int32_t skls_lp_regression(const skls_matrix* A, const double* b, const skls_lp_opts* opts, double* x,
+                                    double* x_c, int32_t* rows1, double* w1, int32_t* rows2, double* w2,
+                                    skls_lp_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Rank-k approximation A ~ L diag(D) W^T (Section 8, theorem on low-rank
  * approximation), in the simplified form of the Section 10 experiments:
  *  1. Y = A R^T for R^ a t_r x m sparse embedding of the columns of A (h and

@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     low_rank,
     lstsq,
     multi_lstsq,
+    lp_regression,
     qr_r,
     sketch,
     sketch_general,

@@ -125,6 +125,43 @@ class SklsMultiInfo(ctypes.Structure):
     ]
 
 
+class SklsLpOpts(ctypes.Structure):
+    _fields_ = [
+        ("p", c_double),
+        ("q", c_int64),
+        ("v", c_int64),
+        ("a", c_int32),
+        ("k_g", c_int32),
+        ("w", c_int64),
+        ("s1", c_double),
+        ("s2", c_double),
+        ("seed", c_uint64),
+        ("max_iter", c_int32),
+        ("reserved0", c_int32),
+        ("tol", c_double),
+        ("reserved", c_int64 * 4),
+    ]
+
+
+class SklsLpInfo(ctypes.Structure):
+    _fields_ = [
+        ("rows_stage1", c_int64),
+        ("rows_stage2", c_int64),
+        ("iters_stage1", c_int32),
+        ("iters_stage2", c_int32),
+        ("converged", c_int32),
+        ("reserved0", c_int32),
+        ("obj_stage1", c_double),
+        ("obj", c_double),
+        ("coreset_obj", c_double),
+        ("ms_condition", ctypes.c_float),
+        ("ms_stage1", ctypes.c_float),
+        ("ms_stage2", ctypes.c_float),
+        ("reserved1", c_int32),
+        ("reserved", c_int64 * 4),
+    ]
+
+
 # name -> (restype, argtypes); every symbol declared in include/skls.h
 SIGNATURES = {
     "skls_status_str": (c_char_p, [c_int32]),
@@ -158,6 +195,10 @@ SIGNATURES = {
     "skls_multi_lstsq_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, POINTER(SklsMultiOpts), POINTER(c_size_t)]),
     "skls_multi_lstsq": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int64, POINTER(SklsMultiOpts), c_void_p, c_void_p,
                                    c_void_p, POINTER(SklsMultiInfo), c_void_p, c_size_t, c_void_p]),
+    "skls_lp_regression_workspace": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLpOpts), POINTER(c_size_t)]),
+    "skls_lp_regression": (c_int32, [POINTER(SklsMatrix), c_void_p, POINTER(SklsLpOpts), c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, POINTER(SklsLpInfo), c_void_p,
+                                     c_size_t, c_void_p]),
     "skls_low_rank_workspace": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLowRankOpts), POINTER(c_size_t)]),
     "skls_low_rank": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLowRankOpts), c_void_p, c_void_p, c_void_p,
                                 POINTER(SklsLowRankInfo), c_void_p, c_size_t, c_void_p]),

@@ -219,6 +219,43 @@ def multi_lstsq(A, B: torch.Tensor, t: int, t_s: int, seed: int, k_g: int = 0, c
     return Y, out
 
 
+def lp_regression(A, b: torch.Tensor, p: float, seed: int, q: int = 0, v: int = 0, a: int = 0, w: int = 0,
+                  s1: float = 0.0, s2: float = 0.0, k_g: int = 0, max_iter: int = 0, tol: float = 0.0,
+                  samples: bool = False):
+    """``l_p`` regression ``min_x ||A x - b||_p`` (Section 9: conditioning by a
+    block-diagonal generalized sparse embedding, then two-stage row sampling
+    and weighted ``l_p`` fits of the samples).  Returns ``(x, info)``, plus a
+    dict with ``x_c`` and the rows and weights of both stages when
+    ``samples``."""
+    m, device = _matrix(A)
+    if b.dtype != torch.float64 or not b.is_contiguous() or b.dim() != 1 or b.shape[0] != m.n:
+        raise TypeError("b must be a contiguous float64 vector of length n")
+    o = L.SklsLpOpts()
+    o.p, o.q, o.v, o.a, o.k_g, o.w = float(p), q, v, a, k_g, w
+    o.s1, o.s2, o.seed, o.max_iter, o.tol = float(s1), float(s2), seed & 0xFFFFFFFFFFFFFFFF, max_iter, float(tol)
+    ws = _workspace(_size(lib().skls_lp_regression_workspace, ctypes.byref(m), ctypes.byref(o)), device)
+    x = torch.empty(m.d, dtype=torch.float64, device=device)
+    extra = None
+    if samples:
+        extra = {"x_c": torch.empty(m.d, dtype=torch.float64, device=device),
+                 "rows1": torch.empty(m.n, dtype=torch.int32, device=device),
+                 "w1": torch.empty(m.n, dtype=torch.float64, device=device),
+                 "rows2": torch.empty(m.n, dtype=torch.int32, device=device),
+                 "w2": torch.empty(m.n, dtype=torch.float64, device=device)}
+    g = (lambda k: _ptr(extra[k])) if samples else (lambda k: None)
+    info = L.SklsLpInfo()
+    L.check(lib().skls_lp_regression(ctypes.byref(m), _ptr(b), ctypes.byref(o), _ptr(x), g("x_c"), g("rows1"),
+                                     g("w1"), g("rows2"), g("w2"), ctypes.byref(info), _ptr(ws), ws.numel(),
+                                     _stream(device)))
+    out = {f: getattr(info, f) for f, _ in L.SklsLpInfo._fields_ if not f.startswith("reserved")}
+    if samples:
+        k1, k2 = out["rows_stage1"], out["rows_stage2"]
+        for key, k in (("rows1", k1), ("w1", k1), ("rows2", k2), ("w2", k2)):
+            extra[key] = extra[key][:k]
+        return x, out, extra
+    return x, out
+
+
 # ------------------------------------------------------------------ a5
 def leverage_scores(A, t: int, seed: int, Pi2: torch.Tensor):
     """Squared row norms of ``A R^{-1} Pi2`` (``Pi2``: ``d x k`` float64)."""

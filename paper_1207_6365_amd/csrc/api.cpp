@@ -778,6 +778,33 @@ int32_t skls_multi_lstsq(const skls_matrix* A, const double* B, int64_t dp, cons
   return run_multi_lstsq(*A, B, P, opts->seed, Y, rows, weights, info, ws, ws_bytes, as_stream(stream));
 }
 
+int32_t skls_lp_regression_workspace(const skls_matrix* A, const skls_lp_opts* opts, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (opts == nullptr || bytes == nullptr) {
+    set_error("opts and bytes must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  LpPlan P;
+  SKLS_TRY(lp_plan(*A, *opts, P));
+  *bytes = lp_ws_bytes(P);
+  return SKLS_OK;
+}
+
+int32_t skls_lp_regression(const skls_matrix* A, const double* b, const skls_lp_opts* opts, double* x, double* x_c,
+                           int32_t* rows1, double* w1, int32_t* rows2, double* w2, skls_lp_info* info, void* ws,
+                           size_t ws_bytes, void* stream) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (opts == nullptr || b == nullptr || x == nullptr) {
+    set_error("opts, b and x must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  LpPlan P;
+  SKLS_TRY(lp_plan(*A, *opts, P));
+  return run_lp(*A, b, P, x, x_c, rows1, w1, rows2, w2, info, ws, ws_bytes, as_stream(stream));
+}
+
 int32_t skls_low_rank_workspace(const skls_matrix* A, const skls_low_rank_opts* opts, size_t* bytes) {
   clear_error();
   SKLS_TRY(validate_matrix(A, true));

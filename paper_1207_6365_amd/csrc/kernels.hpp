@@ -127,4 +127,19 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
                         int32_t* rows_out, double* weights_out, skls_multi_info* info, void* ws, size_t ws_bytes,
                         hipStream_t s);
 
+// ---------------------------------------------------------------- lp.hip
+// Resolved sizes of an l_p regression (options checked and defaulted).
+struct LpPlan {
+  const skls_matrix* A;
+  int64_t n, d, q, v, w, nb, t, cap;
+  int32_t a, kg, max_iter;
+  double p, s1, s2, tol;
+  uint64_t seed;
+  size_t sk_bytes;
+};
+int32_t lp_plan(const skls_matrix& A, const skls_lp_opts& o, LpPlan& P);
+size_t lp_ws_bytes(const LpPlan& P);
+int32_t run_lp(const skls_matrix& A, const double* b, const LpPlan& P, double* x, double* x_c, int32_t* rows1,
+               double* w1, int32_t* rows2, double* w2, skls_lp_info* info, void* ws, size_t ws_bytes,
+               hipStream_t s);
 }  // namespace skls

@@ -289,6 +289,24 @@ __global__ __launch_bounds__(kT) void k_gather_rows(int64_t ns, int64_t cols, in
   }
 }
 
+// Sampled CSR rows written densely: out[r][:] = w[r] * A[list[r]][:] (out
+// zeroed first; repeated columns within a row are summed).
+template <typename TV, typename TR>
+__global__ __launch_bounds__(kT) void k_gather_csr_dense(int64_t ns, int64_t d, const TR* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col, const TV* __restrict__ val,
+                                                         const int32_t* __restrict__ list,
+                                                         const double* __restrict__ w, double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < ns; r += nw) {
+    const int32_t i = list[r];
+    const int64_t b = static_cast<int64_t>(row_ptr[i]), e = static_cast<int64_t>(row_ptr[i + 1]);
+    const double s = w[r];
+    for (int64_t k = b + lane; k < e; k += kWave)
+      unsafeAtomicAdd(out + static_cast<size_t>(r) * d + col[k], s * load_as<double>(val, static_cast<size_t>(k)));
+  }
+}
+
 // Sampled CSR rows: columns copied, values scaled by the row weight (float64).
 template <typename TV, typename TR>
 __global__ __launch_bounds__(kT) void k_gather_csr(int64_t ns, const TR* __restrict__ row_ptr,

@@ -26,7 +26,8 @@ def lib():
 def test_header_declares_the_entry_points():
     names = _declared()
     for must in ("skls_hash", "skls_sketch", "skls_lstsq", "skls_leverage_scores", "skls_low_rank",
-                 "skls_learned_grad", "skls_qr_r", "skls_sketch_general", "skls_multi_lstsq"):
+                 "skls_learned_grad", "skls_qr_r", "skls_sketch_general", "skls_multi_lstsq",
+                 "skls_lp_regression"):
         assert must in names
 
 
@@ -106,6 +107,29 @@ def test_low_rank_workspace_checks_options(lib):
     assert lib.skls_low_rank_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 1
     o.t_s, o.k = 0, 60
     assert lib.skls_low_rank_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 1
+
+
+def test_lp_workspace_checks_options(lib):
+    from paper_1207_6365_amd import _lib as L
+
+    sz = ctypes.c_size_t(0)
+    A = _mat(n=5000, d=16, ld=16)
+    o = L.SklsLpOpts()
+    o.p, o.seed = 1.0, 3
+    assert lib.skls_lp_regression_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 0
+    # F A (2 d^2 rows by default) and the coreset of capacity 2 s2 + 8 sqrt(2 s2) + 64
+    assert sz.value > 512 * 16 * 8 + 1024 * 16 * 8 * 2
+    for bad_p in (0.5, float("inf"), float("nan")):
+        o.p = bad_p
+        assert lib.skls_lp_regression_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 1
+    o.p, o.k_g = 1.5, 65
+    assert lib.skls_lp_regression_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 1
+    o.k_g, o.w, o.q, o.v = 0, 100, 2, 4  # 50 blocks of 8 rows
+    assert lib.skls_lp_regression_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 0
+    o.w = 5000  # one block of 8 rows cannot hold d = 16
+    assert lib.skls_lp_regression_workspace(ctypes.byref(A), ctypes.byref(o), ctypes.byref(sz)) == 2
+    assert lib.skls_lp_regression_workspace(ctypes.byref(_mat(n=10, d=16, ld=16)), ctypes.byref(o),
+                                            ctypes.byref(sz)) == 2
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
