@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--lstsq-steps", type=int, default=3)
     p.add_argument("--only", default=None,
-                   choices=["general", "dense", "small", "lstsq", "multi", "leverage", "low_rank", "learned"],
+                   choices=["general", "dense", "small", "lstsq", "multi", "leverage", "low_rank", "lp", "learned"],
                    help="run only this extra workload after the headline")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run a plain device copy of this many MiB first (scale for HBM byte counters)")
@@ -409,6 +409,47 @@ def main():
                 "kernel_phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
             }
             del A4, A4g
+            torch.cuda.empty_cache()
+
+        if want("lp"):
+            # l_p regression (Section 9) on the CSR workload of the headline
+            # sketch (n=2^22, d=256, 16 nnz/row) with b = A x0 + Laplace noise
+            # and 1% gross outliers; default sizes (F with 2 d^2 rows, s1 = s2
+            # = 32 d); the fit is reported against the planted x0
+            log("l_p regression: CSR n=2^22 d=256 16 nnz/row, p = 1 and 1.5")
+            A6, b6, x6 = W.lp_sparse()
+            A6g = sk.Csr(A6.n, A6.d, torch.from_numpy(A6.row_ptr32()).to(dev), torch.from_numpy(A6.col_idx).to(dev),
+                         torch.from_numpy(A6.val).to(dev))
+            b6g = torch.from_numpy(b6).to(dev)
+            res = {}
+            for pp in (1.0, 1.5):
+                planted = float(np.sum(np.abs(A6.matvec64(x6) - b6) ** pp))
+                lp_seed = W.sketch_seed(6)
+                sk.lp_regression(A6g, b6g, pp, lp_seed)  # warm-up
+                sync()
+                lib.skls_profile_enable(1)
+                reps = 3
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    _, pinfo = sk.lp_regression(A6g, b6g, pp, lp_seed)
+                sync()
+                el = (time.perf_counter() - t0) / reps
+                ph = profile_phases(sk)
+                lib.skls_profile_enable(0)
+                res[f"p{pp:g}"] = {
+                    "ms_per_call": el * 1e3, "calls_per_s": 1.0 / el,
+                    "objective_vs_planted": pinfo["obj"] / planted,
+                    "stage1_objective_vs_planted": pinfo["obj_stage1"] / planted,
+                    "rows": [pinfo["rows_stage1"], pinfo["rows_stage2"]],
+                    "fit_iterations": [pinfo["iters_stage1"], pinfo["iters_stage2"]],
+                    "converged": pinfo["converged"],
+                    "ms_phases": {"condition": pinfo["ms_condition"], "stage1": pinfo["ms_stage1"],
+                                  "stage2": pinfo["ms_stage2"]},
+                    "phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
+                }
+            result["lp_regression"] = {"workload": "CSR n=2^22 d=256 16 nnz/row float32, Laplace(0.1) noise, "
+                                                   "1% outliers", "nnz": int(A6.nnz), **res}
+            del A6g, b6g
             torch.cuda.empty_cache()
 
         if want("learned"):

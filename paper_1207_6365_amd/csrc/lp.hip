@@ -30,7 +30,8 @@ namespace skls {
 namespace {
 
 constexpr uint64_t kStage2Salt = 0x726573616D706C65ull;  // "resample"
-constexpr int kRed = 256;                                 // blocks of every reduction
+constexpr int kRed = 256;                                 // blocks of the reductions over rows
+constexpr int kResBlocks = 1024;                          // blocks of the coreset residual
 
 __device__ __forceinline__ double uniform_at(uint64_t seed, uint64_t salt, int64_t i) {
   return static_cast<double>(splitmix64(seed ^ salt, static_cast<uint64_t>(i)) >> 11) * 0x1.0p-53;
@@ -70,13 +71,29 @@ __global__ __launch_bounds__(kT) void k_abs_pow_rows(int64_t n, const double* __
   block_partial(s, sh, partial + blockIdx.x);
 }
 
-// out[j] = sum_b partial[j * nb + b], j < m, in block order.
-__global__ void k_sum_partials(const double* __restrict__ partial, int nb, int m, double* __restrict__ out) {
-  const int j = threadIdx.x;
-  if (j >= m) return;
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[j * nb + b];
-  out[j] = s;
+// out[j] = sum_b partial[j * nb + b], j < m: one block of kT threads, thread
+// t summing b = t, t + kT, ... before the block sum (fixed order).
+__global__ __launch_bounds__(kT) void k_sum_partials(const double* __restrict__ partial, int nb, int m,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[kT / kWave];
+  for (int j = 0; j < m; ++j) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kT) s += partial[j * nb + b];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[j] = s;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double block_min(double v, double* sh) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double m = sh[0];
+  for (int k = 1; k < kT / kWave; ++k) m = fmin(m, sh[k]);
+  return m;
 }
 
 // Bernoulli draws: prob_i = min(1, s * share_i), share_i = lam_i / L, or
@@ -106,8 +123,9 @@ __global__ __launch_bounds__(kT) void k_take(int64_t n, const int32_t* __restric
   wts[pos[i]] = pow(prob[i], -1.0 / p);
 }
 
-// out_i = M_i x - y_i (y may be NULL), one wavefront per row; with partial:
-// partial[b] = block sum of |out_i|^p, partial[kRed + b] = of |out_i|.
+// out_i = M_i x - y_i (y may be NULL), one wavefront per row; with partial
+// (grid of kResBlocks): partial[b] = block sum of |out_i|^p,
+// partial[kResBlocks + b] = of |out_i|.
 __global__ __launch_bounds__(kT) void k_resid_rows(int64_t ns, int64_t d, const double* __restrict__ M,
                                                    const double* __restrict__ x, const double* __restrict__ y,
                                                    double* __restrict__ out, double p,
@@ -131,7 +149,7 @@ __global__ __launch_bounds__(kT) void k_resid_rows(int64_t ns, int64_t d, const 
   if (partial == nullptr) return;
   block_partial(sp, sh, partial + blockIdx.x);
   __syncthreads();
-  block_partial(s1, sh, partial + kRed + blockIdx.x);
+  block_partial(s1, sh, partial + kResBlocks + blockIdx.x);
 }
 
 // out[i][:] = c_i M[i][:] (c_i = sqrt(cw_i) when SQ), vout_i = c_i y_i.
@@ -279,12 +297,16 @@ __global__ __launch_bounds__(kT) void k_ipm_dirs(int64_t ns, const double* __res
 }
 
 // steps = {factor * min(1, primal ratio), factor * min(1, dual ratio)}.
-__global__ void k_ipm_steps(const double* __restrict__ partial, int nb, double factor, double* __restrict__ steps) {
-  const int j = threadIdx.x;
-  if (j >= 2) return;
-  double m = 1.0;
-  for (int b = 0; b < nb; ++b) m = fmin(m, partial[j * nb + b]);
-  steps[j] = factor * m;
+__global__ __launch_bounds__(kT) void k_ipm_steps(const double* __restrict__ partial, int nb, double factor,
+                                                  double* __restrict__ steps) {
+  __shared__ double sh[kT / kWave];
+  for (int j = 0; j < 2; ++j) {
+    double m = 1.0;
+    for (int b = threadIdx.x; b < nb; b += kT) m = fmin(m, partial[j * nb + b]);
+    m = block_min(m, sh);
+    if (threadIdx.x == 0) steps[j] = factor * m;
+    __syncthreads();
+  }
 }
 
 // Gap after the predictor step -> partial[b].
@@ -305,13 +327,38 @@ __global__ __launch_bounds__(kT) void k_ipm_gaff(int64_t ns, const double* __res
 }
 
 // smu = (gap_aff / gap)^3 * gap / (2 ns).
-__global__ void k_ipm_sigma(const double* __restrict__ partial, int nb, const double* __restrict__ gap, int64_t ns,
-                            double* __restrict__ smu) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kT) void k_ipm_sigma(const double* __restrict__ partial, int nb,
+                                                  const double* __restrict__ gap, int64_t ns,
+                                                  double* __restrict__ smu) {
+  __shared__ double sh[kT / kWave];
   double g = 0.0;
-  for (int b = 0; b < nb; ++b) g += partial[b];
+  for (int b = threadIdx.x; b < nb; b += kT) g += partial[b];
+  g = block_sum(g, sh);
+  if (threadIdx.x != 0) return;
   const double ratio = g / gap[0];
   smu[0] = ratio * ratio * ratio * (gap[0] / (2.0 * static_cast<double>(ns)));
+}
+
+// M^T v for the ns x d coreset: block b sums its slice of rows into
+// part[b][:] (threads over columns), then k_col_sum adds the slices in
+// block order.
+constexpr int kRmvBlocks = 256;
+__global__ __launch_bounds__(kT) void k_rmatvec_part(int64_t ns, int64_t d, const double* __restrict__ M,
+                                                     const double* __restrict__ v, double* __restrict__ part) {
+  const int64_t r0 = blockIdx.x * ns / gridDim.x, r1 = (blockIdx.x + 1) * ns / gridDim.x;
+  for (int64_t c = threadIdx.x; c < d; c += kT) {
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) s += M[static_cast<size_t>(r) * d + c] * v[r];
+    part[static_cast<size_t>(blockIdx.x) * d + c] = s;
+  }
+}
+__global__ __launch_bounds__(kT) void k_col_sum(int nb, int64_t d, const double* __restrict__ part,
+                                                double* __restrict__ out) {
+  const int64_t c = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x;
+  if (c >= d) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[static_cast<size_t>(b) * d + c];
+  out[c] = s;
 }
 
 __global__ __launch_bounds__(kT) void k_ipm_update(int64_t ns, const double* __restrict__ steps,
@@ -337,7 +384,7 @@ struct LpWs {
   size_t gram_bytes;
   double *G, *cholw, *R, *Rinv, *RinvT;
   int32_t* status;
-  double *Pi2, *T, *Z, *score, *lam, *rp, *prob, *part, *sums, *resid, *negx, *one, *ppart, *pred;
+  double *Pi2, *T, *Z, *score, *lam, *rp, *prob, *part, *rmv, *sums, *resid, *negx, *one, *ppart, *pred;
   int32_t *flag, *pos, *itiles, *last, *list;
   double* wts;
   // coreset
@@ -371,7 +418,8 @@ LpWs carve_lp(Arena& ar, const LpPlan& P) {
   w.rp = ar.take<double>(n);
   w.prob = ar.take<double>(n);
   w.resid = ar.take<double>(n);
-  w.part = ar.take<double>(4 * kRed);
+  w.part = ar.take<double>(2 * kResBlocks + 2 * kRed);
+  w.rmv = ar.take<double>(static_cast<size_t>(kRmvBlocks) * d);
   w.sums = ar.take<double>(8);
   w.negx = ar.take<double>(d);
   w.one = ar.take<double>(2);
@@ -399,6 +447,16 @@ LpWs carve_lp(Arena& ar, const LpPlan& P) {
 }
 
 unsigned g_rows(int64_t n) { return grid_for(n, kT, 1u << 24); }
+
+// out = M^T v for the coreset rows (ns x d, row-major).
+int32_t rmatvec(const LpWs& w, int64_t ns, int64_t d, const double* v, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rmatvec_part, dim3(kRmvBlocks), dim3(kT), 0, s, ns, d, w.Ms, v, w.rmv);
+  SKLS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_col_sum, dim3(static_cast<unsigned>(div_up(d, kT))), dim3(kT), 0, s, kRmvBlocks, d, w.rmv,
+                     out);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
 
 // ---------------------------------------------------------------- fits
 struct Fit {
@@ -428,10 +486,10 @@ int32_t factor_weighted(const LpWs& w, int64_t ns, int64_t d, const double* cw, 
 
 int32_t resid(const LpWs& w, int64_t ns, int64_t d, const double* x, double* r, double p, double* f, double* f1,
               hipStream_t s) {
-  hipLaunchKernelGGL(k_resid_rows, dim3(kRed), dim3(kT), 0, s, ns, d, w.Ms, x, w.ys, r, p, w.part);
+  hipLaunchKernelGGL(k_resid_rows, dim3(kResBlocks), dim3(kT), 0, s, ns, d, w.Ms, x, w.ys, r, p, w.part);
   SKLS_CHECK_LAUNCH();
   // dev[6..7]: sums[0..1] hold the sampling totals for the whole call
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, w.part, kRed, 2, w.dev + 6);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kResBlocks, 2, w.dev + 6);
   SKLS_CHECK_LAUNCH();
   double h[2];
   SKLS_TRY(to_host(h, w.dev + 6, sizeof h, s));
@@ -504,16 +562,17 @@ int32_t fit_irls(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, d
 // One reduced Newton solve: rhs = M^T qrho - r1, dx = (M^T Q M)^{-1} rhs,
 // Mdx = M dx, then the directions and step bounds.
 int32_t ipm_direction(const LpWs& w, int64_t ns, int64_t d, double factor, hipStream_t s) {
-  SKLS_TRY(gemm(true, d, 1, ns, 1.0, w.Ms, d, w.qrho, 1, w.rhs, 1, w.gs, s));
+  SKLS_TRY(rmatvec(w, ns, d, w.qrho, w.rhs, s));
   hipLaunchKernelGGL(k_vsub, dim3(g_rows(d)), dim3(kT), 0, s, d, w.rhs, w.r1, w.rhs);
   SKLS_CHECK_LAUNCH();
   SKLS_TRY(run_solve_from_gram(w.Rinv, w.RinvT, w.rhs, d, w.dx, w.tmpd, s));
-  hipLaunchKernelGGL(k_resid_rows, dim3(kRed), dim3(kT), 0, s, ns, d, w.Ms, w.dx, nullptr, w.Mdx, 1.0, nullptr);
+  hipLaunchKernelGGL(k_resid_rows, dim3(kResBlocks), dim3(kT), 0, s, ns, d, w.Ms, w.dx, nullptr, w.Mdx, 1.0,
+                     nullptr);
   SKLS_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_ipm_dirs, dim3(kRed), dim3(kT), 0, s, ns, w.qi, w.rho, w.Mdx, w.a, w.sl, w.z, w.w, w.r4,
                      w.r5, w.da, w.dz, w.dw, w.part);
   SKLS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_ipm_steps, dim3(1), dim3(64), 0, s, w.part, kRed, factor, w.dev + 2);
+  hipLaunchKernelGGL(k_ipm_steps, dim3(1), dim3(kT), 0, s, w.part, kRed, factor, w.dev + 2);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }
@@ -533,14 +592,14 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
                      w.w);
   SKLS_CHECK_LAUNCH();
   // c = M^T a at the start (a = 1/2): the dual equality M^T a = c holds there
-  SKLS_TRY(gemm(true, d, 1, ns, 1.0, w.Ms, d, w.a, 1, w.c, 1, w.gs, s));
+  SKLS_TRY(rmatvec(w, ns, d, w.a, w.c, s));
   out.iters = 0;
   for (int it = 0; it <= max_iter; ++it) {
-    hipLaunchKernelGGL(k_resid_rows, dim3(kRed), dim3(kT), 0, s, ns, d, w.Ms, w.x, w.ys, w.r, 1.0, nullptr);
+    hipLaunchKernelGGL(k_resid_rows, dim3(kResBlocks), dim3(kT), 0, s, ns, d, w.Ms, w.x, w.ys, w.r, 1.0, nullptr);
     SKLS_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_ipm_gap, dim3(kRed), dim3(kT), 0, s, ns, w.a, w.sl, w.z, w.w, w.r, w.part);
     SKLS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, w.part, kRed, 2, w.dev);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kRed, 2, w.dev);
     SKLS_CHECK_LAUNCH();
     double h[2];
     SKLS_TRY(to_host(h, w.dev, sizeof h, s));
@@ -551,7 +610,7 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     }
     if (it == max_iter) break;
     // r1 = c - M^T a
-    SKLS_TRY(gemm(true, d, 1, ns, 1.0, w.Ms, d, w.a, 1, w.tmpd, 1, w.gs, s));
+    SKLS_TRY(rmatvec(w, ns, d, w.a, w.tmpd, s));
     hipLaunchKernelGGL(k_vsub, dim3(g_rows(d)), dim3(kT), 0, s, d, w.c, w.tmpd, w.r1);
     SKLS_CHECK_LAUNCH();
     // predictor
@@ -564,7 +623,7 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     hipLaunchKernelGGL(k_ipm_gaff, dim3(kRed), dim3(kT), 0, s, ns, w.a, w.sl, w.z, w.w, w.da, w.dz, w.dw,
                        w.dev + 2, w.part);
     SKLS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_ipm_sigma, dim3(1), dim3(64), 0, s, w.part, kRed, w.dev, ns, w.dev + 4);
+    hipLaunchKernelGGL(k_ipm_sigma, dim3(1), dim3(kT), 0, s, w.part, kRed, w.dev, ns, w.dev + 4);
     SKLS_CHECK_LAUNCH();
     // corrector
     hipLaunchKernelGGL(k_ipm_rhs<true>, dim3(g), dim3(kT), 0, s, ns, w.r, w.a, w.sl, w.z, w.w, w.da, w.dz, w.dw,
@@ -634,7 +693,7 @@ int32_t full_objective(const skls_matrix& A, const double* b, const LpWs& w, con
   SKLS_TRY(run_pass(pa, s));
   hipLaunchKernelGGL(k_abs_pow_rows, dim3(kRed), dim3(kT), 0, s, n, w.resid, p, rp, w.part);
   SKLS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, w.part, kRed, 1, w.sums + 1);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kRed, 1, w.sums + 1);
   SKLS_CHECK_LAUNCH();
   return to_host(obj, w.sums + 1, sizeof(double), s);
 }
@@ -826,7 +885,7 @@ int32_t run_lp(const skls_matrix& A, const double* b, const LpPlan& P, double* x
     SKLS_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_pow_rows, dim3(kRed), dim3(kT), 0, s, n, w.score, P.p / 2.0, w.lam, w.part);
     SKLS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, w.part, kRed, 1, w.sums);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kRed, 1, w.sums);
     SKLS_CHECK_LAUNCH();
     double L = 0.0;
     SKLS_TRY(to_host(&L, w.sums, sizeof L, s));
