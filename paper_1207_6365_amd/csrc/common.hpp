@@ -54,6 +54,18 @@ struct Arena {
 // ------------------------------------------------------------------ hashing
 // SplitMix64 output `i` of the stream with state `seed` (Steele, Lea & Flood,
 // OOPSLA 2014): finaliser applied to seed + (i + 1) * golden gamma.
+// 16- and 8-byte loads of data that is read once (a stream over A): the
+// non-temporal hint keeps it from displacing reusable lines in the caches.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef unsigned nt_u4 __attribute__((ext_vector_type(4)));
+typedef unsigned nt_u2 __attribute__((ext_vector_type(2)));
+typedef int nt_i4 __attribute__((ext_vector_type(4)));
+template <typename V>
+__device__ __forceinline__ V stream_load(const void* p) {
+  return __builtin_nontemporal_load(static_cast<const V*>(p));
+}
+
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i) {
   uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

@@ -89,14 +89,15 @@ constexpr int kWidePitch = kWideCols + 4;  // floats; rows stay 16-byte aligned
 template <typename TV>
 __device__ __forceinline__ f4_t load4f(const TV* p) {
   if constexpr (std::is_same<TV, float>::value) {
-    return *reinterpret_cast<const f4_t*>(p);
+    const nt_f4 x = stream_load<nt_f4>(p);
+    return f4_t{x[0], x[1], x[2], x[3]};
   } else if constexpr (std::is_same<TV, double>::value) {
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    const double2 b = *reinterpret_cast<const double2*>(p + 2);
-    return f4_t{static_cast<float>(a.x), static_cast<float>(a.y), static_cast<float>(b.x), static_cast<float>(b.y)};
+    const nt_d2 a = stream_load<nt_d2>(p);
+    const nt_d2 b = stream_load<nt_d2>(p + 2);
+    return f4_t{static_cast<float>(a[0]), static_cast<float>(a[1]), static_cast<float>(b[0]), static_cast<float>(b[1])};
   } else {
-    const uint2 u = *reinterpret_cast<const uint2*>(p);
-    return f4_t{bf16_lo(u.x), bf16_hi(u.x), bf16_lo(u.y), bf16_hi(u.y)};
+    const nt_u2 u = stream_load<nt_u2>(p);
+    return f4_t{bf16_lo(u[0]), bf16_hi(u[0]), bf16_lo(u[1]), bf16_hi(u[1])};
   }
 }
 

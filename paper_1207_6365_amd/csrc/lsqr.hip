@@ -31,33 +31,33 @@ struct Ld {
 template <typename TA>
 struct Ld<float, TA, 4> {
   __device__ __forceinline__ static void get(const float* __restrict__ p, TA (&o)[4]) {
-    const float4 x = *reinterpret_cast<const float4*>(p);
-    o[0] = x.x;
-    o[1] = x.y;
-    o[2] = x.z;
-    o[3] = x.w;
+    const nt_f4 x = stream_load<nt_f4>(p);
+    o[0] = x[0];
+    o[1] = x[1];
+    o[2] = x[2];
+    o[3] = x[3];
   }
 };
 template <typename TA>
 struct Ld<double, TA, 2> {
   __device__ __forceinline__ static void get(const double* __restrict__ p, TA (&o)[2]) {
-    const double2 x = *reinterpret_cast<const double2*>(p);
-    o[0] = static_cast<TA>(x.x);
-    o[1] = static_cast<TA>(x.y);
+    const nt_d2 x = stream_load<nt_d2>(p);
+    o[0] = static_cast<TA>(x[0]);
+    o[1] = static_cast<TA>(x[1]);
   }
 };
 template <typename TA>
 struct Ld<bf16_t, TA, 8> {
   __device__ __forceinline__ static void get(const bf16_t* __restrict__ p, TA (&o)[8]) {
-    const uint4 x = *reinterpret_cast<const uint4*>(p);
-    o[0] = bf16_lo(x.x);
-    o[1] = bf16_hi(x.x);
-    o[2] = bf16_lo(x.y);
-    o[3] = bf16_hi(x.y);
-    o[4] = bf16_lo(x.z);
-    o[5] = bf16_hi(x.z);
-    o[6] = bf16_lo(x.w);
-    o[7] = bf16_hi(x.w);
+    const nt_u4 x = stream_load<nt_u4>(p);
+    o[0] = bf16_lo(x[0]);
+    o[1] = bf16_hi(x[0]);
+    o[2] = bf16_lo(x[1]);
+    o[3] = bf16_hi(x[1]);
+    o[4] = bf16_lo(x[2]);
+    o[5] = bf16_hi(x[2]);
+    o[6] = bf16_lo(x[3]);
+    o[7] = bf16_hi(x[3]);
   }
 };
 

@@ -983,33 +983,33 @@ struct RowLoad {
 template <typename TO>
 struct RowLoad<float, TO, 4> {
   __device__ __forceinline__ static void load(const float* __restrict__ p, TO (&out)[4]) {
-    const float4 x = *reinterpret_cast<const float4*>(p);
-    out[0] = x.x;
-    out[1] = x.y;
-    out[2] = x.z;
-    out[3] = x.w;
+    const nt_f4 x = stream_load<nt_f4>(p);
+    out[0] = x[0];
+    out[1] = x[1];
+    out[2] = x[2];
+    out[3] = x[3];
   }
 };
 template <typename TO>
 struct RowLoad<double, TO, 2> {
   __device__ __forceinline__ static void load(const double* __restrict__ p, TO (&out)[2]) {
-    const double2 x = *reinterpret_cast<const double2*>(p);
-    out[0] = static_cast<TO>(x.x);
-    out[1] = static_cast<TO>(x.y);
+    const nt_d2 x = stream_load<nt_d2>(p);
+    out[0] = static_cast<TO>(x[0]);
+    out[1] = static_cast<TO>(x[1]);
   }
 };
 template <typename TO>
 struct RowLoad<bf16_t, TO, 8> {
   __device__ __forceinline__ static void load(const bf16_t* __restrict__ p, TO (&out)[8]) {
-    const uint4 x = *reinterpret_cast<const uint4*>(p);
-    out[0] = bf16_lo(x.x);
-    out[1] = bf16_hi(x.x);
-    out[2] = bf16_lo(x.y);
-    out[3] = bf16_hi(x.y);
-    out[4] = bf16_lo(x.z);
-    out[5] = bf16_hi(x.z);
-    out[6] = bf16_lo(x.w);
-    out[7] = bf16_hi(x.w);
+    const nt_u4 x = stream_load<nt_u4>(p);
+    out[0] = bf16_lo(x[0]);
+    out[1] = bf16_hi(x[0]);
+    out[2] = bf16_lo(x[1]);
+    out[3] = bf16_hi(x[1]);
+    out[4] = bf16_lo(x[2]);
+    out[5] = bf16_hi(x[2]);
+    out[6] = bf16_lo(x[3]);
+    out[7] = bf16_hi(x[3]);
   }
 };
 
