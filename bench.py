@@ -91,6 +91,49 @@ def stored_traffic(kernel: str, source: str):
     return float(fields["traffic_bytes"])
 
 
+def segment_ceiling(dev, sync, n_rows: int):
+    """Rate of random 64- and 128-byte segment reads over a 2 GiB buffer
+    (the probe kernel of paper_1207_6365_amd/probe), and the floor it puts
+    under a CSR sketch that reads one 64-byte segment of columns and one of
+    values per row (16 nonzeros of 4 bytes)."""
+    import torch
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1207_6365_amd", "probe", "libskls_probe.so"))
+    lib.skls_probe_segments.restype = ctypes.c_int
+    lib.skls_probe_segments.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+    foot = 1 << 31
+    data = torch.zeros(foot, dtype=torch.uint8, device=dev)
+    sink = torch.zeros(1, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    out = {}
+    for seg in (64, 128):
+        nseg = (256 << 20) // seg  # 256 MiB of segments per launch
+        idx = torch.randint(0, foot // seg, (nseg,), dtype=torch.int32, device=dev, generator=g)
+        run = lambda: lib.skls_probe_segments(data.data_ptr(), idx.data_ptr(), nseg, seg, sink.data_ptr(),  # noqa: E731
+                                              ctypes.c_void_p(stream.cuda_stream))
+        if run() != 0:
+            raise RuntimeError("segment probe launch failed")
+        sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            run()
+        e1.record(stream)
+        sync()
+        sec = e0.elapsed_time(e1) * 1e-3 / 5
+        out[f"gseg_per_s_{seg}B"] = nseg / sec / 1e9
+        out[f"useful_GBps_{seg}B"] = nseg * seg / sec / 1e9
+        del idx
+    out["csr_sketch_floor_ms"] = 2 * n_rows / (out["gseg_per_s_64B"] * 1e9) * 1e3
+    del data
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_steps(fn, steps, warmup, sync):
     import torch
 
@@ -206,6 +249,13 @@ def main():
     }
     if plan_cnt:
         result["phases_ms"]["sketch_plan"] = plan_tot / plan_cnt
+    if args.only is None:
+        # the rate of random 64-byte segment reads bounds the CSR sketch: each
+        # row's columns and values are two such segments at unrelated addresses
+        log("random-segment read rate (probe kernel, 2 GiB buffer)")
+        ceil = segment_ceiling(dev, sync, A.n)
+        ceil["sketch_frac_of_floor"] = ceil["csr_sketch_floor_ms"] / k_ms
+        result["segment_ceiling"] = ceil
 
     if not args.no_extras and want("general"):
         # generalized sparse embedding (Section 5) of the same input: q groups,
