@@ -898,7 +898,7 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
       using TV = decltype(tv);
       const unsigned g = grid_for(n, kT / kWave, 8192);
       if (!P.csr) {
-        SKLS_TRY(gemm<TV>(false, n, k, m, 1.0, static_cast<const TV*>(A.val), A.ld, Wout, k, w.AW, k, w.part, s));
+        SKLS_TRY(dense_times<TV>(n, m, static_cast<const TV*>(A.val), A.ld, Wout, k, w.AW, w.part, s));
         hipLaunchKernelGGL(k_sumsq<TV>, dim3(w.nblk), dim3(kT), 0, s, int64_t(0), static_cast<const TV*>(A.val), n,
                            m, A.ld, ki, w.dots);
         SKLS_CHECK_LAUNCH();

@@ -866,7 +866,7 @@ int32_t run_lp(const skls_matrix& A, const double* b, const LpPlan& P, double* x
     int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
       using TV = decltype(tv);
       if (A.layout != SKLS_CSR)
-        return gemm<TV>(false, n, kg, d, 1.0, static_cast<const TV*>(A.val), A.ld, w.T, kg, w.Z, kg, w.gs, s);
+        return dense_times<TV>(n, d, static_cast<const TV*>(A.val), A.ld, w.T, kg, w.Z, w.gs, s);
       return with_rowptr(A, [&](auto trt) -> int32_t {
         using TR = decltype(trt);
         if (kg <= 32)

@@ -177,7 +177,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
     int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
       using TV = decltype(tv);
       if (A.layout != SKLS_CSR) {
-        return gemm<TV>(false, n, kg, d, 1.0, static_cast<const TV*>(A.val), A.ld, w.T, kg, w.Z, kg, w.gs, s);
+        return dense_times<TV>(n, d, static_cast<const TV*>(A.val), A.ld, w.T, kg, w.Z, w.gs, s);
       }
       return with_rowptr(A, [&](auto trt) -> int32_t {
         using TR = decltype(trt);
@@ -272,7 +272,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
     st = with_value(A.dtype, [&](auto tv) -> int32_t {
       using TV = decltype(tv);
       if (A.layout != SKLS_CSR) {
-        return gemm<TV>(false, n, dp, d, 1.0, static_cast<const TV*>(A.val), A.ld, Y, dp, w.AY, dp, w.gs, s);
+        return dense_times<TV>(n, d, static_cast<const TV*>(A.val), A.ld, Y, dp, w.AY, w.gs, s);
       }
       return with_rowptr(A, [&](auto trt) -> int32_t {
         using TR = decltype(trt);

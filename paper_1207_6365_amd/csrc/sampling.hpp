@@ -480,6 +480,139 @@ int32_t gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const TAV* 
   return SKLS_OK;
 }
 
+// out (n x k, float64) = A (n x d, float32 or bfloat16 rows) X (d x k,
+// float64), k <= 16 NB, on float64 MFMA (v_mfma_f64_16x16x4f64).  X sits in
+// LDS for the whole launch; each wavefront takes 16 rows at a time and
+// stages a 16 x 32 slab of them in its own LDS tile (16-byte loads, 8 lanes
+// per row, the next slab loaded while the current one is consumed), so that
+// A is read once, in 128-byte row pieces.  Lane (li, lk) supplies row li of
+// the slab at contraction indices 16 m + 4 lk + e, and row 16 m + 4 lk + e
+// of X: any bijection of the contraction index over the lanes gives the
+// same product.  Rows past n are computed from row n-1 and not stored.
+constexpr int kDtCols = 32;
+constexpr int kDtPitch = kDtCols + 4;  // floats; rows stay 16-byte aligned
+constexpr int kDtWaves = 8;
+typedef float dt_f4 __attribute__((ext_vector_type(4)));
+
+template <typename TV>
+__device__ __forceinline__ dt_f4 dt_load4(const TV* p) {
+  if constexpr (std::is_same<TV, float>::value) {
+    return stream_load<nt_f4>(p);
+  } else {
+    const nt_u2 u = stream_load<nt_u2>(p);
+    return dt_f4{bf16_lo(u[0]), bf16_hi(u[0]), bf16_lo(u[1]), bf16_hi(u[1])};
+  }
+}
+
+template <typename TV, int NB>
+__global__ __launch_bounds__(kDtWaves * kWave) void k_dense_times_wide(int64_t n, int d, int64_t ld,
+                                                                      const TV* __restrict__ A,
+                                                                      const double* __restrict__ X, int k, int dpad,
+                                                                      double* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char dt_smem[];
+  constexpr int KW = 16 * NB;
+  double* sX = reinterpret_cast<double*>(dt_smem);  // [dpad][KW]
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  float* tile = reinterpret_cast<float*>(dt_smem + static_cast<size_t>(dpad) * KW * sizeof(double)) +
+                static_cast<size_t>(wid) * 16 * kDtPitch;
+  for (int e = threadIdx.x; e < dpad * KW; e += blockDim.x) {
+    const int r = e / KW, q = e % KW;
+    sX[e] = (r < d && q < k) ? X[static_cast<size_t>(r) * k + q] : 0.0;
+  }
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  const int lrow = lane >> 3, lcol = 4 * (lane & 7);  // loads: rows lrow, lrow + 8; columns lcol .. + 3
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwave = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  const int nchunk = dpad / kDtCols;
+  for (int64_t r0 = wave * 16; r0 < n; r0 += nwave * 16) {
+    const TV* rowp[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int64_t r = r0 + lrow + 8 * it;
+      rowp[it] = A + static_cast<size_t>(r < n ? r : n - 1) * ld;
+    }
+    dt_f4 nxt[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) nxt[it] = lcol < d ? dt_load4<TV>(rowp[it] + lcol) : dt_f4{0.f, 0.f, 0.f, 0.f};
+    d4_t acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int c0 = ch * kDtCols;
+#pragma unroll
+      for (int it = 0; it < 2; ++it) *reinterpret_cast<dt_f4*>(tile + (lrow + 8 * it) * kDtPitch + lcol) = nxt[it];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (ch + 1 < nchunk) {
+        const int c = c0 + kDtCols + lcol;
+#pragma unroll
+        for (int it = 0; it < 2; ++it) nxt[it] = c < d ? dt_load4<TV>(rowp[it] + c) : dt_f4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int m = 0; m < kDtCols / 16; ++m) {
+        const dt_f4 a = *reinterpret_cast<const dt_f4*>(tile + li * kDtPitch + 16 * m + 4 * lk);
+        const double* xb = sX + static_cast<size_t>(c0 + 16 * m + 4 * lk) * KW + li;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(static_cast<double>(a[e]), xb[e * KW + 16 * b], acc[b], 0,
+                                                          0, 0);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // element e of lane (li, lk): row lk + 4 e, column 16 b + li
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t r = r0 + lk + 4 * e;
+        const int c = 16 * b + li;
+        if (r < n && c < k) out[static_cast<size_t>(r) * k + c] = acc[b][e];
+      }
+  }
+}
+
+// out (n x k, packed) = A X for dense A of value type TV: the slab kernel
+// when the rows are float32 or bfloat16 with d a multiple of 4, 16-byte
+// (bfloat16: 8-byte) aligned rows, k <= 32 and X fitting LDS; otherwise the
+// tiled GEMM.
+template <typename TV>
+int32_t dense_times(int64_t n, int64_t d, const TV* A, int64_t ld, const double* X, int64_t k, double* out,
+                    const GemmScratch& sc, hipStream_t s) {
+  if constexpr (!std::is_same<TV, double>::value) {
+    constexpr int VB = sizeof(TV) == 2 ? 8 : 16;
+    const int64_t dpad = div_up(d, kDtCols) * kDtCols;
+    const int NB = k <= 16 ? 1 : 2;
+    const size_t lds = static_cast<size_t>(dpad) * 16 * NB * sizeof(double) +
+                       static_cast<size_t>(kDtWaves) * 16 * kDtPitch * sizeof(float);
+    const bool fits = d % 4 == 0 && (ld * static_cast<int64_t>(sizeof(TV))) % VB == 0 &&
+                      reinterpret_cast<uintptr_t>(A) % VB == 0 && k >= 1 && k <= 32 && lds <= 150 * 1024 && n > 0;
+    if (fits) {
+      int cus = 256;
+      int dev = 0;
+      if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      int64_t g = div_up(n, 16 * kDtWaves);
+      if (g > cus) g = cus;
+      auto go = [&](auto kern) -> int32_t {
+        if (lds > 65536)
+          SKLS_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(g)), dim3(kDtWaves * kWave), lds, s, n,
+                           static_cast<int>(d), ld, A, X, static_cast<int>(k), static_cast<int>(dpad), out);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      };
+      return NB == 1 ? go(k_dense_times_wide<TV, 1>) : go(k_dense_times_wide<TV, 2>);
+    }
+  }
+  return gemm<TV>(false, n, k, d, 1.0, A, ld, X, k, out, k, sc, s);
+}
+
 template <typename T>
 int32_t scan(const T* in, int64_t n, T* tiles, T* out, bool exclusive, hipStream_t s) {
   if (n == 0) return SKLS_OK;
