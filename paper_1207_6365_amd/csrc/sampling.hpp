@@ -491,7 +491,6 @@ int32_t gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const TAV* 
 // same product.  Rows past n are computed from row n-1 and not stored.
 constexpr int kDtCols = 32;
 constexpr int kDtPitch = kDtCols + 4;  // floats; rows stay 16-byte aligned
-constexpr int kDtWaves = 8;
 typedef float dt_f4 __attribute__((ext_vector_type(4)));
 
 template <typename TV>
@@ -504,8 +503,8 @@ __device__ __forceinline__ dt_f4 dt_load4(const TV* p) {
   }
 }
 
-template <typename TV, int NB>
-__global__ __launch_bounds__(kDtWaves * kWave) void k_dense_times_wide(int64_t n, int d, int64_t ld,
+template <typename TV, int NB, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void k_dense_times_wide(int64_t n, int d, int64_t ld,
                                                                       const TV* __restrict__ A,
                                                                       const double* __restrict__ X, int k, int dpad,
                                                                       double* __restrict__ out) {
@@ -587,27 +586,29 @@ int32_t dense_times(int64_t n, int64_t d, const TV* A, int64_t ld, const double*
   if constexpr (!std::is_same<TV, double>::value) {
     constexpr int VB = sizeof(TV) == 2 ? 8 : 16;
     const int64_t dpad = div_up(d, kDtCols) * kDtCols;
+    // 16 wavefronts per block while X leaves room (16 columns), else 8
     const int NB = k <= 16 ? 1 : 2;
+    const int waves = NB == 1 ? 16 : 8;
     const size_t lds = static_cast<size_t>(dpad) * 16 * NB * sizeof(double) +
-                       static_cast<size_t>(kDtWaves) * 16 * kDtPitch * sizeof(float);
+                       static_cast<size_t>(waves) * 16 * kDtPitch * sizeof(float);
     const bool fits = d % 4 == 0 && (ld * static_cast<int64_t>(sizeof(TV))) % VB == 0 &&
                       reinterpret_cast<uintptr_t>(A) % VB == 0 && k >= 1 && k <= 32 && lds <= 150 * 1024 && n > 0;
     if (fits) {
       int cus = 256;
       int dev = 0;
       if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      int64_t g = div_up(n, 16 * kDtWaves);
+      int64_t g = div_up(n, 16 * waves);
       if (g > cus) g = cus;
       auto go = [&](auto kern) -> int32_t {
         if (lds > 65536)
           SKLS_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-        hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(g)), dim3(kDtWaves * kWave), lds, s, n,
+        hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(g)), dim3(waves * kWave), lds, s, n,
                            static_cast<int>(d), ld, A, X, static_cast<int>(k), static_cast<int>(dpad), out);
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
       };
-      return NB == 1 ? go(k_dense_times_wide<TV, 1>) : go(k_dense_times_wide<TV, 2>);
+      return NB == 1 ? go(k_dense_times_wide<TV, 1, 16>) : go(k_dense_times_wide<TV, 2, 8>);
     }
   }
   return gemm<TV>(false, n, k, d, 1.0, A, ld, X, k, out, k, sc, s);
