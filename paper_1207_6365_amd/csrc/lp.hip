@@ -352,13 +352,23 @@ __global__ __launch_bounds__(kT) void k_rmatvec_part(int64_t ns, int64_t d, cons
     part[static_cast<size_t>(blockIdx.x) * d + c] = s;
   }
 }
+// 8 columns per block, 32 threads per column: thread t sums slices t,
+// t + 32, ..., then thread 0 of each column adds the 32 sums in order.
 __global__ __launch_bounds__(kT) void k_col_sum(int nb, int64_t d, const double* __restrict__ part,
                                                 double* __restrict__ out) {
-  const int64_t c = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x;
-  if (c >= d) return;
+  __shared__ double sh[kT / 8][8];
+  const int cc = threadIdx.x & 7, t = threadIdx.x >> 3;
+  const int64_t c = blockIdx.x * static_cast<int64_t>(8) + cc;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[static_cast<size_t>(b) * d + c];
-  out[c] = s;
+  if (c < d)
+    for (int b = t; b < nb; b += kT / 8) s += part[static_cast<size_t>(b) * d + c];
+  sh[t][cc] = s;
+  __syncthreads();
+  if (t == 0 && c < d) {
+    double tot = 0.0;
+    for (int k = 0; k < kT / 8; ++k) tot += sh[k][cc];
+    out[c] = tot;
+  }
 }
 
 __global__ __launch_bounds__(kT) void k_ipm_update(int64_t ns, const double* __restrict__ steps,
@@ -452,7 +462,7 @@ unsigned g_rows(int64_t n) { return grid_for(n, kT, 1u << 24); }
 int32_t rmatvec(const LpWs& w, int64_t ns, int64_t d, const double* v, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_rmatvec_part, dim3(kRmvBlocks), dim3(kT), 0, s, ns, d, w.Ms, v, w.rmv);
   SKLS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_col_sum, dim3(static_cast<unsigned>(div_up(d, kT))), dim3(kT), 0, s, kRmvBlocks, d, w.rmv,
+  hipLaunchKernelGGL(k_col_sum, dim3(static_cast<unsigned>(div_up(d, 8))), dim3(kT), 0, s, kRmvBlocks, d, w.rmv,
                      out);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
@@ -869,14 +879,7 @@ int32_t run_lp(const skls_matrix& A, const double* b, const LpPlan& P, double* x
         return dense_times<TV>(n, d, static_cast<const TV*>(A.val), A.ld, w.T, kg, w.Z, w.gs, s);
       return with_rowptr(A, [&](auto trt) -> int32_t {
         using TR = decltype(trt);
-        if (kg <= 32)
-          hipLaunchKernelGGL((k_spmm<TV, TR, true>), dim3(g), dim3(kT), 0, s, n, kg,
-                             static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), w.T, w.Z);
-        else
-          hipLaunchKernelGGL((k_spmm<TV, TR, false>), dim3(g), dim3(kT), 0, s, n, kg,
-                             static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), w.T, w.Z);
-        SKLS_CHECK_LAUNCH();
-        return SKLS_OK;
+        return spmm<TV, TR>(A, kg, w.T, w.Z, s);
       });
     });
     SKLS_TRY(st);

@@ -173,7 +173,6 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
     hipLaunchKernelGGL(k_sign_projection, dim3(grid_for(d * kg, kT, 1 << 20)), dim3(kT), 0, s, di, kg, seed, w.Pi2);
     SKLS_CHECK_LAUNCH();
     SKLS_TRY(gemm(false, d, kg, d, 1.0, w.Rinv, d, w.Pi2, kg, w.T, kg, w.gs, s));
-    const unsigned g = grid_for(n, kT / kWave, 8192);
     int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
       using TV = decltype(tv);
       if (A.layout != SKLS_CSR) {
@@ -181,14 +180,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
       }
       return with_rowptr(A, [&](auto trt) -> int32_t {
         using TR = decltype(trt);
-        if (kg <= 32)
-          hipLaunchKernelGGL((k_spmm<TV, TR, true>), dim3(g), dim3(kT), 0, s, n, kg,
-                             static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), w.T, w.Z);
-        else
-          hipLaunchKernelGGL((k_spmm<TV, TR, false>), dim3(g), dim3(kT), 0, s, n, kg,
-                             static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), w.T, w.Z);
-        SKLS_CHECK_LAUNCH();
-        return SKLS_OK;
+        return spmm<TV, TR>(A, kg, w.T, w.Z, s);
       });
     });
     SKLS_TRY(st);
@@ -268,7 +260,6 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
     if (weights_out)
       SKLS_TRY_HIP(hipMemcpyAsync(weights_out, w.wts, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
     // ||A Y - B||_F and ||B||_F
-    const unsigned g = grid_for(n, kT / kWave, 8192);
     st = with_value(A.dtype, [&](auto tv) -> int32_t {
       using TV = decltype(tv);
       if (A.layout != SKLS_CSR) {
@@ -276,14 +267,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
       }
       return with_rowptr(A, [&](auto trt) -> int32_t {
         using TR = decltype(trt);
-        if (dpi <= 32)
-          hipLaunchKernelGGL((k_spmm<TV, TR, true>), dim3(g), dim3(kT), 0, s, n, dpi,
-                             static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), Y, w.AY);
-        else
-          hipLaunchKernelGGL((k_spmm<TV, TR, false>), dim3(g), dim3(kT), 0, s, n, dpi,
-                             static_cast<const TR*>(A.row_ptr), A.col_idx, static_cast<const TV*>(A.val), Y, w.AY);
-        SKLS_CHECK_LAUNCH();
-        return SKLS_OK;
+        return spmm<TV, TR>(A, dpi, Y, w.AY, s);
       });
     });
     SKLS_TRY(st);

@@ -614,6 +614,22 @@ int32_t dense_times(int64_t n, int64_t d, const TV* A, int64_t ld, const double*
   return gemm<TV>(false, n, k, d, 1.0, A, ld, X, k, out, k, sc, s);
 }
 
+// out (n x p) = A X for CSR A (n x cols) and X (cols x p, float64), p <= 64.
+template <typename TV, typename TR>
+int32_t spmm(const skls_matrix& A, int p, const double* X, double* out, hipStream_t s) {
+  const int64_t n = A.n;
+  if (n == 0) return SKLS_OK;
+  const auto* rp = static_cast<const TR*>(A.row_ptr);
+  const auto* val = static_cast<const TV*>(A.val);
+  const unsigned g = grid_for(n, kT / kWave, 8192);
+  if (p <= 32)
+    hipLaunchKernelGGL((k_spmm<TV, TR, true>), dim3(g), dim3(kT), 0, s, n, p, rp, A.col_idx, val, X, out);
+  else
+    hipLaunchKernelGGL((k_spmm<TV, TR, false>), dim3(g), dim3(kT), 0, s, n, p, rp, A.col_idx, val, X, out);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
 template <typename T>
 int32_t scan(const T* in, int64_t n, T* tiles, T* out, bool exclusive, hipStream_t s) {
   if (n == 0) return SKLS_OK;
