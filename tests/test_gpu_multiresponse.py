@@ -63,6 +63,17 @@ def test_dense_heavy_rows(sk, storage):
     _check(sk, Ag, Ad, B, 4096, 3000, 77)
 
 
+@pytest.mark.parametrize("d,dp", [(68, 16), (70, 16), (36, 32)])
+def test_dense_product_shapes(sk, d, dp):
+    # A T (32 columns) and A Y (d' columns) on the slab kernel with a padded
+    # last slab (d = 68, 36), and on the tiled GEMM when d is not a multiple
+    # of 4 (d = 70); n is not a multiple of 16 rows per wavefront
+    A, _, _ = W.pareto_rows(n=5003, d=d, storage="f32")
+    Ad = A.astype(np.float64)
+    B = _rhs(Ad, dp, 3)
+    _check(sk, up(A), Ad, B, 2048, 2000, 91)
+
+
 def test_consistent_system_is_solved_exactly(sk):
     A, _, _ = W.lstsq_small()
     B = _rhs(A, 4, 3, noise=0.0)
