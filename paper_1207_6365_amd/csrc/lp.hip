@@ -394,7 +394,7 @@ struct LpWs {
   size_t gram_bytes;
   double *G, *cholw, *R, *Rinv, *RinvT;
   int32_t* status;
-  double *Pi2, *T, *Z, *score, *lam, *rp, *prob, *part, *rmv, *sums, *resid, *negx, *one, *ppart, *pred;
+  double *Pi2, *T, *Z, *score, *lam, *rp, *prob, *part, *rmv, *sums, *resid, *negx, *one, *ppart;
   int32_t *flag, *pos, *itiles, *last, *list;
   double* wts;
   // coreset
@@ -434,7 +434,6 @@ LpWs carve_lp(Arena& ar, const LpPlan& P) {
   w.negx = ar.take<double>(d);
   w.one = ar.take<double>(2);
   w.ppart = ar.take<double>(static_cast<size_t>(pass_blocks(*P.A)) * (d + 1));
-  w.pred = ar.take<double>(static_cast<size_t>(div_up(pass_blocks(*P.A), 32)) * (d + 1));
   w.flag = ar.take<int32_t>(n);
   w.pos = ar.take<int32_t>(n);
   w.itiles = ar.take<int32_t>(tiles_for(n));
@@ -476,8 +475,8 @@ struct Fit {
 };
 
 // Weighted normal equations of the coreset rows scaled by cw (sqrt of cw
-// when SQ): G = Mw^T Mw (with Mw^T yw appended when rhs_from_gram),
-// Cholesky, inverse factor.  Returns 1 when the factor broke down.
+// when SQ): G = Mw^T Mw (with Mw^T yw appended when with_y), Cholesky, and
+// the inverse factor; *bad = 1 (and no inverse) when the factor broke down.
 template <bool SQ>
 int32_t factor_weighted(const LpWs& w, int64_t ns, int64_t d, const double* cw, bool with_y, int32_t* bad,
                         hipStream_t s) {
@@ -508,6 +507,18 @@ int32_t resid(const LpWs& w, int64_t ns, int64_t d, const double* x, double* r, 
   return SKLS_OK;
 }
 
+__global__ void k_fill(int64_t n, double v, double* __restrict__ p) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+int32_t fill_value(double* p, int64_t n, double v, hipStream_t s) {
+  if (n == 0) return SKLS_OK;
+  hipLaunchKernelGGL(k_fill, dim3(g_rows(n)), dim3(kT), 0, s, n, v, p);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
 // Least squares on the rows scaled by cw (cw = NULL: unit weights, which
 // uses a vector of ones in w.cw).
 int32_t weighted_ls(const LpWs& w, int64_t ns, int64_t d, const double* cw, double* x, int32_t* bad,
@@ -516,8 +527,6 @@ int32_t weighted_ls(const LpWs& w, int64_t ns, int64_t d, const double* cw, doub
   if (*bad) return SKLS_OK;
   return run_solve_from_gram(w.Rinv, w.RinvT, w.G + d * (d + 1), d, x, w.tmpd, s);
 }
-
-int32_t fill_value(double* p, int64_t n, double v, hipStream_t s);
 
 int32_t fit_irls(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, double tol, Fit& out,
                  hipStream_t s) {
@@ -647,18 +656,6 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     SKLS_CHECK_LAUNCH();
     out.iters = it + 1;
   }
-  return SKLS_OK;
-}
-
-__global__ void k_fill(int64_t n, double v, double* __restrict__ p) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-int32_t fill_value(double* p, int64_t n, double v, hipStream_t s) {
-  if (n == 0) return SKLS_OK;
-  hipLaunchKernelGGL(k_fill, dim3(g_rows(n)), dim3(kT), 0, s, n, v, p);
-  SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }
 
