@@ -864,25 +864,7 @@ int32_t run_lp(const skls_matrix& A, const double* b, const LpPlan& P, double* x
       return SKLS_ERR_RANK;
     }
     SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s));
-    const int di = static_cast<int>(d);
-    hipLaunchKernelGGL(k_sign_projection, dim3(grid_for(d * kg, kT, 1 << 20)), dim3(kT), 0, s, di, kg, P.seed,
-                       w.Pi2);
-    SKLS_CHECK_LAUNCH();
-    SKLS_TRY(gemm(false, d, kg, d, 1.0, w.Rinv, d, w.Pi2, kg, w.T, kg, w.gs, s));
-    const unsigned g = grid_for(n, kT / kWave, 8192);
-    int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
-      using TV = decltype(tv);
-      if (A.layout != SKLS_CSR)
-        return dense_times<TV>(n, d, static_cast<const TV*>(A.val), A.ld, w.T, kg, w.Z, w.gs, s);
-      return with_rowptr(A, [&](auto trt) -> int32_t {
-        using TR = decltype(trt);
-        return spmm<TV, TR>(A, kg, w.T, w.Z, s);
-      });
-    });
-    SKLS_TRY(st);
-    SKLS_TRY(launch_fill_zero(w.last, 16, s));
-    hipLaunchKernelGGL(k_row_sqnorm, dim3(g), dim3(kT), 0, s, n, kg, w.Z, w.score, w.last);
-    SKLS_CHECK_LAUNCH();
+    SKLS_TRY(row_norm_estimates(A, w.Rinv, kg, P.seed, w.Pi2, w.T, w.Z, w.score, w.last, w.gs, s));
     hipLaunchKernelGGL(k_pow_rows, dim3(kRed), dim3(kT), 0, s, n, w.score, P.p / 2.0, w.lam, w.part);
     SKLS_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kRed, 1, w.sums);

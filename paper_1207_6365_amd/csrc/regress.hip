@@ -143,7 +143,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
     return SKLS_ERR_WORKSPACE;
   }
   const int64_t n = P.n, d = P.d, dp = P.dp;
-  const int kg = P.kg, di = static_cast<int>(d), dpi = static_cast<int>(dp);
+  const int kg = P.kg, dpi = static_cast<int>(dp);
   skls_multi_info inf{};
   hipEvent_t ev[3];
   for (auto& e : ev) SKLS_TRY_HIP(hipEventCreate(&e));
@@ -170,24 +170,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
   int64_t ns = 0;
   {
     PhaseTimer pt("multi_scores", s);
-    hipLaunchKernelGGL(k_sign_projection, dim3(grid_for(d * kg, kT, 1 << 20)), dim3(kT), 0, s, di, kg, seed, w.Pi2);
-    SKLS_CHECK_LAUNCH();
-    SKLS_TRY(gemm(false, d, kg, d, 1.0, w.Rinv, d, w.Pi2, kg, w.T, kg, w.gs, s));
-    int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
-      using TV = decltype(tv);
-      if (A.layout != SKLS_CSR) {
-        return dense_times<TV>(n, d, static_cast<const TV*>(A.val), A.ld, w.T, kg, w.Z, w.gs, s);
-      }
-      return with_rowptr(A, [&](auto trt) -> int32_t {
-        using TR = decltype(trt);
-        return spmm<TV, TR>(A, kg, w.T, w.Z, s);
-      });
-    });
-    SKLS_TRY(st);
-    SKLS_TRY(launch_fill_zero(w.last, 16, s));
-    hipLaunchKernelGGL(k_row_sqnorm, dim3(grid_for(n, kT / kWave, 8192)), dim3(kT), 0, s, n, kg, w.Z, w.score,
-                       w.last);
-    SKLS_CHECK_LAUNCH();
+    SKLS_TRY(row_norm_estimates(A, w.Rinv, kg, seed, w.Pi2, w.T, w.Z, w.score, w.last, w.gs, s));
 
     // ---- step 2: draws, the coreset
     SKLS_TRY(scan<double>(w.score, n, w.dtiles, w.cum, false, s));
@@ -286,7 +269,6 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
   inf.ms_scores = ms;
   SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
   inf.ms_solve = ms;
-  (void)di;
   if (info) *info = inf;
   return SKLS_OK;
 }

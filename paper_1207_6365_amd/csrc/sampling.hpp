@@ -630,6 +630,32 @@ int32_t spmm(const skls_matrix& A, int p, const double* X, double* out, hipStrea
   return SKLS_OK;
 }
 
+// Section 6 row-norm estimates in float64: score_i = ||(A R^{-1} Pi2)_i||^2
+// with Pi2 the d x kg sign matrix / sqrt(kg) of the stream seed ^
+// "leverage".  Pi2, T (d x kg) and Z (n x kg) are scratch; last[0] receives
+// the largest row with a positive score.
+int32_t row_norm_estimates(const skls_matrix& A, const double* Rinv, int kg, uint64_t seed, double* Pi2, double* T,
+                           double* Z, double* score, int32_t* last, const GemmScratch& gs, hipStream_t s) {
+  const int64_t n = A.n, d = A.d;
+  hipLaunchKernelGGL(k_sign_projection, dim3(grid_for(d * kg, kT, 1 << 20)), dim3(kT), 0, s, static_cast<int>(d), kg,
+                     seed, Pi2);
+  SKLS_CHECK_LAUNCH();
+  SKLS_TRY(gemm(false, d, kg, d, 1.0, Rinv, d, Pi2, kg, T, kg, gs, s));
+  int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
+    using TV = decltype(tv);
+    if (A.layout != SKLS_CSR) return dense_times<TV>(n, d, static_cast<const TV*>(A.val), A.ld, T, kg, Z, gs, s);
+    return with_rowptr(A, [&](auto trt) -> int32_t {
+      using TR = decltype(trt);
+      return spmm<TV, TR>(A, kg, T, Z, s);
+    });
+  });
+  SKLS_TRY(st);
+  SKLS_TRY(launch_fill_zero(last, 16, s));
+  hipLaunchKernelGGL(k_row_sqnorm, dim3(grid_for(n, kT / kWave, 8192)), dim3(kT), 0, s, n, kg, Z, score, last);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
 template <typename T>
 int32_t scan(const T* in, int64_t n, T* tiles, T* out, bool exclusive, hipStream_t s) {
   if (n == 0) return SKLS_OK;
