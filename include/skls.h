@@ -375,7 +375,10 @@ SKLS_API int32_t skls_multi_lstsq(const skls_matrix* A, const double* B, int64_t
  * the duality gap is at most tol * max(1, objective)), other p by iteratively
  * reweighted least squares (Newton steps 1/(p-1) long with halving for p > 2;
  * a floor on |r| that shrinks 4x per step to 1e-9 of the mean for p < 2; stops
- * at the floor once the objective changes by at most tol relative).
+ * at the floor once the objective changes by at most tol relative).  Every
+ * fit starts from the least-squares solution of the kept rows and stops there
+ * when its residuals are at rounding level (sum |r| <= 16 d 2^-53 sum |b| over
+ * the kept rows): that solves a consistent system, which is optimal for every p.
  * Synchronous.
  */
 typedef struct {
@@ -394,7 +397,7 @@ typedef struct {
 
 typedef struct {
   int64_t rows_stage1, rows_stage2;  /* rows kept by the two draws */
-  int32_t iters_stage1, iters_stage2;  /* weighted solves of each fit */
+  int32_t iters_stage1, iters_stage2;  /* weighted solves (factorizations) of each fit, the start included */
   int32_t converged;     /* 1 if both fits met their stopping rule */
   int32_t reserved0;
   double obj_stage1;     /* ||A x_c - b||_p^p (float64 accumulation) */

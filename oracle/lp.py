@@ -148,7 +148,8 @@ def _solve_lp_general(M: np.ndarray, y: np.ndarray, p: float) -> np.ndarray:
 
     def h(x):
         r = M @ x - y
-        wts = p * (p - 1) * np.abs(r) ** (p - 2)
+        with np.errstate(divide="ignore"):
+            wts = p * (p - 1) * np.abs(r) ** (p - 2)
         wts = np.where(np.isfinite(wts), wts, 0.0)
         return (M.T * wts) @ M / f0
 

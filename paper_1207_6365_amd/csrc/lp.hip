@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kT) void k_take(int64_t n, const int32_t* __restric
 
 // out_i = M_i x - y_i (y may be NULL), one wavefront per row; with partial
 // (grid of kResBlocks): partial[b] = block sum of |out_i|^p,
-// partial[kResBlocks + b] = of |out_i|.
+// partial[kResBlocks + b] = of |out_i|, partial[2 kResBlocks + b] = of |y_i|.
 __global__ __launch_bounds__(kT) void k_resid_rows(int64_t ns, int64_t d, const double* __restrict__ M,
                                                    const double* __restrict__ x, const double* __restrict__ y,
                                                    double* __restrict__ out, double p,
@@ -133,23 +133,27 @@ __global__ __launch_bounds__(kT) void k_resid_rows(int64_t ns, int64_t d, const 
   __shared__ double sh[kT / kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
-  double sp = 0.0, s1 = 0.0;
+  double sp = 0.0, s1 = 0.0, sy = 0.0;
   for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < ns; r += nw) {
     const double* row = M + static_cast<size_t>(r) * d;
     double s = 0.0;
     for (int64_t c = lane; c < d; c += kWave) s += row[c] * x[c];
     s = wave_total(s);
-    const double v = y ? s - y[r] : s;
+    const double yr = y ? y[r] : 0.0;
+    const double v = s - yr;
     if (lane == 0) {
       out[r] = v;
       sp += pow(fabs(v), p);
       s1 += fabs(v);
+      sy += fabs(yr);
     }
   }
   if (partial == nullptr) return;
   block_partial(sp, sh, partial + blockIdx.x);
   __syncthreads();
   block_partial(s1, sh, partial + kResBlocks + blockIdx.x);
+  __syncthreads();
+  block_partial(sy, sh, partial + 2 * kResBlocks + blockIdx.x);
 }
 
 // out[i][:] = c_i M[i][:] (c_i = sqrt(cw_i) when SQ), vout_i = c_i y_i.
@@ -428,7 +432,7 @@ LpWs carve_lp(Arena& ar, const LpPlan& P) {
   w.rp = ar.take<double>(n);
   w.prob = ar.take<double>(n);
   w.resid = ar.take<double>(n);
-  w.part = ar.take<double>(2 * kResBlocks + 2 * kRed);
+  w.part = ar.take<double>(3 * kResBlocks + 2 * kRed);
   w.rmv = ar.take<double>(static_cast<size_t>(kRmvBlocks) * d);
   w.sums = ar.take<double>(8);
   w.negx = ar.take<double>(d);
@@ -449,7 +453,7 @@ LpWs carve_lp(Arena& ar, const LpPlan& P) {
   for (double** v : vecs) *v = ar.take<double>(cap);
   double** dvecs[] = {&w.x, &w.xn, &w.xt, &w.c, &w.r1, &w.rhs, &w.tmpd, &w.dx};
   for (double** v : dvecs) *v = ar.take<double>(d);
-  w.dev = ar.take<double>(8);  // gap, pobj, steps[2], smu, -, coreset sums[2]
+  w.dev = ar.take<double>(16);  // gap, pobj, steps[2], smu, -, -, -, coreset sums[3]
   w.gs.doubles = size_t(1) << 21;
   w.gs.part = ar.take<double>(w.gs.doubles);
   return w;
@@ -493,19 +497,25 @@ int32_t factor_weighted(const LpWs& w, int64_t ns, int64_t d, const double* cw, 
   return run_trinv(w.R, d, w.Rinv, w.RinvT, s);
 }
 
+// r = M x - y on the coreset; f = sum |r|^p, f1 = sum |r|, fy = sum |y|.
 int32_t resid(const LpWs& w, int64_t ns, int64_t d, const double* x, double* r, double p, double* f, double* f1,
-              hipStream_t s) {
+              double* fy, hipStream_t s) {
   hipLaunchKernelGGL(k_resid_rows, dim3(kResBlocks), dim3(kT), 0, s, ns, d, w.Ms, x, w.ys, r, p, w.part);
   SKLS_CHECK_LAUNCH();
-  // dev[6..7]: sums[0..1] hold the sampling totals for the whole call
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kResBlocks, 2, w.dev + 6);
+  // dev[8..10]: sums[0..1] hold the sampling totals for the whole call
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kResBlocks, 3, w.dev + 8);
   SKLS_CHECK_LAUNCH();
-  double h[2];
-  SKLS_TRY(to_host(h, w.dev + 6, sizeof h, s));
+  double h[3];
+  SKLS_TRY(to_host(h, w.dev + 8, sizeof h, s));
   *f = h[0];
   if (f1) *f1 = h[1];
+  if (fy) *fy = h[2];
   return SKLS_OK;
 }
+
+// The least-squares start fits every kept row to rounding: it solves the
+// consistent system, which is optimal for every p.
+bool exact_start(double f1, double fy, int64_t d) { return f1 <= 16.0 * static_cast<double>(d) * 0x1.0p-53 * fy; }
 
 __global__ void k_fill(int64_t n, double v, double* __restrict__ p) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x;
@@ -537,10 +547,10 @@ int32_t fit_irls(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, d
     set_error("lp_regression: the sampled rows are numerically rank deficient (raise s1 or s2)");
     return SKLS_ERR_RANK;
   }
-  double f = 0.0, f1 = 0.0;
-  SKLS_TRY(resid(w, ns, d, w.x, w.r, p, &f, &f1, s));
+  double f = 0.0, f1 = 0.0, fy = 0.0;
+  SKLS_TRY(resid(w, ns, d, w.x, w.r, p, &f, &f1, &fy, s));
   out.iters = 1;
-  if (p == 2.0) {
+  if (p == 2.0 || exact_start(f1, fy, d)) {
     out.converged = true;
     out.obj = f;
     return SKLS_OK;
@@ -559,7 +569,7 @@ int32_t fit_irls(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, d
     for (;;) {
       hipLaunchKernelGGL(k_vlerp, dim3(g_rows(d)), dim3(kT), 0, s, d, w.x, w.xn, th, w.xt);
       SKLS_CHECK_LAUNCH();
-      SKLS_TRY(resid(w, ns, d, w.xt, rt, p, &ft, nullptr, s));
+      SKLS_TRY(resid(w, ns, d, w.xt, rt, p, &ft, nullptr, nullptr, s));
       if (ft <= f || th < 1e-6 || p < 2.0) break;
       th *= 0.5;
     }
@@ -604,15 +614,20 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     set_error("lp_regression: the sampled rows are numerically rank deficient (raise s1 or s2)");
     return SKLS_ERR_RANK;
   }
-  double f = 0.0, f1 = 0.0;
-  SKLS_TRY(resid(w, ns, d, w.x, w.r, 1.0, &f, &f1, s));
+  double f = 0.0, f1 = 0.0, fy = 0.0;
+  SKLS_TRY(resid(w, ns, d, w.x, w.r, 1.0, &f, &f1, &fy, s));
+  out.iters = 1;
+  out.obj = f;
+  if (exact_start(f1, fy, d)) {
+    out.converged = true;
+    return SKLS_OK;
+  }
   const unsigned g = g_rows(ns);
   hipLaunchKernelGGL(k_ipm_init, dim3(g), dim3(kT), 0, s, ns, w.r, f1 / static_cast<double>(ns), w.a, w.sl, w.z,
                      w.w);
   SKLS_CHECK_LAUNCH();
   // c = M^T a at the start (a = 1/2): the dual equality M^T a = c holds there
   SKLS_TRY(rmatvec(w, ns, d, w.a, w.c, s));
-  out.iters = 0;
   for (int it = 0; it <= max_iter; ++it) {
     hipLaunchKernelGGL(k_resid_rows, dim3(kResBlocks), dim3(kT), 0, s, ns, d, w.Ms, w.x, w.ys, w.r, 1.0, nullptr);
     SKLS_CHECK_LAUNCH();
@@ -654,7 +669,7 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     SKLS_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_vaxpy_dev, dim3(g_rows(d)), dim3(kT), 0, s, d, w.dev + 3, w.dx, w.x);
     SKLS_CHECK_LAUNCH();
-    out.iters = it + 1;
+    out.iters = it + 2;  // the least-squares start and it + 1 interior-point steps
   }
   return SKLS_OK;
 }

@@ -125,6 +125,20 @@ def test_keeping_every_row_gives_the_exact_fit(sk, p):
     assert info["obj"] == pytest.approx(fe, rel=FIT_TOL.get(p, 1e-9))
 
 
+@pytest.mark.parametrize("p", [1.0, 1.5, 3.0])
+def test_consistent_system_is_solved_exactly(sk, p):
+    # b = A x0: the least-squares start already fits every row, the residual
+    # share of stage 2 is empty, and x = x0
+    A, _, x0 = W.lp_dense(n=2500, d=7)
+    b = A @ x0
+    x, info = sk.lp_regression(up(A), up(b), p, 4, q=64, v=4, s1=300.0, s2=300.0)
+    assert np.allclose(x.cpu().numpy(), x0, rtol=0, atol=1e-9 * np.max(np.abs(x0)))
+    assert info["converged"] == 1 and info["iters_stage1"] == 1 and info["iters_stage2"] == 1
+    assert info["obj"] <= (1e-12 * np.sum(np.abs(b))) ** p * b.size
+    ref = LP.lp_regression(A, b, p, 4, 64, 4, 1, 300.0, 300.0)
+    assert np.allclose(ref["x"], x0, rtol=0, atol=1e-9 * np.max(np.abs(x0)))
+
+
 def test_errors(sk):
     A, b, _ = W.lp_dense(n=500, d=4)
     with pytest.raises(sk.SklsError):

@@ -157,6 +157,15 @@ def test_sampled_fit_is_within_one_plus_eps(p):
     assert np.all(out["q"] >= np.minimum(1.0, 800 * share) * (1 - 1e-12))
 
 
+@pytest.mark.parametrize("p", [1.0, 1.5, 3.0])
+def test_consistent_system_is_solved_exactly(p):
+    A, _, x0 = W.lp_dense(n=2500, d=7)
+    b = A @ x0
+    out = LP.lp_regression(A, b, p, 4, 64, 4, 1, 300.0, 300.0)
+    assert np.allclose(out["x"], x0, rtol=0, atol=1e-9 * np.max(np.abs(x0)))
+    assert np.allclose(out["x_c"], x0, rtol=0, atol=1e-9 * np.max(np.abs(x0)))
+
+
 def test_rank_deficient_input_is_rejected():
     A, b, _ = W.lp_dense(n=500, d=4)
     A[:, 2] = 0.0
