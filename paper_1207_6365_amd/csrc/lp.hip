@@ -480,7 +480,9 @@ struct Fit {
 
 // Weighted normal equations of the coreset rows scaled by cw (sqrt of cw
 // when SQ): G = Mw^T Mw (with Mw^T yw appended when with_y), Cholesky, and
-// the inverse factor; *bad = 1 (and no inverse) when the factor broke down.
+// the inverse factor.  With bad given, the Cholesky status is read back now
+// (*bad = 1, and no inverse, when the factor broke down); without it the
+// status stays on the device for the caller's next read.
 template <bool SQ>
 int32_t factor_weighted(const LpWs& w, int64_t ns, int64_t d, const double* cw, bool with_y, int32_t* bad,
                         hipStream_t s) {
@@ -490,21 +492,25 @@ int32_t factor_weighted(const LpWs& w, int64_t ns, int64_t d, const double* cw, 
   const int64_t dd = with_y ? d + 1 : d;
   SKLS_TRY(run_gram(w.Mw, SKLS_F64, d, with_y ? w.yw : nullptr, SKLS_F64, ns, d, w.G, w.gram, w.gram_bytes, s));
   SKLS_TRY(run_cholesky(w.G, dd, d, w.R, w.status, w.cholw, s));
-  int32_t st = 0;
-  SKLS_TRY(to_host(&st, w.status, sizeof st, s));
-  *bad = st;
-  if (st) return SKLS_OK;
+  if (bad != nullptr) {
+    int32_t st = 0;
+    SKLS_TRY(to_host(&st, w.status, sizeof st, s));
+    *bad = st;
+    if (st) return SKLS_OK;
+  }
   return run_trinv(w.R, d, w.Rinv, w.RinvT, s);
 }
 
-// r = M x - y on the coreset; f = sum |r|^p, f1 = sum |r|, fy = sum |y|.
+// r = M x - y on the coreset; f = sum |r|^p, f1 = sum |r|, fy = sum |y|;
+// chol_bad (if given) receives the status of the last factorization.
 int32_t resid(const LpWs& w, int64_t ns, int64_t d, const double* x, double* r, double p, double* f, double* f1,
-              double* fy, hipStream_t s) {
+              double* fy, hipStream_t s, int32_t* chol_bad = nullptr) {
   hipLaunchKernelGGL(k_resid_rows, dim3(kResBlocks), dim3(kT), 0, s, ns, d, w.Ms, x, w.ys, r, p, w.part);
   SKLS_CHECK_LAUNCH();
   // dev[8..10]: sums[0..1] hold the sampling totals for the whole call
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kResBlocks, 3, w.dev + 8);
   SKLS_CHECK_LAUNCH();
+  if (chol_bad) SKLS_TRY_HIP(hipMemcpyAsync(chol_bad, w.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   double h[3];
   SKLS_TRY(to_host(h, w.dev + 8, sizeof h, s));
   *f = h[0];
@@ -529,12 +535,12 @@ int32_t fill_value(double* p, int64_t n, double v, hipStream_t s) {
   return SKLS_OK;
 }
 
-// Least squares on the rows scaled by cw (cw = NULL: unit weights, which
-// uses a vector of ones in w.cw).
+// Least squares on the coreset rows scaled by cw; bad as for
+// factor_weighted (NULL: the status is left on the device).
 int32_t weighted_ls(const LpWs& w, int64_t ns, int64_t d, const double* cw, double* x, int32_t* bad,
                     hipStream_t s) {
   SKLS_TRY(factor_weighted<false>(w, ns, d, cw, true, bad, s));
-  if (*bad) return SKLS_OK;
+  if (bad != nullptr && *bad) return SKLS_OK;
   return run_solve_from_gram(w.Rinv, w.RinvT, w.G + d * (d + 1), d, x, w.tmpd, s);
 }
 
@@ -562,17 +568,17 @@ int32_t fit_irls(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, d
   for (int it = 0; it < max_iter; ++it) {
     hipLaunchKernelGGL(k_irls_weights, dim3(g_rows(ns)), dim3(kT), 0, s, ns, r, eta, (p - 2.0) / 2.0, w.cw);
     SKLS_CHECK_LAUNCH();
-    SKLS_TRY(weighted_ls(w, ns, d, w.cw, w.xn, &bad, s));
-    if (bad) break;  // keep the last iterate
+    SKLS_TRY(weighted_ls(w, ns, d, w.cw, w.xn, nullptr, s));  // status read with the residual below
     double th = p <= 2.0 ? 1.0 : 1.0 / (p - 1.0);
     double ft = 0.0;
     for (;;) {
       hipLaunchKernelGGL(k_vlerp, dim3(g_rows(d)), dim3(kT), 0, s, d, w.x, w.xn, th, w.xt);
       SKLS_CHECK_LAUNCH();
-      SKLS_TRY(resid(w, ns, d, w.xt, rt, p, &ft, nullptr, nullptr, s));
-      if (ft <= f || th < 1e-6 || p < 2.0) break;
+      SKLS_TRY(resid(w, ns, d, w.xt, rt, p, &ft, nullptr, nullptr, s, &bad));
+      if (bad || ft <= f || th < 1e-6 || p < 2.0) break;
       th *= 0.5;
     }
+    if (bad) break;  // the factor broke down: keep the last iterate
     const bool done = eta <= emin && std::fabs(f - ft) <= tol * f;
     SKLS_TRY_HIP(hipMemcpyAsync(w.x, w.xt, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
     std::swap(r, rt);
@@ -635,8 +641,16 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     SKLS_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kRed, 2, w.dev);
     SKLS_CHECK_LAUNCH();
+    // the gap and objective, and the status of the previous step's factor
+    int32_t st = 0;
+    if (it > 0) SKLS_TRY_HIP(hipMemcpyAsync(&st, w.status, sizeof st, hipMemcpyDeviceToHost, s));
     double h[2];
     SKLS_TRY(to_host(h, w.dev, sizeof h, s));
+    if (st) {  // that factor broke down: back to the iterate before the step
+      SKLS_TRY_HIP(hipMemcpyAsync(w.x, w.xt, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
+      out.iters = it;
+      break;
+    }
     out.obj = h[1];
     if (h[0] <= tol * std::max(1.0, h[1])) {
       out.converged = true;
@@ -651,8 +665,7 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     hipLaunchKernelGGL(k_ipm_rhs<false>, dim3(g), dim3(kT), 0, s, ns, w.r, w.a, w.sl, w.z, w.w, w.da, w.dz, w.dw,
                        w.dev + 4, w.qi, w.rho, w.qrho, w.r4, w.r5);
     SKLS_CHECK_LAUNCH();
-    SKLS_TRY(factor_weighted<true>(w, ns, d, w.qi, false, &bad, s));
-    if (bad) break;  // keep the last iterate
+    SKLS_TRY(factor_weighted<true>(w, ns, d, w.qi, false, nullptr, s));  // status read at the next gap
     SKLS_TRY(ipm_direction(w, ns, d, 1.0, s));
     hipLaunchKernelGGL(k_ipm_gaff, dim3(kRed), dim3(kT), 0, s, ns, w.a, w.sl, w.z, w.w, w.da, w.dz, w.dw,
                        w.dev + 2, w.part);
@@ -667,6 +680,7 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     hipLaunchKernelGGL(k_ipm_update, dim3(g), dim3(kT), 0, s, ns, w.dev + 2, w.a, w.sl, w.z, w.w, w.da, w.dz,
                        w.dw);
     SKLS_CHECK_LAUNCH();
+    SKLS_TRY_HIP(hipMemcpyAsync(w.xt, w.x, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(k_vaxpy_dev, dim3(g_rows(d)), dim3(kT), 0, s, d, w.dev + 3, w.dx, w.x);
     SKLS_CHECK_LAUNCH();
     out.iters = it + 2;  // the least-squares start and it + 1 interior-point steps
