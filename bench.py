@@ -134,6 +134,59 @@ def segment_ceiling(dev, sync, n_rows: int):
     return out
 
 
+def oracle_rows(log):
+    """The oracle on bounded samples of the other workloads, one thread (BLAS
+    held to one thread as well): seconds per call and the sample's size, as
+    context for the GPU figures of each row."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    import workloads as W
+
+    def timed(fn, reps=1):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        return (time.perf_counter() - t0) / reps
+
+    out = {}
+    with threadpool_limits(1):
+        log("oracle samples: small regression, heavy-row regression, leverage, multiple responses, low rank, l_p, "
+            "learned gradient")
+        A1, b1, _ = W.lstsq_small()
+        sec = timed(lambda: O.sketch_and_solve(A1, b1, W.sketch_seed(0), 4000), 5)
+        out["lstsq_small"] = {"s_per_call": sec, "sample": "sketch-and-solve, the full small workload"}
+        n2, d2, t2 = 1 << 15, 512, 1 << 13
+        A2, b2, _ = W.pareto_rows(n=n2, d=d2, storage="f32")
+        A2 = A2.astype(np.float64)
+        sec = timed(lambda: O.lstsq(A2, b2, W.sketch_seed(0), t2, 1e-6))
+        out["lstsq"] = {"s_per_call": sec, "rows_per_s": n2 / sec,
+                        "sample": f"certified solve (delta 1e-6) of a heavy-row sample n={n2}, d={d2}, t={t2}"}
+        Pi2 = np.random.default_rng(7).standard_normal((d2, 32)) / np.sqrt(32.0)
+        sec = timed(lambda: O.leverage_approx(A2, W.sketch_seed(0), t2, Pi2))
+        out["leverage"] = {"s_per_call": sec, "rows_per_s": n2 / sec,
+                           "sample": f"leverage scores (k=32) of the same sample n={n2}, d={d2}, t={t2}"}
+        B2 = np.random.default_rng(3).standard_normal((n2, 16))
+        sec = timed(lambda: O.multi_response_lstsq(A2, B2, 77, t2, 4096))
+        out["multi"] = {"s_per_call": sec, "rows_per_s": n2 / sec,
+                        "sample": f"16 responses, the same sample n={n2}, d={d2}, t={t2}, t_s=4096"}
+        A4 = W.planted_lowrank_sparse(n=4096, density=0.02)
+        sec = timed(lambda: O.low_rank(A4, 32, W.sketch_seed(0), 128, 4096))
+        out["low_rank"] = {"s_per_call": sec, "nnz": int(A4.nnz),
+                           "sample": "rank 32 of a planted 4096 x 4096 sparse matrix, t_R=128, t_S=4096"}
+        A6, b6, _ = W.lp_sparse(n=1 << 17, d=64)
+        sec = timed(lambda: O.lp_regression(A6, b6, 1.0, W.sketch_seed(6), 1024, 8, 1, 2048.0, 2048.0))
+        out["lp"] = {"s_per_call": sec, "nnz_per_s": A6.nnz / sec,
+                     "sample": "p = 1, CSR n=2^17, d=64, 16 nnz/row, F with 2 d^2 rows, s1 = s2 = 32 d"}
+        make, _ = W.learned_family()
+        A5 = make(0).astype(np.float64)
+        w5 = np.ones(A5.shape[0])
+        sec = timed(lambda: O.distortion_grad(A5, W.sketch_seed(0), 1024, w5))
+        out["learned"] = {"s_per_call": sec, "sample": "distortion loss gradient of one 32768 x 64 matrix, t=1024"}
+    return out
+
+
 def time_steps(fn, steps, warmup, sync):
     import torch
 
@@ -583,6 +636,8 @@ def main():
                                   "sample": f"full sparse workload (nnz={nnz}), {reps} repetitions of the NumPy "
                                             "float64 oracle sketch, single thread",
                                   "host_cpus": os.cpu_count()}
+        if args.only is None and not args.no_extras:
+            result["cpu_baseline"]["rows"] = oracle_rows(log)
     print(json.dumps(result), flush=True)
 
 
