@@ -373,9 +373,10 @@ SKLS_API int32_t skls_multi_lstsq(const skls_matrix* A, const double* B, int64_t
  * on the float64 coreset: p = 2 through the normal equations, p = 1 by a
  * primal-dual interior-point method on the dual linear program (stops when
  * the duality gap is at most tol * max(1, objective)), other p by iteratively
- * reweighted least squares (Newton steps 1/(p-1) long with halving for p > 2;
- * a floor on |r| that shrinks 4x per step to 1e-9 of the mean for p < 2; stops
- * at the floor once the objective changes by at most tol relative).  Every
+ * reweighted least squares (weights max(|r_i|, eta)^(p-2), with eta starting
+ * at the mean |r| and shrinking 4x per step to 1e-9 of it; Newton steps
+ * 1/(p-1) long with halving for p > 2; stops once eta is at its floor and the
+ * objective changes by at most tol relative).  Every
  * fit starts from the least-squares solution of the kept rows and stops there
  * when its residuals are at rounding level (sum |r| <= 16 d 2^-53 sum |b| over
  * the kept rows): that solves a consistent system, which is optimal for every p.
