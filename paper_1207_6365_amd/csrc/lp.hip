@@ -16,9 +16,10 @@
 // The weighted fits run on the gathered float64 coreset: p = 2 by the normal
 // equations, p = 1 by a primal-dual interior-point method on the dual of the
 // l_1 fit (Mehrotra predictor-corrector), other p by iteratively reweighted
-// least squares (Newton steps of length 1/(p-1) with halving for p > 2, a
-// shrinking floor on |r| for p < 2).  Every step solves a weighted normal
-// system through the float64 Gram, Cholesky and the inverse factor.
+// least squares (a floor on |r| in the weights that shrinks to 1e-9 of the
+// starting mean; Newton steps of length 1/(p-1) with halving for p > 2).
+// Every step solves a weighted normal system through the float64 Gram,
+// Cholesky and the inverse factor.
 
 #include <cmath>
 
