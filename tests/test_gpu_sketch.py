@@ -249,3 +249,42 @@ def test_full_size_dense_sampled_buckets(sk):
     scale = O.sketch_bucket_rows(lambda idx: np.abs(A[idx]).astype(np.float64), seed, A.shape[0], t, buckets,
                                  w=np.ones(A.shape[0]))
     assert_sum_close(SA[buckets], ref, scale, U32)
+
+
+def test_int64_row_pointers_past_2p31_entries(sk):
+    # 2^31 + 80 stored entries (16 per row, n = 2^27 + 5 rows, d = 64): the
+    # entry offsets only fit 64-bit row pointers.  Integer values keep every
+    # bucket sum exact in float32, so sampled rows of S A are compared bit for
+    # bit with the oracle's per-bucket sums.  The entries are drawn on the GPU
+    # from a seeded generator (17 GB; drawing them on the host would take
+    # minutes).
+    n, d, k, t = (1 << 27) + 5, 64, 16, 4096
+    nnz = n * k
+    assert nnz > 2**31
+    g = torch.Generator(device=dev())
+    g.manual_seed(12345)
+    col = torch.randint(0, d, (nnz,), dtype=torch.int32, device=dev(), generator=g)
+    mag = torch.randint(1, 9, (nnz,), dtype=torch.int8, device=dev(), generator=g)
+    sgn = torch.randint(0, 2, (nnz,), dtype=torch.int8, device=dev(), generator=g)
+    val = (mag * (2 * sgn - 1)).to(torch.float32)
+    del mag, sgn
+    row_ptr = torch.arange(0, nnz + 1, k, dtype=torch.int64, device=dev())
+    seed = W.sketch_seed(3)
+    SA = sk.sketch(sk.Csr(n, d, row_ptr, col, val), t, seed).cpu().numpy().astype(np.float64)
+
+    def rows_of(idx):
+        if len(idx) == 0:
+            return np.zeros((0, d))
+        it = torch.from_numpy(np.asarray(idx, dtype=np.int64)).to(dev())
+        ent = (it[:, None] * k + torch.arange(k, device=dev())[None, :]).reshape(-1)
+        c = col[ent].cpu().numpy()
+        v = val[ent].cpu().numpy().astype(np.float64)
+        out = np.zeros((len(idx), d))
+        np.add.at(out, (np.repeat(np.arange(len(idx)), k), c), v)
+        return out
+
+    buckets = np.array([0, 1234, t - 1])
+    ref = O.sketch_bucket_rows(rows_of, seed, n, t, buckets)
+    assert np.array_equal(SA[buckets], ref)
+    del col, val, row_ptr
+    torch.cuda.empty_cache()
