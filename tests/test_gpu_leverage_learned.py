@@ -133,3 +133,29 @@ def test_training_lowers_distortion_on_held_out_matrices(sk):
     assert learned.mean() < plain.mean()
     assert res.used_learned
     print(f"test distortion plain {plain.mean():.4f} learned {learned.mean():.4f}")
+
+
+def test_leverage_past_2p31_entries(sk):
+    # CSR with 2^31 + 80 entries (64-bit row pointers, n = 2^27 + 5, d = 64),
+    # drawn on the GPU from a seeded generator.  With R from a 2^16-row sketch,
+    # A R^{-1} is close to orthonormal, so the scores (unbiased for the squared
+    # row norms with the scaled Gaussian Pi2) sum to about d; every score is
+    # finite and non-negative.
+    import numpy as np
+    import torch
+
+    n, d, k = (1 << 27) + 5, 64, 16
+    nnz = n * k
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(4321)
+    col = torch.randint(0, d, (nnz,), dtype=torch.int32, device="cuda:0", generator=g)
+    val = torch.randn(nnz, dtype=torch.float32, device="cuda:0", generator=g)
+    row_ptr = torch.arange(0, nnz + 1, k, dtype=torch.int64, device="cuda:0")
+    Pi2 = torch.from_numpy(np.random.default_rng(1).standard_normal((d, 32)) / np.sqrt(32.0)).to("cuda:0")
+    scores = sk.leverage_scores(sk.Csr(n, d, row_ptr, col, val), 1 << 16, 99, Pi2)
+    assert scores.numel() == n
+    assert bool(torch.isfinite(scores).all()) and float(scores.min()) >= 0.0
+    total = float(scores.double().sum())
+    assert 0.7 * d < total < 1.3 * d
+    del col, val, row_ptr, scores
+    torch.cuda.empty_cache()
