@@ -89,6 +89,17 @@ def test_dense_matches_oracle(sk, p):
     assert fe * (1 - 1e-9) <= full <= fe * 1.1 ** p
 
 
+@pytest.mark.parametrize("p", [1.0, 1.5])
+def test_several_factor_blocks_match_oracle(sk, p):
+    # d = 130: the weighted normal systems factor in 64-column blocks with a
+    # two-column last block (64 + 64 + 2), solved block by block
+    A, b, _ = W.lp_dense(n=10000, d=130)
+    seed, kw = 0x3150 + int(10 * p), dict(q=1000, v=8, a=1, s1=1000.0, s2=1000.0)
+    ref = LP.lp_regression(A, b, p, seed, kw["q"], kw["v"], kw["a"], kw["s1"], kw["s2"])
+    got = sk.lp_regression(up(A), up(b), p, seed, samples=True, **kw)
+    _check(got, ref, MatrixOp(A), b, p, seed, x_unique=p > 1.0)
+
+
 @pytest.mark.parametrize("row64", [False, True])
 def test_csr_blocks_match_oracle(sk, row64):
     # several blocks of F with a short last block; sizes not multiples of any tile
