@@ -131,7 +131,7 @@ int32_t qr_from(const void* M, int32_t dtype, const void* v, int32_t v_dtype, in
   const int64_t dd = d + (v ? 1 : 0);
   SKLS_TRY(run_gram(M, dtype, d, v, v_dtype, m, d, q.G, q.gram, q.gram_bytes, s));
   SKLS_TRY(run_cholesky(q.G, dd, d, R, q.status, q.W, s));
-  if (Rinv) SKLS_TRY(run_trinv(R, d, Rinv, RinvT, s));
+  if (Rinv) SKLS_TRY(run_trinv(R, d, Rinv, RinvT, s, cholesky_block_inverses(q.W, d)));
   return SKLS_OK;
 }
 

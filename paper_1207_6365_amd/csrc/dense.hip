@@ -549,6 +549,20 @@ __global__ __launch_bounds__(256) void k_trinv_diag(const double* __restrict__ R
   }
 }
 
+// The same first level from inverses already at hand (those run_cholesky
+// keeps, computed by tri_inv_lds from the same block of R): block K of
+// Rinv's rows gets Kinv_K on the diagonal and zero elsewhere.
+__global__ __launch_bounds__(256) void k_trinv_place(const double* __restrict__ Kinv, int d,
+                                                     double* __restrict__ Rinv) {
+  const int K = blockIdx.x * kCB;
+  const int kb = (d - K) < kCB ? (d - K) : kCB;
+  const double* KK = Kinv + static_cast<size_t>(blockIdx.x) * kCB * kCB;
+  for (int i = 0; i < kb; ++i) {
+    double* row = Rinv + static_cast<size_t>(K + i) * d;
+    for (int j = threadIdx.x; j < d; j += 256) row[j] = (j >= K && j < K + kb) ? KK[i * kCB + (j - K)] : 0.0;
+  }
+}
+
 // One 64 x 64 tile of C = alpha A B (row-major, M x N, inner dimension K) on
 // the float64 matrix cores; A, B, C point at the sub-blocks.
 __device__ void gemm_tile64(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
@@ -761,7 +775,11 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
   return SKLS_OK;
 }
 
-size_t cholesky_scratch_doubles(int64_t d) { return static_cast<size_t>(d * d) + kCB * kCB + 8; }
+size_t cholesky_scratch_doubles(int64_t d) {
+  return static_cast<size_t>(d * d) + static_cast<size_t>(div_up(d, kCB)) * kCB * kCB + 8;
+}
+
+const double* cholesky_block_inverses(const double* scratch, int64_t d) { return scratch + d * d; }
 
 int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t* status, double* scratch,
                      hipStream_t s) {
@@ -769,22 +787,23 @@ int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t
   // sqrt(d * eps) * max |R_jj|; treat that as numerical rank deficiency.
   const double rtol = 4.0 * std::sqrt(static_cast<double>(d) * 2.220446049250313e-16);
   PhaseTimer pt("cholesky", s);
-  // scratch: W [d*d] | Kinv [kCB*kCB] | bad flag
+  // scratch: W [d*d] | inverses of the diagonal blocks [nb * kCB*kCB] | bad flag
   double* W = scratch;
   double* Kinv = scratch + d * d;
-  int32_t* bad = reinterpret_cast<int32_t*>(Kinv + kCB * kCB);
+  int32_t* bad = reinterpret_cast<int32_t*>(Kinv + div_up(d, kCB) * kCB * kCB);
   const int di = static_cast<int>(d);
   const unsigned g = static_cast<unsigned>(div_up(d * d, 256) < 4096 ? div_up(d * d, 256) : 4096);
   hipLaunchKernelGGL(k_copy_upper, dim3(g), dim3(256), 0, s, G, ldg, di, W, bad);
   SKLS_CHECK_LAUNCH();
   for (int K = 0; K < di; K += kCB) {
     const int kb = (di - K) < kCB ? (di - K) : kCB;
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, W, di, K, Kinv, bad);
+    double* KinvK = Kinv + static_cast<size_t>(K / kCB) * kCB * kCB;
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, W, di, K, KinvK, bad);
     SKLS_CHECK_LAUNCH();
     const int rest = di - K - kb;
     if (rest <= 0) break;
     const int nt = (rest + kCB - 1) / kCB;
-    hipLaunchKernelGGL(k_chol_trsm, dim3(nt), dim3(256), 0, s, W, di, K, Kinv);
+    hipLaunchKernelGGL(k_chol_trsm, dim3(nt), dim3(256), 0, s, W, di, K, KinvK);
     SKLS_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_chol_syrk, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, W, di, K);
     SKLS_CHECK_LAUNCH();
@@ -794,15 +813,20 @@ int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t
   return SKLS_OK;
 }
 
-// R^{-1} by doubling over diagonal blocks: inverses of the kCB-blocks, then
+// R^{-1} by doubling over diagonal blocks: inverses of the kCB-blocks (or
+// diag_inv, the ones run_cholesky kept for this R), then
 // levels b = kCB, 2 kCB, ... each merging neighbouring blocks with two
 // products on the matrix cores.  RinvT (d x d) serves as the product scratch
 // before it receives the transpose.
-int32_t run_trinv(const double* R, int64_t d, double* Rinv, double* RinvT, hipStream_t s) {
+int32_t run_trinv(const double* R, int64_t d, double* Rinv, double* RinvT, hipStream_t s, const double* diag_inv) {
   PhaseTimer pt("trinv", s);
   const int di = static_cast<int>(d);
   const int nb = static_cast<int>(div_up(d, kCB));
-  hipLaunchKernelGGL(k_trinv_diag, dim3(nb), dim3(256), 0, s, R, di, Rinv);
+  if (diag_inv != nullptr) {
+    hipLaunchKernelGGL(k_trinv_place, dim3(nb), dim3(256), 0, s, diag_inv, di, Rinv);
+  } else {
+    hipLaunchKernelGGL(k_trinv_diag, dim3(nb), dim3(256), 0, s, R, di, Rinv);
+  }
   SKLS_CHECK_LAUNCH();
   for (int b = kCB; b < di; b *= 2) {
     const unsigned merges = static_cast<unsigned>(div_up(d, 2 * static_cast<int64_t>(b)));

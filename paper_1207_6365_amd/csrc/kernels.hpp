@@ -36,7 +36,13 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
 int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t* status, double* scratch,
                      hipStream_t s);
 size_t cholesky_scratch_doubles(int64_t d);
-int32_t run_trinv(const double* R, int64_t d, double* Rinv, double* RinvT, hipStream_t s);
+// The inverses of R's diagonal 64 x 64 blocks that run_cholesky leaves in its
+// scratch (block J at J * 64^2, ld 64), valid until the scratch is reused.
+const double* cholesky_block_inverses(const double* scratch, int64_t d);
+// R^{-1} (and its transpose); diag_inv: the block inverses of this R kept by
+// run_cholesky, or NULL to compute them.
+int32_t run_trinv(const double* R, int64_t d, double* Rinv, double* RinvT, hipStream_t s,
+                  const double* diag_inv = nullptr);
 // y = op(M) x for a d x d row-major float64 M (op = identity).
 int32_t run_gemv(const double* M, int64_t d, const double* x, double* y, hipStream_t s);
 // x = Rinv (RinvT c): sketch-and-solve from the Gram column c = M^T v.

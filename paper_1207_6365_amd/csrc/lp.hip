@@ -499,7 +499,7 @@ int32_t factor_weighted(const LpWs& w, int64_t ns, int64_t d, const double* cw, 
     *bad = st;
     if (st) return SKLS_OK;
   }
-  return run_trinv(w.R, d, w.Rinv, w.RinvT, s);
+  return run_trinv(w.R, d, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, d));
 }
 
 // r = M x - y on the coreset; f = sum |r|^p, f1 = sum |r|, fy = sum |y|;
@@ -893,7 +893,7 @@ int32_t run_lp(const skls_matrix& A, const double* b, const LpPlan& P, double* x
       set_error("lp_regression: F A is numerically rank deficient");
       return SKLS_ERR_RANK;
     }
-    SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s));
+    SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, d)));
     SKLS_TRY(row_norm_estimates(A, w.Rinv, kg, P.seed, w.Pi2, w.T, w.Z, w.score, w.last, w.gs, s));
     hipLaunchKernelGGL(k_pow_rows, dim3(kRed), dim3(kT), 0, s, n, w.score, P.p / 2.0, w.lam, w.part);
     SKLS_CHECK_LAUNCH();

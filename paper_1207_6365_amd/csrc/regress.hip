@@ -166,7 +166,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
     set_error("multi_lstsq: the sketch S1 A is numerically rank deficient");
     return SKLS_ERR_RANK;
   }
-  SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s));
+  SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, d)));
   int64_t ns = 0;
   {
     PhaseTimer pt("multi_scores", s);
@@ -235,7 +235,7 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
       set_error("multi_lstsq: S A is numerically rank deficient (raise t_s)");
       return SKLS_ERR_RANK;
     }
-    SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s));
+    SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, d)));
     SKLS_TRY(gemm(true, d, dp, ns, 1.0, w.SAc, d, w.SBc, dp, w.C, dp, w.gs, s));
     SKLS_TRY(gemm(false, d, dp, d, 1.0, w.RinvT, d, w.C, dp, w.Yt, dp, w.gs, s));
     SKLS_TRY(gemm(false, d, dp, d, 1.0, w.Rinv, d, w.Yt, dp, Y, dp, w.gs, s));
