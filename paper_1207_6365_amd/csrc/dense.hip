@@ -557,9 +557,23 @@ __global__ __launch_bounds__(256) void k_trinv_place(const double* __restrict__ 
   const int K = blockIdx.x * kCB;
   const int kb = (d - K) < kCB ? (d - K) : kCB;
   const double* KK = Kinv + static_cast<size_t>(blockIdx.x) * kCB * kCB;
+  // the kb x kb block: a fixed count of loads per thread, all in flight
+  double v[kCB * kCB / 256];
+#pragma unroll
+  for (int u = 0; u < kCB * kCB / 256; ++u) {
+    const int e = u * 256 + threadIdx.x, i = e / kCB, j = e % kCB;
+    v[u] = (i < kb && j < kb) ? KK[e] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kCB * kCB / 256; ++u) {
+    const int e = u * 256 + threadIdx.x, i = e / kCB, j = e % kCB;
+    if (i < kb && j < kb) Rinv[static_cast<size_t>(K + i) * d + K + j] = v[u];
+  }
+  // zeros elsewhere in these rows
   for (int i = 0; i < kb; ++i) {
     double* row = Rinv + static_cast<size_t>(K + i) * d;
-    for (int j = threadIdx.x; j < d; j += 256) row[j] = (j >= K && j < K + kb) ? KK[i * kCB + (j - K)] : 0.0;
+    for (int j = threadIdx.x; j < d; j += 256)
+      if (j < K || j >= K + kb) row[j] = 0.0;
   }
 }
 
