@@ -111,6 +111,23 @@ def test_csr_blocks_match_oracle(sk, row64):
     _check(got, ref, MatrixOp(A), b, p, seed, x_unique=False)
 
 
+@pytest.mark.parametrize("p", [1.0, 1.5])
+def test_csr_with_empty_rows_matches_oracle(sk, p):
+    # every seventh row empty: its score is zero, so stage 1 never draws it,
+    # while stage 2 may through its residual share (the residual is -b_i)
+    A0, b, _ = W.lp_sparse(n=20000, d=13, k=4)
+    lens = np.diff(A0.row_ptr)
+    lens[3::7] = 0
+    keep = np.repeat(lens > 0, np.diff(A0.row_ptr))
+    A = W.CSR(A0.n, A0.d, np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), A0.col_idx[keep], A0.val[keep])
+    seed = 0xE0 + int(10 * p)
+    kw = dict(q=97, v=4, a=2, s1=500.0, s2=600.0)
+    ref = LP.lp_regression(A, b, p, seed, kw["q"], kw["v"], kw["a"], kw["s1"], kw["s2"])
+    assert not np.any(ref["rows1"] % 7 == 3)
+    got = sk.lp_regression(up_csr(A), up(b), p, seed, samples=True, **kw)
+    _check(got, ref, MatrixOp(A), b, p, seed, x_unique=p > 1.0)
+
+
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_narrow_storage_matches_oracle(sk, storage):
     A, b, _ = W.lp_dense(n=3000, d=16)
