@@ -28,6 +28,22 @@ def test_leverage_small_workload_csr(sk):
     assert np.max(np.abs(got - ref) / ref) <= 1e-5
 
 
+def test_leverage_csr_with_empty_rows(sk):
+    # every eleventh row empty: its score is exactly zero on both sides
+    A0, _, _ = W.lstsq_small()
+    lens = np.diff(A0.row_ptr)
+    lens[5::11] = 0
+    keep = np.repeat(lens > 0, np.diff(A0.row_ptr))
+    A = W.CSR(A0.n, A0.d, np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), A0.col_idx[keep], A0.val[keep])
+    seed, t, k = W.sketch_seed(0), 4000, 32
+    Pi2 = W.gaussian_matrix(7, A.d, k, scale=1 / np.sqrt(k))
+    got = sk.leverage_scores(up_csr(A), t, seed, up(Pi2)).cpu().numpy()
+    ref = O.leverage_approx(O.MatrixOp(A), seed, t, Pi2)
+    empty = lens == 0
+    assert np.all(got[empty] == 0.0) and np.all(ref[empty] == 0.0)
+    assert np.max(np.abs(got[~empty] - ref[~empty]) / ref[~empty]) <= 1e-5
+
+
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_leverage_dense_pareto_rows(sk, storage):
     n, d, t, k = 1 << 14, 64, 4096, 32

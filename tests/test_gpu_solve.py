@@ -53,6 +53,31 @@ def _small():
     return A, b, op, Ad, O.lstsq_exact(Ad, b)
 
 
+def _with_empty_rows(A, every, first):
+    """A copy of CSR A with rows first, first + every, ... emptied."""
+    lens = np.diff(A.row_ptr)
+    lens[first::every] = 0
+    keep = np.repeat(lens > 0, np.diff(A.row_ptr))
+    return W.CSR(A.n, A.d, np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), A.col_idx[keep], A.val[keep])
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+def test_lstsq_csr_with_empty_rows(sk, precision):
+    # every eleventh row empty: those rows add b_i^2 to the residual whatever x
+    A0, b, _ = W.lstsq_small()
+    A = _with_empty_rows(A0, 11, 5)
+    op = O.MatrixOp(A)
+    Ad = op.dense()
+    xs = O.lstsq_exact(Ad, b)
+    seed, t = W.sketch_seed(0), 4000
+    x_g, info = sk.lstsq(up_csr(A), up(b), t, seed, delta=1e-11, precision=precision)
+    x_o, _, _, _, ok_o = O.lstsq(op, b, seed, t, delta=1e-11)
+    assert ok_o and info["certified"] == 1
+    rho_g = O.residual_ratio(Ad, b, x_g.cpu().numpy(), xs)
+    assert abs(rho_g - O.residual_ratio(Ad, b, x_o, xs)) <= 1e-10
+    assert rho_g - 1.0 <= 1e-11
+
+
 def test_sketch_and_solve_parity_small_workload(sk):
     A, b, op, Ad, xs = _small()
     seed, t = W.sketch_seed(0), 4000
