@@ -57,6 +57,25 @@ def test_planted_sparse_matches_oracle(sk, row64):
     assert err >= dk * (1 - 1e-9)
 
 
+def test_empty_rows_and_columns_match_oracle(sk):
+    # the planted input with every ninth row and every seventh column emptied
+    A0 = W.planted_lowrank_sparse(n=3000, rank=8, density=0.04)
+    rows = np.repeat(np.arange(A0.n), np.diff(A0.row_ptr))
+    keep = (rows % 9 != 4) & (A0.col_idx % 7 != 2)
+    lens = np.bincount(rows[keep], minlength=A0.n)
+    A = W.CSR(A0.n, A0.d, np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), A0.col_idx[keep], A0.val[keep])
+    Ad = A.to_dense()
+    assert not np.any(Ad[4::9]) and not np.any(Ad[:, 2::7])
+    k, seed, t_r, t_s = 8, 0x4321, 64, 2048
+    ref = LR.low_rank(A, k, seed, t_r, t_s)
+    got = sk.low_rank(up_csr(A), k, seed, t_r=t_r, t_s=t_s)
+    assert got[3]["rows_sampled"] == int(np.count_nonzero(ref["counts"]))
+    assert not np.any(ref["counts"][4::9])
+    _check(got, ref, Ad)
+    L, Wm = got[0].cpu().numpy(), got[2].cpu().numpy()
+    assert np.max(np.abs(L[4::9])) <= 1e-12 and np.max(np.abs(Wm[2::7])) <= 1e-12
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_dense_matches_oracle(sk, storage):
     g = np.random.default_rng(11)

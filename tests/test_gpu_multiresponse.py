@@ -49,6 +49,19 @@ def test_sparse_small_workload(sk, row64):
     _check(sk, up_csr(A, row64=row64), A, B, 4000, 2500, W.sketch_seed(0))
 
 
+def test_sparse_with_empty_rows(sk):
+    # every eleventh row empty: zero score, never drawn
+    A0, _, _ = W.lstsq_small()
+    lens = np.diff(A0.row_ptr)
+    lens[5::11] = 0
+    keep = np.repeat(lens > 0, np.diff(A0.row_ptr))
+    A = W.CSR(A0.n, A0.d, np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), A0.col_idx[keep], A0.val[keep])
+    B = _rhs(A, 6, 3)
+    _, info = _check(sk, up_csr(A), A, B, 4000, 2500, W.sketch_seed(0))
+    ref = O.multi_response_lstsq(A, B, W.sketch_seed(0), 4000, 2500)
+    assert not np.any(ref["counts"][5::11])
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_dense_heavy_rows(sk, storage):
     A, _, _ = W.pareto_rows(n=1 << 14, d=48, storage="f32" if storage != "bf16" else "bf16")
