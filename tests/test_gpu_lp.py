@@ -128,6 +128,52 @@ def test_csr_with_empty_rows_matches_oracle(sk, p):
     _check(got, ref, MatrixOp(A), b, p, seed, x_unique=p > 1.0)
 
 
+def _check_stage2_valid(got, ref, op, b, p, seed, s2):
+    """Checks for inputs whose stage-1 fit is not unique (a flat set of l_1
+    minimisers): stage 1 as in _check; stage 2 must be the draw that the
+    section's rule gives at the GPU's own x_c, and the final fit optimal on
+    the GPU's coreset."""
+    x, info, sm = got
+    x, xc = _cpu(x), _cpu(sm["x_c"])
+    r1, w1, r2, w2 = (_cpu(sm[k]) for k in ("rows1", "w1", "rows2", "w2"))
+    tol = FIT_TOL[p]
+    assert np.array_equal(r1, ref["rows1"])
+    assert np.allclose(w1, ref["w1"], rtol=1e-12, atol=0)
+    fg = _coreset_obj(op, b, r1, w1, xc, p)
+    fo = _coreset_obj(op, b, ref["rows1"], ref["w1"], ref["x_c"], p)
+    assert abs(fg - fo) <= tol * fo, (fg, fo)
+    lam = ref["scores"] ** (p / 2.0)
+    rp = np.abs(op.matvec(xc) - b) ** p
+    q = np.minimum(1.0, s2 * np.maximum(lam / lam.sum(), rp / rp.sum()))
+    u2 = LP.stream_uniforms(seed, LP.STAGE2_SALT, op.n)
+    diff = np.setxor1d(r2, np.nonzero(u2 < q)[0])
+    assert np.all(np.abs(u2[diff] - q[diff]) <= 1e-6 * q[diff]), diff
+    if diff.size == 0:
+        assert np.allclose(w2, q[r2] ** (-1.0 / p), rtol=1e-9, atol=0)
+    xo = LP.solve_weighted(op.rows(r2), b[r2], w2, p)
+    fg2 = _coreset_obj(op, b, r2, w2, x, p)
+    fo2 = _coreset_obj(op, b, r2, w2, xo, p)
+    assert abs(fg2 - fo2) <= tol * fo2, (fg2, fo2)
+    assert info["coreset_obj"] == pytest.approx(fg2, rel=1e-10)
+    assert info["obj"] == pytest.approx(float(np.sum(np.abs(op.matvec(x) - b) ** p)), rel=1e-10)
+    assert info["converged"] == 1
+
+
+@pytest.mark.parametrize("p", [1.0, 1.5])
+def test_one_column_matches_oracle(sk, p):
+    # d = 1: R is 1 x 1 and the fits are weighted medians (p = 1) or their
+    # l_p analogues.  A weighted median can be any point of an interval, so
+    # at p = 1 the stage-2 draw is checked against the GPU's own x_c
+    A, b, _ = W.lp_sparse(n=6000, d=1, k=1)
+    seed, kw = 0xD1 + int(10 * p), dict(q=64, v=4, a=1, s1=200.0, s2=200.0)
+    ref = LP.lp_regression(A, b, p, seed, kw["q"], kw["v"], kw["a"], kw["s1"], kw["s2"])
+    got = sk.lp_regression(up_csr(A), up(b), p, seed, samples=True, **kw)
+    if p == 1.0:
+        _check_stage2_valid(got, ref, MatrixOp(A), b, p, seed, kw["s2"])
+    else:
+        _check(got, ref, MatrixOp(A), b, p, seed)
+
+
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_narrow_storage_matches_oracle(sk, storage):
     A, b, _ = W.lp_dense(n=3000, d=16)
