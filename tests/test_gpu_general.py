@@ -36,6 +36,25 @@ def test_csr_integer_bit_exact(sk, variant):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
+def test_csr_integer_ragged_and_empty_rows_bit_exact(sk, variant):
+    # row lengths 0..12 (every fifth row empty) over d = 37 columns, integer
+    # values: every copy's additions are exact, so the result is bit-exact
+    A0, b = W.sketch_csr_int(n=30011, d=37, k=12)
+    g = np.random.default_rng(5)
+    lens0 = np.diff(A0.row_ptr)
+    lens = np.minimum(lens0, g.integers(0, 13, A0.n))
+    lens[::5] = 0
+    pos = np.arange(A0.nnz) - np.repeat(A0.row_ptr[:-1], lens0)
+    keep = pos < np.repeat(lens, lens0)
+    A = W.CSR(A0.n, A0.d, np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), A0.col_idx[keep], A0.val[keep])
+    seed, q, v, a = 0x5EED0007, 97, 8, 4
+    SA, Sb = sk.sketch_general(up_csr(A), q, v, a, seed, b=up(b), variant=variant)
+    assert np.array_equal(SA.cpu().numpy().astype(np.float64), O.sketch_generalized(A, seed, q, v, a))
+    refb = O.sketch_generalized(b[:, None].astype(np.float64), seed, q, v, a)[:, 0]
+    assert np.array_equal(Sb.cpu().numpy().astype(np.float64), refb)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("out", [torch.float64, torch.float32])
 def test_csr_float_within_sum_bound(sk, variant, out):
     A = W.csr_uniform_rows(41, 30011, 96, 12)
