@@ -35,9 +35,11 @@ Steps, in the section's order:
    weighted objective.
 
 The weighted sampled problems are solved exactly: ``p = 2`` by Householder
-least squares, ``p = 1`` as a linear program (SciPy's HiGHS), other ``p`` by
-a convex minimiser from the ``p = 2`` start (SciPy's trust-region Newton with
-the exact gradient and Hessian), polished to a vanishing gradient.
+least squares, ``p = 1`` as a linear program (SciPy's HiGHS; its
+interior-point method with crossover where the default method stops
+short), other ``p`` by a convex minimiser from the ``p = 2`` start (SciPy's
+trust-region Newton with the exact gradient and Hessian), polished to a
+vanishing gradient.
 """
 
 from __future__ import annotations
@@ -118,12 +120,16 @@ def _solve_l1(M: np.ndarray, y: np.ndarray) -> np.ndarray:
     Ms = csr_matrix(M)
     I = eye(s, format="csr")
     A_ub = bmat([[Ms, -I], [-Ms, -I]], format="csr")
-    res = linprog(np.r_[np.zeros(d), np.ones(s)], A_ub=A_ub, b_ub=np.r_[y, -y],
-                  bounds=[(None, None)] * d + [(0, None)] * s, method="highs",
-                  options={"primal_feasibility_tolerance": 1e-10, "dual_feasibility_tolerance": 1e-10})
-    if res.status != 0:
-        raise RuntimeError(f"linprog: {res.message}")
-    return res.x[:d]
+    # HiGHS's default method can stop with an unknown status at these
+    # tolerances on larger fits; its interior-point method with crossover
+    # then returns an optimal vertex of the same linear program
+    for method in ("highs", "highs-ipm"):
+        res = linprog(np.r_[np.zeros(d), np.ones(s)], A_ub=A_ub, b_ub=np.r_[y, -y],
+                      bounds=[(None, None)] * d + [(0, None)] * s, method=method,
+                      options={"primal_feasibility_tolerance": 1e-10, "dual_feasibility_tolerance": 1e-10})
+        if res.status == 0:
+            return res.x[:d]
+    raise RuntimeError(f"linprog: {res.message}")
 
 
 def _solve_l2(M: np.ndarray, y: np.ndarray) -> np.ndarray:

@@ -98,6 +98,28 @@ def test_l1_solver_matches_vertex_brute_force():
         assert LP.lp_objective(M, y, x, 1.0) == pytest.approx(best, rel=1e-9)
 
 
+def test_l1_solver_on_a_fit_where_the_default_method_stops_short():
+    # the stage-1 fit of a dense n = 12000, d = 150 input with s1 = 1500 (about
+    # 1500 x 150), on which HiGHS's default method stops with an unknown
+    # status at the oracle's 1e-10 tolerances: the returned x is an optimal
+    # vertex (at least d residuals vanish) that no small perturbation improves
+    A, b, _ = W.lp_dense(n=12000, d=150)
+    seed = 0x3150 + 10
+    R = LP.condition(A, seed, 1200, 8, 1)
+    lam = np.sqrt(LP.row_norm_estimates(A, R, seed, 32))
+    rows, w = LP.bernoulli_sample(np.minimum(1.0, 1500.0 * lam / lam.sum()), 1.0,
+                                  LP.stream_uniforms(seed, SAMPLE_SALT, A.shape[0]))
+    M, y = A[rows] * w[:, None], b[rows] * w
+    x = LP.solve_weighted(M, y, np.ones(rows.size), 1.0)
+    r = M @ x - y
+    assert np.count_nonzero(np.abs(r) <= 1e-9 * np.max(np.abs(y))) >= M.shape[1]
+    f = LP.lp_objective(M, y, x, 1.0)
+    g = np.random.default_rng(8)
+    for _ in range(20):
+        dx = g.standard_normal(x.size) * 1e-6 * np.max(np.abs(x))
+        assert LP.lp_objective(M, y, x + dx, 1.0) >= f * (1 - 1e-12)
+
+
 def test_l2_solver_is_weighted_least_squares():
     g = np.random.default_rng(4)
     M, y, w = g.standard_normal((50, 5)), g.standard_normal(50), g.random(50) + 0.5
