@@ -100,6 +100,17 @@ def test_several_factor_blocks_match_oracle(sk, p):
     _check(got, ref, MatrixOp(A), b, p, seed, x_unique=p > 1.0)
 
 
+def test_wide_l1_fit_matches_oracle(sk):
+    # d = 150 (factor blocks 64 + 64 + 22) with s1 = s2 = 1500: the oracle's
+    # stage-1 fit is one where HiGHS's default method stops short and its
+    # interior-point method with crossover supplies the optimal vertex
+    A, b, _ = W.lp_dense(n=12000, d=150)
+    seed, p, kw = 0x3150 + 10, 1.0, dict(q=1200, v=8, a=1, s1=1500.0, s2=1500.0)
+    ref = LP.lp_regression(A, b, p, seed, kw["q"], kw["v"], kw["a"], kw["s1"], kw["s2"])
+    got = sk.lp_regression(up(A), up(b), p, seed, samples=True, **kw)
+    _check(got, ref, MatrixOp(A), b, p, seed, x_unique=False)
+
+
 @pytest.mark.parametrize("row64", [False, True])
 def test_csr_blocks_match_oracle(sk, row64):
     # several blocks of F with a short last block; sizes not multiples of any tile
