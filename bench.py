@@ -91,49 +91,6 @@ def stored_traffic(kernel: str, source: str):
     return float(fields["traffic_bytes"])
 
 
-def segment_ceiling(dev, sync, n_rows: int):
-    """Rate of random 64- and 128-byte segment reads over a 2 GiB buffer
-    (the probe kernel of paper_1207_6365_amd/probe), and the floor it puts
-    under a CSR sketch that reads one 64-byte segment of columns and one of
-    values per row (16 nonzeros of 4 bytes)."""
-    import torch
-
-    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1207_6365_amd", "probe", "libskls_probe.so"))
-    lib.skls_probe_segments.restype = ctypes.c_int
-    lib.skls_probe_segments.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
-                                        ctypes.c_void_p, ctypes.c_void_p]
-    foot = 1 << 31
-    data = torch.zeros(foot, dtype=torch.uint8, device=dev)
-    sink = torch.zeros(1, dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream(dev)
-    g = torch.Generator(device=dev)
-    g.manual_seed(1)
-    out = {}
-    for seg in (64, 128):
-        nseg = (256 << 20) // seg  # 256 MiB of segments per launch
-        idx = torch.randint(0, foot // seg, (nseg,), dtype=torch.int32, device=dev, generator=g)
-        run = lambda: lib.skls_probe_segments(data.data_ptr(), idx.data_ptr(), nseg, seg, sink.data_ptr(),  # noqa: E731
-                                              ctypes.c_void_p(stream.cuda_stream))
-        if run() != 0:
-            raise RuntimeError("segment probe launch failed")
-        sync()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(5):
-            run()
-        e1.record(stream)
-        sync()
-        sec = e0.elapsed_time(e1) * 1e-3 / 5
-        out[f"gseg_per_s_{seg}B"] = nseg / sec / 1e9
-        out[f"useful_GBps_{seg}B"] = nseg * seg / sec / 1e9
-        del idx
-    out["csr_sketch_floor_ms"] = 2 * n_rows / (out["gseg_per_s_64B"] * 1e9) * 1e3
-    del data
-    torch.cuda.empty_cache()
-    return out
-
-
 def oracle_rows(log):
     """The oracle on bounded samples of the other workloads, one thread (BLAS
     held to one thread as well): seconds per call and the sample's size, as
@@ -203,6 +160,23 @@ def time_steps(fn, steps, warmup, sync):
     return e0.elapsed_time(e1) / steps
 
 
+SPIN_CYCLES = 500_000  # device clock cycles of the spin kernel queued before each profiled call
+
+
+def profile_steps(fn, steps, sync):
+    """Call fn `steps` times with the library's phase events on, each call
+    queued behind a spin kernel, so that the host has enqueued the whole call
+    (kernels and phase events) before the GPU reaches it: each phase's event
+    pair then brackets its kernels only, not the host's launch gaps."""
+    import torch
+
+    sync()
+    for _ in range(steps):
+        torch.cuda._sleep(SPIN_CYCLES)
+        fn()
+    sync()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -262,13 +236,11 @@ def main():
             sk._lib.check(st)
 
     log(f"timing {args.steps} sketch steps after {args.warmup} warm-up steps")
+    ms_step = time_steps(step, args.steps, args.warmup, sync)
     lib.skls_profile_enable(1)
-    ms = time_steps(step, args.steps, args.warmup, sync)
+    profile_steps(step, args.steps, sync)
     phases = profile_phases(sk)
     lib.skls_profile_enable(0)
-    # steady-state step time without the per-phase events
-    ms_clean = time_steps(step, args.steps, 2, sync)
-    ms_step = min(ms, ms_clean)
 
     alg_bytes = 4 * nnz + 4 * nnz + 4 * (A.n + 1) + 4 * t * A.d  # val + col + row_ptr + write S A
     kname = {"atomic": "k_sketch_csr_atomic", "sorted": "k_sketch_csr_sorted"}.get(args.variant, "k_sketch_csr_binned")
@@ -302,13 +274,6 @@ def main():
     }
     if plan_cnt:
         result["phases_ms"]["sketch_plan"] = plan_tot / plan_cnt
-    if args.only is None:
-        # the rate of random 64-byte segment reads bounds the CSR sketch: each
-        # row's columns and values are two such segments at unrelated addresses
-        log("random-segment read rate (probe kernel, 2 GiB buffer)")
-        ceil = segment_ceiling(dev, sync, A.n)
-        ceil["sketch_frac_of_floor"] = ceil["csr_sketch_floor_ms"] / k_ms
-        result["segment_ceiling"] = ceil
 
     if not args.no_extras and want("general"):
         # generalized sparse embedding (Section 5) of the same input: q groups,
@@ -345,8 +310,9 @@ def main():
                 sk._lib.check(lib.skls_sketch(ctypes.byref(dm), None, 0, t, seed, None, variant, SA.data_ptr(), None, 1,
                                               wsd.data_ptr(), wsd.numel(), stream))
 
-            lib.skls_profile_enable(1)
             dms = time_steps(dstep, max(args.steps // 2, 5), 3, sync)
+            lib.skls_profile_enable(1)
+            profile_steps(dstep, max(args.steps // 2, 5), sync)
             dph = profile_phases(sk)
             lib.skls_profile_enable(0)
             dbytes = 4 * D.size + 4 * t * D.shape[1]
@@ -390,7 +356,6 @@ def main():
                 b3g = torch.from_numpy(b3).to(dev)
                 x, info = sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision)  # warm-up
                 sync()
-                lib.skls_profile_enable(1)
                 t0 = time.perf_counter()
                 infos = []
                 for _ in range(args.lstsq_steps):
@@ -398,6 +363,10 @@ def main():
                     infos.append(info)
                 sync()
                 el = (time.perf_counter() - t0) / args.lstsq_steps
+                # kernel phases from one more solve with the phase events on
+                lib.skls_profile_enable(1)
+                sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision)
+                sync()
                 ph = profile_phases(sk)
                 lib.skls_profile_enable(0)
                 key = f"{storage}_{precision}"
@@ -462,13 +431,14 @@ def main():
             Pi2 = torch.from_numpy(np.random.default_rng(7).standard_normal((d3, 32)) / np.sqrt(32.0)).to(dev)
             sk.leverage_scores(A3g, t3, seed, Pi2)
             sync()
-            lib.skls_profile_enable(1)
             t0 = time.perf_counter()
             reps = 3
             for _ in range(reps):
                 sk.leverage_scores(A3g, t3, seed, Pi2)
             sync()
             el = (time.perf_counter() - t0) / reps
+            lib.skls_profile_enable(1)
+            profile_steps(lambda: sk.leverage_scores(A3g, t3, seed, Pi2), 1, sync)
             ph = profile_phases(sk)
             lib.skls_profile_enable(0)
             lc, lt = ph.get("leverage", (1, float("nan")))
@@ -494,13 +464,15 @@ def main():
             lr_seed = W.sketch_seed(0)
             sk.low_rank(A4g, 32, lr_seed, t_r=512)  # warm-up
             sync()
-            lib.skls_profile_enable(1)
             reps = 3
             t0 = time.perf_counter()
             for _ in range(reps):
                 _, _, _, linfo = sk.low_rank(A4g, 32, lr_seed, t_r=512)
             sync()
             el = (time.perf_counter() - t0) / reps
+            lib.skls_profile_enable(1)
+            sk.low_rank(A4g, 32, lr_seed, t_r=512)
+            sync()
             ph = profile_phases(sk)
             lib.skls_profile_enable(0)
             result["low_rank"] = {
@@ -530,13 +502,15 @@ def main():
                 lp_seed = W.sketch_seed(6)
                 sk.lp_regression(A6g, b6g, pp, lp_seed)  # warm-up
                 sync()
-                lib.skls_profile_enable(1)
                 reps = 3
                 t0 = time.perf_counter()
                 for _ in range(reps):
                     _, pinfo = sk.lp_regression(A6g, b6g, pp, lp_seed)
                 sync()
                 el = (time.perf_counter() - t0) / reps
+                lib.skls_profile_enable(1)
+                sk.lp_regression(A6g, b6g, pp, lp_seed)
+                sync()
                 ph = profile_phases(sk)
                 lib.skls_profile_enable(0)
                 res[f"p{pp:g}"] = {

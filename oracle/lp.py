@@ -49,6 +49,7 @@ from types import SimpleNamespace
 import numpy as np
 
 from .hashing import splitmix64
+from .leverage import leverage_approx
 from .linalg import apply_qt, check_rank, householder_qr, solve_upper
 from .lowrank import SAMPLE_SALT, sign_projection
 from .operator import MatrixOp
@@ -93,11 +94,11 @@ def condition(A, seed: int, q: int, v: int, a: int, w: int = 0) -> np.ndarray:
 
 
 def row_norm_estimates(A, R: np.ndarray, seed: int, k_g: int) -> np.ndarray:
-    """Squared row norms of ``A R^{-1} Pi2`` (step 3)."""
+    """Squared row norms of ``A R^{-1} Pi2`` (step 3): the Section 6
+    estimate of :func:`oracle.leverage.leverage_approx` with the given ``R``
+    and the sign matrix ``Pi2``."""
     op = A if isinstance(A, MatrixOp) else MatrixOp(A)
-    T = solve_upper(R, sign_projection(seed, op.d, k_g))
-    Z = op.matmat(T)
-    return (Z * Z).sum(axis=1)
+    return leverage_approx(op, 0, 0, sign_projection(seed, op.d, k_g), R=R)
 
 
 def bernoulli_sample(prob: np.ndarray, p: float, u: np.ndarray):

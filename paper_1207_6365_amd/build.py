@@ -12,9 +12,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libskls.so")
-# measurement aid used by bench.py (random-segment read rate), not the library
-PROBE_SRC = os.path.join(HERE, "probe", "segments.hip")
-PROBE_LIB = os.path.join(HERE, "probe", "libskls_probe.so")
 SOURCES = ["api.cpp", "profile.cpp", "sketch.hip", "dense.hip", "lsqr.hip", "leverage.hip", "learned.hip", "lowrank.hip", "regress.hip", "lp.hip"]
 ARCH = "gfx950"
 
@@ -71,12 +68,6 @@ def build(verbose: bool = True, jobs: int = 6) -> str:
     tmp = LIB + ".tmp"
     subprocess.run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], check=True)
     os.replace(tmp, LIB)
-    ptmp = PROBE_LIB + ".tmp"
-    pr = subprocess.run([cc, *flags(), "-shared", "-o", ptmp, PROBE_SRC], stdout=subprocess.PIPE,
-                        stderr=subprocess.STDOUT)
-    if pr.returncode != 0:
-        raise RuntimeError("hipcc failed on the probe:\n" + pr.stdout.decode(errors="replace"))
-    os.replace(ptmp, PROBE_LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f}s", file=sys.stderr)
     return LIB

@@ -195,3 +195,79 @@ def test_rank_deficient_input_is_rejected():
         LP.lp_regression(A, b, 1.0, 1, 16, 4, 1, s1=100, s2=100)
     with pytest.raises(ValueError):
         LP.lp_regression(A, b, 0.5, 1, 16, 4, 1, s1=100, s2=100)
+
+
+def _exact_r(Ad):
+    # R of A's own QR by LAPACK (non-negative diagonal): A R^-1 is then an
+    # orthonormal basis Q of the column space of A
+    R = np.linalg.qr(Ad, mode="r")
+    return R * np.sign(np.diag(R))[:, None]
+
+
+def test_row_norm_estimates_sum_to_the_squared_frobenius_norm_of_pi2():
+    # with the exact R, A R^-1 = Q has orthonormal columns, so the squared
+    # row norms of Q Pi2 sum to ||Q Pi2||_F^2 = ||Pi2||_F^2 = d for a sign
+    # matrix with entries +-1/sqrt(k) (Section 9 row-norm estimates through
+    # Section 6's Pi2).  R^-T in place of R^-1, unsquared norms, or A in
+    # place of A R^-1 all break the identity.
+    rng = np.random.default_rng(11)
+    n, d = 400, 7
+    Ad = rng.standard_normal((n, d)) * np.exp(rng.standard_normal(n))[:, None]
+    Ad[:, 3] *= 50.0
+    R = _exact_r(Ad)
+    for seed, k in [(1, 8), (2, 32), (3, 5)]:
+        lev = LP.row_norm_estimates(Ad, R, seed, k)
+        assert lev.shape == (n,)
+        assert np.all(lev >= 0)
+        assert lev.sum() == pytest.approx(d, rel=1e-12)
+
+
+def test_row_norm_estimates_are_unbiased_for_the_leverage_scores():
+    # E over the signs of ||e_i^T Q Pi2||^2 = ||Q_i||^2 = u_i (LAPACK Q),
+    # with variance 2 (||z||^4 - ||z||_4^4) / k for z = Q_i (independent
+    # +-1/sqrt(k) entries); the mean over many seeds lies within 5 standard
+    # errors for every row
+    rng = np.random.default_rng(12)
+    n, d, k, reps = 60, 5, 4, 3000
+    Ad = rng.standard_normal((n, d)) * np.exp(rng.standard_normal(n))[:, None]
+    R = _exact_r(Ad)
+    Q = np.linalg.qr(Ad)[0]
+    u = (Q * Q).sum(axis=1)
+    var = 2.0 * (u ** 2 - (Q ** 4).sum(axis=1)) / k
+    acc = np.zeros(n)
+    for s in range(reps):
+        acc += LP.row_norm_estimates(Ad, R, 1000 + s, k)
+    mean = acc / reps
+    se = np.sqrt(var / reps) + 1e-15
+    assert np.all(np.abs(mean - u) <= 5 * se)
+
+
+def test_row_norm_estimates_on_csr_match_a_dense_evaluation():
+    # A R^-1 Pi2 evaluated by LAPACK's inverse and a dense product, for a
+    # sketched R and the sign matrix drawn from the same stream
+    from oracle.lowrank import sign_projection
+
+    A = _small_csr(n=500, d=9, k=4, seed=13)
+    Ad = A.to_dense().astype(np.float64)
+    R = LP.condition(A, 77, 16, 4, 1)
+    Z = Ad @ np.linalg.inv(R) @ sign_projection(5, 9, 16)
+    assert np.allclose(LP.row_norm_estimates(A, R, 5, 16), (Z * Z).sum(axis=1), rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("p", [1.0, 1.5, 3.0])
+def test_stage1_probabilities_follow_the_p_th_power_of_the_l2_estimates(p):
+    # Section 9: the l_p norm of row i of A U is estimated by the l_2 norm of
+    # row i of A U Pi2, so stage 1 keeps row i with probability
+    # min(1, s1 * e_i^p / sum_j e_j^p), e_i = ||(A R^-1 Pi2)_i||_2 (here
+    # evaluated with LAPACK's inverse, independently of the oracle's solves)
+    from oracle.lowrank import sign_projection
+
+    rng = np.random.default_rng(14)
+    n, d = 800, 6
+    Ad = rng.standard_normal((n, d)) * np.exp(rng.standard_normal(n))[:, None]
+    b = Ad @ rng.standard_normal(d) + rng.laplace(0, 0.1, n)
+    seed, s1 = 0x1234, 200.0
+    out = LP.lp_regression(Ad, b, p, seed, 16, 4, 1, s1, s1)
+    e = np.linalg.norm(Ad @ np.linalg.inv(out["R"]) @ sign_projection(seed, d, 32), axis=1)
+    want = np.minimum(1.0, s1 * e ** p / np.sum(e ** p))
+    assert np.allclose(out["pi"], want, rtol=1e-9, atol=1e-15)

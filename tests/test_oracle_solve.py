@@ -90,20 +90,29 @@ def test_lsqr_and_richardson_agree():
 
 
 def test_richardson_contraction_factor():
-    # error in y contracts by exactly max|1 - sigma^2| per step along the
-    # worst singular direction (Section 7.7; the factor exceeds 1 once some
-    # singular value of M passes sqrt(2))
+    # one step of oracle.richardson contracts the error in y = R x by exactly
+    # |1 - sigma^2| along the singular direction of M = A R^-1 with value
+    # sigma (Section 7.7; the factor exceeds 1 once some singular value of M
+    # passes sqrt(2)).  M = U diag(sig) is built with known singular values
+    # and A = M R for an arbitrary well-conditioned upper-triangular R, so a
+    # step through R^-T where R^-1 is meant (or the reverse) fails.
     n, d = 40, 3
     U, _ = np.linalg.qr(_rng(4).standard_normal((n, d)))
     sig = np.array([0.9, 1.0, 1.2])
-    A = U * sig  # M = A when R = I
+    M = U * sig
+    R = np.triu(_rng(8).standard_normal((d, d))) + 3.0 * np.eye(d)
+    A = M @ R
     b = _rng(5).standard_normal(n)
     xs = O.lstsq_exact(A, b)
-    x = xs + np.array([0.0, 0.0, 1.0])  # error along sigma = 1.2
-    r = b - A @ x
-    x_next = x + A.T @ r
-    ratio = np.linalg.norm(A @ (x_next - xs)) / np.linalg.norm(A @ (x - xs))
-    assert ratio == pytest.approx(abs(1 - 1.2 ** 2), rel=1e-10)
+    for j, s in enumerate(sig):
+        x = xs + np.linalg.solve(R, np.eye(d)[j])  # error e_j in y = R x
+        x1, it, ok, _ = O.richardson(A, b, x, R, delta=1e-300, max_iter=1)
+        assert it == 1 and not ok
+        ratio = np.linalg.norm(A @ (x1 - xs)) / np.linalg.norm(A @ (x - xs))
+        assert ratio == pytest.approx(abs(1 - s ** 2), rel=1e-9)
+        x2, _, _, _ = O.richardson(A, b, x, R, delta=1e-300, max_iter=2)
+        ratio2 = np.linalg.norm(A @ (x2 - xs)) / np.linalg.norm(A @ (x - xs))
+        assert ratio2 == pytest.approx((1 - s ** 2) ** 2, rel=1e-8)
 
 
 def test_zero_iterations_when_preconditioner_is_exact():
@@ -124,3 +133,30 @@ def test_lstsq_driver_on_sparse_input():
     assert ok
     xs = O.lstsq_exact(op.dense(), b)
     assert O.residual_ratio(op.dense(), b, x, xs) - 1 <= 1e-10
+
+
+@pytest.mark.parametrize("delta", [1e-1, 1e-3, 1e-6])
+def test_certificate_is_tight_at_the_smallest_singular_value(delta):
+    # The stopping rule certifies ratio <= 1 + delta whenever sigma_min(M) >=
+    # sigma_lb (M = A R^-1).  With sigma_min(M) = sigma_lb exactly and the
+    # error of x along that singular direction, ||M^T r|| / ||r|| equals the
+    # threshold exactly when the ratio equals 1 + delta (Pythagorean identity
+    # of the regression residual), so a point just inside is certified and a
+    # point just outside is not.
+    n, d, slb = 30, 3, 0.5
+    U, _ = np.linalg.qr(_rng(21).standard_normal((n, d + 1)))
+    sig = np.array([slb, 1.0, 1.3])
+    M = U[:, :d] * sig
+    R = np.triu(_rng(22).standard_normal((d, d))) + 2.0 * np.eye(d)
+    A = M @ R
+    rstar = 0.7 * U[:, d]                    # orthogonal to the range of A
+    c = _rng(23).standard_normal(d)
+    b = U[:, :d] @ c + rstar
+    xs = np.linalg.solve(R, c / sig)         # A xs = U c
+    for rel, want in ((1 - 1e-7, True), (1 + 1e-7, False)):
+        rho = (1 + delta) * rel
+        eps = np.linalg.norm(rstar) * np.sqrt(rho ** 2 - 1) / slb
+        x0 = xs + np.linalg.solve(R, eps * np.eye(d)[0])
+        assert O.residual_ratio(A, b, x0, xs) == pytest.approx(rho, rel=1e-12)
+        _, it, ok, _ = O.richardson(A, b, x0, R, delta=delta, sigma_lb=slb, max_iter=0)
+        assert it == 0 and ok is want
