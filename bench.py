@@ -274,6 +274,24 @@ def main():
     }
     if plan_cnt:
         result["phases_ms"]["sketch_plan"] = plan_tot / plan_cnt
+    # the apply alone, with the bucket plan of these row pointers built once
+    # and reused (a matrix whose values or columns change but whose rows keep
+    # their lengths reuses it)
+    hplan = sk.sketch_plan(Ag, t, seed, variant=args.variant)
+    hdesc, hbuf = hplan.desc, hplan.buf
+
+    def hstep():
+        st = lib.skls_sketch_planned(ctypes.byref(mat), None, 0, None, SA.data_ptr(), None, ctypes.byref(hdesc),
+                                     hbuf.data_ptr(), hbuf.numel(), stream)
+        if st != 0:
+            sk._lib.check(st)
+
+    hms = time_steps(hstep, args.steps, args.warmup, sync)
+    result["reused_plan"] = {"ms_per_step": hms, "nnz_per_s": nnz / (hms * 1e-3),
+                             "frac": (alg_bytes - 4 * (A.n + 1)) / (hms * 1e-3) / HBM_PEAK,
+                             "note": "apply only; algorithmic bytes without the row pointers, which only the "
+                                     "plan reads"}
+    del hplan, hbuf
 
     if not args.no_extras and want("general"):
         # generalized sparse embedding (Section 5) of the same input: q groups,
@@ -297,6 +315,7 @@ def main():
     del Ag
 
     # ------------------------------------------------------------ extras
+    small_run = None
     if not args.no_extras:
         if want("dense"):
             log("dense float32 variant (n=2^20, d=256)")
@@ -317,10 +336,25 @@ def main():
             lib.skls_profile_enable(0)
             dbytes = 4 * D.size + 4 * t * D.shape[1]
             dk = dph.get("sketch_apply", (1, float("nan")))
+            # the same sketch with the bucket plan built once and reused: the
+            # plan depends only on (seed, n, t), so every dense matrix with
+            # these rows can share it
+            plan = sk.sketch_plan(Dg, t, seed, variant=args.variant)
+            pdesc, pbuf = plan.desc, plan.buf
+
+            def pstep():
+                sk._lib.check(lib.skls_sketch_planned(ctypes.byref(dm), None, 0, None, SA.data_ptr(), None,
+                                                      ctypes.byref(pdesc), pbuf.data_ptr(), pbuf.numel(), stream))
+
+            pms = time_steps(pstep, max(args.steps // 2, 5), 3, sync)
             result["dense"] = {"entries_per_s": D.size / (dms * 1e-3), "ms_per_step": dms,
                                "kernel_frac": dbytes / (dk[1] / max(dk[0], 1) * 1e-3) / HBM_PEAK,
-                               "step_frac": dbytes / (dms * 1e-3) / HBM_PEAK}
-            del Dg, D
+                               "step_frac": dbytes / (dms * 1e-3) / HBM_PEAK,
+                               "phases_ms": {k: v[1] / max(v[0], 1) for k, v in dph.items()},
+                               "reused_plan": {"entries_per_s": D.size / (pms * 1e-3), "ms_per_step": pms,
+                                               "step_frac": dbytes / (pms * 1e-3) / HBM_PEAK,
+                                               "plan_bytes": int(pbuf.numel())}}
+            del Dg, D, plan, pbuf
 
         if want("small"):
             log("small sparse regression: sketch-and-solve, n=20000 d=20 4 nnz/row float64, t=4000")
@@ -338,8 +372,9 @@ def main():
             sync()
             el = (time.perf_counter() - t0) / reps
             result["lstsq_small"] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
-                                     "note": "sketch-and-solve only (no LSQR), launch-bound; parity with the oracle is "
-                                             "in the tests"}
+                                     "note": "sketch-and-solve only (no LSQR), launch-bound; its residual ratio "
+                                             "against the oracle's is in cpu_baseline.parity"}
+            small_run = (A1, b1, x1.cpu().numpy())
             del A1g, b1g
 
     # ------------------------------------------------------------ least squares
@@ -612,6 +647,19 @@ def main():
                                   "host_cpus": os.cpu_count()}
         if args.only is None and not args.no_extras:
             result["cpu_baseline"]["rows"] = oracle_rows(log)
+        if small_run is not None:
+            # the small regression's sketch-and-solve on the GPU against the
+            # oracle's on the same seeded input: residual ratios to the exact
+            # least-squares residual
+            A1, b1, x1h = small_run
+            Ad1 = O.MatrixOp(A1).dense()
+            xs1 = O.lstsq_exact(Ad1, b1)
+            xo1 = O.sketch_and_solve(A1, b1, seed, 4000)[0]
+            rg, ro = O.residual_ratio(Ad1, b1, x1h, xs1), O.residual_ratio(Ad1, b1, xo1, xs1)
+            result["cpu_baseline"]["parity"] = {
+                "lstsq_small": {"rho_minus_1_gpu": rg - 1.0, "rho_minus_1_oracle": ro - 1.0, "abs_diff": abs(rg - ro),
+                                "x_rel_diff": float(np.linalg.norm(x1h - xo1) / np.linalg.norm(xo1)),
+                                "x_rel_err_gpu": float(np.linalg.norm(x1h - xs1) / np.linalg.norm(xs1))}}
     print(json.dumps(result), flush=True)
 
 

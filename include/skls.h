@@ -149,6 +149,63 @@ SKLS_API int32_t skls_sketch(const skls_matrix* A, const void* b, int32_t b_dtyp
                     size_t ws_bytes, void* stream);
 
 /*
+ * The same sketch of a block of rows that starts at global row `row_start`:
+ * row i of A is hashed as row row_start + i (h, sign and, for CSR, nothing
+ * else changes), so the sketches of consecutive row blocks A_1, A_2, ... of a
+ * taller matrix, each with its own row_start, sum to the sketch of the whole
+ * (S A = sum_g S A_g: Phi D acts on each row independently, Section 2).  b and
+ * w are indexed by the block's own rows.  row_start >= 0; other arguments as
+ * for skls_sketch.  Asynchronous.
+ */
+SKLS_API int32_t skls_sketch_rows(const skls_matrix* A, int64_t row_start, const void* b, int32_t b_dtype, int64_t t,
+                                  uint64_t seed, const float* w, int32_t variant, void* SA, void* Sb,
+                                  int32_t out_dtype, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Reusable bucket plans.  The buckets h(i) depend only on (seed, i, t)
+ * (Section 2), so the grouping of the rows by bucket that the SORTED and
+ * BINNED variants build can be kept and reused for every matrix with the same
+ * rows: any dense matrix with the same n, or a CSR matrix with the same row
+ * pointers (values and columns may change).  skls_sketch_plan builds it into
+ * a caller-owned device buffer and fills the host descriptor; each
+ * skls_sketch_planned call then runs only the reduce.
+ */
+typedef struct {
+  int64_t n, d, t;
+  int64_t row_start;  /* global index of the first row (as skls_sketch_rows) */
+  uint64_t seed;
+  int32_t layout;     /* skls_layout of the matrix the plan was built for */
+  int32_t row_ptr_64;
+  int32_t variant;    /* the variant that will run (AUTO resolved) */
+  int32_t out_dtype;  /* F64 or F32 */
+  int64_t bytes;      /* bytes of the device plan (0 for ATOMIC, which has none) */
+  int64_t reserved[2];
+} skls_sketch_plan_desc;
+
+/* Bytes of the device plan for this input shape, t, variant and output type. */
+SKLS_API int32_t skls_sketch_plan_workspace(const skls_matrix* A, int64_t t, int32_t variant, int32_t out_dtype,
+                                            size_t* bytes);
+/*
+ * Build the plan of A's rows (row pointers for CSR; nothing of the values)
+ * for (row_start, t, seed, variant, out_dtype) into `plan` (device, plan_bytes
+ * from the query) and fill `desc` (host).  Asynchronous.
+ */
+SKLS_API int32_t skls_sketch_plan(const skls_matrix* A, int64_t row_start, int64_t t, uint64_t seed,
+                                  int32_t variant, int32_t out_dtype, void* plan, size_t plan_bytes,
+                                  skls_sketch_plan_desc* desc, void* stream);
+/*
+ * SA = S A (and Sb = S b) with a plan from skls_sketch_plan.  A must have the
+ * plan's n, d, layout and row pointer width, and (CSR) the same row pointer
+ * contents as when the plan was built; results are then those of skls_sketch
+ * with the plan's arguments.  For CSR inputs with b, b[i] is gathered per
+ * row during the reduce (the plan holds no values).  The plan is only read:
+ * several calls may share it.  Asynchronous.
+ */
+SKLS_API int32_t skls_sketch_planned(const skls_matrix* A, const void* b, int32_t b_dtype, const float* w, void* SA,
+                                     void* Sb, const skls_sketch_plan_desc* desc, const void* plan,
+                                     size_t plan_bytes, void* stream);
+
+/*
  * Generalized sparse embedding (Section 5, the construction): a hash h sends
  * each row i to one of q groups; group g applies its own matrix B^(g), the
  * stack of `a` independent sparse embeddings sqrt(1/a) Phi_j D_j onto v
@@ -184,8 +241,10 @@ SKLS_API int32_t skls_sketch_general(const skls_matrix* A, const void* b, int32_
  *  R:     device float64 d x d row-major, upper triangular (zeros below).
  *  Rinv:  device float64 d x d row-major, the inverse of R, or NULL.
  *  Returns SKLS_ERR_RANK (R, Rinv then unspecified) when a pivot of the Gram
- *  matrix is not positive or min R_kk <= 4 sqrt(d * 2^-52) max R_kk (a
- *  Gram-based factor cannot resolve smaller pivots).  Synchronous.
+ *  matrix is not positive or some R_kk <= 4 sqrt(d * 2^-52) sqrt(G_kk), G = M^T M
+ *  (R_kk / sqrt(G_kk) is the sine of the angle between column k and the
+ *  columns before it, so the test does not depend on column scaling; a
+ *  Gram-based factor cannot resolve smaller angles).  Synchronous.
  */
 SKLS_API int32_t skls_qr_r_workspace(int64_t m, int64_t d, size_t* bytes);
 SKLS_API int32_t skls_qr_r(const void* M, int32_t dtype, int64_t m, int64_t d, double* R, double* Rinv, void* ws,
@@ -241,14 +300,32 @@ SKLS_API int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_ls
  * Approximate leverage scores (Section 6, theorem on approximating all leverage
  * scores): scores[i] = || A[i, :] R^{-1} Pi2 ||^2 where R is the triangular
  * factor of S A (S from t, seed) and Pi2 is a d x k Johnson-Lindenstrauss
- * matrix supplied by the caller (device float64, row-major).  Scores are
- * accumulated in float32.
+ * matrix (device float64, row-major).  Pi2 = NULL uses the d x k matrix of
+ * signs / sqrt(k) with the sign of entry e from bit 0 of output e of the
+ * stream seed ^ 0x6C65766572616765 (the projection of skls_low_rank).  The
+ * products A T, T = R^{-1} Pi2, are accumulated in float32.
  *  scores: device float32 [n].
  * Returns SKLS_ERR_RANK if S A is rank deficient.  Synchronous.
  */
 SKLS_API int32_t skls_leverage_workspace(const skls_matrix* A, int64_t t, int32_t k, size_t* bytes);
 SKLS_API int32_t skls_leverage_scores(const skls_matrix* A, int64_t t, uint64_t seed, int32_t k, const double* Pi2,
                              float* scores, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The same scores from a triangular factor the caller already has (Section 6:
+ * any R for which A R^{-1} is well conditioned, such as the R of S A that
+ * skls_qr_r or a least-squares solve produced): scores[i] = ||A[i, :] R^{-1}
+ * Pi2||^2, R^{-1} by the doubling inverse of skls_qr_r.
+ *  R:    device float64 d x d row-major, upper triangular, nonzero diagonal
+ *        (entries below the diagonal are not read).
+ *  Pi2:  device float64 d x k, or NULL for the seeded sign matrix above
+ *        (stream `seed`).
+ *  scores: device float32 [n].  Asynchronous.
+ */
+SKLS_API int32_t skls_leverage_from_r_workspace(const skls_matrix* A, int32_t k, size_t* bytes);
+SKLS_API int32_t skls_leverage_scores_from_r(const skls_matrix* A, const double* R, int32_t k, const double* Pi2,
+                                             uint64_t seed, float* scores, void* ws, size_t ws_bytes,
+                                             void* stream);
 
 /*
  * Gram matrix C = A^T A (float32 output, float32 accumulation), used as the
@@ -276,6 +353,18 @@ SKLS_API int32_t skls_learned_workspace(const skls_matrix* A, int64_t t, size_t*
 SKLS_API int32_t skls_learned_grad(const skls_matrix* A, const float* C, int64_t t, uint64_t seed, const float* w,
                                    float grad_scale, int32_t accumulate, float* loss, float* grad_w, void* ws,
                                    size_t ws_bytes, void* stream);
+
+/*
+ * The same loss and gradient with the forward sketch run from a reusable plan
+ * (skls_sketch_plan of a dense matrix of this shape, float32 output,
+ * row_start 0; t and seed come from desc).  Matrices of one shape share one
+ * plan, since the plan depends only on (seed, n, t).  The workspace of
+ * skls_learned_workspace suffices.  Asynchronous.
+ */
+SKLS_API int32_t skls_learned_grad_planned(const skls_matrix* A, const float* C, const skls_sketch_plan_desc* desc,
+                                           const void* plan, size_t plan_bytes, const float* w, float grad_scale,
+                                           int32_t accumulate, float* loss, float* grad_w, void* ws,
+                                           size_t ws_bytes, void* stream);
 
 /*
  * One Adam step (Kingma & Ba 2015) on w [n] (device float32) with gradient g,

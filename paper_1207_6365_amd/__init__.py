@@ -24,7 +24,10 @@ from .api import (  # noqa: F401
     multi_lstsq,
     lp_regression,
     qr_r,
+    SketchPlan,
     sketch,
     sketch_general,
+    sketch_plan,
+    sketch_planned,
     version,
 )

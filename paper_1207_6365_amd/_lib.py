@@ -42,6 +42,22 @@ class SklsMatrix(ctypes.Structure):
     ]
 
 
+class SklsSketchPlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int64),
+        ("d", c_int64),
+        ("t", c_int64),
+        ("row_start", c_int64),
+        ("seed", c_uint64),
+        ("layout", c_int32),
+        ("row_ptr_64", c_int32),
+        ("variant", c_int32),
+        ("out_dtype", c_int32),
+        ("bytes", c_int64),
+        ("reserved", c_int64 * 2),
+    ]
+
+
 class SklsLstsqOpts(ctypes.Structure):
     _fields_ = [
         ("t", c_int64),
@@ -171,6 +187,13 @@ SIGNATURES = {
     "skls_sketch_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int32, POINTER(c_size_t)]),
     "skls_sketch": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_int64, c_uint64, c_void_p, c_int32,
                               c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
+    "skls_sketch_rows": (c_int32, [POINTER(SklsMatrix), c_int64, c_void_p, c_int32, c_int64, c_uint64, c_void_p,
+                                   c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
+    "skls_sketch_plan_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int32, c_int32, POINTER(c_size_t)]),
+    "skls_sketch_plan": (c_int32, [POINTER(SklsMatrix), c_int64, c_int64, c_uint64, c_int32, c_int32, c_void_p,
+                                   c_size_t, POINTER(SklsSketchPlanDesc), c_void_p]),
+    "skls_sketch_planned": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                      POINTER(SklsSketchPlanDesc), c_void_p, c_size_t, c_void_p]),
     "skls_sketch_general_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int64, c_int32, POINTER(c_size_t)]),
     "skls_sketch_general": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_int64, c_int64, c_int32, c_uint64,
                                       c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
@@ -182,11 +205,17 @@ SIGNATURES = {
     "skls_leverage_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int32, POINTER(c_size_t)]),
     "skls_leverage_scores": (c_int32, [POINTER(SklsMatrix), c_int64, c_uint64, c_int32, c_void_p, c_void_p,
                                        c_void_p, c_size_t, c_void_p]),
+    "skls_leverage_from_r_workspace": (c_int32, [POINTER(SklsMatrix), c_int32, POINTER(c_size_t)]),
+    "skls_leverage_scores_from_r": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_void_p, c_uint64, c_void_p,
+                                              c_void_p, c_size_t, c_void_p]),
     "skls_gram_workspace": (c_int32, [POINTER(SklsMatrix), POINTER(c_size_t)]),
     "skls_gram": (c_int32, [POINTER(SklsMatrix), c_void_p, c_void_p, c_size_t, c_void_p]),
     "skls_learned_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, POINTER(c_size_t)]),
     "skls_learned_grad": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int64, c_uint64, c_void_p, c_float, c_int32,
                                     c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "skls_learned_grad_planned": (c_int32, [POINTER(SklsMatrix), c_void_p, POINTER(SklsSketchPlanDesc), c_void_p,
+                                            c_size_t, c_void_p, c_float, c_int32, c_void_p, c_void_p, c_void_p,
+                                            c_size_t, c_void_p]),
     "skls_adam_step": (c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_float, c_float,
                                  c_float, c_float, c_void_p]),
     "skls_profile_enable": (c_int32, [c_int32]),

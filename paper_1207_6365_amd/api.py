@@ -110,25 +110,70 @@ def hash_rows(n: int, t: int, seed: int, start: int = 0, device="cuda"):
 
 
 # ------------------------------------------------------------------ a2
-def sketch(A, t: int, seed: int, b: torch.Tensor | None = None, w: torch.Tensor | None = None,
-           variant: str = "auto", out_dtype=torch.float32):
-    """``S A`` (and ``S b`` when ``b`` is given); ``w`` replaces the signs."""
-    m, device = _matrix(A)
-    if out_dtype not in (torch.float64, torch.float32):
-        raise TypeError("out_dtype must be float64 or float32")
+def _sketch_inputs(m, b, w):
     if b is not None and (b.dtype not in (torch.float64, torch.float32) or not b.is_contiguous()):
         raise TypeError("b must be a contiguous float64/float32 vector")
     if b is not None and b.numel() != m.n:
         raise ValueError("b must have n entries")
     if w is not None and (w.dtype != torch.float32 or not w.is_contiguous() or w.numel() != m.n):
         raise TypeError("w must be a contiguous float32 vector of n entries")
+
+
+def sketch(A, t: int, seed: int, b: torch.Tensor | None = None, w: torch.Tensor | None = None,
+           variant: str = "auto", out_dtype=torch.float32, row_start: int = 0):
+    """``S A`` (and ``S b`` when ``b`` is given); ``w`` replaces the signs.
+    ``row_start``: global index of ``A``'s first row (a block of a taller
+    matrix), by which its rows are hashed."""
+    m, device = _matrix(A)
+    if out_dtype not in (torch.float64, torch.float32):
+        raise TypeError("out_dtype must be float64 or float32")
+    _sketch_inputs(m, b, w)
     v = _VARIANT[variant]
     ws = _workspace(_size(lib().skls_sketch_workspace, ctypes.byref(m), t, v), device)
     SA = torch.empty((t, m.d), dtype=out_dtype, device=device)
     Sb = torch.empty(t, dtype=out_dtype, device=device) if b is not None else None
-    L.check(lib().skls_sketch(ctypes.byref(m), _ptr(b), _DTYPE[b.dtype] if b is not None else L.F64, t,
-                              seed & 0xFFFFFFFFFFFFFFFF, _ptr(w), v, _ptr(SA), _ptr(Sb), _DTYPE[out_dtype],
-                              _ptr(ws), ws.numel(), _stream(device)))
+    L.check(lib().skls_sketch_rows(ctypes.byref(m), row_start, _ptr(b), _DTYPE[b.dtype] if b is not None else L.F64,
+                                   t, seed & 0xFFFFFFFFFFFFFFFF, _ptr(w), v, _ptr(SA), _ptr(Sb), _DTYPE[out_dtype],
+                                   _ptr(ws), ws.numel(), _stream(device)))
+    return (SA, Sb) if b is not None else SA
+
+
+@dataclass
+class SketchPlan:
+    """A reusable bucket plan: the device buffer and its descriptor."""
+
+    buf: torch.Tensor
+    desc: L.SklsSketchPlanDesc
+
+
+def sketch_plan(A, t: int, seed: int, variant: str = "auto", out_dtype=torch.float32,
+                row_start: int = 0) -> SketchPlan:
+    """Build the bucket plan of ``A``'s rows (row pointers for CSR) once."""
+    m, device = _matrix(A)
+    if out_dtype not in (torch.float64, torch.float32):
+        raise TypeError("out_dtype must be float64 or float32")
+    v = _VARIANT[variant]
+    od = _DTYPE[out_dtype]
+    buf = _workspace(_size(lib().skls_sketch_plan_workspace, ctypes.byref(m), t, v, od), device)
+    desc = L.SklsSketchPlanDesc()
+    L.check(lib().skls_sketch_plan(ctypes.byref(m), row_start, t, seed & 0xFFFFFFFFFFFFFFFF, v, od, _ptr(buf),
+                                   buf.numel(), ctypes.byref(desc), _stream(device)))
+    return SketchPlan(buf, desc)
+
+
+def sketch_planned(plan: SketchPlan, A, b: torch.Tensor | None = None, w: torch.Tensor | None = None,
+                   SA: torch.Tensor | None = None, Sb: torch.Tensor | None = None):
+    """``S A`` (and ``S b``) with a plan from :func:`sketch_plan`."""
+    m, device = _matrix(A)
+    _sketch_inputs(m, b, w)
+    od = torch.float64 if plan.desc.out_dtype == L.F64 else torch.float32
+    if SA is None:
+        SA = torch.empty((plan.desc.t, m.d), dtype=od, device=device)
+    if b is not None and Sb is None:
+        Sb = torch.empty(plan.desc.t, dtype=od, device=device)
+    L.check(lib().skls_sketch_planned(ctypes.byref(m), _ptr(b), _DTYPE[b.dtype] if b is not None else L.F64, _ptr(w),
+                                      _ptr(SA), _ptr(Sb), ctypes.byref(plan.desc), _ptr(plan.buf), plan.buf.numel(),
+                                      _stream(device)))
     return (SA, Sb) if b is not None else SA
 
 
@@ -257,15 +302,28 @@ def lp_regression(A, b: torch.Tensor, p: float, seed: int, q: int = 0, v: int = 
 
 
 # ------------------------------------------------------------------ a5
-def leverage_scores(A, t: int, seed: int, Pi2: torch.Tensor):
-    """Squared row norms of ``A R^{-1} Pi2`` (``Pi2``: ``d x k`` float64)."""
+def leverage_scores(A, t: int, seed: int, Pi2: torch.Tensor | None = None, k: int = 32,
+                    R: torch.Tensor | None = None):
+    """Squared row norms of ``A R^{-1} Pi2`` (Section 6).  ``Pi2``: ``d x k``
+    float64, or None for the seeded ``d x k`` sign matrix of the library.
+    ``R``: a ``d x d`` float64 upper-triangular factor to use instead of the
+    one of ``S A`` (``t`` is then unused)."""
     m, device = _matrix(A)
-    if Pi2.dtype != torch.float64 or not Pi2.is_contiguous() or Pi2.dim() != 2 or Pi2.shape[0] != m.d:
-        raise TypeError("Pi2 must be a contiguous float64 d x k tensor")
-    k = Pi2.shape[1]
-    ws = _workspace(_size(lib().skls_leverage_workspace, ctypes.byref(m), t, k), device)
+    if Pi2 is not None:
+        if Pi2.dtype != torch.float64 or not Pi2.is_contiguous() or Pi2.dim() != 2 or Pi2.shape[0] != m.d:
+            raise TypeError("Pi2 must be a contiguous float64 d x k tensor")
+        k = Pi2.shape[1]
     scores = torch.empty(m.n, dtype=torch.float32, device=device)
-    L.check(lib().skls_leverage_scores(ctypes.byref(m), t, seed & 0xFFFFFFFFFFFFFFFF, k, _ptr(Pi2), _ptr(scores),
+    sd = seed & 0xFFFFFFFFFFFFFFFF
+    if R is not None:
+        if R.dtype != torch.float64 or not R.is_contiguous() or tuple(R.shape) != (m.d, m.d):
+            raise TypeError("R must be a contiguous float64 d x d tensor")
+        ws = _workspace(_size(lib().skls_leverage_from_r_workspace, ctypes.byref(m), k), device)
+        L.check(lib().skls_leverage_scores_from_r(ctypes.byref(m), _ptr(R), k, _ptr(Pi2), sd, _ptr(scores),
+                                                  _ptr(ws), ws.numel(), _stream(device)))
+        return scores
+    ws = _workspace(_size(lib().skls_leverage_workspace, ctypes.byref(m), t, k), device)
+    L.check(lib().skls_leverage_scores(ctypes.byref(m), t, sd, k, _ptr(Pi2), _ptr(scores),
                                        _ptr(ws), ws.numel(), _stream(device)))
     return scores
 
@@ -292,9 +350,12 @@ class LearnedWorkspace:
 def learned_grad(A: torch.Tensor, C: torch.Tensor, t: int, seed: int, w: torch.Tensor,
                  ws: LearnedWorkspace | None = None, loss: torch.Tensor | None = None,
                  grad: torch.Tensor | None = None, grad_scale: float = 1.0, accumulate: bool = False,
-                 want_grad: bool = True):
+                 want_grad: bool = True, plan: SketchPlan | None = None):
     """Distortion loss ``||(S_w A)^T S_w A - C||_F^2`` and ``grad_scale`` times its
-    gradient in ``w`` (added into ``grad`` when ``accumulate``)."""
+    gradient in ``w`` (added into ``grad`` when ``accumulate``).  ``plan``: a
+    reusable plan of :func:`sketch_plan` for ``A``'s shape, ``t`` and
+    ``seed`` (float32 output), so that the forward sketch runs without
+    rebuilding it."""
     m, device = _matrix(A)
     if ws is None or ws.key != (m.n, m.d, t):
         ws = LearnedWorkspace(A, t)
@@ -303,6 +364,14 @@ def learned_grad(A: torch.Tensor, C: torch.Tensor, t: int, seed: int, w: torch.T
         grad = torch.empty(m.n, dtype=torch.float32, device=device)
     if accumulate and grad is None:
         raise ValueError("accumulate needs a grad buffer")
+    if plan is not None:
+        if plan.desc.t != t or plan.desc.seed != seed & 0xFFFFFFFFFFFFFFFF:
+            raise ValueError("the plan was built for another t or seed")
+        L.check(lib().skls_learned_grad_planned(ctypes.byref(m), _ptr(C), ctypes.byref(plan.desc), _ptr(plan.buf),
+                                                plan.buf.numel(), _ptr(w), grad_scale, 1 if accumulate else 0,
+                                                _ptr(loss), _ptr(grad) if want_grad else None, _ptr(ws.buf),
+                                                ws.buf.numel(), _stream(device)))
+        return loss, (grad if want_grad else None)
     L.check(lib().skls_learned_grad(ctypes.byref(m), _ptr(C), t, seed & 0xFFFFFFFFFFFFFFFF, _ptr(w), grad_scale,
                                     1 if accumulate else 0, _ptr(loss), _ptr(grad) if want_grad else None,
                                     _ptr(ws.buf), ws.buf.numel(), _stream(device)))

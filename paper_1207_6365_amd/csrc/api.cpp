@@ -194,6 +194,7 @@ struct LevWs {
   QrWs q;
   double* R;
   double* Rinv;
+  double* Pi2;  // generated projection (used when the caller passes none)
   float* T;
 };
 
@@ -208,6 +209,25 @@ LevWs carve_lev(Arena& ar, const skls_matrix& A, int64_t t, int32_t k) {
   L.q = carve_qr(ar, t, d, d);
   L.R = ar.take<double>(static_cast<size_t>(d * d));
   L.Rinv = ar.take<double>(static_cast<size_t>(d * d));
+  L.Pi2 = ar.take<double>(static_cast<size_t>(d) * k);
+  L.T = ar.take<float>(static_cast<size_t>(d) * k);
+  return L;
+}
+
+// Workspace of the leverage scores from a given R: R^{-1}, its transpose
+// (product scratch of the inverse), the projection and T = R^{-1} Pi2.
+struct LevRWs {
+  double* Rinv;
+  double* RinvT;
+  double* Pi2;
+  float* T;
+};
+
+LevRWs carve_lev_r(Arena& ar, int64_t d, int32_t k) {
+  LevRWs L;
+  L.Rinv = ar.take<double>(static_cast<size_t>(d * d));
+  L.RinvT = ar.take<double>(static_cast<size_t>(d * d));
+  L.Pi2 = ar.take<double>(static_cast<size_t>(d) * k);
   L.T = ar.take<float>(static_cast<size_t>(d) * k);
   return L;
 }
@@ -246,6 +266,34 @@ int32_t check_lstsq(const skls_matrix* A, const skls_lstsq_opts* opts) {
 }
 
 }  // namespace
+
+int32_t check_sketch_args(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t t, int32_t variant,
+                          const void* SA, const void* Sb, int32_t out_dtype) {
+  SKLS_TRY(validate_matrix(A, true));
+  SKLS_TRY(check_t(t));
+  if (variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_BINNED) {
+    set_error("unknown sketch variant %d", variant);
+    return SKLS_ERR_ARG;
+  }
+  if (SA == nullptr) {
+    set_error("SA is NULL");
+    return SKLS_ERR_ARG;
+  }
+  if ((b == nullptr) != (Sb == nullptr)) {
+    set_error("b and Sb must be given together");
+    return SKLS_ERR_ARG;
+  }
+  if (b != nullptr && b_dtype != SKLS_F64 && b_dtype != SKLS_F32) {
+    set_error("b must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  if (out_dtype != SKLS_F64 && out_dtype != SKLS_F32) {
+    set_error("out_dtype must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  return SKLS_OK;
+}
+
 }  // namespace skls
 
 using namespace skls;
@@ -299,35 +347,103 @@ int32_t skls_sketch_workspace(const skls_matrix* A, int64_t t, int32_t variant, 
 
 int32_t skls_sketch(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed, const float* w,
                     int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws, size_t ws_bytes, void* stream) {
+  return skls_sketch_rows(A, 0, b, b_dtype, t, seed, w, variant, SA, Sb, out_dtype, ws, ws_bytes, stream);
+}
+
+int32_t skls_sketch_rows(const skls_matrix* A, int64_t row_start, const void* b, int32_t b_dtype, int64_t t,
+                         uint64_t seed, const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype,
+                         void* ws, size_t ws_bytes, void* stream) {
   clear_error();
-  SKLS_TRY(validate_matrix(A, true));
-  SKLS_TRY(check_t(t));
-  if (variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_BINNED) {
-    set_error("unknown sketch variant %d", variant);
-    return SKLS_ERR_ARG;
-  }
-  if (SA == nullptr) {
-    set_error("SA is NULL");
-    return SKLS_ERR_ARG;
-  }
-  if ((b == nullptr) != (Sb == nullptr)) {
-    set_error("b and Sb must be given together");
-    return SKLS_ERR_ARG;
-  }
-  if (b != nullptr && b_dtype != SKLS_F64 && b_dtype != SKLS_F32) {
-    set_error("b must be F64 or F32");
-    return SKLS_ERR_DTYPE;
-  }
-  if (out_dtype != SKLS_F64 && out_dtype != SKLS_F32) {
-    set_error("out_dtype must be F64 or F32");
-    return SKLS_ERR_DTYPE;
+  SKLS_TRY(check_sketch_args(A, b, b_dtype, t, variant, SA, Sb, out_dtype));
+  if (row_start < 0) {
+    set_error("row_start must be non-negative");
+    return SKLS_ERR_SHAPE;
   }
   const size_t need = sketch_ws_bytes(*A, t, variant);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) {
     set_error("sketch workspace too small: need %zu bytes", need);
     return SKLS_ERR_WORKSPACE;
   }
-  return run_sketch(*A, b, b_dtype, t, seed, w, variant, SA, Sb, out_dtype, ws, ws_bytes, as_stream(stream));
+  return run_sketch_key(*A, b, b_dtype, t, plain_key(seed, static_cast<uint64_t>(row_start)), w, variant, SA, Sb,
+                        out_dtype, ws, ws_bytes, as_stream(stream));
+}
+
+int32_t skls_sketch_plan_workspace(const skls_matrix* A, int64_t t, int32_t variant, int32_t out_dtype,
+                                   size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  SKLS_TRY(check_t(t));
+  if (bytes == nullptr || variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_BINNED) {
+    set_error("need bytes != NULL and a known variant");
+    return SKLS_ERR_ARG;
+  }
+  if (out_dtype != SKLS_F64 && out_dtype != SKLS_F32) {
+    set_error("out_dtype must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  *bytes = sketch_plan_bytes(*A, t, variant, out_dtype);
+  return SKLS_OK;
+}
+
+int32_t skls_sketch_plan(const skls_matrix* A, int64_t row_start, int64_t t, uint64_t seed, int32_t variant,
+                         int32_t out_dtype, void* plan, size_t plan_bytes, skls_sketch_plan_desc* desc,
+                         void* stream) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  SKLS_TRY(check_t(t));
+  if (desc == nullptr || variant < SKLS_SKETCH_AUTO || variant > SKLS_SKETCH_BINNED) {
+    set_error("need desc != NULL and a known variant");
+    return SKLS_ERR_ARG;
+  }
+  if (row_start < 0) {
+    set_error("row_start must be non-negative");
+    return SKLS_ERR_SHAPE;
+  }
+  if (out_dtype != SKLS_F64 && out_dtype != SKLS_F32) {
+    set_error("out_dtype must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  const size_t need = sketch_plan_bytes(*A, t, variant, out_dtype);
+  if (need > 0 && (plan == nullptr || plan_bytes < need)) {
+    set_error("sketch plan buffer too small: need %zu bytes", need);
+    return SKLS_ERR_WORKSPACE;
+  }
+  int32_t resolved = 0;
+  SKLS_TRY(build_sketch_plan(*A, t, plain_key(seed, static_cast<uint64_t>(row_start)), variant, out_dtype, plan,
+                             plan_bytes, &resolved, as_stream(stream)));
+  *desc = skls_sketch_plan_desc{};
+  desc->n = A->n;
+  desc->d = A->d;
+  desc->t = t;
+  desc->row_start = row_start;
+  desc->seed = seed;
+  desc->layout = A->layout;
+  desc->row_ptr_64 = A->layout == SKLS_CSR ? A->row_ptr_64 : 0;
+  desc->variant = resolved;
+  desc->out_dtype = out_dtype;
+  desc->bytes = static_cast<int64_t>(need);
+  return SKLS_OK;
+}
+
+int32_t skls_sketch_planned(const skls_matrix* A, const void* b, int32_t b_dtype, const float* w, void* SA, void* Sb,
+                            const skls_sketch_plan_desc* desc, const void* plan, size_t plan_bytes, void* stream) {
+  clear_error();
+  if (desc == nullptr) {
+    set_error("desc is NULL");
+    return SKLS_ERR_ARG;
+  }
+  SKLS_TRY(check_sketch_args(A, b, b_dtype, desc->t, desc->variant, SA, Sb, desc->out_dtype));
+  if (A->n != desc->n || A->d != desc->d || A->layout != desc->layout ||
+      (A->layout == SKLS_CSR && A->row_ptr_64 != desc->row_ptr_64)) {
+    set_error("the matrix does not match the plan (n, d, layout or row pointer width)");
+    return SKLS_ERR_SHAPE;
+  }
+  if (desc->bytes > 0 && (plan == nullptr || plan_bytes < static_cast<size_t>(desc->bytes))) {
+    set_error("sketch plan buffer too small: need %lld bytes", static_cast<long long>(desc->bytes));
+    return SKLS_ERR_WORKSPACE;
+  }
+  return apply_sketch_plan(*A, b, b_dtype, desc->t, plain_key(desc->seed, static_cast<uint64_t>(desc->row_start)),
+                           w, desc->variant, SA, Sb, desc->out_dtype, plan, plan_bytes, as_stream(stream));
 }
 
 int32_t skls_sketch_general_workspace(const skls_matrix* A, int64_t q, int64_t v, int32_t variant, size_t* bytes) {
@@ -614,8 +730,8 @@ int32_t skls_leverage_scores(const skls_matrix* A, int64_t t, uint64_t seed, int
   clear_error();
   SKLS_TRY(validate_matrix(A, true));
   SKLS_TRY(check_t(t));
-  if (k < 1 || k > 64 || Pi2 == nullptr || scores == nullptr) {
-    set_error("need 1 <= k <= 64 and non-NULL Pi2, scores");
+  if (k < 1 || k > 64 || scores == nullptr) {
+    set_error("need 1 <= k <= 64 and non-NULL scores");
     return SKLS_ERR_ARG;
   }
   if (t < A->d || A->d > 8192) {
@@ -630,6 +746,10 @@ int32_t skls_leverage_scores(const skls_matrix* A, int64_t t, uint64_t seed, int
   SKLS_TRY(run_sketch(*A, nullptr, SKLS_F64, t, seed, nullptr, SKLS_SKETCH_AUTO, L.SA, nullptr, L.sk_dtype, L.sk,
                       L.sk_bytes, s));
   SKLS_TRY(qr_from(L.SA, L.sk_dtype, nullptr, SKLS_F64, t, d, L.q, L.R, L.Rinv, L.q.RinvT, s));
+  if (Pi2 == nullptr) {
+    SKLS_TRY(run_sign_projection(d, k, seed, L.Pi2, s));
+    Pi2 = L.Pi2;
+  }
   SKLS_TRY(run_rinv_times(L.Rinv, d, Pi2, k, L.T, s));
   SKLS_TRY(run_leverage(*A, L.T, k, scores, s));
   int32_t st = 0;
@@ -639,6 +759,45 @@ int32_t skls_leverage_scores(const skls_matrix* A, int64_t t, uint64_t seed, int
     return SKLS_ERR_RANK;
   }
   return SKLS_OK;
+}
+
+int32_t skls_leverage_from_r_workspace(const skls_matrix* A, int32_t k, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (bytes == nullptr || k < 1 || k > 64) {
+    set_error("need bytes != NULL and 1 <= k <= 64");
+    return SKLS_ERR_ARG;
+  }
+  Arena ar(nullptr, 0);
+  carve_lev_r(ar, A->d, k);
+  *bytes = ar.used;
+  return SKLS_OK;
+}
+
+int32_t skls_leverage_scores_from_r(const skls_matrix* A, const double* R, int32_t k, const double* Pi2,
+                                    uint64_t seed, float* scores, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, true));
+  if (k < 1 || k > 64 || R == nullptr || scores == nullptr) {
+    set_error("need 1 <= k <= 64 and non-NULL R, scores");
+    return SKLS_ERR_ARG;
+  }
+  if (A->d > 8192) {
+    set_error("need d <= 8192");
+    return SKLS_ERR_SHAPE;
+  }
+  hipStream_t s = as_stream(stream);
+  const int64_t d = A->d;
+  Arena ar(ws, ws_bytes);
+  LevRWs L = carve_lev_r(ar, d, k);
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  SKLS_TRY(run_trinv(R, d, L.Rinv, L.RinvT, s, nullptr));
+  if (Pi2 == nullptr) {
+    SKLS_TRY(run_sign_projection(d, k, seed, L.Pi2, s));
+    Pi2 = L.Pi2;
+  }
+  SKLS_TRY(run_rinv_times(L.Rinv, d, Pi2, k, L.T, s));
+  return run_leverage(*A, L.T, k, scores, s);
 }
 
 int32_t skls_gram_workspace(const skls_matrix* A, size_t* bytes) {
@@ -699,12 +858,10 @@ int32_t skls_learned_workspace(const skls_matrix* A, int64_t t, size_t* bytes) {
   return SKLS_OK;
 }
 
-int32_t skls_learned_grad(const skls_matrix* A, const float* C, int64_t t, uint64_t seed, const float* w,
-                          float grad_scale, int32_t accumulate, float* loss, float* grad_w, void* ws, size_t ws_bytes,
-                          void* stream) {
-  clear_error();
+namespace {
+
+int32_t check_learned(const skls_matrix* A, const float* C, const float* w, const float* loss) {
   SKLS_TRY(validate_matrix(A, false));
-  SKLS_TRY(check_t(t));
   if (A->layout != SKLS_DENSE || A->dtype != SKLS_F32) {
     set_error("learned values need a dense float32 A");
     return SKLS_ERR_DTYPE;
@@ -717,24 +874,92 @@ int32_t skls_learned_grad(const skls_matrix* A, const float* C, int64_t t, uint6
     set_error("learned values support d <= 4096");
     return SKLS_ERR_SHAPE;
   }
+  return SKLS_OK;
+}
+
+// Scratch of the loss and gradient after the forward sketch: Gram partials,
+// Y^T Y, E and G.
+struct LearnedRest {
+  size_t gb;
+  double* gw;
+  double* P;
+  float* E;
+  float* G;
+};
+
+LearnedRest carve_learned_rest(Arena& ar, int64_t t, int64_t d) {
+  LearnedRest r;
+  r.gb = gram_ws_bytes(t, d);
+  r.gw = reinterpret_cast<double*>(ar.take<char>(r.gb));
+  r.P = ar.take<double>(static_cast<size_t>(d * d));
+  r.E = ar.take<float>(static_cast<size_t>(d * d));
+  r.G = ar.take<float>(static_cast<size_t>(t * d));
+  return r;
+}
+
+// Loss and gradient once the forward sketch Y = S_w A is formed.
+int32_t learned_rest(const skls_matrix& A, const float* C, int64_t t, uint64_t seed, float grad_scale,
+                     int32_t accumulate, float* loss, float* grad_w, const LearnedRest& r, const float* Y,
+                     hipStream_t s) {
+  const int64_t d = A.d;
+  double* P = r.P;
+  float* E = r.E;
+  float* G = r.G;
+  SKLS_TRY(run_gram(Y, SKLS_F32, d, nullptr, SKLS_F64, t, d, P, r.gw, r.gb, s));
+  SKLS_TRY(run_learned_E(P, d, C, d, E, loss, s));
+  if (grad_w == nullptr) return SKLS_OK;
+  SKLS_TRY(run_learned_G(Y, E, t, d, G, s));
+  return run_learned_gather(A, G, static_cast<uint32_t>(t), seed, grad_scale, accumulate != 0, grad_w, s);
+}
+
+}  // namespace
+
+int32_t skls_learned_grad(const skls_matrix* A, const float* C, int64_t t, uint64_t seed, const float* w,
+                          float grad_scale, int32_t accumulate, float* loss, float* grad_w, void* ws, size_t ws_bytes,
+                          void* stream) {
+  clear_error();
+  SKLS_TRY(check_learned(A, C, w, loss));
+  SKLS_TRY(check_t(t));
   hipStream_t s = as_stream(stream);
   const int64_t d = A->d;
   Arena ar(ws, ws_bytes);
   float* Y = ar.take<float>(static_cast<size_t>(t * d));
   const size_t skb = sketch_ws_bytes(*A, t, SKLS_SKETCH_SORTED);
   void* sk = ar.take<char>(skb);
-  const size_t gb = gram_ws_bytes(t, d);
-  double* gw = reinterpret_cast<double*>(ar.take<char>(gb));
-  double* P = ar.take<double>(static_cast<size_t>(d * d));
-  float* E = ar.take<float>(static_cast<size_t>(d * d));
-  float* G = ar.take<float>(static_cast<size_t>(t * d));
+  const LearnedRest r = carve_learned_rest(ar, t, d);
   SKLS_TRY(need_ws(ar, ws, ws_bytes));
   SKLS_TRY(run_sketch(*A, nullptr, SKLS_F64, t, seed, w, SKLS_SKETCH_SORTED, Y, nullptr, SKLS_F32, sk, skb, s));
-  SKLS_TRY(run_gram(Y, SKLS_F32, d, nullptr, SKLS_F64, t, d, P, gw, gb, s));
-  SKLS_TRY(run_learned_E(P, d, C, d, E, loss, s));
-  if (grad_w == nullptr) return SKLS_OK;
-  SKLS_TRY(run_learned_G(Y, E, t, d, G, s));
-  return run_learned_gather(*A, G, static_cast<uint32_t>(t), seed, grad_scale, accumulate != 0, grad_w, s);
+  return learned_rest(*A, C, t, seed, grad_scale, accumulate, loss, grad_w, r, Y, s);
+}
+
+int32_t skls_learned_grad_planned(const skls_matrix* A, const float* C, const skls_sketch_plan_desc* desc,
+                                  const void* plan, size_t plan_bytes, const float* w, float grad_scale,
+                                  int32_t accumulate, float* loss, float* grad_w, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  clear_error();
+  SKLS_TRY(check_learned(A, C, w, loss));
+  if (desc == nullptr) {
+    set_error("desc is NULL");
+    return SKLS_ERR_ARG;
+  }
+  if (desc->n != A->n || desc->d != A->d || desc->layout != SKLS_DENSE || desc->out_dtype != SKLS_F32 ||
+      desc->row_start != 0) {
+    set_error("the plan must come from a dense float32-output sketch of a matrix of this shape, row_start 0");
+    return SKLS_ERR_SHAPE;
+  }
+  if (desc->bytes > 0 && (plan == nullptr || plan_bytes < static_cast<size_t>(desc->bytes))) {
+    set_error("sketch plan buffer too small: need %lld bytes", static_cast<long long>(desc->bytes));
+    return SKLS_ERR_WORKSPACE;
+  }
+  const int64_t t = desc->t, d = A->d;
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  float* Y = ar.take<float>(static_cast<size_t>(t * d));
+  const LearnedRest r = carve_learned_rest(ar, t, d);
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  SKLS_TRY(apply_sketch_plan(*A, nullptr, SKLS_F64, t, plain_key(desc->seed), w, desc->variant, Y, nullptr, SKLS_F32,
+                             plan, plan_bytes, s));
+  return learned_rest(*A, C, t, desc->seed, grad_scale, accumulate, loss, grad_w, r, Y, s);
 }
 
 int32_t skls_adam_step(int64_t n, float* w, const float* g, float* m, float* v, int32_t step, float lr, float beta1,

@@ -86,15 +86,23 @@ __device__ __forceinline__ bool negative_of(uint64_t z) { return (z & 1ull) != 0
 // bucket = h(r) v + h_j(r) with the outer h(r) = bucket_of(output r of the
 // stream `outer`, q) shared by all copies and h_j(r) = bucket_of(z, v), z =
 // output r of the copy's stream `seed` (which also gives the sign); t = q v.
+// The kernels pass local row indices; `base` is added to them, so a block of
+// rows that starts at global row `base` hashes its rows by their global index
+// (S A = sum over row blocks g of S A_g, the linearity of Phi D).
 struct HashKey {
   uint64_t seed;
   uint64_t outer;
   uint32_t q, v;
+  uint64_t base = 0;
 };
-inline HashKey plain_key(uint64_t s) { return HashKey{s, 0, 0, 0}; }
-__device__ __forceinline__ uint64_t hk_z(const HashKey& k, uint64_t r) { return splitmix64(k.seed, r); }
+inline HashKey plain_key(uint64_t s, uint64_t base = 0) {
+  HashKey k{s, 0, 0, 0};
+  k.base = base;
+  return k;
+}
+__device__ __forceinline__ uint64_t hk_z(const HashKey& k, uint64_t r) { return splitmix64(k.seed, r + k.base); }
 __device__ __forceinline__ uint32_t hk_bucket(const HashKey& k, uint64_t z, uint64_t r, uint32_t t) {
-  return k.v == 0 ? bucket_of(z, t) : bucket_of(splitmix64(k.outer, r), k.q) * k.v + bucket_of(z, k.v);
+  return k.v == 0 ? bucket_of(z, t) : bucket_of(splitmix64(k.outer, r + k.base), k.q) * k.v + bucket_of(z, k.v);
 }
 __device__ __forceinline__ uint32_t hk_bucket_r(const HashKey& k, uint64_t r, uint32_t t) {
   return hk_bucket(k, hk_z(k, r), r, t);

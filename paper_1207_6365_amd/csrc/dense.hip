@@ -482,42 +482,41 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double* __restrict__ W, int d
   }
 }
 
-// R = upper triangle of W; status = rank test on the diagonal.
+// R = upper triangle of W; status = rank test on the diagonal, column by
+// column: R_kk / sqrt(G_kk) is the sine of the angle between column k of the
+// factored matrix and the span of the columns before it, which does not
+// change when a column is scaled.
 __global__ __launch_bounds__(256) void k_chol_finish(const double* __restrict__ W, int d, double* __restrict__ R,
-                                                     const int32_t* __restrict__ bad, int32_t* __restrict__ status,
-                                                     double rtol) {
+                                                     const double* __restrict__ gdiag, const int32_t* __restrict__ bad,
+                                                     int32_t* __restrict__ status, double rtol) {
   for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < static_cast<int64_t>(d) * d;
        idx += static_cast<int64_t>(gridDim.x) * 256) {
     const int i = static_cast<int>(idx / d), j = static_cast<int>(idx % d);
     R[idx] = j >= i ? W[idx] : 0.0;
   }
   if (blockIdx.x == 0) {
-    __shared__ double smx[256], smn[256];
-    double mx = 0.0, mn = INFINITY;
+    __shared__ int32_t sbad;
+    if (threadIdx.x == 0) sbad = 0;
+    __syncthreads();
+    int32_t mine = 0;
     for (int k = threadIdx.x; k < d; k += 256) {
       const double r = W[static_cast<size_t>(k) * d + k];
-      mx = r > mx ? r : mx;
-      mn = r < mn ? r : mn;
+      if (!(r > rtol * sqrt(gdiag[k]))) mine = 1;
     }
-    smx[threadIdx.x] = mx;
-    smn[threadIdx.x] = mn;
+    if (mine) atomicOr(&sbad, 1);
     __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int k = 1; k < 256; ++k) {
-        mx = smx[k] > mx ? smx[k] : mx;
-        mn = smn[k] < mn ? smn[k] : mn;
-      }
-      status[0] = (bad[0] || !(mn > rtol * mx)) ? 1 : 0;
-    }
+    if (threadIdx.x == 0) status[0] = (bad[0] || sbad) ? 1 : 0;
   }
 }
 
 __global__ void k_copy_upper(const double* __restrict__ G, int64_t ldg, int d, double* __restrict__ W,
-                             int32_t* __restrict__ bad) {
+                             double* __restrict__ gdiag, int32_t* __restrict__ bad) {
   for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < static_cast<int64_t>(d) * d;
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int i = static_cast<int>(idx / d), j = static_cast<int>(idx % d);
-    W[idx] = j >= i ? G[static_cast<size_t>(i) * ldg + j] : 0.0;
+    const double g = G[static_cast<size_t>(i) * ldg + j];
+    W[idx] = j >= i ? g : 0.0;
+    if (i == j) gdiag[i] = g;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) bad[0] = 0;
 }
@@ -790,24 +789,28 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
 }
 
 size_t cholesky_scratch_doubles(int64_t d) {
-  return static_cast<size_t>(d * d) + static_cast<size_t>(div_up(d, kCB)) * kCB * kCB + 8;
+  return static_cast<size_t>(d * d) + static_cast<size_t>(div_up(d, kCB)) * kCB * kCB + static_cast<size_t>(d) + 8;
 }
 
 const double* cholesky_block_inverses(const double* scratch, int64_t d) { return scratch + d * d; }
 
 int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t* status, double* scratch,
                      hipStream_t s) {
-  // Threshold: a Gram-based factor cannot resolve |R_kk| below about
-  // sqrt(d * eps) * max |R_jj|; treat that as numerical rank deficiency.
+  // Threshold: R_kk^2 = G_kk - sum_i R_ik^2 is formed with an error of
+  // about d * eps * G_kk, so a Gram-based factor cannot resolve R_kk below
+  // about sqrt(d * eps) * sqrt(G_kk); treat that as numerical rank
+  // deficiency (a per-column test: scaling a column scales both sides).
   const double rtol = 4.0 * std::sqrt(static_cast<double>(d) * 2.220446049250313e-16);
   PhaseTimer pt("cholesky", s);
-  // scratch: W [d*d] | inverses of the diagonal blocks [nb * kCB*kCB] | bad flag
+  // scratch: W [d*d] | inverses of the diagonal blocks [nb * kCB*kCB] |
+  // diagonal of G [d] | bad flag
   double* W = scratch;
   double* Kinv = scratch + d * d;
-  int32_t* bad = reinterpret_cast<int32_t*>(Kinv + div_up(d, kCB) * kCB * kCB);
+  double* gdiag = Kinv + div_up(d, kCB) * kCB * kCB;
+  int32_t* bad = reinterpret_cast<int32_t*>(gdiag + d);
   const int di = static_cast<int>(d);
   const unsigned g = static_cast<unsigned>(div_up(d * d, 256) < 4096 ? div_up(d * d, 256) : 4096);
-  hipLaunchKernelGGL(k_copy_upper, dim3(g), dim3(256), 0, s, G, ldg, di, W, bad);
+  hipLaunchKernelGGL(k_copy_upper, dim3(g), dim3(256), 0, s, G, ldg, di, W, gdiag, bad);
   SKLS_CHECK_LAUNCH();
   for (int K = 0; K < di; K += kCB) {
     const int kb = (di - K) < kCB ? (di - K) : kCB;
@@ -822,7 +825,7 @@ int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t
     hipLaunchKernelGGL(k_chol_syrk, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, W, di, K);
     SKLS_CHECK_LAUNCH();
   }
-  hipLaunchKernelGGL(k_chol_finish, dim3(g), dim3(256), 0, s, W, di, R, bad, status, rtol);
+  hipLaunchKernelGGL(k_chol_finish, dim3(g), dim3(256), 0, s, W, di, R, gdiag, bad, status, rtol);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }

@@ -25,6 +25,19 @@ int32_t run_sketch_key(const skls_matrix& A, const void* b, int32_t b_dtype, int
                        size_t ws_bytes, hipStream_t s);
 int32_t launch_hash_key(int64_t n, uint32_t t, HashKey key, int64_t start, int32_t* bucket, int8_t* sign,
                         hipStream_t s);
+// Reusable bucket plans: bytes of the device buffer, building it (without b
+// and w), and the reduce with it.  `resolved` is the variant that ran
+// (AUTO resolved); the apply needs the same A shape, t, key, variant and
+// output type.
+size_t sketch_plan_bytes(const skls_matrix& A, int64_t t, int32_t variant, int32_t out_dtype);
+int32_t build_sketch_plan(const skls_matrix& A, int64_t t, HashKey key, int32_t variant, int32_t out_dtype,
+                          void* plan, size_t plan_bytes, int32_t* resolved, hipStream_t s);
+int32_t apply_sketch_plan(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, HashKey key,
+                          const float* w, int32_t resolved, void* SA, void* Sb, int32_t out_dtype, const void* plan,
+                          size_t plan_bytes, hipStream_t s);
+// Argument checks shared by the sketch entry points (api.cpp).
+int32_t check_sketch_args(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t t, int32_t variant,
+                          const void* SA, const void* Sb, int32_t out_dtype);
 
 // ---------------------------------------------------------------- dense.hip
 // Gram of the augmented matrix [M | v] (m x dd, dd = d or d+1), float64.
@@ -48,6 +61,10 @@ int32_t run_gemv(const double* M, int64_t d, const double* x, double* y, hipStre
 // x = Rinv (RinvT c): sketch-and-solve from the Gram column c = M^T v.
 // T = Rinv P (d x k), float32 result.
 int32_t run_rinv_times(const double* Rinv, int64_t d, const double* P, int32_t k, float* T, hipStream_t s);
+// Pi2 (rows x kg, row-major) = signs / sqrt(kg), sign of entry e from bit 0
+// of output e of the stream seed ^ "leverage" (the projection of the
+// Section 6 estimates used by every sampling path).
+int32_t run_sign_projection(int64_t rows, int32_t kg, uint64_t seed, double* Pi2, hipStream_t s);
 int32_t run_solve_from_gram(const double* Rinv, const double* RinvT, const double* c, int64_t d, double* x,
                             double* tmp, hipStream_t s);
 

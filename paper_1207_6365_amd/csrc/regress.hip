@@ -103,6 +103,14 @@ MrWs carve_mr(Arena& ar, const MultiPlan& P) {
 
 }  // namespace
 
+int32_t run_sign_projection(int64_t rows, int32_t kg, uint64_t seed, double* Pi2, hipStream_t s) {
+  if (rows * kg == 0) return SKLS_OK;
+  hipLaunchKernelGGL(k_sign_projection, dim3(grid_for(rows * kg, kT, 1 << 20)), dim3(kT), 0, s,
+                     static_cast<int>(rows), kg, seed, Pi2);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
 int32_t multi_plan(const skls_matrix& A, int64_t dp, const skls_multi_opts& o, MultiPlan& P) {
   P.n = A.n;
   P.d = A.d;

@@ -771,7 +771,8 @@ template <typename TV, typename TR, typename TO>
 __global__ __launch_bounds__(kBinThreads) void k_sketch_csr_binned(
     int d, uint32_t t, int sh, int splits, HashKey seed, const int32_t* __restrict__ col,
     const TV* __restrict__ val, const float* __restrict__ w, BinSegs S, const CsrRec<TR, TO>* __restrict__ recs,
-    TO* __restrict__ SA, TO* __restrict__ Sb, int acc_bytes, int sb_bytes, int quad_ok) {
+    TO* __restrict__ SA, TO* __restrict__ Sb, const void* __restrict__ bg, int bg_f64, int acc_bytes, int sb_bytes,
+    int quad_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t wsum[kBinWaves];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -817,7 +818,8 @@ __global__ __launch_bounds__(kBinThreads) void k_sketch_csr_binned(
         R.len[h] = has ? cur[h].len : 0;
         R.sc[h] = w ? static_cast<TO>(w[cur[h].row]) : (negative_of(z) ? TO(-1) : TO(1));
         R.off[h] = lb * d;
-        if (Sb != nullptr && has) lds_add1(sbacc, lb, cur[h].sbv);
+        if (Sb != nullptr && has)
+          lds_add1(sbacc, lb, bg ? R.sc[h] * load_b<TO>(bg, bg_f64, cur[h].row) : cur[h].sbv);
       }
       // next step's records are requested after this step's rows are set up
       // (so no wait there covers them) and before this step's gathers
@@ -885,7 +887,7 @@ template <typename TV, typename TR, typename TO>
 __global__ __launch_bounds__(kThreads) void k_sketch_csr_sorted(
     int d, uint32_t t, int bpw, HashKey seed, const int32_t* __restrict__ col, const TV* __restrict__ val,
     const float* __restrict__ w, const int32_t* __restrict__ off, const CsrRec<TR, TO>* __restrict__ recs,
-    TO* __restrict__ SA, TO* __restrict__ Sb, int per_wave, int quad_ok) {
+    TO* __restrict__ SA, TO* __restrict__ Sb, const void* __restrict__ bg, int bg_f64, int per_wave, int quad_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t b0 = (static_cast<int64_t>(blockIdx.x) * kBucketWaves + wid) * bpw;
@@ -926,13 +928,13 @@ __global__ __launch_bounds__(kThreads) void k_sketch_csr_sorted(
         L.dstart[rk0] = cur.a.start;
         L.dlen[rk0] = cur.a.len;
         L.dscale[rk0] = row_scale<TO>(seed, r0, w);
-        L.dsbv[rk0] = cur.a.sbv;
+        L.dsbv[rk0] = bg ? L.dscale[rk0] * load_b<TO>(bg, bg_f64, r0) : cur.a.sbv;
       }
       if (lane + kWave < m) {
         L.dstart[rk1] = cur.b.start;
         L.dlen[rk1] = cur.b.len;
         L.dscale[rk1] = row_scale<TO>(seed, r1, w);
-        L.dsbv[rk1] = cur.b.sbv;
+        L.dsbv[rk1] = bg ? L.dscale[rk1] * load_b<TO>(bg, bg_f64, r1) : cur.b.sbv;
       }
     }
     wave_sync();
@@ -957,7 +959,7 @@ __global__ __launch_bounds__(kThreads) void k_sketch_csr_sorted(
             R.st[h] = e.start;
             R.len[h] = e.len;
             R.sc[h] = row_scale<TO>(seed, e.row, w);
-            sb += e.sbv;
+            sb += bg ? R.sc[h] * load_b<TO>(bg, bg_f64, e.row) : e.sbv;
           }
         }
       }
@@ -1597,9 +1599,12 @@ BinSegs bin_segs(const BucketPlan& P, int64_t n) {
 }
 
 // Apply of the SORTED and BINNED variants once the plan is built.
+// CSR records carry scale(row) * b[row] when the plan was built with b; a
+// plan built without it (a reusable plan) takes b here instead (bg), and the
+// reduce kernels gather b[row] for each record.
 template <typename TO>
 int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, int b_f64, uint32_t t, HashKey seed,
-                      const float* w, TO* SA, TO* Sb, hipStream_t s) {
+                      const float* w, TO* SA, TO* Sb, const void* bg, hipStream_t s) {
   const PlanShape& S = P.S;
   const int d = static_cast<int>(A.d);
   const int64_t n = A.n;
@@ -1659,7 +1664,7 @@ int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, 
         hipLaunchKernelGGL((k_sketch_csr_binned<TV, TR, TO>), dim3(static_cast<unsigned>(S.C) * S.splits),
                            dim3(kBinThreads), lds, s, d, t, S.sh, S.splits, seed, A.col_idx,
                            static_cast<const TV*>(A.val), w, bin_segs(P, n), static_cast<const Rec*>(P.coarse), SA,
-                           Sb, acc_bytes, sb_bytes, quad_ok);
+                           Sb, bg, b_f64, acc_bytes, sb_bytes, quad_ok);
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
       }
@@ -1674,7 +1679,7 @@ int32_t apply_planned(const skls_matrix& A, const BucketPlan& P, const void* b, 
       const unsigned grid = static_cast<unsigned>(div_up(div_up(t, bpw), kBucketWaves));
       hipLaunchKernelGGL((k_sketch_csr_sorted<TV, TR, TO>), dim3(grid), dim3(kThreads), lds, s, d, t, bpw, seed,
                          A.col_idx, static_cast<const TV*>(A.val), w, P.off, static_cast<const Rec*>(P.fine), SA,
-                         Sb, per_wave, quad_ok);
+                         Sb, bg, b_f64, per_wave, quad_ok);
       SKLS_CHECK_LAUNCH();
       return SKLS_OK;
     });
@@ -1701,13 +1706,11 @@ size_t sketch_ws_bytes(const skls_matrix& A, int64_t t, int32_t variant) {
   return need;
 }
 
-int32_t run_sketch_key(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, HashKey seed,
-                       const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
-                       size_t ws_bytes, hipStream_t s) {
-  const int ob = out_bytes_of(out_dtype);
-  const int32_t v = pick_variant(A, t, variant, ob);
+namespace {
+
+int32_t check_variant(const skls_matrix& A, int64_t t, int32_t v, int ob, int32_t requested) {
   if (v != SKLS_SKETCH_ATOMIC && v != SKLS_SKETCH_SORTED && v != SKLS_SKETCH_BINNED) {
-    set_error("unknown sketch variant %d", variant);
+    set_error("unknown sketch variant %d", requested);
     return SKLS_ERR_ARG;
   }
   if (v == SKLS_SKETCH_BINNED && !binned_ok(A, t, ob)) {
@@ -1718,71 +1721,140 @@ int32_t run_sketch_key(const skls_matrix& A, const void* b, int32_t b_dtype, int
     set_error("sorted CSR sketch supports d * sizeof(out) <= %d bytes; use the binned or atomic variant", kAccMax);
     return SKLS_ERR_SHAPE;
   }
-  const int b_f64 = (b_dtype == SKLS_F64) ? 1 : 0;
-  const uint32_t tt = static_cast<uint32_t>(t);
+  return SKLS_OK;
+}
+
+// ATOMIC: S A zeroed, then every entry added with a device-wide atomic.
+int32_t run_atomic(const skls_matrix& A, const void* b, int b_f64, uint32_t tt, HashKey seed, const float* w, void* SA,
+                   void* Sb, int32_t out_dtype, hipStream_t s) {
   const int d = static_cast<int>(A.d);
   const int64_t n = A.n;
-  if (v == SKLS_SKETCH_ATOMIC) {
-    return with_out(out_dtype, [&](auto to) -> int32_t {
-      using TO = decltype(to);
-      {
-        PhaseTimer pt("sketch_zero", s);
-        SKLS_TRY(launch_fill_zero(SA, static_cast<size_t>(t) * A.d * sizeof(TO), s));
-        if (Sb) SKLS_TRY(launch_fill_zero(Sb, static_cast<size_t>(t) * sizeof(TO), s));
+  return with_out(out_dtype, [&](auto to) -> int32_t {
+    using TO = decltype(to);
+    {
+      PhaseTimer pt("sketch_zero", s);
+      SKLS_TRY(launch_fill_zero(SA, static_cast<size_t>(tt) * A.d * sizeof(TO), s));
+      if (Sb) SKLS_TRY(launch_fill_zero(Sb, static_cast<size_t>(tt) * sizeof(TO), s));
+    }
+    if (n == 0) return SKLS_OK;
+    PhaseTimer pt("sketch_apply", s);
+    return with_value(A.dtype, [&](auto tv) -> int32_t {
+      using TV = decltype(tv);
+      if (A.layout == SKLS_DENSE) {
+        hipLaunchKernelGGL((k_sketch_dense_atomic<TV, TO>), dim3(grid_for(n * kWave, kThreads, 32768)),
+                           dim3(kThreads), 0, s, n, d, A.ld, tt, seed, static_cast<const TV*>(A.val), b, b_f64, w,
+                           static_cast<TO*>(SA), static_cast<TO*>(Sb));
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
       }
-      if (n == 0) return SKLS_OK;
-      PhaseTimer pt("sketch_apply", s);
-      return with_value(A.dtype, [&](auto tv) -> int32_t {
-        using TV = decltype(tv);
-        if (A.layout == SKLS_DENSE) {
-          hipLaunchKernelGGL((k_sketch_dense_atomic<TV, TO>), dim3(grid_for(n * kWave, kThreads, 32768)),
-                             dim3(kThreads), 0, s, n, d, A.ld, tt, seed, static_cast<const TV*>(A.val), b, b_f64, w,
-                             static_cast<TO*>(SA), static_cast<TO*>(Sb));
+      return with_rowptr(A, [&](auto tr) -> int32_t {
+        using TR = decltype(tr);
+        return with_lanes(lanes_per_row(A), [&](auto lc) -> int32_t {
+          constexpr int L = decltype(lc)::value;
+          hipLaunchKernelGGL((k_sketch_csr_atomic<TV, TR, TO, L>), dim3(grid_for(n * L, kThreads, 32768)),
+                             dim3(kThreads), 0, s, n, d, tt, seed, static_cast<const TR*>(A.row_ptr), A.col_idx,
+                             static_cast<const TV*>(A.val), b, b_f64, w, static_cast<TO*>(SA),
+                             static_cast<TO*>(Sb));
           SKLS_CHECK_LAUNCH();
           return SKLS_OK;
-        }
-        return with_rowptr(A, [&](auto tr) -> int32_t {
-          using TR = decltype(tr);
-          return with_lanes(lanes_per_row(A), [&](auto lc) -> int32_t {
-            constexpr int L = decltype(lc)::value;
-            hipLaunchKernelGGL((k_sketch_csr_atomic<TV, TR, TO, L>), dim3(grid_for(n * L, kThreads, 32768)),
-                               dim3(kThreads), 0, s, n, d, tt, seed, static_cast<const TR*>(A.row_ptr), A.col_idx,
-                               static_cast<const TV*>(A.val), b, b_f64, w, static_cast<TO*>(SA),
-                               static_cast<TO*>(Sb));
-            SKLS_CHECK_LAUNCH();
-            return SKLS_OK;
-          });
         });
       });
     });
-  }
+  });
+}
+
+// Build the bucket plan of a SORTED or BINNED sketch into P (b and w enter
+// CSR records only when given).
+int32_t plan_into(const skls_matrix& A, const BucketPlan& P, const void* b, int b_f64, uint32_t tt, HashKey seed,
+                  const float* w, int32_t out_dtype, hipStream_t s) {
+  const RowSrc src{A.layout == SKLS_CSR ? A.row_ptr : nullptr, b, b_f64, w};
+  const int64_t n = A.n;
+  PhaseTimer pt("sketch_plan", s);
+  if (A.layout != SKLS_CSR) return build_plan<int32_t>(n, tt, seed, P, src, s);
+  return with_out(out_dtype, [&](auto to) -> int32_t {
+    using TO = decltype(to);
+    return A.row_ptr_64 ? build_plan<CsrRec<int64_t, TO>>(n, tt, seed, P, src, s)
+                        : build_plan<CsrRec<int32_t, TO>>(n, tt, seed, P, src, s);
+  });
+}
+
+// Reduce with a built plan (S A zeroed first when several blocks share a bin).
+int32_t apply_with(const skls_matrix& A, const BucketPlan& P, const void* b, int b_f64, uint32_t tt, HashKey seed,
+                   const float* w, void* SA, void* Sb, int32_t out_dtype, const void* bg, hipStream_t s) {
+  return with_out(out_dtype, [&](auto to) -> int32_t {
+    using TO = decltype(to);
+    if (P.S.splits > 1) {
+      PhaseTimer pt("sketch_zero", s);
+      SKLS_TRY(launch_fill_zero(SA, static_cast<size_t>(tt) * A.d * sizeof(TO), s));
+      if (Sb) SKLS_TRY(launch_fill_zero(Sb, static_cast<size_t>(tt) * sizeof(TO), s));
+    }
+    PhaseTimer pt("sketch_apply", s);
+    return apply_planned<TO>(A, P, b, b_f64, tt, seed, w, static_cast<TO*>(SA), static_cast<TO*>(Sb), bg, s);
+  });
+}
+
+}  // namespace
+
+int32_t run_sketch_key(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, HashKey seed,
+                       const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
+                       size_t ws_bytes, hipStream_t s) {
+  const int ob = out_bytes_of(out_dtype);
+  const int32_t v = pick_variant(A, t, variant, ob);
+  SKLS_TRY(check_variant(A, t, v, ob, variant));
+  const int b_f64 = (b_dtype == SKLS_F64) ? 1 : 0;
+  const uint32_t tt = static_cast<uint32_t>(t);
+  if (v == SKLS_SKETCH_ATOMIC) return run_atomic(A, b, b_f64, tt, seed, w, SA, Sb, out_dtype, s);
   const PlanShape S = plan_shape(A, t, v, ob);
   Arena ar(ws, ws_bytes);
-  const BucketPlan P = carve_plan(ar, S, n, t);
+  const BucketPlan P = carve_plan(ar, S, A.n, t);
   if (!ws || !ar.fits()) {
     set_error("sketch workspace too small: need %zu bytes, have %zu", ar.used, ws_bytes);
     return SKLS_ERR_WORKSPACE;
   }
-  const RowSrc src{A.layout == SKLS_CSR ? A.row_ptr : nullptr, b, b_f64, w};
-  return with_out(out_dtype, [&](auto to) -> int32_t {
-    using TO = decltype(to);
-    {
-      PhaseTimer pt("sketch_plan", s);
-      if (A.layout == SKLS_CSR) {
-        const int32_t st = A.row_ptr_64 ? build_plan<CsrRec<int64_t, TO>>(n, tt, seed, P, src, s)
-                                        : build_plan<CsrRec<int32_t, TO>>(n, tt, seed, P, src, s);
-        SKLS_TRY(st);
-      } else {
-        SKLS_TRY(build_plan<int32_t>(n, tt, seed, P, src, s));
-      }
-      if (S.splits > 1) {
-        SKLS_TRY(launch_fill_zero(SA, static_cast<size_t>(t) * A.d * sizeof(TO), s));
-        if (Sb) SKLS_TRY(launch_fill_zero(Sb, static_cast<size_t>(t) * sizeof(TO), s));
-      }
-    }
-    PhaseTimer pt("sketch_apply", s);
-    return apply_planned<TO>(A, P, b, b_f64, tt, seed, w, static_cast<TO*>(SA), static_cast<TO*>(Sb), s);
-  });
+  SKLS_TRY(plan_into(A, P, b, b_f64, tt, seed, w, out_dtype, s));
+  return apply_with(A, P, b, b_f64, tt, seed, w, SA, Sb, out_dtype, nullptr, s);
+}
+
+// ---------------------------------------------------------------- reusable plans
+size_t sketch_plan_bytes(const skls_matrix& A, int64_t t, int32_t variant, int32_t out_dtype) {
+  const int ob = out_bytes_of(out_dtype);
+  const int32_t v = pick_variant(A, t, variant, ob);
+  if (v != SKLS_SKETCH_SORTED && v != SKLS_SKETCH_BINNED) return 0;
+  return plan_bytes(plan_shape(A, t, v, ob), A.n, t);
+}
+
+int32_t build_sketch_plan(const skls_matrix& A, int64_t t, HashKey seed, int32_t variant, int32_t out_dtype,
+                          void* plan, size_t plan_bytes_, int32_t* resolved, hipStream_t s) {
+  const int ob = out_bytes_of(out_dtype);
+  const int32_t v = pick_variant(A, t, variant, ob);
+  SKLS_TRY(check_variant(A, t, v, ob, variant));
+  *resolved = v;
+  if (v == SKLS_SKETCH_ATOMIC) return SKLS_OK;
+  Arena ar(plan, plan_bytes_);
+  const BucketPlan P = carve_plan(ar, plan_shape(A, t, v, ob), A.n, t);
+  if (!plan || !ar.fits()) {
+    set_error("sketch plan buffer too small: need %zu bytes, have %zu", ar.used, plan_bytes_);
+    return SKLS_ERR_WORKSPACE;
+  }
+  return plan_into(A, P, nullptr, 0, static_cast<uint32_t>(t), seed, nullptr, out_dtype, s);
+}
+
+int32_t apply_sketch_plan(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, HashKey seed,
+                          const float* w, int32_t resolved, void* SA, void* Sb, int32_t out_dtype, const void* plan,
+                          size_t plan_bytes_, hipStream_t s) {
+  const int ob = out_bytes_of(out_dtype);
+  SKLS_TRY(check_variant(A, t, resolved, ob, resolved));
+  const int b_f64 = (b_dtype == SKLS_F64) ? 1 : 0;
+  const uint32_t tt = static_cast<uint32_t>(t);
+  if (resolved == SKLS_SKETCH_ATOMIC) return run_atomic(A, b, b_f64, tt, seed, w, SA, Sb, out_dtype, s);
+  Arena ar(const_cast<void*>(plan), plan_bytes_);
+  const BucketPlan P = carve_plan(ar, plan_shape(A, t, resolved, ob), A.n, t);
+  if (!plan || !ar.fits()) {
+    set_error("sketch plan buffer too small: need %zu bytes, have %zu", ar.used, plan_bytes_);
+    return SKLS_ERR_WORKSPACE;
+  }
+  // CSR records of a reusable plan carry no share of S b: the reduce gathers b
+  return apply_with(A, P, b, b_f64, tt, seed, w, SA, Sb, out_dtype, A.layout == SKLS_CSR ? b : nullptr, s);
 }
 
 int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,

@@ -35,28 +35,37 @@ def signs(n: int, t: int, seed: int, device) -> torch.Tensor:
     return s.to(torch.float32)
 
 
-def prepare(mats: list[torch.Tensor], t: int, seed: int):
+def shared_plan(A: torch.Tensor, t: int, seed: int) -> api.SketchPlan:
+    """The bucket plan of the forward sketch: it depends only on (seed, n, t),
+    so one plan serves every matrix of the family."""
+    return api.sketch_plan(A, t, seed, variant="sorted", out_dtype=torch.float32)
+
+
+def prepare(mats: list[torch.Tensor], t: int, seed: int, plan: api.SketchPlan | None = None):
     """Gram matrices and normalisers ``||A^T A||_F^2`` (the loss at ``w = 0``)."""
     n = mats[0].shape[0]
     dev = mats[0].device
     ws = api.LearnedWorkspace(mats[0], t)
+    plan = shared_plan(mats[0], t, seed) if plan is None else plan
     zero = torch.zeros(n, dtype=torch.float32, device=dev)
     grams, norms = [], []
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     for A in mats:
         C = api.gram(A)
-        api.learned_grad(A, C, t, seed, zero, ws=ws, loss=loss, want_grad=False)
+        api.learned_grad(A, C, t, seed, zero, ws=ws, loss=loss, want_grad=False, plan=plan)
         grams.append(C)
         norms.append(float(loss.item()))
     return grams, norms, ws
 
 
-def distortions(mats, grams, norms, t: int, seed: int, w: torch.Tensor, ws=None) -> np.ndarray:
+def distortions(mats, grams, norms, t: int, seed: int, w: torch.Tensor, ws=None,
+                plan: api.SketchPlan | None = None) -> np.ndarray:
     """Normalised distortion of each matrix for values ``w``."""
     loss = torch.empty(1, dtype=torch.float32, device=w.device)
+    plan = shared_plan(mats[0], t, seed) if plan is None else plan
     out = []
     for A, C, nrm in zip(mats, grams, norms):
-        api.learned_grad(A, C, t, seed, w, ws=ws, loss=loss, want_grad=False)
+        api.learned_grad(A, C, t, seed, w, ws=ws, loss=loss, want_grad=False, plan=plan)
         out.append(float(loss.item()) / nrm)
     return np.array(out)
 
@@ -65,8 +74,9 @@ def train(train_mats, val_mats, t: int, seed: int, steps: int = 300, lr: float =
           rng_seed: int = 0, log_every: int = 0) -> TrainResult:
     n = train_mats[0].shape[0]
     dev = train_mats[0].device
-    grams, norms, ws = prepare(train_mats, t, seed)
-    vgrams, vnorms, _ = prepare(val_mats, t, seed)
+    plan = shared_plan(train_mats[0], t, seed)
+    grams, norms, ws = prepare(train_mats, t, seed, plan)
+    vgrams, vnorms, _ = prepare(val_mats, t, seed, plan)
     w = signs(n, t, seed, dev)
     w_plain = w.clone()
     m = torch.zeros_like(w)
@@ -80,12 +90,12 @@ def train(train_mats, val_mats, t: int, seed: int, steps: int = 300, lr: float =
         idx = rng.choice(len(train_mats), size=bsz, replace=False)
         for j, i in enumerate(idx):
             api.learned_grad(train_mats[i], grams[i], t, seed, w, ws=ws, loss=loss, grad=g,
-                             grad_scale=1.0 / (bsz * norms[i]), accumulate=j > 0)
+                             grad_scale=1.0 / (bsz * norms[i]), accumulate=j > 0, plan=plan)
         api.adam_step(w, g, m, v, step, lr)
         if log_every and (step % log_every == 0 or step == steps):
-            hist.append((step, float(distortions(val_mats, vgrams, vnorms, t, seed, w, ws).mean())))
-    d_plain = float(distortions(val_mats, vgrams, vnorms, t, seed, w_plain, ws).mean())
-    d_learned = float(distortions(val_mats, vgrams, vnorms, t, seed, w, ws).mean())
+            hist.append((step, float(distortions(val_mats, vgrams, vnorms, t, seed, w, ws, plan).mean())))
+    d_plain = float(distortions(val_mats, vgrams, vnorms, t, seed, w_plain, ws, plan).mean())
+    d_learned = float(distortions(val_mats, vgrams, vnorms, t, seed, w, ws, plan).mean())
     use = d_learned < d_plain
     return TrainResult(w=w if use else w_plain, learned=w, used_learned=use, val_plain=d_plain,
                        val_learned=d_learned, history=hist)
