@@ -206,6 +206,23 @@ SKLS_API int32_t skls_sketch_planned(const skls_matrix* A, const void* b, int32_
                                      size_t plan_bytes, void* stream);
 
 /*
+ * skls_sketch without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The bucket plan is kept in a fixed array of
+ * SKLS_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it
+ * runs on until the process ends; the call allocates nothing.  Arguments and
+ * results as for skls_sketch.  Inputs whose plan needs more than that
+ * (skls_sketch_workspace) are rejected with SKLS_ERR_WORKSPACE.  Every call
+ * on a device shares that device's array: calls that overlap on one device
+ * (other streams or host threads) race and must be serialised by the caller.
+ * Asynchronous.
+ */
+#define SKLS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+SKLS_API int32_t skls_sketch_noalloc(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
+                                     const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype,
+                                     void* stream);
+
+/*
  * Generalized sparse embedding (Section 5, the construction): a hash h sends
  * each row i to one of q groups; group g applies its own matrix B^(g), the
  * stack of `a` independent sparse embeddings sqrt(1/a) Phi_j D_j onto v

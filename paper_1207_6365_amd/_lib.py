@@ -194,6 +194,8 @@ SIGNATURES = {
                                    c_size_t, POINTER(SklsSketchPlanDesc), c_void_p]),
     "skls_sketch_planned": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                       POINTER(SklsSketchPlanDesc), c_void_p, c_size_t, c_void_p]),
+    "skls_sketch_noalloc": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_int64, c_uint64, c_void_p, c_int32,
+                                      c_void_p, c_void_p, c_int32, c_void_p]),
     "skls_sketch_general_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int64, c_int32, POINTER(c_size_t)]),
     "skls_sketch_general": (c_int32, [POINTER(SklsMatrix), c_void_p, c_int32, c_int64, c_int64, c_int32, c_uint64,
                                       c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
