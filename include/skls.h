@@ -280,13 +280,22 @@ typedef struct {
   int32_t sketch_only;  /* 1: return the sketch-and-solve x~ without iterating */
   int32_t variant;      /* sketch variant (SKLS_SKETCH_*) */
   const float* w;       /* learned sketch values (device float32 [n]) or NULL */
+  const double* x0;     /* device float64 [d] or NULL: start the iteration here instead of at the
+                           sketch-and-solve x~ (Section 7.7 starts from any x(0) whose error is at
+                           most that of x = 0); the sketch still provides R */
+  int32_t max_retries;  /* extra attempts with a new sketch when one fails (0: none): a sketch whose
+                           S A is rank deficient, or an iteration that does not certify within
+                           max_iter.  Attempt r uses seed + r * 0x9E3779B97F4A7C15 (mod 2^64); the
+                           failure probability of a sparse embedding (Section 3) then drops
+                           geometrically with the attempts */
+  int32_t reserved;
 } skls_lstsq_opts;
 
 typedef struct {
   int32_t iterations;     /* LSQR iterations run */
   int32_t refinements;    /* outer float64 residual refinements (mixed) */
   int32_t certified;      /* 1 if the stopping certificate holds at the result */
-  int32_t reserved;
+  int32_t retries;        /* attempts after the first (each with a new sketch) */
   double resid_norm;      /* ||b - A x|| at the result (float64 accumulation) */
   double grad_norm;       /* ||R^{-T} A^T (b - A x)|| at the result */
   double ratio_bound;     /* certified bound on ||Ax-b|| / min ||Ax-b|| (given sigma_lb) */
@@ -307,6 +316,7 @@ SKLS_API int32_t skls_lstsq_workspace(const skls_matrix* A, const skls_lstsq_opt
  *  b:    device float64 [n].
  *  x:    device float64 [d], output.
  *  info: host, may be NULL.
+ * With max_retries, a failed attempt is repeated with a new seed (info->retries).
  * Returns SKLS_ERR_RANK if S A is rank deficient (x unspecified) and
  * SKLS_ERR_NOCONV if max_iter ran out (x = last iterate).  Synchronous.
  */

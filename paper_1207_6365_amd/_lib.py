@@ -69,6 +69,9 @@ class SklsLstsqOpts(ctypes.Structure):
         ("sketch_only", c_int32),
         ("variant", c_int32),
         ("w", c_void_p),
+        ("x0", c_void_p),
+        ("max_retries", c_int32),
+        ("reserved", c_int32),
     ]
 
 
@@ -77,7 +80,7 @@ class SklsLstsqInfo(ctypes.Structure):
         ("iterations", c_int32),
         ("refinements", c_int32),
         ("certified", c_int32),
-        ("reserved", c_int32),
+        ("retries", c_int32),
         ("resid_norm", c_double),
         ("grad_norm", c_double),
         ("ratio_bound", c_double),

@@ -215,18 +215,25 @@ def qr_r(M: torch.Tensor, inverse: bool = True):
 # ------------------------------------------------------------------ a3 + a4
 def lstsq(A, b: torch.Tensor, t: int, seed: int, delta: float = 1e-6, precision: str = "plain",
           sigma_lb: float = 0.5, max_iter: int = 100, sketch_only: bool = False, variant: str = "auto",
-          w: torch.Tensor | None = None, raise_noconv: bool = True):
+          w: torch.Tensor | None = None, raise_noconv: bool = True, x0: torch.Tensor | None = None,
+          max_retries: int = 0):
     """Least squares ``min ||A x - b||``: sketch-and-solve, then R-preconditioned
-    LSQR to a certified residual ratio ``<= 1 + delta``.  Returns ``(x, info)``."""
+    LSQR to a certified residual ratio ``<= 1 + delta``.  ``x0``: start of the
+    iteration in place of the sketch-and-solve solution; ``max_retries``:
+    extra attempts with a new sketch after a failed one.  Returns ``(x, info)``."""
     m, device = _matrix(A)
     if b.dtype != torch.float64 or not b.is_contiguous() or b.numel() != m.n:
         raise TypeError("b must be a contiguous float64 vector with n entries")
+    if x0 is not None and (x0.dtype != torch.float64 or not x0.is_contiguous() or x0.numel() != m.d):
+        raise TypeError("x0 must be a contiguous float64 vector with d entries")
     o = L.SklsLstsqOpts()
     o.t, o.seed, o.delta, o.sigma_lb, o.max_iter = t, seed & 0xFFFFFFFFFFFFFFFF, delta, sigma_lb, max_iter
     o.precision = {"plain": 0, "mixed": 1}[precision]
     o.sketch_only = 1 if sketch_only else 0
     o.variant = _VARIANT[variant]
     o.w = _ptr(w)
+    o.x0 = _ptr(x0)
+    o.max_retries = max_retries
     ws = _workspace(_size(lib().skls_lstsq_workspace, ctypes.byref(m), ctypes.byref(o)), device)
     x = torch.empty(m.d, dtype=torch.float64, device=device)
     info = L.SklsLstsqInfo()

@@ -130,8 +130,7 @@ int32_t qr_from(const void* M, int32_t dtype, const void* v, int32_t v_dtype, in
                 double* R, double* Rinv, double* RinvT, hipStream_t s) {
   const int64_t dd = d + (v ? 1 : 0);
   SKLS_TRY(run_gram(M, dtype, d, v, v_dtype, m, d, q.G, q.gram, q.gram_bytes, s));
-  SKLS_TRY(run_cholesky(q.G, dd, d, R, q.status, q.W, s));
-  if (Rinv) SKLS_TRY(run_trinv(R, d, Rinv, RinvT, s, cholesky_block_inverses(q.W, d)));
+  SKLS_TRY(run_cholesky(q.G, dd, d, R, Rinv, Rinv ? RinvT : nullptr, q.status, q.W, s));
   return SKLS_OK;
 }
 
@@ -260,6 +259,10 @@ int32_t check_lstsq(const skls_matrix* A, const skls_lstsq_opts* opts) {
   }
   if (opts->sigma_lb > 1.0 || opts->delta < 0.0) {
     set_error("need 0 < sigma_lb <= 1 and delta >= 0");
+    return SKLS_ERR_ARG;
+  }
+  if (opts->max_retries < 0 || opts->max_retries > 64) {
+    set_error("max_retries must lie in [0, 64]");
     return SKLS_ERR_ARG;
   }
   return SKLS_OK;
@@ -560,27 +563,14 @@ int32_t skls_lstsq_workspace(const skls_matrix* A, const skls_lstsq_opts* opts, 
   return SKLS_OK;
 }
 
-int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_lstsq_opts* opts, double* x,
-                   skls_lstsq_info* info, void* ws, size_t ws_bytes, void* stream) {
-  clear_error();
-  SKLS_TRY(check_lstsq(A, opts));
-  if (b == nullptr || x == nullptr) {
-    set_error("b and x must be non-NULL");
-    return SKLS_ERR_ARG;
-  }
-  if (A->d > 8192) {
-    set_error("lstsq supports d <= 8192");
-    return SKLS_ERR_SHAPE;
-  }
-  skls_lstsq_opts o = *opts;
-  fill_opts(o);
+namespace {
+
+// One attempt of skls_lstsq with the seed in o (options filled, workspace
+// carved); inf is reset and filled.
+int32_t lstsq_once(const skls_matrix* A, const double* b, const skls_lstsq_opts& o, double* x, LsWs& L,
+                   skls_lstsq_info& inf, hipStream_t s) {
   const bool plain = o.precision == 0;
   const int64_t d = A->d, dd = d + 1;
-  hipStream_t s = as_stream(stream);
-  Arena ar(ws, ws_bytes);
-  LsWs L = carve_ls(ar, *A, o);
-  SKLS_TRY(need_ws(ar, ws, ws_bytes));
-  skls_lstsq_info inf;
   std::memset(&inf, 0, sizeof inf);
   inf.resid_norm = inf.grad_norm = inf.ratio_bound = -1.0;
 
@@ -599,7 +589,11 @@ int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_lstsq_opts*
   SKLS_TRY(run_sketch(*A, b, SKLS_F64, o.t, o.seed, o.w, o.variant, L.SA, L.Sb, sk_dtype, L.sk, L.sk_bytes, s));
   SKLS_TRY_HIP(hipEventRecord(ev[1], s));
   SKLS_TRY(qr_from(L.SA, sk_dtype, L.Sb, sk_dtype, o.t, d, L.q, L.R, L.Rinv, L.q.RinvT, s));
-  SKLS_TRY(run_solve_from_gram(L.Rinv, L.q.RinvT, L.q.G + d * dd, d, x, L.tmp, s));
+  if (o.x0 != nullptr) {
+    SKLS_TRY_HIP(hipMemcpyAsync(x, o.x0, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
+  } else {
+    SKLS_TRY(run_solve_from_gram(L.Rinv, L.q.RinvT, L.q.G + d * dd, d, x, L.tmp, s));
+  }
   SKLS_TRY_HIP(hipEventRecord(ev[2], s));
   int32_t rank_bad = 0;
   double sb_norm2 = 0.0;  // ||S b||^2, close to ||b||^2 for an embedding
@@ -611,14 +605,10 @@ int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_lstsq_opts*
   SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
   inf.ms_qr = ms;
   if (rank_bad) {
-    if (info) *info = inf;
     set_error("the sketch S A is numerically rank deficient");
     return SKLS_ERR_RANK;
   }
-  if (o.sketch_only) {
-    if (info) *info = inf;
-    return SKLS_OK;
-  }
+  if (o.sketch_only) return SKLS_OK;
 
   // --- R-preconditioned LSQR on M = A R^{-1} (Section 7.7), with float64
   //     residual refinement.  Plain: every pass in float64.  Mixed: inner
@@ -706,9 +696,43 @@ int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_lstsq_opts*
     const double r2 = inf.resid_norm * inf.resid_norm - e * e;
     inf.ratio_bound = (r2 > 0.0) ? std::sqrt(1.0 + e * e / r2) : INFINITY;
   }
-  if (info) *info = inf;
   if (status == SKLS_ERR_NOCONV) set_error("LSQR did not certify the target within max_iter=%d", o.max_iter);
   return status;
+}
+
+}  // namespace
+
+int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_lstsq_opts* opts, double* x,
+                   skls_lstsq_info* info, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKLS_TRY(check_lstsq(A, opts));
+  if (b == nullptr || x == nullptr) {
+    set_error("b and x must be non-NULL");
+    return SKLS_ERR_ARG;
+  }
+  if (A->d > 8192) {
+    set_error("lstsq supports d <= 8192");
+    return SKLS_ERR_SHAPE;
+  }
+  skls_lstsq_opts o = *opts;
+  fill_opts(o);
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  LsWs L = carve_ls(ar, *A, o);
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  // attempt r sketches with seed + r * golden gamma: a fresh, independent S
+  int32_t st = SKLS_OK;
+  skls_lstsq_info inf;
+  for (int32_t r = 0;; ++r) {
+    skls_lstsq_opts a = o;
+    a.seed = o.seed + static_cast<uint64_t>(r) * 0x9E3779B97F4A7C15ull;
+    clear_error();
+    st = lstsq_once(A, b, a, x, L, inf, s);
+    inf.retries = r;
+    if ((st != SKLS_ERR_RANK && st != SKLS_ERR_NOCONV) || r >= o.max_retries) break;
+  }
+  if (info) *info = inf;
+  return st;
 }
 
 int32_t skls_leverage_workspace(const skls_matrix* A, int64_t t, int32_t k, size_t* bytes) {

@@ -282,20 +282,129 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 // kCB rows: factor the diagonal block in LDS (and invert it), solve for the
 // block row to its right, then update the trailing upper triangle.
 constexpr int kCB = 64;
+constexpr int kCP = kCB + 1;  // LDS pitch of a 64 x 64 tile of doubles
 
-// x = r^{-1} for the kb x kb upper triangle r (kb <= kCB), in LDS, by
-// doubling: with the inverses of two neighbouring diagonal blocks known, the
-// block above the diagonal between them is -X11 (R12 X22).  `t` holds the
-// products R12 X22 of one level (at most kCB * kCB / 4 values).  The whole
-// block of threads takes part; x is zero below the diagonal.
-__device__ void tri_inv_lds(const double (*r)[kCB + 1], double (*x)[kCB + 1], double* t, int kb) {
+// C (the 32 x 32 quadrant (wi, wj) of a 64 x 64 product, as 2 x 2 MFMA
+// tiles of 16 x 16) += A^T B for A, B held in LDS by inner index:
+// A[k][m], B[k][n], k in [0, 64).  Four wavefronts, one quadrant each.
+// Accumulator element e of lane l: row wi * 32 + a * 16 + l / 16 + 4 e,
+// column wj * 32 + b * 16 + l % 16.
+__device__ __forceinline__ void mfma_atb64(const double (*A)[kCP], const double (*B)[kCP], d4_t (&acc)[2][2]) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int wi = wv >> 1, wj = wv & 1;
+  const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll 4
+  for (int kk = 0; kk < kCB; kk += 4) {
+    const double a0 = A[kk + lr][wi * 32 + lc], a1 = A[kk + lr][wi * 32 + 16 + lc];
+    const double b0 = B[kk + lr][wj * 32 + lc], b1 = B[kk + lr][wj * 32 + 16 + lc];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void for_acc(F&& f) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int wi = wv >> 1, wj = wv & 1;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) f(a, b, e, wi * 32 + a * 16 + (lane >> 4) + 4 * e, wj * 32 + b * 16 + (lane & 15));
+}
+
+__device__ __forceinline__ void zero_acc(d4_t (&acc)[2][2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+}
+
+// dst = the 64 x 64 tile at src (leading dimension ld), rows < nr and
+// columns < nc, zero elsewhere; TRANS stores it transposed.  Every thread's
+// sixteen loads are in flight before its LDS stores (the tiles sit in L2,
+// so the latency of one load would otherwise be paid sixteen times).
+template <bool TRANS>
+__device__ __forceinline__ void tile_to_lds(double (*dst)[kCP], const double* __restrict__ src, int64_t ld, int nr,
+                                            int nc) {
+  double v[kCB * kCB / 256];
+#pragma unroll
+  for (int u = 0; u < kCB * kCB / 256; ++u) {
+    const int e = static_cast<int>(threadIdx.x) + 256 * u;
+    const int r = e >> 6, c = e & (kCB - 1);
+    v[u] = (r < nr && c < nc) ? src[static_cast<int64_t>(r) * ld + c] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kCB * kCB / 256; ++u) {
+    const int e = static_cast<int>(threadIdx.x) + 256 * u;
+    const int r = e >> 6, c = e & (kCB - 1);
+    if (TRANS)
+      dst[c][r] = v[u];
+    else
+      dst[r][c] = v[u];
+  }
+}
+
+// One level b in {16, 32} of the doubling inverse on the matrix cores:
+// for each merge of two b x b diagonal blocks at o1 = 2 m b, o2 = o1 + b,
+// T = r[o1:o2, o2:o2+b] x[o2.., o2..], then x[o1:o2, o2:o2+b] = -x[o1:o2, o1:o2] T.
+// Entries past the tile's size are zero in r and x, so the full 64 x 64 is
+// processed.  Wavefront w takes the 16 x 16 output tile w of the level.
+template <int B>
+__device__ __forceinline__ void inv_level_mfma(const double (*r)[kCP], double (*x)[kCP], double* t) {
+  constexpr int kTiles = (B / 16) * (B / 16);  // output tiles per merge
+  constexpr int kMerges = kCB / (2 * B);
+  static_assert(kTiles * kMerges <= 4, "at most one tile per wavefront");
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int lr = lane >> 4, lc = lane & 15;
+  const bool busy = wv < kTiles * kMerges;
+  const int m = wv / kTiles, tile = wv % kTiles;
+  const int ti = tile / (B / 16), tj = tile % (B / 16);
+  const int o1 = 2 * m * B, o2 = o1 + B;
+  double* tm = t + m * B * B;  // T of this merge, B x B row-major
+  if (busy) {
+    d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < B; kk += 4) {
+      const double a = r[o1 + ti * 16 + lc][o2 + kk + lr];
+      const double b = x[o2 + kk + lr][o2 + tj * 16 + lc];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) tm[(ti * 16 + lr + 4 * e) * B + tj * 16 + lc] = acc[e];
+  }
+  __syncthreads();
+  if (busy) {
+    d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < B; kk += 4) {
+      const double a = x[o1 + ti * 16 + lc][o1 + kk + lr];
+      const double b = tm[(kk + lr) * B + tj * 16 + lc];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[o1 + ti * 16 + lr + 4 * e][o2 + tj * 16 + lc] = -acc[e];
+  }
+  __syncthreads();
+}
+
+// x = r^{-1} for the kb x kb upper triangle r (kb <= kCB, r zero elsewhere),
+// in LDS, by doubling: with the inverses of two neighbouring diagonal blocks
+// known, the block above the diagonal between them is -X11 (R12 X22).  The
+// levels of 1 to 8 columns run on vector units, those of 16 and 32 on the
+// matrix cores.  `t` holds at least kCB * kCB / 4 values.  The whole block of
+// 256 threads takes part; x is zero below the diagonal and past kb.
+__device__ void tri_inv_lds(const double (*r)[kCP], double (*x)[kCP], double* t, int kb) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < kCB * kCB; e += nt) {
     const int i = e / kCB, j = e % kCB;
     x[i][j] = (i == j && i < kb) ? 1.0 / r[i][i] : 0.0;
   }
   __syncthreads();
-  for (int sb = 0; (1 << sb) < kb; ++sb) {
+  for (int sb = 0; sb < 4 && (1 << sb) < kb; ++sb) {
     const int b = 1 << sb, mb = b - 1;
     const int nm = (kb + 2 * b - 1) >> (sb + 1);  // merges (the last may lack a right block)
     // t_m[i][j] = sum_l r[o1 + i][o2 + l] x[o2 + l][o2 + j], l <= j
@@ -303,14 +412,9 @@ __device__ void tri_inv_lds(const double (*r)[kCB + 1], double (*x)[kCB + 1], do
       const int m = e >> (2 * sb), i = (e >> sb) & mb, j = e & mb;
       const int o1 = (2 * m) << sb, o2 = o1 + b;
       if (o2 + j >= kb) continue;
-      double s0 = 0.0, s1 = 0.0;
-      int l = 0;
-      for (; l + 1 <= j; l += 2) {
-        s0 += r[o1 + i][o2 + l] * x[o2 + l][o2 + j];
-        s1 += r[o1 + i][o2 + l + 1] * x[o2 + l + 1][o2 + j];
-      }
-      if (l <= j) s0 += r[o1 + i][o2 + l] * x[o2 + l][o2 + j];
-      t[e] = s0 + s1;
+      double s0 = 0.0;
+      for (int l = 0; l <= j; ++l) s0 += r[o1 + i][o2 + l] * x[o2 + l][o2 + j];
+      t[e] = s0;
     }
     __syncthreads();
     // x[o1 + i][o2 + j] = -sum_l x[o1 + i][o1 + l] t_m[l][j], l >= i
@@ -319,203 +423,325 @@ __device__ void tri_inv_lds(const double (*r)[kCB + 1], double (*x)[kCB + 1], do
       const int o1 = (2 * m) << sb, o2 = o1 + b;
       if (o2 + j >= kb) continue;
       const double* tm = t + (m << (2 * sb));
-      double s0 = 0.0, s1 = 0.0;
-      int l = i;
-      for (; l + 1 < b; l += 2) {
-        s0 += x[o1 + i][o1 + l] * tm[(l << sb) + j];
-        s1 += x[o1 + i][o1 + l + 1] * tm[((l + 1) << sb) + j];
-      }
-      if (l < b) s0 += x[o1 + i][o1 + l] * tm[(l << sb) + j];
-      x[o1 + i][o2 + j] = -(s0 + s1);
+      double s0 = 0.0;
+      for (int l = i; l < b; ++l) s0 += x[o1 + i][o1 + l] * tm[(l << sb) + j];
+      x[o1 + i][o2 + j] = -s0;
     }
     __syncthreads();
   }
+  if (kb > 16) inv_level_mfma<16>(r, x, t);
+  if (kb > 32) inv_level_mfma<32>(r, x, t);
 }
 
-// W[K:K+kb, K:K+kb] -> R_KK (in place) and Kinv = R_KK^{-1} (kb x kb, ld kCB).
-// Right-looking factorisation with the trailing triangle in registers: wave
-// g, lane j holds rows g, g + 4, ..., g + 60 of column j.  Step k publishes
-// row k (double-buffered in LDS, stored by residue class of the row index so
-// that each wave reads its 16 values as 8 contiguous pairs), then every
-// thread updates its column: one barrier per column, no LDS round trip in
-// the update.
-__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ W, int d, int K, double* __restrict__ Kinv,
-                                                   int32_t* __restrict__ bad) {
-  __shared__ double a[kCB][kCB + 1];   // the inverse
-  __shared__ double rr[kCB][kCB + 1];  // R_KK
-  __shared__ double t[kCB * kCB / 4];
-  __shared__ __align__(16) double prow[2][4][kCB / 4 + 2];  // row k of the trailing block, [i % 4][i / 4]
+// 1 / x to double precision: the hardware reciprocal estimate refined by two
+// Newton steps (each roughly doubles the correct bits).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Factor the kb x kb tile whose upper triangle thread (g, j) (g = wave,
+// j = lane) holds in c[q] = element (4 q + g, j) into rr = R_KK (upper, zero
+// elsewhere).  Right-looking with the trailing triangle in registers: step k
+// publishes row k (double-buffered in LDS, stored by residue class of the row
+// index so that each wave reads its 16 values as 8 contiguous pairs), then
+// every thread updates its column: one barrier per column.  To keep the
+// chain from one column to the next short:
+//  * the update uses a_ij - a_ki (a_kj / a_kk), so the chain holds one
+//    reciprocal of the pivot and no square root;
+//  * the wave that owns row k + 1 updates and publishes it before the rest
+//    of its column, so the next barrier does not wait for the other updates;
+//  * R's rows are scaled by 1 / sqrt(pivot) after the loop.
+// The columns run as a loop over groups of four (not unrolled: straight-line
+// code for all 64 columns would be fetched once and run once, and its
+// instruction fetches dominated); after each group the registers shift down
+// by one, so c[0] always holds the group's own rows and every register index
+// is fixed.  Elements below the diagonal (i > j) are updated too; they are
+// never published or read.  Returns 1 on this thread if a pivot was not
+// positive.
+__device__ int factor_tile_regs(double (&c)[kCB / 4], double (*rr)[kCP], double (*prow)[4][kCB / 4 + 2], int kb) {
+  __shared__ double piv_of[kCB];
+  const int tid = threadIdx.x;
+  // the wave index in a scalar register: the row tests below are branches
+  const int j = tid & (kCB - 1), g = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < kCB * kCP; e += 256) (&rr[0][0])[e] = 0.0;
+  int badk = 0;
+  if (g == 0) prow[0][j & 3][j >> 2] = c[0];  // row 0
+  for (int qk = 0; 4 * qk < kb; ++qk) {
+#pragma unroll
+    for (int gk = 0; gk < 4; ++gk) {
+      const int k = 4 * qk + gk;
+      if (k < kb) {
+        const double (*pr)[kCB / 4 + 2] = prow[gk & 1];  // k & 1
+        __syncthreads();  // row k is published
+        double piv = pr[gk][qk];
+        if (!(piv > 0.0)) {
+          badk = 1;
+          piv = 1.0;
+        }
+        const double ip = recip(piv);
+        const double akj = j >= k ? pr[j & 3][j >> 2] : 0.0;
+        const double f = akj * ip;
+        // row k at this thread's rows 4 (qk + q) + g (indices past the last
+        // row clamped: those registers are not used)
+        double rowk[kCB / 4];
+#pragma unroll
+        for (int q = 0; q < kCB / 4; ++q) rowk[q] = pr[g][(qk + q) < kCB / 4 ? qk + q : kCB / 4 - 1];
+        // row k + 1 first: owned by wave (k + 1) & 3, register (gk + 1) >> 2
+        const int q1 = (gk + 1) >> 2;
+        const int g1 = (gk + 1) & 3, k1 = k + 1;
+        if (k1 < kb && g == g1) {
+          c[q1] -= rowk[q1] * f;
+          if (j >= k1) prow[(gk + 1) & 1][j & 3][j >> 2] = c[q1];
+        }
+        if (g == 0 && j >= k && j < kb) rr[k][j] = akj;  // scaled below
+        if (g == 0 && j == k) piv_of[k] = piv;
+        if (g > gk && !(q1 == 0 && g == g1)) c[0] -= rowk[0] * f;
+#pragma unroll
+        for (int q = 1; q < kCB / 4; ++q)
+          if (!(q == q1 && g == g1)) c[q] -= rowk[q] * f;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q + 1 < kCB / 4; ++q) c[q] = c[q + 1];
+    c[kCB / 4 - 1] = 0.0;
+  }
+  __syncthreads();
+  // R_kj = a_kj / sqrt(pivot_k) with a_kj the values at step k
+  for (int e = tid; e < kb * kCB; e += 256) {
+    const int k = e / kCB, jj = e % kCB;
+    if (jj >= k && jj < kb) {
+      const double rk = sqrt(piv_of[k]);
+      rr[k][jj] = jj == k ? rk : rr[k][jj] / rk;
+    }
+  }
+  __syncthreads();
+  return badk;
+}
+
+// Where the factorisation writes R^{-1} (and its transpose), or nulls.
+struct InvOut {
+  double* X;   // d x d, R^{-1}
+  double* XT;  // d x d, R^{-T}
+};
+
+// Factor + invert a diagonal tile held in c[] (see factor_tile_regs): writes
+// R_KK into R (rows / columns K .. K + kb), its inverse into Kinv (ld kCB)
+// and, when asked, into the diagonal block of R^{-1} and R^{-T}.
+__device__ void finish_tile(double (&c)[kCB / 4], double* __restrict__ R, int d, int K, double* __restrict__ Kinv,
+                            int32_t* __restrict__ bad, double (*rr)[kCP], double (*x)[kCP], double* t,
+                            double (*prow)[4][kCB / 4 + 2], InvOut inv) {
   const int kb = (d - K) < kCB ? (d - K) : kCB;
+  const int tid = threadIdx.x;
+  const int j = tid & (kCB - 1), g = tid >> 6;
+  const int badk = factor_tile_regs(c, rr, prow, kb);
+  if (badk) atomicOr(bad, 1);
+  for (int i = g; i < kb; i += 4)
+    if (j >= i && j < kb) R[static_cast<size_t>(K + i) * d + K + j] = rr[i][j];
+  tri_inv_lds(rr, x, t, kb);
+  for (int i = g; i < kb; i += 4)
+    if (j < kb) {
+      Kinv[i * kCB + j] = x[i][j];
+      if (inv.X != nullptr && j >= i) {
+        inv.X[static_cast<size_t>(K + i) * d + K + j] = x[i][j];
+        inv.XT[static_cast<size_t>(K + j) * d + K + i] = x[i][j];
+      }
+    }
+}
+
+// Block column K of X = R^{-1} above the diagonal, from X R = I:
+//   X[J, K] = -(sum_{M = J .. K-1} X[J, M] R[M, K]) Kinv_K,   J < K,
+// which needs only the columns of X before K, the rows of R above block row
+// K in column K, and Kinv_K: all known once tile K is factored.  One block
+// of 256 threads per J; a, b are 64 x 64 LDS tiles.  Writes X[J, K] and its
+// transpose.
+__device__ __forceinline__ void inv_column_tile(const double* __restrict__ R, int d, int J, int K, const double* __restrict__ Kinv,
+                                InvOut inv, double (*a)[kCP], double (*b)[kCP]) {
+  const int tid = threadIdx.x;
+  const int J0 = J * kCB, K0 = K * kCB;
+  const int kbj = (d - J0) < kCB ? (d - J0) : kCB, kbk = (d - K0) < kCB ? (d - K0) : kCB;
+  d4_t acc[2][2];
+  zero_acc(acc);
+  for (int M = J; M < K; ++M) {
+    const int M0 = M * kCB;
+    const int kbm = (d - M0) < kCB ? (d - M0) : kCB;
+    __syncthreads();
+    // a[k][m] = X[J0 + m][M0 + k] (transposed for the A^T B product), b = R[M, K]
+    tile_to_lds<true>(a, inv.X + static_cast<size_t>(J0) * d + M0, d, kbj, kbm);
+    tile_to_lds<false>(b, R + static_cast<size_t>(M0) * d + K0, d, kbm, kbk);
+    __syncthreads();
+    mfma_atb64(a, b, acc);
+  }
+  __syncthreads();
+  // a[k][m] = acc[m][k], b = Kinv_K
+  for_acc([&](int i, int j, int e, int row, int col) { a[col][row] = acc[i][j][e]; });
+  tile_to_lds<false>(b, Kinv + static_cast<size_t>(K) * kCB * kCB, kCB, kbk, kbk);
+  __syncthreads();
+  zero_acc(acc);
+  mfma_atb64(a, b, acc);
+  for_acc([&](int i, int j, int e, int row, int col) {
+    if (row < kbj && col < kbk) {
+      inv.X[static_cast<size_t>(J0 + row) * d + K0 + col] = -acc[i][j][e];
+      inv.XT[static_cast<size_t>(K0 + col) * d + J0 + row] = -acc[i][j][e];
+    }
+  });
+}
+
+// First diagonal tile: W[0:kb, 0:kb] -> R_00 and its inverse.
+__global__ __launch_bounds__(256) void k_chol_first(const double* __restrict__ W, double* __restrict__ R, int d,
+                                                    double* __restrict__ Kinv, int32_t* __restrict__ bad,
+                                                    InvOut inv) {
+  __shared__ double rr[kCB][kCP];
+  __shared__ double x[kCB][kCP];
+  __shared__ double t[kCB * kCB / 4];
+  __shared__ __align__(16) double prow[2][4][kCB / 4 + 2];
+  const int kb = d < kCB ? d : kCB;
   const int tid = threadIdx.x;
   const int j = tid & (kCB - 1), g = tid >> 6;
   double c[kCB / 4];
 #pragma unroll
   for (int q = 0; q < kCB / 4; ++q) {
     const int i = 4 * q + g;
-    c[q] = (j < kb && i <= j) ? W[static_cast<size_t>(K + i) * d + K + j] : 0.0;
+    c[q] = (j < kb && i <= j) ? W[static_cast<size_t>(i) * d + j] : 0.0;
   }
-  for (int e = tid; e < kCB * (kCB + 1); e += 256) (&rr[0][0])[e] = 0.0;
-  int badk = 0;
-#pragma unroll
-  for (int qk = 0; qk < kCB / 4; ++qk) {
-#pragma unroll
-    for (int gk = 0; gk < 4; ++gk) {
-      const int k = 4 * qk + gk;
-      if (k < kb) {
-        double (*pr)[kCB / 4 + 2] = prow[k & 1];
-        if (g == gk && j >= k) pr[j & 3][j >> 2] = c[qk];
-        __syncthreads();
-        double piv = pr[gk][qk];
-        if (!(piv > 0.0)) {
-          badk = 1;
-          piv = 1.0;
-        }
-        const double rk = sqrt(piv);
-        const double ri = 1.0 / rk;
-        const double akj = j >= k ? pr[j & 3][j >> 2] : 0.0;
-        const double rkj = akj * ri;
-        if (g == 0 && j >= k && j < kb) rr[k][j] = j == k ? rk : rkj;
-        const double f = rkj * ri;
-        double rowk[kCB / 4];
-#pragma unroll
-        for (int q = 0; q < kCB / 4; q += 2) {
-          const double2 v = *reinterpret_cast<const double2*>(&pr[g][q]);
-          rowk[q] = v.x;
-          rowk[q + 1] = v.y;
-        }
-#pragma unroll
-        for (int q = 0; q < kCB / 4; ++q) {
-          const int i = 4 * q + g;
-          if (q >= qk) c[q] = (i > k && i <= j) ? c[q] - rowk[q] * f : c[q];
-        }
-      }
-    }
-  }
-  if (badk && tid == 0) bad[0] = 1;
-  __syncthreads();
-  for (int i = g; i < kb; i += 4)
-    if (j >= i && j < kb) W[static_cast<size_t>(K + i) * d + K + j] = rr[i][j];
-  tri_inv_lds(rr, a, t, kb);
-  for (int i = g; i < kb; i += 4)
-    if (j < kb) Kinv[i * kCB + j] = a[i][j];
+  finish_tile(c, R, d, 0, Kinv, bad, rr, x, t, prow, inv);
 }
 
-constexpr int kCL = 32;  // rows of the panels staged per step
-
-// Block row solve: W[K:K+kb, J0:J0+64] <- R_KK^{-T} W[K:K+kb, J0:J0+64].
-__global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ W, int d, int K,
-                                                   const double* __restrict__ Kinv) {
-  __shared__ double ki[kCL][kCB + 1];
-  __shared__ double p[kCL][kCB + 1];
-  const int kb = (d - K) < kCB ? (d - K) : kCB;
-  const int J0 = K + kb + blockIdx.x * kCB;
-  const int tid = threadIdx.x;
-  const int j = tid % kCB, i0 = tid / kCB;  // this thread: rows i0, i0+4, ..., column j
-  double acc[kCB / 4];
-#pragma unroll
-  for (int q = 0; q < kCB / 4; ++q) acc[q] = 0.0;
-  for (int l0 = 0; l0 < kb; l0 += kCL) {
-    __syncthreads();
-    for (int e = tid; e < kCL * kCB; e += 256) {
-      const int l = e / kCB, c = e % kCB;
-      ki[l][c] = (l0 + l < kb && c < kb) ? Kinv[(l0 + l) * kCB + c] : 0.0;
-      p[l][c] = (l0 + l < kb && J0 + c < d) ? W[static_cast<size_t>(K + l0 + l) * d + J0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kCB / 4; ++q) {
-      const int i = i0 + 4 * q;
-      double s = 0.0;
-      for (int l = 0; l < kCL; ++l) s += ki[l][i] * p[l][j];  // Kinv is upper: ki[l][i] = 0 for l > i
-      acc[q] += s;
-    }
+// One step of the blocked Cholesky after block column K is factored (R_KK
+// and Kinv_K = R_KK^{-1} known).  Block (ti, tj), ti <= tj, of the trailing
+// block triangle, I = K + 1 + ti, J = K + 1 + tj (64-column blocks):
+//   P_I = Kinv_K^T W[K, I], P_J = Kinv_K^T W[K, J]     (the rows R[K, I], R[K, J])
+//   W[I, J] -= P_I^T P_J                                (on the matrix cores)
+// The block of the diagonal tile (I, I) writes R[K, I] = P_I; the block of
+// (K + 1, K + 1) then factors the updated tile and inverts it, so the next
+// step finds R_{K+1,K+1} and Kinv_{K+1} ready.  W's block row K is only
+// read (the solved rows go to R), so blocks may recompute the same P_I.
+__global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ W, double* __restrict__ R, int d, int K,
+                                                   double* __restrict__ Kinv, int32_t* __restrict__ bad,
+                                                   InvOut inv) {
+  __shared__ double ki[kCB][kCP];
+  __shared__ double pI[kCB][kCP];
+  __shared__ double pJ[kCB][kCP];
+  __shared__ double t[kCB * kCB / 4];
+  __shared__ __align__(16) double prow[2][4][kCB / 4 + 2];
+  const int nb = (d + kCB - 1) / kCB;
+  const int T = nb - K - 1;
+  const int ntrail = T * (T + 1) / 2;
+  if (static_cast<int>(blockIdx.x) >= ntrail) {
+    // the blocks past the trailing update form block column K of R^{-1}
+    inv_column_tile(R, d, static_cast<int>(blockIdx.x) - ntrail, K, Kinv, inv, pI, pJ);
+    return;
   }
-  __syncthreads();  // every panel row is read before any is overwritten
-  if (J0 + j < d) {
-#pragma unroll
-    for (int q = 0; q < kCB / 4; ++q) {
-      const int i = i0 + 4 * q;
-      if (i < kb) W[static_cast<size_t>(K + i) * d + J0 + j] = acc[q];
-    }
-  }
-}
-
-// Trailing update of the upper tile (I0, J0): W[I, J] -= R_KI^T R_KJ.
-__global__ __launch_bounds__(256) void k_chol_syrk(double* __restrict__ W, int d, int K) {
-  __shared__ double pi[kCL][kCB + 1];
-  __shared__ double pj[kCL][kCB + 1];
-  const int kb = (d - K) < kCB ? (d - K) : kCB;
-  const int T0 = K + kb;
-  const int nt = (d - T0 + kCB - 1) / kCB;
   int p = blockIdx.x, ti = 0;
-  while (p >= nt - ti) {
-    p -= nt - ti;
+  while (p >= T - ti) {
+    p -= T - ti;
     ++ti;
   }
-  const int I0 = T0 + ti * kCB, J0 = T0 + (ti + p) * kCB;
+  const int tj = ti + p;
+  const int r0 = K * kCB, kb = (d - r0) < kCB ? (d - r0) : kCB;
+  const int I0 = (K + 1 + ti) * kCB, J0 = (K + 1 + tj) * kCB;
+  const bool diag = ti == tj;
   const int tid = threadIdx.x;
-  const int j = tid % kCB, i0 = tid / kCB;
-  double acc[kCB / 4];
-#pragma unroll
-  for (int q = 0; q < kCB / 4; ++q) acc[q] = 0.0;
-  for (int l0 = 0; l0 < kb; l0 += kCL) {
-    __syncthreads();
-    for (int e = tid; e < kCL * kCB; e += 256) {
+  // Kinv_K and the unsolved rows W[K, I], W[K, J] (zero past kb and d)
+  tile_to_lds<false>(ki, Kinv + static_cast<size_t>(K) * kCB * kCB, kCB, kb, kb);
+  tile_to_lds<false>(pI, W + static_cast<size_t>(r0) * d + I0, d, kb, d - I0);
+  if (!diag) tile_to_lds<false>(pJ, W + static_cast<size_t>(r0) * d + J0, d, kb, d - J0);
+  __syncthreads();
+  d4_t aI[2][2], aJ[2][2];
+  zero_acc(aI);
+  mfma_atb64(ki, pI, aI);
+  if (!diag) {
+    zero_acc(aJ);
+    mfma_atb64(ki, pJ, aJ);
+  }
+  __syncthreads();  // every read of the unsolved rows is done
+  for_acc([&](int a, int b, int e, int row, int col) { pI[row][col] = aI[a][b][e]; });
+  if (!diag) for_acc([&](int a, int b, int e, int row, int col) { pJ[row][col] = aJ[a][b][e]; });
+  __syncthreads();
+  if (diag) {
+    // this block owns column block I: the solved rows R[K, I]
+    for (int e = tid; e < kb * kCB; e += 256) {
       const int l = e / kCB, c = e % kCB;
-      const bool in = l0 + l < kb;
-      pi[l][c] = (in && I0 + c < d) ? W[static_cast<size_t>(K + l0 + l) * d + I0 + c] : 0.0;
-      pj[l][c] = (in && J0 + c < d) ? W[static_cast<size_t>(K + l0 + l) * d + J0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kCB / 4; ++q) {
-      const int i = i0 + 4 * q;
-      double s = 0.0;
-      for (int l = 0; l < kCL; ++l) s += pi[l][i] * pj[l][j];
-      acc[q] += s;
+      if (I0 + c < d) R[static_cast<size_t>(r0 + l) * d + I0 + c] = pI[l][c];
     }
   }
+  d4_t u[2][2];
+  zero_acc(u);
+  mfma_atb64(pI, diag ? pI : pJ, u);
+  const bool next = diag && ti == 0;
+  if (!next) {
+    for_acc([&](int a, int b, int e, int row, int col) {
+      if (I0 + row < d && J0 + col < d) {
+        double* w = W + static_cast<size_t>(I0 + row) * d + J0 + col;
+        *w = *w - u[a][b][e];
+      }
+    });
+    return;
+  }
+  // (K + 1, K + 1): the updated tile goes through LDS (pJ is free) into the
+  // factorisation's register layout
+  __syncthreads();  // pI is read by every wavefront's update before reuse
+  for_acc([&](int a, int b, int e, int row, int col) {
+    const double w = (I0 + row < d && I0 + col < d) ? W[static_cast<size_t>(I0 + row) * d + I0 + col] : 0.0;
+    pJ[row][col] = w - u[a][b][e];
+  });
+  __syncthreads();
+  const int kb1 = (d - I0) < kCB ? (d - I0) : kCB;
+  const int j = tid & (kCB - 1), g = tid >> 6;
+  double c[kCB / 4];
 #pragma unroll
   for (int q = 0; q < kCB / 4; ++q) {
-    const int i = i0 + 4 * q;
-    if (I0 + i < d && J0 + j < d && J0 + j >= I0 + i) W[static_cast<size_t>(I0 + i) * d + J0 + j] -= acc[q];
+    const int i = 4 * q + g;
+    c[q] = (j < kb1 && i <= j) ? pJ[i][j] : 0.0;
   }
+  __syncthreads();
+  finish_tile(c, R, d, I0, Kinv + static_cast<size_t>(K + 1) * kCB * kCB, bad, pI, ki, t, prow, inv);
 }
 
-// R = upper triangle of W; status = rank test on the diagonal, column by
-// column: R_kk / sqrt(G_kk) is the sine of the angle between column k of the
-// factored matrix and the span of the columns before it, which does not
-// change when a column is scaled.
-__global__ __launch_bounds__(256) void k_chol_finish(const double* __restrict__ W, int d, double* __restrict__ R,
+// The last block column of R^{-1} (the steps form the others): block J < K.
+__global__ __launch_bounds__(256) void k_inv_column(const double* __restrict__ R, int d, int K,
+                                                    const double* __restrict__ Kinv, InvOut inv) {
+  __shared__ double a[kCB][kCP];
+  __shared__ double b[kCB][kCP];
+  inv_column_tile(R, d, static_cast<int>(blockIdx.x), K, Kinv, inv, a, b);
+}
+
+// status = rank test on the diagonal of R, column by column: R_kk /
+// sqrt(G_kk) is the sine of the angle between column k of the factored
+// matrix and the span of the columns before it, which does not change when a
+// column is scaled.  One block.
+__global__ __launch_bounds__(256) void k_chol_finish(const double* __restrict__ R, int d,
                                                      const double* __restrict__ gdiag, const int32_t* __restrict__ bad,
                                                      int32_t* __restrict__ status, double rtol) {
-  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < static_cast<int64_t>(d) * d;
-       idx += static_cast<int64_t>(gridDim.x) * 256) {
-    const int i = static_cast<int>(idx / d), j = static_cast<int>(idx % d);
-    R[idx] = j >= i ? W[idx] : 0.0;
+  __shared__ int32_t sbad;
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  int32_t mine = 0;
+  for (int k = threadIdx.x; k < d; k += 256) {
+    const double r = R[static_cast<size_t>(k) * d + k];
+    if (!(r > rtol * sqrt(gdiag[k]))) mine = 1;
   }
-  if (blockIdx.x == 0) {
-    __shared__ int32_t sbad;
-    if (threadIdx.x == 0) sbad = 0;
-    __syncthreads();
-    int32_t mine = 0;
-    for (int k = threadIdx.x; k < d; k += 256) {
-      const double r = W[static_cast<size_t>(k) * d + k];
-      if (!(r > rtol * sqrt(gdiag[k]))) mine = 1;
-    }
-    if (mine) atomicOr(&sbad, 1);
-    __syncthreads();
-    if (threadIdx.x == 0) status[0] = (bad[0] || sbad) ? 1 : 0;
-  }
+  if (mine) atomicOr(&sbad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) status[0] = (bad[0] || sbad) ? 1 : 0;
 }
 
+// W = upper triangle of G (zero below), R = 0, R^{-1} = R^{-T} = 0 (when
+// asked), gdiag = diagonal of G, bad = 0.
 __global__ void k_copy_upper(const double* __restrict__ G, int64_t ldg, int d, double* __restrict__ W,
-                             double* __restrict__ gdiag, int32_t* __restrict__ bad) {
+                             double* __restrict__ R, InvOut inv, double* __restrict__ gdiag,
+                             int32_t* __restrict__ bad) {
   for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < static_cast<int64_t>(d) * d;
        idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int i = static_cast<int>(idx / d), j = static_cast<int>(idx % d);
     const double g = G[static_cast<size_t>(i) * ldg + j];
     W[idx] = j >= i ? g : 0.0;
+    R[idx] = 0.0;
+    if (inv.X != nullptr) {
+      inv.X[idx] = 0.0;
+      inv.XT[idx] = 0.0;
+    }
     if (i == j) gdiag[i] = g;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) bad[0] = 0;
@@ -794,8 +1020,8 @@ size_t cholesky_scratch_doubles(int64_t d) {
 
 const double* cholesky_block_inverses(const double* scratch, int64_t d) { return scratch + d * d; }
 
-int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t* status, double* scratch,
-                     hipStream_t s) {
+int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, double* Rinv, double* RinvT,
+                     int32_t* status, double* scratch, hipStream_t s) {
   // Threshold: R_kk^2 = G_kk - sum_i R_ik^2 is formed with an error of
   // about d * eps * G_kk, so a Gram-based factor cannot resolve R_kk below
   // about sqrt(d * eps) * sqrt(G_kk); treat that as numerical rank
@@ -808,24 +1034,28 @@ int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t
   double* Kinv = scratch + d * d;
   double* gdiag = Kinv + div_up(d, kCB) * kCB * kCB;
   int32_t* bad = reinterpret_cast<int32_t*>(gdiag + d);
+  const InvOut inv{Rinv, Rinv != nullptr ? RinvT : nullptr};
   const int di = static_cast<int>(d);
   const unsigned g = static_cast<unsigned>(div_up(d * d, 256) < 4096 ? div_up(d * d, 256) : 4096);
-  hipLaunchKernelGGL(k_copy_upper, dim3(g), dim3(256), 0, s, G, ldg, di, W, gdiag, bad);
+  hipLaunchKernelGGL(k_copy_upper, dim3(g), dim3(256), 0, s, G, ldg, di, W, R, inv, gdiag, bad);
   SKLS_CHECK_LAUNCH();
-  for (int K = 0; K < di; K += kCB) {
-    const int kb = (di - K) < kCB ? (di - K) : kCB;
-    double* KinvK = Kinv + static_cast<size_t>(K / kCB) * kCB * kCB;
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, W, di, K, KinvK, bad);
-    SKLS_CHECK_LAUNCH();
-    const int rest = di - K - kb;
-    if (rest <= 0) break;
-    const int nt = (rest + kCB - 1) / kCB;
-    hipLaunchKernelGGL(k_chol_trsm, dim3(nt), dim3(256), 0, s, W, di, K, KinvK);
-    SKLS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_chol_syrk, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, W, di, K);
+  // block column 0, then one launch per step: the trailing update of step K,
+  // the factorisation of diagonal tile K + 1 and (when asked) block column K
+  // of R^{-1}; the last column of R^{-1} after the steps
+  hipLaunchKernelGGL(k_chol_first, dim3(1), dim3(256), 0, s, W, R, di, Kinv, bad, inv);
+  SKLS_CHECK_LAUNCH();
+  const int nb = static_cast<int>(div_up(d, kCB));
+  for (int K = 0; K + 1 < nb; ++K) {
+    const int T = nb - K - 1;
+    const int extra = inv.X != nullptr ? K : 0;
+    hipLaunchKernelGGL(k_chol_step, dim3(T * (T + 1) / 2 + extra), dim3(256), 0, s, W, R, di, K, Kinv, bad, inv);
     SKLS_CHECK_LAUNCH();
   }
-  hipLaunchKernelGGL(k_chol_finish, dim3(g), dim3(256), 0, s, W, di, R, gdiag, bad, status, rtol);
+  if (inv.X != nullptr && nb > 1) {
+    hipLaunchKernelGGL(k_inv_column, dim3(nb - 1), dim3(256), 0, s, R, di, nb - 1, Kinv, inv);
+    SKLS_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_chol_finish, dim3(1), dim3(256), 0, s, R, di, gdiag, bad, status, rtol);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }

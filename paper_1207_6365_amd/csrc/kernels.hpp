@@ -45,9 +45,10 @@ size_t gram_ws_bytes(int64_t m, int64_t dd);
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,
                  double* G /* dd x dd */, void* ws, size_t ws_bytes, hipStream_t s);
 // Cholesky of the leading d x d block of G (leading dimension ldg): R upper,
-// status[0] = 0 ok / 1 rank deficient.
-int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, int32_t* status, double* scratch,
-                     hipStream_t s);
+// status[0] = 0 ok / 1 rank deficient.  With Rinv and RinvT (d x d each, or
+// both NULL) it also forms R^{-1} and R^{-T} within the same launches.
+int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, double* Rinv, double* RinvT,
+                     int32_t* status, double* scratch, hipStream_t s);
 size_t cholesky_scratch_doubles(int64_t d);
 // The inverses of R's diagonal 64 x 64 blocks that run_cholesky leaves in its
 // scratch (block J at J * 64^2, ld 64), valid until the scratch is reused.

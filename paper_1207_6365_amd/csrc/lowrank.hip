@@ -698,14 +698,13 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
     SKLS_TRY(st);
   }
   SKLS_TRY(run_gram(w.Y, SKLS_F64, tr, nullptr, SKLS_F64, n, tr, w.G, w.gram, w.gram_bytes, s));
-  SKLS_TRY(run_cholesky(w.G, tr, tr, w.R, w.status, w.cholw, s));
+  SKLS_TRY(run_cholesky(w.G, tr, tr, w.R, w.Rinv, w.RinvT, w.status, w.cholw, s));
   int32_t st_h = 0;
   SKLS_TRY(to_host(&st_h, w.status, sizeof st_h, s));
   if (st_h) {
     set_error("low_rank: A R^T is numerically rank deficient (lower t_r)");
     return SKLS_ERR_RANK;
   }
-  SKLS_TRY(run_trinv(w.R, tr, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, tr)));
   SKLS_TRY_HIP(hipEventRecord(ev[1], s));
 
   // ---- step 2: scores of Y, sampling, sampled rows
@@ -802,13 +801,12 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
   {
     PhaseTimer pt("lowrank_topk", s);
     SKLS_TRY(run_gram(w.SY, SKLS_F64, tr, nullptr, SKLS_F64, ns, tr, w.G, w.gram, w.gram_bytes, s));
-    SKLS_TRY(run_cholesky(w.G, tr, tr, w.R, w.status, w.cholw, s));
+    SKLS_TRY(run_cholesky(w.G, tr, tr, w.R, w.Rinv, w.RinvT, w.status, w.cholw, s));
     SKLS_TRY(to_host(&st_h, w.status, sizeof st_h, s));
     if (st_h) {
       set_error("low_rank: S U is numerically rank deficient (raise t_s)");
       return SKLS_ERR_RANK;
     }
-    SKLS_TRY(run_trinv(w.R, tr, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, tr)));
     SKLS_TRY(gemm(false, ns, tr, tr, 1.0, w.SY, tr, w.Rinv, tr, w.Q, tr, w.part, s));
     hipLaunchKernelGGL(k_sign_block, dim3(grid_for(m * p, kT, 8192)), dim3(kT), 0, s, m, p, seed, w.F);
     SKLS_CHECK_LAUNCH();

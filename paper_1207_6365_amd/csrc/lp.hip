@@ -492,14 +492,13 @@ int32_t factor_weighted(const LpWs& w, int64_t ns, int64_t d, const double* cw, 
   SKLS_CHECK_LAUNCH();
   const int64_t dd = with_y ? d + 1 : d;
   SKLS_TRY(run_gram(w.Mw, SKLS_F64, d, with_y ? w.yw : nullptr, SKLS_F64, ns, d, w.G, w.gram, w.gram_bytes, s));
-  SKLS_TRY(run_cholesky(w.G, dd, d, w.R, w.status, w.cholw, s));
+  SKLS_TRY(run_cholesky(w.G, dd, d, w.R, w.Rinv, w.RinvT, w.status, w.cholw, s));
   if (bad != nullptr) {
     int32_t st = 0;
     SKLS_TRY(to_host(&st, w.status, sizeof st, s));
     *bad = st;
-    if (st) return SKLS_OK;
   }
-  return run_trinv(w.R, d, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, d));
+  return SKLS_OK;
 }
 
 // r = M x - y on the coreset; f = sum |r|^p, f1 = sum |r|, fy = sum |y|;
@@ -886,14 +885,13 @@ int32_t run_lp(const skls_matrix& A, const double* b, const LpPlan& P, double* x
     const int64_t m = P.nb * P.t;
     if (P.a > 1) SKLS_TRY(launch_scale(w.FA, static_cast<size_t>(m) * d, SKLS_F64, 1.0 / std::sqrt(double(P.a)), s));
     SKLS_TRY(run_gram(w.FA, SKLS_F64, d, nullptr, SKLS_F64, m, d, w.G, w.gram, w.gram_bytes, s));
-    SKLS_TRY(run_cholesky(w.G, d, d, w.R, w.status, w.cholw, s));
+    SKLS_TRY(run_cholesky(w.G, d, d, w.R, w.Rinv, w.RinvT, w.status, w.cholw, s));
     int32_t st_h = 0;
     SKLS_TRY(to_host(&st_h, w.status, sizeof st_h, s));
     if (st_h) {
       set_error("lp_regression: F A is numerically rank deficient");
       return SKLS_ERR_RANK;
     }
-    SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, d)));
     SKLS_TRY(row_norm_estimates(A, w.Rinv, kg, P.seed, w.Pi2, w.T, w.Z, w.score, w.last, w.gs, s));
     hipLaunchKernelGGL(k_pow_rows, dim3(kRed), dim3(kT), 0, s, n, w.score, P.p / 2.0, w.lam, w.part);
     SKLS_CHECK_LAUNCH();

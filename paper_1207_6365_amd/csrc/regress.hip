@@ -168,13 +168,12 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
   SKLS_TRY(run_sketch(A, nullptr, SKLS_F64, P.t, seed, nullptr, SKLS_SKETCH_AUTO, w.SA1, nullptr, SKLS_F64, w.sk,
                       w.sk_bytes, s));
   SKLS_TRY(run_gram(w.SA1, SKLS_F64, d, nullptr, SKLS_F64, P.t, d, w.G, w.gram, w.gram_bytes, s));
-  SKLS_TRY(run_cholesky(w.G, d, d, w.R, w.status, w.cholw, s));
+  SKLS_TRY(run_cholesky(w.G, d, d, w.R, w.Rinv, w.RinvT, w.status, w.cholw, s));
   SKLS_TRY(to_host(&st_h, w.status, sizeof st_h, s));
   if (st_h) {
     set_error("multi_lstsq: the sketch S1 A is numerically rank deficient");
     return SKLS_ERR_RANK;
   }
-  SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, d)));
   int64_t ns = 0;
   {
     PhaseTimer pt("multi_scores", s);
@@ -237,13 +236,12 @@ int32_t run_multi_lstsq(const skls_matrix& A, const double* B, const MultiPlan& 
     hipLaunchKernelGGL(k_gather_rows<double>, dim3(gr), dim3(kT), 0, s, ns, dp, dp, B, w.list, w.wts, w.SBc);
     SKLS_CHECK_LAUNCH();
     SKLS_TRY(run_gram(w.SAc, SKLS_F64, d, nullptr, SKLS_F64, ns, d, w.G, w.gram, w.gram_bytes, s));
-    SKLS_TRY(run_cholesky(w.G, d, d, w.R, w.status, w.cholw, s));
+    SKLS_TRY(run_cholesky(w.G, d, d, w.R, w.Rinv, w.RinvT, w.status, w.cholw, s));
     SKLS_TRY(to_host(&st_h, w.status, sizeof st_h, s));
     if (st_h) {
       set_error("multi_lstsq: S A is numerically rank deficient (raise t_s)");
       return SKLS_ERR_RANK;
     }
-    SKLS_TRY(run_trinv(w.R, d, w.Rinv, w.RinvT, s, cholesky_block_inverses(w.cholw, d)));
     SKLS_TRY(gemm(true, d, dp, ns, 1.0, w.SAc, d, w.SBc, dp, w.C, dp, w.gs, s));
     SKLS_TRY(gemm(false, d, dp, d, 1.0, w.RinvT, d, w.C, dp, w.Yt, dp, w.gs, s));
     SKLS_TRY(gemm(false, d, dp, d, 1.0, w.Rinv, d, w.Yt, dp, Y, dp, w.gs, s));

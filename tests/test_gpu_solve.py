@@ -200,3 +200,54 @@ def test_lstsq_past_2p31_entries(sk, precision):
     assert torch.max(torch.abs(x - x0)).item() < 1e-3 * 8 / np.sqrt(n * k / d)
     del col, val, row_ptr, b, r
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+def test_lstsq_warm_start_matches_oracle_lsqr(sk, precision):
+    # Section 7.7 starts the iteration from any x(0); both sides start at the
+    # same x0 (zero, and the exact solution plus a perturbation) with the R of
+    # the same sketch, and certify 1 + 1e-11
+    A, b, op, Ad, xs = _small()
+    seed, t = W.sketch_seed(0), 4000
+    _, R_o, _, _ = O.sketch_and_solve(op, b, seed, t)
+    g = np.random.default_rng(12)
+    for x0 in (np.zeros(A.d), xs + 0.1 * g.standard_normal(A.d)):
+        x_g, info = sk.lstsq(up_csr(A), up(b), t, seed, delta=1e-11, precision=precision, x0=up(x0))
+        x_o, it_o, ok, _ = O.lsqr(op, b, x0, R_o, 1e-11)
+        assert ok and info["certified"] == 1 and info["retries"] == 0
+        rho_g = O.residual_ratio(Ad, b, x_g.cpu().numpy(), xs)
+        assert abs(rho_g - O.residual_ratio(Ad, b, x_o, xs)) <= 1e-10
+        assert rho_g - 1.0 <= 1e-11
+
+
+def test_lstsq_retries_a_rank_deficient_sketch(sk):
+    # t = d with a few rows: some seeds leave a bucket empty (S A rank
+    # deficient).  Attempt r uses seed + r * 0x9E3779B97F4A7C15; the call
+    # must report the first attempt whose sketch has full rank and return
+    # the oracle's solution with that sketch.
+    g = np.random.default_rng(13)
+    n, d = 60, 8
+    Ad = g.standard_normal((n, d))
+    b = g.standard_normal(n)
+    xs = O.lstsq_exact(Ad, b)
+    gamma = 0x9E3779B97F4A7C15
+    mask = (1 << 64) - 1
+
+    def full_rank(sd):
+        return np.linalg.matrix_rank(O.sketch_dense(Ad, sd, d)) == d
+
+    seed = next(sd for sd in range(1, 10000) if not full_rank(sd) and full_rank((sd + gamma) & mask))
+    seed1 = (seed + gamma) & mask
+    with pytest.raises(sk.SklsError) as e:
+        sk.lstsq(up(Ad), up(b), d, seed, delta=1e-11)
+    assert e.value.status == 4
+    # a sketch with t = d is a poor embedding: give both sides a lower bound
+    # on sigma_min(A R^-1) that holds, so that their certificates are valid
+    _, R1, _, _ = O.sketch_and_solve(Ad, b, seed1, d)
+    lb = min(0.5, 0.9 * np.linalg.svd(Ad @ np.linalg.inv(R1), compute_uv=False).min())
+    x_g, info = sk.lstsq(up(Ad), up(b), d, seed, delta=1e-11, max_retries=3, max_iter=400, sigma_lb=lb)
+    assert info["retries"] == 1 and info["certified"] == 1
+    x_o, _, _, _, ok = O.lstsq(Ad, b, seed1, d, delta=1e-11, sigma_lb=lb, max_iter=400)
+    assert ok
+    rho_g = O.residual_ratio(Ad, b, x_g.cpu().numpy(), xs)
+    assert abs(rho_g - O.residual_ratio(Ad, b, x_o, xs)) <= 1e-10
