@@ -91,10 +91,10 @@ def stored_traffic(kernel: str, source: str):
     return float(fields["traffic_bytes"])
 
 
-def oracle_rows(log):
-    """The oracle on bounded samples of the other workloads, one thread (BLAS
-    held to one thread as well): seconds per call and the sample's size, as
-    context for the GPU figures of each row."""
+def oracle_rows(log, threads=1):
+    """The oracle on bounded samples of the other workloads: seconds per call
+    and the sample's size, as context for the GPU figures of each row.
+    threads=1 holds BLAS to one thread; None lets it use every host core."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -108,9 +108,9 @@ def oracle_rows(log):
         return (time.perf_counter() - t0) / reps
 
     out = {}
-    with threadpool_limits(1):
-        log("oracle samples: small regression, heavy-row regression, leverage, multiple responses, low rank, l_p, "
-            "learned gradient")
+    with threadpool_limits(threads):
+        log(f"oracle samples ({threads or 'all'} thread(s)): small regression, heavy-row regression, leverage, "
+            "multiple responses, low rank, l_p, learned gradient")
         A1, b1, _ = W.lstsq_small()
         sec = timed(lambda: O.sketch_and_solve(A1, b1, W.sketch_seed(0), 4000), 5)
         out["lstsq_small"] = {"s_per_call": sec, "sample": "sketch-and-solve, the full small workload"}
@@ -647,6 +647,11 @@ def main():
                                   "host_cpus": os.cpu_count()}
         if args.only is None and not args.no_extras:
             result["cpu_baseline"]["rows"] = oracle_rows(log)
+            # the same samples with BLAS free to use every host core (the
+            # headline sketch has no multithreaded NumPy path: its figure
+            # holds for any core count)
+            result["cpu_baseline"]["rows_all_cores"] = oracle_rows(log, threads=None)
+            result["cpu_baseline"]["rows_all_cores"]["cores"] = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
         if small_run is not None:
             # the small regression's sketch-and-solve on the GPU against the
             # oracle's on the same seeded input: residual ratios to the exact
