@@ -558,7 +558,6 @@ __device__ void finish_tile(double (&c)[kCB / 4], double* __restrict__ R, int d,
 // transpose.
 __device__ __forceinline__ void inv_column_tile(const double* __restrict__ R, int d, int J, int K, const double* __restrict__ Kinv,
                                 InvOut inv, double (*a)[kCP], double (*b)[kCP]) {
-  const int tid = threadIdx.x;
   const int J0 = J * kCB, K0 = K * kCB;
   const int kbj = (d - J0) < kCB ? (d - J0) : kCB, kbk = (d - K0) < kCB ? (d - K0) : kCB;
   d4_t acc[2][2];

@@ -391,6 +391,84 @@ __global__ __launch_bounds__(kT) void k_spmm(int64_t rows, int p, const TR* __re
   }
 }
 
+// score[i] = || A[i, :] T ||^2 for CSR A and T (d x kg, kg <= 32, float64)
+// with T staged in LDS (rows padded to 32 values), so the gathers of T's
+// rows are LDS reads.  A wavefront takes eight consecutive rows at a time,
+// eight lanes per row, four columns of T per lane; each lane loads its
+// row's entries sixteen at a time (all loads in flight) and the squares are
+// summed over the row's lanes.  last[0] = the largest row with a positive
+// score.  Float64 throughout, no n x kg intermediate.
+constexpr int kProjThreads = 512;
+template <typename TV, typename TR>
+__global__ __launch_bounds__(kProjThreads) void k_csr_proj_sqnorm(int64_t n, int d, int kg,
+                                                                 const TR* __restrict__ rp,
+                                                                 const int32_t* __restrict__ col,
+                                                                 const TV* __restrict__ val,
+                                                                 const double* __restrict__ T,
+                                                                 double* __restrict__ score,
+                                                                 int32_t* __restrict__ last) {
+  extern __shared__ double Ts[];  // [d][32]
+  __shared__ int32_t wlast[kProjThreads / kWave];
+  for (int e = threadIdx.x; e < d * 32; e += kProjThreads) {
+    const int r = e >> 5, c = e & 31;
+    Ts[e] = c < kg ? T[static_cast<size_t>(r) * kg + c] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int slot = lane >> 3, cg = lane & 7;
+  constexpr int kWaves = kProjThreads / kWave;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kWaves * 8;
+  int32_t mine = -1;
+  for (int64_t r0 = (static_cast<int64_t>(blockIdx.x) * kWaves + wid) * 8; r0 < n; r0 += stride) {
+    const int64_t r = r0 + slot;
+    const bool live = r < n;
+    const int64_t b = live ? static_cast<int64_t>(rp[r]) : 0, e = live ? static_cast<int64_t>(rp[r + 1]) : 0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int64_t k0 = b; __any(k0 < e); k0 += 16) {
+      int32_t j[16];
+      double v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t k = k0 + q;
+        const bool ok = k < e;
+        j[q] = ok ? col[k] : 0;
+        v[q] = ok ? load_as<double>(val, static_cast<size_t>(k)) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double* t = Ts + j[q] * 32 + cg * 4;
+        const double2 t01 = *reinterpret_cast<const double2*>(t);
+        const double2 t23 = *reinterpret_cast<const double2*>(t + 2);
+        a0 += v[q] * t01.x;
+        a1 += v[q] * t01.y;
+        a2 += v[q] * t23.x;
+        a3 += v[q] * t23.y;
+      }
+    }
+    double sq = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+    sq += __shfl_xor(sq, 1);
+    sq += __shfl_xor(sq, 2);
+    sq += __shfl_xor(sq, 4);
+    if (live && cg == 0) {
+      score[r] = sq;
+      if (sq > 0.0) mine = static_cast<int32_t>(r) > mine ? static_cast<int32_t>(r) : mine;
+    }
+  }
+  // largest row with a positive score: over the wave, the block, the grid
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t o = __shfl_xor(mine, off);
+    mine = o > mine ? o : mine;
+  }
+  if (lane == 0) wlast[wid] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t m = -1;
+    for (int k = 0; k < kWaves; ++k) m = wlast[k] > m ? wlast[k] : m;
+    if (m >= 0) atomicMax(last, m);
+  }
+}
+
 // out (rows x p) = A X for dense A (rows x cols, leading dimension ld, any
 // value type) and X (cols x p); one wavefront per row as in k_spmm.
 template <typename TV>
@@ -641,6 +719,32 @@ int32_t row_norm_estimates(const skls_matrix& A, const double* Rinv, int kg, uin
                      seed, Pi2);
   SKLS_CHECK_LAUNCH();
   SKLS_TRY(gemm(false, d, kg, d, 1.0, Rinv, d, Pi2, kg, T, kg, gs, s));
+  SKLS_TRY(launch_fill_zero(last, 16, s));
+  const size_t proj_lds = static_cast<size_t>(d) * 32 * sizeof(double);
+  if (A.layout == SKLS_CSR && kg <= 32 && proj_lds <= 96 * 1024) {
+    // CSR rows against T in LDS: the scores directly, no n x kg product
+    if (n == 0) return SKLS_OK;
+    return with_value(A.dtype, [&](auto tv) -> int32_t {
+      using TV = decltype(tv);
+      return with_rowptr(A, [&](auto trt) -> int32_t {
+        using TR = decltype(trt);
+        const void* kern = reinterpret_cast<const void*>(&k_csr_proj_sqnorm<TV, TR>);
+        SKLS_TRY_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(proj_lds)));
+        int cus = 256, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                     hipSuccess || cus < 1)
+          cus = 256;
+        const int64_t per_block = (kProjThreads / kWave) * 8;
+        int64_t g = div_up(n, per_block);
+        if (g > 2 * cus) g = 2 * cus;
+        hipLaunchKernelGGL((k_csr_proj_sqnorm<TV, TR>), dim3(static_cast<unsigned>(g)), dim3(kProjThreads), proj_lds,
+                           s, n, static_cast<int>(d), kg, static_cast<const TR*>(A.row_ptr), A.col_idx,
+                           static_cast<const TV*>(A.val), T, score, last);
+        SKLS_CHECK_LAUNCH();
+        return SKLS_OK;
+      });
+    });
+  }
   int32_t st = with_value(A.dtype, [&](auto tv) -> int32_t {
     using TV = decltype(tv);
     if (A.layout != SKLS_CSR) return dense_times<TV>(n, d, static_cast<const TV*>(A.val), A.ld, T, kg, Z, gs, s);
@@ -650,7 +754,6 @@ int32_t row_norm_estimates(const skls_matrix& A, const double* Rinv, int kg, uin
     });
   });
   SKLS_TRY(st);
-  SKLS_TRY(launch_fill_zero(last, 16, s));
   hipLaunchKernelGGL(k_row_sqnorm, dim3(grid_for(n, kT / kWave, 8192)), dim3(kT), 0, s, n, kg, Z, score, last);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
