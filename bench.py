@@ -418,6 +418,31 @@ def main():
                     "pass_frac": pass_bytes / (pt_ / max(pc, 1) * 1e-3) / HBM_PEAK,
                     "phases_ms": {k: v[1] / max(v[0], 1) for k, v in ph.items()},
                 }
+                # R from the second stage Pi1 = F S (m = 4 d and 8 d) in place of S A
+                stage = {}
+                for m2 in (4 * d3, 8 * d3):
+                    sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision, second_stage=m2)
+                    sync()
+                    t0 = time.perf_counter()
+                    sinfos = []
+                    for _ in range(args.lstsq_steps):
+                        _, si = sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision, second_stage=m2)
+                        sinfos.append(si)
+                    sync()
+                    el2 = (time.perf_counter() - t0) / args.lstsq_steps
+                    lib.skls_profile_enable(1)
+                    sk.lstsq(A3g, b3g, t3, seed, delta=1e-6, precision=precision, second_stage=m2)
+                    sync()
+                    ph2 = profile_phases(sk)
+                    lib.skls_profile_enable(0)
+                    stage[str(m2)] = {
+                        "solves_per_s": 1.0 / el2, "ms_per_solve": el2 * 1e3,
+                        "certified": all(i["certified"] == 1 for i in sinfos),
+                        "iterations": sinfos[-1]["iterations"], "refinements": sinfos[-1]["refinements"],
+                        "ms_qr": sinfos[-1]["ms_qr"], "ms_iter": sinfos[-1]["ms_iter"],
+                        "ms_second_stage": ph2.get("second_stage", (1, float("nan")))[1],
+                    }
+                res[key]["second_stage"] = stage
                 del A3g, b3g
                 torch.cuda.empty_cache()
             result["lstsq"] = res

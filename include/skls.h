@@ -288,7 +288,11 @@ typedef struct {
                            max_iter.  Attempt r uses seed + r * 0x9E3779B97F4A7C15 (mod 2^64); the
                            failure probability of a sparse embedding (Section 3) then drops
                            geometrically with the attempts */
-  int32_t reserved;
+  int32_t second_stage; /* 0: factor S A directly.  m > 0 (d <= m <= t, m <= 65536): factor
+                           Pi1 A = F (S A) instead, F the m x t sign matrix of skls_second_stage
+                           (stream seed), and take x~ from F S b.  sigma_lb should then reflect the
+                           wider spread of F (about 1 - sqrt(d / m) for the smallest singular value
+                           of F restricted to the range of S A) */
 } skls_lstsq_opts;
 
 typedef struct {
@@ -322,6 +326,29 @@ SKLS_API int32_t skls_lstsq_workspace(const skls_matrix* A, const skls_lstsq_opt
  */
 SKLS_API int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_lstsq_opts* opts, double* x,
                    skls_lstsq_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Second sketch stage (Section 6: Pi1 = F S, the sparse embedding followed by
+ * a dense Johnson-Lindenstrauss map; the composition facts of Section 8 keep
+ * the embedding property of the product): given S A and
+ * S b (t rows), FSA = F (S A) and FSb = F (S b) with F the m x t matrix whose
+ * entry (i, r) is -1 / sqrt(m) when bit b(r mod 64) of SplitMix64 output
+ * i * ceil(t / 64) + floor(r / 64) of the stream seed ^ 0x7374616765327369 is
+ * set, else +1 / sqrt(m); b(c) = 32 floor(c / 32) + 16 (c mod 2) + 15 -
+ * floor((c mod 32) / 2), a fixed order of the word's bits.
+ *  SA:   device [t x d] row-major, dtype F64 or F32.  Each entry is rounded to
+ *        float32 and then to bfloat16 (round to nearest even each); the products
+ *        with the signs are summed in float32 over splits of the t rows and the
+ *        splits in float64.
+ *  Sb:   device [t] of the same dtype, or NULL (then FSb is not written).  F S b
+ *        is summed in float64 from Sb as given.
+ *  FSA:  device float64 [m x d] row-major, output.  FSb: device float64 [m].
+ *  Requires 1 <= d <= 8192, 1 <= m <= 65536, 1 <= t < 2^31.  Asynchronous.
+ */
+SKLS_API int32_t skls_second_stage_workspace(int64_t t, int64_t d, int64_t m, size_t* bytes);
+SKLS_API int32_t skls_second_stage(const void* SA, const void* Sb, int32_t dtype, int64_t t, int64_t d, int64_t m,
+                                   uint64_t seed, double* FSA, double* FSb, void* ws, size_t ws_bytes,
+                                   void* stream);
 
 /*
  * Approximate leverage scores (Section 6, theorem on approximating all leverage

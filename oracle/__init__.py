@@ -15,6 +15,8 @@ Time" (arXiv:1207.6365) it follows:
   residual ratio via the Pythagorean identity (Section 7.2 facts)
 * :mod:`.solve`    -- sketch-and-solve (Section 7 regression theorem),
   preconditioned LSQR and Richardson iteration (Section 7.7)
+* :mod:`.stage2`   -- the second sketch stage ``Pi1 = F S`` with a dense sign
+  matrix ``F`` (Section 6; composition facts of Section 8)
 * :mod:`.leverage` -- exact and approximate leverage scores (Section 6)
 * :mod:`.multiresponse` -- multiple-response regression by leverage-score
   sampling (Section 7, generalized-regression algorithm)

@@ -24,6 +24,7 @@ from .api import (  # noqa: F401
     multi_lstsq,
     lp_regression,
     qr_r,
+    second_stage,
     SketchPlan,
     sketch,
     sketch_general,

@@ -71,7 +71,7 @@ class SklsLstsqOpts(ctypes.Structure):
         ("w", c_void_p),
         ("x0", c_void_p),
         ("max_retries", c_int32),
-        ("reserved", c_int32),
+        ("second_stage", c_int32),
     ]
 
 
@@ -207,6 +207,9 @@ SIGNATURES = {
     "skls_lstsq_workspace": (c_int32, [POINTER(SklsMatrix), POINTER(SklsLstsqOpts), POINTER(c_size_t)]),
     "skls_lstsq": (c_int32, [POINTER(SklsMatrix), c_void_p, POINTER(SklsLstsqOpts), c_void_p,
                              POINTER(SklsLstsqInfo), c_void_p, c_size_t, c_void_p]),
+    "skls_second_stage_workspace": (c_int32, [c_int64, c_int64, c_int64, POINTER(c_size_t)]),
+    "skls_second_stage": (c_int32, [c_void_p, c_void_p, c_int32, c_int64, c_int64, c_int64, c_uint64, c_void_p,
+                                    c_void_p, c_void_p, c_size_t, c_void_p]),
     "skls_leverage_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, c_int32, POINTER(c_size_t)]),
     "skls_leverage_scores": (c_int32, [POINTER(SklsMatrix), c_int64, c_uint64, c_int32, c_void_p, c_void_p,
                                        c_void_p, c_size_t, c_void_p]),

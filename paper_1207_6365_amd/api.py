@@ -216,11 +216,13 @@ def qr_r(M: torch.Tensor, inverse: bool = True):
 def lstsq(A, b: torch.Tensor, t: int, seed: int, delta: float = 1e-6, precision: str = "plain",
           sigma_lb: float = 0.5, max_iter: int = 100, sketch_only: bool = False, variant: str = "auto",
           w: torch.Tensor | None = None, raise_noconv: bool = True, x0: torch.Tensor | None = None,
-          max_retries: int = 0):
+          max_retries: int = 0, second_stage: int = 0):
     """Least squares ``min ||A x - b||``: sketch-and-solve, then R-preconditioned
     LSQR to a certified residual ratio ``<= 1 + delta``.  ``x0``: start of the
     iteration in place of the sketch-and-solve solution; ``max_retries``:
-    extra attempts with a new sketch after a failed one.  Returns ``(x, info)``."""
+    extra attempts with a new sketch after a failed one; ``second_stage = m``:
+    take R from ``F (S A)`` (m rows, see :func:`second_stage`) instead of
+    ``S A``.  Returns ``(x, info)``."""
     m, device = _matrix(A)
     if b.dtype != torch.float64 or not b.is_contiguous() or b.numel() != m.n:
         raise TypeError("b must be a contiguous float64 vector with n entries")
@@ -234,6 +236,7 @@ def lstsq(A, b: torch.Tensor, t: int, seed: int, delta: float = 1e-6, precision:
     o.w = _ptr(w)
     o.x0 = _ptr(x0)
     o.max_retries = max_retries
+    o.second_stage = second_stage
     ws = _workspace(_size(lib().skls_lstsq_workspace, ctypes.byref(m), ctypes.byref(o)), device)
     x = torch.empty(m.d, dtype=torch.float64, device=device)
     info = L.SklsLstsqInfo()
@@ -244,6 +247,23 @@ def lstsq(A, b: torch.Tensor, t: int, seed: int, delta: float = 1e-6, precision:
     if st != 0 and not (st == 5 and not raise_noconv):
         L.check(st)
     return x, out
+
+
+def second_stage(SA: torch.Tensor, Sb: torch.Tensor | None, m: int, seed: int):
+    """``(F SA, F Sb)`` for the m x t sign matrix F of the second sketch
+    stage (float64 results; ``Sb`` may be None, then the second is None).
+    ``SA``: contiguous float64/float32 ``[t, d]``; ``Sb`` the same dtype ``[t]``."""
+    if SA.dim() != 2 or SA.dtype not in (torch.float64, torch.float32) or not SA.is_contiguous():
+        raise TypeError("SA must be a contiguous float64/float32 matrix")
+    t, d = SA.shape
+    if Sb is not None and (Sb.dtype != SA.dtype or not Sb.is_contiguous() or Sb.numel() != t):
+        raise TypeError("Sb must be a contiguous vector of SA's dtype with t entries")
+    ws = _workspace(_size(lib().skls_second_stage_workspace, t, d, m), SA.device)
+    FSA = torch.empty(m, d, dtype=torch.float64, device=SA.device)
+    FSb = torch.empty(m, dtype=torch.float64, device=SA.device) if Sb is not None else None
+    L.check(lib().skls_second_stage(_ptr(SA), _ptr(Sb), _DTYPE[SA.dtype], t, d, m, seed & 0xFFFFFFFFFFFFFFFF,
+                                    _ptr(FSA), _ptr(FSb), _ptr(ws), ws.numel(), _stream(SA.device)))
+    return FSA, FSb
 
 
 def multi_lstsq(A, B: torch.Tensor, t: int, t_s: int, seed: int, k_g: int = 0, coreset: bool = False):

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libskls.so")
-SOURCES = ["api.cpp", "profile.cpp", "noalloc.hip", "sketch.hip", "dense.hip", "lsqr.hip", "leverage.hip", "learned.hip", "lowrank.hip", "regress.hip", "lp.hip"]
+SOURCES = ["api.cpp", "profile.cpp", "noalloc.hip", "sketch.hip", "dense.hip", "lsqr.hip", "leverage.hip", "learned.hip", "lowrank.hip", "regress.hip", "lp.hip", "stage2.hip"]
 ARCH = "gfx950"
 
 

@@ -155,6 +155,9 @@ struct LsWs {
   double* partial;
   double* red;
   int32_t nblk;
+  double* FSA;   // second stage: F S A [m x d], F S b [m], split partials
+  double* FSb;
+  float* fpart;
 };
 
 LsWs carve_ls(Arena& ar, const skls_matrix& A, const skls_lstsq_opts& o) {
@@ -166,7 +169,15 @@ LsWs carve_ls(Arena& ar, const skls_matrix& A, const skls_lstsq_opts& o) {
   L.Sb = ar.take<char>(static_cast<size_t>(t) * es);
   L.sk_bytes = sketch_ws_bytes(A, t, o.variant);
   L.sk = ar.take<char>(L.sk_bytes);
-  L.q = carve_qr(ar, t, d, dd);
+  const int64_t m = o.second_stage;
+  L.q = carve_qr(ar, m > 0 ? m : t, d, dd);
+  L.FSA = L.FSb = nullptr;
+  L.fpart = nullptr;
+  if (m > 0) {
+    L.FSA = ar.take<double>(static_cast<size_t>(m * d));
+    L.FSb = ar.take<double>(static_cast<size_t>(m));
+    L.fpart = ar.take<float>(second_stage_scratch_floats(m, d, t));
+  }
   L.R = ar.take<double>(static_cast<size_t>(d * d));
   L.Rinv = ar.take<double>(static_cast<size_t>(d * d));
   L.tmp = ar.take<double>(static_cast<size_t>(d));
@@ -231,6 +242,8 @@ LevRWs carve_lev_r(Arena& ar, int64_t d, int32_t k) {
   return L;
 }
 
+constexpr int32_t kMaxStageRows = 65536;
+
 void fill_opts(skls_lstsq_opts& o) {
   if (o.delta <= 0.0) o.delta = 1e-6;
   if (o.sigma_lb <= 0.0) o.sigma_lb = 0.5;
@@ -264,6 +277,20 @@ int32_t check_lstsq(const skls_matrix* A, const skls_lstsq_opts* opts) {
   if (opts->max_retries < 0 || opts->max_retries > 64) {
     set_error("max_retries must lie in [0, 64]");
     return SKLS_ERR_ARG;
+  }
+  if (opts->second_stage != 0 &&
+      (opts->second_stage < A->d || opts->second_stage > opts->t || opts->second_stage > kMaxStageRows)) {
+    set_error("second_stage m=%d must be 0 or satisfy d <= m <= t and m <= %d", opts->second_stage, kMaxStageRows);
+    return SKLS_ERR_ARG;
+  }
+  return SKLS_OK;
+}
+
+int32_t check_stage(int64_t t, int64_t d, int64_t m) {
+  SKLS_TRY(check_t(t));
+  if (d < 1 || d > 8192 || m < 1 || m > kMaxStageRows) {
+    set_error("second stage needs 1 <= d <= 8192 and 1 <= m <= %d", kMaxStageRows);
+    return SKLS_ERR_SHAPE;
   }
   return SKLS_OK;
 }
@@ -588,7 +615,13 @@ int32_t lstsq_once(const skls_matrix* A, const double* b, const skls_lstsq_opts&
   SKLS_TRY_HIP(hipEventRecord(ev[0], s));
   SKLS_TRY(run_sketch(*A, b, SKLS_F64, o.t, o.seed, o.w, o.variant, L.SA, L.Sb, sk_dtype, L.sk, L.sk_bytes, s));
   SKLS_TRY_HIP(hipEventRecord(ev[1], s));
-  SKLS_TRY(qr_from(L.SA, sk_dtype, L.Sb, sk_dtype, o.t, d, L.q, L.R, L.Rinv, L.q.RinvT, s));
+  if (o.second_stage > 0) {
+    // Pi1 = F S (Section 6): factor F S A, x~ from F S b
+    SKLS_TRY(run_second_stage(L.SA, L.Sb, sk_dtype, o.t, d, o.second_stage, o.seed, L.FSA, L.FSb, L.fpart, s));
+    SKLS_TRY(qr_from(L.FSA, SKLS_F64, L.FSb, SKLS_F64, o.second_stage, d, L.q, L.R, L.Rinv, L.q.RinvT, s));
+  } else {
+    SKLS_TRY(qr_from(L.SA, sk_dtype, L.Sb, sk_dtype, o.t, d, L.q, L.R, L.Rinv, L.q.RinvT, s));
+  }
   if (o.x0 != nullptr) {
     SKLS_TRY_HIP(hipMemcpyAsync(x, o.x0, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
   } else {
@@ -733,6 +766,37 @@ int32_t skls_lstsq(const skls_matrix* A, const double* b, const skls_lstsq_opts*
   }
   if (info) *info = inf;
   return st;
+}
+
+int32_t skls_second_stage_workspace(int64_t t, int64_t d, int64_t m, size_t* bytes) {
+  clear_error();
+  if (bytes == nullptr) {
+    set_error("bytes pointer is NULL");
+    return SKLS_ERR_ARG;
+  }
+  SKLS_TRY(check_stage(t, d, m));
+  Arena ar(nullptr, 0);
+  ar.take<float>(second_stage_scratch_floats(m, d, t));
+  *bytes = ar.used;
+  return SKLS_OK;
+}
+
+int32_t skls_second_stage(const void* SA, const void* Sb, int32_t dtype, int64_t t, int64_t d, int64_t m,
+                          uint64_t seed, double* FSA, double* FSb, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKLS_TRY(check_stage(t, d, m));
+  if (SA == nullptr || FSA == nullptr || (Sb != nullptr && FSb == nullptr)) {
+    set_error("SA and FSA must be non-NULL, and FSb too when Sb is given");
+    return SKLS_ERR_ARG;
+  }
+  if (dtype != SKLS_F64 && dtype != SKLS_F32) {
+    set_error("SA must be F64 or F32");
+    return SKLS_ERR_DTYPE;
+  }
+  Arena ar(ws, ws_bytes);
+  float* part = ar.take<float>(second_stage_scratch_floats(m, d, t));
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  return run_second_stage(SA, Sb, dtype, t, d, m, seed, FSA, FSb, part, as_stream(stream));
 }
 
 int32_t skls_leverage_workspace(const skls_matrix* A, int64_t t, int32_t k, size_t* bytes) {

@@ -69,6 +69,13 @@ int32_t run_sign_projection(int64_t rows, int32_t kg, uint64_t seed, double* Pi2
 int32_t run_solve_from_gram(const double* Rinv, const double* RinvT, const double* c, int64_t d, double* x,
                             double* tmp, hipStream_t s);
 
+// ---------------------------------------------------------------- stage2.hip
+// FSA = F SA, FSb = F Sb (Sb may be NULL) for the m x t sign matrix F of the
+// second sketch stage; scratch holds second_stage_scratch_floats floats.
+size_t second_stage_scratch_floats(int64_t m, int64_t d, int64_t t);
+int32_t run_second_stage(const void* SA, const void* Sb, int32_t dtype, int64_t t, int64_t d, int64_t m,
+                         uint64_t seed, double* FSA, double* FSb, float* scratch, hipStream_t s);
+
 // ---------------------------------------------------------------- lsqr.hip
 // One pass over A: U_new[i] = A[i,:] p + coef * Z[i]; partial sums of
 // ||U_new||^2 and A^T U_new per block.  Precision: TA = float or double.
