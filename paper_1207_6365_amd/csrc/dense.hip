@@ -172,6 +172,7 @@ __global__ __launch_bounds__(kGThreads) void k_gram_partial(const TI* __restrict
       rv = k < k1 ? x : 0.0;
     }
   };
+  const bool full = I0 + kGT <= d && J0 + kGT <= d;  // the whole tile lies inside d x d
   int buf = 0;
   if (k0 < k1) {
     gram_fetch<TI, VEC, DIAG>(M, ld, k0, k1, I0, J0, d, ra, rb, ia, ib);
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(kGThreads) void k_gram_partial(const TI* __restrict
       for (int e = 0; e < 4; ++e) {
         const int row = wi * 64 + x * 16 + lr + 4 * e;
         const int colx = wj * 64 + y * 16 + lc;
-        out[row * kGT + colx] = acc[x][y][e];
+        if (full || (I0 + row < d && J0 + colx < d)) out[row * kGT + colx] = acc[x][y][e];
       }
   if (WITHV) {
     const int c = threadIdx.x % kGT, h = threadIdx.x / kGT;
@@ -267,14 +268,23 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   tile_of(p, T, ti, tj);
   const int S = ti == tj ? Sd : So;
   const int idx = blockIdx.y * 256 + threadIdx.x;
-  double s = 0.0;
-  for (int sp = 0; sp < S; ++sp) s += partial[(static_cast<size_t>(sp) * P + p) * (kGT * kGT) + idx];
   const int i = ti * kGT + idx / kGT, j = tj * kGT + idx % kGT;
-  // diagonal tiles hold both (i, j) and (j, i): write each pair once
-  if (i < d && j < d && (ti != tj || i <= j)) {
-    G[static_cast<size_t>(i) * dd + j] = s;
-    G[static_cast<size_t>(j) * dd + i] = s;
+  // diagonal tiles hold both (i, j) and (j, i): write each pair once; the
+  // partial tiles hold only entries inside the d x d matrix
+  if (!(i < d && j < d && (ti != tj || i <= j))) return;
+  // eight running sums so that eight loads are in flight
+  const double* src = partial + static_cast<size_t>(p) * (kGT * kGT) + idx;
+  const size_t stride = static_cast<size_t>(P) * (kGT * kGT);
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int sp = 0;
+  for (; sp + 8 <= S; sp += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += src[static_cast<size_t>(sp + u) * stride];
   }
+  for (int u = 0; sp < S; ++sp, ++u) acc[u] += src[static_cast<size_t>(sp) * stride];
+  const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  G[static_cast<size_t>(i) * dd + j] = s;
+  G[static_cast<size_t>(j) * dd + i] = s;
 }
 
 // ---------------------------------------------------------------- blocked Cholesky

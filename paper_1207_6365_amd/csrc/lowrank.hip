@@ -111,26 +111,108 @@ __global__ void k_sign_block(int64_t rows, int cols, uint64_t seed, double* __re
 }
 
 // Column counts of a CSR matrix (one atomic per entry).
-__global__ void k_col_count(int64_t nnz, const int32_t* __restrict__ col, int32_t* __restrict__ cnt) {
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < nnz;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    atomicAdd(cnt + col[e], 1);
-}
+// ---------------------------------------------------------------- transpose
+// CSR -> CSC of the sampled rows by a counting sort whose counters live in
+// LDS: the entries are cut into chunks of `chunk` entries and the columns
+// into ranges of kTrCols; block (c, g) counts, then places, the entries of
+// chunk c that fall in range g.  No device-scope atomics.
+constexpr int kTrCols = 16384;  // columns per range (64 KiB of LDS counters)
+constexpr int kTrChunks = 64;   // most chunks of entries
+constexpr int kTrBatch = 8;     // entries per thread with loads in flight together
 
-// Transpose (CSR -> CSC): entry (r, j, v) goes to slot cp[j] + (running count
-// of column j); rows within a column come in no fixed order.
-__global__ __launch_bounds__(kT) void k_csr_to_csc(int64_t rows, const int64_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                   const int32_t* __restrict__ cp, int32_t* __restrict__ cursor,
-                                                   int32_t* __restrict__ row_out, double* __restrict__ val_out) {
+// rowid[e] = the row of entry e; one wavefront per row.
+__global__ __launch_bounds__(kT) void k_entry_rows(int64_t rows, const int64_t* __restrict__ rp,
+                                                   int32_t* __restrict__ rowid) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
-  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
-    for (int64_t k = rp[r] + lane; k < rp[r + 1]; k += kWave) {
-      const int32_t j = col[k];
-      const int32_t slot = cp[j] + atomicAdd(cursor + j, 1);
-      row_out[slot] = static_cast<int32_t>(r);
-      val_out[slot] = val[k];
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw)
+    for (int64_t k = rp[r] + lane; k < rp[r + 1]; k += kWave) rowid[k] = static_cast<int32_t>(r);
+}
+
+// cnt[c * m + j] = entries of column j in chunk c, for the block's range.
+__global__ __launch_bounds__(kT) void k_chunk_col_count(int64_t nnz, int64_t chunk, int m,
+                                                        const int32_t* __restrict__ col, int32_t* __restrict__ cnt) {
+  __shared__ int32_t h[kTrCols];
+  const int64_t c = blockIdx.x;
+  const int g0 = blockIdx.y * kTrCols;
+  const int w = (m - g0) < kTrCols ? m - g0 : kTrCols;
+  for (int i = threadIdx.x; i < w; i += kT) h[i] = 0;
+  __syncthreads();
+  const int64_t e0 = c * chunk;
+  const int64_t e1 = (e0 + chunk) < nnz ? e0 + chunk : nnz;
+  // kTrBatch independent column loads in flight per thread, then the adds
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kTrBatch * kT) {
+    int j[kTrBatch];
+#pragma unroll
+    for (int u = 0; u < kTrBatch; ++u) {
+      const int64_t x = e + static_cast<int64_t>(u) * kT;
+      const int jj = col[x < e1 ? x : e1 - 1] - g0;  // an unconditional load (clamped index)
+      j[u] = x < e1 ? jj : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kTrBatch; ++u)
+      if (static_cast<unsigned>(j[u]) < static_cast<unsigned>(w)) atomicAdd(&h[j[u]], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < w; i += kT) cnt[c * m + g0 + i] = h[i];
+}
+
+// Per column: the counts become exclusive prefixes over the chunks (in
+// place) and tot[j] the column's total; tot[m] = 0 closes the scan input.
+__global__ void k_chunk_prefix(int m, int chunks, int32_t* __restrict__ cnt, int32_t* __restrict__ tot) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > m) return;
+  if (j == m) {
+    tot[m] = 0;
+    return;
+  }
+  int32_t sacc = 0;
+  for (int c = 0; c < chunks; ++c) {
+    const size_t e = static_cast<size_t>(c) * m + j;
+    const int32_t v = cnt[e];
+    cnt[e] = sacc;
+    sacc += v;
+  }
+  tot[j] = sacc;
+}
+
+// Entry (r, j, v) of chunk c goes to slot cp[j] + cnt[c][j] + (its rank
+// among the chunk's entries of column j, taken from an LDS cursor); rows
+// within a column come in no fixed order.
+__global__ __launch_bounds__(kT) void k_chunk_fill(int64_t nnz, int64_t chunk, int m, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val, const int32_t* __restrict__ rowid,
+                                                   const int32_t* __restrict__ cp, const int32_t* __restrict__ cnt,
+                                                   int32_t* __restrict__ row_out, double* __restrict__ val_out) {
+  __shared__ int32_t cur[kTrCols];
+  const int64_t c = blockIdx.x;
+  const int g0 = blockIdx.y * kTrCols;
+  const int w = (m - g0) < kTrCols ? m - g0 : kTrCols;
+  for (int i = threadIdx.x; i < w; i += kT) cur[i] = cp[g0 + i] + cnt[c * m + g0 + i];
+  __syncthreads();
+  const int64_t e0 = c * chunk;
+  const int64_t e1 = (e0 + chunk) < nnz ? e0 + chunk : nnz;
+  // kTrBatch entries per thread at a time: their loads are all issued
+  // before the LDS cursor updates and the scattered stores
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kTrBatch * kT) {
+    int j[kTrBatch];
+    int32_t r[kTrBatch];
+    double v[kTrBatch];
+#pragma unroll
+    for (int u = 0; u < kTrBatch; ++u) {
+      const int64_t x = e + static_cast<int64_t>(u) * kT;
+      const int64_t xc = x < e1 ? x : e1 - 1;  // unconditional loads (clamped index)
+      const int jj = col[xc] - g0;
+      j[u] = x < e1 ? jj : -1;
+      r[u] = rowid[xc];
+      v[u] = val[xc];
+    }
+#pragma unroll
+    for (int u = 0; u < kTrBatch; ++u) {
+      if (static_cast<unsigned>(j[u]) < static_cast<unsigned>(w)) {
+        const int32_t slot = atomicAdd(&cur[j[u]], 1);
+        row_out[slot] = r[u];
+        val_out[slot] = v[u];
+      }
     }
   }
 }
@@ -242,7 +324,9 @@ __global__ __launch_bounds__(1024) void k_jacobi(int r, int c, const double* __r
 // G <- J^T G J to one 2 x 2 block (row pair x column pair) and V <- V J to
 // rows of one column pair.  Sweeps end when no pair has |g_pq| above twice
 // the rounding level of a c-term sum, relative to sqrt(|g_pp g_qq|) and to
-// max |g_ii| (below the latter rounding alone can keep it), at most 60.
+// max |g_ii| (below the latter rounding alone can keep it), at most 60; all
+// pairs are tested together before each sweep, so no sweep is spent only to
+// find that nothing rotates.
 // All 1024 threads of the block call it; g and v are c padded to even cc.
 struct JacLds {
   double g[kMaxP][kMaxP + 1];
@@ -272,6 +356,18 @@ __device__ void jacobi_sym_lds(int c, JacLds& L) {
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) L.rotated = 0;
     __syncthreads();
+    // any pair still above the tolerance?
+    for (int e = tid; e < c * c; e += nt) {
+      const int i = e / c, j = e % c;
+      if (i < j) {
+        const double ga = L.g[i][j];
+        if (fabs(ga) > floor_abs && fabs(ga) > tol * sqrt(fabs(L.g[i][i] * L.g[j][j]))) L.rotated = 1;
+      }
+    }
+    __syncthreads();
+    const int open = L.rotated;
+    __syncthreads();
+    if (!open) break;
     for (int round = 0; round < cc - 1; ++round) {
       if (tid < np) {
         const int p = L.tp[round][tid], q = L.tq[round][tid];
@@ -351,17 +447,21 @@ __global__ __launch_bounds__(1024) void k_jacobi_sym(int c, const double* __rest
 }
 
 // Orthonormalising maps from the c x c Gram G = X^T X: Mx with X Mx having
-// orthonormal columns and F with X = (X Mx) F on the span kept.  Near the
+// orthonormal columns and F with X = (X Mx) F on the span kept.  With
+// only_if set, the kernel runs only when *only_if is nonzero (the Cholesky
+// factor before it found X numerically rank deficient).  Near the
 // identity (||G - I||_inf <= 1e-5) by the series G^{-1/2} = I - E/2 + 3E^2/8
 // and G^{1/2} = I + E/2 - E^2/8 (E = G - I; the rest is O(||E||^3));
 // otherwise from the eigendecomposition G = V diag(lam) V^T:
 // Mx = V diag(lam^{-1/2}), F = diag(lam^{1/2}) V^T, with directions of
 // eigenvalue <= floor_rel * lam_max dropped (zero columns).
 __global__ __launch_bounds__(1024) void k_orth_maps(int c, const double* __restrict__ G, double floor_rel,
-                                                    double* __restrict__ Mx, double* __restrict__ F) {
+                                                    double* __restrict__ Mx, double* __restrict__ F,
+                                                    const int32_t* __restrict__ only_if) {
   __shared__ JacLds L;
   __shared__ double rowsum[kMaxP];
   __shared__ double lam[kMaxP];
+  if (only_if != nullptr && *only_if == 0) return;
   const int tid = threadIdx.x;
   jacobi_load(c, G, L);
   if (tid < c) {
@@ -482,7 +582,7 @@ struct LrWs {
   double* valc;
   int32_t* rowT;
   double* valT;
-  int32_t *cp, *ccnt, *ctiles;
+  int32_t *cp, *ccnt, *ctiles, *rowid, *chunkcnt;
   double *SY, *Q, *F, *Ft, *G1, *X1, *P, *Pt;
   GemmScratch part;
   double *Gp, *V, *Wj, *lam, *Mx, *F1, *F2, *Fac;
@@ -533,6 +633,8 @@ LrWs carve_lr(Arena& ar, const LowRankPlan& P) {
   w.cp = P.csr ? ar.take<int32_t>(m + 1) : nullptr;
   w.ccnt = P.csr ? ar.take<int32_t>(m + 1) : nullptr;
   w.ctiles = P.csr ? ar.take<int32_t>(tiles_for(m + 1)) : nullptr;
+  w.rowid = P.csr ? ar.take<int32_t>(P.nnzmax) : nullptr;
+  w.chunkcnt = P.csr ? ar.take<int32_t>(static_cast<size_t>(kTrChunks) * m) : nullptr;
   w.SY = ar.take<double>(static_cast<size_t>(ns) * tr);
   w.Q = ar.take<double>(static_cast<size_t>(ns) * tr);
   w.F = ar.take<double>(static_cast<size_t>(m) * p);
@@ -570,14 +672,27 @@ LrWs carve_lr(Arena& ar, const LowRankPlan& P) {
   return w;
 }
 
-// X (rows x c, packed) -> X with orthonormal columns (two passes of
-// Gram-based orthonormalisation); fac (c x c) with X_in = X_out fac.
+// X (rows x c, packed) -> X with orthonormal columns by two passes of
+// Gram-based orthonormalisation (CholeskyQR2); fac (c x c) with
+// X_in = X_out fac.  Pass 1 maps X by R^{-1} for the Cholesky factor R of
+// its Gram; where that factor reports numerical rank deficiency, the
+// eigendecomposition maps (which drop the null directions) replace it on
+// the device, with no host round trip.  Pass 2 starts from a Gram within
+// about kappa(X)^2 u of the identity and takes the series maps of
+// k_orth_maps (or its eigen route when further away).
 int32_t svqb2(double* X, double* tmp, int64_t rows, int c, double* fac, LrWs& w, hipStream_t s) {
   double* cur = X;
   double* nxt = tmp;
+  int32_t* chol_bad = w.status + 2;
   for (int pass = 0; pass < 2; ++pass) {
     SKLS_TRY(run_gram(cur, SKLS_F64, c, nullptr, SKLS_F64, rows, c, w.Gp, w.gram, w.gram_bytes, s));
-    hipLaunchKernelGGL(k_orth_maps, dim3(1), dim3(1024), 0, s, c, w.Gp, kDropRel, w.Mx, pass == 0 ? w.F1 : w.F2);
+    if (pass == 0) {
+      SKLS_TRY(run_cholesky(w.Gp, c, c, w.F1, w.Mx, w.Wj, chol_bad, w.cholw, s));
+      hipLaunchKernelGGL(k_orth_maps, dim3(1), dim3(1024), 0, s, c, w.Gp, kDropRel, w.Mx, w.F1, chol_bad);
+    } else {
+      hipLaunchKernelGGL(k_orth_maps, dim3(1), dim3(1024), 0, s, c, w.Gp, kDropRel, w.Mx, w.F2,
+                         static_cast<const int32_t*>(nullptr));
+    }
     SKLS_CHECK_LAUNCH();
     SKLS_TRY(gemm(false, rows, c, c, 1.0, cur, c, w.Mx, c, nxt, c, w.part, s));
     std::swap(cur, nxt);
@@ -776,14 +891,20 @@ int32_t run_low_rank(const skls_matrix& A, const LowRankPlan& P, uint64_t seed, 
           set_error("low_rank: the sampled rows hold 2^31 or more nonzeros");
           return SKLS_ERR_SHAPE;
         }
-        const size_t cbytes = static_cast<size_t>((m + 1 + 3) / 4) * 16;
-        SKLS_TRY(launch_fill_zero(w.ccnt, cbytes, s));
-        hipLaunchKernelGGL(k_col_count, dim3(grid_for(nnz_s, kT, 8192)), dim3(kT), 0, s, nnz_s, w.colc, w.ccnt);
+        const int64_t chunk = std::max<int64_t>(16384, div_up(nnz_s, kTrChunks));
+        const int chunks = static_cast<int>(std::max<int64_t>(div_up(nnz_s, chunk), 1));
+        const dim3 tg(static_cast<unsigned>(chunks), static_cast<unsigned>(div_up(m, kTrCols)));
+        hipLaunchKernelGGL(k_entry_rows, dim3(grid_for(ns, kT / kWave, 8192)), dim3(kT), 0, s, ns, w.rp, w.rowid);
+        SKLS_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_chunk_col_count, tg, dim3(kT), 0, s, nnz_s, chunk, static_cast<int>(m), w.colc,
+                           w.chunkcnt);
+        SKLS_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_chunk_prefix, dim3(static_cast<unsigned>(div_up(m + 1, kT))), dim3(kT), 0, s,
+                           static_cast<int>(m), chunks, w.chunkcnt, w.ccnt);
         SKLS_CHECK_LAUNCH();
         SKLS_TRY(scan<int32_t>(w.ccnt, m + 1, w.ctiles, w.cp, true, s));  // cp[m] = nnz_s
-        SKLS_TRY(launch_fill_zero(w.ccnt, cbytes, s));
-        hipLaunchKernelGGL(k_csr_to_csc, dim3(grid_for(ns, kT / kWave, 8192)), dim3(kT), 0, s, ns, w.rp, w.colc,
-                           w.valc, w.cp, w.ccnt, w.rowT, w.valT);
+        hipLaunchKernelGGL(k_chunk_fill, tg, dim3(kT), 0, s, nnz_s, chunk, static_cast<int>(m), w.colc, w.valc,
+                           w.rowid, w.cp, w.chunkcnt, w.rowT, w.valT);
         SKLS_CHECK_LAUNCH();
         return SKLS_OK;
       });

@@ -339,13 +339,14 @@ __device__ __forceinline__ double lane_d(double v, int q) {
 
 // out (rows x p) = S X for S in CSR (any value and row-pointer type) and X
 // (cols x p, float64); one wavefront per row.  The row's entries are loaded
-// 64 at a time and read back lane by lane as scalars (uniform index), four
+// 64 at a time and read back lane by lane as scalars (uniform index), eight
 // independent loads of X in flight.  HALF: p <= 32, the two half-waves take
 // alternate entries and are summed at the end.
 template <typename TV, typename TR, bool HALF>
 __global__ __launch_bounds__(kT) void k_spmm(int64_t rows, int p, const TR* __restrict__ rp,
                                              const int32_t* __restrict__ col, const TV* __restrict__ val,
                                              const double* __restrict__ X, double* __restrict__ out) {
+  constexpr int NB = 8;  // gathers in flight per lane
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t nw = static_cast<int64_t>(gridDim.x) * (kT / kWave);
   const int c = HALF ? (lane & 31) : lane;
@@ -355,18 +356,18 @@ __global__ __launch_bounds__(kT) void k_spmm(int64_t rows, int p, const TR* __re
   constexpr int STEP = HALF ? 2 : 1;
   for (int64_t r = blockIdx.x * static_cast<int64_t>(kT / kWave) + threadIdx.x / kWave; r < rows; r += nw) {
     const int64_t b = static_cast<int64_t>(rp[r]), e = static_cast<int64_t>(rp[r + 1]);
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t k0 = b; k0 < e; k0 += kWave) {
       const int64_t k = k0 + lane;
       const int32_t cj = k < e ? col[k] : 0;
       const double vj = k < e ? load_as<double>(val, static_cast<size_t>(k)) : 0.0;  // 0 beyond the row
       const int cnt = (e - k0) < kWave ? static_cast<int>(e - k0) : kWave;
-      const int cnt_up = (cnt + 4 * STEP - 1) / (4 * STEP) * (4 * STEP);  // zero values pad the tail
-      for (int q = 0; q < cnt_up; q += 4 * STEP) {
-        int32_t j[4];
-        double v[4];
+      const int cnt_up = (cnt + NB * STEP - 1) / (NB * STEP) * (NB * STEP);  // zero values pad the tail
+      for (int q = 0; q < cnt_up; q += NB * STEP) {
+        int32_t j[NB];
+        double v[NB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < NB; ++u) {
           const int qa = q + u * STEP;
           if (HALF) {
             const int32_t ja = lane_i(cj, qa), jb = lane_i(cj, qa + 1);
@@ -378,16 +379,16 @@ __global__ __launch_bounds__(kT) void k_spmm(int64_t rows, int p, const TR* __re
             v[u] = lane_d(vj, qa);
           }
         }
-        double x[4];
+        double x[NB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = X[static_cast<size_t>(j[u]) * p + lc];
-        acc0 += v[0] * x[0] + v[2] * x[2];
-        acc1 += v[1] * x[1] + v[3] * x[3];
+        for (int u = 0; u < NB; ++u) x[u] = X[static_cast<size_t>(j[u]) * p + lc];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[u & 3] += v[u] * x[u];
       }
     }
-    double acc = acc0 + acc1;
-    if (HALF) acc += __shfl_xor(acc, 32);
-    if (live && h == 0) out[static_cast<size_t>(r) * p + c] = acc;
+    double a = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if (HALF) a += __shfl_xor(a, 32);
+    if (live && h == 0) out[static_cast<size_t>(r) * p + c] = a;
   }
 }
 
