@@ -374,6 +374,21 @@ def main():
             result["lstsq_small"] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
                                      "note": "sketch-and-solve only (no LSQR), launch-bound; its residual ratio "
                                              "against the oracle's is in cpu_baseline.parity"}
+            # certified solves (sketch-and-solve, then LSQR to 1 + 1e-6)
+            certified = {}
+            for precision in ("plain", "mixed"):
+                for _ in range(3):
+                    sk.lstsq(A1g, b1g, 4000, seed, delta=1e-6, precision=precision)
+                sync()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    _, ci = sk.lstsq(A1g, b1g, 4000, seed, delta=1e-6, precision=precision)
+                sync()
+                el = (time.perf_counter() - t0) / reps
+                certified[precision] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
+                                        "iterations": ci["iterations"], "refinements": ci["refinements"],
+                                        "certified": ci["certified"]}
+            result["lstsq_small"]["certified_1e-6"] = certified
             small_run = (A1, b1, x1.cpu().numpy())
             del A1g, b1g
 

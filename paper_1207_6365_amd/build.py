@@ -73,5 +73,47 @@ def build(verbose: bool = True, jobs: int = 6) -> str:
     return LIB
 
 
+# Host-code sanitizers: every flag applies to the host compilation only
+# (-Xarch_host); the device code is built as usual and not instrumented.  The
+# result serves host-side checks of the C ABI (argument validation,
+# workspace arithmetic).
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(outdir: str, driver: str, jobs: int = 6) -> str:
+    """Compile the library's host code with AddressSanitizer and
+    UndefinedBehaviorSanitizer into ``outdir`` and link it with the C program
+    ``driver``; returns the path of the executable."""
+    cc = hipcc()
+    os.makedirs(outdir, exist_ok=True)
+    base = [f"--offload-arch={ARCH}", "-O1", "-g", "-std=c++17", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", os.path.join(ROOT, "include"), "-I", CSRC, *SAN_FLAGS]
+    procs, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(outdir, os.path.splitext(src)[0] + ".o")
+        objs.append(obj)
+        cmd = [cc, *base, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        while sum(p.poll() is None for _, p in procs) >= jobs:
+            time.sleep(0.05)
+    failed = []
+    for src, p in procs:
+        out = p.communicate()[0].decode(errors="replace")
+        if p.returncode != 0:
+            failed.append(f"== {src}\n{out}")
+    if failed:
+        raise RuntimeError("sanitized host build failed:\n" + "\n".join(failed))
+    lib = os.path.join(outdir, "libskls_host_san.so")
+    subprocess.run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", lib, *objs, *SAN_FLAGS], check=True)
+    exe = os.path.join(outdir, "abi_check")
+    drv_obj = os.path.join(outdir, "driver.o")
+    subprocess.run([cc, "-x", "c", "-O1", "-g", "-I", os.path.join(ROOT, "include"), *SAN_FLAGS, "-c", driver,
+                    "-o", drv_obj], check=True)
+    subprocess.run([cc, "-o", exe, drv_obj, lib, *SAN_FLAGS, f"-Wl,-rpath,{outdir}"], check=True)
+    return exe
+
+
 if __name__ == "__main__":
     build()

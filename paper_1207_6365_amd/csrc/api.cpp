@@ -592,6 +592,16 @@ int32_t skls_lstsq_workspace(const skls_matrix* A, const skls_lstsq_opts* opts, 
 
 namespace {
 
+// LSQR steps enqueued between reads of the device state: about 32 MB of A
+// per batch, at most 8 steps.
+int lsqr_batch(const skls_matrix& A, bool plain) {
+  const int64_t es = A.dtype == SKLS_F64 ? 8 : (A.dtype == SKLS_F32 ? 4 : 2);
+  const int64_t bytes = A.layout == SKLS_CSR ? A.nnz * (es + 4) + A.n * 8 : A.n * A.d * es;
+  const int64_t per = bytes + A.n * (plain ? 16 : 8);  // plus U read and written
+  const int64_t b = per > 0 ? (int64_t(32) << 20) / per : 8;
+  return static_cast<int>(b < 1 ? 1 : (b > 8 ? 8 : b));
+}
+
 // One attempt of skls_lstsq with the seed in o (options filled, workspace
 // carved); inf is reset and filled.
 int32_t lstsq_once(const skls_matrix* A, const double* b, const skls_lstsq_opts& o, double* x, LsWs& L,
@@ -703,16 +713,43 @@ int32_t lstsq_once(const skls_matrix* A, const double* b, const skls_lstsq_opts&
     pa.z_is_b = 0;
     pa.coef = L.st + LSQR_COEF;
     SKLS_TRY(run_gemv(L.Rinv, d, L.v, L.p, s));
+    // Steps are enqueued in batches and the state is read once per batch:
+    // the step kernel applies the stopping test itself and leaves the state
+    // alone after it holds, so steps past the stop only repeat the same
+    // pass.  The first batch is one step; later ones are one fewer than the
+    // steps that the observed rate of decrease of est_ar / est_r predicts
+    // are still needed, at most `cap` (several for a small A, where a host
+    // round trip costs as much as a step; one for a large A).
+    const int cap = lsqr_batch(*A, plain);
+    int64_t taken = 0;  // steps of this inner solve already counted
+    double ratio = ratio0;
+    int nb_next = 1;
     while (inf.iterations < o.max_iter) {
-      SKLS_TRY(run_pass(pa, s));
-      SKLS_TRY(run_reduce_partials(L.partial, L.nblk, d, L.gsum, L.red, s));
-      SKLS_TRY(run_gemv(L.q.RinvT, d, L.gsum, L.vp, s));
-      SKLS_TRY(run_lsqr_step(L.gsum, L.vp, d, L.v, L.w, L.y, L.st, s));
-      SKLS_TRY(run_gemv(L.Rinv, d, L.v, L.p, s));
-      ++inf.iterations;
+      const int nb = std::min(nb_next, o.max_iter - inf.iterations);
+      for (int b = 0; b < nb; ++b) {
+        SKLS_TRY(run_pass(pa, s));
+        SKLS_TRY(run_reduce_partials(L.partial, L.nblk, d, L.gsum, L.red, s));
+        SKLS_TRY(run_gemv(L.q.RinvT, d, L.gsum, L.vp, s));
+        SKLS_TRY(run_lsqr_step(L.gsum, L.vp, d, L.v, L.w, L.y, L.st, target, s));
+        SKLS_TRY(run_gemv(L.Rinv, d, L.v, L.p, s));
+      }
       SKLS_TRY_HIP(hipMemcpyAsync(hs, L.st, sizeof hs, hipMemcpyDeviceToHost, s));
       SKLS_TRY_HIP(hipStreamSynchronize(s));
-      if (hs[LSQR_DONE] != 0.0 || hs[LSQR_EST_AR] <= target * hs[LSQR_EST_R]) break;
+      const int64_t count = static_cast<int64_t>(hs[LSQR_COUNT]);
+      const int64_t did = count - taken;
+      inf.iterations += static_cast<int32_t>(did);
+      taken = count;
+      if (hs[LSQR_STOP] != 0.0) break;
+      const double now = hs[LSQR_EST_R] > 0.0 ? hs[LSQR_EST_AR] / hs[LSQR_EST_R] : 0.0;
+      nb_next = 1;
+      if (did > 0 && now > 0.0 && ratio > 0.0 && now < ratio) {
+        const double rate = std::pow(now / ratio, 1.0 / static_cast<double>(did));
+        // one step short of the prediction: a step is wasted only if the
+        // decrease speeds up, and a wrong guess costs one more read
+        const double need = std::ceil(std::log(target / now) / std::log(rate)) - 1.0;
+        if (need > 1.0) nb_next = need >= cap ? cap : static_cast<int>(need);
+      }
+      ratio = now;
     }
     // x += R^{-1} y
     SKLS_TRY(run_gemv(L.Rinv, d, L.y, L.tmp, s));

@@ -110,12 +110,16 @@ enum {
   LSQR_EST_AR,
   LSQR_ONE,
   LSQR_DONE,
+  LSQR_STOP,   // 1 once a step met the inner target (later steps leave the state alone)
+  LSQR_COUNT,  // steps taken since the last init
   LSQR_NSTATE
 };
 int32_t run_lsqr_init(const double* gsum, const double* vp, int64_t d, double* v, double* w, double* y, double* st,
                       hipStream_t s);
+// One step; it is skipped (state unchanged) once st[LSQR_STOP] is set, and
+// sets it when the recurrence ends or est_ar <= target * est_r.
 int32_t run_lsqr_step(const double* gsum, const double* vp, int64_t d, double* v, double* w, double* y, double* st,
-                      hipStream_t s);
+                      double target, hipStream_t s);
 // y = a * x (d-vectors); x += t.
 int32_t run_scale(const double* x, int64_t d, double a, double* y, hipStream_t s);
 int32_t run_add(double* x, const double* t, int64_t d, hipStream_t s);

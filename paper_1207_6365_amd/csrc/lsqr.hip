@@ -408,13 +408,17 @@ __global__ __launch_bounds__(256) void k_lsqr_init(const double* __restrict__ gs
     st[LSQR_EST_AR] = alpha * beta;
     st[LSQR_ONE] = 1.0;
     st[LSQR_DONE] = (alpha > 0.0 && beta > 0.0) ? 0.0 : 1.0;
+    st[LSQR_STOP] = 0.0;
+    st[LSQR_COUNT] = 0.0;
   }
 }
 
 __global__ __launch_bounds__(256) void k_lsqr_step(const double* __restrict__ gsum, const double* __restrict__ vp,
                                                    int d, double* __restrict__ v, double* __restrict__ w,
-                                                   double* __restrict__ y, double* __restrict__ st) {
+                                                   double* __restrict__ y, double* __restrict__ st, double target) {
   __shared__ double scratch[4];
+  // read by every thread before thread 0 writes it below (after a barrier)
+  if (st[LSQR_STOP] != 0.0) return;
   const double beta = sqrt(gsum[d]);
   const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
   double ss = 0.0;
@@ -448,9 +452,13 @@ __global__ __launch_bounds__(256) void k_lsqr_step(const double* __restrict__ gs
     st[LSQR_RHOBAR] = -c * alpha;
     st[LSQR_PHIBAR] = phibar_new;
     st[LSQR_COEF] = beta > 0.0 ? -alpha / beta : 0.0;
+    const double est_ar = phibar_new * alpha * fabs(c);
+    const bool done = !(alpha > 0.0 && beta > 0.0);
     st[LSQR_EST_R] = phibar_new;
-    st[LSQR_EST_AR] = phibar_new * alpha * fabs(c);
-    st[LSQR_DONE] = (alpha > 0.0 && beta > 0.0) ? 0.0 : 1.0;
+    st[LSQR_EST_AR] = est_ar;
+    st[LSQR_DONE] = done ? 1.0 : 0.0;
+    st[LSQR_COUNT] += 1.0;
+    st[LSQR_STOP] = (done || est_ar <= target * phibar_new) ? 1.0 : 0.0;
   }
 }
 
@@ -472,8 +480,8 @@ int32_t run_lsqr_init(const double* gsum, const double* vp, int64_t d, double* v
 }
 
 int32_t run_lsqr_step(const double* gsum, const double* vp, int64_t d, double* v, double* w, double* y, double* st,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_lsqr_step, dim3(1), dim3(256), 0, s, gsum, vp, static_cast<int>(d), v, w, y, st);
+                      double target, hipStream_t s) {
+  hipLaunchKernelGGL(k_lsqr_step, dim3(1), dim3(256), 0, s, gsum, vp, static_cast<int>(d), v, w, y, st, target);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }
