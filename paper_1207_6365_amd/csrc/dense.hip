@@ -971,6 +971,36 @@ size_t gram_ws_bytes(int64_t m, int64_t dd) {
   return need;
 }
 
+namespace {
+
+// A second stream on the current device (default priority, created once per
+// host thread and device) with the two events that fork work onto it from a
+// caller's stream and join it back.
+struct SideStream {
+  int device = -1;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+SideStream* side_stream() {
+  thread_local SideStream side[16];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return nullptr;
+  SideStream& x = side[dev];
+  if (x.s == nullptr) {
+    if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&x.join, hipEventDisableTiming) != hipSuccess) {
+      x.s = nullptr;
+      return nullptr;
+    }
+    x.device = dev;
+  }
+  return &x;
+}
+
+}  // namespace
+
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,
                  double* G, void* ws, size_t ws_bytes, hipStream_t s) {
   const GramShape g = gram_shape(m, d);
@@ -985,6 +1015,17 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
   const int v_f64 = v_dtype == SKLS_F64 ? 1 : 0;
   const int di = static_cast<int>(d);
   PhaseTimer pt("gram", s);
+  // On large inputs the off-diagonal tiles run on a side stream beside the
+  // diagonal ones (the two launches are independent), joined before the
+  // reduction; on small ones the fork and join across queues cost more than
+  // the overlap gains.
+  SideStream* side = (g.So > 0 && m * d >= (int64_t(1) << 24)) ? side_stream() : nullptr;
+  hipStream_t so = s;
+  if (side != nullptr) {
+    SKLS_TRY_HIP(hipEventRecord(side->fork, s));
+    SKLS_TRY_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
+    so = side->s;
+  }
   auto launch = [&](auto tag, auto vec) -> int32_t {
     using TI = decltype(tag);
     constexpr bool VEC = decltype(vec)::value;
@@ -998,7 +1039,7 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
     }
     SKLS_CHECK_LAUNCH();
     if (g.So > 0) {
-      hipLaunchKernelGGL((k_gram_partial<TI, VEC, false, false>), dim3(g.P - g.T, g.So), dim3(kGThreads), 0, s, Mt,
+      hipLaunchKernelGGL((k_gram_partial<TI, VEC, false, false>), dim3(g.P - g.T, g.So), dim3(kGThreads), 0, so, Mt,
                          ld, v, v_f64, m, di, g.T, g.P, g.rpo, partial, partial_v);
       SKLS_CHECK_LAUNCH();
     }
@@ -1015,6 +1056,16 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
     case SKLS_F32: st = with_vec(float{}); break;
     case SKLS_BF16: st = with_vec(bf16_t{}); break;
     default: set_error("gram: bad dtype"); return SKLS_ERR_DTYPE;
+  }
+  if (side != nullptr) {
+    // join even after a failed launch, so that the side stream never runs
+    // past the caller's stream
+    const hipError_t e1 = hipEventRecord(side->join, side->s);
+    const hipError_t e2 = hipStreamWaitEvent(s, side->join, 0);
+    if (st == SKLS_OK && (e1 != hipSuccess || e2 != hipSuccess)) {
+      set_error("gram: joining the side stream failed");
+      return SKLS_ERR_DEVICE;
+    }
   }
   if (st != SKLS_OK) return st;
   hipLaunchKernelGGL(k_gram_reduce, dim3(g.P + 1, kGT * kGT / 256), dim3(256), 0, s, partial, partial_v, g.P, g.Sd,

@@ -86,6 +86,25 @@ __global__ __launch_bounds__(kT) void k_sum_partials(const double* __restrict__ 
   }
 }
 
+// k_sum_partials for the two interior-point sums (gap, objective), which it
+// also writes with the factor status straight to pinned host memory.
+__global__ __launch_bounds__(kT) void k_gap_publish(const double* __restrict__ partial, int nb,
+                                                    double* __restrict__ out, const int32_t* __restrict__ status,
+                                                    double* host_g, int32_t* host_st) {
+  __shared__ double sh[kT / kWave];
+  for (int j = 0; j < 2; ++j) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kT) s += partial[j * nb + b];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+      out[j] = s;
+      host_g[j] = s;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) host_st[0] = status[0];
+}
+
 __device__ __forceinline__ double block_min(double v, double* sh) {
   for (int off = kWave / 2; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -180,20 +199,10 @@ __global__ __launch_bounds__(kT) void k_irls_weights(int64_t ns, const double* _
 }
 
 // d-vectors: out = a - b; x = x + t (y - x); x += (*alpha) v.
-__global__ void k_vsub(int64_t d, const double* __restrict__ a, const double* __restrict__ b,
-                       double* __restrict__ out) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x;
-  if (i < d) out[i] = a[i] - b[i];
-}
 __global__ void k_vlerp(int64_t d, const double* __restrict__ x, const double* __restrict__ y, double t,
                         double* __restrict__ out) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x;
   if (i < d) out[i] = x[i] + t * (y[i] - x[i]);
-}
-__global__ void k_vaxpy_dev(int64_t d, const double* __restrict__ alpha, const double* __restrict__ v,
-                            double* __restrict__ x) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x;
-  if (i < d) x[i] += alpha[0] * v[i];
 }
 
 // ---------------------------------------------------------------- l_1 fit
@@ -359,8 +368,10 @@ __global__ __launch_bounds__(kT) void k_rmatvec_part(int64_t ns, int64_t d, cons
 }
 // 8 columns per block, 32 threads per column: thread t sums slices t,
 // t + 32, ..., then thread 0 of each column adds the 32 sums in order.
+// out[c] = s_sum * (sum of the slices) + s_other * other[c] (other may be NULL).
 __global__ __launch_bounds__(kT) void k_col_sum(int nb, int64_t d, const double* __restrict__ part,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out, double s_sum,
+                                                const double* __restrict__ other, double s_other) {
   __shared__ double sh[kT / 8][8];
   const int cc = threadIdx.x & 7, t = threadIdx.x >> 3;
   const int64_t c = blockIdx.x * static_cast<int64_t>(8) + cc;
@@ -372,16 +383,24 @@ __global__ __launch_bounds__(kT) void k_col_sum(int nb, int64_t d, const double*
   if (t == 0 && c < d) {
     double tot = 0.0;
     for (int k = 0; k < kT / 8; ++k) tot += sh[k][cc];
-    out[c] = tot;
+    out[c] = other != nullptr ? s_sum * tot + s_other * other[c] : s_sum * tot;
   }
 }
 
+// The step on the duals and slacks; x (d entries) is first copied to save
+// and then moved by the dual step length along dx.
 __global__ __launch_bounds__(kT) void k_ipm_update(int64_t ns, const double* __restrict__ steps,
                                                    double* __restrict__ a, double* __restrict__ sl,
                                                    double* __restrict__ z, double* __restrict__ w,
                                                    const double* __restrict__ da, const double* __restrict__ dz,
-                                                   const double* __restrict__ dw) {
+                                                   const double* __restrict__ dw, int64_t d,
+                                                   const double* __restrict__ dx, double* __restrict__ x,
+                                                   double* __restrict__ save) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(kT) + threadIdx.x;
+  for (int64_t j = i; j < d; j += static_cast<int64_t>(gridDim.x) * kT) {
+    save[j] = x[j];
+    x[j] += steps[1] * dx[j];
+  }
   if (i >= ns) return;
   const double ap = steps[0], ad = steps[1];
   a[i] += ap * da[i];
@@ -463,11 +482,12 @@ LpWs carve_lp(Arena& ar, const LpPlan& P) {
 unsigned g_rows(int64_t n) { return grid_for(n, kT, 1u << 24); }
 
 // out = M^T v for the coreset rows (ns x d, row-major).
-int32_t rmatvec(const LpWs& w, int64_t ns, int64_t d, const double* v, double* out, hipStream_t s) {
+int32_t rmatvec(const LpWs& w, int64_t ns, int64_t d, const double* v, double* out, hipStream_t s,
+                double s_sum = 1.0, const double* other = nullptr, double s_other = 0.0) {
   hipLaunchKernelGGL(k_rmatvec_part, dim3(kRmvBlocks), dim3(kT), 0, s, ns, d, w.Ms, v, w.rmv);
   SKLS_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_col_sum, dim3(static_cast<unsigned>(div_up(d, 8))), dim3(kT), 0, s, kRmvBlocks, d, w.rmv,
-                     out);
+                     out, s_sum, other, s_other);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }
@@ -597,9 +617,7 @@ int32_t fit_irls(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, d
 // One reduced Newton solve: rhs = M^T qrho - r1, dx = (M^T Q M)^{-1} rhs,
 // Mdx = M dx, then the directions and step bounds.
 int32_t ipm_direction(const LpWs& w, int64_t ns, int64_t d, double factor, hipStream_t s) {
-  SKLS_TRY(rmatvec(w, ns, d, w.qrho, w.rhs, s));
-  hipLaunchKernelGGL(k_vsub, dim3(g_rows(d)), dim3(kT), 0, s, d, w.rhs, w.r1, w.rhs);
-  SKLS_CHECK_LAUNCH();
+  SKLS_TRY(rmatvec(w, ns, d, w.qrho, w.rhs, s, 1.0, w.r1, -1.0));  // rhs = M^T qrho - r1
   SKLS_TRY(run_solve_from_gram(w.Rinv, w.RinvT, w.rhs, d, w.dx, w.tmpd, s));
   hipLaunchKernelGGL(k_resid_rows, dim3(kResBlocks), dim3(kT), 0, s, ns, d, w.Ms, w.dx, nullptr, w.Mdx, 1.0,
                      nullptr);
@@ -610,6 +628,23 @@ int32_t ipm_direction(const LpWs& w, int64_t ns, int64_t d, double factor, hipSt
   hipLaunchKernelGGL(k_ipm_steps, dim3(1), dim3(kT), 0, s, w.part, kRed, factor, w.dev + 2);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
+}
+
+// Pinned host memory for reads that must not wait for later work on the
+// stream: two slots of (gap, objective) and the factor status.  One small
+// buffer per host thread, allocated on first use and kept.
+// Coherent, so that a kernel's stores reach it without a copy.
+struct GapSlots {
+  double g[2][2];
+  int32_t st[2];
+};
+GapSlots* gap_slots() {
+  thread_local GapSlots* p = nullptr;
+  if (p == nullptr) {
+    void* q = nullptr;
+    if (hipHostMalloc(&q, sizeof(GapSlots), hipHostMallocCoherent) == hipSuccess) p = static_cast<GapSlots*>(q);
+  }
+  return p;
 }
 
 int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, Fit& out, hipStream_t s) {
@@ -628,44 +663,58 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     out.converged = true;
     return SKLS_OK;
   }
+  GapSlots* hs = gap_slots();
+  if (hs == nullptr) {
+    set_error("lp_regression: no pinned host memory for the gap reads");
+    return SKLS_ERR_DEVICE;
+  }
+  GapSlots* dg = nullptr;  // the same memory as the device addresses it
+  SKLS_TRY_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&dg), hs, 0));
+  hipEvent_t ev[2];
+  SKLS_TRY_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    set_error("lp_regression: hipEventCreate failed");
+    return SKLS_ERR_DEVICE;
+  }
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      (void)hipEventDestroy(e[0]);
+      (void)hipEventDestroy(e[1]);
+    }
+  } guard{ev};
   const unsigned g = g_rows(ns);
   hipLaunchKernelGGL(k_ipm_init, dim3(g), dim3(kT), 0, s, ns, w.r, f1 / static_cast<double>(ns), w.a, w.sl, w.z,
                      w.w);
   SKLS_CHECK_LAUNCH();
   // c = M^T a at the start (a = 1/2): the dual equality M^T a = c holds there
   SKLS_TRY(rmatvec(w, ns, d, w.a, w.c, s));
-  for (int it = 0; it <= max_iter; ++it) {
+  // x before step it is kept in save[it & 1] (two slots: a step taken ahead
+  // of its decision may have to be undone, and so may the one before it)
+  double* save[2] = {w.xt, w.xn};
+  // the duality gap and objective at the current iterate, and the status of
+  // the factor of the step that led to it, into pinned slot k
+  auto gap = [&](int k) -> int32_t {
     hipLaunchKernelGGL(k_resid_rows, dim3(kResBlocks), dim3(kT), 0, s, ns, d, w.Ms, w.x, w.ys, w.r, 1.0, nullptr);
     SKLS_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_ipm_gap, dim3(kRed), dim3(kT), 0, s, ns, w.a, w.sl, w.z, w.w, w.r, w.part);
     SKLS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, w.part, kRed, 2, w.dev);
+    hipLaunchKernelGGL(k_gap_publish, dim3(1), dim3(kT), 0, s, w.part, kRed, w.dev, w.status, dg->g[k],
+                       &dg->st[k]);
     SKLS_CHECK_LAUNCH();
-    // the gap and objective, and the status of the previous step's factor
-    int32_t st = 0;
-    if (it > 0) SKLS_TRY_HIP(hipMemcpyAsync(&st, w.status, sizeof st, hipMemcpyDeviceToHost, s));
-    double h[2];
-    SKLS_TRY(to_host(h, w.dev, sizeof h, s));
-    if (st) {  // that factor broke down: back to the iterate before the step
-      SKLS_TRY_HIP(hipMemcpyAsync(w.x, w.xt, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
-      out.iters = it;
-      break;
-    }
-    out.obj = h[1];
-    if (h[0] <= tol * std::max(1.0, h[1])) {
-      out.converged = true;
-      break;
-    }
-    if (it == max_iter) break;
+    SKLS_TRY_HIP(hipEventRecord(ev[k], s));
+    return SKLS_OK;
+  };
+  // one predictor-corrector step from the current iterate
+  auto step = [&](int it) -> int32_t {
     // r1 = c - M^T a
-    SKLS_TRY(rmatvec(w, ns, d, w.a, w.tmpd, s));
-    hipLaunchKernelGGL(k_vsub, dim3(g_rows(d)), dim3(kT), 0, s, d, w.c, w.tmpd, w.r1);
-    SKLS_CHECK_LAUNCH();
+    SKLS_TRY(rmatvec(w, ns, d, w.a, w.r1, s, -1.0, w.c, 1.0));
     // predictor
     hipLaunchKernelGGL(k_ipm_rhs<false>, dim3(g), dim3(kT), 0, s, ns, w.r, w.a, w.sl, w.z, w.w, w.da, w.dz, w.dw,
                        w.dev + 4, w.qi, w.rho, w.qrho, w.r4, w.r5);
     SKLS_CHECK_LAUNCH();
-    SKLS_TRY(factor_weighted<true>(w, ns, d, w.qi, false, nullptr, s));  // status read at the next gap
+    SKLS_TRY(factor_weighted<true>(w, ns, d, w.qi, false, nullptr, s));  // status read with the next gap
     SKLS_TRY(ipm_direction(w, ns, d, 1.0, s));
     hipLaunchKernelGGL(k_ipm_gaff, dim3(kRed), dim3(kT), 0, s, ns, w.a, w.sl, w.z, w.w, w.da, w.dz, w.dw,
                        w.dev + 2, w.part);
@@ -677,14 +726,45 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
                        w.dev + 4, w.qi, w.rho, w.qrho, w.r4, w.r5);
     SKLS_CHECK_LAUNCH();
     SKLS_TRY(ipm_direction(w, ns, d, 0.99995, s));
+    // the duals and slacks, and x (saved first) by the dual step along dx
     hipLaunchKernelGGL(k_ipm_update, dim3(g), dim3(kT), 0, s, ns, w.dev + 2, w.a, w.sl, w.z, w.w, w.da, w.dz,
-                       w.dw);
+                       w.dw, d, w.dx, w.x, save[it & 1]);
     SKLS_CHECK_LAUNCH();
-    SKLS_TRY_HIP(hipMemcpyAsync(w.xt, w.x, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_vaxpy_dev, dim3(g_rows(d)), dim3(kT), 0, s, d, w.dev + 3, w.dx, w.x);
-    SKLS_CHECK_LAUNCH();
+    return SKLS_OK;
+  };
+  auto restore = [&](int from) -> int32_t {
+    SKLS_TRY_HIP(hipMemcpyAsync(w.x, save[from & 1], sizeof(double) * d, hipMemcpyDeviceToDevice, s));
+    return SKLS_OK;
+  };
+  // Iteration it reads gap(it) while step(it), enqueued ahead of the
+  // decision, already runs: the host's round trip is hidden behind the
+  // step.  The iterates accepted are those of the plain loop (read the gap,
+  // then step); a step taken ahead and not wanted is undone.
+  SKLS_TRY(gap(0));
+  if (max_iter > 0) SKLS_TRY(step(0));
+  for (int it = 0; it <= max_iter; ++it) {
+    const int k = it & 1;
+    SKLS_TRY_HIP(hipEventSynchronize(ev[k]));
+    const double hgap = hs->g[k][0], hobj = hs->g[k][1];
+    const int32_t st = it > 0 ? hs->st[k] : 0;
+    const bool ahead = it < max_iter;  // step(it) was enqueued
+    if (st) {  // the factor of step(it - 1) broke down: back to the iterate before it
+      SKLS_TRY(restore(it - 1));
+      out.iters = it;
+      break;
+    }
+    out.obj = hobj;
+    if (hgap <= tol * std::max(1.0, hobj)) {
+      if (ahead) SKLS_TRY(restore(it));
+      out.converged = true;
+      break;
+    }
+    if (!ahead) break;
     out.iters = it + 2;  // the least-squares start and it + 1 interior-point steps
+    SKLS_TRY(gap(k ^ 1));
+    if (it + 1 < max_iter) SKLS_TRY(step(it + 1));
   }
+  SKLS_TRY_HIP(hipStreamSynchronize(s));
   return SKLS_OK;
 }
 
