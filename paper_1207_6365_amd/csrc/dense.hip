@@ -451,83 +451,131 @@ __device__ __forceinline__ double recip(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+// Lane `src`'s value of v, in every lane (two 32-bit reads of one lane).
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(bits & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), src);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kPW = 16;           // panel width of the tile factor
+constexpr int kSP = kCP;          // LDS pitch of the scaled panel rows
+
 // Factor the kb x kb tile whose upper triangle thread (g, j) (g = wave,
 // j = lane) holds in c[q] = element (4 q + g, j) into rr = R_KK (upper, zero
-// elsewhere).  Right-looking with the trailing triangle in registers: step k
-// publishes row k (double-buffered in LDS, stored by residue class of the row
-// index so that each wave reads its 16 values as 8 contiguous pairs), then
-// every thread updates its column: one barrier per column.  To keep the
-// chain from one column to the next short:
-//  * the update uses a_ij - a_ki (a_kj / a_kk), so the chain holds one
-//    reciprocal of the pivot and no square root;
-//  * the wave that owns row k + 1 updates and publishes it before the rest
-//    of its column, so the next barrier does not wait for the other updates;
-//  * R's rows are scaled by 1 / sqrt(pivot) after the loop.
-// The columns run as a loop over groups of four (not unrolled: straight-line
-// code for all 64 columns would be fetched once and run once, and its
-// instruction fetches dominated); after each group the registers shift down
-// by one, so c[0] always holds the group's own rows and every register index
-// is fixed.  Elements below the diagonal (i > j) are updated too; they are
-// never published or read.  Returns 1 on this thread if a pivot was not
-// positive.
-__device__ int factor_tile_regs(double (&c)[kCB / 4], double (*rr)[kCP], double (*prow)[4][kCB / 4 + 2], int kb) {
+// elsewhere), in panels of 16 rows.  The unscaled elimination
+// a_ij -= a_ki (a_kj / a_kk) runs inside a panel on wavefront 0 alone, with
+// lane j holding column j of the panel's rows in registers: the pivot of
+// step k comes from the lane that holds it (readlane), the multipliers from
+// an LDS copy of row k (one write, broadcast reads), so the chain from one
+// column to the next has no block barrier.  The rows of a finished panel,
+// scaled by 1 / sqrt(pivot), then update the trailing triangle on the
+// matrix cores (rank 16, all four wavefronts).  R's rows are scaled by
+// 1 / sqrt(pivot) at the end.  Each column still costs about 650 cycles: the
+// LDS round trip, the reciprocal of the pivot and the update that yields the
+// next pivot are a chain.
+// Elements below the diagonal are updated too and cleared at the end.  `t`
+// holds the scaled panel rows (at least kPW * kSP values).  Returns 1 if a
+// pivot was not positive (it then counts as 1 and the factorisation goes on).
+__device__ int factor_tile_panels(double (&c)[kCB / 4], double (*rr)[kCP], double* t, int kb) {
   __shared__ double piv_of[kCB];
+  __shared__ int32_t any_bad;
+  __shared__ __align__(16) double rowk[kCB];
   const int tid = threadIdx.x;
-  // the wave index in a scalar register: the row tests below are branches
   const int j = tid & (kCB - 1), g = __builtin_amdgcn_readfirstlane(tid >> 6);
-  for (int e = tid; e < kCB * kCP; e += 256) (&rr[0][0])[e] = 0.0;
-  int badk = 0;
-  if (g == 0) prow[0][j & 3][j >> 2] = c[0];  // row 0
-  for (int qk = 0; 4 * qk < kb; ++qk) {
 #pragma unroll
-    for (int gk = 0; gk < 4; ++gk) {
-      const int k = 4 * qk + gk;
-      if (k < kb) {
-        const double (*pr)[kCB / 4 + 2] = prow[gk & 1];  // k & 1
-        __syncthreads();  // row k is published
-        double piv = pr[gk][qk];
-        if (!(piv > 0.0)) {
-          badk = 1;
-          piv = 1.0;
+  for (int q = 0; q < kCB / 4; ++q) rr[4 * q + g][j] = c[q];
+  if (tid == 0) any_bad = 0;
+  __syncthreads();
+  for (int p0 = 0; p0 < kb; p0 += kPW) {
+    const int np = (kb - p0) < kPW ? kb - p0 : kPW;
+    if (g == 0) {
+      double a[kPW];
+#pragma unroll
+      for (int i = 0; i < kPW; ++i) a[i] = rr[p0 + i][j];
+      int bad = 0;
+      double pv[kPW];
+#pragma unroll
+      for (int k = 0; k < kPW; ++k) {
+        pv[k] = 1.0;
+        if (k < np) {
+          double piv = lane_bcast(a[k], p0 + k);
+          if (!(piv > 0.0)) {
+            bad = 1;
+            piv = 1.0;
+          }
+          pv[k] = piv;
+          const double rp = recip(piv);
+          if (j == 0) piv_of[p0 + k] = piv;
+          // row k once to LDS; the panel's multipliers come back as
+          // broadcast reads (fewer instructions than one readlane pair each)
+          rowk[j] = a[k];
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          double f[kPW];
+#pragma unroll
+          for (int i = 0; i < kPW; i += 2) {
+            const double2 pr = *reinterpret_cast<const double2*>(&rowk[p0 + i]);
+            f[i] = pr.x;
+            f[i + 1] = pr.y;
+          }
+#pragma unroll
+          for (int i = k + 1; i < kPW; ++i)
+            if (i < np) a[i] -= (f[i] * rp) * a[k];
+          __builtin_amdgcn_wave_barrier();  // the reads of rowk are done before the next write
         }
-        const double ip = recip(piv);
-        const double akj = j >= k ? pr[j & 3][j >> 2] : 0.0;
-        const double f = akj * ip;
-        // row k at this thread's rows 4 (qk + q) + g (indices past the last
-        // row clamped: those registers are not used)
-        double rowk[kCB / 4];
-#pragma unroll
-        for (int q = 0; q < kCB / 4; ++q) rowk[q] = pr[g][(qk + q) < kCB / 4 ? qk + q : kCB / 4 - 1];
-        // row k + 1 first: owned by wave (k + 1) & 3, register (gk + 1) >> 2
-        const int q1 = (gk + 1) >> 2;
-        const int g1 = (gk + 1) & 3, k1 = k + 1;
-        if (k1 < kb && g == g1) {
-          c[q1] -= rowk[q1] * f;
-          if (j >= k1) prow[(gk + 1) & 1][j & 3][j >> 2] = c[q1];
-        }
-        if (g == 0 && j >= k && j < kb) rr[k][j] = akj;  // scaled below
-        if (g == 0 && j == k) piv_of[k] = piv;
-        if (g > gk && !(q1 == 0 && g == g1)) c[0] -= rowk[0] * f;
-#pragma unroll
-        for (int q = 1; q < kCB / 4; ++q)
-          if (!(q == q1 && g == g1)) c[q] -= rowk[q] * f;
       }
-    }
+      // the panel's rows back, unscaled, and scaled by 1 / sqrt(pivot) for
+      // the trailing update
 #pragma unroll
-    for (int q = 0; q + 1 < kCB / 4; ++q) c[q] = c[q + 1];
-    c[kCB / 4 - 1] = 0.0;
-  }
-  __syncthreads();
-  // R_kj = a_kj / sqrt(pivot_k) with a_kj the values at step k
-  for (int e = tid; e < kb * kCB; e += 256) {
-    const int k = e / kCB, jj = e % kCB;
-    if (jj >= k && jj < kb) {
-      const double rk = sqrt(piv_of[k]);
-      rr[k][jj] = jj == k ? rk : rr[k][jj] / rk;
+      for (int i = 0; i < kPW; ++i)
+        if (i < np) {
+          rr[p0 + i][j] = a[i];
+          t[i * kSP + j] = a[i] * recip(sqrt(pv[i]));
+        }
+      if (bad && j == 0) any_bad = 1;
     }
+    __syncthreads();
+    // trailing triangle [p0 + np, kb): a_rc -= sum_i t[i][r] t[i][c], 16 x 16
+    // tiles (ti <= tj) on v_mfma_f64_16x16x4f64, one tile per wavefront at a time
+    const int pe = p0 + np;
+    const int nt = (kb - pe + 15) / 16;
+    const int ntiles = nt * (nt + 1) / 2;
+    const int lr = j >> 4, lc = j & 15;
+    for (int tt = g; tt < ntiles; tt += 4) {
+      int ti = 0, rem = tt;
+      while (rem >= nt - ti) {
+        rem -= nt - ti;
+        ++ti;
+      }
+      const int r0 = pe + 16 * ti, c0 = pe + 16 * (ti + rem);
+      d4_t acc = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < kPW; kk += 4) {
+        const double av = t[(kk + lr) * kSP + r0 + lc];  // A[m][k] = t[k][r0 + m]
+        const double bv = t[(kk + lr) * kSP + c0 + lc];  // B[k][n] = t[k][c0 + n]
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rr[r0 + lr + 4 * e][c0 + lc] -= acc[e];
+    }
+    __syncthreads();
+  }
+  // R_kj = a_kj / sqrt(pivot_k) with a_kj the values at step k; zero below
+  // the diagonal and past kb
+  for (int e = tid; e < kCB * kCB; e += 256) {
+    const int k = e / kCB, jj = e % kCB;
+    double v = 0.0;
+    if (k < kb && jj < kb && jj >= k) {
+      const double rk = sqrt(piv_of[k]);
+      v = jj == k ? rk : rr[k][jj] / rk;
+    }
+    rr[k][jj] = v;
   }
   __syncthreads();
-  return badk;
+  return any_bad;
 }
 
 // Where the factorisation writes R^{-1} (and its transpose), or nulls.
@@ -536,16 +584,15 @@ struct InvOut {
   double* XT;  // d x d, R^{-T}
 };
 
-// Factor + invert a diagonal tile held in c[] (see factor_tile_regs): writes
+// Factor + invert a diagonal tile held in c[] (see factor_tile_panels): writes
 // R_KK into R (rows / columns K .. K + kb), its inverse into Kinv (ld kCB)
 // and, when asked, into the diagonal block of R^{-1} and R^{-T}.
 __device__ void finish_tile(double (&c)[kCB / 4], double* __restrict__ R, int d, int K, double* __restrict__ Kinv,
-                            int32_t* __restrict__ bad, double (*rr)[kCP], double (*x)[kCP], double* t,
-                            double (*prow)[4][kCB / 4 + 2], InvOut inv) {
+                            int32_t* __restrict__ bad, double (*rr)[kCP], double (*x)[kCP], double* t, InvOut inv) {
   const int kb = (d - K) < kCB ? (d - K) : kCB;
   const int tid = threadIdx.x;
   const int j = tid & (kCB - 1), g = tid >> 6;
-  const int badk = factor_tile_regs(c, rr, prow, kb);
+  const int badk = factor_tile_panels(c, rr, t, kb);
   if (badk) atomicOr(bad, 1);
   for (int i = g; i < kb; i += 4)
     if (j >= i && j < kb) R[static_cast<size_t>(K + i) * d + K + j] = rr[i][j];
@@ -603,8 +650,7 @@ __global__ __launch_bounds__(256) void k_chol_first(const double* __restrict__ W
                                                     InvOut inv) {
   __shared__ double rr[kCB][kCP];
   __shared__ double x[kCB][kCP];
-  __shared__ double t[kCB * kCB / 4];
-  __shared__ __align__(16) double prow[2][4][kCB / 4 + 2];
+  __shared__ double t[kPW * kSP > kCB * kCB / 4 ? kPW * kSP : kCB * kCB / 4];
   const int kb = d < kCB ? d : kCB;
   const int tid = threadIdx.x;
   const int j = tid & (kCB - 1), g = tid >> 6;
@@ -614,7 +660,7 @@ __global__ __launch_bounds__(256) void k_chol_first(const double* __restrict__ W
     const int i = 4 * q + g;
     c[q] = (j < kb && i <= j) ? W[static_cast<size_t>(i) * d + j] : 0.0;
   }
-  finish_tile(c, R, d, 0, Kinv, bad, rr, x, t, prow, inv);
+  finish_tile(c, R, d, 0, Kinv, bad, rr, x, t, inv);
 }
 
 // One step of the blocked Cholesky after block column K is factored (R_KK
@@ -632,8 +678,7 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ W, doubl
   __shared__ double ki[kCB][kCP];
   __shared__ double pI[kCB][kCP];
   __shared__ double pJ[kCB][kCP];
-  __shared__ double t[kCB * kCB / 4];
-  __shared__ __align__(16) double prow[2][4][kCB / 4 + 2];
+  __shared__ double t[kPW * kSP > kCB * kCB / 4 ? kPW * kSP : kCB * kCB / 4];
   const int nb = (d + kCB - 1) / kCB;
   const int T = nb - K - 1;
   const int ntrail = T * (T + 1) / 2;
@@ -705,7 +750,7 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ W, doubl
     c[q] = (j < kb1 && i <= j) ? pJ[i][j] : 0.0;
   }
   __syncthreads();
-  finish_tile(c, R, d, I0, Kinv + static_cast<size_t>(K + 1) * kCB * kCB, bad, pI, ki, t, prow, inv);
+  finish_tile(c, R, d, I0, Kinv + static_cast<size_t>(K + 1) * kCB * kCB, bad, pI, ki, t, inv);
 }
 
 // The last block column of R^{-1} (the steps form the others): block J < K.
