@@ -240,6 +240,103 @@ __global__ __launch_bounds__(kGThreads) void k_gram_partial(const TI* __restrict
   }
 }
 
+// Gram of a matrix of at most 64 columns (no v).  k_gram_partial gives each
+// wave a 64 x 64 quadrant of a 128 x 128 tile, so at d <= 64 one wave would
+// take every row alone while three multiply zeros.  Here the four waves split
+// each staged chunk of kSK rows by rows (16 each) and form only the 16 x 16
+// blocks on and above the diagonal of the one 64 x 64 tile (the reduction
+// reads the upper triangle of diagonal tiles); their sums meet in LDS at the
+// end.  Block b writes split b of the partial layout of k_gram_partial
+// (pair 0), entries inside d x d, so k_gram_reduce finishes the Gram.
+constexpr int kSK = 64;  // rows per staged chunk
+constexpr int kSB = 10;  // 16 x 16 blocks (x <= y) of a 64 x 64 upper triangle
+constexpr int kSL = kSK * 64 / 4 / kGThreads;  // 4-wide loads per thread per chunk
+
+template <typename TI, bool VEC>
+__global__ __launch_bounds__(kGThreads) void k_gram_small(const TI* __restrict__ M, int64_t ld, int64_t m, int d,
+                                                          int64_t rows_per_split, double* __restrict__ partial) {
+  using TS = GStage<TI>;
+  constexpr size_t kStage = 2 * kSK * 64 * sizeof(TS);
+  constexpr size_t kRed = 3 * kSB * 4 * kWave * sizeof(double);
+  __shared__ __align__(16) unsigned char lds[kStage > kRed ? kStage : kRed];
+  TS(*As)[kSK][64] = reinterpret_cast<TS(*)[kSK][64]>(lds);
+  const int64_t k0 = static_cast<int64_t>(blockIdx.x) * rows_per_split;
+  const int64_t k1 = (k0 + rows_per_split < m) ? k0 + rows_per_split : m;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int lr = lane >> 4, lc = lane & 15;
+  d4_t acc[kSB];
+#pragma unroll
+  for (int n = 0; n < kSB; ++n) acc[n] = d4_t{0.0, 0.0, 0.0, 0.0};
+  TS ra[kSL][4];
+  bool ia[kSL];
+  auto fetch = [&](int64_t kb) {
+#pragma unroll
+    for (int u = 0; u < kSL; ++u) {
+      const int e = (u * kGThreads + static_cast<int>(threadIdx.x)) * 4;
+      gload4<TI, VEC>(M, ld, kb + e / 64, k1, e % 64, d, ra[u], ia[u]);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < kSL; ++u) {
+      const int e = (u * kGThreads + static_cast<int>(threadIdx.x)) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[buf][e / 64][e % 64 + q] = ia[u] ? ra[u][q] : TS(0);
+    }
+  };
+  int buf = 0;
+  if (k0 < k1) {
+    fetch(k0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t kb = k0; kb < k1; kb += kSK) {
+    const bool more = kb + kSK < k1;
+    if (more) fetch(kb + kSK);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      // the two operands of a diagonal tile are the same staged rows
+      double a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = static_cast<double>(As[buf][wv * 16 + kk + lr][q * 16 + lc]);
+      int n = 0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = x; y < 4; ++y, ++n) acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], a[y], acc[n], 0, 0, 0);
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // the staging buffers are free (the loop ended on a barrier): waves 1..3
+  // leave their sums in LDS, wave 0 adds them and stores the split
+  double* red = reinterpret_cast<double*>(lds);
+  if (wv > 0) {
+#pragma unroll
+    for (int n = 0; n < kSB; ++n)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[((wv - 1) * kSB * 4 + n * 4 + e) * kWave + lane] = acc[n][e];
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  double* out = partial + static_cast<size_t>(blockIdx.x) * (kGT * kGT);
+  int n = 0;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = x; y < 4; ++y, ++n)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double v = acc[n][e];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) v += red[(w * kSB * 4 + n * 4 + e) * kWave + lane];
+        // element e of lane l: row l / 16 + 4 e, column l % 16 of the block
+        const int row = x * 16 + lr + 4 * e, col = y * 16 + lc;
+        if (row < d && col < d) out[row * kGT + col] = v;
+      }
+}
+
 // G[i][j] (both triangles) from the partial tiles (diagonal tiles summed over
 // Sd splits, the others over So); column d from the partial M^T v when v was
 // given.
@@ -997,8 +1094,25 @@ GramShape gram_shape(int64_t m, int64_t d) {
   return g;
 }
 
-size_t gram_bytes(const GramShape& g) {
-  const int S = g.Sd > g.So ? g.Sd : g.So;
+// Splits of the small-Gram kernel: whole chunks of kSK rows, at most 256.
+int small_splits(int64_t m, int64_t& rps) {
+  const int64_t mm = m > 0 ? m : 1;
+  int64_t x = div_up(mm, kSK);
+  if (x > 256) x = 256;
+  rps = div_up(div_up(mm, x), kSK) * kSK;
+  return static_cast<int>(div_up(mm, rps));
+}
+
+size_t gram_bytes(const GramShape& g, int64_t m, int64_t d) {
+  int S = g.Sd > g.So ? g.Sd : g.So;
+  if (d <= 64) {
+    // room for the small-Gram kernel's splits as well; their count is at
+    // most min(256, ceil(m / kSK)), which grows with m, so a workspace sized
+    // for m rows also serves every shorter matrix
+    const int64_t x = div_up(m > 0 ? m : 1, kSK);
+    const int Ss = static_cast<int>(x < 256 ? x : 256);
+    S = Ss > S ? Ss : S;
+  }
   return (static_cast<size_t>(S) * g.P * kGT * kGT + static_cast<size_t>(g.Sd) * (g.T * kGT + 1)) * sizeof(double) +
          512;
 }
@@ -1010,7 +1124,7 @@ size_t gram_ws_bytes(int64_t m, int64_t dd) {
   size_t need = 0;
   for (int64_t d : {dd, dd - 1}) {
     if (d < 1) continue;
-    const size_t b = gram_bytes(gram_shape(m, d));
+    const size_t b = gram_bytes(gram_shape(m, d), m, d);
     need = b > need ? b : need;
   }
   return need;
@@ -1049,11 +1163,41 @@ SideStream* side_stream() {
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,
                  double* G, void* ws, size_t ws_bytes, hipStream_t s) {
   const GramShape g = gram_shape(m, d);
-  if (ws_bytes < gram_bytes(g) || ws == nullptr) {
+  if (ws_bytes < gram_bytes(g, m, d) || ws == nullptr) {
     set_error("gram workspace too small");
     return SKLS_ERR_WORKSPACE;
   }
   Arena ar(ws, ws_bytes);
+  if (v == nullptr && d <= 64) {
+    int64_t rps;
+    const int S = small_splits(m, rps);
+    double* partial = static_cast<double*>(ws);
+    const int di = static_cast<int>(d);
+    PhaseTimer pt("gram", s);
+    auto launch = [&](auto tag) -> int32_t {
+      using TI = decltype(tag);
+      const TI* Mt = static_cast<const TI*>(M);
+      const bool vec = (reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * sizeof(TI)) % 16 == 0) && (d % 4 == 0);
+      if (vec)
+        hipLaunchKernelGGL((k_gram_small<TI, true>), dim3(S), dim3(kGThreads), 0, s, Mt, ld, m, di, rps, partial);
+      else
+        hipLaunchKernelGGL((k_gram_small<TI, false>), dim3(S), dim3(kGThreads), 0, s, Mt, ld, m, di, rps, partial);
+      SKLS_CHECK_LAUNCH();
+      return SKLS_OK;
+    };
+    int32_t st;
+    switch (dtype) {
+      case SKLS_F64: st = launch(double{}); break;
+      case SKLS_F32: st = launch(float{}); break;
+      case SKLS_BF16: st = launch(bf16_t{}); break;
+      default: set_error("gram: bad dtype"); return SKLS_ERR_DTYPE;
+    }
+    if (st != SKLS_OK) return st;
+    hipLaunchKernelGGL(k_gram_reduce, dim3(2, kGT * kGT / 256), dim3(256), 0, s, partial, partial, 1, S, 0, 1, di, 0,
+                       G);
+    SKLS_CHECK_LAUNCH();
+    return SKLS_OK;
+  }
   const int S = g.Sd > g.So ? g.Sd : g.So;
   double* partial = ar.take<double>(static_cast<size_t>(S) * g.P * kGT * kGT);
   double* partial_v = ar.take<double>(static_cast<size_t>(g.Sd) * (g.T * kGT + 1));  // M^T v parts, then v^T v parts

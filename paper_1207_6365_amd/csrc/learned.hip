@@ -24,17 +24,64 @@ __global__ __launch_bounds__(1024) void k_learned_E(const double* __restrict__ P
   if (threadIdx.x == 0) *loss = static_cast<float>(s);
 }
 
-// G = 4 Y E (t x d times d x d), one thread per output element.
+// G = 4 Y E (t x d times d x d).  A block forms a kGR x kGC tile of G; the
+// inner index runs in chunks of kGKc staged in LDS (the Y rows and the E
+// block), so every thread keeps four independent sums and the loads of a
+// chunk are in flight together.  Entries outside t x d are staged as zeros
+// from clamped, always valid addresses.
+constexpr int kGR = 16, kGC = 64, kGKc = 64;
+
 __global__ __launch_bounds__(256) void k_learned_G(const float* __restrict__ Y, const float* __restrict__ E,
                                                    int64_t t, int d, float* __restrict__ G) {
-  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (idx >= t * d) return;
-  const int64_t b = idx / d;
-  const int c = static_cast<int>(idx % d);
-  const float* y = Y + b * d;
-  float s = 0.0f;
-  for (int k = 0; k < d; ++k) s += y[k] * E[static_cast<size_t>(k) * d + c];
-  G[idx] = 4.0f * s;
+  __shared__ __align__(16) float Es[kGKc][kGC];
+  __shared__ float Ys[kGR][kGKc + 1];
+  const int tid = threadIdx.x;
+  const int r = tid / 16, c4 = (tid % 16) * 4;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGR;
+  const int cb = blockIdx.y * kGC;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < d; k0 += kGKc) {
+    float e[kGKc * kGC / 256], y[kGR * kGKc / 256];
+#pragma unroll
+    for (int u = 0; u < kGKc * kGC / 256; ++u) {
+      const int q = u * 256 + tid, kk = q / kGC, cc = q % kGC;
+      const bool in = k0 + kk < d && cb + cc < d;
+      const float x = E[in ? static_cast<size_t>(k0 + kk) * d + cb + cc : 0];
+      e[u] = in ? x : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kGR * kGKc / 256; ++u) {
+      const int q = u * 256 + tid, rr = q / kGKc, kk = q % kGKc;
+      const bool in = r0 + rr < t && k0 + kk < d;
+      const float x = Y[in ? static_cast<size_t>(r0 + rr) * d + k0 + kk : 0];
+      y[u] = in ? x : 0.0f;
+    }
+    __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+    for (int u = 0; u < kGKc * kGC / 256; ++u) {
+      const int q = u * 256 + tid;
+      Es[q / kGC][q % kGC] = e[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kGR * kGKc / 256; ++u) {
+      const int q = u * 256 + tid;
+      Ys[q / kGKc][q % kGKc] = y[u];
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < kGKc; ++kk) {
+      const float yv = Ys[r][kk];
+      const float4 ev = *reinterpret_cast<const float4*>(&Es[kk][c4]);
+      acc[0] += yv * ev.x;
+      acc[1] += yv * ev.y;
+      acc[2] += yv * ev.z;
+      acc[3] += yv * ev.w;
+    }
+  }
+  if (r0 + r >= t) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (cb + c4 + k < d) G[static_cast<size_t>(r0 + r) * d + cb + c4 + k] = 4.0f * acc[k];
 }
 
 // grad[i] = < G[h(i), :], A[i, :] > with 16 lanes per row.
@@ -80,8 +127,8 @@ int32_t run_learned_E(const double* P, int64_t ldp, const float* C, int64_t d, f
 }
 
 int32_t run_learned_G(const float* Y, const float* E, int64_t t, int64_t d, float* G, hipStream_t s) {
-  hipLaunchKernelGGL(k_learned_G, dim3(static_cast<unsigned>(div_up(t * d, 256))), dim3(256), 0, s, Y, E, t,
-                     static_cast<int>(d), G);
+  hipLaunchKernelGGL(k_learned_G, dim3(static_cast<unsigned>(div_up(t, kGR)), static_cast<unsigned>(div_up(d, kGC))),
+                     dim3(256), 0, s, Y, E, t, static_cast<int>(d), G);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }

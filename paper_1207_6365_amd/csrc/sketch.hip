@@ -1024,26 +1024,33 @@ struct DenseLds {
   int32_t drow[kCsrSortCap];
 };
 
-// Sum of the bucket's rows for this lane's column slices.  Batches of RB rows
-// are loaded unconditionally (rows past the end repeat row 0 and are skipped
-// when summing), so all loads of a batch are in flight together; rows are
-// added in bucket order.
+// Sum of the bucket's rows for this lane's column slices.  A row takes
+// ceil(d / V) lanes; when that is at most 16 (32) the wave splits into 4 (2)
+// groups of lanes, group g taking rows g, g + 4 (g + 2), ... of the bucket,
+// and the groups' sums meet by lane exchanges at the end, so that narrow rows
+// do not leave most of the wave idle.  Batches of RB rows per group are loaded
+// unconditionally (rows past the end repeat row 0 and are skipped when
+// summing), so all loads of a batch are in flight together.
 template <typename TV, typename TO, int V, bool SORTED>
 __device__ __forceinline__ void dense_rows(const DenseLds<TO>& L, const int32_t* __restrict__ perm, int beg, int m,
                                            HashKey seed, const float* __restrict__ w, const TV* __restrict__ A,
                                            int64_t ld, int d, TO* __restrict__ out, int lane) {
   constexpr int RB = 8;
-  for (int c0 = lane * V; c0 < d; c0 += kWave * V) {
+  const int chunks = (d + V - 1) / V;
+  const int LG = chunks <= 16 ? 16 : (chunks <= 32 ? 32 : kWave);  // lanes per group
+  const int NG = kWave / LG, g = lane / LG, sub = lane % LG;
+  for (int c0 = sub * V; c0 < d; c0 += LG * V) {
     TO acc[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) acc[k] = TO(0);
-    for (int j = 0; j < m; j += RB) {
+    for (int j = g; j < m; j += RB * NG) {
       TO sc[RB], x[RB][V];
       bool ok[RB];
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
-        ok[q] = j + q < m;
-        const int jc = ok[q] ? j + q : 0;
+        const int jq = j + q * NG;
+        ok[q] = jq < m;
+        const int jc = ok[q] ? jq : 0;
         const int32_t r = SORTED ? L.drow[jc] : perm[beg + jc];
         sc[q] = SORTED ? L.dscale[jc] : row_scale<TO>(seed, r, w);
         RowLoad<TV, TO, V>::load(A + static_cast<size_t>(r) * ld + c0, x[q]);
@@ -1054,8 +1061,14 @@ __device__ __forceinline__ void dense_rows(const DenseLds<TO>& L, const int32_t*
 #pragma unroll
           for (int k = 0; k < V; ++k) acc[k] += sc[q] * x[q][k];
     }
+    // lanes of one column slice in the other groups hold the same trip
+    // counts, so the exchanges run with every partner active
+    for (int off = LG; off < kWave; off <<= 1)
 #pragma unroll
-    for (int k = 0; k < V; ++k) out[c0 + k] = acc[k];
+      for (int k = 0; k < V; ++k) acc[k] += __shfl_xor(acc[k], off, kWave);
+    if (g == 0)
+#pragma unroll
+      for (int k = 0; k < V; ++k) out[c0 + k] = acc[k];
   }
 }
 

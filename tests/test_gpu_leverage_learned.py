@@ -84,7 +84,26 @@ def test_gram_matches_numpy(sk):
         assert np.max(np.abs(C - ref)) <= 1e-6 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("n,d,t", [(4096, 16, 128), (32768, 64, 1024)])
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,d,ld", [(1, 1, 1), (63, 3, 3), (64, 64, 64), (65, 61, 61), (1000, 64, 72),
+                                    (16385, 32, 32), (70001, 64, 64), (5000, 65, 65)])
+def test_gram_narrow_integer_exact(sk, storage, n, d, ld):
+    # small integers: every partial sum is an integer below 2^24, so the
+    # float32 Gram equals the exact one bit for bit whatever the split of the
+    # rows and the order of the sums (d <= 64 takes the small-Gram kernel,
+    # d = 65 the tiled one)
+    g = np.random.default_rng(n + d)
+    X = g.integers(-7, 8, size=(n, ld))
+    if storage == "bf16":
+        Ag = up_bf16(W.bf16_round(X.astype(np.float32)))[:, :d]
+    else:
+        Ag = up(X.astype(np.float64 if storage == "f64" else np.float32))[:, :d]
+    A = X[:, :d].astype(np.int64)
+    C = sk.gram(Ag).cpu().numpy()
+    assert np.array_equal(C.astype(np.int64), A.T @ A)
+
+
+@pytest.mark.parametrize("n,d,t", [(4096, 16, 128), (32768, 64, 1024), (5000, 70, 333)])
 def test_learned_loss_and_gradient(sk, n, d, t):
     make, _ = W.learned_family(num=4, n=n, d=d)
     A = make(1)

@@ -88,7 +88,8 @@ def test_csr_f32_tolerance_and_ragged_rows(sk, variant):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("storage,d,ld", [("f32", 40, 40), ("f32", 37, 37), ("f32", 64, 70), ("bf16", 64, 64),
-                                          ("bf16", 30, 30), ("f64", 24, 24)])
+                                          ("bf16", 30, 30), ("f64", 24, 24), ("f32", 4, 4), ("f32", 100, 100),
+                                          ("f32", 128, 128)])
 def test_dense_storage_types(sk, variant, storage, d, ld):
     n, t, seed = 20000, 900, 31337
     g = np.random.default_rng(d)
