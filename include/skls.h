@@ -421,6 +421,34 @@ SKLS_API int32_t skls_learned_grad_planned(const skls_matrix* A, const float* C,
                                            size_t ws_bytes, void* stream);
 
 /*
+ * The weighted sum of the gradients of a batch of count matrices of one
+ * shape (n, d), the forward sketches run from one reusable plan as in
+ * skls_learned_grad_planned:
+ *   loss[j] = ||E_j||_F^2 of matrix j (raw, unweighted),
+ *   grad_w  = sum_j scale[j] * dloss_j/dw   (accumulate = 0), or += it.
+ * The matrices' chains of launches run on up to four streams at once (the
+ * caller's and three of the library's, default priority), forked from and
+ * joined back to `stream`; matrix j adds its weighted gradient into the slot
+ * of lane j mod 4, and the slots are summed in lane order at the end.  The
+ * result is the same from run to run; it may differ in the last bits from a
+ * sequence of skls_learned_grad_planned calls, which add in matrix order.
+ *  count:  number of matrices, >= 1.
+ *  A:      host array of count dense float32 matrix descriptors of the
+ *          plan's shape (each with its own ld).
+ *  C:      host array of count device pointers to float32 d x d targets.
+ *  scale:  host array of count weights, or NULL for weights 1.
+ *  loss:   device float32 [count].
+ *  grad_w: device float32 [n], or NULL to evaluate the losses only.
+ *  ws:     skls_learned_batch_workspace bytes (A: any matrix of the shape).
+ * Overlapping calls must use distinct workspaces.  Asynchronous.
+ */
+SKLS_API int32_t skls_learned_batch_workspace(const skls_matrix* A, int64_t t, size_t* bytes);
+SKLS_API int32_t skls_learned_grad_batch(int32_t count, const skls_matrix* A, const float* const* C,
+                                         const float* scale, const skls_sketch_plan_desc* desc, const void* plan,
+                                         size_t plan_bytes, const float* w, int32_t accumulate, float* loss,
+                                         float* grad_w, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * One Adam step (Kingma & Ba 2015) on w [n] (device float32) with gradient g,
  * moments m, v (device float32, caller-initialised to 0), step >= 1.
  * Asynchronous.

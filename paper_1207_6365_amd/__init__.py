@@ -12,11 +12,13 @@ does (and raises if ``libskls.so`` has not been built).
 from ._lib import SklsError  # noqa: F401
 from .api import (  # noqa: F401
     Csr,
+    LearnedBatchWorkspace,
     LearnedWorkspace,
     adam_step,
     gram,
     hash_rows,
     learned_grad,
+    learned_grad_batch,
     leverage_scores,
     lib,
     low_rank,

@@ -224,6 +224,10 @@ SIGNATURES = {
     "skls_learned_grad_planned": (c_int32, [POINTER(SklsMatrix), c_void_p, POINTER(SklsSketchPlanDesc), c_void_p,
                                             c_size_t, c_void_p, c_float, c_int32, c_void_p, c_void_p, c_void_p,
                                             c_size_t, c_void_p]),
+    "skls_learned_batch_workspace": (c_int32, [POINTER(SklsMatrix), c_int64, POINTER(c_size_t)]),
+    "skls_learned_grad_batch": (c_int32, [c_int32, POINTER(SklsMatrix), POINTER(c_void_p), POINTER(c_float),
+                                          POINTER(SklsSketchPlanDesc), c_void_p, c_size_t, c_void_p, c_int32,
+                                          c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "skls_adam_step": (c_int32, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_float, c_float,
                                  c_float, c_float, c_void_p]),
     "skls_profile_enable": (c_int32, [c_int32]),

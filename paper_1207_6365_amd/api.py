@@ -405,6 +405,47 @@ def learned_grad(A: torch.Tensor, C: torch.Tensor, t: int, seed: int, w: torch.T
     return loss, (grad if want_grad else None)
 
 
+class LearnedBatchWorkspace:
+    """Reusable workspace for :func:`learned_grad_batch` at one ``(n, d, t)``."""
+
+    def __init__(self, A: torch.Tensor, t: int):
+        m, device = _matrix(A)
+        self.key = (m.n, m.d, t)
+        self.buf = _workspace(_size(lib().skls_learned_batch_workspace, ctypes.byref(m), t), device)
+
+
+def learned_grad_batch(mats, grams, plan: SketchPlan, w: torch.Tensor, grad: torch.Tensor | None,
+                       scale=None, ws: LearnedBatchWorkspace | None = None, loss: torch.Tensor | None = None,
+                       accumulate: bool = False):
+    """Losses of the matrices ``mats`` (one shape, float32) against their Gram
+    targets ``grams`` and the sum of their gradients in ``w`` weighted by
+    ``scale`` (one float per matrix; default 1), written to ``grad`` (added
+    when ``accumulate``; ``None``: the losses only).  The forward sketches run from the reusable
+    ``plan``; the matrices' chains run on several streams at once.  Returns
+    ``(loss, grad)`` with ``loss`` a float32 device vector of the raw loss of
+    each matrix."""
+    if len(mats) != len(grams) or not mats:
+        raise ValueError("need one Gram target per matrix and at least one matrix")
+    count = len(mats)
+    if scale is not None and len(scale) != count:
+        raise ValueError("need one weight per matrix")
+    descs = [_matrix(A) for A in mats]
+    device = descs[0][1]
+    m0 = descs[0][0]
+    if ws is None or ws.key != (m0.n, m0.d, plan.desc.t):
+        ws = LearnedBatchWorkspace(mats[0], plan.desc.t)
+    loss = torch.empty(count, dtype=torch.float32, device=device) if loss is None else loss
+    if loss.numel() < count or loss.dtype != torch.float32:
+        raise ValueError("loss must be a float32 vector with one entry per matrix")
+    arr = (L.SklsMatrix * count)(*[m for m, _ in descs])
+    cps = (ctypes.c_void_p * count)(*[_ptr(C) for C in grams])
+    sc = None if scale is None else (ctypes.c_float * count)(*[float(x) for x in scale])
+    L.check(lib().skls_learned_grad_batch(count, arr, cps, sc, ctypes.byref(plan.desc), _ptr(plan.buf),
+                                          plan.buf.numel(), _ptr(w), 1 if accumulate else 0, _ptr(loss),
+                                          _ptr(grad), _ptr(ws.buf), ws.buf.numel(), _stream(device)))
+    return loss, grad
+
+
 def adam_step(w: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float = 1e-2,
               beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
     """In-place Adam update of ``w`` (float32 device vectors)."""

@@ -1087,6 +1087,148 @@ int32_t skls_learned_grad_planned(const skls_matrix* A, const float* C, const sk
   return learned_rest(*A, C, t, desc->seed, grad_scale, accumulate, loss, grad_w, r, Y, s);
 }
 
+namespace {
+
+// Concurrent chains of the batched learned gradient: the caller's stream and
+// kLanes - 1 more.
+constexpr int kLanes = 4;
+
+// Streams beside a caller's stream on the current device: non-blocking, of
+// default priority, each with an event that joins it back; plus one event
+// that forks work onto them.  Created once per host thread and device.
+struct LanePool {
+  hipStream_t s[kLanes - 1] = {};
+  hipEvent_t done[kLanes - 1] = {};
+  hipEvent_t fork = nullptr;
+  bool ready = false;
+};
+
+int32_t lane_pool(LanePool** out) {
+  thread_local LanePool pools[16];
+  int dev = 0;
+  SKLS_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 16) {
+    set_error("device index %d out of range", dev);
+    return SKLS_ERR_DEVICE;
+  }
+  LanePool& p = pools[dev];
+  if (!p.ready) {
+    LanePool q;
+    bool ok = hipEventCreateWithFlags(&q.fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < kLanes - 1; ++k)
+      ok = hipStreamCreateWithFlags(&q.s[k], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&q.done[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      for (int k = 0; k < kLanes - 1; ++k) {
+        if (q.s[k] != nullptr) (void)hipStreamDestroy(q.s[k]);
+        if (q.done[k] != nullptr) (void)hipEventDestroy(q.done[k]);
+      }
+      if (q.fork != nullptr) (void)hipEventDestroy(q.fork);
+      set_error("creating the streams of the batched gradient failed");
+      return SKLS_ERR_DEVICE;
+    }
+    q.ready = true;
+    p = q;
+  }
+  *out = &p;
+  return SKLS_OK;
+}
+
+struct BatchLanes {
+  float* Y[kLanes];
+  LearnedRest r[kLanes];
+  float* slots;  // kLanes gradient slots of n floats, one after another
+};
+
+BatchLanes carve_batch(Arena& ar, int64_t n, int64_t t, int64_t d) {
+  BatchLanes b;
+  for (int k = 0; k < kLanes; ++k) {
+    b.Y[k] = ar.take<float>(static_cast<size_t>(t * d));
+    b.r[k] = carve_learned_rest(ar, t, d);
+  }
+  b.slots = ar.take<float>(static_cast<size_t>(kLanes * n));
+  return b;
+}
+
+}  // namespace
+
+int32_t skls_learned_batch_workspace(const skls_matrix* A, int64_t t, size_t* bytes) {
+  clear_error();
+  SKLS_TRY(validate_matrix(A, false));
+  SKLS_TRY(check_t(t));
+  if (bytes == nullptr) {
+    set_error("bytes pointer is NULL");
+    return SKLS_ERR_ARG;
+  }
+  Arena ar(nullptr, 0);
+  carve_batch(ar, A->n, t, A->d);
+  *bytes = ar.used;
+  return SKLS_OK;
+}
+
+int32_t skls_learned_grad_batch(int32_t count, const skls_matrix* A, const float* const* C, const float* scale,
+                                const skls_sketch_plan_desc* desc, const void* plan, size_t plan_bytes,
+                                const float* w, int32_t accumulate, float* loss, float* grad_w, void* ws,
+                                size_t ws_bytes, void* stream) {
+  clear_error();
+  if (count < 1 || A == nullptr || C == nullptr || desc == nullptr) {
+    set_error("need count >= 1 and non-NULL A, C and desc");
+    return SKLS_ERR_ARG;
+  }
+  for (int32_t j = 0; j < count; ++j) {
+    SKLS_TRY(check_learned(&A[j], C[j], w, loss));
+    if (A[j].n != desc->n || A[j].d != desc->d || desc->layout != SKLS_DENSE || desc->out_dtype != SKLS_F32 ||
+        desc->row_start != 0) {
+      set_error("matrix %d: the plan must come from a dense float32-output sketch of a matrix of this shape, "
+                "row_start 0", j);
+      return SKLS_ERR_SHAPE;
+    }
+  }
+  if (desc->bytes > 0 && (plan == nullptr || plan_bytes < static_cast<size_t>(desc->bytes))) {
+    set_error("sketch plan buffer too small: need %lld bytes", static_cast<long long>(desc->bytes));
+    return SKLS_ERR_WORKSPACE;
+  }
+  const int64_t t = desc->t, d = A[0].d, n = A[0].n;
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  const BatchLanes b = carve_batch(ar, n, t, d);
+  SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  const int lanes = count < kLanes ? count : kLanes;
+  LanePool* pool = nullptr;
+  hipStream_t st[kLanes] = {s, s, s, s};
+  if (lanes > 1) {
+    SKLS_TRY(lane_pool(&pool));
+    SKLS_TRY_HIP(hipEventRecord(pool->fork, s));
+    for (int k = 1; k < lanes; ++k) {
+      SKLS_TRY_HIP(hipStreamWaitEvent(pool->s[k - 1], pool->fork, 0));
+      st[k] = pool->s[k - 1];
+    }
+  }
+  // matrix j runs on lane j mod lanes, adding its weighted gradient into
+  // that lane's slot; the lanes' slots are summed on the caller's stream at
+  // the end
+  int32_t status = SKLS_OK;
+  for (int32_t j = 0; j < count && status == SKLS_OK; ++j) {
+    const int k = j % lanes;
+    status = apply_sketch_plan(A[j], nullptr, SKLS_F64, t, plain_key(desc->seed), w, desc->variant, b.Y[k], nullptr,
+                               SKLS_F32, plan, plan_bytes, st[k]);
+    if (status == SKLS_OK)
+      status = learned_rest(A[j], C[j], t, desc->seed, scale != nullptr ? scale[j] : 1.0f, j >= lanes ? 1 : 0,
+                            loss + j, grad_w != nullptr ? b.slots + k * n : nullptr, b.r[k], b.Y[k], st[k]);
+  }
+  // join even after a failure, so that no lane runs past the caller's stream
+  for (int k = 1; k < lanes; ++k) {
+    const hipError_t e1 = hipEventRecord(pool->done[k - 1], st[k]);
+    const hipError_t e2 = hipStreamWaitEvent(s, pool->done[k - 1], 0);
+    if (status == SKLS_OK && (e1 != hipSuccess || e2 != hipSuccess)) {
+      set_error("joining the streams of the batched gradient failed");
+      status = SKLS_ERR_DEVICE;
+    }
+  }
+  if (status != SKLS_OK || grad_w == nullptr) return status;
+  return run_sum_slots(n, b.slots, n, lanes, 1.0f, accumulate != 0, grad_w, s);
+}
+
 int32_t skls_adam_step(int64_t n, float* w, const float* g, float* m, float* v, int32_t step, float lr, float beta1,
                        float beta2, float eps, void* stream) {
   clear_error();

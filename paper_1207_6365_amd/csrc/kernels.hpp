@@ -133,6 +133,8 @@ int32_t run_learned_E(const double* P, int64_t ldp, const float* C, int64_t d, f
 int32_t run_learned_G(const float* Y, const float* E, int64_t t, int64_t d, float* G, hipStream_t s);
 int32_t run_learned_gather(const skls_matrix& A, const float* G, uint32_t t, uint64_t seed, float scale,
                            bool accumulate, float* grad, hipStream_t s);
+int32_t run_sum_slots(int64_t n, const float* slots, int64_t stride, int k, float scale, bool accumulate,
+                      float* grad, hipStream_t s);
 int32_t run_adam(int64_t n, float* w, const float* g, float* m, float* v, int32_t step, float lr, float b1,
                  float b2, float eps, hipStream_t s);
 int32_t run_convert_f64_to_f32(const double* in, float* out, int64_t count, hipStream_t s);

@@ -84,7 +84,10 @@ __global__ __launch_bounds__(256) void k_learned_G(const float* __restrict__ Y, 
     if (cb + c4 + k < d) G[static_cast<size_t>(r0 + r) * d + cb + c4 + k] = 4.0f * acc[k];
 }
 
-// grad[i] = < G[h(i), :], A[i, :] > with 16 lanes per row.
+// grad[i] = < G[h(i), :], A[i, :] > with 16 lanes per row; VEC (16-byte
+// aligned rows, d a multiple of 4): each lane reads four consecutive entries
+// of both rows at once.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_learned_gather(int64_t n, int d, int64_t ld, const float* __restrict__ A,
                                                         const float* __restrict__ G, uint32_t t, uint64_t seed,
                                                         float scale, int accumulate, float* __restrict__ grad) {
@@ -97,10 +100,30 @@ __global__ __launch_bounds__(256) void k_learned_gather(int64_t n, int d, int64_
     const float* a = A + static_cast<size_t>(r) * ld;
     const float* g = G + static_cast<size_t>(h) * d;
     float s = 0.0f;
-    for (int c = sub; c < d; c += L) s += a[c] * g[c];
+    if (VEC) {
+      for (int c = sub * 4; c < d; c += L * 4) {
+        const nt_f4 x = stream_load<nt_f4>(a + c);
+        const float4 y = *reinterpret_cast<const float4*>(g + c);
+        s += x[0] * y.x + x[1] * y.y + x[2] * y.z + x[3] * y.w;
+      }
+    } else {
+      for (int c = sub; c < d; c += L) s += a[c] * g[c];
+    }
 #pragma unroll
     for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
     if (sub == 0) grad[r] = accumulate ? grad[r] + scale * s : scale * s;
+  }
+}
+
+// grad = (accumulate ? grad : 0) + scale * (slot 0 + ... + slot k-1), the
+// slots summed in index order.
+__global__ void k_sum_slots(int64_t n, const float* __restrict__ slots, int64_t stride, int k, float scale,
+                            int accumulate, float* __restrict__ grad) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float s = slots[i];
+    for (int j = 1; j < k; ++j) s += slots[j * stride + i];
+    grad[i] = accumulate ? grad[i] + scale * s : scale * s;
   }
 }
 
@@ -139,8 +162,22 @@ int32_t run_learned_gather(const skls_matrix& A, const float* G, uint32_t t, uin
   PhaseTimer pt("learned_gather", s);
   int64_t blocks = div_up(A.n * 16, 256);
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_learned_gather, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A.n,
-                     static_cast<int>(A.d), A.ld, static_cast<const float*>(A.val), G, t, seed, scale, accumulate ? 1 : 0, grad);
+  const bool vec = reinterpret_cast<uintptr_t>(A.val) % 16 == 0 && A.ld % 4 == 0 && A.d % 4 == 0 &&
+                   reinterpret_cast<uintptr_t>(G) % 16 == 0;
+  const auto kern = vec ? k_learned_gather<true> : k_learned_gather<false>;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A.n, static_cast<int>(A.d), A.ld,
+                     static_cast<const float*>(A.val), G, t, seed, scale, accumulate ? 1 : 0, grad);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
+int32_t run_sum_slots(int64_t n, const float* slots, int64_t stride, int k, float scale, bool accumulate,
+                      float* grad, hipStream_t s) {
+  if (n == 0) return SKLS_OK;
+  int64_t blocks = div_up(n, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_sum_slots, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, n, slots, stride, k, scale,
+                     accumulate ? 1 : 0, grad);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }

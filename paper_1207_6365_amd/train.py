@@ -48,26 +48,19 @@ def prepare(mats: list[torch.Tensor], t: int, seed: int, plan: api.SketchPlan | 
     ws = api.LearnedWorkspace(mats[0], t)
     plan = shared_plan(mats[0], t, seed) if plan is None else plan
     zero = torch.zeros(n, dtype=torch.float32, device=dev)
-    grams, norms = [], []
-    loss = torch.empty(1, dtype=torch.float32, device=dev)
-    for A in mats:
-        C = api.gram(A)
-        api.learned_grad(A, C, t, seed, zero, ws=ws, loss=loss, want_grad=False, plan=plan)
-        grams.append(C)
-        norms.append(float(loss.item()))
+    grams = [api.gram(A) for A in mats]
+    loss, _ = api.learned_grad_batch(mats, grams, plan, zero, None)
+    norms = [float(x) for x in loss.cpu().numpy()]
     return grams, norms, ws
 
 
 def distortions(mats, grams, norms, t: int, seed: int, w: torch.Tensor, ws=None,
                 plan: api.SketchPlan | None = None) -> np.ndarray:
     """Normalised distortion of each matrix for values ``w``."""
-    loss = torch.empty(1, dtype=torch.float32, device=w.device)
     plan = shared_plan(mats[0], t, seed) if plan is None else plan
-    out = []
-    for A, C, nrm in zip(mats, grams, norms):
-        api.learned_grad(A, C, t, seed, w, ws=ws, loss=loss, want_grad=False, plan=plan)
-        out.append(float(loss.item()) / nrm)
-    return np.array(out)
+    loss, _ = api.learned_grad_batch(mats, grams, plan, w, None, ws=ws if isinstance(ws, api.LearnedBatchWorkspace)
+                                     else None)
+    return loss.cpu().numpy().astype(np.float64) / np.asarray(norms, dtype=np.float64)
 
 
 def train(train_mats, val_mats, t: int, seed: int, steps: int = 300, lr: float = 1e-2, batch: int = 16,
@@ -82,20 +75,20 @@ def train(train_mats, val_mats, t: int, seed: int, steps: int = 300, lr: float =
     m = torch.zeros_like(w)
     v = torch.zeros_like(w)
     g = torch.empty_like(w)
-    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    bws = api.LearnedBatchWorkspace(train_mats[0], t)
     rng = np.random.default_rng(rng_seed)
     hist = []
     bsz = min(batch, len(train_mats))
+    bloss = torch.empty(bsz, dtype=torch.float32, device=dev)
     for step in range(1, steps + 1):
         idx = rng.choice(len(train_mats), size=bsz, replace=False)
-        for j, i in enumerate(idx):
-            api.learned_grad(train_mats[i], grams[i], t, seed, w, ws=ws, loss=loss, grad=g,
-                             grad_scale=1.0 / (bsz * norms[i]), accumulate=j > 0, plan=plan)
+        api.learned_grad_batch([train_mats[i] for i in idx], [grams[i] for i in idx], plan, w, g,
+                               scale=[1.0 / (bsz * norms[i]) for i in idx], ws=bws, loss=bloss)
         api.adam_step(w, g, m, v, step, lr)
         if log_every and (step % log_every == 0 or step == steps):
-            hist.append((step, float(distortions(val_mats, vgrams, vnorms, t, seed, w, ws, plan).mean())))
-    d_plain = float(distortions(val_mats, vgrams, vnorms, t, seed, w_plain, ws, plan).mean())
-    d_learned = float(distortions(val_mats, vgrams, vnorms, t, seed, w, ws, plan).mean())
+            hist.append((step, float(distortions(val_mats, vgrams, vnorms, t, seed, w, bws, plan).mean())))
+    d_plain = float(distortions(val_mats, vgrams, vnorms, t, seed, w_plain, bws, plan).mean())
+    d_learned = float(distortions(val_mats, vgrams, vnorms, t, seed, w, bws, plan).mean())
     use = d_learned < d_plain
     return TrainResult(w=w if use else w_plain, learned=w, used_learned=use, val_plain=d_plain,
                        val_learned=d_learned, history=hist)

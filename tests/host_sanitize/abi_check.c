@@ -128,6 +128,10 @@ int main(void) {
   expect(skls_gram(NULL, NULL, NULL, 0, NULL) != SKLS_OK, "gram NULL");
   expect(skls_learned_workspace(&A, 1024, &bytes) == SKLS_OK, "learned_workspace");
   expect(skls_learned_workspace(&A, 0, &bytes) != SKLS_OK, "learned_workspace t = 0");
+  expect(skls_learned_batch_workspace(&A, 1024, &bytes) == SKLS_OK && bytes > 0, "learned_batch_workspace");
+  expect(skls_learned_batch_workspace(&A, 0, &bytes) != SKLS_OK, "learned_batch_workspace t = 0");
+  expect(skls_learned_grad_batch(0, &A, NULL, NULL, NULL, NULL, 0, NULL, 0, NULL, NULL, NULL, 0, NULL) != SKLS_OK,
+         "learned_grad_batch count = 0");
 
   /* multiple responses, l_p, low rank */
   skls_multi_opts mo;

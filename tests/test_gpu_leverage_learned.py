@@ -122,6 +122,38 @@ def test_learned_loss_and_gradient(sk, n, d, t):
     assert torch.allclose(g2, 1.5 * grad, rtol=1e-5, atol=1e-6 * float(grad.abs().max()))
 
 
+@pytest.mark.parametrize("n,d,t,count", [(5000, 70, 333, 3), (32768, 64, 1024, 6), (4096, 16, 128, 1)])
+def test_learned_batch_matches_single_calls(sk, n, d, t, count):
+    # the batched gradient over several streams against one planned call per
+    # matrix: the losses bit for bit (the same kernels on the same inputs),
+    # the weighted gradient sum to float32 rounding of the different order
+    make, _ = W.learned_family(num=count, n=n, d=d)
+    seed = W.sketch_seed(1)
+    mats = [up(make(i)) for i in range(count)]
+    grams = [sk.gram(A) for A in mats]
+    w = up(np.random.default_rng(8).standard_normal(n).astype(np.float32))
+    plan = sk.sketch_plan(mats[0], t, seed, variant="sorted", out_dtype=torch.float32)
+    scale = [0.5 + 0.25 * i for i in range(count)]
+    ref_loss, ref = [], torch.zeros(n, dtype=torch.float32, device=dev())
+    for i, (A, C) in enumerate(zip(mats, grams)):
+        loss, g = sk.learned_grad(A, C, t, seed, w, plan=plan)
+        ref_loss.append(loss.item())
+        ref += scale[i] * g
+    loss, grad = sk.learned_grad_batch(mats, grams, plan, w, torch.empty(n, device=dev()), scale=scale)
+    assert np.array_equal(loss.cpu().numpy(), np.array(ref_loss, dtype=np.float32))
+    tol = 1e-5 * float(ref.abs().max())
+    assert torch.allclose(grad, ref, rtol=1e-5, atol=tol)
+    # the same call again gives the same bits; accumulate adds; NULL grad
+    # gives the losses alone
+    _, again = sk.learned_grad_batch(mats, grams, plan, w, torch.empty(n, device=dev()), scale=scale)
+    assert torch.equal(again, grad)
+    acc = grad.clone()
+    sk.learned_grad_batch(mats, grams, plan, w, acc, scale=scale, accumulate=True)
+    assert torch.allclose(acc, 2 * grad, rtol=1e-6, atol=1e-6 * float(grad.abs().max()))
+    only, none = sk.learned_grad_batch(mats, grams, plan, w, None)
+    assert none is None and torch.equal(only, loss)
+
+
 def test_learned_plain_signs_match_closed_form_expectation(sk):
     # mean distortion of random-sign sketches over seeds vs the closed form
     n, d, t = 2048, 8, 64
