@@ -1022,17 +1022,31 @@ LearnedRest carve_learned_rest(Arena& ar, int64_t t, int64_t d) {
   return r;
 }
 
-// Loss and gradient once the forward sketch Y = S_w A is formed.
+// Most small-Gram splits whose sum k_learned_PE takes in its one block.
+constexpr int kMaxPESplits = 64;
+
+// Loss and gradient once the forward sketch Y = S_w A is formed.  At d <= 64
+// (and t <= 64 * kMaxPESplits) the Gram's splits go straight into the loss
+// and E; with the bucket order of the sketch's plan (off, perm) the product
+// 4 Y E and the gather run as one launch as well.
 int32_t learned_rest(const skls_matrix& A, const float* C, int64_t t, uint64_t seed, float grad_scale,
                      int32_t accumulate, float* loss, float* grad_w, const LearnedRest& r, const float* Y,
-                     hipStream_t s) {
+                     hipStream_t s, const int32_t* off = nullptr, const int32_t* perm = nullptr) {
   const int64_t d = A.d;
   double* P = r.P;
   float* E = r.E;
   float* G = r.G;
-  SKLS_TRY(run_gram(Y, SKLS_F32, d, nullptr, SKLS_F64, t, d, P, r.gw, r.gb, s));
-  SKLS_TRY(run_learned_E(P, d, C, d, E, loss, s));
+  if (d <= 64 && gram_small_splits(t) <= kMaxPESplits) {
+    int S = 0, pitch = 0;
+    SKLS_TRY(run_gram_small_partials(Y, SKLS_F32, d, t, d, r.gw, r.gb, &S, &pitch, s));
+    SKLS_TRY(run_learned_PE(r.gw, S, pitch, C, d, E, loss, s));
+  } else {
+    SKLS_TRY(run_gram(Y, SKLS_F32, d, nullptr, SKLS_F64, t, d, P, r.gw, r.gb, s));
+    SKLS_TRY(run_learned_E(P, d, C, d, E, loss, s));
+  }
   if (grad_w == nullptr) return SKLS_OK;
+  if (d <= 64 && off != nullptr && perm != nullptr)
+    return run_learned_G_gather(Y, E, t, off, perm, A, grad_scale, accumulate != 0, grad_w, s);
   SKLS_TRY(run_learned_G(Y, E, t, d, G, s));
   return run_learned_gather(A, G, static_cast<uint32_t>(t), seed, grad_scale, accumulate != 0, grad_w, s);
 }
@@ -1082,9 +1096,11 @@ int32_t skls_learned_grad_planned(const skls_matrix* A, const float* C, const sk
   float* Y = ar.take<float>(static_cast<size_t>(t * d));
   const LearnedRest r = carve_learned_rest(ar, t, d);
   SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  const int32_t *off = nullptr, *perm = nullptr;
+  SKLS_TRY(sorted_plan_order(*A, t, desc->variant, SKLS_F32, plan, plan_bytes, &off, &perm));
   SKLS_TRY(apply_sketch_plan(*A, nullptr, SKLS_F64, t, plain_key(desc->seed), w, desc->variant, Y, nullptr, SKLS_F32,
                              plan, plan_bytes, s));
-  return learned_rest(*A, C, t, desc->seed, grad_scale, accumulate, loss, grad_w, r, Y, s);
+  return learned_rest(*A, C, t, desc->seed, grad_scale, accumulate, loss, grad_w, r, Y, s, off, perm);
 }
 
 namespace {
@@ -1193,6 +1209,8 @@ int32_t skls_learned_grad_batch(int32_t count, const skls_matrix* A, const float
   Arena ar(ws, ws_bytes);
   const BatchLanes b = carve_batch(ar, n, t, d);
   SKLS_TRY(need_ws(ar, ws, ws_bytes));
+  const int32_t *off = nullptr, *perm = nullptr;
+  SKLS_TRY(sorted_plan_order(A[0], t, desc->variant, SKLS_F32, plan, plan_bytes, &off, &perm));
   const int lanes = count < kLanes ? count : kLanes;
   LanePool* pool = nullptr;
   hipStream_t st[kLanes] = {s, s, s, s};
@@ -1214,7 +1232,8 @@ int32_t skls_learned_grad_batch(int32_t count, const skls_matrix* A, const float
                                SKLS_F32, plan, plan_bytes, st[k]);
     if (status == SKLS_OK)
       status = learned_rest(A[j], C[j], t, desc->seed, scale != nullptr ? scale[j] : 1.0f, j >= lanes ? 1 : 0,
-                            loss + j, grad_w != nullptr ? b.slots + k * n : nullptr, b.r[k], b.Y[k], st[k]);
+                            loss + j, grad_w != nullptr ? b.slots + k * n : nullptr, b.r[k], b.Y[k], st[k], off,
+                            perm);
   }
   // join even after a failure, so that no lane runs past the caller's stream
   for (int k = 1; k < lanes; ++k) {

@@ -1160,6 +1160,56 @@ SideStream* side_stream() {
 
 }  // namespace
 
+namespace {
+
+// The small-Gram launch (d <= 64, no v): its splits go to partial.
+int32_t launch_gram_small(const void* M, int32_t dtype, int64_t ld, int64_t m, int64_t d, double* partial, int* splits,
+                          hipStream_t s) {
+  int64_t rps;
+  const int S = small_splits(m, rps);
+  const int di = static_cast<int>(d);
+  auto launch = [&](auto tag) -> int32_t {
+    using TI = decltype(tag);
+    const TI* Mt = static_cast<const TI*>(M);
+    const bool vec = (reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * sizeof(TI)) % 16 == 0) && (d % 4 == 0);
+    if (vec)
+      hipLaunchKernelGGL((k_gram_small<TI, true>), dim3(S), dim3(kGThreads), 0, s, Mt, ld, m, di, rps, partial);
+    else
+      hipLaunchKernelGGL((k_gram_small<TI, false>), dim3(S), dim3(kGThreads), 0, s, Mt, ld, m, di, rps, partial);
+    SKLS_CHECK_LAUNCH();
+    return SKLS_OK;
+  };
+  *splits = S;
+  switch (dtype) {
+    case SKLS_F64: return launch(double{});
+    case SKLS_F32: return launch(float{});
+    case SKLS_BF16: return launch(bf16_t{});
+    default: set_error("gram: bad dtype"); return SKLS_ERR_DTYPE;
+  }
+}
+
+}  // namespace
+
+int gram_small_splits(int64_t m) {
+  int64_t rps;
+  return small_splits(m, rps);
+}
+
+int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_t m, int64_t d, void* ws,
+                                size_t ws_bytes, int* splits, int* pitch, hipStream_t s) {
+  if (d < 1 || d > 64) {
+    set_error("small Gram: need 1 <= d <= 64");
+    return SKLS_ERR_SHAPE;
+  }
+  if (ws == nullptr || ws_bytes < gram_bytes(gram_shape(m, d), m, d)) {
+    set_error("gram workspace too small");
+    return SKLS_ERR_WORKSPACE;
+  }
+  *pitch = kGT;
+  PhaseTimer pt("gram", s);
+  return launch_gram_small(M, dtype, ld, m, d, static_cast<double*>(ws), splits, s);
+}
+
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,
                  double* G, void* ws, size_t ws_bytes, hipStream_t s) {
   const GramShape g = gram_shape(m, d);
@@ -1169,32 +1219,11 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
   }
   Arena ar(ws, ws_bytes);
   if (v == nullptr && d <= 64) {
-    int64_t rps;
-    const int S = small_splits(m, rps);
-    double* partial = static_cast<double*>(ws);
-    const int di = static_cast<int>(d);
     PhaseTimer pt("gram", s);
-    auto launch = [&](auto tag) -> int32_t {
-      using TI = decltype(tag);
-      const TI* Mt = static_cast<const TI*>(M);
-      const bool vec = (reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * sizeof(TI)) % 16 == 0) && (d % 4 == 0);
-      if (vec)
-        hipLaunchKernelGGL((k_gram_small<TI, true>), dim3(S), dim3(kGThreads), 0, s, Mt, ld, m, di, rps, partial);
-      else
-        hipLaunchKernelGGL((k_gram_small<TI, false>), dim3(S), dim3(kGThreads), 0, s, Mt, ld, m, di, rps, partial);
-      SKLS_CHECK_LAUNCH();
-      return SKLS_OK;
-    };
-    int32_t st;
-    switch (dtype) {
-      case SKLS_F64: st = launch(double{}); break;
-      case SKLS_F32: st = launch(float{}); break;
-      case SKLS_BF16: st = launch(bf16_t{}); break;
-      default: set_error("gram: bad dtype"); return SKLS_ERR_DTYPE;
-    }
-    if (st != SKLS_OK) return st;
-    hipLaunchKernelGGL(k_gram_reduce, dim3(2, kGT * kGT / 256), dim3(256), 0, s, partial, partial, 1, S, 0, 1, di, 0,
-                       G);
+    int S = 0;
+    SKLS_TRY(launch_gram_small(M, dtype, ld, m, d, static_cast<double*>(ws), &S, s));
+    hipLaunchKernelGGL(k_gram_reduce, dim3(2, kGT * kGT / 256), dim3(256), 0, s, static_cast<const double*>(ws),
+                       static_cast<const double*>(ws), 1, S, 0, 1, static_cast<int>(d), 0, G);
     SKLS_CHECK_LAUNCH();
     return SKLS_OK;
   }

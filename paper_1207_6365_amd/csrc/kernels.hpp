@@ -35,6 +35,11 @@ int32_t build_sketch_plan(const skls_matrix& A, int64_t t, HashKey key, int32_t 
 int32_t apply_sketch_plan(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, HashKey key,
                           const float* w, int32_t resolved, void* SA, void* Sb, int32_t out_dtype, const void* plan,
                           size_t plan_bytes, hipStream_t s);
+// The bucket order of a dense SORTED plan: off[t + 1] (bucket offsets into
+// perm) and perm[n] (row ids in bucket order).  Both NULL when the plan is of
+// another variant or layout.
+int32_t sorted_plan_order(const skls_matrix& A, int64_t t, int32_t resolved, int32_t out_dtype, const void* plan,
+                          size_t plan_bytes, const int32_t** off, const int32_t** perm);
 // Argument checks shared by the sketch entry points (api.cpp).
 int32_t check_sketch_args(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t t, int32_t variant,
                           const void* SA, const void* Sb, int32_t out_dtype);
@@ -44,6 +49,13 @@ int32_t check_sketch_args(const skls_matrix* A, const void* b, int32_t b_dtype, 
 size_t gram_ws_bytes(int64_t m, int64_t dd);
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,
                  double* G /* dd x dd */, void* ws, size_t ws_bytes, hipStream_t s);
+// The row splits of M^T M for d <= 64 (no v), without their sum: split k at
+// partial + k * pitch * pitch, entry (i, j), i <= j < d, at i * pitch + j.
+// ws as for run_gram (gram_ws_bytes(m, d) bytes); *splits = their number.
+// Number of splits run_gram_small_partials makes for m rows.
+int gram_small_splits(int64_t m);
+int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_t m, int64_t d, void* ws,
+                                size_t ws_bytes, int* splits, int* pitch, hipStream_t s);
 // Cholesky of the leading d x d block of G (leading dimension ldg): R upper,
 // status[0] = 0 ok / 1 rank deficient.  With Rinv and RinvT (d x d each, or
 // both NULL) it also forms R^{-1} and R^{-T} within the same launches.
@@ -133,6 +145,13 @@ int32_t run_learned_E(const double* P, int64_t ldp, const float* C, int64_t d, f
 int32_t run_learned_G(const float* Y, const float* E, int64_t t, int64_t d, float* G, hipStream_t s);
 int32_t run_learned_gather(const skls_matrix& A, const float* G, uint32_t t, uint64_t seed, float scale,
                            bool accumulate, float* grad, hipStream_t s);
+// Loss and E from the small-Gram splits (run_gram_small_partials), one block.
+int32_t run_learned_PE(const double* partial, int S, int pitch, const float* C, int64_t d, float* E, float* loss,
+                       hipStream_t s);
+// G = 4 Y E and the gradient gather in one launch, from the bucket order of a
+// dense SORTED plan (sorted_plan_order); d <= 64.
+int32_t run_learned_G_gather(const float* Y, const float* E, int64_t t, const int32_t* off, const int32_t* perm,
+                             const skls_matrix& A, float scale, bool accumulate, float* grad, hipStream_t s);
 int32_t run_sum_slots(int64_t n, const float* slots, int64_t stride, int k, float scale, bool accumulate,
                       float* grad, hipStream_t s);
 int32_t run_adam(int64_t n, float* w, const float* g, float* m, float* v, int32_t step, float lr, float b1,

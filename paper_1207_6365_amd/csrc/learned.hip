@@ -84,6 +84,131 @@ __global__ __launch_bounds__(256) void k_learned_G(const float* __restrict__ Y, 
     if (cb + c4 + k < d) G[static_cast<size_t>(r0 + r) * d + cb + c4 + k] = 4.0f * acc[k];
 }
 
+// P = the sum of the S row splits of Y^T Y (entries i <= j of split k at
+// partial + k * pitch^2 + i * pitch + j), E = P - C in both triangles
+// (float32) and loss = ||E||_F^2, in one block.  Entries (i, j) and (j, i)
+// sum the same values in the same order, so E is as symmetric as C.
+__global__ __launch_bounds__(1024) void k_learned_PE(const double* __restrict__ partial, int S, int pitch,
+                                                     const float* __restrict__ C, int d, float* __restrict__ E,
+                                                     float* __restrict__ loss) {
+  __shared__ double scratch[16];
+  const size_t stride = static_cast<size_t>(pitch) * pitch;
+  double s = 0.0;
+  for (int idx = threadIdx.x; idx < d * d; idx += blockDim.x) {
+    const int i = idx / d, j = idx % d;
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    const double* src = partial + static_cast<size_t>(lo) * pitch + hi;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 4 <= S; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] += src[(k + u) * stride];
+    }
+    for (int u = 0; k < S; ++k, ++u) a[u] += src[k * stride];
+    const double e = ((a[0] + a[1]) + (a[2] + a[3])) - static_cast<double>(C[idx]);
+    E[idx] = static_cast<float>(e);
+    s += e * e;
+  }
+  s = block_sum(s, scratch);
+  if (threadIdx.x == 0) *loss = static_cast<float>(s);
+}
+
+// G = 4 Y E for the kFB buckets b0 .. b0 + kFB - 1 of this block, held in
+// LDS, then the gradient of every row of those buckets:
+//   grad[r] = scale * < G[h(r)], A[r] >   (d <= 64).
+// The rows come from the bucket order of the sketch's plan, where the rows of
+// the block's buckets are one contiguous run of perm; groups of 16 lanes take
+// every 16th of them, kFU at a time, so their loads are in flight together.
+// Loads are unconditional (clamped indices, values masked afterwards).
+constexpr int kFB = 4, kFU = 4;
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_learned_G_gather(const float* __restrict__ Y, const float* __restrict__ E,
+                                                          int64_t t, int d, const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ perm, int64_t ld,
+                                                          const float* __restrict__ A, float scale, int accumulate,
+                                                          float* __restrict__ grad) {
+  __shared__ float Es[64][64];
+  __shared__ __align__(16) float Gs[kFB][64];
+  __shared__ float Ys[kFB][64];
+  const int tid = threadIdx.x;
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kFB;
+  float e[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = u * 256 + tid, k = q / 64, c = q % 64;
+    const bool in = k < d && c < d;
+    const float x = E[in ? k * d + c : 0];
+    e[u] = in ? x : 0.0f;
+  }
+  const int r = tid / 64, c = tid % 64;  // kFB x 64 = 256 threads
+  {
+    const bool in = b0 + r < t && c < d;
+    const float x = Y[in ? static_cast<size_t>(b0 + r) * d + c : 0];
+    Ys[r][c] = in ? x : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int q = u * 256 + tid;
+    Es[q / 64][q % 64] = e[u];
+  }
+  __syncthreads();
+  float acc = 0.0f;
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) acc += Ys[r][k] * Es[k][c];
+  Gs[r][c] = 4.0f * acc;
+  __syncthreads();
+  if (b0 >= t) return;
+  const int64_t bl = (b0 + kFB < t) ? b0 + kFB : t;
+  const int32_t P0 = off[b0], P1 = off[bl];
+  int32_t ob[kFB - 1];
+#pragma unroll
+  for (int u = 0; u < kFB - 1; ++u) ob[u] = off[(b0 + 1 + u < bl) ? b0 + 1 + u : bl];
+  const int grp = tid / 16, sub = tid % 16;
+  for (int32_t p = P0 + grp; p < P1; p += 16 * kFU) {
+    int32_t row[kFU], kb[kFU];
+    bool ok[kFU];
+#pragma unroll
+    for (int u = 0; u < kFU; ++u) {
+      const int32_t pu = p + 16 * u;
+      ok[u] = pu < P1;
+      const int32_t pc = ok[u] ? pu : P0;
+      row[u] = perm[pc];
+      kb[u] = 0;
+#pragma unroll
+      for (int v = 0; v < kFB - 1; ++v) kb[u] += pc >= ob[v] ? 1 : 0;
+    }
+    float sum[kFU];
+    if (VEC) {
+      const bool live = sub * 4 < d;
+      const int cc = live ? sub * 4 : 0;
+      nt_f4 x[kFU];
+#pragma unroll
+      for (int u = 0; u < kFU; ++u) x[u] = stream_load<nt_f4>(A + static_cast<size_t>(row[u]) * ld + cc);
+#pragma unroll
+      for (int u = 0; u < kFU; ++u) {
+        const float4 g = *reinterpret_cast<const float4*>(&Gs[kb[u]][cc]);
+        const float v = x[u][0] * g.x + x[u][1] * g.y + x[u][2] * g.z + x[u][3] * g.w;
+        sum[u] = live ? v : 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kFU; ++u) {
+        sum[u] = 0.0f;
+        for (int cc = sub; cc < d; cc += 16) sum[u] += A[static_cast<size_t>(row[u]) * ld + cc] * Gs[kb[u]][cc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kFU; ++u)
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) sum[u] += __shfl_xor(sum[u], o, kWave);
+    if (sub == 0)
+#pragma unroll
+      for (int u = 0; u < kFU; ++u)
+        if (ok[u]) grad[row[u]] = accumulate ? grad[row[u]] + scale * sum[u] : scale * sum[u];
+  }
+}
+
 // grad[i] = < G[h(i), :], A[i, :] > with 16 lanes per row; VEC (16-byte
 // aligned rows, d a multiple of 4): each lane reads four consecutive entries
 // of both rows at once.
@@ -167,6 +292,29 @@ int32_t run_learned_gather(const skls_matrix& A, const float* G, uint32_t t, uin
   const auto kern = vec ? k_learned_gather<true> : k_learned_gather<false>;
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, A.n, static_cast<int>(A.d), A.ld,
                      static_cast<const float*>(A.val), G, t, seed, scale, accumulate ? 1 : 0, grad);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
+int32_t run_learned_PE(const double* partial, int S, int pitch, const float* C, int64_t d, float* E, float* loss,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_learned_PE, dim3(1), dim3(1024), 0, s, partial, S, pitch, C, static_cast<int>(d), E, loss);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
+int32_t run_learned_G_gather(const float* Y, const float* E, int64_t t, const int32_t* off, const int32_t* perm,
+                             const skls_matrix& A, float scale, bool accumulate, float* grad, hipStream_t s) {
+  if (A.d > 64) {
+    set_error("the fused gradient needs d <= 64");
+    return SKLS_ERR_SHAPE;
+  }
+  PhaseTimer pt("learned_gather", s);
+  const bool vec = reinterpret_cast<uintptr_t>(A.val) % 16 == 0 && A.ld % 4 == 0 && A.d % 4 == 0;
+  const auto kern = vec ? k_learned_G_gather<true> : k_learned_G_gather<false>;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(div_up(t, kFB))), dim3(256), 0, s, Y, E, t,
+                     static_cast<int>(A.d), off, perm, A.ld, static_cast<const float*>(A.val), scale,
+                     accumulate ? 1 : 0, grad);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }

@@ -1870,6 +1870,22 @@ int32_t apply_sketch_plan(const skls_matrix& A, const void* b, int32_t b_dtype, 
   return apply_with(A, P, b, b_f64, tt, seed, w, SA, Sb, out_dtype, A.layout == SKLS_CSR ? b : nullptr, s);
 }
 
+int32_t sorted_plan_order(const skls_matrix& A, int64_t t, int32_t resolved, int32_t out_dtype, const void* plan,
+                          size_t plan_bytes_, const int32_t** off, const int32_t** perm) {
+  *off = nullptr;
+  *perm = nullptr;
+  if (A.layout != SKLS_DENSE || resolved != SKLS_SKETCH_SORTED) return SKLS_OK;
+  Arena ar(const_cast<void*>(plan), plan_bytes_);
+  const BucketPlan P = carve_plan(ar, plan_shape(A, t, resolved, out_bytes_of(out_dtype)), A.n, t);
+  if (!plan || !ar.fits()) {
+    set_error("sketch plan buffer too small: need %zu bytes, have %zu", ar.used, plan_bytes_);
+    return SKLS_ERR_WORKSPACE;
+  }
+  *off = P.off;
+  *perm = static_cast<const int32_t*>(P.fine);
+  return SKLS_OK;
+}
+
 int32_t run_sketch(const skls_matrix& A, const void* b, int32_t b_dtype, int64_t t, uint64_t seed,
                    const float* w, int32_t variant, void* SA, void* Sb, int32_t out_dtype, void* ws,
                    size_t ws_bytes, hipStream_t s) {

@@ -103,19 +103,25 @@ def test_gram_narrow_integer_exact(sk, storage, n, d, ld):
     assert np.array_equal(C.astype(np.int64), A.T @ A)
 
 
-@pytest.mark.parametrize("n,d,t", [(4096, 16, 128), (32768, 64, 1024), (5000, 70, 333)])
+@pytest.mark.parametrize("n,d,t", [(4096, 16, 128), (32768, 64, 1024), (5000, 70, 333), (3000, 13, 37),
+                                   (3000, 24, 37)])
 def test_learned_loss_and_gradient(sk, n, d, t):
-    make, _ = W.learned_family(num=4, n=n, d=d)
+    # both the call that builds its own plan and the call with a shared plan
+    # (at d <= 64 the product 4 Y E and the gather then run as one kernel
+    # over the plan's bucket order), each against the oracle
+    make, _ = W.learned_family(num=4, n=n, d=d, rank=min(16, d))
     A = make(1)
     seed = W.sketch_seed(0)
     w = np.random.default_rng(5).standard_normal(n).astype(np.float32)
     Ag = up(A)
     C = sk.gram(Ag)
-    loss, grad = sk.learned_grad(Ag, C, t, seed, up(w))
     L_o, g_o = O.distortion_grad(A.astype(np.float64), seed, t, w.astype(np.float64))
-    assert abs(loss.item() - L_o) <= 1e-4 * L_o
-    gg = grad.cpu().numpy()
-    assert np.linalg.norm(gg - g_o) <= 1e-4 * np.linalg.norm(g_o)
+    plan = sk.sketch_plan(Ag, t, seed, variant="sorted", out_dtype=torch.float32)
+    for pl in (plan, None):
+        loss, grad = sk.learned_grad(Ag, C, t, seed, up(w), plan=pl)
+        assert abs(loss.item() - L_o) <= 1e-4 * L_o
+        gg = grad.cpu().numpy()
+        assert np.linalg.norm(gg - g_o) <= 1e-4 * np.linalg.norm(g_o)
     # scaled accumulation: grad2 = grad + 0.5 grad
     g2 = grad.clone()
     sk.learned_grad(Ag, C, t, seed, up(w), loss=loss, grad=g2, grad_scale=0.5, accumulate=True)
