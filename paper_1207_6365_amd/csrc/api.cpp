@@ -638,20 +638,30 @@ int32_t lstsq_once(const skls_matrix* A, const double* b, const skls_lstsq_opts&
     SKLS_TRY(run_solve_from_gram(L.Rinv, L.q.RinvT, L.q.G + d * dd, d, x, L.tmp, s));
   }
   SKLS_TRY_HIP(hipEventRecord(ev[2], s));
-  int32_t rank_bad = 0;
-  double sb_norm2 = 0.0;  // ||S b||^2, close to ||b||^2 for an embedding
-  SKLS_TRY_HIP(hipMemcpyAsync(&sb_norm2, L.q.G + d * dd + d, sizeof(double), hipMemcpyDeviceToHost, s));
-  SKLS_TRY(read_status(L.q.status, s, &rank_bad));
   float ms = 0.0f;
-  SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-  inf.ms_sketch = ms;
-  SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
-  inf.ms_qr = ms;
-  if (rank_bad) {
-    set_error("the sketch S A is numerically rank deficient");
-    return SKLS_ERR_RANK;
+  auto qr_times = [&]() -> int32_t {
+    SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    inf.ms_sketch = ms;
+    SKLS_TRY_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+    inf.ms_qr = ms;
+    return SKLS_OK;
+  };
+  if (o.sketch_only) {
+    int32_t rank_bad = 0;
+    SKLS_TRY(read_status(L.q.status, s, &rank_bad));
+    SKLS_TRY(qr_times());
+    if (rank_bad) {
+      set_error("the sketch S A is numerically rank deficient");
+      return SKLS_ERR_RANK;
+    }
+    return SKLS_OK;
   }
-  if (o.sketch_only) return SKLS_OK;
+  // The rank test of R and ||S b||^2 (close to ||b||^2 for an embedding) are
+  // read with the first LSQR state, one host round trip later: the work
+  // enqueued meanwhile on a rank-deficient R is discarded.
+  double sb_norm2 = 0.0;
+  double *hm = nullptr, *dm = nullptr;  // the state mirror: host and device addresses
+  SKLS_TRY(lsqr_mirror(&hm, &dm));
 
   // --- R-preconditioned LSQR on M = A R^{-1} (Section 7.7), with float64
   //     residual refinement.  Plain: every pass in float64.  Mixed: inner
@@ -669,22 +679,28 @@ int32_t lstsq_once(const skls_matrix* A, const double* b, const skls_lstsq_opts&
   int outer = 0;
   for (;;) {
     // explicit residual r = b - A x and g = R^{-T} A^T r, float64 accumulation
-    SKLS_TRY(run_scale(x, d, -1.0, L.p, s));
+    // (the first pass also sets the coefficient 1 it reads; init keeps it)
+    SKLS_TRY(run_scale(x, d, -1.0, L.p, s, outer == 0 ? L.st + LSQR_ONE : nullptr));
     pa.p = L.p;
     pa.coef = L.st + LSQR_ONE;
     pa.Z = b;
     pa.z_is_b = 1;
     pa.acc_f64 = 1;
-    if (outer == 0) {
-      static const double kOne = 1.0;
-      SKLS_TRY_HIP(hipMemcpyAsync(L.st + LSQR_ONE, &kOne, sizeof(double), hipMemcpyHostToDevice, s));
-    }
     SKLS_TRY(run_pass(pa, s));
     SKLS_TRY(run_reduce_partials(L.partial, L.nblk, d, L.gsum, L.red, s));
     SKLS_TRY(run_gemv(L.q.RinvT, d, L.gsum, L.vp, s));
-    SKLS_TRY(run_lsqr_init(L.gsum, L.vp, d, L.v, L.w, L.y, L.st, s));
-    SKLS_TRY_HIP(hipMemcpyAsync(hs, L.st, sizeof hs, hipMemcpyDeviceToHost, s));
+    SKLS_TRY(run_lsqr_init(L.gsum, L.vp, d, L.v, L.w, L.y, L.st, s, dm, outer == 0 ? L.q.status : nullptr,
+                           outer == 0 ? L.q.G + d * dd + d : nullptr));
     SKLS_TRY_HIP(hipStreamSynchronize(s));
+    std::memcpy(hs, hm, sizeof hs);
+    if (outer == 0) {
+      sb_norm2 = hm[LSQR_NSTATE + 1];
+      SKLS_TRY(qr_times());
+      if (hm[LSQR_NSTATE] != 0.0) {
+        set_error("the sketch S A is numerically rank deficient");
+        return SKLS_ERR_RANK;
+      }
+    }
     const double rn = hs[LSQR_RNORM], gn = hs[LSQR_ARNORM];
     inf.resid_norm = rn;
     inf.grad_norm = gn;
@@ -730,11 +746,11 @@ int32_t lstsq_once(const skls_matrix* A, const double* b, const skls_lstsq_opts&
         SKLS_TRY(run_pass(pa, s));
         SKLS_TRY(run_reduce_partials(L.partial, L.nblk, d, L.gsum, L.red, s));
         SKLS_TRY(run_gemv(L.q.RinvT, d, L.gsum, L.vp, s));
-        SKLS_TRY(run_lsqr_step(L.gsum, L.vp, d, L.v, L.w, L.y, L.st, target, s));
+        SKLS_TRY(run_lsqr_step(L.gsum, L.vp, d, L.v, L.w, L.y, L.st, target, s, dm));
         SKLS_TRY(run_gemv(L.Rinv, d, L.v, L.p, s));
       }
-      SKLS_TRY_HIP(hipMemcpyAsync(hs, L.st, sizeof hs, hipMemcpyDeviceToHost, s));
       SKLS_TRY_HIP(hipStreamSynchronize(s));
+      std::memcpy(hs, hm, sizeof hs);
       const int64_t count = static_cast<int64_t>(hs[LSQR_COUNT]);
       const int64_t did = count - taken;
       inf.iterations += static_cast<int32_t>(did);

@@ -240,21 +240,26 @@ __global__ __launch_bounds__(kGThreads) void k_gram_partial(const TI* __restrict
   }
 }
 
-// Gram of a matrix of at most 64 columns (no v).  k_gram_partial gives each
-// wave a 64 x 64 quadrant of a 128 x 128 tile, so at d <= 64 one wave would
-// take every row alone while three multiply zeros.  Here the four waves split
-// each staged chunk of kSK rows by rows (16 each) and form only the 16 x 16
-// blocks on and above the diagonal of the one 64 x 64 tile (the reduction
-// reads the upper triangle of diagonal tiles); their sums meet in LDS at the
-// end.  Block b writes split b of the partial layout of k_gram_partial
-// (pair 0), entries inside d x d, so k_gram_reduce finishes the Gram.
+// Gram of a matrix of at most 64 columns (with v: [M | v], at most 64 in
+// all).  k_gram_partial gives each wave a 64 x 64 quadrant of a 128 x 128
+// tile, so at d <= 64 one wave would take every row alone while three
+// multiply zeros.  Here the four waves split each staged chunk of kSK rows by
+// rows (16 each) and form only the 16 x 16 blocks on and above the diagonal
+// of the one 64 x 64 tile (the reduction reads the upper triangle of diagonal
+// tiles); their sums meet in LDS at the end.  Block b writes split b of the
+// partial layout of k_gram_partial (pair 0), entries inside d x d, so
+// k_gram_reduce finishes the Gram.
 constexpr int kSK = 64;  // rows per staged chunk
 constexpr int kSB = 10;  // 16 x 16 blocks (x <= y) of a 64 x 64 upper triangle
 constexpr int kSL = kSK * 64 / 4 / kGThreads;  // 4-wide loads per thread per chunk
 
-template <typename TI, bool VEC>
-__global__ __launch_bounds__(kGThreads) void k_gram_small(const TI* __restrict__ M, int64_t ld, int64_t m, int d,
+template <typename TI, bool VEC, bool WITHV>
+__global__ __launch_bounds__(kGThreads) void k_gram_small(const TI* __restrict__ M, int64_t ld,
+                                                          const void* __restrict__ v, int v_f64, int64_t m, int d,
                                                           int64_t rows_per_split, double* __restrict__ partial) {
+  // WITHV: the product is [M | v] with v as column dm = d - 1 (v in the
+  // staging precision: float64 with float64 M, float32 otherwise)
+  const int dm = WITHV ? d - 1 : d;
   using TS = GStage<TI>;
   constexpr size_t kStage = 2 * kSK * 64 * sizeof(TS);
   constexpr size_t kRed = 3 * kSB * 4 * kWave * sizeof(double);
@@ -273,7 +278,25 @@ __global__ __launch_bounds__(kGThreads) void k_gram_small(const TI* __restrict__
 #pragma unroll
     for (int u = 0; u < kSL; ++u) {
       const int e = (u * kGThreads + static_cast<int>(threadIdx.x)) * 4;
-      gload4<TI, VEC>(M, ld, kb + e / 64, k1, e % 64, d, ra[u], ia[u]);
+      gload4<TI, VEC>(M, ld, kb + e / 64, k1, e % 64, dm, ra[u], ia[u]);
+      if (WITHV) {
+        const int c = e % 64;
+        if (c <= dm && dm < c + 4) {  // this group of four holds column dm
+          const int64_t k = kb + e / 64;
+          const int64_t kc = k < k1 ? k : k1 - 1;
+          const TS x = v_f64 ? static_cast<TS>(static_cast<const double*>(v)[kc])
+                             : static_cast<TS>(static_cast<const float*>(v)[kc]);
+          // VEC zeroes the whole group through ia; fill it explicitly
+          if (VEC) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ra[u][q] = TS(0);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (c + q == dm) ra[u][q] = k < k1 ? x : TS(0);
+          ia[u] = true;
+        }
+      }
     }
   };
   auto stash = [&](int buf) {
@@ -328,12 +351,12 @@ __global__ __launch_bounds__(kGThreads) void k_gram_small(const TI* __restrict__
     for (int y = x; y < 4; ++y, ++n)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        double v = acc[n][e];
+        double sum = acc[n][e];
 #pragma unroll
-        for (int w = 0; w < 3; ++w) v += red[(w * kSB * 4 + n * 4 + e) * kWave + lane];
+        for (int w = 0; w < 3; ++w) sum += red[(w * kSB * 4 + n * 4 + e) * kWave + lane];
         // element e of lane l: row l / 16 + 4 e, column l % 16 of the block
         const int row = x * 16 + lr + 4 * e, col = y * 16 + lc;
-        if (row < d && col < d) out[row * kGT + col] = v;
+        if (row < d && col < d) out[row * kGT + col] = sum;
       }
 }
 
@@ -1162,20 +1185,29 @@ SideStream* side_stream() {
 
 namespace {
 
-// The small-Gram launch (d <= 64, no v): its splits go to partial.
-int32_t launch_gram_small(const void* M, int32_t dtype, int64_t ld, int64_t m, int64_t d, double* partial, int* splits,
-                          hipStream_t s) {
+// The small-Gram launch (d columns of M, d + 1 <= 64 with v, d <= 64
+// without): its splits go to partial.
+int32_t launch_gram_small(const void* M, int32_t dtype, int64_t ld, const void* v, int v_f64, int64_t m, int64_t d,
+                          double* partial, int* splits, hipStream_t s) {
   int64_t rps;
   const int S = small_splits(m, rps);
-  const int di = static_cast<int>(d);
+  const int dp = static_cast<int>(v != nullptr ? d + 1 : d);  // columns of the product
   auto launch = [&](auto tag) -> int32_t {
     using TI = decltype(tag);
     const TI* Mt = static_cast<const TI*>(M);
     const bool vec = (reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * sizeof(TI)) % 16 == 0) && (d % 4 == 0);
-    if (vec)
-      hipLaunchKernelGGL((k_gram_small<TI, true>), dim3(S), dim3(kGThreads), 0, s, Mt, ld, m, di, rps, partial);
-    else
-      hipLaunchKernelGGL((k_gram_small<TI, false>), dim3(S), dim3(kGThreads), 0, s, Mt, ld, m, di, rps, partial);
+    const dim3 g(S), b(kGThreads);
+    if (v != nullptr) {
+      if (vec)
+        hipLaunchKernelGGL((k_gram_small<TI, true, true>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial);
+      else
+        hipLaunchKernelGGL((k_gram_small<TI, false, true>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial);
+    } else {
+      if (vec)
+        hipLaunchKernelGGL((k_gram_small<TI, true, false>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial);
+      else
+        hipLaunchKernelGGL((k_gram_small<TI, false, false>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial);
+    }
     SKLS_CHECK_LAUNCH();
     return SKLS_OK;
   };
@@ -1207,7 +1239,7 @@ int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_
   }
   *pitch = kGT;
   PhaseTimer pt("gram", s);
-  return launch_gram_small(M, dtype, ld, m, d, static_cast<double*>(ws), splits, s);
+  return launch_gram_small(M, dtype, ld, nullptr, 0, m, d, static_cast<double*>(ws), splits, s);
 }
 
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,
@@ -1218,12 +1250,16 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
     return SKLS_ERR_WORKSPACE;
   }
   Arena ar(ws, ws_bytes);
-  if (v == nullptr && d <= 64) {
+  // v rides along as column d when it is in the staging precision of M
+  const bool small_v = v != nullptr && d + 1 <= 64 &&
+                       (dtype == SKLS_F64 ? v_dtype == SKLS_F64 : v_dtype == SKLS_F32);
+  if ((v == nullptr && d <= 64) || small_v) {
     PhaseTimer pt("gram", s);
     int S = 0;
-    SKLS_TRY(launch_gram_small(M, dtype, ld, m, d, static_cast<double*>(ws), &S, s));
+    SKLS_TRY(launch_gram_small(M, dtype, ld, v, v_dtype == SKLS_F64 ? 1 : 0, m, d, static_cast<double*>(ws), &S, s));
+    const int dp = static_cast<int>(v != nullptr ? d + 1 : d);
     hipLaunchKernelGGL(k_gram_reduce, dim3(2, kGT * kGT / 256), dim3(256), 0, s, static_cast<const double*>(ws),
-                       static_cast<const double*>(ws), 1, S, 0, 1, static_cast<int>(d), 0, G);
+                       static_cast<const double*>(ws), 1, S, 0, 1, dp, 0, G);
     SKLS_CHECK_LAUNCH();
     return SKLS_OK;
   }

@@ -126,14 +126,21 @@ enum {
   LSQR_COUNT,  // steps taken since the last init
   LSQR_NSTATE
 };
+// The init and the steps also copy the state into `mirror` (device address
+// of pinned host memory from lsqr_mirror, or NULL); the init adds *flag and
+// *extra after it (mirror[LSQR_NSTATE], mirror[LSQR_NSTATE + 1]; 0 for NULL).
 int32_t run_lsqr_init(const double* gsum, const double* vp, int64_t d, double* v, double* w, double* y, double* st,
-                      hipStream_t s);
+                      hipStream_t s, double* mirror = nullptr, const int32_t* flag = nullptr,
+                      const double* extra = nullptr);
 // One step; it is skipped (state unchanged) once st[LSQR_STOP] is set, and
 // sets it when the recurrence ends or est_ar <= target * est_r.
 int32_t run_lsqr_step(const double* gsum, const double* vp, int64_t d, double* v, double* w, double* y, double* st,
-                      double target, hipStream_t s);
-// y = a * x (d-vectors); x += t.
-int32_t run_scale(const double* x, int64_t d, double a, double* y, hipStream_t s);
+                      double target, hipStream_t s, double* mirror = nullptr);
+// LSQR_NSTATE + 2 doubles of pinned, coherent host memory per host thread
+// (allocated on first use): its host and device addresses.
+int32_t lsqr_mirror(double** host, double** dev);
+// y = a * x (d-vectors), and *one = 1 when one is not NULL; x += t.
+int32_t run_scale(const double* x, int64_t d, double a, double* y, hipStream_t s, double* one = nullptr);
 int32_t run_add(double* x, const double* t, int64_t d, hipStream_t s);
 
 // ---------------------------------------------------------------- leverage.hip

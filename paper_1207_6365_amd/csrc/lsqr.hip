@@ -377,9 +377,19 @@ int32_t run_reduce_partials(const double* partial, int32_t nblk, int64_t d, doub
 namespace skls {
 namespace {
 
+// Thread 0 copies the state into the host mirror (when given) after writing
+// it, so a host that waits for the stream reads it without a copy.
+__device__ __forceinline__ void mirror_state(const double* __restrict__ st, double* __restrict__ mir) {
+  if (mir == nullptr) return;
+#pragma unroll
+  for (int k = 0; k < LSQR_NSTATE; ++k) mir[k] = st[k];
+}
+
 __global__ __launch_bounds__(256) void k_lsqr_init(const double* __restrict__ gsum, const double* __restrict__ vp,
                                                    int d, double* __restrict__ v, double* __restrict__ w,
-                                                   double* __restrict__ y, double* __restrict__ st) {
+                                                   double* __restrict__ y, double* __restrict__ st,
+                                                   double* __restrict__ mir, const int32_t* __restrict__ flag,
+                                                   const double* __restrict__ extra) {
   __shared__ double scratch[4];
   const double beta = sqrt(gsum[d]);
   const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -410,12 +420,18 @@ __global__ __launch_bounds__(256) void k_lsqr_init(const double* __restrict__ gs
     st[LSQR_DONE] = (alpha > 0.0 && beta > 0.0) ? 0.0 : 1.0;
     st[LSQR_STOP] = 0.0;
     st[LSQR_COUNT] = 0.0;
+    mirror_state(st, mir);
+    if (mir != nullptr) {
+      mir[LSQR_NSTATE] = flag != nullptr ? static_cast<double>(*flag) : 0.0;
+      mir[LSQR_NSTATE + 1] = extra != nullptr ? *extra : 0.0;
+    }
   }
 }
 
 __global__ __launch_bounds__(256) void k_lsqr_step(const double* __restrict__ gsum, const double* __restrict__ vp,
                                                    int d, double* __restrict__ v, double* __restrict__ w,
-                                                   double* __restrict__ y, double* __restrict__ st, double target) {
+                                                   double* __restrict__ y, double* __restrict__ st, double target,
+                                                   double* __restrict__ mir) {
   __shared__ double scratch[4];
   // read by every thread before thread 0 writes it below (after a barrier)
   if (st[LSQR_STOP] != 0.0) return;
@@ -459,11 +475,14 @@ __global__ __launch_bounds__(256) void k_lsqr_step(const double* __restrict__ gs
     st[LSQR_DONE] = done ? 1.0 : 0.0;
     st[LSQR_COUNT] += 1.0;
     st[LSQR_STOP] = (done || est_ar <= target * phibar_new) ? 1.0 : 0.0;
+    mirror_state(st, mir);
   }
 }
 
-__global__ void k_axpy_neg(const double* __restrict__ x, int d, double a, double* __restrict__ y) {
+__global__ void k_axpy_neg(const double* __restrict__ x, int d, double a, double* __restrict__ y,
+                           double* __restrict__ one) {
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d; c += gridDim.x * blockDim.x) y[c] = a * x[c];
+  if (one != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *one = 1.0;
 }
 
 __global__ void k_add(double* __restrict__ x, const double* __restrict__ t, int d) {
@@ -473,22 +492,36 @@ __global__ void k_add(double* __restrict__ x, const double* __restrict__ t, int 
 }  // namespace
 
 int32_t run_lsqr_init(const double* gsum, const double* vp, int64_t d, double* v, double* w, double* y, double* st,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_lsqr_init, dim3(1), dim3(256), 0, s, gsum, vp, static_cast<int>(d), v, w, y, st);
+                      hipStream_t s, double* mirror, const int32_t* flag, const double* extra) {
+  hipLaunchKernelGGL(k_lsqr_init, dim3(1), dim3(256), 0, s, gsum, vp, static_cast<int>(d), v, w, y, st, mirror, flag,
+                     extra);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }
 
 int32_t run_lsqr_step(const double* gsum, const double* vp, int64_t d, double* v, double* w, double* y, double* st,
-                      double target, hipStream_t s) {
-  hipLaunchKernelGGL(k_lsqr_step, dim3(1), dim3(256), 0, s, gsum, vp, static_cast<int>(d), v, w, y, st, target);
+                      double target, hipStream_t s, double* mirror) {
+  hipLaunchKernelGGL(k_lsqr_step, dim3(1), dim3(256), 0, s, gsum, vp, static_cast<int>(d), v, w, y, st, target,
+                     mirror);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }
 
-int32_t run_scale(const double* x, int64_t d, double a, double* y, hipStream_t s) {
+int32_t lsqr_mirror(double** host, double** dev) {
+  thread_local double* h = nullptr;
+  if (h == nullptr) {
+    void* q = nullptr;
+    SKLS_TRY_HIP(hipHostMalloc(&q, sizeof(double) * (LSQR_NSTATE + 2), hipHostMallocCoherent));
+    h = static_cast<double*>(q);
+  }
+  *host = h;
+  SKLS_TRY_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(dev), h, 0));
+  return SKLS_OK;
+}
+
+int32_t run_scale(const double* x, int64_t d, double a, double* y, hipStream_t s, double* one) {
   hipLaunchKernelGGL(k_axpy_neg, dim3(static_cast<unsigned>(div_up(d, 256))), dim3(256), 0, s, x, static_cast<int>(d),
-                     a, y);
+                     a, y, one);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }

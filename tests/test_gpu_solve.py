@@ -92,6 +92,29 @@ def test_sketch_and_solve_parity_small_workload(sk):
     assert info["ms_sketch"] >= 0 and info["ms_qr"] >= 0
 
 
+@pytest.mark.parametrize("d", [13, 60, 63])
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+def test_narrow_dense_solves_match_oracle(sk, d, precision):
+    # d + 1 <= 64: the Gram of [S A | S b] runs on the small-Gram kernel with
+    # S b as its last column (d = 60 with four-wide loads, 13 and 63 element
+    # by element; S A in float64 for plain, float32 for mixed)
+    g = np.random.default_rng(d)
+    n, t = 6000, 4000
+    A = g.standard_normal((n, d)).astype(np.float32)
+    Ad = A.astype(np.float64)
+    b = Ad @ g.standard_normal(d) + 0.1 * g.standard_normal(n)
+    op = O.MatrixOp(Ad)
+    xs = O.lstsq_exact(Ad, b)
+    seed = W.sketch_seed(5)
+    if precision == "plain":
+        x_g, _ = sk.lstsq(up(A), up(b), t, seed, sketch_only=True)
+        x_o, *_ = O.sketch_and_solve(op, b, seed, t)
+        assert np.linalg.norm(x_g.cpu().numpy() - x_o) <= 1e-9 * np.linalg.norm(x_o)
+    x_g, info = sk.lstsq(up(A), up(b), t, seed, delta=1e-11, precision=precision)
+    assert info["certified"] == 1
+    assert O.residual_ratio(Ad, b, x_g.cpu().numpy(), xs) - 1.0 <= 1e-11
+
+
 @pytest.mark.parametrize("precision", ["plain", "mixed"])
 @pytest.mark.parametrize("variant", ["atomic", "sorted"])
 def test_lstsq_parity_small_workload(sk, precision, variant):
