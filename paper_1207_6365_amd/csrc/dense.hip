@@ -783,6 +783,47 @@ __global__ __launch_bounds__(256) void k_chol_first(const double* __restrict__ W
   finish_tile(c, R, d, 0, Kinv, bad, rr, x, t, inv);
 }
 
+// d <= kCB: the whole factorisation in one block.  The upper triangle of G
+// goes straight into the factor's registers, the tile is factored and
+// inverted as in k_chol_first, the parts of R, R^{-1} and R^{-T} it leaves
+// unwritten are zeroed, and the rank test of k_chol_finish runs on the
+// factored diagonal (against G's own diagonal).
+__global__ __launch_bounds__(256) void k_chol_small(const double* __restrict__ G, int64_t ldg, int d,
+                                                    double* __restrict__ R, double* __restrict__ Kinv, InvOut inv,
+                                                    int32_t* __restrict__ status, double rtol) {
+  __shared__ double rr[kCB][kCP];
+  __shared__ double x[kCB][kCP];
+  __shared__ double t[kPW * kSP > kCB * kCB / 4 ? kPW * kSP : kCB * kCB / 4];
+  __shared__ int32_t sbad;
+  const int tid = threadIdx.x;
+  const int j = tid & (kCB - 1), g = tid >> 6;
+  if (tid == 0) sbad = 0;
+  for (int e = tid; e < d * d; e += 256) {
+    const int r = e / d, c = e % d;
+    if (c < r) {
+      R[e] = 0.0;
+      if (inv.X != nullptr) inv.X[e] = 0.0;
+    } else if (c > r && inv.X != nullptr) {
+      inv.XT[e] = 0.0;
+    }
+  }
+  double c[kCB / 4];
+#pragma unroll
+  for (int q = 0; q < kCB / 4; ++q) {
+    const int i = 4 * q + g;
+    c[q] = (j < d && i <= j) ? G[static_cast<size_t>(i) * ldg + j] : 0.0;
+  }
+  __syncthreads();  // sbad is set before finish_tile may raise it
+  finish_tile(c, R, d, 0, Kinv, &sbad, rr, x, t, inv);
+  __syncthreads();
+  int32_t mine = 0;
+  for (int k = tid; k < d; k += 256)
+    if (!(rr[k][k] > rtol * sqrt(G[static_cast<size_t>(k) * ldg + k]))) mine = 1;
+  if (mine) atomicOr(&sbad, 1);
+  __syncthreads();
+  if (tid == 0) status[0] = sbad ? 1 : 0;
+}
+
 // One step of the blocked Cholesky after block column K is factored (R_KK
 // and Kinv_K = R_KK^{-1} known).  Block (ti, tj), ti <= tj, of the trailing
 // block triangle, I = K + 1 + ti, J = K + 1 + tj (64-column blocks):
@@ -1350,6 +1391,11 @@ int32_t run_cholesky(const double* G, int64_t ldg, int64_t d, double* R, double*
   int32_t* bad = reinterpret_cast<int32_t*>(gdiag + d);
   const InvOut inv{Rinv, Rinv != nullptr ? RinvT : nullptr};
   const int di = static_cast<int>(d);
+  if (d <= kCB) {
+    hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(256), 0, s, G, ldg, di, R, Kinv, inv, status, rtol);
+    SKLS_CHECK_LAUNCH();
+    return SKLS_OK;
+  }
   const unsigned g = static_cast<unsigned>(div_up(d * d, 256) < 4096 ? div_up(d * d, 256) : 4096);
   hipLaunchKernelGGL(k_copy_upper, dim3(g), dim3(256), 0, s, G, ldg, di, W, R, inv, gdiag, bad);
   SKLS_CHECK_LAUNCH();
