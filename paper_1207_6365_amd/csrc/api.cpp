@@ -1038,13 +1038,16 @@ LearnedRest carve_learned_rest(Arena& ar, int64_t t, int64_t d) {
   return r;
 }
 
-// Most small-Gram splits whose sum k_learned_PE takes in its one block.
-constexpr int kMaxPESplits = 64;
+// The Gram of Y goes straight into the loss for t <= kPEMaxRows, in
+// kPESplits row splits: k_learned_PE sums them in one block, whose reads of
+// the splits bound it, so few long splits beat many short ones there.
+constexpr int64_t kPEMaxRows = 4096;
+constexpr int kPESplits = 4;
 
 // Loss and gradient once the forward sketch Y = S_w A is formed.  At d <= 64
-// (and t <= 64 * kMaxPESplits) the Gram's splits go straight into the loss
-// and E; with the bucket order of the sketch's plan (off, perm) the product
-// 4 Y E and the gather run as one launch as well.
+// (and t <= kPEMaxRows) the Gram's splits go straight into the loss and E;
+// with the bucket order of the sketch's plan (off, perm) the product 4 Y E
+// and the gather run as one launch as well.
 int32_t learned_rest(const skls_matrix& A, const float* C, int64_t t, uint64_t seed, float grad_scale,
                      int32_t accumulate, float* loss, float* grad_w, const LearnedRest& r, const float* Y,
                      hipStream_t s, const int32_t* off = nullptr, const int32_t* perm = nullptr) {
@@ -1052,9 +1055,9 @@ int32_t learned_rest(const skls_matrix& A, const float* C, int64_t t, uint64_t s
   double* P = r.P;
   float* E = r.E;
   float* G = r.G;
-  if (d <= 64 && gram_small_splits(t) <= kMaxPESplits) {
+  if (d <= 64 && t <= kPEMaxRows) {
     int S = 0, pitch = 0;
-    SKLS_TRY(run_gram_small_partials(Y, SKLS_F32, d, t, d, r.gw, r.gb, &S, &pitch, s));
+    SKLS_TRY(run_gram_small_partials(Y, SKLS_F32, d, t, d, kPESplits, r.gw, r.gb, &S, &pitch, s));
     SKLS_TRY(run_learned_PE(r.gw, S, pitch, C, d, E, loss, s));
   } else {
     SKLS_TRY(run_gram(Y, SKLS_F32, d, nullptr, SKLS_F64, t, d, P, r.gw, r.gb, s));

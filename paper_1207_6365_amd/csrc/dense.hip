@@ -1158,11 +1158,12 @@ GramShape gram_shape(int64_t m, int64_t d) {
   return g;
 }
 
-// Splits of the small-Gram kernel: whole chunks of kSK rows, at most 256.
-int small_splits(int64_t m, int64_t& rps) {
+// Splits of the small-Gram kernel: whole chunks of kSK rows, at most cap
+// (<= 256).
+int small_splits(int64_t m, int64_t& rps, int cap = 256) {
   const int64_t mm = m > 0 ? m : 1;
   int64_t x = div_up(mm, kSK);
-  if (x > 256) x = 256;
+  if (x > cap) x = cap;
   rps = div_up(div_up(mm, x), kSK) * kSK;
   return static_cast<int>(div_up(mm, rps));
 }
@@ -1229,9 +1230,9 @@ namespace {
 // The small-Gram launch (d columns of M, d + 1 <= 64 with v, d <= 64
 // without): its splits go to partial.
 int32_t launch_gram_small(const void* M, int32_t dtype, int64_t ld, const void* v, int v_f64, int64_t m, int64_t d,
-                          double* partial, int* splits, hipStream_t s) {
+                          double* partial, int* splits, hipStream_t s, int cap = 256) {
   int64_t rps;
-  const int S = small_splits(m, rps);
+  const int S = small_splits(m, rps, cap);
   const int dp = static_cast<int>(v != nullptr ? d + 1 : d);  // columns of the product
   auto launch = [&](auto tag) -> int32_t {
     using TI = decltype(tag);
@@ -1263,15 +1264,10 @@ int32_t launch_gram_small(const void* M, int32_t dtype, int64_t ld, const void* 
 
 }  // namespace
 
-int gram_small_splits(int64_t m) {
-  int64_t rps;
-  return small_splits(m, rps);
-}
-
-int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_t m, int64_t d, void* ws,
-                                size_t ws_bytes, int* splits, int* pitch, hipStream_t s) {
-  if (d < 1 || d > 64) {
-    set_error("small Gram: need 1 <= d <= 64");
+int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_t m, int64_t d, int max_splits,
+                                void* ws, size_t ws_bytes, int* splits, int* pitch, hipStream_t s) {
+  if (d < 1 || d > 64 || max_splits < 1 || max_splits > 256) {
+    set_error("small Gram: need 1 <= d <= 64 and 1 <= max_splits <= 256");
     return SKLS_ERR_SHAPE;
   }
   if (ws == nullptr || ws_bytes < gram_bytes(gram_shape(m, d), m, d)) {
@@ -1280,7 +1276,7 @@ int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_
   }
   *pitch = kGT;
   PhaseTimer pt("gram", s);
-  return launch_gram_small(M, dtype, ld, nullptr, 0, m, d, static_cast<double*>(ws), splits, s);
+  return launch_gram_small(M, dtype, ld, nullptr, 0, m, d, static_cast<double*>(ws), splits, s, max_splits);
 }
 
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,

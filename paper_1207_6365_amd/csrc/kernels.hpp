@@ -49,13 +49,12 @@ int32_t check_sketch_args(const skls_matrix* A, const void* b, int32_t b_dtype, 
 size_t gram_ws_bytes(int64_t m, int64_t dd);
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,
                  double* G /* dd x dd */, void* ws, size_t ws_bytes, hipStream_t s);
-// The row splits of M^T M for d <= 64 (no v), without their sum: split k at
-// partial + k * pitch * pitch, entry (i, j), i <= j < d, at i * pitch + j.
-// ws as for run_gram (gram_ws_bytes(m, d) bytes); *splits = their number.
-// Number of splits run_gram_small_partials makes for m rows.
-int gram_small_splits(int64_t m);
-int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_t m, int64_t d, void* ws,
-                                size_t ws_bytes, int* splits, int* pitch, hipStream_t s);
+// The row splits of M^T M for d <= 64 (no v), at most max_splits (<= 256) of
+// whole 64-row chunks, without their sum: split k at partial + k * pitch *
+// pitch, entry (i, j), i <= j < d, at i * pitch + j.  ws as for run_gram
+// (gram_ws_bytes(m, d) bytes); *splits = their number.
+int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_t m, int64_t d, int max_splits,
+                                void* ws, size_t ws_bytes, int* splits, int* pitch, hipStream_t s);
 // Cholesky of the leading d x d block of G (leading dimension ldg): R upper,
 // status[0] = 0 ok / 1 rank deficient.  With Rinv and RinvT (d x d each, or
 // both NULL) it also forms R^{-1} and R^{-T} within the same launches.

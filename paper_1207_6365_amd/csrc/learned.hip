@@ -86,29 +86,60 @@ __global__ __launch_bounds__(256) void k_learned_G(const float* __restrict__ Y, 
 
 // P = the sum of the S row splits of Y^T Y (entries i <= j of split k at
 // partial + k * pitch^2 + i * pitch + j), E = P - C in both triangles
-// (float32) and loss = ||E||_F^2, in one block.  Entries (i, j) and (j, i)
-// sum the same values in the same order, so E is as symmetric as C.
+// (float32) and loss = ||E||_F^2, in one block of 1024 threads (d <= 64, so
+// at most four entries per thread).  Only entries i <= j read the splits,
+// along the rows of the partial tile (the lower entries would read it down
+// its columns, one cache line per lane); each writes E[i][j] and E[j][i].  A
+// thread's entries read their splits together, eight splits at a time.
 __global__ __launch_bounds__(1024) void k_learned_PE(const double* __restrict__ partial, int S, int pitch,
                                                      const float* __restrict__ C, int d, float* __restrict__ E,
                                                      float* __restrict__ loss) {
+  constexpr int kU = 4, kK = 8;
   __shared__ double scratch[16];
   const size_t stride = static_cast<size_t>(pitch) * pitch;
-  double s = 0.0;
-  for (int idx = threadIdx.x; idx < d * d; idx += blockDim.x) {
-    const int i = idx / d, j = idx % d;
-    const int lo = i < j ? i : j, hi = i < j ? j : i;
-    const double* src = partial + static_cast<size_t>(lo) * pitch + hi;
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    int k = 0;
-    for (; k + 4 <= S; k += 4) {
+  const int n = d * d;
+  const double* src[kU];
+  int ii[kU], jj[kU];
+  bool act[kU];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] += src[(k + u) * stride];
-    }
-    for (int u = 0; k < S; ++k, ++u) a[u] += src[k * stride];
-    const double e = ((a[0] + a[1]) + (a[2] + a[3])) - static_cast<double>(C[idx]);
-    E[idx] = static_cast<float>(e);
-    s += e * e;
+  for (int u = 0; u < kU; ++u) {
+    const int idx = static_cast<int>(threadIdx.x) + u * 1024;
+    ii[u] = idx / d;
+    jj[u] = idx % d;
+    act[u] = idx < n && ii[u] <= jj[u];
+    // idle lanes read entry (0, 0), one line for all of them
+    src[u] = partial + (act[u] ? static_cast<size_t>(ii[u]) * pitch + jj[u] : 0);
   }
+  double a[kU] = {0.0, 0.0, 0.0, 0.0};
+  int k = 0;
+  for (; k + kK <= S; k += kK) {
+    double x[kK][kU];
+#pragma unroll
+    for (int kk = 0; kk < kK; ++kk)
+#pragma unroll
+      for (int u = 0; u < kU; ++u) x[kk][u] = src[u][(k + kk) * stride];
+#pragma unroll
+    for (int kk = 0; kk < kK; ++kk)
+#pragma unroll
+      for (int u = 0; u < kU; ++u) a[u] += x[kk][u];
+  }
+  for (; k < S; ++k)
+#pragma unroll
+    for (int u = 0; u < kU; ++u) a[u] += src[u][k * stride];
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kU; ++u)
+    if (act[u]) {
+      const int i = ii[u], j = jj[u];
+      const double e = a[u] - static_cast<double>(C[i * d + j]);
+      E[i * d + j] = static_cast<float>(e);
+      s += e * e;
+      if (i != j) {
+        const double f = a[u] - static_cast<double>(C[j * d + i]);
+        E[j * d + i] = static_cast<float>(f);
+        s += f * f;
+      }
+    }
   s = block_sum(s, scratch);
   if (threadIdx.x == 0) *loss = static_cast<float>(s);
 }
