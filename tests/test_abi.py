@@ -88,6 +88,40 @@ def test_workspace_sizes(lib):
     assert lib.skls_qr_r_workspace(10, 20, ctypes.byref(sz)) == 2
 
 
+def test_learned_batch_workspace_and_argument_checks(lib):
+    # every check below fails before any device call
+    from paper_1207_6365_amd import _lib as L
+
+    sz = ctypes.c_size_t(0)
+    A = _mat(n=32768, d=64, ld=64)
+    assert lib.skls_learned_batch_workspace(ctypes.byref(A), 1024, ctypes.byref(sz)) == 0
+    # four lanes, each with Y = S_w A (t x d floats), plus four gradient slots
+    assert sz.value >= 4 * 1024 * 64 * 4 + 4 * 32768 * 4
+    assert lib.skls_learned_batch_workspace(ctypes.byref(A), 0, ctypes.byref(sz)) == 2
+    desc = L.SklsSketchPlanDesc()
+    desc.n, desc.d, desc.t, desc.layout, desc.out_dtype = 32768, 64, 1024, 0, 1
+    mats = (L.SklsMatrix * 2)(A, A)
+    cps = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    args = (ctypes.byref(desc), 0x1000, 1 << 20, 0x1000, 0, 0x1000, 0x1000, 0x1000, 1 << 30, None)
+    assert lib.skls_learned_grad_batch(0, mats, cps, None, *args) == 1  # count 0
+    assert lib.skls_learned_grad_batch(2, mats, None, None, *args) == 1  # no targets
+    desc.n = 1000  # the plan is for another shape
+    assert lib.skls_learned_grad_batch(2, mats, cps, None, *args) == 2
+    assert b"plan" in lib.skls_last_error()
+    desc.n = 32768
+    bf = (L.SklsMatrix * 1)(_mat(n=32768, d=64, ld=64, dtype=2))  # bfloat16 A
+    assert lib.skls_learned_grad_batch(1, bf, cps, None, *args) == 3
+
+
+def test_learned_batch_binding_checks_lists():
+    import paper_1207_6365_amd.api as api
+
+    with pytest.raises(ValueError):
+        api.learned_grad_batch([], [], None, None, None)
+    with pytest.raises(ValueError):
+        api.learned_grad_batch([object()], [], None, None, None)
+
+
 def test_low_rank_workspace_checks_options(lib):
     from paper_1207_6365_amd import _lib as L
 
