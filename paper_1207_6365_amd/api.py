@@ -432,7 +432,7 @@ def learned_grad_batch(mats, grams, plan: SketchPlan, w: torch.Tensor, grad: tor
     descs = [_matrix(A) for A in mats]
     device = descs[0][1]
     m0 = descs[0][0]
-    if ws is None or ws.key != (m0.n, m0.d, plan.desc.t):
+    if not isinstance(ws, LearnedBatchWorkspace) or ws.key != (m0.n, m0.d, plan.desc.t):
         ws = LearnedBatchWorkspace(mats[0], plan.desc.t)
     loss = torch.empty(count, dtype=torch.float32, device=device) if loss is None else loss
     if loss.numel() < count or loss.dtype != torch.float32:

@@ -42,14 +42,15 @@ def shared_plan(A: torch.Tensor, t: int, seed: int) -> api.SketchPlan:
 
 
 def prepare(mats: list[torch.Tensor], t: int, seed: int, plan: api.SketchPlan | None = None):
-    """Gram matrices and normalisers ``||A^T A||_F^2`` (the loss at ``w = 0``)."""
+    """Gram matrices, normalisers ``||A^T A||_F^2`` (the loss at ``w = 0``)
+    and a workspace for batched calls at this shape."""
     n = mats[0].shape[0]
     dev = mats[0].device
-    ws = api.LearnedWorkspace(mats[0], t)
+    ws = api.LearnedBatchWorkspace(mats[0], t)
     plan = shared_plan(mats[0], t, seed) if plan is None else plan
     zero = torch.zeros(n, dtype=torch.float32, device=dev)
     grams = [api.gram(A) for A in mats]
-    loss, _ = api.learned_grad_batch(mats, grams, plan, zero, None)
+    loss, _ = api.learned_grad_batch(mats, grams, plan, zero, None, ws=ws)
     norms = [float(x) for x in loss.cpu().numpy()]
     return grams, norms, ws
 
@@ -58,8 +59,7 @@ def distortions(mats, grams, norms, t: int, seed: int, w: torch.Tensor, ws=None,
                 plan: api.SketchPlan | None = None) -> np.ndarray:
     """Normalised distortion of each matrix for values ``w``."""
     plan = shared_plan(mats[0], t, seed) if plan is None else plan
-    loss, _ = api.learned_grad_batch(mats, grams, plan, w, None, ws=ws if isinstance(ws, api.LearnedBatchWorkspace)
-                                     else None)
+    loss, _ = api.learned_grad_batch(mats, grams, plan, w, None, ws=ws)
     return loss.cpu().numpy().astype(np.float64) / np.asarray(norms, dtype=np.float64)
 
 
@@ -68,14 +68,13 @@ def train(train_mats, val_mats, t: int, seed: int, steps: int = 300, lr: float =
     n = train_mats[0].shape[0]
     dev = train_mats[0].device
     plan = shared_plan(train_mats[0], t, seed)
-    grams, norms, ws = prepare(train_mats, t, seed, plan)
+    grams, norms, bws = prepare(train_mats, t, seed, plan)
     vgrams, vnorms, _ = prepare(val_mats, t, seed, plan)
     w = signs(n, t, seed, dev)
     w_plain = w.clone()
     m = torch.zeros_like(w)
     v = torch.zeros_like(w)
     g = torch.empty_like(w)
-    bws = api.LearnedBatchWorkspace(train_mats[0], t)
     rng = np.random.default_rng(rng_seed)
     hist = []
     bsz = min(batch, len(train_mats))
