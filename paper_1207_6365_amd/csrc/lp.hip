@@ -564,6 +564,9 @@ int32_t weighted_ls(const LpWs& w, int64_t ns, int64_t d, const double* cw, doub
   return run_solve_from_gram(w.Rinv, w.RinvT, w.G + d * (d + 1), d, x, w.tmpd, s);
 }
 
+int32_t irls_ahead(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, double tol, double f0, double eta0,
+                   double emin, Fit& out, hipStream_t s);
+
 int32_t fit_irls(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, double tol, Fit& out,
                  hipStream_t s) {
   int32_t bad = 0;
@@ -583,6 +586,7 @@ int32_t fit_irls(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, d
   }
   double eta = f1 / static_cast<double>(ns);
   const double emin = 1e-9 * eta;
+  if (p < 2.0) return irls_ahead(w, ns, d, p, max_iter, tol, f, eta, emin, out, s);
   double* r = w.r;
   double* rt = w.rt;
   for (int it = 0; it < max_iter; ++it) {
@@ -764,6 +768,89 @@ int32_t fit_l1(const LpWs& w, int64_t ns, int64_t d, int max_iter, double tol, F
     SKLS_TRY(gap(k ^ 1));
     if (it + 1 < max_iter) SKLS_TRY(step(it + 1));
   }
+  SKLS_TRY_HIP(hipStreamSynchronize(s));
+  return SKLS_OK;
+}
+
+// IRLS for 1 < p < 2 from the least-squares start (x_0 = w.x, r_0 = w.r,
+// objective f0), with each iteration's objective and factor status read one
+// iteration late.  Below p = 2 the step is taken in full, and the weights of
+// the next iteration need only the residual on the device and eta, whose
+// schedule is fixed.  So iteration k + 1 is enqueued before iteration k's
+// result is read, and the host's round trip hides behind it.  Iterates live
+// in a ring of three: x_{k+1} may already be enqueued when a broken factor in
+// step k makes x_{k-1} the answer.  Residuals live in a ring of two.  The
+// iterates, decisions and result are those of the plain loop in fit_irls.
+int32_t irls_ahead(const LpWs& w, int64_t ns, int64_t d, double p, int max_iter, double tol, double f0, double eta0,
+                   double emin, Fit& out, hipStream_t s) {
+  GapSlots* hs = gap_slots();
+  if (hs == nullptr) {
+    set_error("lp_regression: no pinned host memory for the objective reads");
+    return SKLS_ERR_DEVICE;
+  }
+  GapSlots* dg = nullptr;  // the same memory as the device addresses it
+  SKLS_TRY_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&dg), hs, 0));
+  hipEvent_t ev[2];
+  SKLS_TRY_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    set_error("lp_regression: hipEventCreate failed");
+    return SKLS_ERR_DEVICE;
+  }
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      (void)hipEventDestroy(e[0]);
+      (void)hipEventDestroy(e[1]);
+    }
+  } guard{ev};
+  double* X[3] = {w.x, w.xt, w.dx};  // x_k in X[k % 3] (dx is free outside the interior point)
+  double* Rr[2] = {w.r, w.rt};        // r_k in Rr[k % 2]
+  // eta of iteration k >= 1: eta0, then a quarter of the last, floored at emin
+  auto eta_of = [&](int k) {
+    double e = eta0;
+    for (int i = 1; i < k; ++i) e = std::max(emin, e * 0.25);
+    return e;
+  };
+  // iteration k from x_{k-1} and r_{k-1}: its objective and factor status go
+  // to pinned slot k % 2
+  auto iter = [&](int k) -> int32_t {
+    hipLaunchKernelGGL(k_irls_weights, dim3(g_rows(ns)), dim3(kT), 0, s, ns, Rr[(k - 1) & 1], eta_of(k),
+                       (p - 2.0) / 2.0, w.cw);
+    SKLS_CHECK_LAUNCH();
+    SKLS_TRY(weighted_ls(w, ns, d, w.cw, w.xn, nullptr, s));
+    hipLaunchKernelGGL(k_vlerp, dim3(g_rows(d)), dim3(kT), 0, s, d, X[(k - 1) % 3], w.xn, 1.0, X[k % 3]);
+    SKLS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_resid_rows, dim3(kResBlocks), dim3(kT), 0, s, ns, d, w.Ms, X[k % 3], w.ys, Rr[k & 1], p,
+                       w.part);
+    SKLS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_gap_publish, dim3(1), dim3(kT), 0, s, w.part, kResBlocks, w.dev + 8, w.status,
+                       dg->g[k & 1], &dg->st[k & 1]);
+    SKLS_CHECK_LAUNCH();
+    SKLS_TRY_HIP(hipEventRecord(ev[k & 1], s));
+    return SKLS_OK;
+  };
+  double f = f0;
+  int result = 0;
+  if (max_iter > 0) SKLS_TRY(iter(1));
+  for (int k = 1; k <= max_iter; ++k) {
+    if (k + 1 <= max_iter) SKLS_TRY(iter(k + 1));  // ahead of the decision on k
+    SKLS_TRY_HIP(hipEventSynchronize(ev[k & 1]));
+    const double fk = hs->g[k & 1][0];
+    if (hs->st[k & 1]) break;  // the factor of step k broke down: keep x_{k-1}
+    const bool done = eta_of(k) <= emin && std::fabs(f - fk) <= tol * f;
+    f = fk;
+    result = k;
+    out.iters = k + 1;
+    if (done) {
+      out.converged = true;
+      break;
+    }
+  }
+  // x_result is intact: the iterations enqueued after it wrote the other slots
+  if (result % 3 != 0)
+    SKLS_TRY_HIP(hipMemcpyAsync(w.x, X[result % 3], sizeof(double) * d, hipMemcpyDeviceToDevice, s));
+  out.obj = f;
   SKLS_TRY_HIP(hipStreamSynchronize(s));
   return SKLS_OK;
 }
