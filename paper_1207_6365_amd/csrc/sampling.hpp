@@ -59,29 +59,59 @@ __global__ __launch_bounds__(kT) void k_gemm(int64_t M, int64_t N, int64_t K, in
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
-  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
-    __syncthreads();
+  // Each chunk of 16 inner indices is fetched into registers while the
+  // previous one is multiplied.  Loads are unconditional (an index outside
+  // the matrix reads element 0 and the value is masked afterwards), so all
+  // loads of a chunk are in flight together.
+  constexpr int RA = 16 * TM / kT, RB = 16 * TN / kT;
+  double ra[RA], rb[RB];
+  auto a_at = [&](int r, int& kk, int& c) {
+    const int e = tid + r * kT;
+    if (TA) {
+      c = e % TM;
+      kk = e / TM;
+    } else {
+      kk = e & 15;
+      c = e >> 4;
+    }
+  };
+  auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int r = 0; r < 16 * TM / kT; ++r) {
-      const int e = tid + r * kT;
-      if (TA) {
-        const int c = e % TM, kk = e / TM;
-        const int64_t gi = i0 + c, gk = k0 + kk;
-        As[kk][c] = (gi < M && gk < ke) ? load_as<double>(A, static_cast<size_t>(gk * lda + gi)) : 0.0;
-      } else {
-        const int kk = e & 15, c = e >> 4;
-        const int64_t gi = i0 + c, gk = k0 + kk;
-        As[kk][c] = (gi < M && gk < ke) ? load_as<double>(A, static_cast<size_t>(gi * lda + gk)) : 0.0;
-      }
+    for (int r = 0; r < RA; ++r) {
+      int kk, c;
+      a_at(r, kk, c);
+      const int64_t gi = i0 + c, gk = k0 + kk;
+      const bool in = gi < M && gk < ke;
+      const size_t idx = in ? static_cast<size_t>(TA ? gk * lda + gi : gi * lda + gk) : 0;
+      const double x = load_as<double>(A, idx);
+      ra[r] = in ? x : 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < 16 * TN / kT; ++r) {
+    for (int r = 0; r < RB; ++r) {
       const int e = tid + r * kT;
       const int c = e % TN, kk = e / TN;
       const int64_t gj = j0 + c, gk = k0 + kk;
-      Bs[kk][c] = (gj < N && gk < ke) ? B[gk * ldb + gj] : 0.0;
+      const bool in = gj < N && gk < ke;
+      const double x = B[in ? gk * ldb + gj : 0];
+      rb[r] = in ? x : 0.0;
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+    __syncthreads();  // the previous chunk's products are done with the tiles
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      int kk, c;
+      a_at(r, kk, c);
+      As[kk][c] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int e = tid + r * kT;
+      Bs[e / TN][e % TN] = rb[r];
     }
     __syncthreads();
+    if (k0 + 16 < ke) fetch(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
       const double a0 = As[kk + lr][wi * 32 + lc], a1 = As[kk + lr][wi * 32 + 16 + lc];
