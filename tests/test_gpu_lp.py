@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 # relative tolerance of a weighted fit's objective against the exact optimum:
 # the IPM stops at a duality gap of 1e-12 of the objective and the oracle's LP
 # solver at feasibility 1e-10; IRLS stops once the objective moves by 1e-12
-FIT_TOL = {1.0: 1e-8, 1.5: 1e-9, 2.0: 1e-12, 3.0: 1e-9}
+FIT_TOL = {1.0: 1e-8, 1.2: 1e-9, 1.5: 1e-9, 2.0: 1e-12, 3.0: 1e-9}
 
 
 @pytest.fixture(scope="module")
@@ -77,7 +77,7 @@ def _check(got, ref, op, b, p, seed, x_unique=True):
     return full
 
 
-@pytest.mark.parametrize("p", [1.0, 1.5, 2.0, 3.0])
+@pytest.mark.parametrize("p", [1.0, 1.2, 1.5, 2.0, 3.0])
 def test_dense_matches_oracle(sk, p):
     A, b, _ = W.lp_dense(n=4000, d=8)
     seed, kw = 0x1234 + int(10 * p), dict(q=64, v=8, a=2, s1=400.0, s2=400.0)
