@@ -426,12 +426,16 @@ SKLS_API int32_t skls_learned_grad_planned(const skls_matrix* A, const float* C,
  * skls_learned_grad_planned:
  *   loss[j] = ||E_j||_F^2 of matrix j (raw, unweighted),
  *   grad_w  = sum_j scale[j] * dloss_j/dw   (accumulate = 0), or += it.
- * The matrices' chains of launches run on up to four streams at once (the
- * caller's and three of the library's, default priority), forked from and
- * joined back to `stream`; matrix j adds its weighted gradient into the slot
- * of lane j mod 4, and the slots are summed in lane order at the end.  The
- * result is the same from run to run; it may differ in the last bits from a
- * sequence of skls_learned_grad_planned calls, which add in matrix order.
+ * At d <= 64 and t <= 4096 with a dense SORTED plan each step is one launch
+ * over up to 16 matrices at a time (sketches, Gram, losses, the gradient of
+ * each matrix into a slot of its own, the sum of the slots in matrix order).
+ * Otherwise the matrices' chains of launches run on up to four streams at
+ * once (the caller's and three of the library's, default priority), forked
+ * from and joined back to `stream`; matrix j adds its weighted gradient into
+ * the slot of lane j mod 4, and the slots are summed in lane order at the
+ * end.  Either way the result is the same from run to run; it may differ in
+ * the last bits from a sequence of skls_learned_grad_planned calls, which add
+ * in matrix order.
  *  count:  number of matrices, >= 1.
  *  A:      host array of count dense float32 matrix descriptors of the
  *          plan's shape (each with its own ld).

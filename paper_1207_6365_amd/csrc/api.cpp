@@ -1175,6 +1175,33 @@ struct BatchLanes {
   float* slots;  // kLanes gradient slots of n floats, one after another
 };
 
+// The other use of the batch workspace, when every step has a one-launch
+// form (d <= 64, t <= kPEMaxRows, a dense sorted plan): up to kSortedMany
+// matrices at a time, each with its sketch, Gram splits, E and gradient slot.
+struct BatchMany {
+  float* Y;
+  int64_t ystride;
+  double* partial;
+  int64_t pstride;
+  float* E;
+  float* slots;
+  int64_t gstride;
+};
+
+bool many_applies(int64_t d, int64_t t) { return d <= 64 && t <= kPEMaxRows; }
+
+BatchMany carve_many(Arena& ar, int64_t n, int64_t t, int64_t d) {
+  BatchMany b;
+  b.ystride = div_up(t * d, 64) * 64;
+  b.pstride = static_cast<int64_t>(kPESplits) * gram_small_split_doubles();
+  b.gstride = div_up(n, 64) * 64;
+  b.Y = ar.take<float>(static_cast<size_t>(kSortedMany * b.ystride));
+  b.partial = ar.take<double>(static_cast<size_t>(kSortedMany * b.pstride));
+  b.E = ar.take<float>(static_cast<size_t>(kSortedMany * d * d));
+  b.slots = ar.take<float>(static_cast<size_t>(kSortedMany * b.gstride));
+  return b;
+}
+
 BatchLanes carve_batch(Arena& ar, int64_t n, int64_t t, int64_t d) {
   BatchLanes b;
   for (int k = 0; k < kLanes; ++k) {
@@ -1197,7 +1224,13 @@ int32_t skls_learned_batch_workspace(const skls_matrix* A, int64_t t, size_t* by
   }
   Arena ar(nullptr, 0);
   carve_batch(ar, A->n, t, A->d);
-  *bytes = ar.used;
+  size_t need = ar.used;
+  if (many_applies(A->d, t)) {
+    Arena am(nullptr, 0);
+    carve_many(am, A->n, t, A->d);
+    need = am.used > need ? am.used : need;
+  }
+  *bytes = need;
   return SKLS_OK;
 }
 
@@ -1225,11 +1258,43 @@ int32_t skls_learned_grad_batch(int32_t count, const skls_matrix* A, const float
   }
   const int64_t t = desc->t, d = A[0].d, n = A[0].n;
   hipStream_t s = as_stream(stream);
+  const int32_t *off = nullptr, *perm = nullptr;
+  SKLS_TRY(sorted_plan_order(A[0], t, desc->variant, SKLS_F32, plan, plan_bytes, &off, &perm));
+  if (off != nullptr && many_applies(d, t)) {
+    // every step as one launch over up to kSortedMany matrices: the sketches,
+    // the Gram splits, E and the losses, 4 Y E with the gather into one slot
+    // per matrix, and the sum of the slots
+    Arena am(ws, ws_bytes);
+    const BatchMany b = carve_many(am, n, t, d);
+    SKLS_TRY(need_ws(am, ws, ws_bytes));
+    for (int32_t g0 = 0; g0 < count; g0 += kSortedMany) {
+      const int cnt = count - g0 < kSortedMany ? count - g0 : kSortedMany;
+      LearnedMany args{};
+      bool vec = true;
+      for (int j = 0; j < cnt; ++j) {
+        const skls_matrix& M = A[g0 + j];
+        args.A[j] = static_cast<const float*>(M.val);
+        args.ld[j] = M.ld;
+        args.C[j] = C[g0 + j];
+        args.scale[j] = scale != nullptr ? scale[g0 + j] : 1.0f;
+        vec = vec && reinterpret_cast<uintptr_t>(M.val) % 16 == 0 && M.ld % 4 == 0 && M.d % 4 == 0;
+      }
+      SKLS_TRY(apply_sorted_many(A + g0, cnt, t, plain_key(desc->seed), w, plan, plan_bytes, b.Y, b.ystride, s));
+      int S = 0, pitch = 0;
+      SKLS_TRY(run_gram_small_partials_many(b.Y, cnt, b.ystride, t, d, kPESplits, b.partial, b.pstride, &S, &pitch,
+                                            s));
+      SKLS_TRY(run_learned_PE_many(b.partial, b.pstride, S, pitch, args, cnt, d, b.E, loss + g0, s));
+      if (grad_w != nullptr) {
+        SKLS_TRY(run_learned_G_gather_many(b.Y, b.ystride, b.E, t, d, off, perm, args, cnt, vec, b.slots, b.gstride,
+                                           s));
+        SKLS_TRY(run_sum_slots(n, b.slots, b.gstride, cnt, 1.0f, accumulate != 0 || g0 > 0, grad_w, s));
+      }
+    }
+    return SKLS_OK;
+  }
   Arena ar(ws, ws_bytes);
   const BatchLanes b = carve_batch(ar, n, t, d);
   SKLS_TRY(need_ws(ar, ws, ws_bytes));
-  const int32_t *off = nullptr, *perm = nullptr;
-  SKLS_TRY(sorted_plan_order(A[0], t, desc->variant, SKLS_F32, plan, plan_bytes, &off, &perm));
   const int lanes = count < kLanes ? count : kLanes;
   LanePool* pool = nullptr;
   hipStream_t st[kLanes] = {s, s, s, s};

@@ -256,9 +256,14 @@ constexpr int kSL = kSK * 64 / 4 / kGThreads;  // 4-wide loads per thread per ch
 template <typename TI, bool VEC, bool WITHV>
 __global__ __launch_bounds__(kGThreads) void k_gram_small(const TI* __restrict__ M, int64_t ld,
                                                           const void* __restrict__ v, int v_f64, int64_t m, int d,
-                                                          int64_t rows_per_split, double* __restrict__ partial) {
+                                                          int64_t rows_per_split, double* __restrict__ partial,
+                                                          int64_t mstride, int64_t pstride) {
   // WITHV: the product is [M | v] with v as column dm = d - 1 (v in the
-  // staging precision: float64 with float64 M, float32 otherwise)
+  // staging precision: float64 with float64 M, float32 otherwise).  Several
+  // matrices of one shape: matrix blockIdx.y at M + y * mstride, its splits
+  // at partial + y * pstride.
+  M += static_cast<int64_t>(blockIdx.y) * mstride;
+  partial += static_cast<int64_t>(blockIdx.y) * pstride;
   const int dm = WITHV ? d - 1 : d;
   using TS = GStage<TI>;
   constexpr size_t kStage = 2 * kSK * 64 * sizeof(TS);
@@ -1230,25 +1235,31 @@ namespace {
 // The small-Gram launch (d columns of M, d + 1 <= 64 with v, d <= 64
 // without): its splits go to partial.
 int32_t launch_gram_small(const void* M, int32_t dtype, int64_t ld, const void* v, int v_f64, int64_t m, int64_t d,
-                          double* partial, int* splits, hipStream_t s, int cap = 256) {
+                          double* partial, int* splits, hipStream_t s, int cap = 256, int count = 1,
+                          int64_t mstride = 0, int64_t pstride = 0) {
   int64_t rps;
   const int S = small_splits(m, rps, cap);
   const int dp = static_cast<int>(v != nullptr ? d + 1 : d);  // columns of the product
   auto launch = [&](auto tag) -> int32_t {
     using TI = decltype(tag);
     const TI* Mt = static_cast<const TI*>(M);
-    const bool vec = (reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * sizeof(TI)) % 16 == 0) && (d % 4 == 0);
-    const dim3 g(S), b(kGThreads);
+    const bool vec = (reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * sizeof(TI)) % 16 == 0) && (d % 4 == 0) &&
+                     ((mstride * static_cast<int64_t>(sizeof(TI))) % 16 == 0);
+    const dim3 g(S, count), b(kGThreads);
     if (v != nullptr) {
       if (vec)
-        hipLaunchKernelGGL((k_gram_small<TI, true, true>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial);
+        hipLaunchKernelGGL((k_gram_small<TI, true, true>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial,
+                           mstride, pstride);
       else
-        hipLaunchKernelGGL((k_gram_small<TI, false, true>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial);
+        hipLaunchKernelGGL((k_gram_small<TI, false, true>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial,
+                           mstride, pstride);
     } else {
       if (vec)
-        hipLaunchKernelGGL((k_gram_small<TI, true, false>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial);
+        hipLaunchKernelGGL((k_gram_small<TI, true, false>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial,
+                           mstride, pstride);
       else
-        hipLaunchKernelGGL((k_gram_small<TI, false, false>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial);
+        hipLaunchKernelGGL((k_gram_small<TI, false, false>), g, b, 0, s, Mt, ld, v, v_f64, m, dp, rps, partial,
+                           mstride, pstride);
     }
     SKLS_CHECK_LAUNCH();
     return SKLS_OK;
@@ -1277,6 +1288,23 @@ int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_
   *pitch = kGT;
   PhaseTimer pt("gram", s);
   return launch_gram_small(M, dtype, ld, nullptr, 0, m, d, static_cast<double*>(ws), splits, s, max_splits);
+}
+
+int64_t gram_small_split_doubles() { return static_cast<int64_t>(kGT) * kGT; }
+
+int32_t run_gram_small_partials_many(const float* M, int count, int64_t mstride, int64_t m, int64_t d,
+                                     int max_splits, double* partial, int64_t pstride, int* splits, int* pitch,
+                                     hipStream_t s) {
+  int64_t rps;
+  if (d < 1 || d > 64 || count < 1 || max_splits < 1 || max_splits > 256 ||
+      pstride < static_cast<int64_t>(small_splits(m, rps, max_splits)) * kGT * kGT) {
+    set_error("small Gram of several matrices: bad shape or split room");
+    return SKLS_ERR_SHAPE;
+  }
+  *pitch = kGT;
+  PhaseTimer pt("gram", s);
+  return launch_gram_small(M, SKLS_F32, d, nullptr, 0, m, d, partial, splits, s, max_splits, count, mstride,
+                           pstride);
 }
 
 int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_t v_dtype, int64_t m, int64_t d,

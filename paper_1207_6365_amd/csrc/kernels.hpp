@@ -40,6 +40,12 @@ int32_t apply_sketch_plan(const skls_matrix& A, const void* b, int32_t b_dtype, 
 // another variant or layout.
 int32_t sorted_plan_order(const skls_matrix& A, int64_t t, int32_t resolved, int32_t out_dtype, const void* plan,
                           size_t plan_bytes, const int32_t** off, const int32_t** perm);
+// The apply of a dense SORTED plan (float32 output, no b) to up to
+// kSortedMany dense float32 matrices of one shape in one launch: matrix j's
+// sketch goes to SA + j * sa_stride.
+constexpr int kSortedMany = 16;
+int32_t apply_sorted_many(const skls_matrix* A, int count, int64_t t, HashKey key, const float* w, const void* plan,
+                          size_t plan_bytes, float* SA, int64_t sa_stride, hipStream_t s);
 // Argument checks shared by the sketch entry points (api.cpp).
 int32_t check_sketch_args(const skls_matrix* A, const void* b, int32_t b_dtype, int64_t t, int32_t variant,
                           const void* SA, const void* Sb, int32_t out_dtype);
@@ -55,6 +61,13 @@ int32_t run_gram(const void* M, int32_t dtype, int64_t ld, const void* v, int32_
 // (gram_ws_bytes(m, d) bytes); *splits = their number.
 int32_t run_gram_small_partials(const void* M, int32_t dtype, int64_t ld, int64_t m, int64_t d, int max_splits,
                                 void* ws, size_t ws_bytes, int* splits, int* pitch, hipStream_t s);
+// The same for `count` float32 matrices of one shape (m x d, leading dimension
+// d) at M + j * mstride, their splits at partial + j * pstride (at least
+// max_splits * gram_small_split_doubles() doubles apart), in one launch.
+int64_t gram_small_split_doubles();
+int32_t run_gram_small_partials_many(const float* M, int count, int64_t mstride, int64_t m, int64_t d,
+                                     int max_splits, double* partial, int64_t pstride, int* splits, int* pitch,
+                                     hipStream_t s);
 // Cholesky of the leading d x d block of G (leading dimension ldg): R upper,
 // status[0] = 0 ok / 1 rank deficient.  With Rinv and RinvT (d x d each, or
 // both NULL) it also forms R^{-1} and R^{-T} within the same launches.
@@ -158,6 +171,24 @@ int32_t run_learned_PE(const double* partial, int S, int pitch, const float* C, 
 // dense SORTED plan (sorted_plan_order); d <= 64.
 int32_t run_learned_G_gather(const float* Y, const float* E, int64_t t, const int32_t* off, const int32_t* perm,
                              const skls_matrix& A, float scale, bool accumulate, float* grad, hipStream_t s);
+// Per-matrix arguments of the learned kernels that take several matrices of
+// one shape at once (up to kSortedMany).
+struct LearnedMany {
+  const float* A[kSortedMany];
+  int64_t ld[kSortedMany];
+  const float* C[kSortedMany];
+  float scale[kSortedMany];
+};
+// Loss and E of each of `count` matrices from its small-Gram splits (block j:
+// splits at partial + j * pstride, E + j d^2, loss[j]).
+int32_t run_learned_PE_many(const double* partial, int64_t pstride, int S, int pitch, const LearnedMany& args,
+                            int count, int64_t d, float* E, float* loss, hipStream_t s);
+// 4 Y E and the gather for each of `count` matrices (sketch at Y + j * ystride,
+// E + j d^2), matrix j's weighted gradient written to grad + j * gstride;
+// vec: every A is 16-byte aligned with ld and d multiples of 4.
+int32_t run_learned_G_gather_many(const float* Y, int64_t ystride, const float* E, int64_t t, int64_t d,
+                                  const int32_t* off, const int32_t* perm, const LearnedMany& args, int count,
+                                  bool vec, float* grad, int64_t gstride, hipStream_t s);
 int32_t run_sum_slots(int64_t n, const float* slots, int64_t stride, int k, float scale, bool accumulate,
                       float* grad, hipStream_t s);
 int32_t run_adam(int64_t n, float* w, const float* g, float* m, float* v, int32_t step, float lr, float b1,

@@ -91,9 +91,9 @@ __global__ __launch_bounds__(256) void k_learned_G(const float* __restrict__ Y, 
 // along the rows of the partial tile (the lower entries would read it down
 // its columns, one cache line per lane); each writes E[i][j] and E[j][i].  A
 // thread's entries read their splits together, eight splits at a time.
-__global__ __launch_bounds__(1024) void k_learned_PE(const double* __restrict__ partial, int S, int pitch,
-                                                     const float* __restrict__ C, int d, float* __restrict__ E,
-                                                     float* __restrict__ loss) {
+__device__ __forceinline__ void learned_pe_body(const double* __restrict__ partial, int S, int pitch,
+                                                const float* __restrict__ C, int d, float* __restrict__ E,
+                                                float* __restrict__ loss) {
   constexpr int kU = 4, kK = 8;
   __shared__ double scratch[16];
   const size_t stride = static_cast<size_t>(pitch) * pitch;
@@ -144,6 +144,21 @@ __global__ __launch_bounds__(1024) void k_learned_PE(const double* __restrict__ 
   if (threadIdx.x == 0) *loss = static_cast<float>(s);
 }
 
+__global__ __launch_bounds__(1024) void k_learned_PE(const double* __restrict__ partial, int S, int pitch,
+                                                     const float* __restrict__ C, int d, float* __restrict__ E,
+                                                     float* __restrict__ loss) {
+  learned_pe_body(partial, S, pitch, C, d, E, loss);
+}
+
+// Several matrices of one shape in one launch: block j takes matrix j, whose
+// splits start at partial + j * pstride, E at E + j d^2 and loss at loss[j].
+__global__ __launch_bounds__(1024) void k_learned_PE_many(const double* __restrict__ partial, int64_t pstride, int S,
+                                                          int pitch, LearnedMany args, int d, float* __restrict__ E,
+                                                          float* __restrict__ loss) {
+  const int j = blockIdx.x;
+  learned_pe_body(partial + j * pstride, S, pitch, args.C[j], d, E + static_cast<int64_t>(j) * d * d, loss + j);
+}
+
 // G = 4 Y E for the kFB buckets b0 .. b0 + kFB - 1 of this block, held in
 // LDS, then the gradient of every row of those buckets:
 //   grad[r] = scale * < G[h(r)], A[r] >   (d <= 64).
@@ -154,11 +169,11 @@ __global__ __launch_bounds__(1024) void k_learned_PE(const double* __restrict__ 
 constexpr int kFB = 4, kFU = 4;
 
 template <bool VEC>
-__global__ __launch_bounds__(256) void k_learned_G_gather(const float* __restrict__ Y, const float* __restrict__ E,
-                                                          int64_t t, int d, const int32_t* __restrict__ off,
-                                                          const int32_t* __restrict__ perm, int64_t ld,
-                                                          const float* __restrict__ A, float scale, int accumulate,
-                                                          float* __restrict__ grad) {
+__device__ __forceinline__ void learned_g_gather_body(const float* __restrict__ Y, const float* __restrict__ E,
+                                                      int64_t t, int d, const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ perm, int64_t ld,
+                                                      const float* __restrict__ A, float scale, int accumulate,
+                                                      float* __restrict__ grad) {
   __shared__ float Es[64][64];
   __shared__ __align__(16) float Gs[kFB][64];
   __shared__ float Ys[kFB][64];
@@ -238,6 +253,29 @@ __global__ __launch_bounds__(256) void k_learned_G_gather(const float* __restric
       for (int u = 0; u < kFU; ++u)
         if (ok[u]) grad[row[u]] = accumulate ? grad[row[u]] + scale * sum[u] : scale * sum[u];
   }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_learned_G_gather(const float* __restrict__ Y, const float* __restrict__ E,
+                                                          int64_t t, int d, const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ perm, int64_t ld,
+                                                          const float* __restrict__ A, float scale, int accumulate,
+                                                          float* __restrict__ grad) {
+  learned_g_gather_body<VEC>(Y, E, t, d, off, perm, ld, A, scale, accumulate, grad);
+}
+
+// Several matrices of one shape in one launch: matrix blockIdx.y has its
+// sketch at Y + y * ystride, E at E + y d^2, and writes its weighted gradient
+// to its own slot, grad + y * gstride.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_learned_G_gather_many(const float* __restrict__ Y, int64_t ystride,
+                                                               const float* __restrict__ E, int64_t t, int d,
+                                                               const int32_t* __restrict__ off,
+                                                               const int32_t* __restrict__ perm, LearnedMany args,
+                                                               float* __restrict__ grad, int64_t gstride) {
+  const int j = blockIdx.y;
+  learned_g_gather_body<VEC>(Y + j * ystride, E + static_cast<int64_t>(j) * d * d, t, d, off, perm, args.ld[j],
+                             args.A[j], args.scale[j], 0, grad + j * gstride);
 }
 
 // grad[i] = < G[h(i), :], A[i, :] > with 16 lanes per row; VEC (16-byte
@@ -346,6 +384,30 @@ int32_t run_learned_G_gather(const float* Y, const float* E, int64_t t, const in
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(div_up(t, kFB))), dim3(256), 0, s, Y, E, t,
                      static_cast<int>(A.d), off, perm, A.ld, static_cast<const float*>(A.val), scale,
                      accumulate ? 1 : 0, grad);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
+int32_t run_learned_PE_many(const double* partial, int64_t pstride, int S, int pitch, const LearnedMany& args,
+                            int count, int64_t d, float* E, float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_learned_PE_many, dim3(count), dim3(1024), 0, s, partial, pstride, S, pitch, args,
+                     static_cast<int>(d), E, loss);
+  SKLS_CHECK_LAUNCH();
+  return SKLS_OK;
+}
+
+int32_t run_learned_G_gather_many(const float* Y, int64_t ystride, const float* E, int64_t t, int64_t d,
+                                  const int32_t* off, const int32_t* perm, const LearnedMany& args, int count,
+                                  bool vec, float* grad, int64_t gstride, hipStream_t s) {
+  if (d > 64) {
+    set_error("the fused gradient needs d <= 64");
+    return SKLS_ERR_SHAPE;
+  }
+  PhaseTimer pt("learned_gather", s);
+  const dim3 grid(static_cast<unsigned>(div_up(t, kFB)), static_cast<unsigned>(count));
+  const auto kern = vec ? k_learned_G_gather_many<true> : k_learned_G_gather_many<false>;
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, Y, ystride, E, t, static_cast<int>(d), off, perm, args, grad,
+                     gstride);
   SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }

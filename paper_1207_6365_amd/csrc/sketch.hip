@@ -1073,10 +1073,12 @@ __device__ __forceinline__ void dense_rows(const DenseLds<TO>& L, const int32_t*
 }
 
 template <typename TV, typename TO, int V>
-__global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted(
-    int d, int64_t ld, uint32_t t, int bpw, HashKey seed, const TV* __restrict__ A, const void* __restrict__ b,
-    int b_f64, const float* __restrict__ w, const int32_t* __restrict__ off, const int32_t* __restrict__ perm,
-    TO* __restrict__ SA, TO* __restrict__ Sb) {
+__device__ __forceinline__ void sketch_dense_sorted_body(int d, int64_t ld, uint32_t t, int bpw, HashKey seed,
+                                                         const TV* __restrict__ A, const void* __restrict__ b,
+                                                         int b_f64, const float* __restrict__ w,
+                                                         const int32_t* __restrict__ off,
+                                                         const int32_t* __restrict__ perm, TO* __restrict__ SA,
+                                                         TO* __restrict__ Sb) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t b0 = (static_cast<int64_t>(blockIdx.x) * kBucketWaves + wid) * bpw;
@@ -1146,6 +1148,33 @@ __global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted(
     r0 = n0;
     r1 = n1;
   }
+}
+
+template <typename TV, typename TO, int V>
+__global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted(
+    int d, int64_t ld, uint32_t t, int bpw, HashKey seed, const TV* __restrict__ A, const void* __restrict__ b,
+    int b_f64, const float* __restrict__ w, const int32_t* __restrict__ off, const int32_t* __restrict__ perm,
+    TO* __restrict__ SA, TO* __restrict__ Sb) {
+  sketch_dense_sorted_body<TV, TO, V>(d, ld, t, bpw, seed, A, b, b_f64, w, off, perm, SA, Sb);
+}
+
+// The same for up to kSortedMany dense float32 matrices of one shape sharing
+// the plan (float32 output, no b): matrix blockIdx.y is args.A[y] (leading
+// dimension args.ld[y]) and its sketch goes to SA + y * sa_stride.
+struct SortedMany {
+  const float* A[kSortedMany];
+  int64_t ld[kSortedMany];
+};
+
+template <int V>
+__global__ __launch_bounds__(kThreads) void k_sketch_dense_sorted_many(int d, uint32_t t, int bpw, HashKey seed,
+                                                                       SortedMany args, const float* __restrict__ w,
+                                                                       const int32_t* __restrict__ off,
+                                                                       const int32_t* __restrict__ perm,
+                                                                       float* __restrict__ SA, int64_t sa_stride) {
+  const int y = blockIdx.y;
+  sketch_dense_sorted_body<float, float, V>(d, args.ld[y], t, bpw, seed, args.A[y], nullptr, 0, w, off, perm,
+                                            SA + static_cast<int64_t>(y) * sa_stride, nullptr);
 }
 
 // ---------------------------------------------------------------- a2: dense, binned
@@ -1883,6 +1912,49 @@ int32_t sorted_plan_order(const skls_matrix& A, int64_t t, int32_t resolved, int
   }
   *off = P.off;
   *perm = static_cast<const int32_t*>(P.fine);
+  return SKLS_OK;
+}
+
+int32_t apply_sorted_many(const skls_matrix* A, int count, int64_t t, HashKey key, const float* w, const void* plan,
+                          size_t plan_bytes, float* SA, int64_t sa_stride, hipStream_t s) {
+  if (count < 1 || count > kSortedMany) {
+    set_error("sorted sketch of several matrices: need 1 <= count <= %d", kSortedMany);
+    return SKLS_ERR_ARG;
+  }
+  const int32_t *off = nullptr, *perm = nullptr;
+  SKLS_TRY(sorted_plan_order(A[0], t, SKLS_SKETCH_SORTED, SKLS_F32, plan, plan_bytes, &off, &perm));
+  if (off == nullptr) {
+    set_error("sorted sketch of several matrices: the plan is not a dense sorted one");
+    return SKLS_ERR_ARG;
+  }
+  SortedMany args{};
+  bool vec = (sa_stride % 4) == 0;
+  for (int j = 0; j < count; ++j) {
+    if (A[j].layout != SKLS_DENSE || A[j].dtype != SKLS_F32 || A[j].n != A[0].n || A[j].d != A[0].d) {
+      set_error("sorted sketch of several matrices: matrix %d is not a dense float32 matrix of the first's shape", j);
+      return SKLS_ERR_SHAPE;
+    }
+    args.A[j] = static_cast<const float*>(A[j].val);
+    args.ld[j] = A[j].ld;
+    vec = vec && vec_ok<float>(A[j].val, A[j].ld, A[j].d, 4);
+  }
+  const uint32_t tt = static_cast<uint32_t>(t);
+  const int d = static_cast<int>(A[0].d);
+  const size_t lds = kBucketWaves * sizeof(DenseLds<float>);
+  const void* kern = vec ? reinterpret_cast<const void*>(&k_sketch_dense_sorted_many<4>)
+                         : reinterpret_cast<const void*>(&k_sketch_dense_sorted_many<1>);
+  // each matrix as it would run alone (small sketches are bound by latency,
+  // so the matrices' blocks together fill the chip better)
+  const int bpw = buckets_per_wave(t, resident_waves(kern, lds));
+  const dim3 grid(static_cast<unsigned>(div_up(div_up(t, bpw), kBucketWaves)), static_cast<unsigned>(count));
+  const HashKey seed = key;
+  if (vec)
+    hipLaunchKernelGGL(k_sketch_dense_sorted_many<4>, grid, dim3(kThreads), lds, s, d, tt, bpw, seed, args, w, off,
+                       perm, SA, sa_stride);
+  else
+    hipLaunchKernelGGL(k_sketch_dense_sorted_many<1>, grid, dim3(kThreads), lds, s, d, tt, bpw, seed, args, w, off,
+                       perm, SA, sa_stride);
+  SKLS_CHECK_LAUNCH();
   return SKLS_OK;
 }
 
