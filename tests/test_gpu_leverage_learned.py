@@ -129,7 +129,7 @@ def test_learned_loss_and_gradient(sk, n, d, t):
 
 
 @pytest.mark.parametrize("n,d,t,count", [(5000, 70, 333, 3), (32768, 64, 1024, 6), (4096, 16, 128, 1),
-                                         (4096, 16, 128, 18), (3000, 13, 37, 3)])
+                                         (4096, 16, 128, 18), (3000, 13, 37, 3), (500, 1, 1, 2), (2000, 8, 5, 17)])
 def test_learned_batch_matches_single_calls(sk, n, d, t, count):
     # the batched gradient against one planned call per matrix.  d = 70 runs
     # the per-matrix kernels on several streams (the losses then equal the
